@@ -1,0 +1,200 @@
+/*
+ * spalu.h - C ABI of the MI355X (gfx950) recursive sparse LU library.
+ *
+ * The library factors A x = b for a finite-difference matrix on a regular
+ * 2D or 3D grid (the linear system of eq. (1.2); any invertible matrix
+ * whose graph is the 5-point or 7-point stencil, symmetric or not) with the
+ * recursive sparse LU "spaLU" of Zhu & Lai (arXiv 2408.14193):
+ * nested dissection with segments (Section 3, Algorithm 1), leaf
+ * elimination, per-level hybrid-sampled interpolative decompositions with
+ * Schur sparsification, segment LU and separator elimination (Section 4,
+ * Algorithm 2), and the solve x = V~ W~ b (eq. (4.13)), optionally followed
+ * by FP64 iterative refinement.
+ *
+ * Conventions for every entry point:
+ *   - Return value: SPALU_OK (0) or a negative SPALU_E* code.  On failure a
+ *     thread-local message is available from spalu_last_error(), output
+ *     handles are set to NULL and nothing throws across the ABI.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the current device.  All device work is enqueued on
+ *     the caller's stream (a hipStream_t passed as void*, NULL = the null
+ *     stream); calls return after their last host read, so results are
+ *     ready once the caller synchronises that stream.
+ *   - The library allocates no device memory: the caller queries a size,
+ *     allocates (for example through PyTorch's caching allocator) and
+ *     passes the buffer, which must stay alive until the matching free.
+ *   - Vertex ids: interior grid node (x, y, z) has id x + nx*(y + ny*z).
+ */
+#ifndef SPALU_H
+#define SPALU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SPALU_OK = 0,
+  SPALU_EINVAL = -1,       /* bad argument (null pointer, size, dims)         */
+  SPALU_ENOMEM = -2,       /* workspace smaller than the queried size         */
+  SPALU_ESINGULAR = -3,    /* a zero pivot in a diagonal block                */
+  SPALU_ENOCONV = -4,      /* refinement did not reach the tolerance          */
+  SPALU_EDEVICE = -5,      /* a HIP runtime call failed                       */
+  SPALU_EUNSUPPORTED = -6  /* matrix pattern outside the grid stencil, etc.   */
+};
+
+enum { SPALU_FP64 = 0, SPALU_FP32 = 1 };
+
+typedef struct spalu_nd_s spalu_nd_t;
+typedef struct spalu_factor_s spalu_factor_t;
+
+/* ---------------------------------------------------------------------------
+ * Nested dissection (Section 3, Algorithm 1; separator rule of eq. (3.1)).
+ *
+ * On a regular grid the degree-biased separator growth runs straight, so
+ * every box is bisected by the grid line (2D) or plane (3D) through its
+ * median vertex, perpendicular to its longest side (ties: x, then y, then
+ * z); children are the two halves without the separator.  All leaves sit at
+ * depth L.  Segments of level l: connected pieces of one separator whose
+ * vertices border the same depth-l boxes (regular = two boxes, junction =
+ * fewer), refined so that each nests in one segment of level l-1.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t levels;    /* L; 0 = smallest L with all leaf sides <= leaf_max */
+  int32_t leaf_max;  /* default 7 (leaf pitch 8 on 2^m - 1 grids)        */
+} spalu_nd_opts;
+
+/* dim = 2 or 3; grid = interior sizes (nx, ny[, nz]) (host).  opts may be
+ * NULL.  *out receives a caller-owned handle (spalu_nd_free). */
+int spalu_nd_order(int32_t dim, const int32_t* grid, const spalu_nd_opts* opts,
+                   spalu_nd_t** out);
+
+/* Sizes: number of unknowns, L, number of etree nodes, total segments over
+ * all levels.  Any output pointer may be NULL. */
+int spalu_nd_info(const spalu_nd_t* nd, int64_t* n, int32_t* levels, int64_t* nnodes,
+                  int64_t* nsegments);
+
+/* perm (host, n entries): new -> old elimination order: leaves in
+ * left-first depth-first order, then separators of level L..1, each level
+ * left to right, vertex ids ascending inside each node. */
+int spalu_nd_perm(const spalu_nd_t* nd, int64_t* perm);
+
+/* Elimination tree in perm order (host arrays of nnodes entries): first
+ * position in perm, size, level (L+1 for leaves, 1 for the root
+ * separator) and parent node (-1 for the root). */
+int spalu_nd_etree(const spalu_nd_t* nd, int64_t* begin, int64_t* size, int32_t* level,
+                   int64_t* parent);
+
+/* Segments of level l (1..L).  Call once with verts == NULL to get
+ * *nseg and *nverts, then with host arrays: seg_ptr (nseg+1), verts
+ * (nverts; each segment's vertex ids ascending, segments ordered by their
+ * smallest id), flags (nseg; bit0 regular, bit1 on a level-l separator),
+ * parent (nseg; segment of level l-1 that contains it, -1 if eliminated at
+ * level l), npairs/pairs (2*npairs ints: coupled (c, d) pairs incl. c == d,
+ * sorted).  pairs may be NULL. */
+int spalu_nd_segments(const spalu_nd_t* nd, int32_t level, int64_t* nseg, int64_t* nverts,
+                      int64_t* seg_ptr, int32_t* verts, int32_t* flags, int32_t* parent,
+                      int64_t* npairs, int32_t* pairs);
+
+void spalu_nd_free(spalu_nd_t* nd);
+
+/* ---------------------------------------------------------------------------
+ * Factorization (Algorithm 2).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double eps;          /* ID tolerance, relative |R_jj| <= eps |R_11|; 0 = off */
+  int32_t precision;   /* SPALU_FP64 (plain form) or SPALU_FP32 (mixed form)  */
+  uint32_t seed;       /* Philox key for the Gaussian sampling matrix         */
+  double rho;          /* near field: Chebyshev distance <= max(1, rho*span)  */
+  int32_t h0;          /* first number of samples of the adaptive ID          */
+  int32_t probes;      /* Gaussian probes of the a-posteriori ID check        */
+  double tau;          /* accept if max probe error <= tau * eps * |R_11|     */
+  const int32_t* h_init; /* optional device array, per (level, segment) start
+                            samples (learned form); index = seg_base[l] + c,
+                            see spalu_factor_seg_base; <= 0 entries use h0   */
+} spalu_factor_opts;
+
+typedef struct {
+  int64_t n;
+  int32_t levels;
+  int64_t segments;          /* segments over all levels                     */
+  int64_t sparsified;        /* segments that went through the ID            */
+  int64_t sample_passes;     /* ID passes (>= sparsified; more = resampling) */
+  int64_t resampled;         /* segments needing more than one pass          */
+  int64_t max_front;         /* largest segment size seen                    */
+  double q_tilde;            /* max_l e'_l / e_l (Section 6)                 */
+  double flops;              /* algorithmic flops of the factorization       */
+  double bytes;              /* algorithmic HBM bytes of the factorization   */
+  int64_t workspace_bytes;
+  int32_t singular_level;    /* level of a zero pivot (-1 none)              */
+} spalu_factor_info;
+
+/* Default options (eps 1e-6, FP64, seed 1234, rho 0.5, h0 8, 5 probes,
+ * tau 10). */
+void spalu_factor_opts_default(spalu_factor_opts* o);
+
+/* Bytes of device workspace that spalu_factor needs for this ND and
+ * options (static layout sized by uncompressed segment sizes). */
+int spalu_factor_workspace(const spalu_nd_t* nd, const spalu_factor_opts* opts, size_t* bytes);
+
+/* Index base of level l's segments in the per-segment arrays (h_init, and
+ * spalu_factor_ranks): base[l] for l = 1..L, base[L+1] = total. */
+int spalu_factor_seg_base(const spalu_nd_t* nd, int64_t* base /* L+2 */);
+
+/* Factor the CSR matrix (device arrays: rowptr n+1, colind nnz, vals nnz;
+ * column indices ascending in each row, pattern inside the stencil) on
+ * stream.  workspace: device buffer of at least the queried bytes, owned
+ * by the caller, kept by the factor until spalu_factor_free.  The CSR
+ * arrays are borrowed too: solve reads them for refinement residuals, so
+ * they must outlive the factor.  info (host) may be NULL.
+ * Errors: EINVAL, ENOMEM, EUNSUPPORTED, ESINGULAR (info->singular_level),
+ * EDEVICE.  Synchronises the stream once at the end (status readback). */
+int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                 const double* vals, const spalu_factor_opts* opts, void* workspace,
+                 size_t workspace_bytes, void* stream, spalu_factor_t** out,
+                 spalu_factor_info* info);
+
+/* Per-segment results of the factorization (host arrays of base[L+1]
+ * entries, index seg_base[l] + c): size before the ID, skeleton rank,
+ * samples of the accepted pass, number of passes.  Synchronises. */
+int spalu_factor_ranks(const spalu_factor_t* f, int32_t* n_before, int32_t* rank, int32_t* h,
+                       int32_t* passes);
+
+void spalu_factor_free(spalu_factor_t* f);
+
+/* ---------------------------------------------------------------------------
+ * Solve x = V~ W~ b (eqs. (4.12)-(4.13)) and FP64 iterative refinement
+ * r = b - A x, x += M r until max_j ||r_j|| / ||b_j|| <= tol.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  double tol;        /* target relative residual; 0 = direct solve only */
+  int32_t max_iter;  /* refinement iterations (default 30)              */
+} spalu_solve_opts;
+
+typedef struct {
+  int32_t iterations;
+  double max_rel_residual;   /* max_j ||b_j - A x_j|| / ||b_j|| at exit   */
+  double first_rel_residual; /* same after the direct solve               */
+} spalu_solve_info;
+
+/* Bytes of device workspace for nrhs right-hand sides. */
+int spalu_solve_workspace(const spalu_factor_t* f, int32_t nrhs, size_t* bytes);
+
+/* B, X: device, column-major n x nrhs with leading dimensions ldb, ldx >= n
+ * (FP64).  X may equal B.  opts, info (host) may be NULL (direct solve).
+ * rel_res (host, nrhs entries, may be NULL) receives the final relative
+ * residual of each column.  With refinement the call synchronises once per
+ * iteration (residual norm readback); ENOCONV if tol is not reached in
+ * max_iter iterations (X holds the last iterate). */
+int spalu_solve(const spalu_factor_t* f, int32_t nrhs, const double* B, int64_t ldb, double* X,
+                int64_t ldx, const spalu_solve_opts* opts, void* workspace,
+                size_t workspace_bytes, void* stream, double* rel_res, spalu_solve_info* info);
+
+const char* spalu_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPALU_H */

@@ -86,7 +86,7 @@ def lu_solve(LU, piv, X):
     return solve_upper(LU, solve_lower_unit(LU, apply_row_pivots(piv, X)))
 
 
-def cpqr_id(Y, eps, max_rank=None):
+def cpqr_id(Y, eps, max_rank=None, margins=None):
     """Interpolative decomposition by Householder QR with column pivoting
     (Section 4.1, eqs. (4.1)-(4.3)).
 
@@ -98,7 +98,9 @@ def cpqr_id(Y, eps, max_rank=None):
 
     Returns (k, perm, T, r11): perm lists original column indices in pivot
     order (first k = skeleton), T = R_11^{-1} R_12 is k x (n-k), and r11 is
-    |R_11|.
+    |R_11|.  If ``margins`` is a list, the relative distance of every
+    rank decision to the threshold, |norm / (eps |R_11|) - 1|, is appended
+    (how close a differently rounded run could come to deciding otherwise).
     """
     Y = np.array(Y, dtype=np.float64, copy=True)
     m, n = Y.shape
@@ -113,6 +115,8 @@ def cpqr_id(Y, eps, max_rank=None):
         mx = norms.max() if norms.size else 0.0
         if j == 0:
             r11 = mx
+        if margins is not None and eps > 0 and r11 > 0:
+            margins.append(abs(mx / (eps * r11) - 1.0))
         if mx == 0.0 or mx <= eps * r11:
             k = j
             break

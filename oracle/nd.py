@@ -285,9 +285,12 @@ def nd_order(dims, levels=None, leaf_max=7):
     # leaves: interior vertices and the level-L segments on their boundary
     leaves = []
     segL = levels_out[L].segs
+    on_leaf = {}
+    for s, sg in enumerate(segL):
+        for b in sg.sig:
+            on_leaf.setdefault(b, []).append(s)
     for b in by_depth[L]:
-        bsegs = [s for s, sg in enumerate(segL) if b.index in sg.sig]
-        leaves.append((_box_ids(idx3, b.lo, b.hi), bsegs))
+        leaves.append((_box_ids(idx3, b.lo, b.hi), on_leaf.get(b.index, [])))
 
     return ND(dims=dims3, dim=dim, L=L, perm=perm, node_begin=node_begin, node_size=node_size,
               node_level=node_level, node_parent=node_parent, leaves=leaves, levels=levels_out)

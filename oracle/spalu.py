@@ -68,6 +68,7 @@ class SegRec:
     sparsified: bool
     h: int = 0
     passes: int = 0
+    margin: float = float("inf")   # closest rank / check decision to its threshold
 
     @property
     def skel(self):
@@ -113,7 +114,9 @@ def _dense(A, rows, cols):
 
 def segment_id(nd, lev, c, blocks, cur, opts, sym):
     """Hybrid-sampled CPQR ID of one segment (Sections 4.1-4.2); returns
-    (k, perm, T, h, passes) or None when the segment has no coupling rows."""
+    (k, perm, T, h, passes, margin) or None when the segment has no coupling
+    rows; margin is the closest of its rank and check decisions to the
+    threshold (relative)."""
     lvl = nd.levels[lev]
     seg = lvl.segs[c]
     n = len(cur[c])
@@ -141,21 +144,24 @@ def segment_id(nd, lev, c, blocks, cur, opts, sym):
     if opts.rank_hint is not None:
         h = int(opts.rank_hint(lev, c, dict(n=n, nnear=int(near.sum()), nfar=len(BF))))
     passes = 0
+    margins = []
     while True:
         passes += 1
         if h >= len(BF):
             Y = np.vstack([BN, BF])
-            k, perm, T, r11 = dense.cpqr_id(Y, opts.eps)
-            return k, perm, T, len(BF), passes
+            k, perm, T, r11 = dense.cpqr_id(Y, opts.eps, margins=margins)
+            return k, perm, T, len(BF), passes, min(margins, default=float("inf"))
         G = gaussian(opts.seed, lev, 0, np.arange(h), vf, c, hf)
         Y = np.vstack([BN, (G @ BF) / math.sqrt(h)])
-        k, perm, T, r11 = dense.cpqr_id(Y, opts.eps)
+        k, perm, T, r11 = dense.cpqr_id(Y, opts.eps, margins=margins)
         Om = gaussian(opts.seed, lev, 1, np.arange(opts.probes), vf, c, hf)
         P = Om @ BF
         E = P[:, perm[k:]] - P[:, perm[:k]] @ T
         err = float(np.sqrt((E ** 2).sum(axis=1)).max()) if E.size else 0.0
+        if r11 > 0:
+            margins.append(abs(err / (opts.tau * opts.eps * r11) - 1.0))
         if err <= opts.tau * opts.eps * r11:
-            return k, perm, T, h, passes
+            return k, perm, T, h, passes, min(margins, default=float("inf"))
         h *= 2
 
 
@@ -222,7 +228,7 @@ def factor(nd, A, opts=None):
             M = blocks[(c, c)]
             n = len(cur[c])
             if c in ids:
-                k, perm, T, h, passes = ids[c]
+                k, perm, T, h, passes, margin = ids[c]
                 nr = n - k
                 order = np.concatenate([perm[k:], perm[:k]])
                 M1 = M[:, order].copy()
@@ -231,7 +237,7 @@ def factor(nd, A, opts=None):
                 M2[:nr, :] -= T.T @ M2[nr:, :]
                 LU, piv = dense.lu_window(M2, split=nr)
                 recs.append(SegRec(dofs=cur[c][order], nr=nr, T=T, LU=LU, piv=piv,
-                                   sparsified=True, h=h, passes=passes))
+                                   sparsified=True, h=h, passes=passes, margin=margin))
             else:
                 LU, piv = dense.lu_window(M, split=0)
                 recs.append(SegRec(dofs=cur[c].copy(), nr=0, T=None, LU=LU, piv=piv,

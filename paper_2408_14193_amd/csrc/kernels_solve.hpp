@@ -1,0 +1,257 @@
+// Solve kernels: x = V~ W~ b (eqs. (4.12)-(4.13)) applied to nrhs columns
+// at once, and the FP64 residual of iterative refinement.  The working
+// vector W is DOF-major (W[v*nrhs + j]) so a segment's gather of its DOFs
+// reads nrhs contiguous values per DOF.
+#pragma once
+
+#include "device_common.hpp"
+#include "kernels_factor.hpp"
+#include "layout.hpp"
+
+namespace spalu {
+
+template <typename T>
+__global__ void k_rhs_in(const double* B, int64_t ldb, int64_t n, int nrhs, T* W) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int64_t v = t / nrhs;
+  const int j = int(t % nrhs);
+  W[t] = T(B[v + j * ldb]);
+}
+
+template <typename T>
+__global__ void k_rhs_out(const T* W, int64_t n, int nrhs, double* X, int64_t ldx, int accumulate) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int64_t v = t / nrhs;
+  const int j = int(t % nrhs);
+  if (accumulate)
+    X[v + j * ldx] += double(W[t]);
+  else
+    X[v + j * ldx] = double(W[t]);
+}
+
+// Leaf interiors: Z_I = A_II^{-1} W_I (forward) or
+// W_I = A_II^{-1} (B_I - A_IB W_B) (backward).
+template <typename T, bool BACKWARD>
+__global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nleaf, GridGeom g,
+                                                   const int64_t* rowptr, const int32_t* colind,
+                                                   const double* vals, const int32_t* iarena,
+                                                   const T* varena, const T* B0, T* W, T* Z, int nrhs) {
+  extern __shared__ double lds[];
+  const int lf = blockIdx.x;
+  if (lf >= nleaf) return;
+  const DLeaf L = leaves[lf];
+  const int ni = L.ni, nb = L.nb, tid = threadIdx.x;
+  const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1;
+  const int32_t* piv = iarena + L.ioff + nb;
+  const T* LU = varena + L.lu_off;
+  const int jc = ni > 0 ? (LDS_DOUBLES / ni < nrhs ? LDS_DOUBLES / ni : nrhs) : nrhs;
+  for (int j0 = 0; j0 < nrhs; j0 += jc) {
+    const int nc = nrhs - j0 < jc ? nrhs - j0 : jc;
+    for (int t = tid; t < ni * nc; t += WG) {
+      const int i = t / nc, j = t % nc;
+      const int ix = i % w0, iy = (i / w0) % w1, iz = i / (w0 * w1);
+      const int u = (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz));
+      double v;
+      if (!BACKWARD) {
+        v = double(W[size_t(u) * nrhs + j0 + j]);
+      } else {
+        v = double(B0[size_t(u) * nrhs + j0 + j]);
+        for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+          const int w = colind[e];
+          int cw[3];
+          vcoords(g, w, cw);
+          const bool inside = cw[0] >= L.lo[0] && cw[0] <= L.hi[0] && cw[1] >= L.lo[1] &&
+                              cw[1] <= L.hi[1] && cw[2] >= L.lo[2] && cw[2] <= L.hi[2];
+          if (!inside) v -= vals[e] * double(W[size_t(w) * nrhs + j0 + j]);
+        }
+      }
+      lds[t] = v;
+    }
+    __syncthreads();
+    block_lower_solve<T>(LU, ni, piv, ni, lds, nc, nc);
+    block_upper_solve<T>(LU, ni, ni, lds, nc, nc);
+    for (int t = tid; t < ni * nc; t += WG) {
+      const int i = t / nc, j = t % nc;
+      const int ix = i % w0, iy = (i / w0) % w1, iz = i / (w0 * w1);
+      const int u = (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz));
+      if (BACKWARD)
+        W[size_t(u) * nrhs + j0 + j] = T(lds[t]);
+      else
+        Z[size_t(u) * nrhs + j0 + j] = T(lds[t]);
+    }
+    __syncthreads();
+  }
+}
+
+// W_u -= sum over leaf-interior neighbours i of a_ui Z_i, for separator u.
+template <typename T>
+__global__ void k_sep_from_leaves(int64_t n, const int8_t* seplev, const int64_t* rowptr,
+                                  const int32_t* colind, const double* vals, const T* Z, T* W, int nrhs) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n * nrhs) return;
+  const int64_t u = t / nrhs;
+  const int j = int(t % nrhs);
+  if (seplev[u] == 0) return;
+  double acc = 0.0;
+  for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+    const int w = colind[e];
+    if (seplev[w] == 0) acc += vals[e] * double(Z[size_t(w) * nrhs + j]);
+  }
+  W[t] = T(double(W[t]) - acc);
+}
+
+// Per segment of level l: forward (U_T, then P and L^{-1}) or backward
+// (U^{-1}, then L_T) on its DOFs in [remainder; skeleton] order.
+template <typename T, bool BACKWARD>
+__global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, const int32_t* iarena,
+                                                  const T* varena, DLevelDyn dyn, T* W, int nrhs) {
+  extern __shared__ double lds[];
+  const int c = blockIdx.x;
+  if (c >= nseg) return;
+  const int tid = threadIdx.x;
+  const DSeg S = segs[c];
+  const int n = dyn.n[c];
+  if (n == 0) return;
+  const int k = dyn.k[c], nr = dyn.nr[c];
+  const bool sp = dyn.passes[c] > 0 && nr > 0 && k > 0;
+  const int32_t* dofs = iarena + S.ioff;
+  const int32_t* piv = dofs + 2 * S.cap;
+  const T* LU = varena + S.lu_off;
+  const T* Tm = varena + S.t_off;
+  if (n > LDS_DOUBLES) {
+    // too large for the staging buffer: poison the result so the residual
+    // check reports the failure instead of returning a wrong solution
+    for (int t = tid; t < n * nrhs; t += WG) W[size_t(dofs[t / nrhs]) * nrhs + t % nrhs] = T(NAN);
+    return;
+  }
+  const int jc = LDS_DOUBLES / n < nrhs ? LDS_DOUBLES / n : nrhs;
+  for (int j0 = 0; j0 < nrhs; j0 += jc) {
+    const int nc = nrhs - j0 < jc ? nrhs - j0 : jc;
+    for (int t = tid; t < n * nc; t += WG) {
+      const int i = t / nc, j = t % nc;
+      lds[t] = double(W[size_t(dofs[i]) * nrhs + j0 + j]);
+    }
+    __syncthreads();
+    if (!BACKWARD) {
+      if (sp) {
+        for (int t = tid; t < nr * nc; t += WG) {
+          const int q = t / nc, j = t % nc;
+          double s = 0.0;
+          for (int i = 0; i < k; ++i) s += double(Tm[size_t(i) * nr + q]) * lds[size_t(nr + i) * nc + j];
+          lds[t] -= s;
+        }
+        __syncthreads();
+      }
+      block_lower_solve<T>(LU, n, piv, n, lds, nc, nc);
+    } else {
+      block_upper_solve<T>(LU, n, n, lds, nc, nc);
+      if (sp) {
+        for (int t = tid; t < k * nc; t += WG) {
+          const int i = t / nc, j = t % nc;
+          double s = 0.0;
+          for (int q = 0; q < nr; ++q) s += double(Tm[size_t(i) * nr + q]) * lds[size_t(q) * nc + j];
+          lds[size_t(nr + i) * nc + j] -= s;
+        }
+        __syncthreads();
+      }
+    }
+    for (int t = tid; t < n * nc; t += WG) {
+      const int i = t / nc, j = t % nc;
+      W[size_t(dofs[i]) * nrhs + j0 + j] = T(lds[t]);
+    }
+    __syncthreads();
+  }
+}
+
+// Forward separator elimination (Z_l): owner = non-separator segment a,
+// W[skel_a] -= sum over level-l separators s next to a of A'_{a,s} W[skel_s].
+template <typename T>
+__global__ __launch_bounds__(WG) void k_sep_fwd(const DSeg* segs, int nseg, const DNbr* nbrs,
+                                                const DBlk* blks, const int32_t* iarena, const T* varena,
+                                                DLevelDyn dyn, T* W, int nrhs) {
+  const int a = blockIdx.x;
+  if (a >= nseg) return;
+  const DSeg S = segs[a];
+  if (S.flags & SEG_IS_SEP) return;
+  const int ka = dyn.k[a], nra = dyn.nr[a];
+  const int32_t* da = iarena + S.ioff + nra;
+  for (int t = threadIdx.x; t < ka * nrhs; t += WG) {
+    const int i = t / nrhs, j = t % nrhs;
+    double acc = 0.0;
+    for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+      const DNbr nb = nbrs[e];
+      if (!nb.d_is_sep) continue;
+      const int ks = dyn.k[nb.d], nrs = dyn.nr[nb.d];
+      const int32_t* ds = iarena + segs[nb.d].ioff + nrs;
+      const T* A = varena + blks[nb.blk_cd].soff;
+      for (int u = 0; u < ks; ++u) acc += double(A[size_t(i) * ks + u]) * double(W[size_t(ds[u]) * nrhs + j]);
+    }
+    const size_t idx = size_t(da[i]) * nrhs + j;
+    W[idx] = T(double(W[idx]) - acc);
+  }
+}
+
+// Backward separator elimination (Z_u): owner = separator s,
+// W[skel_s] -= sum over its neighbours b of A'_{s,b} W[skel_b].
+template <typename T>
+__global__ __launch_bounds__(WG) void k_sep_bwd(const DSeg* segs, int nseg, const DNbr* nbrs,
+                                                const DBlk* blks, const int32_t* iarena, const T* varena,
+                                                DLevelDyn dyn, T* W, int nrhs) {
+  const int s = blockIdx.x;
+  if (s >= nseg) return;
+  const DSeg S = segs[s];
+  if (!(S.flags & SEG_IS_SEP)) return;
+  const int ks = dyn.k[s], nrs = dyn.nr[s];
+  const int32_t* ds = iarena + S.ioff + nrs;
+  for (int t = threadIdx.x; t < ks * nrhs; t += WG) {
+    const int i = t / nrhs, j = t % nrhs;
+    double acc = 0.0;
+    for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+      const DNbr nb = nbrs[e];
+      const int kb = dyn.k[nb.d], nrb = dyn.nr[nb.d];
+      const int32_t* db = iarena + segs[nb.d].ioff + nrb;
+      const T* A = varena + blks[nb.blk_cd].soff;
+      for (int u = 0; u < kb; ++u) acc += double(A[size_t(i) * kb + u]) * double(W[size_t(db[u]) * nrhs + j]);
+    }
+    const size_t idx = size_t(ds[i]) * nrhs + j;
+    W[idx] = T(double(W[idx]) - acc);
+  }
+}
+
+// r = b - A x in FP64 (column-major, ld n), per-block partial sums of
+// ||r_j||^2 (and ||b_j||^2 when want_b) for a deterministic reduction.
+__global__ __launch_bounds__(WG) void k_residual(int64_t n, int nrhs, const int64_t* rowptr,
+                                                 const int32_t* colind, const double* vals,
+                                                 const double* B, int64_t ldb, const double* X,
+                                                 int64_t ldx, double* R, double* part_r, double* part_b) {
+  __shared__ double red[NWAVE];
+  const int j = blockIdx.y;
+  const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
+  double r = 0.0, b = 0.0;
+  if (v < n) {
+    b = B[v + j * ldb];
+    double ax = 0.0;
+    for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) ax += vals[e] * X[colind[e] + j * ldx];
+    r = b - ax;
+    R[v + j * n] = r;
+  }
+  const double sr = block_sum(r * r, red);
+  const double sb = block_sum(b * b, red);
+  if (threadIdx.x == 0) {
+    part_r[size_t(j) * gridDim.x + blockIdx.x] = sr;
+    part_b[size_t(j) * gridDim.x + blockIdx.x] = sb;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_reduce_cols(const double* part, int nblk, int nrhs, double* out) {
+  __shared__ double red[NWAVE];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += WG) s += part[size_t(j) * nblk + b];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+}  // namespace spalu

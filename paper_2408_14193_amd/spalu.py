@@ -1,0 +1,262 @@
+"""Python binding of libspalu (ctypes): argument marshalling only.
+
+Every step of nested dissection planning, factorization and solve runs in
+the compiled library (host planner + HIP kernels for gfx950).  PyTorch
+provides device memory (workspaces are torch tensors) and the stream (the
+current torch stream).  If the library is missing this module raises on
+import; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspalu.so")
+
+# torch is imported first so its HIP runtime is the one loaded in the
+# process; the library's libamdhip64.so.7 dependency then binds to it by
+# SONAME instead of pulling a second runtime from /opt/rocm.
+import torch  # noqa: E402,F401
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libspalu.so is not built; run paper_2408_14193_amd/build.py "
+                      "(or __graft_entry__.build())")
+_lib = C.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, ESINGULAR, ENOCONV, EDEVICE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32 = 0, 1
+_NAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", ESINGULAR: "ESINGULAR", ENOCONV: "ENOCONV",
+          EDEVICE: "EDEVICE", EUNSUPPORTED: "EUNSUPPORTED"}
+
+
+class SpaluError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_NAMES.get(code, code), msg))
+        self.code = code
+
+
+class NdOpts(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("leaf_max", C.c_int32)]
+
+
+class FactorOpts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("precision", C.c_int32), ("seed", C.c_uint32),
+                ("rho", C.c_double), ("h0", C.c_int32), ("probes", C.c_int32),
+                ("tau", C.c_double), ("h_init", C.c_void_p)]
+
+
+class FactorInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("levels", C.c_int32), ("segments", C.c_int64),
+                ("sparsified", C.c_int64), ("sample_passes", C.c_int64),
+                ("resampled", C.c_int64), ("max_front", C.c_int64), ("q_tilde", C.c_double),
+                ("flops", C.c_double), ("bytes", C.c_double), ("workspace_bytes", C.c_int64),
+                ("singular_level", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("max_rel_residual", C.c_double),
+                ("first_rel_residual", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+P = C.c_void_p
+I64P = C.POINTER(C.c_int64)
+I32P = C.POINTER(C.c_int32)
+_lib.spalu_last_error.restype = C.c_char_p
+_lib.spalu_nd_order.argtypes = [C.c_int32, I32P, C.POINTER(NdOpts), C.POINTER(P)]
+_lib.spalu_nd_info.argtypes = [P, I64P, I32P, I64P, I64P]
+_lib.spalu_nd_perm.argtypes = [P, I64P]
+_lib.spalu_nd_etree.argtypes = [P, I64P, I64P, I32P, I64P]
+_lib.spalu_nd_segments.argtypes = [P, C.c_int32, I64P, I64P, I64P, I32P, I32P, I32P, I64P, I32P]
+_lib.spalu_nd_free.argtypes = [P]
+_lib.spalu_nd_free.restype = None
+_lib.spalu_factor_opts_default.argtypes = [C.POINTER(FactorOpts)]
+_lib.spalu_factor_opts_default.restype = None
+_lib.spalu_factor_workspace.argtypes = [P, C.POINTER(FactorOpts), C.POINTER(C.c_size_t)]
+_lib.spalu_factor_seg_base.argtypes = [P, I64P]
+_lib.spalu_factor.argtypes = [P, C.c_int64, P, P, P, C.POINTER(FactorOpts), P, C.c_size_t, P,
+                              C.POINTER(P), C.POINTER(FactorInfo)]
+_lib.spalu_factor_ranks.argtypes = [P, I32P, I32P, I32P, I32P]
+_lib.spalu_factor_free.argtypes = [P]
+_lib.spalu_factor_free.restype = None
+_lib.spalu_solve_workspace.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+_lib.spalu_solve.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64, C.POINTER(SolveOpts), P,
+                             C.c_size_t, P, C.POINTER(C.c_double), C.POINTER(SolveInfo)]
+
+EXPORTED = ["spalu_nd_order", "spalu_nd_info", "spalu_nd_perm", "spalu_nd_etree",
+            "spalu_nd_segments", "spalu_nd_free", "spalu_factor_opts_default",
+            "spalu_factor_workspace", "spalu_factor_seg_base", "spalu_factor",
+            "spalu_factor_ranks", "spalu_factor_free", "spalu_solve_workspace", "spalu_solve",
+            "spalu_last_error"]
+
+
+def _check(rc):
+    if rc != OK:
+        raise SpaluError(rc, _lib.spalu_last_error().decode())
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class ND:
+    """Nested dissection of a regular grid (spalu_nd_order)."""
+
+    def __init__(self, dims, levels=0, leaf_max=7):
+        self.dims = tuple(int(d) for d in dims)
+        g = (C.c_int32 * 3)(*(list(self.dims) + [1] * (3 - len(self.dims))))
+        h = P()
+        _check(_lib.spalu_nd_order(len(self.dims), g, C.byref(NdOpts(levels, leaf_max)), C.byref(h)))
+        self._h = h
+        n, L, nn, ns = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int64()
+        _check(_lib.spalu_nd_info(h, C.byref(n), C.byref(L), C.byref(nn), C.byref(ns)))
+        self.n, self.L, self.nnodes, self.nsegments = n.value, L.value, nn.value, ns.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.spalu_nd_free(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def perm(self):
+        out = np.empty(self.n, dtype=np.int64)
+        _check(_lib.spalu_nd_perm(self._h, _ptr(out, C.c_int64)))
+        return out
+
+    def etree(self):
+        b = np.empty(self.nnodes, np.int64)
+        s = np.empty(self.nnodes, np.int64)
+        lv = np.empty(self.nnodes, np.int32)
+        p = np.empty(self.nnodes, np.int64)
+        _check(_lib.spalu_nd_etree(self._h, _ptr(b, C.c_int64), _ptr(s, C.c_int64),
+                                   _ptr(lv, C.c_int32), _ptr(p, C.c_int64)))
+        return b, s, lv, p
+
+    def segments(self, level):
+        ns, nv, npr = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_lib.spalu_nd_segments(self._h, level, C.byref(ns), C.byref(nv), None, None, None,
+                                      None, C.byref(npr), None))
+        ptr = np.empty(ns.value + 1, np.int64)
+        verts = np.empty(nv.value, np.int32)
+        flags = np.empty(ns.value, np.int32)
+        parent = np.empty(ns.value, np.int32)
+        pairs = np.empty(2 * npr.value, np.int32)
+        _check(_lib.spalu_nd_segments(self._h, level, C.byref(ns), C.byref(nv), _ptr(ptr, C.c_int64),
+                                      _ptr(verts, C.c_int32), _ptr(flags, C.c_int32),
+                                      _ptr(parent, C.c_int32), C.byref(npr), _ptr(pairs, C.c_int32)))
+        return ptr, verts, flags, parent, pairs.reshape(-1, 2)
+
+    def seg_base(self):
+        b = np.empty(self.L + 2, np.int64)
+        _check(_lib.spalu_factor_seg_base(self._h, _ptr(b, C.c_int64)))
+        return b
+
+
+def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, tau=10.0,
+                h_init=None):
+    o = FactorOpts()
+    _lib.spalu_factor_opts_default(C.byref(o))
+    o.eps, o.precision, o.seed, o.rho, o.h0, o.probes, o.tau = (
+        float(eps), int(precision), int(seed) & 0xFFFFFFFF, float(rho), int(h0), int(probes), float(tau))
+    o.h_init = None if h_init is None else int(h_init.data_ptr())
+    return o
+
+
+def factor_workspace_bytes(nd, opts):
+    b = C.c_size_t()
+    _check(_lib.spalu_factor_workspace(nd.handle, C.byref(opts), C.byref(b)))
+    return b.value
+
+
+class Factor:
+    """spaLU factorization of a CSR matrix held in device memory (torch)."""
+
+    def __init__(self, nd, rowptr, colind, vals, eps=1e-6, precision=FP64, seed=1234, rho=0.5,
+                 h0=8, probes=5, tau=10.0, h_init=None, stream=None):
+        import torch
+        assert rowptr.is_cuda and rowptr.dtype == torch.int64
+        assert colind.is_cuda and colind.dtype == torch.int32
+        assert vals.is_cuda and vals.dtype == torch.float64
+        self.nd = nd
+        self.csr = (rowptr.contiguous(), colind.contiguous(), vals.contiguous())
+        self.h_init = h_init
+        self.opts = factor_opts(eps, precision, seed, rho, h0, probes, tau, h_init)
+        nbytes = factor_workspace_bytes(nd, self.opts)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=rowptr.device)
+        s = torch.cuda.current_stream() if stream is None else stream
+        self.stream = s
+        h = P()
+        info = FactorInfo()
+        _check(_lib.spalu_factor(nd.handle, nd.n, self.csr[0].data_ptr(), self.csr[1].data_ptr(),
+                                 self.csr[2].data_ptr(), C.byref(self.opts),
+                                 self.workspace.data_ptr(), nbytes, s.cuda_stream, C.byref(h),
+                                 C.byref(info)))
+        self._h = h
+        self.info = info.as_dict()
+        self._solve_ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.spalu_factor_free(h)
+            self._h = None
+
+    def ranks(self):
+        tot = int(self.nd.seg_base()[-1])
+        nb, rk, hh, ps = (np.empty(tot, np.int32) for _ in range(4))
+        _check(_lib.spalu_factor_ranks(self._h, _ptr(nb, C.c_int32), _ptr(rk, C.c_int32),
+                                       _ptr(hh, C.c_int32), _ptr(ps, C.c_int32)))
+        return nb, rk, hh, ps
+
+    def solve_workspace(self, nrhs):
+        import torch
+        if nrhs not in self._solve_ws:
+            b = C.c_size_t()
+            _check(_lib.spalu_solve_workspace(self._h, nrhs, C.byref(b)))
+            self._solve_ws[nrhs] = torch.empty(b.value, dtype=torch.uint8,
+                                               device=self.workspace.device)
+        return self._solve_ws[nrhs]
+
+    def solve_into(self, Bt, Xt, tol=0.0, max_iter=30, stream=None):
+        """Bt, Xt: (nrhs, n) float64 contiguous device tensors (column-major
+        n x nrhs).  Returns (info dict, per-column relative residuals)."""
+        nrhs, n = Bt.shape
+        ws = self.solve_workspace(nrhs)
+        s = self.stream if stream is None else stream
+        rr = np.zeros(nrhs, np.float64)
+        info = SolveInfo()
+        rc = _lib.spalu_solve(self._h, nrhs, Bt.data_ptr(), n, Xt.data_ptr(), n,
+                              C.byref(SolveOpts(float(tol), int(max_iter))), ws.data_ptr(),
+                              ws.numel(), s.cuda_stream, _ptr(rr, C.c_double), C.byref(info))
+        if rc not in (OK, ENOCONV):
+            _check(rc)
+        d = info.as_dict()
+        d["converged"] = rc == OK
+        return d, rr
+
+    def solve(self, B, tol=0.0, max_iter=30):
+        """B: (n, nrhs) or (n,) float64 device tensor.  Returns (X, info)."""
+        import torch
+        vec = B.dim() == 1
+        Bt = (B[None, :] if vec else B.t()).contiguous()
+        Xt = torch.empty_like(Bt)
+        info, rr = self.solve_into(Bt, Xt, tol, max_iter)
+        info["rel_res"] = rr
+        X = Xt[0] if vec else Xt.t()
+        return X, info
