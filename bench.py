@@ -1,0 +1,217 @@
+"""Benchmark: factor + solve throughput (DOF/s) of spaLU on one MI355X.
+
+A step is one whole pass of the hot path over one batch of synthetic input:
+factorization (leaf elimination, per-level IDs and sparsification, segment
+LU, separator elimination, merges) followed by the multi-RHS solve with FP64
+iterative refinement to the workload's tolerance.  The matrix, right-hand
+sides and nested-dissection plan are resident before the timed region
+(nested dissection is a closed-form host step, timed and reported apart).
+
+Default workload: -div(a grad u) on the 1023 x 1023 interior grid, a =
+exp(Gaussian random field, correlation length 0.05, std 1), 16 right-hand
+sides uniform in [-1, 1], eps = 1e-4, refinement to 1e-10.  The headline
+`value` is the mixed form (FP32 storage and GEMMs, FP64 pivoted LU / ID
+solve / residual); the plain FP64 form is reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--side", type=int, default=None)
+    ap.add_argument("--nrhs", type=int, default=None)
+    ap.add_argument("--forms", default="mixed,plain")
+    ap.add_argument("--cpu-side", type=int, default=255)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(S, P, nd, dev, form, steps, warmup, profile):
+    import numpy as np
+    import torch
+    prec = S.FP32 if form == "mixed" else S.FP64
+    rp = torch.from_numpy(P.indptr).to(dev)
+    ci = torch.from_numpy(P.indices).to(dev)
+    v = torch.from_numpy(P.data).to(dev)
+    B = torch.from_numpy(np.ascontiguousarray(P.rhs.T)).to(dev)   # (nrhs, n): column-major n x nrhs
+    X = torch.empty_like(B)
+    tol = P.tol
+
+    def step():
+        t0 = time.perf_counter()
+        F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec)
+        t1 = time.perf_counter()
+        info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(form == "mixed"))
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return F, info, rr, t1 - t0, t2 - t1
+
+    for i in range(warmup):
+        F, info, rr, tf, ts = step()
+        log("[%s] warmup %d: factor %.1f ms, solve %.1f ms, %d refinement steps, residual %.2e"
+            % (form, i, tf * 1e3, ts * 1e3, info["iterations"], rr.max()))
+        del F
+    torch.cuda.synchronize()
+    if profile:
+        S.profile(True)
+    tfs, tss, its, res = [], [], [], []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        F, info, rr, tf, ts = step()
+        tfs.append(tf)
+        tss.append(ts)
+        its.append(info["iterations"])
+        res.append(float(rr.max()))
+        last = F
+        del F
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    finfo = dict(last.info)
+    finfo["flops"], finfo["bytes"] = last.work()
+    del last
+    prof = S.profile_read() if profile else None
+    if profile:
+        S.profile(False)
+    ms = (t1 - t0) * 1e3 / steps
+    log("[%s] %d steps: %.1f ms/step (factor %.1f, solve %.1f), refinement %s, residual %.2e"
+        % (form, steps, ms, 1e3 * sum(tfs) / steps, 1e3 * sum(tss) / steps, its, max(res)))
+    return dict(ms_per_step=ms, factor_ms=1e3 * sum(tfs) / steps, solve_ms=1e3 * sum(tss) / steps,
+                refine_iters=its, max_rel_residual=max(res), factor_info=finfo,
+                converged=all(r <= tol for r in res), profile=prof)
+
+
+def roofline(prof, form):
+    """Dominant kernel by summed event time; achieved = algorithmic bytes per
+    launch / average launch time."""
+    name, st = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = st["ms"] / st["launches"]
+    bpl = st["bytes"] / st["launches"]
+    fpl = st["flops"] / st["launches"]
+    gbs = bpl / (avg_ms * 1e-3) / 1e9
+    tfs = fpl / (avg_ms * 1e-3) / 1e12
+    peak_f = FP32_PEAK_TFS if form == "mixed" else FP64_PEAK_TFS
+    return dict(kernel=name, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None,
+                launches=st["launches"], avg_launch_ms=round(avg_ms, 4),
+                bytes_per_launch=bpl, flops_per_launch=fpl,
+                achieved_tflops=round(tfs, 4), flop_frac=round(tfs / peak_f, 5),
+                share_of_step=None)
+
+
+def cpu_baseline(cfg, side):
+    """The FP64 oracle on a bounded sample of the same workload family."""
+    from threadpoolctl import threadpool_limits
+    from oracle import spalu as O
+    from oracle.nd import nd_order
+    from workloads import make_config
+    P = make_config(cfg, side=side)
+    nd = nd_order(P.dims)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        F = O.factor(nd, P.scipy(), O.Opts(eps=P.eps))
+        t1 = time.perf_counter()
+        x, it, hist = O.solve(F, P.rhs, tol=P.tol, max_iter=50)
+        t2 = time.perf_counter()
+    n = P.n
+    return dict(value=round(n / (t2 - t0), 2), unit="DOF/s", cores=1, kind="oracle",
+                sample="%s %s (%d DOF), %d RHS, eps %g, FP64, refinement to %g: factor %.1f s, "
+                       "solve %.1f s (%d refinement steps, residual %.1e)"
+                       % (P.name, "x".join(map(str, P.dims)), n, P.nrhs, P.eps, P.tol,
+                          t1 - t0, t2 - t1, it, hist[-1].max()))
+
+
+def main():
+    a = parse()
+    ws = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or ws != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2408_14193_amd import spalu as S
+    from workloads import make_config
+    dev = torch.device("cuda:0")
+    P = make_config(a.config, side=a.side, nrhs=a.nrhs)
+    t0 = time.perf_counter()
+    nd = S.ND(P.dims)
+    t_nd = time.perf_counter() - t0
+    log("workload %s %s: N=%d, nrhs=%d, eps=%g, tol=%g, L=%d, ND %.2f s (host)"
+        % (P.name, P.dims, P.n, P.nrhs, P.eps, P.tol, nd.L, t_nd))
+    forms = a.forms.split(",")
+    res = {}
+    for i, f in enumerate(forms):
+        res[f] = run_form(S, P, nd, dev, f, a.steps, a.warmup, profile=(i == 0))
+    head = forms[0]
+    r = res[head]
+    value = P.n / (r["ms_per_step"] * 1e-3)
+    roof = roofline(r["profile"], head)
+    total_ms = sum(st["ms"] for st in r["profile"].values()) / a.steps
+    roof["share_of_step"] = round(r["profile"][roof["kernel"]]["ms"] / a.steps / r["ms_per_step"], 4)
+    out = {
+        "metric": "DOF/s factor+solve to 1e-8 rel. residual, mixed/learned vs plain FP64",
+        "value": round(value, 1),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32" if head == "mixed" else "fp64",
+        "data": "synthetic",
+        "config": {"workload": "%s %s, N=%d, %d RHS, eps=%g, refinement to %g, %s form"
+                               % (P.name, "x".join(map(str, P.dims)), P.n, P.nrhs, P.eps, P.tol, head),
+                   "n": P.n, "nrhs": P.nrhs, "eps": P.eps, "tol": P.tol, "levels": nd.L,
+                   "nd_host_s": round(t_nd, 3)},
+        "factor_ms": round(r["factor_ms"], 3),
+        "solve_ms": round(r["solve_ms"], 3),
+        "refine_iters": r["refine_iters"],
+        "max_rel_residual": r["max_rel_residual"],
+        "converged": r["converged"],
+        "roofline": roof,
+        "kernel_ms_per_step": {k: round(v["ms"] / a.steps, 4) for k, v in
+                               sorted(r["profile"].items(), key=lambda kv: -kv[1]["ms"])},
+        "profiled_kernel_ms_per_step": round(total_ms, 3),
+        "factor_stats": {k: r["factor_info"][k] for k in
+                         ("sparsified", "sample_passes", "resampled", "max_front", "q_tilde",
+                          "flops", "bytes", "workspace_bytes")},
+    }
+    for f in forms[1:]:
+        rf = res[f]
+        vf = P.n / (rf["ms_per_step"] * 1e-3)
+        out["%s_form" % f] = {"value": round(vf, 1), "ms_per_step": round(rf["ms_per_step"], 3),
+                              "factor_ms": round(rf["factor_ms"], 3), "solve_ms": round(rf["solve_ms"], 3),
+                              "refine_iters": rf["refine_iters"],
+                              "max_rel_residual": rf["max_rel_residual"], "converged": rf["converged"]}
+        out["ratio_%s_vs_%s" % (head, f)] = round(value / vf, 3)
+    if not a.no_cpu:
+        log("cpu baseline: oracle on a %dx%d sample ..." % (a.cpu_side, a.cpu_side))
+        out["cpu_baseline"] = cpu_baseline(a.config, a.cpu_side)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

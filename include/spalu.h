@@ -125,8 +125,6 @@ typedef struct {
   int64_t resampled;         /* segments needing more than one pass          */
   int64_t max_front;         /* largest segment size seen                    */
   double q_tilde;            /* max_l e'_l / e_l (Section 6)                 */
-  double flops;              /* algorithmic flops of the factorization       */
-  double bytes;              /* algorithmic HBM bytes of the factorization   */
   int64_t workspace_bytes;
   int32_t singular_level;    /* level of a zero pivot (-1 none)              */
 } spalu_factor_info;
@@ -162,6 +160,12 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
 int spalu_factor_ranks(const spalu_factor_t* f, int32_t* n_before, int32_t* rank, int32_t* h,
                        int32_t* passes);
 
+/* Algorithmic flops and HBM bytes of the factorization (host computation
+ * from the actual segment sizes: leaf LUs and Schur products, ID sampling and
+ * CPQR, transforms and segment LUs, coupling scaling, separator Schur GEMMs
+ * and merges).  Either output may be NULL. */
+int spalu_factor_work(const spalu_factor_t* f, double* flops, double* bytes);
+
 void spalu_factor_free(spalu_factor_t* f);
 
 /* ---------------------------------------------------------------------------
@@ -171,6 +175,11 @@ void spalu_factor_free(spalu_factor_t* f);
 typedef struct {
   double tol;        /* target relative residual; 0 = direct solve only */
   int32_t max_iter;  /* refinement iterations (default 30)              */
+  int32_t graph;     /* 1: capture one application of the factor (all
+                        level sweeps) as a HIP graph on first use and
+                        replay it; the graph is cached on the ND handle and
+                        keyed by every pointer it bakes in.  0: direct
+                        launches.  NULL opts means 0.                    */
 } spalu_solve_opts;
 
 typedef struct {
@@ -191,6 +200,28 @@ int spalu_solve_workspace(const spalu_factor_t* f, int32_t nrhs, size_t* bytes);
 int spalu_solve(const spalu_factor_t* f, int32_t nrhs, const double* B, int64_t ldb, double* X,
                 int64_t ldx, const spalu_solve_opts* opts, void* workspace,
                 size_t workspace_bytes, void* stream, double* rel_res, spalu_solve_info* info);
+
+/* ---------------------------------------------------------------------------
+ * Profiling (process-wide, not thread-safe; for benchmarks).  While on, every
+ * kernel launch of spalu_factor / spalu_solve is bracketed by HIP events on
+ * the launch stream; at the end of each call the elapsed times are summed
+ * per kernel together with the launch's algorithmic bytes and flops (what
+ * the step must move and compute given the actual segment sizes, excluding
+ * padding and staging).  spalu_profile(on) also clears the totals.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double ms;       /* summed event time */
+  double bytes;    /* summed algorithmic HBM bytes */
+  double flops;    /* summed algorithmic flops */
+} spalu_kernel_stat;
+
+void spalu_profile(int32_t on);
+
+/* Copies up to max per-kernel totals into out (host); *count = kernels with
+ * at least one launch.  out may be NULL to query the count. */
+int spalu_profile_read(spalu_kernel_stat* out, int32_t max, int32_t* count);
 
 const char* spalu_last_error(void);
 

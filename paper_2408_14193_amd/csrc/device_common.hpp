@@ -12,6 +12,13 @@ namespace spalu {
 constexpr int WG = 256;      // threads per workgroup (4 wave64)
 constexpr int NWAVE = WG / 64;
 constexpr int LDS_DOUBLES = 4096;  // dynamic LDS staging buffer (32 KB)
+constexpr int LEAF_LDS_DOUBLES = 6144;  // leaf factorization staging (48 KB)
+
+// Staging doubles of a leaf: LU + A_IB solve, then LU + inverse.
+__host__ __device__ inline int leaf_lds_need(int ni, int nb) {
+  const int a = ni * ni + ni * nb, b = 2 * ni * ni;
+  return a > b ? a : b;
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -207,6 +214,35 @@ __device__ inline void block_upper_solve(const TL* LU, int ldl, int n, double* X
     }
     __syncthreads();
   }
+}
+
+// Packed inverses of a unit-lower / upper LU (row-major n x n in W):
+// out[i][j] = (L^{-1})[i][j] for i > j, (U^{-1})[i][j] for i <= j.  X is an
+// n x n double workspace.
+template <typename TO>
+__device__ inline void block_packed_inverse(const double* W, int n, double* X, TO* out) {
+  const int tid = threadIdx.x;
+  // L^{-1}: forward elimination on the identity (columns c <= j are live)
+  for (int t = tid; t < n * n; t += WG) X[t] = (t / n == t % n) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const int m = n - j - 1;
+    for (int t = tid; t < m * (j + 1); t += WG) {
+      const int i = j + 1 + t / (j + 1), cidx = t % (j + 1);
+      X[size_t(i) * n + cidx] -= W[size_t(i) * n + j] * X[size_t(j) * n + cidx];
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < n * n; t += WG)
+    if (t / n > t % n) out[t] = TO(X[t]);
+  __syncthreads();
+  // U^{-1}: back substitution on the identity
+  for (int t = tid; t < n * n; t += WG) X[t] = (t / n == t % n) ? 1.0 : 0.0;
+  __syncthreads();
+  block_upper_solve<double>(W, n, n, X, n, n);
+  for (int t = tid; t < n * n; t += WG)
+    if (t / n <= t % n) out[t] = TO(X[t]);
+  __syncthreads();
 }
 
 }  // namespace spalu

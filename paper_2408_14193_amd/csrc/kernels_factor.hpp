@@ -68,7 +68,7 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
   const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1;
   const int32_t* bverts = iarena + L.ioff;
   int32_t* piv = iarena + L.ioff + nb;
-  const bool fits = ni * ni + ni * nb <= LDS_DOUBLES;
+  const bool fits = leaf_lds_need(ni, nb) <= LEAF_LDS_DOUBLES;
   double* A = fits ? lds : gscratch + size_t(lf) * gscr_stride;
   double* X = A + ni * ni;
   for (int t = tid; t < ni * ni + ni * nb; t += WG) A[t] = 0.0;
@@ -118,8 +118,15 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
     }
     S[t] = T(acc);
   }
+  // A_II^{-1} (stored in place of the LU; the solve applies it as a product)
+  __syncthreads();
+  double* Ai = A + ni * ni;
+  for (int t = tid; t < ni * ni; t += WG) Ai[t] = (t / ni == t % ni) ? 1.0 : 0.0;
+  __syncthreads();
+  block_lower_solve<double>(A, ni, piv, ni, Ai, ni, ni);
+  block_upper_solve<double>(A, ni, ni, Ai, ni, ni);
   T* LUo = varena + L.lu_off;
-  for (int t = tid; t < ni * ni; t += WG) LUo[t] = T(A[t]);
+  for (int t = tid; t < ni * ni; t += WG) LUo[t] = T(Ai[t]);
 }
 
 // Level-L setup: sizes and DOF lists of the level-L segments.
@@ -519,8 +526,9 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   int32_t* piv = perm + S.cap;
   int32_t* tmp = piv + S.cap;  // tag region, >= cap ints
   const T* M = varena + blks[S.diag_blk].off;
-  const bool inlds = size_t(n) * n <= LDS_DOUBLES;
+  const bool inlds = 2 * size_t(n) * n <= LDS_DOUBLES;
   double* W = inlds ? lds : scratch + S.scr_off;
+  double* X = W + size_t(n) * n;  // inverse workspace
   // gather in [r; s] order: o[p] = perm[k + p] (p < nr), perm[p - nr]
   for (int t = tid; t < n * n; t += WG) {
     const int p = t / n, q = t % n;
@@ -550,8 +558,10 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   }
   if (block_lu_window(W, n, n, sp ? nr : 0, piv, &s_piv)) atomicOr(status, 1);
   __syncthreads();
+  // packed inverses: strictly lower part of L^{-1} (unit diagonal implied)
+  // and upper part of U^{-1}, so every later application is a product
   T* LU = varena + S.lu_off;
-  for (int t = tid; t < n * n; t += WG) LU[t] = T(W[t]);
+  block_packed_inverse(W, n, X, LU);
   if (sp) {
     for (int p = tid; p < n; p += WG) tmp[p] = dofs[p < nr ? perm[k + p] : perm[p - nr]];
     __syncthreads();
@@ -559,7 +569,10 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   }
 }
 
-// Coupling scaling: A'_{cd} = L_ss,c^{-1} P_s,c A_cd[s_c, s_d] U_ss,d^{-1}.
+// Coupling scaling: A'_{cd} = L_ss,c^{-1} P_s,c A_cd[s_c, s_d] U_ss,d^{-1},
+// with the skeleton blocks of the packed inverses of c and d (the inverse of
+// a block triangular matrix has the inverse of its trailing diagonal block as
+// its trailing diagonal block).
 template <typename T>
 __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_t* blk_list, int nlist,
                                                   const DSeg* segs, const int32_t* iarena, T* varena,
@@ -580,87 +593,71 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
   const int32_t* pivc = permc + segs[c].cap;
   const T* A = varena + B.off;
   T* out = varena + B.soff;
-  const bool inlds = size_t(kc) * kd <= LDS_DOUBLES;
-  // staging: LDS, or in place in the output region (promoted to double
-  // only when T is double; float blocks that do not fit are staged in
-  // double through the output region of twice the size is not available,
-  // so they are processed column by column below)
-  double* X = lds;
+  const T* Lc = varena + segs[c].lu_off;  // packed inverse of c
+  const T* Ud = varena + segs[d].lu_off;  // packed inverse of d
+  // row map of the skeleton-part pivots of c: row i of P_s X is row rm[i]
+  __shared__ int s_rm[1024];
+  int* rm = kc <= 1024 ? s_rm : reinterpret_cast<int*>(lds);
+  if (tid == 0) {
+    for (int i = 0; i < kc; ++i) rm[i] = i;
+    for (int j = 0; j < kc; ++j) {
+      const int p = pivc[nrc + j] - nrc;
+      const int t = rm[j];
+      rm[j] = rm[p];
+      rm[p] = t;
+    }
+  }
+  __syncthreads();
+  const bool inlds = 2 * size_t(kc) * kd <= LDS_DOUBLES && kc <= 1024;
   if (inlds) {
+    double* X = lds;
+    double* Yb = lds + size_t(kc) * kd;
     for (int t = tid; t < kc * kd; t += WG) {
       const int i = t / kd, j = t % kd;
-      const int si = spc ? permc[i] : i, sj = spd ? permd[j] : j;
+      const int r = rm[i];
+      const int si = spc ? permc[r] : r, sj = spd ? permd[j] : j;
       X[t] = double(A[size_t(si) * nd + sj]);
     }
     __syncthreads();
-    const T* LUc = varena + segs[c].lu_off;
-    const T* LUd = varena + segs[d].lu_off;
-    // rows: P_s then L_ss^{-1} (skeleton part of c's LU)
-    for (int col = tid; col < kd; col += WG)
-      for (int j = 0; j < kc; ++j) {
-        const int p = pivc[nrc + j] - nrc;
-        if (p != j) {
-          const double t = X[size_t(j) * kd + col];
-          X[size_t(j) * kd + col] = X[size_t(p) * kd + col];
-          X[size_t(p) * kd + col] = t;
-        }
-      }
-    __syncthreads();
-    for (int j = 0; j < kc; ++j) {
-      const int m = kc - j - 1;
-      for (int t = tid; t < m * kd; t += WG) {
-        const int i = j + 1 + t / kd, col = t % kd;
-        X[size_t(i) * kd + col] -= double(LUc[size_t(nrc + i) * nc + nrc + j]) * X[size_t(j) * kd + col];
-      }
-      __syncthreads();
-    }
-    // columns: X U_ss,d^{-1}
-    for (int j = 0; j < kd; ++j) {
-      const double u = double(LUd[size_t(nrd + j) * nd + nrd + j]);
-      for (int i = tid; i < kc; i += WG) X[size_t(i) * kd + j] /= u;
-      __syncthreads();
-      const int m = kd - j - 1;
-      for (int t = tid; t < kc * m; t += WG) {
-        const int i = t / m, col = j + 1 + t % m;
-        X[size_t(i) * kd + col] -= X[size_t(i) * kd + j] * double(LUd[size_t(nrd + j) * nd + nrd + col]);
-      }
-      __syncthreads();
-    }
-    for (int t = tid; t < kc * kd; t += WG) out[t] = T(X[t]);
-  } else {
-    // large block: one thread per column for the row solve, then one thread
-    // per row for the column solve, working in the output region
     for (int t = tid; t < kc * kd; t += WG) {
       const int i = t / kd, j = t % kd;
-      const int si = spc ? permc[i] : i, sj = spd ? permd[j] : j;
+      double v = X[t];
+      const T* lrow = Lc + size_t(nrc + i) * nc + nrc;
+      for (int u = 0; u < i; ++u) v += double(lrow[u]) * X[size_t(u) * kd + j];
+      Yb[t] = v;
+    }
+    __syncthreads();
+    for (int t = tid; t < kc * kd; t += WG) {
+      const int i = t / kd, j = t % kd;
+      double v = 0.0;
+      for (int u = 0; u <= j; ++u) v += Yb[size_t(i) * kd + u] * double(Ud[size_t(nrd + u) * nd + nrd + j]);
+      out[t] = T(v);
+    }
+  } else {
+    // large block: in place in the output region; columns for L^{-1}
+    // (rows descending), then rows for U^{-1} (columns descending)
+    for (int t = tid; t < kc * kd; t += WG) {
+      const int i = t / kd, j = t % kd;
+      const int r = rm[i];
+      const int si = spc ? permc[r] : r, sj = spd ? permd[j] : j;
       out[t] = A[size_t(si) * nd + sj];
     }
     __syncthreads();
-    const T* LUc = varena + segs[c].lu_off;
-    const T* LUd = varena + segs[d].lu_off;
-    for (int col = tid; col < kd; col += WG) {
-      for (int j = 0; j < kc; ++j) {
-        const int p = pivc[nrc + j] - nrc;
-        if (p != j) {
-          const T t = out[size_t(j) * kd + col];
-          out[size_t(j) * kd + col] = out[size_t(p) * kd + col];
-          out[size_t(p) * kd + col] = t;
-        }
+    for (int j = tid; j < kd; j += WG)
+      for (int i = kc - 1; i > 0; --i) {
+        double v = double(out[size_t(i) * kd + j]);
+        const T* lrow = Lc + size_t(nrc + i) * nc + nrc;
+        for (int u = 0; u < i; ++u) v += double(lrow[u]) * double(out[size_t(u) * kd + j]);
+        out[size_t(i) * kd + j] = T(v);
       }
-      for (int i = 1; i < kc; ++i) {
-        double s = double(out[size_t(i) * kd + col]);
-        for (int j = 0; j < i; ++j) s -= double(LUc[size_t(nrc + i) * nc + nrc + j]) * double(out[size_t(j) * kd + col]);
-        out[size_t(i) * kd + col] = T(s);
-      }
-    }
     __syncthreads();
-    for (int i = tid; i < kc; i += WG) {
-      for (int j = 0; j < kd; ++j) {
-        double s = double(out[size_t(i) * kd + j]);
-        for (int t = 0; t < j; ++t) s -= double(out[size_t(i) * kd + t]) * double(LUd[size_t(nrd + t) * nd + nrd + j]);
-        out[size_t(i) * kd + j] = T(s / double(LUd[size_t(nrd + j) * nd + nrd + j]));
+    for (int i = tid; i < kc; i += WG)
+      for (int j = kd - 1; j >= 0; --j) {
+        double v = 0.0;
+        for (int u = 0; u <= j; ++u)
+          v += double(out[size_t(i) * kd + u]) * double(Ud[size_t(nrd + u) * nd + nrd + j]);
+        out[size_t(i) * kd + j] = T(v);
       }
-    }
   }
 }
 

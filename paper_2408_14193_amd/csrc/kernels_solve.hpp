@@ -20,6 +20,12 @@ __global__ void k_rhs_in(const double* B, int64_t ldb, int64_t n, int nrhs, T* W
 }
 
 template <typename T>
+__global__ void k_copy(const T* src, T* dst, int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) dst[t] = src[t];
+}
+
+template <typename T>
 __global__ void k_rhs_out(const T* W, int64_t n, int nrhs, double* X, int64_t ldx, int accumulate) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n * nrhs) return;
@@ -32,7 +38,7 @@ __global__ void k_rhs_out(const T* W, int64_t n, int nrhs, double* X, int64_t ld
 }
 
 // Leaf interiors: Z_I = A_II^{-1} W_I (forward) or
-// W_I = A_II^{-1} (B_I - A_IB W_B) (backward).
+// W_I = A_II^{-1} (B_I - A_IB W_B) (backward), with the stored inverse.
 template <typename T, bool BACKWARD>
 __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nleaf, GridGeom g,
                                                    const int64_t* rowptr, const int32_t* colind,
@@ -42,10 +48,9 @@ __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nlea
   const int lf = blockIdx.x;
   if (lf >= nleaf) return;
   const DLeaf L = leaves[lf];
-  const int ni = L.ni, nb = L.nb, tid = threadIdx.x;
+  const int ni = L.ni, tid = threadIdx.x;
   const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1;
-  const int32_t* piv = iarena + L.ioff + nb;
-  const T* LU = varena + L.lu_off;
+  const T* Ai = varena + L.lu_off;
   const int jc = ni > 0 ? (LDS_DOUBLES / ni < nrhs ? LDS_DOUBLES / ni : nrhs) : nrhs;
   for (int j0 = 0; j0 < nrhs; j0 += jc) {
     const int nc = nrhs - j0 < jc ? nrhs - j0 : jc;
@@ -70,16 +75,17 @@ __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nlea
       lds[t] = v;
     }
     __syncthreads();
-    block_lower_solve<T>(LU, ni, piv, ni, lds, nc, nc);
-    block_upper_solve<T>(LU, ni, ni, lds, nc, nc);
     for (int t = tid; t < ni * nc; t += WG) {
       const int i = t / nc, j = t % nc;
+      const T* arow = Ai + size_t(i) * ni;
+      double acc = 0.0;
+      for (int q = 0; q < ni; ++q) acc += double(arow[q]) * lds[q * nc + j];
       const int ix = i % w0, iy = (i / w0) % w1, iz = i / (w0 * w1);
       const int u = (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz));
       if (BACKWARD)
-        W[size_t(u) * nrhs + j0 + j] = T(lds[t]);
+        W[size_t(u) * nrhs + j0 + j] = T(acc);
       else
-        Z[size_t(u) * nrhs + j0 + j] = T(lds[t]);
+        Z[size_t(u) * nrhs + j0 + j] = T(acc);
     }
     __syncthreads();
   }
@@ -103,7 +109,8 @@ __global__ void k_sep_from_leaves(int64_t n, const int8_t* seplev, const int64_t
 }
 
 // Per segment of level l: forward (U_T, then P and L^{-1}) or backward
-// (U^{-1}, then L_T) on its DOFs in [remainder; skeleton] order.
+// (U^{-1}, then L_T) on its DOFs in [remainder; skeleton] order, with the
+// packed inverses of the two-stage LU.
 template <typename T, bool BACKWARD>
 __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, const int32_t* iarena,
                                                   const T* varena, DLevelDyn dyn, T* W, int nrhs) {
@@ -118,20 +125,22 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
   const bool sp = dyn.passes[c] > 0 && nr > 0 && k > 0;
   const int32_t* dofs = iarena + S.ioff;
   const int32_t* piv = dofs + 2 * S.cap;
-  const T* LU = varena + S.lu_off;
+  const T* Inv = varena + S.lu_off;
   const T* Tm = varena + S.t_off;
-  if (n > LDS_DOUBLES) {
+  if (2 * n > LDS_DOUBLES) {
     // too large for the staging buffer: poison the result so the residual
     // check reports the failure instead of returning a wrong solution
     for (int t = tid; t < n * nrhs; t += WG) W[size_t(dofs[t / nrhs]) * nrhs + t % nrhs] = T(NAN);
     return;
   }
-  const int jc = LDS_DOUBLES / n < nrhs ? LDS_DOUBLES / n : nrhs;
+  const int jc = LDS_DOUBLES / (2 * n) < nrhs ? LDS_DOUBLES / (2 * n) : nrhs;
   for (int j0 = 0; j0 < nrhs; j0 += jc) {
     const int nc = nrhs - j0 < jc ? nrhs - j0 : jc;
+    double* X = lds;
+    double* Yb = lds + size_t(n) * nc;
     for (int t = tid; t < n * nc; t += WG) {
       const int i = t / nc, j = t % nc;
-      lds[t] = double(W[size_t(dofs[i]) * nrhs + j0 + j]);
+      X[t] = double(W[size_t(dofs[i]) * nrhs + j0 + j]);
     }
     __syncthreads();
     if (!BACKWARD) {
@@ -139,27 +148,50 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
         for (int t = tid; t < nr * nc; t += WG) {
           const int q = t / nc, j = t % nc;
           double s = 0.0;
-          for (int i = 0; i < k; ++i) s += double(Tm[size_t(i) * nr + q]) * lds[size_t(nr + i) * nc + j];
-          lds[t] -= s;
+          for (int i = 0; i < k; ++i) s += double(Tm[size_t(i) * nr + q]) * X[size_t(nr + i) * nc + j];
+          X[t] -= s;
         }
         __syncthreads();
       }
-      block_lower_solve<T>(LU, n, piv, n, lds, nc, nc);
+      for (int j = tid; j < nc; j += WG)
+        for (int r = 0; r < n; ++r) {
+          const int p = piv[r];
+          if (p != r) {
+            const double t = X[size_t(r) * nc + j];
+            X[size_t(r) * nc + j] = X[size_t(p) * nc + j];
+            X[size_t(p) * nc + j] = t;
+          }
+        }
+      __syncthreads();
+      for (int t = tid; t < n * nc; t += WG) {
+        const int i = t / nc, j = t % nc;
+        const T* row = Inv + size_t(i) * n;
+        double v = X[t];
+        for (int u = 0; u < i; ++u) v += double(row[u]) * X[size_t(u) * nc + j];
+        W[size_t(dofs[i]) * nrhs + j0 + j] = T(v);
+      }
     } else {
-      block_upper_solve<T>(LU, n, n, lds, nc, nc);
+      for (int t = tid; t < n * nc; t += WG) {
+        const int i = t / nc, j = t % nc;
+        const T* row = Inv + size_t(i) * n;
+        double v = 0.0;
+        for (int u = i; u < n; ++u) v += double(row[u]) * X[size_t(u) * nc + j];
+        Yb[t] = v;
+      }
+      __syncthreads();
       if (sp) {
         for (int t = tid; t < k * nc; t += WG) {
           const int i = t / nc, j = t % nc;
           double s = 0.0;
-          for (int q = 0; q < nr; ++q) s += double(Tm[size_t(i) * nr + q]) * lds[size_t(q) * nc + j];
-          lds[size_t(nr + i) * nc + j] -= s;
+          for (int q = 0; q < nr; ++q) s += double(Tm[size_t(i) * nr + q]) * Yb[size_t(q) * nc + j];
+          Yb[size_t(nr + i) * nc + j] -= s;
         }
         __syncthreads();
       }
-    }
-    for (int t = tid; t < n * nc; t += WG) {
-      const int i = t / nc, j = t % nc;
-      W[size_t(dofs[i]) * nrhs + j0 + j] = T(lds[t]);
+      for (int t = tid; t < n * nc; t += WG) {
+        const int i = t / nc, j = t % nc;
+        W[size_t(dofs[i]) * nrhs + j0 + j] = T(Yb[t]);
+      }
     }
     __syncthreads();
   }

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -68,18 +70,42 @@ struct Layout {
   size_t bytes = 0;
   int64_t nseg_total = 0;
   std::vector<int64_t> seg_base;  // per level
+  size_t leaf_i0 = 0, leaf_i1 = 0;  // int-arena range of the leaf lists
+  int dim = 2, L = 0;
+  double nsep_verts = 0.0;  // vertices on separators (all levels)
+  // host image of the tables (pinned), rebuilt only when rho changes
+  char* image = nullptr;
+  size_t image_bytes = 0;
+  double image_rho = -1.0;
+  ~Layout() {
+    if (image) (void)hipHostFree(image);
+  }
 };
 
 }  // namespace
 
+// Captured solve sweeps: one graph per set of pointers it bakes in.
+struct SweepGraph {
+  const void *ws, *sw, *rowptr, *colind, *vals;
+  int nrhs, prec;
+  hipGraphExec_t exec;
+};
+
 struct spalu_nd_s {
   Plan plan;
-  std::unique_ptr<Layout> layout[2];
+  std::shared_ptr<Layout> layout[2];
+  std::vector<SweepGraph> graphs;  // most recent last
+  hipStream_t capture_stream = nullptr;
+  ~spalu_nd_s() {
+    for (auto& gph : graphs) (void)hipGraphExecDestroy(gph.exec);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
 };
 
 struct spalu_factor_s {
   const spalu_nd_t* nd = nullptr;
   const Layout* lay = nullptr;
+  std::shared_ptr<const Layout> lay_sp;
   int prec = 0;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
@@ -88,6 +114,8 @@ struct spalu_factor_s {
   const int32_t* colind = nullptr;
   const double* vals = nullptr;
   GridGeom g{};
+  // per level: n, k, nr, h, passes, off (host copy after the factorization)
+  std::shared_ptr<std::vector<std::vector<int32_t>>> dyn_host;
 };
 
 namespace {
@@ -95,12 +123,15 @@ namespace {
 // ---------------------------------------------------------------------------
 // Static layout of the factorization for one ND and precision.
 // ---------------------------------------------------------------------------
-std::unique_ptr<Layout> build_layout(const Plan& P, int prec) {
-  auto lay = std::make_unique<Layout>();
+std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
+  auto lay = std::make_shared<Layout>();
   Layout& Y = *lay;
   Y.prec = prec;
   Y.vsize = prec == SPALU_FP32 ? 4 : 8;
   const int L = P.L;
+  Y.dim = P.dim;
+  Y.L = L;
+  for (int8_t sl : P.seplev) Y.nsep_verts += sl > 0 ? 1.0 : 0.0;
   Y.lv.assign(L + 1, LevelTabs());
   size_t iar = 0, var = 0, pool = 0;
   Y.seg_base.assign(L + 2, 0);
@@ -170,7 +201,7 @@ std::unique_ptr<Layout> build_layout(const Plan& P, int prec) {
       var += size_t(cap * cap);
       D.t_off = int64_t(var);
       var += size_t(cap * cap / 4 + 1);
-      size_t need = size_t(cap * cap);
+      size_t need = size_t(2 * cap * cap);
       if ((D.flags & SEG_REGULAR) && (D.flags & SEG_HAS_NBR))
         need = std::max(need, size_t((3 * rcap[c] + 9) * cap));
       D.scr_off = int64_t(level_pool);
@@ -274,9 +305,11 @@ std::unique_ptr<Layout> build_layout(const Plan& P, int prec) {
     var += size_t(D.ni) * D.ni;
     D.s_off = int64_t(var);
     var += size_t(nb) * nb;
-    leaf_need = std::max(leaf_need, size_t(D.ni) * D.ni + size_t(D.ni) * nb);
+    leaf_need = std::max(leaf_need, size_t(leaf_lds_need(D.ni, nb)));
   }
-  if (leaf_need > size_t(LDS_DOUBLES)) {
+  Y.leaf_i0 = Y.leaves.empty() ? iar : size_t(Y.leaves[0].ioff);
+  Y.leaf_i1 = iar;
+  if (leaf_need > size_t(LEAF_LDS_DOUBLES)) {
     Y.leaf_scr_stride = leaf_need;
     pool = std::max(pool, leaf_need * P.leaves.size());
   }
@@ -368,6 +401,296 @@ const X* tab(char* ws, size_t off) {
 unsigned nblocks(int64_t n, int b = WG) { return unsigned(std::max<int64_t>(1, (n + b - 1) / b)); }
 
 constexpr size_t LDS_BYTES = size_t(LDS_DOUBLES) * 8;
+constexpr size_t LEAF_LDS_BYTES = size_t(LEAF_LDS_DOUBLES) * 8;
+
+
+// ---------------------------------------------------------------------------
+// Profiling: when enabled, every launch is bracketed by HIP events on the
+// launch stream; after the call's final synchronisation the elapsed times
+// are accumulated per kernel together with the launch's algorithmic bytes
+// and flops, computed from the actual segment sizes.
+// ---------------------------------------------------------------------------
+enum KId {
+  K_CHECK, K_INIT, K_LEAF, K_ASM, K_ID, K_LU, K_SCALE, K_MSIZE, K_MELIM,
+  K_LSOLVE_F, K_SEPLEAF, K_SSOLVE_F, K_SEPFWD, K_SEPBWD, K_SSOLVE_B, K_LSOLVE_B,
+  K_RHSIN, K_RHSOUT, K_RESID, K_REDUCE, K_APPLY, K_COUNT
+};
+const char* const kNames[K_COUNT] = {
+    "check_pattern", "init_level", "leaf_factor", "assemble_leafL", "seg_id", "seg_lu", "blk_scale",
+    "merge_sizes", "merge_elim", "leaf_solve_fwd", "sep_from_leaves", "seg_solve_fwd", "sep_fwd",
+    "sep_bwd", "seg_solve_bwd", "leaf_solve_bwd", "rhs_in", "rhs_out", "residual", "reduce_cols",
+    "solve_sweep_graph"};
+
+struct PendingLaunch {
+  int kid, level;
+  hipEvent_t a, b;
+};
+
+struct TimedLaunch {
+  int kid, level, nrhs;
+  double ms;
+  int64_t nrows;
+  std::shared_ptr<const Layout> lay;
+  std::shared_ptr<const std::vector<std::vector<int32_t>>> dyn;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<PendingLaunch> pend;
+  std::vector<TimedLaunch> done;  // accounted lazily in spalu_profile_read
+  int64_t launches[K_COUNT] = {};
+  double ms[K_COUNT] = {}, bytes[K_COUNT] = {}, flops[K_COUNT] = {};
+  void reset() {
+    for (auto& p : pend) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    pend.clear();
+    done.clear();
+    for (int k = 0; k < K_COUNT; ++k) launches[k] = 0, ms[k] = bytes[k] = flops[k] = 0.0;
+  }
+};
+Profiler g_prof;
+const bool g_prof_verbose = std::getenv("SPALU_PROFILE_VERBOSE") != nullptr;
+
+int prof_begin(int kid, int level, hipStream_t st) {
+  if (!g_prof.on) return -1;
+  PendingLaunch p{kid, level, nullptr, nullptr};
+  if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return -1;
+  (void)hipEventRecord(p.a, st);
+  g_prof.pend.push_back(p);
+  return int(g_prof.pend.size()) - 1;
+}
+
+void prof_end(int idx, hipStream_t st) {
+  if (idx >= 0) (void)hipEventRecord(g_prof.pend[size_t(idx)].b, st);
+}
+
+#define LAUNCH(kid, level, ...)                  \
+  do {                                           \
+    const int pi_ = prof_begin(kid, level, st);  \
+    __VA_ARGS__;                                 \
+    HIPCHK(hipGetLastError());                   \
+    prof_end(pi_, st);                           \
+  } while (0)
+
+// Algorithmic work of one launch (bytes that the step must move, flops it
+// must do), from the actual sizes; nrhs = 0 for factorization kernels.
+using DynHost = std::vector<std::vector<int32_t>>;
+
+void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, int nrhs, double& by,
+             double& fl) {
+  const double vs = double(Y.vsize);
+  const double nnzrow = 2.0 * Y.dim + 1.0;
+  by = fl = 0.0;
+  auto dynv = [&](int lev, int which, int c) { return double(dh[lev][size_t(which) * Y.lv[lev].segs.size() + c]); };
+  switch (kid) {
+    case K_LEAF:
+      for (auto& L : Y.leaves) {
+        const double ni = L.ni, nb = L.nb;
+        by += (ni + nb) * (nnzrow * 12.0 + 8.0) + ni * ni * vs + ni * 4.0 + nb * nb * vs;
+        fl += 2.0 / 3.0 * ni * ni * ni + 2.0 * ni * ni * nb + 2.0 * nb * nb;
+      }
+      break;
+    case K_ASM: {
+      const LevelTabs& T = Y.lv[l];
+      for (size_t b = 0; b < T.blks.size(); ++b) {
+        const double e = dynv(l, 0, T.blks[b].c) * dynv(l, 0, T.blks[b].d);
+        by += e * vs * (1.0 + double(Y.lc_ptr[b + 1] - Y.lc_ptr[b]));
+        fl += e * double(Y.lc_ptr[b + 1] - Y.lc_ptr[b]);
+      }
+      break;
+    }
+    case K_ID: {
+      const LevelTabs& T = Y.lv[l];
+      for (size_t c = 0; c < T.segs.size(); ++c) {
+        if (dynv(l, 4, int(c)) <= 0) continue;
+        const double n = dynv(l, 0, int(c)), k = dynv(l, 1, int(c)), h = dynv(l, 3, int(c));
+        double R = 0.0;
+        for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) R += 2.0 * dynv(l, 0, T.nbrs[e].d);
+        by += R * n * vs + k * (n - k) * vs + n * 4.0;
+        fl += 2.0 * h * R * n + 4.0 * (R < h ? R : h) * n * k + k * k * (n - k);
+      }
+      break;
+    }
+    case K_LU: {
+      const LevelTabs& T = Y.lv[l];
+      for (size_t c = 0; c < T.segs.size(); ++c) {
+        const double n = dynv(l, 0, int(c)), k = dynv(l, 1, int(c)), nr = dynv(l, 2, int(c));
+        by += 2.0 * n * n * vs + k * nr * vs + n * 8.0;
+        fl += 2.0 / 3.0 * n * n * n + 4.0 * n * k * nr;
+      }
+      break;
+    }
+    case K_SCALE: {
+      const LevelTabs& T = Y.lv[l];
+      for (int32_t b : T.scale_list) {
+        const double kc = dynv(l, 1, T.blks[b].c), kd = dynv(l, 1, T.blks[b].d);
+        by += 2.0 * kc * kd * vs + 0.5 * (kc * kc + kd * kd) * vs;
+        fl += kc * kc * kd + kc * kd * kd;
+      }
+      break;
+    }
+    case K_MSIZE: {
+      const LevelTabs& T = Y.lv[l];
+      for (size_t c = 0; c < T.segs.size(); ++c) by += 8.0 * dynv(l, 1, int(c));
+      break;
+    }
+    case K_MELIM: {
+      const LevelTabs& T = Y.lv[l];
+      const LevelTabs& U = Y.lv[l - 1];
+      for (size_t b = 0; b < U.blks.size(); ++b) {
+        by += dynv(l - 1, 0, U.blks[b].c) * dynv(l - 1, 0, U.blks[b].d) * vs;
+        for (int q = T.task_ptr[b]; q < T.task_ptr[b + 1]; ++q) {
+          const DTask& tk = T.tasks[size_t(q)];
+          const double kc = dynv(l, 1, tk.c), kd = dynv(l, 1, tk.d);
+          if (tk.src >= 0) by += kc * kd * vs;
+          for (int e = tk.sep_begin; e < tk.sep_end; ++e) {
+            const double ks = dynv(l, 1, T.terms[size_t(e)].s);
+            by += (kc * ks + ks * kd) * vs;
+            fl += 2.0 * kc * ks * kd;
+          }
+        }
+      }
+      break;
+    }
+    case K_LSOLVE_F:
+    case K_LSOLVE_B:
+      for (auto& L : Y.leaves) {
+        const double ni = L.ni, nb = L.nb;
+        by += ni * ni * vs + 2.0 * ni * nrhs * vs + (kid == K_LSOLVE_B ? nb * nrhs * vs + ni * nnzrow * 12.0 : 0.0);
+        fl += 2.0 * ni * ni * nrhs;
+      }
+      break;
+    case K_SEPLEAF: {
+      const double nsep = Y.nsep_verts;
+      by = nsep * (nnzrow * 12.0 + 8.0 + 3.0 * nrhs * vs);
+      fl = 2.0 * nsep * 2.0 * nrhs;
+      break;
+    }
+    case K_SSOLVE_F:
+    case K_SSOLVE_B: {
+      const LevelTabs& T = Y.lv[l];
+      for (size_t c = 0; c < T.segs.size(); ++c) {
+        const double n = dynv(l, 0, int(c)), k = dynv(l, 1, int(c)), nr = dynv(l, 2, int(c));
+        by += 0.5 * n * n * vs + k * nr * vs + 2.0 * n * nrhs * vs + n * 4.0;
+        fl += n * n * nrhs + 2.0 * k * nr * nrhs;
+      }
+      break;
+    }
+    case K_SEPFWD:
+    case K_SEPBWD: {
+      const LevelTabs& T = Y.lv[l];
+      for (size_t c = 0; c < T.segs.size(); ++c) {
+        const bool sep = (T.segs[c].flags & SEG_IS_SEP) != 0;
+        if (sep != (kid == K_SEPBWD)) continue;
+        const double kc = dynv(l, 1, int(c));
+        bool any = false;
+        for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) {
+          if (kid == K_SEPFWD && !T.nbrs[e].d_is_sep) continue;
+          const double kd = dynv(l, 1, T.nbrs[e].d);
+          by += kc * kd * vs + kd * nrhs * vs;
+          fl += 2.0 * kc * kd * nrhs;
+          any = true;
+        }
+        if (any) by += 2.0 * kc * nrhs * vs;
+      }
+      break;
+    }
+    case K_RHSIN:
+    case K_RHSOUT:
+      by = double(nrows) * nrhs * (8.0 + vs);
+      break;
+    case K_RESID:
+      by = double(nrows) * (nnzrow * 12.0 + 8.0) + 3.0 * double(nrows) * nrhs * 8.0;
+      fl = 2.0 * double(nrows) * nnzrow * nrhs;
+      break;
+    case K_APPLY: {
+      double a, b;
+      for (int kid2 : {int(K_LSOLVE_F), int(K_SEPLEAF), int(K_LSOLVE_B)}) {
+        account(Y, dh, nrows, kid2, 0, nrhs, a, b);
+        by += a;
+        fl += b;
+      }
+      for (int l2 = 1; l2 <= Y.L; ++l2)
+        for (int kid2 : {int(K_SSOLVE_F), int(K_SEPFWD), int(K_SEPBWD), int(K_SSOLVE_B)}) {
+          account(Y, dh, nrows, kid2, l2, nrhs, a, b);
+          by += a;
+          fl += b;
+        }
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// Collects the event times of the call's launches; the byte/flop accounting
+// happens later (spalu_profile_read), outside any timed region.
+void prof_flush(const spalu_factor_t* F, int nrhs) {
+  if (!g_prof.on) return;
+  for (auto& p : g_prof.pend) {
+    float ms = 0.f;
+    (void)hipEventSynchronize(p.b);
+    if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) ms = 0.f;
+    g_prof.done.push_back(TimedLaunch{p.kid, p.level, nrhs, double(ms), F->n, F->lay_sp, F->dyn_host});
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  g_prof.pend.clear();
+}
+
+void prof_account_pending() {
+  for (auto& t : g_prof.done) {
+    double by, fl;
+    account(*t.lay, *t.dyn, t.nrows, t.kid, t.level, t.nrhs, by, fl);
+    if (g_prof_verbose)
+      std::fprintf(stderr, "spalu-prof %-16s level %2d  %9.4f ms  %12.0f B  %12.0f flop\n", kNames[t.kid], t.level,
+                   t.ms, by, fl);
+    g_prof.ms[t.kid] += t.ms;
+    g_prof.bytes[t.kid] += by;
+    g_prof.flops[t.kid] += fl;
+    g_prof.launches[t.kid] += 1;
+  }
+  g_prof.done.clear();
+}
+
+// One device-to-host copy of every level's size arrays (they are adjacent
+// in the workspace).
+int read_dyn_host(spalu_factor_t* F) {
+  const Layout& Y = *F->lay;
+  const int L = F->nd->plan.L;
+  const size_t lo = Y.lv[1].o_dyn, hi = Y.lv[L].o_dyn + 6 * Y.lv[L].segs.size() * 4;
+  std::vector<char> raw(hi - lo);
+  HIPCHK(hipMemcpy(raw.data(), F->ws + lo, raw.size(), hipMemcpyDeviceToHost));
+  auto dh = std::make_shared<DynHost>(size_t(L) + 1);
+  for (int l = 1; l <= L; ++l) {
+    (*dh)[l].resize(6 * Y.lv[l].segs.size());
+    std::memcpy((*dh)[l].data(), raw.data() + (Y.lv[l].o_dyn - lo), (*dh)[l].size() * 4);
+  }
+  F->dyn_host = dh;
+  return SPALU_OK;
+}
+
+// Algorithmic flops and bytes of the whole factorization.
+void factor_work(const spalu_factor_t* F, double& fl, double& by) {
+  const Layout& Y = *F->lay;
+  const DynHost& dh = *F->dyn_host;
+  fl = by = 0.0;
+  double a, b;
+  for (int kid : {int(K_LEAF), int(K_ASM)}) {
+    account(Y, dh, F->n, kid, Y.L, 0, a, b);
+    by += a;
+    fl += b;
+  }
+  for (int l = 1; l <= Y.L; ++l)
+    for (int kid : {int(K_ID), int(K_LU), int(K_SCALE), int(K_MSIZE), int(K_MELIM)}) {
+      if (l == 1 && (kid == K_MSIZE || kid == K_MELIM)) continue;
+      account(Y, dh, F->n, kid, l, 0, a, b);
+      by += a;
+      fl += b;
+    }
+}
 
 template <typename T>
 int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) {
@@ -381,24 +704,20 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
   int* status = reinterpret_cast<int*>(ws + Y.o_status);
   const int L = P.L;
   HIPCHK(hipMemsetAsync(status, 0, 64, st));
-  k_check_pattern<<<nblocks(F->n), WG, 0, st>>>(F->g, F->n, F->rowptr, F->colind, status);
-  HIPCHK(hipGetLastError());
+  LAUNCH(K_CHECK, 0, k_check_pattern<<<nblocks(F->n), WG, 0, st>>>(F->g, F->n, F->rowptr, F->colind, status));
   {
     const LevelTabs& TL = Y.lv[L];
     DLevelDyn dL = dyn_of(ws, Y, L);
-    k_init_level<<<unsigned(TL.segs.size()), 64, 0, st>>>(tab<DSeg>(ws, TL.o_segs), int(TL.segs.size()),
+    LAUNCH(K_INIT, L, k_init_level<<<unsigned(TL.segs.size()), 64, 0, st>>>(tab<DSeg>(ws, TL.o_segs), int(TL.segs.size()),
                                                            tab<int32_t>(ws, Y.o_vptrL),
-                                                           tab<int32_t>(ws, Y.o_vertsL), iar, dL);
-    HIPCHK(hipGetLastError());
-    k_leaf_factor<T><<<unsigned(Y.leaves.size()), WG, LDS_BYTES, st>>>(
+                                                           tab<int32_t>(ws, Y.o_vertsL), iar, dL));
+    LAUNCH(K_LEAF, L, k_leaf_factor<T><<<unsigned(Y.leaves.size()), WG, LEAF_LDS_BYTES, st>>>(
         tab<DLeaf>(ws, Y.o_leaves), int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var,
-        scr, int64_t(Y.leaf_scr_stride), status);
-    HIPCHK(hipGetLastError());
-    k_assemble_leafL<T><<<unsigned(TL.blks.size()), WG, 0, st>>>(
+        scr, int64_t(Y.leaf_scr_stride), status));
+    LAUNCH(K_ASM, L, k_assemble_leafL<T><<<unsigned(TL.blks.size()), WG, 0, st>>>(
         tab<DBlk>(ws, TL.o_blks), int(TL.blks.size()), tab<DSeg>(ws, TL.o_segs), iar, dL,
         tab<int32_t>(ws, Y.o_lc_ptr), tab<DLeafContrib>(ws, Y.o_lc), tab<DLeaf>(ws, Y.o_leaves),
-        F->rowptr, F->colind, F->vals, var);
-    HIPCHK(hipGetLastError());
+        F->rowptr, F->colind, F->vals, var));
   }
   for (int l = L; l >= 1; --l) {
     const LevelTabs& T_ = Y.lv[l];
@@ -415,31 +734,29 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     prm.level = l;
     prm.seg_base = int(Y.seg_base[l]);
     prm.h_init = o.h_init;
-    k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), blks, F->g, iar,
-                                                     var, scr, d, prm);
-    HIPCHK(hipGetLastError());
-    k_seg_lu<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, blks, iar, var, scr, d, status);
-    HIPCHK(hipGetLastError());
+    LAUNCH(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), blks, F->g, iar,
+                                                     var, scr, d, prm));
+    LAUNCH(K_LU, l, k_seg_lu<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, blks, iar, var, scr, d, status));
     if (!T_.scale_list.empty()) {
-      k_blk_scale<T><<<unsigned(T_.scale_list.size()), WG, LDS_BYTES, st>>>(
-          blks, tab<int32_t>(ws, T_.o_scale), int(T_.scale_list.size()), segs, iar, var, d);
-      HIPCHK(hipGetLastError());
+      LAUNCH(K_SCALE, l, k_blk_scale<T><<<unsigned(T_.scale_list.size()), WG, LDS_BYTES, st>>>(
+          blks, tab<int32_t>(ws, T_.o_scale), int(T_.scale_list.size()), segs, iar, var, d));
     }
     if (l > 1) {
       const LevelTabs& U = Y.lv[l - 1];
       DLevelDyn du = dyn_of(ws, Y, l - 1);
-      k_merge_sizes<<<unsigned(U.segs.size()), 64, 0, st>>>(
+      LAUNCH(K_MSIZE, l, k_merge_sizes<<<unsigned(U.segs.size()), 64, 0, st>>>(
           tab<DSeg>(ws, U.o_segs), int(U.segs.size()), tab<int32_t>(ws, T_.o_cons_ptr),
-          tab<int32_t>(ws, T_.o_cons), segs, iar, d, du);
-      HIPCHK(hipGetLastError());
-      k_merge_elim<T><<<unsigned(U.blks.size()), WG, 0, st>>>(
+          tab<int32_t>(ws, T_.o_cons), segs, iar, d, du));
+      LAUNCH(K_MELIM, l, k_merge_elim<T><<<unsigned(U.blks.size()), WG, 0, st>>>(
           tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
-          tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du);
-      HIPCHK(hipGetLastError());
+          tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du));
     }
   }
   HIPCHK(hipMemcpyAsync(status_host, status, 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  const int rc = read_dyn_host(F);
+  if (rc) return rc;
+  prof_flush(F, 0);
   return SPALU_OK;
 }
 
@@ -473,48 +790,83 @@ SolveWs solve_layout(const spalu_factor_t* F, int nrhs) {
 
 // One application of the factor: W <- M^{-1} B0 (both in the working layout).
 template <typename T>
-int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs) {
+int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStream_t st) {
   const Layout& Y = *F->lay;
   const Plan& P = F->nd->plan;
   char* ws = F->ws;
-  hipStream_t st = F->stream;
   const int32_t* iar = reinterpret_cast<const int32_t*>(ws + Y.o_iarena);
   const T* var = reinterpret_cast<const T*>(ws + Y.o_varena);
   const int L = P.L;
   const size_t nn = size_t(F->n) * nrhs;
-  HIPCHK(hipMemcpyAsync(W, B0, nn * sizeof(T), hipMemcpyDeviceToDevice, st));
+  k_copy<T><<<nblocks(int64_t(nn)), WG, 0, st>>>(B0, W, int64_t(nn));
+  HIPCHK(hipGetLastError());
   const DLeaf* leaves = tab<DLeaf>(ws, Y.o_leaves);
-  k_leaf_solve<T, false><<<unsigned(Y.leaves.size()), WG, LDS_BYTES, st>>>(
-      leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var, B0, W, Z, nrhs);
-  HIPCHK(hipGetLastError());
-  k_sep_from_leaves<T><<<nblocks(int64_t(nn)), WG, 0, st>>>(F->n, tab<int8_t>(ws, Y.o_seplev), F->rowptr,
-                                                             F->colind, F->vals, Z, W, nrhs);
-  HIPCHK(hipGetLastError());
+  LAUNCH(K_LSOLVE_F, 0, k_leaf_solve<T, false><<<unsigned(Y.leaves.size()), WG, LDS_BYTES, st>>>(
+      leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var, B0, W, Z, nrhs));
+  LAUNCH(K_SEPLEAF, 0, k_sep_from_leaves<T><<<nblocks(int64_t(nn)), WG, 0, st>>>(F->n, tab<int8_t>(ws, Y.o_seplev), F->rowptr,
+                                                             F->colind, F->vals, Z, W, nrhs));
   for (int l = L; l >= 1; --l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
     DLevelDyn d = dyn_of(ws, Y, l);
-    k_seg_solve<T, false><<<unsigned(ns), WG, LDS_BYTES, st>>>(tab<DSeg>(ws, T_.o_segs), ns, iar, var, d, W,
-                                                               nrhs);
-    HIPCHK(hipGetLastError());
-    k_sep_fwd<T><<<unsigned(ns), WG, 0, st>>>(tab<DSeg>(ws, T_.o_segs), ns, tab<DNbr>(ws, T_.o_nbrs),
-                                             tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs);
-    HIPCHK(hipGetLastError());
+    LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, LDS_BYTES, st>>>(tab<DSeg>(ws, T_.o_segs), ns, iar, var, d, W,
+                                                               nrhs));
+    LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<unsigned(ns), WG, 0, st>>>(tab<DSeg>(ws, T_.o_segs), ns, tab<DNbr>(ws, T_.o_nbrs),
+                                             tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
   }
   for (int l = 1; l <= L; ++l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
     DLevelDyn d = dyn_of(ws, Y, l);
-    k_sep_bwd<T><<<unsigned(ns), WG, 0, st>>>(tab<DSeg>(ws, T_.o_segs), ns, tab<DNbr>(ws, T_.o_nbrs),
-                                             tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs);
-    HIPCHK(hipGetLastError());
-    k_seg_solve<T, true><<<unsigned(ns), WG, LDS_BYTES, st>>>(tab<DSeg>(ws, T_.o_segs), ns, iar, var, d, W,
-                                                              nrhs);
-    HIPCHK(hipGetLastError());
+    LAUNCH(K_SEPBWD, l, k_sep_bwd<T><<<unsigned(ns), WG, 0, st>>>(tab<DSeg>(ws, T_.o_segs), ns, tab<DNbr>(ws, T_.o_nbrs),
+                                             tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
+    LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, LDS_BYTES, st>>>(tab<DSeg>(ws, T_.o_segs), ns, iar, var, d, W,
+                                                              nrhs));
   }
-  k_leaf_solve<T, true><<<unsigned(Y.leaves.size()), WG, LDS_BYTES, st>>>(
-      leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var, B0, W, Z, nrhs);
-  HIPCHK(hipGetLastError());
+  LAUNCH(K_LSOLVE_B, 0, k_leaf_solve<T, true><<<unsigned(Y.leaves.size()), WG, LDS_BYTES, st>>>(
+      leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var, B0, W, Z, nrhs));
+  return SPALU_OK;
+}
+
+// One application of the factor on stream st, either as direct launches
+// or as a replay of a captured graph of the same launches.
+template <typename T>
+int apply(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, const char* sw, bool graph,
+          hipStream_t st) {
+  if (!graph) return apply_inverse<T>(F, B0, W, Z, nrhs, st);
+  spalu_nd_t* nd = const_cast<spalu_nd_t*>(F->nd);
+  hipGraphExec_t exec = nullptr;
+  for (auto& gph : nd->graphs)
+    if (gph.ws == F->ws && gph.sw == sw && gph.rowptr == F->rowptr && gph.colind == F->colind &&
+        gph.vals == F->vals && gph.nrhs == nrhs && gph.prec == F->prec)
+      exec = gph.exec;
+  if (!exec) {
+    if (!nd->capture_stream) HIPCHK(hipStreamCreateWithFlags(&nd->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = nd->capture_stream;
+    const bool prof_was = g_prof.on;  // no event records inside the capture
+    g_prof.on = false;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const int rc = apply_inverse<T>(F, B0, W, Z, nrhs, cs);
+    g_prof.on = prof_was;
+    hipGraph_t graph_ = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph_);
+    if (rc) {
+      if (graph_) (void)hipGraphDestroy(graph_);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(SPALU_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph_, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph_);
+    if (e2 != hipSuccess) return fail(SPALU_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    if (nd->graphs.size() >= 8) {
+      (void)hipGraphExecDestroy(nd->graphs.front().exec);
+      nd->graphs.erase(nd->graphs.begin());
+    }
+    nd->graphs.push_back(SweepGraph{F->ws, sw, F->rowptr, F->colind, F->vals, nrhs, F->prec, exec});
+  }
+  const int pi = prof_begin(K_APPLY, 0, st);
+  HIPCHK(hipGraphLaunch(exec, st));
+  prof_end(pi, st);
   return SPALU_OK;
 }
 
@@ -545,27 +897,26 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     Bsrc = R;
     ldbres = F->n;
   }
-  k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(B, ldb, F->n, nrhs, B0);
-  HIPCHK(hipGetLastError());
-  int rc = apply_inverse<T>(F, B0, W, Z, nrhs);
+  LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(B, ldb, F->n, nrhs, B0));
+  const bool graph = so.graph != 0;
+  int rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);
   if (rc) return rc;
-  k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 0);
-  HIPCHK(hipGetLastError());
-  if (!want_res) return SPALU_OK;
+  LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 0));
+  if (!want_res) {
+    prof_flush(F, nrhs);
+    return SPALU_OK;
+  }
   std::vector<double> hr(nrhs), hb(nrhs);
   double first = -1.0, worst = 0.0;
   int it = 0;
   std::vector<double> bnorm;
   while (true) {
     dim3 grid(s.rblk, unsigned(nrhs));
-    k_residual<<<grid, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Bsrc, ldbres, X, ldx, R,
-                                    pr, pb);
-    HIPCHK(hipGetLastError());
-    k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pr, int(s.rblk), nrhs, nr);
-    HIPCHK(hipGetLastError());
+    LAUNCH(K_RESID, 0, k_residual<<<grid, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Bsrc, ldbres, X, ldx, R,
+                                    pr, pb));
+    LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pr, int(s.rblk), nrhs, nr));
     if (bnorm.empty()) {
-      k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pb, int(s.rblk), nrhs, nb);
-      HIPCHK(hipGetLastError());
+      LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pb, int(s.rblk), nrhs, nb));
       HIPCHK(hipMemcpyAsync(hb.data(), nb, size_t(nrhs) * 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipMemcpyAsync(hr.data(), nr, size_t(nrhs) * 8, hipMemcpyDeviceToHost, st));
@@ -583,14 +934,13 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     if (first < 0) first = worst;
     if (so.tol <= 0.0 || worst <= so.tol || it >= so.max_iter) break;
     // correction: solve with r as right-hand side, x += M r
-    k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(R, F->n, F->n, nrhs, B0);
-    HIPCHK(hipGetLastError());
-    rc = apply_inverse<T>(F, B0, W, Z, nrhs);
+    LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(R, F->n, F->n, nrhs, B0));
+    rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);
     if (rc) return rc;
-    k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 1);
-    HIPCHK(hipGetLastError());
+    LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 1));
     ++it;
   }
+  prof_flush(F, nrhs);
   if (info) {
     info->iterations = it;
     info->max_rel_residual = worst;
@@ -602,6 +952,60 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
 
 }  // namespace
 
+
+// Host image of every table plus the leaf boundary lists, in pinned memory
+// so the upload of a factorization is two asynchronous copies.  Rebuilt only
+// when the near-field radius option changes.
+static int build_image(const Plan& P, Layout* Y, double rho) {
+  if (Y->image && Y->image_rho == rho) return SPALU_OK;
+  const size_t bytes = Y->blob_bytes + (Y->leaf_i1 - Y->leaf_i0) * 4;
+  if (!Y->image || Y->image_bytes < bytes) {
+    if (Y->image) (void)hipHostFree(Y->image);
+    Y->image = nullptr;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&Y->image), std::max<size_t>(bytes, 1), hipHostMallocDefault));
+    Y->image_bytes = bytes;
+  }
+  char* blob = Y->image;
+  std::memset(blob, 0, Y->blob_bytes);
+  auto cp = [&](size_t off, const void* src, size_t b) {
+    if (b) std::memcpy(blob + off, src, b);
+  };
+  for (int l = 1; l <= P.L; ++l) {
+    const LevelTabs& T = Y->lv[l];
+    std::vector<DSeg> segs = T.segs;
+    for (auto& sg : segs) {
+      int span = 0;
+      for (int a = 0; a < 3; ++a) span = std::max(span, sg.hi[a] - sg.lo[a] + 1);
+      sg.thr = std::max(1, int(std::ceil(rho * span)));
+    }
+    cp(T.o_segs, segs.data(), segs.size() * sizeof(DSeg));
+    cp(T.o_nbrs, T.nbrs.data(), T.nbrs.size() * sizeof(DNbr));
+    cp(T.o_blks, T.blks.data(), T.blks.size() * sizeof(DBlk));
+    cp(T.o_scale, T.scale_list.data(), T.scale_list.size() * 4);
+    cp(T.o_cons_ptr, T.cons_ptr.data(), T.cons_ptr.size() * 4);
+    cp(T.o_cons, T.cons.data(), T.cons.size() * 4);
+    cp(T.o_task_ptr, T.task_ptr.data(), T.task_ptr.size() * 4);
+    cp(T.o_tasks, T.tasks.data(), T.tasks.size() * sizeof(DTask));
+    cp(T.o_terms, T.terms.data(), T.terms.size() * sizeof(DSepTerm));
+  }
+  cp(Y->o_leaves, Y->leaves.data(), Y->leaves.size() * sizeof(DLeaf));
+  cp(Y->o_lc_ptr, Y->lc_ptr.data(), Y->lc_ptr.size() * 4);
+  cp(Y->o_lc, Y->lc.data(), Y->lc.size() * sizeof(DLeafContrib));
+  cp(Y->o_vptrL, Y->vptrL.data(), Y->vptrL.size() * 4);
+  cp(Y->o_vertsL, Y->vertsL.data(), Y->vertsL.size() * 4);
+  cp(Y->o_seplev, P.seplev.data(), size_t(P.N));
+  // leaf boundary lists (then an unused piv range) in the int-arena layout
+  int32_t* li = reinterpret_cast<int32_t*>(blob + Y->blob_bytes);
+  std::memset(li, 0, (Y->leaf_i1 - Y->leaf_i0) * 4);
+  const PLevel& PLL = P.levels[P.L];
+  for (size_t i = 0; i < P.leaves.size(); ++i) {
+    int32_t* dst = li + (size_t(Y->leaves[i].ioff) - Y->leaf_i0);
+    for (int sg : P.leaves[i].bsegs)
+      for (int32_t v : PLL.segs[sg].verts) *dst++ = v;
+  }
+  Y->image_rho = rho;
+  return SPALU_OK;
+}
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -701,6 +1105,11 @@ static const Layout* get_layout(const spalu_nd_t* nd, int prec) {
   return m->layout[prec].get();
 }
 
+static std::shared_ptr<const Layout> layout_ptr(const spalu_nd_t* nd, int prec) {
+  get_layout(nd, prec);
+  return nd->layout[prec];
+}
+
 int spalu_factor_workspace(const spalu_nd_t* nd, const spalu_factor_opts* opts, size_t* bytes) {
   if (!nd || !bytes) return fail(SPALU_EINVAL, "null argument");
   spalu_factor_opts o;
@@ -751,6 +1160,7 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   auto F = std::make_unique<spalu_factor_t>();
   F->nd = nd;
   F->lay = Y;
+  F->lay_sp = layout_ptr(nd, o.precision);
   F->prec = o.precision;
   F->ws = static_cast<char*>(workspace);
   F->stream = static_cast<hipStream_t>(stream);
@@ -759,51 +1169,14 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   F->colind = colind;
   F->vals = vals;
   F->g = GridGeom{nd->plan.dims[0], nd->plan.dims[1], nd->plan.dims[2]};
-  // tables: patch the option-dependent near-field radius, then upload
-  std::vector<char> blob(Y->blob_bytes, 0);
   const Plan& P = nd->plan;
-  for (int l = 1; l <= P.L; ++l) {
-    const LevelTabs& T = Y->lv[l];
-    std::vector<DSeg> segs = T.segs;
-    for (auto& s : segs) {
-      int span = 0;
-      for (int a = 0; a < 3; ++a) span = std::max(span, s.hi[a] - s.lo[a] + 1);
-      s.thr = std::max(1, int(std::ceil(o.rho * span)));
-    }
-    auto cp = [&](size_t off, const void* src, size_t b) {
-      if (b) std::memcpy(blob.data() + off, src, b);
-    };
-    cp(T.o_segs, segs.data(), segs.size() * sizeof(DSeg));
-    cp(T.o_nbrs, T.nbrs.data(), T.nbrs.size() * sizeof(DNbr));
-    cp(T.o_blks, T.blks.data(), T.blks.size() * sizeof(DBlk));
-    cp(T.o_scale, T.scale_list.data(), T.scale_list.size() * 4);
-    cp(T.o_cons_ptr, T.cons_ptr.data(), T.cons_ptr.size() * 4);
-    cp(T.o_cons, T.cons.data(), T.cons.size() * 4);
-    cp(T.o_task_ptr, T.task_ptr.data(), T.task_ptr.size() * 4);
-    cp(T.o_tasks, T.tasks.data(), T.tasks.size() * sizeof(DTask));
-    cp(T.o_terms, T.terms.data(), T.terms.size() * sizeof(DSepTerm));
-  }
-  std::memcpy(blob.data() + Y->o_leaves, Y->leaves.data(), Y->leaves.size() * sizeof(DLeaf));
-  std::memcpy(blob.data() + Y->o_lc_ptr, Y->lc_ptr.data(), Y->lc_ptr.size() * 4);
-  if (!Y->lc.empty()) std::memcpy(blob.data() + Y->o_lc, Y->lc.data(), Y->lc.size() * sizeof(DLeafContrib));
-  std::memcpy(blob.data() + Y->o_vptrL, Y->vptrL.data(), Y->vptrL.size() * 4);
-  std::memcpy(blob.data() + Y->o_vertsL, Y->vertsL.data(), Y->vertsL.size() * 4);
-  std::memcpy(blob.data() + Y->o_seplev, P.seplev.data(), size_t(P.N));
-  // leaf boundary vertex lists into the int arena image
-  std::vector<int32_t> leaf_ints;
-  HIPCHK(hipMemcpyAsync(F->ws, blob.data(), blob.size(), hipMemcpyHostToDevice, F->stream));
-  {
-    // bverts of each leaf: concatenated level-L segment vertices
-    const PLevel& PLL = P.levels[P.L];
-    for (size_t i = 0; i < P.leaves.size(); ++i) {
-      std::vector<int32_t> bv;
-      for (int s : P.leaves[i].bsegs)
-        for (int32_t v : PLL.segs[s].verts) bv.push_back(v);
-      if (!bv.empty())
-        HIPCHK(hipMemcpyAsync(F->ws + Y->o_iarena + size_t(Y->leaves[i].ioff) * 4, bv.data(), bv.size() * 4,
-                              hipMemcpyHostToDevice, F->stream));
-    }
-  }
+  Layout* YM = const_cast<Layout*>(Y);
+  const int irc = build_image(P, YM, o.rho);
+  if (irc) return irc;
+  HIPCHK(hipMemcpyAsync(F->ws, YM->image, Y->blob_bytes, hipMemcpyHostToDevice, F->stream));
+  if (Y->leaf_i1 > Y->leaf_i0)
+    HIPCHK(hipMemcpyAsync(F->ws + Y->o_iarena + Y->leaf_i0 * 4, YM->image + Y->blob_bytes,
+                          (Y->leaf_i1 - Y->leaf_i0) * 4, hipMemcpyHostToDevice, F->stream));
   int status = 0;
   int rc = o.precision == SPALU_FP64 ? run_factor<double>(F.get(), o, &status)
                                      : run_factor<float>(F.get(), o, &status);
@@ -821,8 +1194,7 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
     int64_t spc = 0, passes = 0, res = 0, mf = 0;
     for (int l = 1; l <= P.L; ++l) {
       const size_t ns = Y->lv[l].segs.size();
-      std::vector<int32_t> dv(6 * ns);
-      HIPCHK(hipMemcpy(dv.data(), F->ws + Y->lv[l].o_dyn, dv.size() * 4, hipMemcpyDeviceToHost));
+      const std::vector<int32_t>& dv = (*F->dyn_host)[l];
       int e = 0, e2 = 0;
       bool any = false;
       for (size_t c = 0; c < ns; ++c) {
@@ -874,6 +1246,40 @@ int spalu_factor_ranks(const spalu_factor_t* f, int32_t* n_before, int32_t* rank
 
 void spalu_factor_free(spalu_factor_t* f) { delete f; }
 
+int spalu_factor_work(const spalu_factor_t* f, double* flops, double* bytes) {
+  if (!f) return fail(SPALU_EINVAL, "f is NULL");
+  double fl, by;
+  factor_work(f, fl, by);
+  if (flops) *flops = fl;
+  if (bytes) *bytes = by;
+  return SPALU_OK;
+}
+
+void spalu_profile(int32_t on) {
+  g_prof.reset();
+  g_prof.on = on != 0;
+}
+
+int spalu_profile_read(spalu_kernel_stat* out, int32_t max, int32_t* count) {
+  if (!count) return fail(SPALU_EINVAL, "count is NULL");
+  prof_account_pending();
+  int32_t m = 0;
+  for (int k = 0; k < K_COUNT; ++k) {
+    if (g_prof.launches[k] == 0) continue;
+    if (out && m < max) {
+      std::memset(&out[m], 0, sizeof(spalu_kernel_stat));
+      std::strncpy(out[m].name, kNames[k], sizeof(out[m].name) - 1);
+      out[m].launches = g_prof.launches[k];
+      out[m].ms = g_prof.ms[k];
+      out[m].bytes = g_prof.bytes[k];
+      out[m].flops = g_prof.flops[k];
+    }
+    ++m;
+  }
+  *count = m;
+  return SPALU_OK;
+}
+
 int spalu_solve_workspace(const spalu_factor_t* f, int32_t nrhs, size_t* bytes) {
   if (!f || !bytes || nrhs < 1) return fail(SPALU_EINVAL, "bad argument");
   *bytes = solve_layout(f, nrhs).bytes;
@@ -886,7 +1292,7 @@ int spalu_solve(const spalu_factor_t* f, int32_t nrhs, const double* B, int64_t 
   if (!f || !B || !X || !workspace || nrhs < 1) return fail(SPALU_EINVAL, "bad argument");
   if (ldb < f->n || ldx < f->n) return fail(SPALU_EINVAL, "leading dimension < n");
   if (workspace_bytes < solve_layout(f, nrhs).bytes) return fail(SPALU_ENOMEM, "workspace too small");
-  spalu_solve_opts so{0.0, 30};
+  spalu_solve_opts so{0.0, 30, 0};
   if (opts) so = *opts;
   if (so.max_iter < 0) return fail(SPALU_EINVAL, "bad max_iter");
   if (so.tol > 0.0 && X == B) return fail(SPALU_EINVAL, "refinement needs X != B");

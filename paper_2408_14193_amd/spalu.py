@@ -52,7 +52,7 @@ class FactorInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("levels", C.c_int32), ("segments", C.c_int64),
                 ("sparsified", C.c_int64), ("sample_passes", C.c_int64),
                 ("resampled", C.c_int64), ("max_front", C.c_int64), ("q_tilde", C.c_double),
-                ("flops", C.c_double), ("bytes", C.c_double), ("workspace_bytes", C.c_int64),
+                ("workspace_bytes", C.c_int64),
                 ("singular_level", C.c_int32)]
 
     def as_dict(self):
@@ -60,7 +60,7 @@ class FactorInfo(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("graph", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -89,17 +89,27 @@ _lib.spalu_factor_seg_base.argtypes = [P, I64P]
 _lib.spalu_factor.argtypes = [P, C.c_int64, P, P, P, C.POINTER(FactorOpts), P, C.c_size_t, P,
                               C.POINTER(P), C.POINTER(FactorInfo)]
 _lib.spalu_factor_ranks.argtypes = [P, I32P, I32P, I32P, I32P]
+_lib.spalu_factor_work.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
 _lib.spalu_factor_free.argtypes = [P]
 _lib.spalu_factor_free.restype = None
 _lib.spalu_solve_workspace.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
 _lib.spalu_solve.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64, C.POINTER(SolveOpts), P,
                              C.c_size_t, P, C.POINTER(C.c_double), C.POINTER(SolveInfo)]
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double),
+                ("bytes", C.c_double), ("flops", C.c_double)]
+
+
+_lib.spalu_profile.argtypes = [C.c_int32]
+_lib.spalu_profile.restype = None
+_lib.spalu_profile_read.argtypes = [C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]
+
 EXPORTED = ["spalu_nd_order", "spalu_nd_info", "spalu_nd_perm", "spalu_nd_etree",
             "spalu_nd_segments", "spalu_nd_free", "spalu_factor_opts_default",
             "spalu_factor_workspace", "spalu_factor_seg_base", "spalu_factor",
-            "spalu_factor_ranks", "spalu_factor_free", "spalu_solve_workspace", "spalu_solve",
-            "spalu_last_error"]
+            "spalu_factor_ranks", "spalu_factor_work", "spalu_factor_free", "spalu_solve_workspace", "spalu_solve",
+            "spalu_profile", "spalu_profile_read", "spalu_last_error"]
 
 
 def _check(rc):
@@ -224,6 +234,12 @@ class Factor:
                                        _ptr(hh, C.c_int32), _ptr(ps, C.c_int32)))
         return nb, rk, hh, ps
 
+    def work(self):
+        """Algorithmic (flops, bytes) of this factorization."""
+        fl, by = C.c_double(), C.c_double()
+        _check(_lib.spalu_factor_work(self._h, C.byref(fl), C.byref(by)))
+        return fl.value, by.value
+
     def solve_workspace(self, nrhs):
         import torch
         if nrhs not in self._solve_ws:
@@ -233,7 +249,7 @@ class Factor:
                                                device=self.workspace.device)
         return self._solve_ws[nrhs]
 
-    def solve_into(self, Bt, Xt, tol=0.0, max_iter=30, stream=None):
+    def solve_into(self, Bt, Xt, tol=0.0, max_iter=30, stream=None, graph=True):
         """Bt, Xt: (nrhs, n) float64 contiguous device tensors (column-major
         n x nrhs).  Returns (info dict, per-column relative residuals)."""
         nrhs, n = Bt.shape
@@ -242,7 +258,8 @@ class Factor:
         rr = np.zeros(nrhs, np.float64)
         info = SolveInfo()
         rc = _lib.spalu_solve(self._h, nrhs, Bt.data_ptr(), n, Xt.data_ptr(), n,
-                              C.byref(SolveOpts(float(tol), int(max_iter))), ws.data_ptr(),
+                              C.byref(SolveOpts(float(tol), int(max_iter), 1 if graph else 0)),
+                              ws.data_ptr(),
                               ws.numel(), s.cuda_stream, _ptr(rr, C.c_double), C.byref(info))
         if rc not in (OK, ENOCONV):
             _check(rc)
@@ -250,13 +267,29 @@ class Factor:
         d["converged"] = rc == OK
         return d, rr
 
-    def solve(self, B, tol=0.0, max_iter=30):
+    def solve(self, B, tol=0.0, max_iter=30, graph=True):
         """B: (n, nrhs) or (n,) float64 device tensor.  Returns (X, info)."""
         import torch
         vec = B.dim() == 1
         Bt = (B[None, :] if vec else B.t()).contiguous()
         Xt = torch.empty_like(Bt)
-        info, rr = self.solve_into(Bt, Xt, tol, max_iter)
+        info, rr = self.solve_into(Bt, Xt, tol, max_iter, graph=graph)
         info["rel_res"] = rr
         X = Xt[0] if vec else Xt.t()
         return X, info
+
+
+def profile(on=True):
+    """Enable (and clear) or disable per-kernel event timing in the library."""
+    _lib.spalu_profile(1 if on else 0)
+
+
+def profile_read():
+    """Per-kernel totals since the last profile(): {name: dict(launches, ms,
+    bytes, flops)}."""
+    cnt = C.c_int32()
+    _check(_lib.spalu_profile_read(None, 0, C.byref(cnt)))
+    arr = (KernelStat * max(1, cnt.value))()
+    _check(_lib.spalu_profile_read(arr, cnt.value, C.byref(cnt)))
+    return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, bytes=arr[i].bytes,
+                                       flops=arr[i].flops) for i in range(cnt.value)}

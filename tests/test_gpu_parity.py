@@ -195,3 +195,22 @@ def test_error_paths(S):
     F = S.Factor(nd, rp, ci, v, eps=1e-2)
     X, info = F.solve(B, tol=1e-30, max_iter=1)
     assert not info["converged"] and info["iterations"] == 1
+
+
+def test_graph_replays_match_direct_launches(S):
+    """The captured sweep graph replayed across refinement steps (eager
+    residual work and synchronisations between replays) gives bitwise the
+    same iterates as direct launches, for both storage precisions."""
+    import torch
+    for prec in (S.FP64, S.FP32):
+        P = make_config(1, side=63, nrhs=3)
+        nd, F, B = gpu_factor(S, P, eps=P.eps, precision=prec)
+        Bt = B.t().contiguous()
+        Xd = torch.empty_like(Bt)
+        Xg = torch.empty_like(Bt)
+        i1, r1 = F.solve_into(Bt, Xd, tol=1e-12, max_iter=6, graph=False)
+        i2, r2 = F.solve_into(Bt, Xg, tol=1e-12, max_iter=6, graph=True)
+        i3, r3 = F.solve_into(Bt, Xg, tol=1e-12, max_iter=6, graph=True)   # cached graph
+        assert torch.equal(Xd, Xg)
+        assert i1["iterations"] == i2["iterations"] == i3["iterations"]
+        assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
