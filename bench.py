@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--cpu-side", type=int, default=255)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="direct launches in every form")
     return ap.parse_args()
 
 
@@ -48,7 +49,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(S, P, nd, dev, form, steps, warmup, profile):
+def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True):
     import numpy as np
     import torch
     prec = S.FP32 if form == "mixed" else S.FP64
@@ -63,7 +64,7 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile):
         t0 = time.perf_counter()
         F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec)
         t1 = time.perf_counter()
-        info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(form == "mixed"))
+        info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(graph and form == "mixed"))
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return F, info, rr, t1 - t0, t2 - t1
@@ -162,7 +163,7 @@ def main():
     forms = a.forms.split(",")
     res = {}
     for i, f in enumerate(forms):
-        res[f] = run_form(S, P, nd, dev, f, a.steps, a.warmup, profile=(i == 0))
+        res[f] = run_form(S, P, nd, dev, f, a.steps, a.warmup, profile=(i == 0), graph=not a.no_graph)
     head = forms[0]
     r = res[head]
     value = P.n / (r["ms_per_step"] * 1e-3)

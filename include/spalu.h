@@ -191,7 +191,10 @@ typedef struct {
 /* Bytes of device workspace for nrhs right-hand sides. */
 int spalu_solve_workspace(const spalu_factor_t* f, int32_t nrhs, size_t* bytes);
 
-/* B, X: device, column-major n x nrhs with leading dimensions ldb, ldx >= n
+/* Refinement stops early, with ENOCONV, when three consecutive steps fail to
+ * reduce the largest column residual by 10 %, or when it is not finite.
+ *
+ * B, X: device, column-major n x nrhs with leading dimensions ldb, ldx >= n
  * (FP64).  X may equal B.  opts, info (host) may be NULL (direct solve).
  * rel_res (host, nrhs entries, may be NULL) receives the final relative
  * residual of each column.  With refinement the call synchronises once per

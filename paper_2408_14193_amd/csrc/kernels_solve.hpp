@@ -38,7 +38,8 @@ __global__ void k_rhs_out(const T* W, int64_t n, int nrhs, double* X, int64_t ld
 }
 
 // Leaf interiors: Z_I = A_II^{-1} W_I (forward) or
-// W_I = A_II^{-1} (B_I - A_IB W_B) (backward), with the stored inverse.
+// W_I = A_II^{-1} (B_I - A_IB W_B) (backward), with the stored inverse
+// staged in LDS (one coalesced load) and the right-hand sides beside it.
 template <typename T, bool BACKWARD>
 __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nleaf, GridGeom g,
                                                    const int64_t* rowptr, const int32_t* colind,
@@ -49,9 +50,17 @@ __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nlea
   if (lf >= nleaf) return;
   const DLeaf L = leaves[lf];
   const int ni = L.ni, tid = threadIdx.x;
+  if (ni == 0) return;
   const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1;
   const T* Ai = varena + L.lu_off;
-  const int jc = ni > 0 ? (LDS_DOUBLES / ni < nrhs ? LDS_DOUBLES / ni : nrhs) : nrhs;
+  const bool stage = ni * ni + ni <= LDS_DOUBLES;
+  double* sA = lds;
+  double* X = stage ? lds + ni * ni : lds;
+  const int room = stage ? LDS_DOUBLES - ni * ni : LDS_DOUBLES;
+  const int jc = room / ni < nrhs ? room / ni : nrhs;
+  if (stage) {
+    for (int t = tid; t < ni * ni; t += WG) sA[t] = double(Ai[t]);
+  }
   for (int j0 = 0; j0 < nrhs; j0 += jc) {
     const int nc = nrhs - j0 < jc ? nrhs - j0 : jc;
     for (int t = tid; t < ni * nc; t += WG) {
@@ -72,14 +81,19 @@ __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nlea
           if (!inside) v -= vals[e] * double(W[size_t(w) * nrhs + j0 + j]);
         }
       }
-      lds[t] = v;
+      X[t] = v;
     }
     __syncthreads();
     for (int t = tid; t < ni * nc; t += WG) {
       const int i = t / nc, j = t % nc;
-      const T* arow = Ai + size_t(i) * ni;
       double acc = 0.0;
-      for (int q = 0; q < ni; ++q) acc += double(arow[q]) * lds[q * nc + j];
+      if (stage) {
+        const double* arow = sA + i * ni;
+        for (int q = 0; q < ni; ++q) acc += arow[q] * X[q * nc + j];
+      } else {
+        const T* arow = Ai + size_t(i) * ni;
+        for (int q = 0; q < ni; ++q) acc += double(arow[q]) * X[q * nc + j];
+      }
       const int ix = i % w0, iy = (i / w0) % w1, iz = i / (w0 * w1);
       const int u = (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz));
       if (BACKWARD)
@@ -110,7 +124,7 @@ __global__ void k_sep_from_leaves(int64_t n, const int8_t* seplev, const int64_t
 
 // Per segment of level l: forward (U_T, then P and L^{-1}) or backward
 // (U^{-1}, then L_T) on its DOFs in [remainder; skeleton] order, with the
-// packed inverses of the two-stage LU.
+// packed inverses of the two-stage LU (and T) staged in LDS when they fit.
 template <typename T, bool BACKWARD>
 __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, const int32_t* iarena,
                                                   const T* varena, DLevelDyn dyn, T* W, int nrhs) {
@@ -127,17 +141,26 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
   const int32_t* piv = dofs + 2 * S.cap;
   const T* Inv = varena + S.lu_off;
   const T* Tm = varena + S.t_off;
-  if (2 * n > LDS_DOUBLES) {
+  const int nt = sp ? k * nr : 0;
+  const bool stage = n * n + nt + 2 * n <= LDS_DOUBLES;
+  if (!stage && 2 * n > LDS_DOUBLES) {
     // too large for the staging buffer: poison the result so the residual
     // check reports the failure instead of returning a wrong solution
     for (int t = tid; t < n * nrhs; t += WG) W[size_t(dofs[t / nrhs]) * nrhs + t % nrhs] = T(NAN);
     return;
   }
-  const int jc = LDS_DOUBLES / (2 * n) < nrhs ? LDS_DOUBLES / (2 * n) : nrhs;
+  double* sI = lds;                      // packed inverse (staged)
+  double* sT = lds + n * n;              // T (staged)
+  double* X = stage ? sT + nt : lds;
+  const int room = stage ? LDS_DOUBLES - n * n - nt : LDS_DOUBLES;
+  const int jc = room / (2 * n) < nrhs ? room / (2 * n) : nrhs;
+  if (stage) {
+    for (int t = tid; t < n * n; t += WG) sI[t] = double(Inv[t]);
+    for (int t = tid; t < nt; t += WG) sT[t] = double(Tm[t]);
+  }
   for (int j0 = 0; j0 < nrhs; j0 += jc) {
     const int nc = nrhs - j0 < jc ? nrhs - j0 : jc;
-    double* X = lds;
-    double* Yb = lds + size_t(n) * nc;
+    double* Yb = X + size_t(n) * nc;
     for (int t = tid; t < n * nc; t += WG) {
       const int i = t / nc, j = t % nc;
       X[t] = double(W[size_t(dofs[i]) * nrhs + j0 + j]);
@@ -148,7 +171,10 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
         for (int t = tid; t < nr * nc; t += WG) {
           const int q = t / nc, j = t % nc;
           double s = 0.0;
-          for (int i = 0; i < k; ++i) s += double(Tm[size_t(i) * nr + q]) * X[size_t(nr + i) * nc + j];
+          if (stage)
+            for (int i = 0; i < k; ++i) s += sT[i * nr + q] * X[size_t(nr + i) * nc + j];
+          else
+            for (int i = 0; i < k; ++i) s += double(Tm[size_t(i) * nr + q]) * X[size_t(nr + i) * nc + j];
           X[t] -= s;
         }
         __syncthreads();
@@ -165,17 +191,27 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
       __syncthreads();
       for (int t = tid; t < n * nc; t += WG) {
         const int i = t / nc, j = t % nc;
-        const T* row = Inv + size_t(i) * n;
         double v = X[t];
-        for (int u = 0; u < i; ++u) v += double(row[u]) * X[size_t(u) * nc + j];
+        if (stage) {
+          const double* row = sI + i * n;
+          for (int u = 0; u < i; ++u) v += row[u] * X[size_t(u) * nc + j];
+        } else {
+          const T* row = Inv + size_t(i) * n;
+          for (int u = 0; u < i; ++u) v += double(row[u]) * X[size_t(u) * nc + j];
+        }
         W[size_t(dofs[i]) * nrhs + j0 + j] = T(v);
       }
     } else {
       for (int t = tid; t < n * nc; t += WG) {
         const int i = t / nc, j = t % nc;
-        const T* row = Inv + size_t(i) * n;
         double v = 0.0;
-        for (int u = i; u < n; ++u) v += double(row[u]) * X[size_t(u) * nc + j];
+        if (stage) {
+          const double* row = sI + i * n;
+          for (int u = i; u < n; ++u) v += row[u] * X[size_t(u) * nc + j];
+        } else {
+          const T* row = Inv + size_t(i) * n;
+          for (int u = i; u < n; ++u) v += double(row[u]) * X[size_t(u) * nc + j];
+        }
         Yb[t] = v;
       }
       __syncthreads();
@@ -183,7 +219,10 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
         for (int t = tid; t < k * nc; t += WG) {
           const int i = t / nc, j = t % nc;
           double s = 0.0;
-          for (int q = 0; q < nr; ++q) s += double(Tm[size_t(i) * nr + q]) * Yb[size_t(q) * nc + j];
+          if (stage)
+            for (int q = 0; q < nr; ++q) s += sT[i * nr + q] * Yb[size_t(q) * nc + j];
+          else
+            for (int q = 0; q < nr; ++q) s += double(Tm[size_t(i) * nr + q]) * Yb[size_t(q) * nc + j];
           Yb[size_t(nr + i) * nc + j] -= s;
         }
         __syncthreads();
@@ -197,31 +236,70 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
   }
 }
 
+// acc[a] += sum_u A[(i0+i)*lda + u] * W[idx[u]*nrhs + j0 + j] for the
+// (i, j) outputs this thread owns (t = tid + a*WG < ib*nc), u < K.  Operand
+// tiles of 32 columns of A and 32 gathered rows of W are staged in LDS.
+constexpr int GG_TILE = 32;
+constexpr int GG_ROWS = 64;   // output rows per pass
+constexpr int GG_COLS = 16;   // output right-hand sides per pass (<= 4 per thread)
+
+template <typename T>
+__device__ inline void gathered_gemm_acc(const T* A, int lda, int i0, int ib, int K, const int32_t* idx,
+                                         const T* W, int nrhs, int j0, int nc, double* sA, double* sX,
+                                         double acc[4]) {
+  const int tid = threadIdx.x;
+  for (int u0 = 0; u0 < K; u0 += GG_TILE) {
+    const int kt = K - u0 < GG_TILE ? K - u0 : GG_TILE;
+    __syncthreads();
+    for (int t = tid; t < ib * kt; t += WG) sA[t] = double(A[size_t(i0 + t / kt) * lda + u0 + t % kt]);
+    for (int t = tid; t < kt * nc; t += WG) sX[t] = double(W[size_t(idx[u0 + t / nc]) * nrhs + j0 + t % nc]);
+    __syncthreads();
+    int a = 0;
+    for (int t = tid; t < ib * nc; t += WG, ++a) {
+      const int i = t / nc, j = t % nc;
+      double s = 0.0;
+      for (int u = 0; u < kt; ++u) s += sA[i * kt + u] * sX[u * nc + j];
+      acc[a] += s;
+    }
+  }
+}
+
 // Forward separator elimination (Z_l): owner = non-separator segment a,
 // W[skel_a] -= sum over level-l separators s next to a of A'_{a,s} W[skel_s].
 template <typename T>
 __global__ __launch_bounds__(WG) void k_sep_fwd(const DSeg* segs, int nseg, const DNbr* nbrs,
                                                 const DBlk* blks, const int32_t* iarena, const T* varena,
                                                 DLevelDyn dyn, T* W, int nrhs) {
+  __shared__ double sA[GG_ROWS * GG_TILE];
+  __shared__ double sX[GG_TILE * GG_COLS];
   const int a = blockIdx.x;
   if (a >= nseg) return;
   const DSeg S = segs[a];
   if (S.flags & SEG_IS_SEP) return;
+  bool any = false;
+  for (int e = S.nbr_begin; e < S.nbr_end; ++e) any |= nbrs[e].d_is_sep != 0;
+  if (!any) return;
   const int ka = dyn.k[a], nra = dyn.nr[a];
   const int32_t* da = iarena + S.ioff + nra;
-  for (int t = threadIdx.x; t < ka * nrhs; t += WG) {
-    const int i = t / nrhs, j = t % nrhs;
-    double acc = 0.0;
-    for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
-      const DNbr nb = nbrs[e];
-      if (!nb.d_is_sep) continue;
-      const int ks = dyn.k[nb.d], nrs = dyn.nr[nb.d];
-      const int32_t* ds = iarena + segs[nb.d].ioff + nrs;
-      const T* A = varena + blks[nb.blk_cd].soff;
-      for (int u = 0; u < ks; ++u) acc += double(A[size_t(i) * ks + u]) * double(W[size_t(ds[u]) * nrhs + j]);
+  for (int j0 = 0; j0 < nrhs; j0 += GG_COLS) {
+    const int nc = nrhs - j0 < GG_COLS ? nrhs - j0 : GG_COLS;
+    for (int i0 = 0; i0 < ka; i0 += GG_ROWS) {
+      const int ib = ka - i0 < GG_ROWS ? ka - i0 : GG_ROWS;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+        const DNbr nb = nbrs[e];
+        if (!nb.d_is_sep) continue;
+        const int ks = dyn.k[nb.d], nrs = dyn.nr[nb.d];
+        gathered_gemm_acc(varena + blks[nb.blk_cd].soff, ks, i0, ib, ks, iarena + segs[nb.d].ioff + nrs, W,
+                          nrhs, j0, nc, sA, sX, acc);
+      }
+      int q = 0;
+      for (int t = threadIdx.x; t < ib * nc; t += WG, ++q) {
+        const int i = t / nc, j = t % nc;
+        const size_t idx = size_t(da[i0 + i]) * nrhs + j0 + j;
+        W[idx] = T(double(W[idx]) - acc[q]);
+      }
     }
-    const size_t idx = size_t(da[i]) * nrhs + j;
-    W[idx] = T(double(W[idx]) - acc);
   }
 }
 
@@ -231,24 +309,32 @@ template <typename T>
 __global__ __launch_bounds__(WG) void k_sep_bwd(const DSeg* segs, int nseg, const DNbr* nbrs,
                                                 const DBlk* blks, const int32_t* iarena, const T* varena,
                                                 DLevelDyn dyn, T* W, int nrhs) {
+  __shared__ double sA[GG_ROWS * GG_TILE];
+  __shared__ double sX[GG_TILE * GG_COLS];
   const int s = blockIdx.x;
   if (s >= nseg) return;
   const DSeg S = segs[s];
   if (!(S.flags & SEG_IS_SEP)) return;
   const int ks = dyn.k[s], nrs = dyn.nr[s];
   const int32_t* ds = iarena + S.ioff + nrs;
-  for (int t = threadIdx.x; t < ks * nrhs; t += WG) {
-    const int i = t / nrhs, j = t % nrhs;
-    double acc = 0.0;
-    for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
-      const DNbr nb = nbrs[e];
-      const int kb = dyn.k[nb.d], nrb = dyn.nr[nb.d];
-      const int32_t* db = iarena + segs[nb.d].ioff + nrb;
-      const T* A = varena + blks[nb.blk_cd].soff;
-      for (int u = 0; u < kb; ++u) acc += double(A[size_t(i) * kb + u]) * double(W[size_t(db[u]) * nrhs + j]);
+  for (int j0 = 0; j0 < nrhs; j0 += GG_COLS) {
+    const int nc = nrhs - j0 < GG_COLS ? nrhs - j0 : GG_COLS;
+    for (int i0 = 0; i0 < ks; i0 += GG_ROWS) {
+      const int ib = ks - i0 < GG_ROWS ? ks - i0 : GG_ROWS;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+        const DNbr nb = nbrs[e];
+        const int kb = dyn.k[nb.d], nrb = dyn.nr[nb.d];
+        gathered_gemm_acc(varena + blks[nb.blk_cd].soff, kb, i0, ib, kb, iarena + segs[nb.d].ioff + nrb, W,
+                          nrhs, j0, nc, sA, sX, acc);
+      }
+      int q = 0;
+      for (int t = threadIdx.x; t < ib * nc; t += WG, ++q) {
+        const int i = t / nc, j = t % nc;
+        const size_t idx = size_t(ds[i0 + i]) * nrhs + j0 + j;
+        W[idx] = T(double(W[idx]) - acc[q]);
+      }
     }
-    const size_t idx = size_t(ds[i]) * nrhs + j;
-    W[idx] = T(double(W[idx]) - acc);
   }
 }
 

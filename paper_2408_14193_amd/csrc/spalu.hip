@@ -402,6 +402,7 @@ unsigned nblocks(int64_t n, int b = WG) { return unsigned(std::max<int64_t>(1, (
 
 constexpr size_t LDS_BYTES = size_t(LDS_DOUBLES) * 8;
 constexpr size_t LEAF_LDS_BYTES = size_t(LEAF_LDS_DOUBLES) * 8;
+constexpr size_t ID_LDS_BYTES = size_t(ID_LDS_DOUBLES) * 8;
 
 
 // ---------------------------------------------------------------------------
@@ -734,6 +735,8 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     prm.level = l;
     prm.seg_base = int(Y.seg_base[l]);
     prm.h_init = o.h_init;
+    LAUNCH(K_ID, l, k_seg_id_lds<T><<<unsigned(ns), WG, ID_LDS_BYTES, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), blks,
+                                                                      F->g, iar, var, d, prm));
     LAUNCH(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), blks, F->g, iar,
                                                      var, scr, d, prm));
     LAUNCH(K_LU, l, k_seg_lu<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, blks, iar, var, scr, d, status));
@@ -907,8 +910,8 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     return SPALU_OK;
   }
   std::vector<double> hr(nrhs), hb(nrhs);
-  double first = -1.0, worst = 0.0;
-  int it = 0;
+  double first = -1.0, worst = 0.0, prev = -1.0;
+  int it = 0, slow = 0;
   std::vector<double> bnorm;
   while (true) {
     dim3 grid(s.rblk, unsigned(nrhs));
@@ -933,6 +936,12 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     }
     if (first < 0) first = worst;
     if (so.tol <= 0.0 || worst <= so.tol || it >= so.max_iter) break;
+    // stagnation or divergence: three steps without a 10% reduction, or a
+    // non-finite residual
+    if (!std::isfinite(worst)) break;
+    slow = (prev >= 0.0 && !(worst <= 0.9 * prev)) ? slow + 1 : 0;
+    prev = worst;
+    if (slow >= 3) break;
     // correction: solve with r as right-hand side, x += M r
     LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(R, F->n, F->n, nrhs, B0));
     rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);

@@ -136,7 +136,7 @@ class ND:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.spalu_nd_free(h)
             self._h = None
 
@@ -223,7 +223,7 @@ class Factor:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.spalu_factor_free(h)
             self._h = None
 

@@ -177,7 +177,10 @@ CONFIGS = [
     dict(name="diffusion2d_grf", side=1023, dim=2, eps=1e-4, nrhs=16, dist="uniform", tol=1e-10, prec="fp32"),
     dict(name="convdiff2d", side=2047, dim=2, eps=1e-5, nrhs=64, dist="uniform", tol=1e-8, prec="fp32"),
     dict(name="laplace3d", side=127, dim=3, eps=1e-4, nrhs=8, dist="normal", tol=1e-8, prec="fp32"),
-    dict(name="helmholtz2d", side=1023, dim=2, eps=1e-4, nrhs=256, dist="uniform", tol=1e-8, prec="fp32"),
+    # eps 1e-6: at 10 points per wavelength the compression error of eps 1e-4
+    # grows with N past what refinement of the indefinite operator tolerates
+    # (direct residual 0.25 at 127^2, 1.8 at 255^2), at 1e-6 it stays ~5e-3
+    dict(name="helmholtz2d", side=1023, dim=2, eps=1e-6, nrhs=256, dist="uniform", tol=1e-8, prec="fp32"),
 ]
 
 
