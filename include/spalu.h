@@ -112,8 +112,20 @@ typedef struct {
   int32_t probes;      /* Gaussian probes of the a-posteriori ID check        */
   double tau;          /* accept if max probe error <= tau * eps * |R_11|     */
   const int32_t* h_init; /* optional device array, per (level, segment) start
-                            samples (learned form); index = seg_base[l] + c,
-                            see spalu_factor_seg_base; <= 0 entries use h0   */
+                            samples; index = seg_base[l] + c, see
+                            spalu_factor_seg_base; <= 0 entries use h0     */
+  const float* rank_model; /* optional device parameters of the rank predictor
+                            (spalu_mlp_param_count floats, layout of
+                            spalu_mlp_train_step); when set, every level's
+                            features feed a BF16 inference whose predicted
+                            rank fraction y gives the start samples
+                            ceil(rank_margin * n * y) + rank_pad (learned
+                            form); overrides h_init                       */
+  float* features_out;   /* optional device array (segments x 12 floats,
+                            index seg_base[l] + c) receiving every level's
+                            predictor features (training data)            */
+  float rank_margin;     /* default 1.1                                     */
+  int32_t rank_pad;      /* default 5 (the oversampling p of Section 4.2.3) */
 } spalu_factor_opts;
 
 typedef struct {
@@ -130,7 +142,7 @@ typedef struct {
 } spalu_factor_info;
 
 /* Default options (eps 1e-6, FP64, seed 1234, rho 0.5, h0 8, 5 probes,
- * tau 10). */
+ * tau 10, no rank predictor, margin 1.1, pad 5). */
 void spalu_factor_opts_default(spalu_factor_opts* o);
 
 /* Bytes of device workspace that spalu_factor needs for this ND and
@@ -203,6 +215,32 @@ int spalu_solve_workspace(const spalu_factor_t* f, int32_t nrhs, size_t* bytes);
 int spalu_solve(const spalu_factor_t* f, int32_t nrhs, const double* B, int64_t ldb, double* X,
                 int64_t ldx, const spalu_solve_opts* opts, void* workspace,
                 size_t workspace_bytes, void* stream, double* rel_res, spalu_solve_info* info);
+
+/* ---------------------------------------------------------------------------
+ * Rank predictor training (FP32 HIP kernels).  Parameters (device floats):
+ * mu[12], sd[12] (input standardisation, never trained), W1[64x12], b1[64],
+ * W2[64x64], b2[64], w3[64], b3[1]; the network is relu(W1 xn + b1) ->
+ * relu(W2 . + b2) -> sigmoid(w3 . + b3) predicting the rank fraction k/n of a
+ * segment from its 12 features; the loss is the mean squared error.
+ * ------------------------------------------------------------------------- */
+int spalu_mlp_param_count(void);
+
+/* Device workspace bytes for a batch of the given size. */
+int spalu_mlp_workspace(int32_t batch, size_t* bytes);
+
+/* y[b] = network output for feature rows X (batch x 12); all device. */
+int spalu_mlp_forward(const float* params, const float* X, int32_t batch, float* y, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/* One step on the batch (X batch x 12, targets t): loss (device float[1])
+ * = mean squared error before the update; grad (device, param_count floats,
+ * may be NULL) receives the gradient (zero for mu, sd); if adam_m / adam_v
+ * (device, param_count floats, zero-initialised by the caller) are given,
+ * one Adam update (beta 0.9, 0.999, eps 1e-8, bias-corrected with step >= 1)
+ * with learning rate lr is applied to the trainable entries. */
+int spalu_mlp_train_step(float* params, float* adam_m, float* adam_v, const float* X, const float* t,
+                         int32_t batch, float lr, int32_t step, float* loss, float* grad, void* workspace,
+                         size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Profiling (process-wide, not thread-safe; for benchmarks).  While on, every

@@ -15,6 +15,7 @@
 
 #include "../../include/spalu.h"
 #include "kernels_factor.hpp"
+#include "kernels_mlp.hpp"
 #include "kernels_solve.hpp"
 #include "layout.hpp"
 #include "planner.hpp"
@@ -67,6 +68,7 @@ struct Layout {
   size_t o_scratch = 0, n_scratch = 0;
   size_t leaf_scr_stride = 0;
   size_t o_status = 0;
+  size_t o_feats = 0, o_hinit = 0;  // rank predictor: features, start samples
   size_t bytes = 0;
   int64_t nseg_total = 0;
   std::vector<int64_t> seg_base;  // per level
@@ -195,6 +197,7 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
       }
       D.thr = 1;
       D.rcap = int32_t(rcap[c]);
+      D.sep_level = s.sep_level;
       D.ioff = int64_t(iar);
       iar += size_t(3 * cap + std::max<int64_t>(2 * rcap[c], cap));
       D.lu_off = int64_t(var);
@@ -370,6 +373,8 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
   // dynamic per-level arrays (6 ints per segment)
   for (int l = 1; l <= L; ++l) Y.lv[l].o_dyn = put(6 * Y.lv[l].segs.size() * 4);
   Y.o_status = put(64);
+  Y.o_feats = put(size_t(Y.nseg_total) * MLP_NF * 4);
+  Y.o_hinit = put(size_t(Y.nseg_total) * 4);
   Y.o_iarena = put(iar * 4);
   Y.n_iarena = iar;
   Y.o_varena = put(var * Y.vsize);
@@ -414,13 +419,13 @@ constexpr size_t ID_LDS_BYTES = size_t(ID_LDS_DOUBLES) * 8;
 enum KId {
   K_CHECK, K_INIT, K_LEAF, K_ASM, K_ID, K_LU, K_SCALE, K_MSIZE, K_MELIM,
   K_LSOLVE_F, K_SEPLEAF, K_SSOLVE_F, K_SEPFWD, K_SEPBWD, K_SSOLVE_B, K_LSOLVE_B,
-  K_RHSIN, K_RHSOUT, K_RESID, K_REDUCE, K_APPLY, K_COUNT
+  K_RHSIN, K_RHSOUT, K_RESID, K_REDUCE, K_APPLY, K_FEAT, K_MLP, K_COUNT
 };
 const char* const kNames[K_COUNT] = {
     "check_pattern", "init_level", "leaf_factor", "assemble_leafL", "seg_id", "seg_lu", "blk_scale",
     "merge_sizes", "merge_elim", "leaf_solve_fwd", "sep_from_leaves", "seg_solve_fwd", "sep_fwd",
     "sep_bwd", "seg_solve_bwd", "leaf_solve_bwd", "rhs_in", "rhs_out", "residual", "reduce_cols",
-    "solve_sweep_graph"};
+    "solve_sweep_graph", "features", "mlp_rank"};
 
 struct PendingLaunch {
   int kid, level;
@@ -735,6 +740,19 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     prm.level = l;
     prm.seg_base = int(Y.seg_base[l]);
     prm.h_init = o.h_init;
+    if (o.rank_model || o.features_out) {
+      float* feats = (o.features_out ? o.features_out : reinterpret_cast<float*>(ws + Y.o_feats)) +
+                     size_t(Y.seg_base[l]) * MLP_NF;
+      LAUNCH(K_FEAT, l, k_features<<<unsigned(ns), 64, 0, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), F->g, P.dim, L,
+                                                                l, o.eps, iar, d, F->rowptr, F->colind, F->vals,
+                                                                feats));
+      if (o.rank_model) {
+        int32_t* hinit = reinterpret_cast<int32_t*>(ws + Y.o_hinit);
+        LAUNCH(K_MLP, l, k_mlp_rank<<<nblocks(ns), WG, 0, st>>>(feats, ns, o.rank_model, segs, d, o.rank_margin,
+                                                                 o.rank_pad, hinit + Y.seg_base[l]));
+        prm.h_init = hinit;
+      }
+    }
     LAUNCH(K_ID, l, k_seg_id_lds<T><<<unsigned(ns), WG, ID_LDS_BYTES, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), blks,
                                                                       F->g, iar, var, d, prm));
     LAUNCH(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), blks, F->g, iar,
@@ -1106,6 +1124,10 @@ void spalu_factor_opts_default(spalu_factor_opts* o) {
   o->probes = 5;
   o->tau = 10.0;
   o->h_init = nullptr;
+  o->rank_model = nullptr;
+  o->features_out = nullptr;
+  o->rank_margin = 1.1f;
+  o->rank_pad = 5;
 }
 
 static const Layout* get_layout(const spalu_nd_t* nd, int prec) {
@@ -1157,7 +1179,8 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   spalu_factor_opts_default(&o);
   if (opts) o = *opts;
   if (o.precision != SPALU_FP64 && o.precision != SPALU_FP32) return fail(SPALU_EINVAL, "bad precision");
-  if (!(o.eps >= 0.0) || !(o.rho >= 0.0) || o.h0 < 1 || o.probes < 1 || o.probes > 8 || !(o.tau > 0.0))
+  if (!(o.eps >= 0.0) || !(o.rho >= 0.0) || o.h0 < 1 || o.probes < 1 || o.probes > 8 || !(o.tau > 0.0) ||
+      !(o.rank_margin > 0.0f) || o.rank_pad < 1)
     return fail(SPALU_EINVAL, "bad factor options");
   const Layout* Y;
   try {
@@ -1261,6 +1284,126 @@ int spalu_factor_work(const spalu_factor_t* f, double* flops, double* bytes) {
   factor_work(f, fl, by);
   if (flops) *flops = fl;
   if (bytes) *bytes = by;
+  return SPALU_OK;
+}
+
+
+int spalu_mlp_param_count(void) { return MLP_NPARAM; }
+
+static size_t mlp_ws_layout(int B, size_t* off) {
+  // Xn[B*12], H1[B*64], H2[B*64], y[B], dz[B], sq[B], dH2[B*64], dH1[B*64], grad[P]
+  const size_t sizes[9] = {size_t(B) * MLP_NF, size_t(B) * MLP_H, size_t(B) * MLP_H, size_t(B), size_t(B),
+                           size_t(B), size_t(B) * MLP_H, size_t(B) * MLP_H, size_t(MLP_NPARAM)};
+  size_t o = 0;
+  for (int i = 0; i < 9; ++i) {
+    off[i] = o;
+    o = align256(o + sizes[i] * 4);
+  }
+  return o;
+}
+
+int spalu_mlp_workspace(int32_t batch, size_t* bytes) {
+  if (batch < 1 || !bytes) return fail(SPALU_EINVAL, "bad argument");
+  size_t off[9];
+  *bytes = mlp_ws_layout(batch, off);
+  return SPALU_OK;
+}
+
+static int mlp_forward_impl(const float* params, const float* X, int B, const float* t, char* ws, hipStream_t st,
+                            float** Xn, float** H1, float** H2, float** y, float** dz, float** sq) {
+  size_t off[9];
+  mlp_ws_layout(B, off);
+  *Xn = reinterpret_cast<float*>(ws + off[0]);
+  *H1 = reinterpret_cast<float*>(ws + off[1]);
+  *H2 = reinterpret_cast<float*>(ws + off[2]);
+  *y = reinterpret_cast<float*>(ws + off[3]);
+  *dz = reinterpret_cast<float*>(ws + off[4]);
+  *sq = reinterpret_cast<float*>(ws + off[5]);
+  k_mlp_normalize<<<nblocks(int64_t(B) * MLP_NF), WG, 0, st>>>(X, B, params, *Xn);
+  HIPCHK(hipGetLastError());
+  // H1 = relu(Xn W1^T + b1)
+  k_gemm_f32<<<dim3(1, unsigned(B)), MLP_H, 0, st>>>(B, MLP_H, MLP_NF, *Xn, MLP_NF, 1, params + MLP_OFF_W1, 1,
+                                                     MLP_NF, *H1, MLP_H, 0.f);
+  HIPCHK(hipGetLastError());
+  k_bias_relu<<<nblocks(int64_t(B) * MLP_H), WG, 0, st>>>(*H1, B, params + MLP_OFF_B1);
+  HIPCHK(hipGetLastError());
+  k_gemm_f32<<<dim3(1, unsigned(B)), MLP_H, 0, st>>>(B, MLP_H, MLP_H, *H1, MLP_H, 1, params + MLP_OFF_W2, 1, MLP_H,
+                                                     *H2, MLP_H, 0.f);
+  HIPCHK(hipGetLastError());
+  k_bias_relu<<<nblocks(int64_t(B) * MLP_H), WG, 0, st>>>(*H2, B, params + MLP_OFF_B2);
+  HIPCHK(hipGetLastError());
+  k_mlp_out<<<nblocks(B), WG, 0, st>>>(*H2, B, params, t, *y, *dz, *sq);
+  HIPCHK(hipGetLastError());
+  return SPALU_OK;
+}
+
+int spalu_mlp_forward(const float* params, const float* X, int32_t batch, float* y, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  if (!params || !X || !y || !workspace || batch < 1 || batch > 65535)
+    return fail(SPALU_EINVAL, "bad argument (batch must be in [1, 65535])");
+  size_t off[9];
+  if (workspace_bytes < mlp_ws_layout(batch, off)) return fail(SPALU_ENOMEM, "workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float *Xn, *H1, *H2, *yy, *dz, *sq;
+  const int rc = mlp_forward_impl(params, X, batch, nullptr, static_cast<char*>(workspace), st, &Xn, &H1, &H2, &yy,
+                                  &dz, &sq);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(y, yy, size_t(batch) * 4, hipMemcpyDeviceToDevice, st));
+  return SPALU_OK;
+}
+
+int spalu_mlp_train_step(float* params, float* adam_m, float* adam_v, const float* X, const float* t,
+                         int32_t batch, float lr, int32_t step, float* loss, float* grad, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+  if (!params || !X || !t || batch < 1 || batch > 65535 || !workspace || !loss)
+    return fail(SPALU_EINVAL, "bad argument (batch must be in [1, 65535])");
+  if ((adam_m == nullptr) != (adam_v == nullptr) || (adam_m && step < 1)) return fail(SPALU_EINVAL, "bad Adam state");
+  size_t off[9];
+  if (workspace_bytes < mlp_ws_layout(batch, off)) return fail(SPALU_ENOMEM, "workspace too small");
+  const int B = batch;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  float *Xn, *H1, *H2, *y, *dz, *sq;
+  int rc = mlp_forward_impl(params, X, B, t, ws, st, &Xn, &H1, &H2, &y, &dz, &sq);
+  if (rc) return rc;
+  float* dH2 = reinterpret_cast<float*>(ws + off[6]);
+  float* dH1 = reinterpret_cast<float*>(ws + off[7]);
+  float* g = grad ? grad : reinterpret_cast<float*>(ws + off[8]);
+  HIPCHK(hipMemsetAsync(g, 0, size_t(MLP_OFF_W1) * 4, st));
+  // loss = mean of squared errors
+  k_mean<<<1, 64, 0, st>>>(sq, B, loss);
+  HIPCHK(hipGetLastError());
+  // output layer
+  k_gemm_f32<<<dim3(1, MLP_H), 64, 0, st>>>(MLP_H, 1, B, H2, 1, MLP_H, dz, 1, 0, g + MLP_OFF_W3, 1, 0.f);
+  HIPCHK(hipGetLastError());
+  k_colsum<<<1, 64, 0, st>>>(dz, B, 1, 1, g + MLP_OFF_B3);
+  HIPCHK(hipGetLastError());
+  // second hidden layer
+  k_mlp_dh2<<<nblocks(int64_t(B) * MLP_H), WG, 0, st>>>(dz, H2, B, params, dH2);
+  HIPCHK(hipGetLastError());
+  k_gemm_f32<<<dim3(1, MLP_H), MLP_H, 0, st>>>(MLP_H, MLP_H, B, dH2, 1, MLP_H, H1, MLP_H, 1, g + MLP_OFF_W2,
+                                               MLP_H, 0.f);
+  HIPCHK(hipGetLastError());
+  k_colsum<<<1, MLP_H, 0, st>>>(dH2, B, MLP_H, MLP_H, g + MLP_OFF_B2);
+  HIPCHK(hipGetLastError());
+  // first hidden layer: dH1 = (dH2 W2) masked by H1 > 0
+  k_gemm_f32<<<dim3(1, unsigned(B)), MLP_H, 0, st>>>(B, MLP_H, MLP_H, dH2, MLP_H, 1, params + MLP_OFF_W2, MLP_H, 1,
+                                                     dH1, MLP_H, 0.f);
+  HIPCHK(hipGetLastError());
+  k_mask_pos<<<nblocks(int64_t(B) * MLP_H), WG, 0, st>>>(dH1, H1, B * MLP_H);
+  HIPCHK(hipGetLastError());
+  k_gemm_f32<<<dim3(1, MLP_H), MLP_NF, 0, st>>>(MLP_H, MLP_NF, B, dH1, 1, MLP_H, Xn, MLP_NF, 1, g + MLP_OFF_W1,
+                                                MLP_NF, 0.f);
+  HIPCHK(hipGetLastError());
+  k_colsum<<<1, MLP_H, 0, st>>>(dH1, B, MLP_H, MLP_H, g + MLP_OFF_B1);
+  HIPCHK(hipGetLastError());
+  if (adam_m) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, float(step)), c2 = 1.f - std::pow(b2, float(step));
+    k_adam<<<nblocks(MLP_NPARAM - MLP_OFF_W1), WG, 0, st>>>(params, g, adam_m, adam_v, MLP_OFF_W1, MLP_NPARAM, lr, b1,
+                                                            b2, 1e-8f, c1, c2);
+    HIPCHK(hipGetLastError());
+  }
   return SPALU_OK;
 }
 

@@ -45,7 +45,8 @@ class NdOpts(C.Structure):
 class FactorOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("precision", C.c_int32), ("seed", C.c_uint32),
                 ("rho", C.c_double), ("h0", C.c_int32), ("probes", C.c_int32),
-                ("tau", C.c_double), ("h_init", C.c_void_p)]
+                ("tau", C.c_double), ("h_init", C.c_void_p), ("rank_model", C.c_void_p),
+                ("features_out", C.c_void_p), ("rank_margin", C.c_float), ("rank_pad", C.c_int32)]
 
 
 class FactorInfo(C.Structure):
@@ -101,6 +102,11 @@ class KernelStat(C.Structure):
                 ("bytes", C.c_double), ("flops", C.c_double)]
 
 
+_lib.spalu_mlp_param_count.restype = C.c_int
+_lib.spalu_mlp_workspace.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+_lib.spalu_mlp_forward.argtypes = [P, P, C.c_int32, P, P, C.c_size_t, P]
+_lib.spalu_mlp_train_step.argtypes = [P, P, P, P, P, C.c_int32, C.c_float, C.c_int32, P, P, P,
+                                      C.c_size_t, P]
 _lib.spalu_profile.argtypes = [C.c_int32]
 _lib.spalu_profile.restype = None
 _lib.spalu_profile_read.argtypes = [C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]
@@ -109,7 +115,8 @@ EXPORTED = ["spalu_nd_order", "spalu_nd_info", "spalu_nd_perm", "spalu_nd_etree"
             "spalu_nd_segments", "spalu_nd_free", "spalu_factor_opts_default",
             "spalu_factor_workspace", "spalu_factor_seg_base", "spalu_factor",
             "spalu_factor_ranks", "spalu_factor_work", "spalu_factor_free", "spalu_solve_workspace", "spalu_solve",
-            "spalu_profile", "spalu_profile_read", "spalu_last_error"]
+            "spalu_mlp_param_count", "spalu_mlp_workspace", "spalu_mlp_forward",
+            "spalu_mlp_train_step", "spalu_profile", "spalu_profile_read", "spalu_last_error"]
 
 
 def _check(rc):
@@ -179,12 +186,15 @@ class ND:
 
 
 def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, tau=10.0,
-                h_init=None):
+                h_init=None, rank_model=None, features_out=None, rank_margin=1.1, rank_pad=5):
     o = FactorOpts()
     _lib.spalu_factor_opts_default(C.byref(o))
     o.eps, o.precision, o.seed, o.rho, o.h0, o.probes, o.tau = (
         float(eps), int(precision), int(seed) & 0xFFFFFFFF, float(rho), int(h0), int(probes), float(tau))
     o.h_init = None if h_init is None else int(h_init.data_ptr())
+    o.rank_model = None if rank_model is None else int(rank_model.data_ptr())
+    o.features_out = None if features_out is None else int(features_out.data_ptr())
+    o.rank_margin, o.rank_pad = float(rank_margin), int(rank_pad)
     return o
 
 
@@ -198,7 +208,8 @@ class Factor:
     """spaLU factorization of a CSR matrix held in device memory (torch)."""
 
     def __init__(self, nd, rowptr, colind, vals, eps=1e-6, precision=FP64, seed=1234, rho=0.5,
-                 h0=8, probes=5, tau=10.0, h_init=None, stream=None):
+                 h0=8, probes=5, tau=10.0, h_init=None, rank_model=None, features_out=None,
+                 stream=None):
         import torch
         assert rowptr.is_cuda and rowptr.dtype == torch.int64
         assert colind.is_cuda and colind.dtype == torch.int32
@@ -206,7 +217,15 @@ class Factor:
         self.nd = nd
         self.csr = (rowptr.contiguous(), colind.contiguous(), vals.contiguous())
         self.h_init = h_init
-        self.opts = factor_opts(eps, precision, seed, rho, h0, probes, tau, h_init)
+        self.rank_model = rank_model
+        if rank_model is not None:
+            assert rank_model.is_cuda and rank_model.dtype == torch.float32
+            assert rank_model.numel() == mlp_param_count()
+        if features_out is not None:
+            assert features_out.is_cuda and features_out.dtype == torch.float32
+            assert features_out.numel() >= nd.nsegments * 12
+        self.opts = factor_opts(eps, precision, seed, rho, h0, probes, tau, h_init, rank_model,
+                                features_out)
         nbytes = factor_workspace_bytes(nd, self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=rowptr.device)
         s = torch.cuda.current_stream() if stream is None else stream
@@ -293,3 +312,39 @@ def profile_read():
     _check(_lib.spalu_profile_read(arr, cnt.value, C.byref(cnt)))
     return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, bytes=arr[i].bytes,
                                        flops=arr[i].flops) for i in range(cnt.value)}
+
+
+def mlp_param_count():
+    return int(_lib.spalu_mlp_param_count())
+
+
+def _mlp_ws(batch, device):
+    b = C.c_size_t()
+    _check(_lib.spalu_mlp_workspace(int(batch), C.byref(b)))
+    return torch.empty(b.value, dtype=torch.uint8, device=device)
+
+
+def mlp_forward(params, X):
+    """Network outputs (rank fractions) for feature rows X (B x 12), FP32."""
+    B = X.shape[0]
+    y = torch.empty(B, dtype=torch.float32, device=X.device)
+    ws = _mlp_ws(B, X.device)
+    _check(_lib.spalu_mlp_forward(params.data_ptr(), X.contiguous().data_ptr(), B, y.data_ptr(),
+                                  ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream))
+    return y
+
+
+def mlp_train_step(params, X, t, lr=1e-3, step=1, adam=None, want_grad=False, ws=None):
+    """One FP32 training step on the GPU (forward, backward, optional Adam
+    with state adam = (m, v)).  Returns (loss tensor, grad tensor or None)."""
+    B = X.shape[0]
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    grad = torch.empty(mlp_param_count(), dtype=torch.float32, device=X.device) if want_grad else None
+    ws = _mlp_ws(B, X.device) if ws is None else ws
+    m, v = (None, None) if adam is None else adam
+    _check(_lib.spalu_mlp_train_step(params.data_ptr(), None if m is None else m.data_ptr(),
+                                     None if v is None else v.data_ptr(), X.contiguous().data_ptr(),
+                                     t.contiguous().data_ptr(), B, float(lr), int(step), loss.data_ptr(),
+                                     None if grad is None else grad.data_ptr(), ws.data_ptr(), ws.numel(),
+                                     torch.cuda.current_stream().cuda_stream))
+    return loss, grad

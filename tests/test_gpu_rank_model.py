@@ -1,0 +1,135 @@
+"""GPU tests of the learned-rank form: the library's FP32 training kernels
+against the FP64 oracle (forward, gradients, Adam), the device features
+against the oracle's features, the fallback when predictions are bad, and
+what the trained network gains over the plain adaptive ID."""
+import os
+
+import numpy as np
+import pytest
+
+from helpers import rel_res, to_device
+from oracle import mlp as M
+from oracle import spalu as O
+from oracle.nd import nd_order
+from workloads import make_config
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_2408_14193_amd import spalu
+    return spalu
+
+
+def _data(seed=0, B=300):
+    rng = np.random.default_rng(seed)
+    p = M.init_params(rng.standard_normal(M.NF), 0.5 + rng.random(M.NF), seed)
+    p[M.OFF_B1:M.OFF_W2] = 0.1 * rng.standard_normal(M.H)
+    p[M.OFF_B2:M.OFF_W3] = 0.1 * rng.standard_normal(M.H)
+    X = rng.standard_normal((B, M.NF))
+    t = rng.random(B)
+    return p.astype(np.float32), X.astype(np.float32), t.astype(np.float32)
+
+
+def test_forward_and_gradient_match_oracle(S):
+    import torch
+    p, X, t = _data()
+    dp = torch.from_numpy(p).cuda()
+    y = S.mlp_forward(dp, torch.from_numpy(X).cuda()).cpu().numpy()
+    yo, _ = M.forward(p.astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(y - yo)) <= 1e-5
+    loss, grad = S.mlp_train_step(dp, torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda(), want_grad=True)
+    lo, go = M.loss_and_grad(p.astype(np.float64), X.astype(np.float64), t.astype(np.float64))
+    g = grad.cpu().numpy().astype(np.float64)
+    assert abs(float(loss.item()) - lo) <= 1e-5 * max(1.0, lo)
+    assert np.linalg.norm(g - go) <= 1e-4 * np.linalg.norm(go)
+    assert np.all(g[:M.OFF_W1] == 0.0)
+
+
+def test_adam_step_matches_oracle(S):
+    import torch
+    p, X, t = _data(1)
+    dp = torch.from_numpy(p).cuda()
+    m = torch.zeros_like(dp)
+    v = torch.zeros_like(dp)
+    Xd, td = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+    po = p.astype(np.float64)
+    mo = np.zeros_like(po)
+    vo = np.zeros_like(po)
+    for step in (1, 2, 3):
+        S.mlp_train_step(dp, Xd, td, lr=1e-3, step=step, adam=(m, v))
+        _, go = M.loss_and_grad(po, X.astype(np.float64), t.astype(np.float64))
+        po, mo, vo = M.adam_step(po, go, mo, vo, step, lr=1e-3)
+    assert np.max(np.abs(dp.cpu().numpy() - po)) <= 1e-5
+
+
+@pytest.mark.parametrize("cfg", [0, 2, 4])
+def test_device_features_match_oracle(S, cfg):
+    import torch
+    P = make_config(cfg, side=31, nrhs=1)
+    eps = P.eps
+    nd = S.ND(P.dims)
+    rp, ci, v, B = to_device(P)
+    feats = torch.zeros(nd.nsegments * 12, dtype=torch.float32, device="cuda")
+    F = S.Factor(nd, rp, ci, v, eps=eps, features_out=feats)
+    fg = feats.view(-1, 12).cpu().numpy()
+    ndo = nd_order(P.dims)
+    OF = O.factor(ndo, P.scipy(), O.Opts(eps=eps))
+    base = nd.seg_base()
+    A = P.scipy()
+    for lev in (ndo.L, ndo.L - 1, 1):
+        rec = OF.levels[lev]
+        cur = {c: r.dofs for c, r in enumerate(rec.segs)}
+        for c in range(len(rec.segs)):
+            fo = M.segment_features(ndo, A, lev, c, cur, eps)
+            assert np.allclose(fg[base[lev] + c], fo, rtol=1e-5, atol=1e-5), (lev, c, fg[base[lev] + c], fo)
+
+
+def test_bad_predictions_fall_back_to_resampling(S):
+    """A predictor that always says rank 0 starts every ID at h = pad
+    samples; the probe check must reject the under-sampled IDs and the
+    doubling fallback must still reach an accurate factorization."""
+    import torch
+    P = make_config(4, side=63, nrhs=2)
+    nd = S.ND(P.dims)
+    rp, ci, v, B = to_device(P)
+    p = np.zeros(S.mlp_param_count(), np.float32)
+    p[12:24] = 1.0
+    p[-1] = -40.0                      # sigmoid(-40): predicted rank 0
+    Fb = S.Factor(nd, rp, ci, v, eps=P.eps, rank_model=torch.from_numpy(p).cuda())
+    Fp = S.Factor(nd, rp, ci, v, eps=P.eps)
+    assert Fb.info["resampled"] > 0
+    nb, rk, hh, ps = Fb.ranks()
+    assert ps.max() > 1
+    Xb, ib = Fb.solve(B, tol=1e-10, max_iter=40)
+    Xp, ip = Fp.solve(B, tol=1e-10, max_iter=40)
+    assert ib["converged"] and ip["converged"]
+    assert ib["first_rel_residual"] <= 10 * ip["first_rel_residual"]
+    assert rel_res(P, Xb.cpu().numpy()).max() <= 1e-10
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(os.path.dirname(os.path.dirname(__file__)),
+                                                    "paper_2408_14193_amd", "rank_model.npy")),
+                    reason="trained weights not present")
+def test_trained_predictor_saves_sampling_passes(S):
+    """Ablation on the Helmholtz family (10 points per wavelength): the
+    trained predictor needs fewer ID passes than the plain adaptive sampler
+    and the refined solution is as accurate."""
+    from paper_2408_14193_amd import rank_model
+    P = make_config(4, side=255, nrhs=4)
+    nd = S.ND(P.dims)
+    rp, ci, v, B = to_device(P)
+    w = rank_model.load()
+    Fl = S.Factor(nd, rp, ci, v, eps=P.eps, precision=S.FP32, rank_model=w)
+    Fp = S.Factor(nd, rp, ci, v, eps=P.eps, precision=S.FP32)
+    print("learned: passes %d resampled %d | plain: passes %d resampled %d"
+          % (Fl.info["sample_passes"], Fl.info["resampled"], Fp.info["sample_passes"], Fp.info["resampled"]))
+    assert Fl.info["resampled"] < Fp.info["resampled"]
+    assert Fl.info["sample_passes"] < Fp.info["sample_passes"]
+    Xl, il = Fl.solve(B, tol=1e-8, max_iter=40)
+    Xp, ip = Fp.solve(B, tol=1e-8, max_iter=40)
+    assert il["converged"] and ip["converged"]
+    assert rel_res(P, Xl.cpu().numpy()).max() <= 1e-8
