@@ -10,8 +10,12 @@ sides and nested-dissection plan are resident before the timed region
 Default workload: -div(a grad u) on the 1023 x 1023 interior grid, a =
 exp(Gaussian random field, correlation length 0.05, std 1), 16 right-hand
 sides uniform in [-1, 1], eps = 1e-4, refinement to 1e-10.  The headline
-`value` is the mixed form (FP32 storage and GEMMs, FP64 pivoted LU / ID
-solve / residual); the plain FP64 form is reported beside it.
+`value` is the learned form: FP32 storage and products (FP64 pivoted LU of
+diagonal blocks, ID triangular solve and refinement residual), the solve
+sweeps captured as a HIP graph, and the trained rank predictor choosing each
+segment's first sample count.  Beside it: the mixed form (the same without
+the predictor) and the plain form (FP64 everywhere, adaptive sampling,
+direct per-level launches).
 """
 from __future__ import annotations
 
@@ -37,7 +41,7 @@ def parse():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--side", type=int, default=None)
     ap.add_argument("--nrhs", type=int, default=None)
-    ap.add_argument("--forms", default="mixed,plain")
+    ap.add_argument("--forms", default="learned,mixed,plain")
     ap.add_argument("--cpu-side", type=int, default=255)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--verbose", action="store_true")
@@ -52,7 +56,11 @@ def log(*a):
 def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True):
     import numpy as np
     import torch
-    prec = S.FP32 if form == "mixed" else S.FP64
+    prec = S.FP64 if form == "plain" else S.FP32
+    model = None
+    if form == "learned":
+        from paper_2408_14193_amd import rank_model
+        model = rank_model.load(device=dev)
     rp = torch.from_numpy(P.indptr).to(dev)
     ci = torch.from_numpy(P.indices).to(dev)
     v = torch.from_numpy(P.data).to(dev)
@@ -62,9 +70,9 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True):
 
     def step():
         t0 = time.perf_counter()
-        F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec)
+        F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec, rank_model=model)
         t1 = time.perf_counter()
-        info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(graph and form == "mixed"))
+        info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(graph and form != "plain"))
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return F, info, rr, t1 - t0, t2 - t1
@@ -112,7 +120,7 @@ def roofline(prof, form):
     fpl = st["flops"] / st["launches"]
     gbs = bpl / (avg_ms * 1e-3) / 1e9
     tfs = fpl / (avg_ms * 1e-3) / 1e12
-    peak_f = FP32_PEAK_TFS if form == "mixed" else FP64_PEAK_TFS
+    peak_f = FP64_PEAK_TFS if form == "plain" else FP32_PEAK_TFS
     return dict(kernel=name, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None,
                 launches=st["launches"], avg_launch_ms=round(avg_ms, 4),
@@ -181,7 +189,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32" if head == "mixed" else "fp64",
+        "dtype": "fp64" if head == "plain" else "fp32",
         "data": "synthetic",
         "config": {"workload": "%s %s, N=%d, %d RHS, eps=%g, refinement to %g, %s form"
                                % (P.name, "x".join(map(str, P.dims)), P.n, P.nrhs, P.eps, P.tol, head),
