@@ -109,6 +109,29 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   }
 }
 
+// Orders the LDS accesses of one wave (no workgroup barrier).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Both normals of one Philox draw: rows 2*pair (cos branch) and 2*pair+1
+// (sin branch) of the same stream, as gauss_entry defines them.
+__device__ inline void gauss_pair(uint32_t seed, int level, int stream, int pair, int vert, int seg, int half,
+                                  double* even, double* odd) {
+  uint32_t c[4] = {uint32_t(pair), uint32_t(vert), uint32_t(seg), uint32_t(half)};
+  philox4x32_10(c, seed, uint32_t(2 * level + stream));
+  const uint64_t a = ((uint64_t(c[1]) << 32) | c[0]) >> 11;
+  const uint64_t b = ((uint64_t(c[3]) << 32) | c[2]) >> 11;
+  const double u1 = double(a) * 0x1p-53 + 0x1p-54;
+  const double u2 = double(b) * 0x1p-53 + 0x1p-54;
+  const double r = sqrt(-2.0 * log(u1));
+  const double ang = 2.0 * 3.141592653589793 * u2;
+  *even = r * cos(ang);
+  *odd = r * sin(ang);
+}
+
 // Normal number of row `row` for the DOF (vert, half) of segment `seg`:
 // key (seed, 2*level+stream), counter (row>>1, vert, seg, half), two 53-bit
 // uniforms, Box-Muller (cos branch for even rows, sin for odd).

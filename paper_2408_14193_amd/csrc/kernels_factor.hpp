@@ -189,576 +189,6 @@ struct IdParams {
   const int32_t* h_init;  // optional start samples (learned form)
 };
 
-// CPQR of Y (m x n, column-major, ld) with fresh column norms each step and
-// the tie rule of the oracle; returns k and writes |R_11| to *r11.  perm[]
-// (original column index per position) is permuted alongside.
-__device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps, double* nrm,
-                          double* s_scal, int* s_int, double* r11_out) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int kk = m < n ? m : n;
-  int k = kk;
-  double r11 = 0.0;
-  for (int j = 0; j < kk; ++j) {
-    for (int col = j + wv; col < n; col += NWAVE) {
-      double s = 0.0;
-      for (int i = j + lane; i < m; i += 64) {
-        const double y = Y[size_t(col) * ld + i];
-        s += y * y;
-      }
-      s = wave_sum(s);
-      if (lane == 0) nrm[col] = sqrt(s);
-    }
-    __syncthreads();
-    if (wv == 0) {
-      double mx = 0.0;
-      for (int col = j + lane; col < n; col += 64) mx = fmax(mx, nrm[col]);
-      mx = wave_max(mx);
-      int key = 1 << 30, q = 1 << 30;
-      for (int col = j + lane; col < n; col += 64)
-        if (nrm[col] >= mx * (1.0 - 1e-12)) {
-          const int pk = perm[col];
-          if (pk < key) {
-            key = pk;
-            q = col;
-          }
-        }
-      wave_argmin_int(key, q);
-      if (lane == 0) {
-        s_scal[0] = mx;
-        s_int[0] = q;
-      }
-    }
-    __syncthreads();
-    const double mx = s_scal[0];
-    const int q = s_int[0];
-    if (j == 0) r11 = mx;
-    if (mx == 0.0 || mx <= eps * r11) {
-      k = j;
-      break;
-    }
-    if (q != j) {
-      for (int i = tid; i < m; i += WG) {
-        const double t = Y[size_t(j) * ld + i];
-        Y[size_t(j) * ld + i] = Y[size_t(q) * ld + i];
-        Y[size_t(q) * ld + i] = t;
-      }
-      if (tid == 0) {
-        const int t = perm[j];
-        perm[j] = perm[q];
-        perm[q] = t;
-      }
-    }
-    __syncthreads();
-    const double alpha = nrm[q];
-    const double x0 = Y[size_t(j) * ld + j];
-    const double sg = x0 >= 0.0 ? 1.0 : -1.0;
-    const double v0 = x0 + sg * alpha;
-    if (wv == 0) {
-      double s = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) {
-        const double y = Y[size_t(j) * ld + i];
-        s += y * y;
-      }
-      s = wave_sum(s);
-      if (lane == 0) s_scal[1] = s + v0 * v0;
-    }
-    __syncthreads();
-    const double vv = s_scal[1];
-    for (int col = j + 1 + wv; col < n; col += NWAVE) {
-      double w = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) w += Y[size_t(j) * ld + i] * Y[size_t(col) * ld + i];
-      w = wave_sum(w) + v0 * Y[size_t(col) * ld + j];
-      const double f = 2.0 * w / vv;
-      if (lane == 0) Y[size_t(col) * ld + j] -= f * v0;
-      for (int i = j + 1 + lane; i < m; i += 64) Y[size_t(col) * ld + i] -= f * Y[size_t(j) * ld + i];
-    }
-    __syncthreads();
-    if (tid == 0) Y[size_t(j) * ld + j] = -sg * alpha;
-    __syncthreads();
-  }
-  *r11_out = r11;
-  return k;
-}
-
-// LDS-resident ID: sizes for which all coupling rows, the work matrix and
-// a sampling tile fit the 48 KB staging buffer.
-constexpr int ID_LDS_DOUBLES = 6144;
-constexpr int ID_TILE = 32;            // G tile is ID_TILE x ID_TILE
-constexpr int ID_MAXR = 1024;          // rows
-constexpr int ID_MAXNB = 64;           // neighbour segments
-
-__device__ inline bool id_fits_lds(int n, int R, int nnb) {
-  // n <= 64: a 32-row sampling tile times n columns is at most 8 outputs
-  // per thread (the per-thread accumulators)
-  return nnb <= ID_MAXNB && R <= ID_MAXR && n <= 64 &&
-         2 * R * n + ID_TILE * ID_TILE + 9 * n <= ID_LDS_DOUBLES;
-}
-
-// Rows of the stacked coupling matrix: 2 * sum of neighbour sizes.
-__device__ inline int id_rows(const DSeg& S, const DNbr* nbrs, const DLevelDyn& dyn) {
-  int R = 0;
-  for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += 2 * dyn.n[nbrs[e].d];
-  return R;
-}
-
-template <typename T>
-__global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const DNbr* nbrs,
-                                               const DBlk* blks, GridGeom g, int32_t* iarena,
-                                               T* varena, double* scratch, DLevelDyn dyn,
-                                               IdParams prm) {
-  extern __shared__ double lds[];
-  __shared__ double s_nrm[512];
-  __shared__ double s_scal[4];
-  __shared__ int s_int[4];
-  __shared__ int s_w[NWAVE];
-  __shared__ int s_cnt[2];
-  const int c = blockIdx.x;
-  if (c >= nseg) return;
-  const int tid = threadIdx.x;
-  const DSeg S = segs[c];
-  const int n = dyn.n[c];
-  const bool do_id = (S.flags & SEG_REGULAR) && (S.flags & SEG_HAS_NBR) && prm.eps > 0.0 && n > 0;
-  if (do_id && id_fits_lds(n, id_rows(S, nbrs, dyn), S.nbr_end - S.nbr_begin)) return;
-  int32_t* dofs = iarena + S.ioff;
-  int32_t* perm = dofs + S.cap;
-  int32_t* tag = perm + 2 * S.cap;  // after piv
-  for (int i = tid; i < n; i += WG) perm[i] = i;
-  if (!do_id) {
-    if (tid == 0) {
-      dyn.k[c] = n;
-      dyn.nr[c] = 0;
-      dyn.h[c] = 0;
-      dyn.passes[c] = 0;
-    }
-    return;
-  }
-  const size_t rc = size_t(S.rcap);
-  double* BN = scratch + S.scr_off;  // near rows, column-major (ld rcap)
-  double* BF = BN + rc * S.cap;      // far rows, row-major (ld n)
-  double* Yg = BF + rc * S.cap;      // work matrix, column-major (ld rcap)
-  double* P = Yg + rc * S.cap;       // probe rows, row-major (8 x n)
-  if (tid == 0) {
-    s_cnt[0] = 0;
-    s_cnt[1] = 0;
-  }
-  __syncthreads();
-  // 1. stack [A_{n,c}; A_{c,n}^T] row by row, split near / far
-  for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
-    const DNbr nb = nbrs[e];
-    const int nd = dyn.n[nb.d];
-    const int32_t* dd = iarena + segs[nb.d].ioff;
-    for (int half = 0; half < 2; ++half) {
-      const T* blk = varena + blks[half == 0 ? nb.blk_dc : nb.blk_cd].off;
-      for (int base = 0; base < nd; base += WG) {
-        const int i = base + tid;
-        const bool valid = i < nd;
-        int v = 0;
-        bool near = false;
-        if (valid) {
-          v = dd[i];
-          int cv[3];
-          vcoords(g, v, cv);
-          int dist = 0;
-          for (int a = 0; a < 3; ++a) {
-            int da = S.lo[a] - cv[a];
-            if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
-            if (da > dist) dist = da;
-          }
-          near = dist <= S.thr;
-        }
-        int tn, tf;
-        const int pn = block_scan_flag(valid && near, s_w, &tn);
-        const int pf = block_scan_flag(valid && !near, s_w, &tf);
-        const int bn = s_cnt[0], bf = s_cnt[1];
-        if (valid) {
-          if (near) {
-            const int r = bn + pn;
-            for (int j = 0; j < n; ++j)
-              BN[size_t(j) * rc + r] = double(half == 0 ? blk[size_t(i) * n + j] : blk[size_t(j) * nd + i]);
-          } else {
-            const int r = bf + pf;
-            for (int j = 0; j < n; ++j)
-              BF[size_t(r) * n + j] = double(half == 0 ? blk[size_t(i) * n + j] : blk[size_t(j) * nd + i]);
-            tag[2 * r] = v;
-            tag[2 * r + 1] = half;
-          }
-        }
-        __syncthreads();
-        if (tid == 0) {
-          s_cnt[0] = bn + tn;
-          s_cnt[1] = bf + tf;
-        }
-        __syncthreads();
-      }
-    }
-  }
-  const int nN = s_cnt[0], nF = s_cnt[1];
-  if (nN + nF == 0) {  // no coupling rows left: nothing to compress against
-    if (tid == 0) {
-      dyn.k[c] = n;
-      dyn.nr[c] = 0;
-      dyn.h[c] = 0;
-      dyn.passes[c] = 0;
-    }
-    return;
-  }
-  int h = prm.h0;
-  if (prm.h_init) {
-    const int hi = prm.h_init[prm.seg_base + c];
-    if (hi > 0) h = hi;
-  }
-  int passes = 0, k = 0;
-  double r11 = 0.0;
-  T* Tm = varena + S.t_off;
-  while (true) {
-    ++passes;
-    const bool sampled = h < nF;
-    const int m = nN + (sampled ? h : nF);
-    // 2. Y = [B_N; G B_F / sqrt(h)] (or the exact far rows)
-    for (int t = tid; t < nN * n; t += WG) {
-      const int j = t / nN, i = t % nN;
-      Yg[size_t(j) * rc + i] = BN[size_t(j) * rc + i];
-    }
-    if (!sampled) {
-      for (int t = tid; t < nF * n; t += WG) {
-        const int f = t / n, j = t % n;
-        Yg[size_t(j) * rc + nN + f] = BF[size_t(f) * n + j];
-      }
-    } else {
-      const double sc = 1.0 / sqrt(double(h));
-      for (int t = tid; t < h * n; t += WG) {
-        const int i = t % h, j = t / h;
-        Yg[size_t(j) * rc + nN + i] = 0.0;
-      }
-      for (int t = tid; t < prm.probes * n; t += WG) P[t] = 0.0;
-      const int hp = h + prm.probes;  // sample rows, then probe rows
-      for (int i0 = 0; i0 < hp; i0 += 32) {
-        const int ih = hp - i0 < 32 ? hp - i0 : 32;
-        for (int f0 = 0; f0 < nF; f0 += 64) {
-          const int fw = nF - f0 < 64 ? nF - f0 : 64;
-          __syncthreads();
-          for (int t = tid; t < ih * fw; t += WG) {
-            const int ii = t / fw, f = t % fw;
-            const int row = i0 + ii;
-            const int stream = row < h ? 0 : 1;
-            const int r = row < h ? row : row - h;
-            lds[ii * 64 + f] = gauss_entry(prm.seed, prm.level, stream, r, tag[2 * (f0 + f)], c,
-                                           tag[2 * (f0 + f) + 1]);
-          }
-          __syncthreads();
-          for (int t = tid; t < ih * n; t += WG) {
-            const int ii = t / n, j = t % n;
-            double acc = 0.0;
-            for (int f = 0; f < fw; ++f) acc += lds[ii * 64 + f] * BF[size_t(f0 + f) * n + j];
-            const int row = i0 + ii;
-            if (row < h)
-              Yg[size_t(j) * rc + nN + row] += acc;
-            else
-              P[(row - h) * n + j] += acc;
-          }
-        }
-      }
-      __syncthreads();
-      for (int t = tid; t < h * n; t += WG) {
-        const int i = t % h, j = t / h;
-        Yg[size_t(j) * rc + nN + i] *= sc;
-      }
-    }
-    for (int i = tid; i < n; i += WG) perm[i] = i;
-    __syncthreads();
-    // 3. CPQR (staged in LDS when it fits)
-    const bool inlds = size_t(m) * n <= LDS_DOUBLES;
-    double* Y = inlds ? lds : Yg;
-    const int ld = inlds ? m : int(rc);
-    if (inlds) {
-      for (int t = tid; t < m * n; t += WG) {
-        const int j = t / m, i = t % m;
-        lds[t] = Yg[size_t(j) * rc + i];
-      }
-    }
-    double* nrm = n <= 512 ? s_nrm : P + 8 * n;
-    __syncthreads();
-    k = block_cpqr(Y, ld, m, n, perm, prm.eps, nrm, s_scal, s_int, &r11);
-    __syncthreads();
-    // 4. T = R11^{-1} R12 (back substitution in FP64, in place in Y)
-    const int nr = n - k;
-    for (int q = tid; q < nr; q += WG) {
-      double* col = Y + size_t(k + q) * ld;
-      for (int i = k - 1; i >= 0; --i) {
-        double s = col[i];
-        for (int t = i + 1; t < k; ++t) s -= Y[size_t(t) * ld + i] * col[t];
-        col[i] = s / Y[size_t(i) * ld + i];
-      }
-    }
-    __syncthreads();
-    bool accept = true;
-    if (sampled) {
-      // 5. a-posteriori check with the probe rows: E = P_r - P_s T
-      double worst = 0.0;
-      for (int pr = 0; pr < prm.probes; ++pr) {
-        double s = 0.0;
-        for (int q = tid; q < nr; q += WG) {
-          double e = P[pr * n + perm[k + q]];
-          for (int t = 0; t < k; ++t) e -= P[pr * n + perm[t]] * Y[size_t(k + q) * ld + t];
-          s += e * e;
-        }
-        s = block_sum(s, s_scal);
-        worst = fmax(worst, sqrt(s));
-      }
-      accept = worst <= prm.tau * prm.eps * r11;
-    }
-    if (accept) {
-      for (int t = tid; t < k * nr; t += WG) {
-        const int i = t / nr, q = t % nr;
-        Tm[t] = T(Y[size_t(k + q) * ld + i]);
-      }
-      break;
-    }
-    h *= 2;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    dyn.k[c] = k;
-    dyn.nr[c] = n - k;
-    dyn.h[c] = h < nF ? h : nF;
-    dyn.passes[c] = passes;
-  }
-}
-
-
-// The same ID with every operand in LDS (small segments: the fine levels,
-// where nearly all segments live).  One parallel gather of the stacked rows
-// [A_{n,s}; A_{s,n}^T], one block scan to place near rows in Y and far rows
-// in B_F, then sampling, CPQR, T and the probe check without leaving LDS.
-template <typename T>
-__global__ __launch_bounds__(WG) void k_seg_id_lds(const DSeg* segs, int nseg, const DNbr* nbrs,
-                                                   const DBlk* blks, GridGeom g, int32_t* iarena,
-                                                   T* varena, DLevelDyn dyn, IdParams prm) {
-  extern __shared__ double lds[];
-  __shared__ int s_noff[ID_MAXNB + 1];
-  __shared__ int s_tag[2 * ID_MAXR];
-  __shared__ int s_dst[ID_MAXR];
-  __shared__ int s_perm[512];
-  __shared__ double s_scal[4];
-  __shared__ int s_int[4];
-  __shared__ int s_w[NWAVE];
-  const int c = blockIdx.x;
-  if (c >= nseg) return;
-  const int tid = threadIdx.x;
-  const DSeg S = segs[c];
-  const int n = dyn.n[c];
-  const bool do_id = (S.flags & SEG_REGULAR) && (S.flags & SEG_HAS_NBR) && prm.eps > 0.0 && n > 0;
-  const int nnb = S.nbr_end - S.nbr_begin;
-  if (!do_id) return;  // handled (identity) by the global kernel
-  const int R = id_rows(S, nbrs, dyn);
-  if (!id_fits_lds(n, R, nnb)) return;
-  int32_t* dofs = iarena + S.ioff;
-  int32_t* perm = dofs + S.cap;
-  if (tid == 0) {
-    int o = 0;
-    for (int e = 0; e < nnb; ++e) {
-      s_noff[e] = o;
-      o += 2 * dyn.n[nbrs[S.nbr_begin + e].d];
-    }
-    s_noff[nnb] = o;
-  }
-  __syncthreads();
-  if (R == 0) {
-    for (int i = tid; i < n; i += WG) perm[i] = i;
-    if (tid == 0) {
-      dyn.k[c] = n;
-      dyn.nr[c] = 0;
-      dyn.h[c] = 0;
-      dyn.passes[c] = 0;
-    }
-    return;
-  }
-  double* Y = lds;                          // column-major, ld R
-  double* BF = lds + size_t(R) * n;         // far rows, row-major (ld n)
-  double* Gt = BF + size_t(R) * n;          // sampling tile
-  double* P = Gt + ID_TILE * ID_TILE;       // probe rows (8 x n)
-  double* nrm = P + 8 * n;                  // column norms (n)
-  // 1. classify rows (near / far) and place them
-  int nN = 0, nF = 0;
-  for (int base = 0; base < R; base += WG) {
-    const int r = base + tid;
-    const bool valid = r < R;
-    bool near = false;
-    int v = 0, half = 0;
-    if (valid) {
-      int e = 0;
-      while (s_noff[e + 1] <= r) ++e;
-      const DNbr nb = nbrs[S.nbr_begin + e];
-      const int nd = dyn.n[nb.d];
-      const int q = r - s_noff[e];
-      half = q / nd;
-      v = iarena[segs[nb.d].ioff + (q % nd)];
-      int cv[3];
-      vcoords(g, v, cv);
-      int dist = 0;
-      for (int a = 0; a < 3; ++a) {
-        int da = S.lo[a] - cv[a];
-        if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
-        if (da > dist) dist = da;
-      }
-      near = dist <= S.thr;
-    }
-    int tn, tf;
-    const int pn = block_scan_flag(valid && near, s_w, &tn);
-    const int pf = block_scan_flag(valid && !near, s_w, &tf);
-    if (valid) {
-      if (near) {
-        s_dst[r] = nN + pn;
-      } else {
-        s_dst[r] = -(nF + pf) - 1;
-        s_tag[2 * (nF + pf)] = v;
-        s_tag[2 * (nF + pf) + 1] = half;
-      }
-    }
-    nN += tn;
-    nF += tf;
-  }
-  __syncthreads();
-  // 2. gather values: near rows into Y, far rows into BF
-  for (int t = tid; t < R * n; t += WG) {
-    const int r = t / n, j = t % n;
-    int e = 0;
-    while (s_noff[e + 1] <= r) ++e;
-    const DNbr nb = nbrs[S.nbr_begin + e];
-    const int nd = dyn.n[nb.d];
-    const int q = r - s_noff[e];
-    const int half = q / nd, i = q % nd;
-    const double val = half == 0 ? double(varena[blks[nb.blk_dc].off + size_t(i) * n + j])
-                                 : double(varena[blks[nb.blk_cd].off + size_t(j) * nd + i]);
-    const int dst = s_dst[r];
-    if (dst >= 0)
-      Y[size_t(j) * R + dst] = val;
-    else
-      BF[size_t(-dst - 1) * n + j] = val;
-  }
-  __syncthreads();
-  int h = prm.h0;
-  if (prm.h_init) {
-    const int hi = prm.h_init[prm.seg_base + c];
-    if (hi > 0) h = hi;
-  }
-  int passes = 0, k = 0;
-  double r11 = 0.0;
-  T* Tm = varena + S.t_off;
-  while (true) {
-    ++passes;
-    const bool sampled = h < nF;
-    const int m = nN + (sampled ? h : nF);
-    if (passes > 1) {
-      // the previous CPQR overwrote the near rows: gather them again
-      for (int t = tid; t < R * n; t += WG) {
-        const int r = t / n, j = t % n;
-        const int dst = s_dst[r];
-        if (dst < 0) continue;
-        int e = 0;
-        while (s_noff[e + 1] <= r) ++e;
-        const DNbr nb = nbrs[S.nbr_begin + e];
-        const int nd = dyn.n[nb.d];
-        const int q = r - s_noff[e];
-        const int half = q / nd, i = q % nd;
-        Y[size_t(j) * R + dst] = half == 0 ? double(varena[blks[nb.blk_dc].off + size_t(i) * n + j])
-                                           : double(varena[blks[nb.blk_cd].off + size_t(j) * nd + i]);
-      }
-    }
-    if (!sampled) {
-      for (int t = tid; t < nF * n; t += WG) {
-        const int f = t / n, j = t % n;
-        Y[size_t(j) * R + nN + f] = BF[size_t(f) * n + j];
-      }
-    } else {
-      const double sc = 1.0 / sqrt(double(h));
-      const int hp = h + prm.probes;
-      for (int i0 = 0; i0 < hp; i0 += ID_TILE) {
-        const int ih = hp - i0 < ID_TILE ? hp - i0 : ID_TILE;
-        // each thread owns (row, column) outputs of this row tile
-        double acc[8];
-        for (int a = 0; a < 8; ++a) acc[a] = 0.0;
-        for (int f0 = 0; f0 < nF; f0 += ID_TILE) {
-          const int fw = nF - f0 < ID_TILE ? nF - f0 : ID_TILE;
-          __syncthreads();
-          for (int t = tid; t < ih * fw; t += WG) {
-            const int ii = t / fw, f = t % fw;
-            const int row = i0 + ii;
-            const int stream = row < h ? 0 : 1;
-            const int rr = row < h ? row : row - h;
-            Gt[ii * ID_TILE + f] = gauss_entry(prm.seed, prm.level, stream, rr, s_tag[2 * (f0 + f)], c,
-                                               s_tag[2 * (f0 + f) + 1]);
-          }
-          __syncthreads();
-          int a = 0;
-          for (int t = tid; t < ih * n; t += WG, ++a) {
-            const int ii = t / n, j = t % n;
-            double sacc = 0.0;
-            for (int f = 0; f < fw; ++f) sacc += Gt[ii * ID_TILE + f] * BF[size_t(f0 + f) * n + j];
-            if (a < 8) acc[a] += sacc;
-          }
-        }
-        int a = 0;
-        for (int t = tid; t < ih * n; t += WG, ++a) {
-          const int ii = t / n, j = t % n;
-          const int row = i0 + ii;
-          if (row < h)
-            Y[size_t(j) * R + nN + row] = acc[a] * sc;
-          else
-            P[(row - h) * n + j] = acc[a];
-        }
-      }
-    }
-    for (int i = tid; i < n; i += WG) s_perm[i] = i;
-    __syncthreads();
-    // 3. CPQR in LDS
-    k = block_cpqr(Y, R, m, n, s_perm, prm.eps, nrm, s_scal, s_int, &r11);
-    __syncthreads();
-    // 4. T = R11^{-1} R12 in place
-    const int nr = n - k;
-    for (int q = tid; q < nr; q += WG) {
-      double* col = Y + size_t(k + q) * R;
-      for (int i = k - 1; i >= 0; --i) {
-        double sv = col[i];
-        for (int t = i + 1; t < k; ++t) sv -= Y[size_t(t) * R + i] * col[t];
-        col[i] = sv / Y[size_t(i) * R + i];
-      }
-    }
-    __syncthreads();
-    bool accept = true;
-    if (sampled) {
-      double worst = 0.0;
-      for (int pr = 0; pr < prm.probes; ++pr) {
-        double sv = 0.0;
-        for (int q = tid; q < nr; q += WG) {
-          double e = P[pr * n + s_perm[k + q]];
-          for (int t = 0; t < k; ++t) e -= P[pr * n + s_perm[t]] * Y[size_t(k + q) * R + t];
-          sv += e * e;
-        }
-        sv = block_sum(sv, s_scal);
-        worst = fmax(worst, sqrt(sv));
-      }
-      accept = worst <= prm.tau * prm.eps * r11;
-    }
-    if (accept) {
-      for (int t = tid; t < k * nr; t += WG) {
-        const int i = t / nr, q = t % nr;
-        Tm[t] = T(Y[size_t(k + q) * R + i]);
-      }
-      for (int i = tid; i < n; i += WG) perm[i] = s_perm[i];
-      break;
-    }
-    h *= 2;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    dyn.k[c] = k;
-    dyn.nr[c] = n - k;
-    dyn.h[c] = h < nF ? h : nF;
-    dyn.passes[c] = passes;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Transform U_t A L_t of the diagonal block and two-stage LU (eqs. (2.7),
 // (4.10)); the DOF list is reordered to [remainder; skeleton].

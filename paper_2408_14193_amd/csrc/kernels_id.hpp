@@ -1,0 +1,810 @@
+// Column-parallel interpolative decomposition of the segments of one level
+// (Sections 4.1-4.2, stacked form of eq. (4.12)).
+//
+// One workgroup of NW wave64 handles one segment.  Lane j owns column j of
+// the stacked coupling matrix [A_{n,c}; A_{c,n}^T] (NCOL columns per lane,
+// so n <= 64 * NCOL), and the waves share its rows (row i belongs to wave
+// i mod NW).  Column norms, Householder dot products and updates are then
+// per-lane loops over rows with no cross-lane reduction; the pivot search is
+// one wave reduction.  Pivoting never moves data: lane j keeps original
+// column j, and a position -> column table records the order.
+//
+// Three tiers cover the segment sizes of a level:
+//   A  NW = 1,  Y and row table in LDS (fine levels: thousands of segments)
+//   B  NW = 4,  Y and row table in LDS (middle levels)
+//   C  NW = 16, Y and row table in the segment's global scratch (top levels,
+//      a few segments whose coupling rows exceed the LDS)
+// Segments wider than 128 columns take the block-cooperative kernel
+// k_seg_id.  Every tier computes the same tier function, so each segment is
+// handled by exactly one launch; tier A also writes the identity result of
+// segments without an ID.
+#pragma once
+
+#include "device_common.hpp"
+#include "kernels_factor.hpp"
+#include "layout.hpp"
+
+namespace spalu {
+
+constexpr int ID_MAXPROBES = 8;
+
+// One row of the stacked coupling matrix.
+struct IdRow {
+  int64_t base;    // value-arena offset of the entry in column 0
+  int32_t stride;  // value-arena step between columns
+  int32_t vh;      // 2 * vertex + half (half 1: a row of A_{c,d}^T)
+};
+
+// Sampling tiles: IDC_IC sample rows x idc_ft(NCOL) far rows per step.
+constexpr int IDC_IC = 8;
+__host__ __device__ constexpr int idc_ft(int ncol) { return ncol == 1 ? 16 : 8; }
+
+// LDS bytes of one workgroup of a tier (rows_in_lds: Y and the row table).
+__host__ __device__ inline size_t idc_lds_bytes(int nw, int ncol, int n, int R, bool rows_in_lds) {
+  size_t b = 0;
+  if (rows_in_lds) b += size_t(R) * n * 8 + size_t(R) * (sizeof(IdRow) + 4);
+  b += size_t(ID_MAXPROBES) * n * 8;              // probe rows
+  b += size_t(nw) * IDC_IC * idc_ft(ncol) * 8;    // Gaussian tiles
+  b += size_t(2) * nw * 64 * ncol * 8;            // norm and dot partials
+  b += size_t(n) * 4 + 16;                        // position -> column
+  return (b + 15) & ~size_t(15);
+}
+
+// Doubles of global scratch a tier-C segment uses (Y, then the row table
+// and the row order).
+__host__ __device__ inline size_t idc_scratch_doubles(int n, int R) {
+  return size_t(R) * n + (size_t(R) * (sizeof(IdRow) + 4) + 7) / 8;
+}
+
+struct IdTiers {
+  int budget_a;  // LDS bytes of the tier-A launch
+  int budget_b;  // LDS bytes of the tier-B launch
+};
+
+// 0: no ID (identity), 1/2/3: tiers A/B/C, 4: block-cooperative kernel.
+__device__ inline int id_tier(const DSeg& S, int n, int R, double eps, IdTiers t) {
+  const bool do_id = (S.flags & SEG_REGULAR) && (S.flags & SEG_HAS_NBR) && eps > 0.0 && n > 0;
+  if (!do_id || R == 0) return 0;
+  if (n <= 64 && idc_lds_bytes(1, 1, n, R, true) <= size_t(t.budget_a)) return 1;
+  if (n <= 128 && idc_lds_bytes(4, 2, n, R, true) <= size_t(t.budget_b)) return 2;
+  if (n <= 128) return 3;
+  return 4;
+}
+
+template <int NW>
+__device__ inline void grp_sync() {
+  if constexpr (NW == 1)
+    wave_sync();
+  else
+    __syncthreads();
+}
+
+// Y[(y0 + p) * n + j] = A(row order[p]) for p in [0, cnt) (rows of the
+// waves' share), with the row list read forwards (near) or backwards (far).
+template <typename T, int NW, int NCOL>
+__device__ inline void idc_gather(const T* __restrict__ varena, const IdRow* rows, const int* order, int R,
+                                  bool backwards, int cnt, double* Y, int y0, int n) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int p = w; p < cnt; p += NW) {
+    const IdRow m = rows[backwards ? order[R - 1 - p] : order[p]];
+#pragma unroll
+    for (int s = 0; s < NCOL; ++s) {
+      const int j = lane + 64 * s;
+      if (j < n) Y[size_t(y0 + p) * n + j] = double(varena[m.base + int64_t(j) * m.stride]);
+    }
+  }
+}
+
+template <typename T, int NW, int NCOL, bool YG>
+__global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int nseg, const DNbr* nbrs,
+                                                         const DBlk* blks, GridGeom g, int32_t* iarena,
+                                                         T* __restrict__ varena, double* __restrict__ scratch,
+                                                         DLevelDyn dyn, IdParams prm, IdTiers tiers) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int s_cnt[2];
+  __shared__ int s_acc;
+  constexpr int NT = 64 * NW;
+  constexpr int TIER = YG ? 3 : (NW == 1 ? 1 : 2);
+  constexpr int IC = IDC_IC;
+  constexpr int IDC_FT = idc_ft(NCOL);
+  const int c = blockIdx.x;
+  if (c >= nseg) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const DSeg S = segs[c];
+  const int n = dyn.n[c];
+  int R = 0;
+  for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += 2 * dyn.n[nbrs[e].d];
+  const int tier = id_tier(S, n, R, prm.eps, tiers);
+  int32_t* dofs = iarena + S.ioff;
+  int32_t* perm_out = dofs + S.cap;
+  if (TIER == 1 && tier == 0) {
+    for (int i = tid; i < n; i += NT) perm_out[i] = i;
+    if (tid == 0) {
+      dyn.k[c] = n;
+      dyn.nr[c] = 0;
+      dyn.h[c] = 0;
+      dyn.passes[c] = 0;
+    }
+    return;
+  }
+  if (tier != TIER) return;
+
+  // ---- memory carve-up ----
+  char* sp = smem;
+  double* Y;
+  IdRow* rows;
+  int* order;
+  if constexpr (YG) {
+    Y = scratch + S.scr_off;
+    rows = reinterpret_cast<IdRow*>(Y + size_t(R) * n);
+    order = reinterpret_cast<int*>(rows + R);
+  } else {
+    Y = reinterpret_cast<double*>(sp);
+    sp += size_t(R) * n * 8;
+    rows = reinterpret_cast<IdRow*>(sp);
+    sp += size_t(R) * sizeof(IdRow);
+  }
+  double* P = reinterpret_cast<double*>(sp);  // probe rows, row-major (probes x n)
+  sp += size_t(ID_MAXPROBES) * n * 8;
+  double* Gt = reinterpret_cast<double*>(sp) + size_t(w) * IC * IDC_FT;  // this wave's Gaussian tile
+  sp += size_t(NW) * IC * IDC_FT * 8;
+  double* pn = reinterpret_cast<double*>(sp);  // norm partials [NW][NCOL][64]
+  sp += size_t(NW) * 64 * NCOL * 8;
+  double* pd = reinterpret_cast<double*>(sp);  // dot partials [NW][NCOL][64]
+  sp += size_t(NW) * 64 * NCOL * 8;
+  if constexpr (!YG) {
+    order = reinterpret_cast<int*>(sp);
+    sp += size_t(R) * 4;
+  }
+  int* pos2col = reinterpret_cast<int*>(sp);
+
+  // ---- 1. row table: near rows listed from the front, far rows from the back ----
+  if (w == 0) {
+    int nN = 0, nF = 0, r0 = 0;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+      const DNbr nb = nbrs[e];
+      const int nd = dyn.n[nb.d];
+      const int32_t* dd = iarena + segs[nb.d].ioff;
+      const int64_t off0 = blks[nb.blk_dc].off, off1 = blks[nb.blk_cd].off;
+      for (int half = 0; half < 2; ++half) {
+        for (int i0 = 0; i0 < nd; i0 += 64) {
+          const int i = i0 + lane;
+          const bool valid = i < nd;
+          int v = 0;
+          bool near = false;
+          if (valid) {
+            v = dd[i];
+            int cv[3];
+            vcoords(g, v, cv);
+            int dist = 0;
+            for (int a = 0; a < 3; ++a) {
+              int da = S.lo[a] - cv[a];
+              if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
+              if (da > dist) dist = da;
+            }
+            near = dist <= S.thr;
+          }
+          const uint64_t mn = __ballot(valid && near), mf = __ballot(valid && !near);
+          if (valid) {
+            const int r = r0 + half * nd + i;
+            IdRow m;
+            m.base = half == 0 ? off0 + int64_t(i) * n : off1 + i;
+            m.stride = half == 0 ? 1 : nd;
+            m.vh = 2 * v + half;
+            rows[r] = m;
+            if (near)
+              order[nN + __popcll(mn & below)] = r;
+            else
+              order[R - 1 - (nF + __popcll(mf & below))] = r;
+          }
+          nN += __popcll(mn);
+          nF += __popcll(mf);
+        }
+      }
+      r0 += 2 * nd;
+    }
+    if (lane == 0) {
+      s_cnt[0] = nN;
+      s_cnt[1] = nF;
+    }
+  }
+  __syncthreads();
+  const int nN = s_cnt[0], nF = s_cnt[1];
+
+  int h = prm.h0;
+  if (prm.h_init) {
+    const int hi = prm.h_init[prm.seg_base + c];
+    if (hi > 0) h = hi;
+  }
+  const int probes = prm.probes;
+  int passes = 0, k = 0;
+  double r11 = 0.0;
+  while (true) {
+    ++passes;
+    const bool sampled = h < nF;
+    const int m = nN + (sampled ? h : nF);
+    // ---- 2. Y = [B_N; G B_F / sqrt(h)] or the exact far rows ----
+    idc_gather<T, NW, NCOL>(varena, rows, order, R, false, nN, Y, 0, n);
+    if (!sampled) {
+      idc_gather<T, NW, NCOL>(varena, rows, order, R, true, nF, Y, nN, n);
+    } else {
+      const double sc = 1.0 / sqrt(double(h));
+      for (int stream = 0; stream < 2; ++stream) {
+        const int nrows = stream == 0 ? h : probes;
+        for (int i0 = 0; i0 < nrows; i0 += IC) {
+          const int ih = nrows - i0 < IC ? nrows - i0 : IC;
+          double acc[IC][NCOL];
+#pragma unroll
+          for (int a = 0; a < IC; ++a)
+#pragma unroll
+            for (int s = 0; s < NCOL; ++s) acc[a][s] = 0.0;
+          for (int f0 = w * IDC_FT; f0 < nF; f0 += NW * IDC_FT) {
+            const int fw = nF - f0 < IDC_FT ? nF - f0 : IDC_FT;
+            double b[IDC_FT][NCOL];
+#pragma unroll
+            for (int ff = 0; ff < IDC_FT; ++ff) {
+              IdRow mr;
+              mr.base = 0;
+              mr.stride = 0;
+              if (ff < fw) mr = rows[order[R - 1 - (f0 + ff)]];
+#pragma unroll
+              for (int s = 0; s < NCOL; ++s) {
+                const int j = lane + 64 * s;
+                b[ff][s] = (ff < fw && j < n) ? double(varena[mr.base + int64_t(j) * mr.stride]) : 0.0;
+              }
+            }
+            // Gaussian tile: IC rows x IDC_FT far rows, one Philox draw per row pair
+            for (int t = lane; t < (IC / 2) * IDC_FT; t += 64) {
+              const int pr = t / IDC_FT, ff = t % IDC_FT;
+              double ev = 0.0, od = 0.0;
+              if (ff < fw && 2 * pr < ih) {
+                const int vh = rows[order[R - 1 - (f0 + ff)]].vh;
+                gauss_pair(prm.seed, prm.level, stream, (i0 >> 1) + pr, vh >> 1, c, vh & 1, &ev, &od);
+              }
+              Gt[(2 * pr) * IDC_FT + ff] = ev;
+              Gt[(2 * pr + 1) * IDC_FT + ff] = 2 * pr + 1 < ih ? od : 0.0;
+            }
+            wave_sync();
+#pragma unroll
+            for (int ff = 0; ff < IDC_FT; ++ff)
+#pragma unroll
+              for (int a = 0; a < IC; ++a) {
+                const double gv = Gt[a * IDC_FT + ff];
+#pragma unroll
+                for (int s = 0; s < NCOL; ++s) acc[a][s] += gv * b[ff][s];
+              }
+            wave_sync();
+          }
+          // combine the waves' partial sums in wave order
+          for (int ww = 0; ww < NW; ++ww) {
+            if (w == ww) {
+#pragma unroll
+              for (int a = 0; a < IC; ++a) {
+                if (a < ih) {
+                  const int row = i0 + a;
+#pragma unroll
+                  for (int s = 0; s < NCOL; ++s) {
+                    const int j = lane + 64 * s;
+                    if (j < n) {
+                      double* dst = stream == 0 ? &Y[size_t(nN + row) * n + j] : &P[size_t(row) * n + j];
+                      const double prev = ww == 0 ? 0.0 : *dst;
+                      const double v = prev + acc[a][s];
+                      *dst = (ww == NW - 1 && stream == 0) ? v * sc : v;
+                    }
+                  }
+                }
+              }
+            }
+            if (NW > 1) __syncthreads();
+          }
+        }
+      }
+    }
+    for (int i = tid; i < n; i += NT) pos2col[i] = i;
+    __syncthreads();
+
+    // ---- 3. CPQR (fresh norms, tie rule: smallest original column) ----
+    uint64_t done[NCOL];
+#pragma unroll
+    for (int s = 0; s < NCOL; ++s) done[s] = 0ull;
+#pragma unroll
+    for (int s = 0; s < NCOL; ++s) {
+      const int j = lane + 64 * s;
+      double a0 = 0.0, a1 = 0.0;
+      if (j < n) {
+        int i = w;
+        for (; i + NW < m; i += 2 * NW) {
+          const double y0 = Y[size_t(i) * n + j], y1 = Y[size_t(i + NW) * n + j];
+          a0 += y0 * y0;
+          a1 += y1 * y1;
+        }
+        if (i < m) {
+          const double y0 = Y[size_t(i) * n + j];
+          a0 += y0 * y0;
+        }
+      }
+      pn[(w * NCOL + s) * 64 + lane] = a0 + a1;
+    }
+    __syncthreads();
+    const int kmax = m < n ? m : n;
+    k = kmax;
+    for (int j = 0; j < kmax; ++j) {
+      double nv[NCOL];
+      bool act[NCOL];
+      double mxl = 0.0;
+#pragma unroll
+      for (int s = 0; s < NCOL; ++s) {
+        const int col = lane + 64 * s;
+        act[s] = col < n && !((done[s] >> lane) & 1ull);
+        double t = 0.0;
+        for (int ww = 0; ww < NW; ++ww) t += pn[(ww * NCOL + s) * 64 + lane];
+        nv[s] = sqrt(t);
+        if (act[s]) mxl = fmax(mxl, nv[s]);
+      }
+      const double mx = wave_max(mxl);
+      int q = -1;
+#pragma unroll
+      for (int s = 0; s < NCOL; ++s) {
+        const uint64_t cm = __ballot(act[s] && nv[s] >= mx * (1.0 - 1e-12));
+        if (q < 0 && cm) q = 64 * s + __ffsll((unsigned long long)cm) - 1;
+      }
+      if (j == 0) r11 = mx;
+      if (mx == 0.0 || mx <= prm.eps * r11 || q < 0) {
+        k = j;
+        break;
+      }
+      const int qs = q >> 6, ql = q & 63;
+      double nq = nv[0];
+#pragma unroll
+      for (int s = 1; s < NCOL; ++s)
+        if (qs == s) nq = nv[s];
+      const double alpha = __shfl(nq, ql, 64);
+      const double x0 = Y[size_t(j) * n + q];
+      const double sg = x0 >= 0.0 ? 1.0 : -1.0;
+      const double v0 = x0 + sg * alpha;
+      const double vv = 2.0 * alpha * (alpha + fabs(x0));
+      const int jown = j % NW;
+      const int i1 = j + 1 + ((w - (j + 1) % NW) + NW) % NW;  // this wave's first row below j
+      // dot products of the reflector with every live column
+#pragma unroll
+      for (int s = 0; s < NCOL; ++s) {
+        const int col = lane + 64 * s;
+        double d0 = 0.0, d1 = 0.0;
+        if (act[s] && col != q) {
+          if (w == jown) d0 = v0 * Y[size_t(j) * n + col];
+          int i = i1;
+          for (; i + NW < m; i += 2 * NW) {
+            d0 += Y[size_t(i) * n + q] * Y[size_t(i) * n + col];
+            d1 += Y[size_t(i + NW) * n + q] * Y[size_t(i + NW) * n + col];
+          }
+          if (i < m) d0 += Y[size_t(i) * n + q] * Y[size_t(i) * n + col];
+        }
+        pd[(w * NCOL + s) * 64 + lane] = d0 + d1;
+      }
+      __syncthreads();
+      // apply the reflector; accumulate the fresh norms of rows > j
+#pragma unroll
+      for (int s = 0; s < NCOL; ++s) {
+        const int col = lane + 64 * s;
+        double a0 = 0.0, a1 = 0.0;
+        if (act[s] && col != q) {
+          double t = 0.0;
+          for (int ww = 0; ww < NW; ++ww) t += pd[(ww * NCOL + s) * 64 + lane];
+          const double f = 2.0 * t / vv;
+          if (w == jown) Y[size_t(j) * n + col] -= f * v0;
+          int i = i1;
+          for (; i + NW < m; i += 2 * NW) {
+            const double y0 = Y[size_t(i) * n + col] - f * Y[size_t(i) * n + q];
+            const double y1 = Y[size_t(i + NW) * n + col] - f * Y[size_t(i + NW) * n + q];
+            Y[size_t(i) * n + col] = y0;
+            Y[size_t(i + NW) * n + col] = y1;
+            a0 += y0 * y0;
+            a1 += y1 * y1;
+          }
+          if (i < m) {
+            const double y0 = Y[size_t(i) * n + col] - f * Y[size_t(i) * n + q];
+            Y[size_t(i) * n + col] = y0;
+            a0 += y0 * y0;
+          }
+        }
+        pn[(w * NCOL + s) * 64 + lane] = a0 + a1;
+      }
+      if (w == jown && lane == ql) Y[size_t(j) * n + q] = -sg * alpha;
+      done[qs] |= 1ull << ql;
+      if (tid == 0) {
+        // position j takes column q; the column there moves to q's old position
+        int qp = j;
+        while (pos2col[qp] != q) ++qp;
+        pos2col[qp] = pos2col[j];
+        pos2col[j] = q;
+      }
+      __syncthreads();
+    }
+
+    // ---- 4. T = R11^{-1} R12, in place in rows < k of the remaining columns ----
+    const int nr = n - k;
+    for (int i = k - 1; i >= 0; --i) {
+      const int ci = pos2col[i];
+      const double rii = Y[size_t(i) * n + ci];
+      double tq[NCOL];
+#pragma unroll
+      for (int s = 0; s < NCOL; ++s) {
+        const int qq = lane + 64 * s;
+        tq[s] = qq < nr ? Y[size_t(i) * n + pos2col[k + qq]] / rii : 0.0;
+      }
+      grp_sync<NW>();
+#pragma unroll
+      for (int s = 0; s < NCOL; ++s) {
+        const int qq = lane + 64 * s;
+        if (qq < nr) {
+          const int cq = pos2col[k + qq];
+          if (w == i % NW) Y[size_t(i) * n + cq] = tq[s];
+          for (int t = w; t < i; t += NW) Y[size_t(t) * n + cq] -= Y[size_t(t) * n + ci] * tq[s];
+        }
+      }
+      grp_sync<NW>();
+    }
+    __syncthreads();
+
+    // ---- 5. a-posteriori check with the probe rows: E = P_r - P_s T ----
+    bool accept = true;
+    if (sampled) {
+      if (w == 0) {
+        double worst = 0.0;
+        for (int pr = 0; pr < probes; ++pr) {
+          double sv = 0.0;
+#pragma unroll
+          for (int s = 0; s < NCOL; ++s) {
+            const int qq = lane + 64 * s;
+            if (qq < nr) {
+              const int cq = pos2col[k + qq];
+              double e = P[size_t(pr) * n + cq];
+              for (int t = 0; t < k; ++t) e -= P[size_t(pr) * n + pos2col[t]] * Y[size_t(t) * n + cq];
+              sv += e * e;
+            }
+          }
+          worst = fmax(worst, sqrt(wave_sum(sv)));
+        }
+        if (lane == 0) s_acc = worst <= prm.tau * prm.eps * r11 ? 1 : 0;
+      }
+      __syncthreads();
+      accept = s_acc != 0;
+    }
+    if (accept) {
+      T* Tm = varena + S.t_off;
+      for (int t = tid; t < k * nr; t += NT) {
+        const int i = t / nr, qq = t % nr;
+        Tm[t] = T(Y[size_t(i) * n + pos2col[k + qq]]);
+      }
+      for (int i = tid; i < n; i += NT) perm_out[i] = pos2col[i];
+      break;
+    }
+    h *= 2;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    dyn.k[c] = k;
+    dyn.nr[c] = n - k;
+    dyn.h[c] = h < nF ? h : nF;
+    dyn.passes[c] = passes;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block-cooperative ID for segments wider than 128 columns: the stacked rows
+// are staged in the segment's global scratch, the CPQR runs on 256 threads.
+// ---------------------------------------------------------------------------
+
+// CPQR of Y (m x n, column-major, ld) with fresh column norms each step and
+// the tie rule of the oracle; returns k and writes |R_11| to *r11.  perm[]
+// (original column index per position) is permuted alongside.
+__device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps, double* nrm,
+                          double* s_scal, int* s_int, double* r11_out) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int kk = m < n ? m : n;
+  int k = kk;
+  double r11 = 0.0;
+  for (int j = 0; j < kk; ++j) {
+    for (int col = j + wv; col < n; col += NWAVE) {
+      double s = 0.0;
+      for (int i = j + lane; i < m; i += 64) {
+        const double y = Y[size_t(col) * ld + i];
+        s += y * y;
+      }
+      s = wave_sum(s);
+      if (lane == 0) nrm[col] = sqrt(s);
+    }
+    __syncthreads();
+    if (wv == 0) {
+      double mx = 0.0;
+      for (int col = j + lane; col < n; col += 64) mx = fmax(mx, nrm[col]);
+      mx = wave_max(mx);
+      int key = 1 << 30, q = 1 << 30;
+      for (int col = j + lane; col < n; col += 64)
+        if (nrm[col] >= mx * (1.0 - 1e-12)) {
+          const int pk = perm[col];
+          if (pk < key) {
+            key = pk;
+            q = col;
+          }
+        }
+      wave_argmin_int(key, q);
+      if (lane == 0) {
+        s_scal[0] = mx;
+        s_int[0] = q;
+      }
+    }
+    __syncthreads();
+    const double mx = s_scal[0];
+    const int q = s_int[0];
+    if (j == 0) r11 = mx;
+    if (mx == 0.0 || mx <= eps * r11) {
+      k = j;
+      break;
+    }
+    if (q != j) {
+      for (int i = tid; i < m; i += WG) {
+        const double t = Y[size_t(j) * ld + i];
+        Y[size_t(j) * ld + i] = Y[size_t(q) * ld + i];
+        Y[size_t(q) * ld + i] = t;
+      }
+      if (tid == 0) {
+        const int t = perm[j];
+        perm[j] = perm[q];
+        perm[q] = t;
+      }
+    }
+    __syncthreads();
+    const double alpha = nrm[q];
+    const double x0 = Y[size_t(j) * ld + j];
+    const double sg = x0 >= 0.0 ? 1.0 : -1.0;
+    const double v0 = x0 + sg * alpha;
+    if (wv == 0) {
+      double s = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) {
+        const double y = Y[size_t(j) * ld + i];
+        s += y * y;
+      }
+      s = wave_sum(s);
+      if (lane == 0) s_scal[1] = s + v0 * v0;
+    }
+    __syncthreads();
+    const double vv = s_scal[1];
+    for (int col = j + 1 + wv; col < n; col += NWAVE) {
+      double w = 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) w += Y[size_t(j) * ld + i] * Y[size_t(col) * ld + i];
+      w = wave_sum(w) + v0 * Y[size_t(col) * ld + j];
+      const double f = 2.0 * w / vv;
+      if (lane == 0) Y[size_t(col) * ld + j] -= f * v0;
+      for (int i = j + 1 + lane; i < m; i += 64) Y[size_t(col) * ld + i] -= f * Y[size_t(j) * ld + i];
+    }
+    __syncthreads();
+    if (tid == 0) Y[size_t(j) * ld + j] = -sg * alpha;
+    __syncthreads();
+  }
+  *r11_out = r11;
+  return k;
+}
+
+
+template <typename T>
+__global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const DNbr* nbrs,
+                                               const DBlk* blks, GridGeom g, int32_t* iarena,
+                                               T* varena, double* scratch, DLevelDyn dyn,
+                                               IdParams prm, IdTiers tiers) {
+  extern __shared__ double lds[];
+  __shared__ double s_nrm[512];
+  __shared__ double s_scal[4];
+  __shared__ int s_int[4];
+  __shared__ int s_w[NWAVE];
+  __shared__ int s_cnt[2];
+  const int c = blockIdx.x;
+  if (c >= nseg) return;
+  const int tid = threadIdx.x;
+  const DSeg S = segs[c];
+  const int n = dyn.n[c];
+  int R = 0;
+  for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += 2 * dyn.n[nbrs[e].d];
+  if (id_tier(S, n, R, prm.eps, tiers) != 4) return;
+  int32_t* dofs = iarena + S.ioff;
+  int32_t* perm = dofs + S.cap;
+  int32_t* tag = perm + 2 * S.cap;  // after piv
+  for (int i = tid; i < n; i += WG) perm[i] = i;
+  const size_t rc = size_t(S.rcap);
+  double* BN = scratch + S.scr_off;  // near rows, column-major (ld rcap)
+  double* BF = BN + rc * S.cap;      // far rows, row-major (ld n)
+  double* Yg = BF + rc * S.cap;      // work matrix, column-major (ld rcap)
+  double* P = Yg + rc * S.cap;       // probe rows, row-major (8 x n)
+  if (tid == 0) {
+    s_cnt[0] = 0;
+    s_cnt[1] = 0;
+  }
+  __syncthreads();
+  // 1. stack [A_{n,c}; A_{c,n}^T] row by row, split near / far
+  for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+    const DNbr nb = nbrs[e];
+    const int nd = dyn.n[nb.d];
+    const int32_t* dd = iarena + segs[nb.d].ioff;
+    for (int half = 0; half < 2; ++half) {
+      const T* blk = varena + blks[half == 0 ? nb.blk_dc : nb.blk_cd].off;
+      for (int base = 0; base < nd; base += WG) {
+        const int i = base + tid;
+        const bool valid = i < nd;
+        int v = 0;
+        bool near = false;
+        if (valid) {
+          v = dd[i];
+          int cv[3];
+          vcoords(g, v, cv);
+          int dist = 0;
+          for (int a = 0; a < 3; ++a) {
+            int da = S.lo[a] - cv[a];
+            if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
+            if (da > dist) dist = da;
+          }
+          near = dist <= S.thr;
+        }
+        int tn, tf;
+        const int pn = block_scan_flag(valid && near, s_w, &tn);
+        const int pf = block_scan_flag(valid && !near, s_w, &tf);
+        const int bn = s_cnt[0], bf = s_cnt[1];
+        if (valid) {
+          if (near) {
+            const int r = bn + pn;
+            for (int j = 0; j < n; ++j)
+              BN[size_t(j) * rc + r] = double(half == 0 ? blk[size_t(i) * n + j] : blk[size_t(j) * nd + i]);
+          } else {
+            const int r = bf + pf;
+            for (int j = 0; j < n; ++j)
+              BF[size_t(r) * n + j] = double(half == 0 ? blk[size_t(i) * n + j] : blk[size_t(j) * nd + i]);
+            tag[2 * r] = v;
+            tag[2 * r + 1] = half;
+          }
+        }
+        __syncthreads();
+        if (tid == 0) {
+          s_cnt[0] = bn + tn;
+          s_cnt[1] = bf + tf;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  const int nN = s_cnt[0], nF = s_cnt[1];
+  if (nN + nF == 0) {  // no coupling rows left: nothing to compress against
+    if (tid == 0) {
+      dyn.k[c] = n;
+      dyn.nr[c] = 0;
+      dyn.h[c] = 0;
+      dyn.passes[c] = 0;
+    }
+    return;
+  }
+  int h = prm.h0;
+  if (prm.h_init) {
+    const int hi = prm.h_init[prm.seg_base + c];
+    if (hi > 0) h = hi;
+  }
+  int passes = 0, k = 0;
+  double r11 = 0.0;
+  T* Tm = varena + S.t_off;
+  while (true) {
+    ++passes;
+    const bool sampled = h < nF;
+    const int m = nN + (sampled ? h : nF);
+    // 2. Y = [B_N; G B_F / sqrt(h)] (or the exact far rows)
+    for (int t = tid; t < nN * n; t += WG) {
+      const int j = t / nN, i = t % nN;
+      Yg[size_t(j) * rc + i] = BN[size_t(j) * rc + i];
+    }
+    if (!sampled) {
+      for (int t = tid; t < nF * n; t += WG) {
+        const int f = t / n, j = t % n;
+        Yg[size_t(j) * rc + nN + f] = BF[size_t(f) * n + j];
+      }
+    } else {
+      const double sc = 1.0 / sqrt(double(h));
+      for (int t = tid; t < h * n; t += WG) {
+        const int i = t % h, j = t / h;
+        Yg[size_t(j) * rc + nN + i] = 0.0;
+      }
+      for (int t = tid; t < prm.probes * n; t += WG) P[t] = 0.0;
+      const int hp = h + prm.probes;  // sample rows, then probe rows
+      for (int i0 = 0; i0 < hp; i0 += 32) {
+        const int ih = hp - i0 < 32 ? hp - i0 : 32;
+        for (int f0 = 0; f0 < nF; f0 += 64) {
+          const int fw = nF - f0 < 64 ? nF - f0 : 64;
+          __syncthreads();
+          for (int t = tid; t < ih * fw; t += WG) {
+            const int ii = t / fw, f = t % fw;
+            const int row = i0 + ii;
+            const int stream = row < h ? 0 : 1;
+            const int r = row < h ? row : row - h;
+            lds[ii * 64 + f] = gauss_entry(prm.seed, prm.level, stream, r, tag[2 * (f0 + f)], c,
+                                           tag[2 * (f0 + f) + 1]);
+          }
+          __syncthreads();
+          for (int t = tid; t < ih * n; t += WG) {
+            const int ii = t / n, j = t % n;
+            double acc = 0.0;
+            for (int f = 0; f < fw; ++f) acc += lds[ii * 64 + f] * BF[size_t(f0 + f) * n + j];
+            const int row = i0 + ii;
+            if (row < h)
+              Yg[size_t(j) * rc + nN + row] += acc;
+            else
+              P[(row - h) * n + j] += acc;
+          }
+        }
+      }
+      __syncthreads();
+      for (int t = tid; t < h * n; t += WG) {
+        const int i = t % h, j = t / h;
+        Yg[size_t(j) * rc + nN + i] *= sc;
+      }
+    }
+    for (int i = tid; i < n; i += WG) perm[i] = i;
+    __syncthreads();
+    // 3. CPQR (staged in LDS when it fits)
+    const bool inlds = size_t(m) * n <= LDS_DOUBLES;
+    double* Y = inlds ? lds : Yg;
+    const int ld = inlds ? m : int(rc);
+    if (inlds) {
+      for (int t = tid; t < m * n; t += WG) {
+        const int j = t / m, i = t % m;
+        lds[t] = Yg[size_t(j) * rc + i];
+      }
+    }
+    double* nrm = n <= 512 ? s_nrm : P + 8 * n;
+    __syncthreads();
+    k = block_cpqr(Y, ld, m, n, perm, prm.eps, nrm, s_scal, s_int, &r11);
+    __syncthreads();
+    // 4. T = R11^{-1} R12 (back substitution in FP64, in place in Y)
+    const int nr = n - k;
+    for (int q = tid; q < nr; q += WG) {
+      double* col = Y + size_t(k + q) * ld;
+      for (int i = k - 1; i >= 0; --i) {
+        double s = col[i];
+        for (int t = i + 1; t < k; ++t) s -= Y[size_t(t) * ld + i] * col[t];
+        col[i] = s / Y[size_t(i) * ld + i];
+      }
+    }
+    __syncthreads();
+    bool accept = true;
+    if (sampled) {
+      // 5. a-posteriori check with the probe rows: E = P_r - P_s T
+      double worst = 0.0;
+      for (int pr = 0; pr < prm.probes; ++pr) {
+        double s = 0.0;
+        for (int q = tid; q < nr; q += WG) {
+          double e = P[pr * n + perm[k + q]];
+          for (int t = 0; t < k; ++t) e -= P[pr * n + perm[t]] * Y[size_t(k + q) * ld + t];
+          s += e * e;
+        }
+        s = block_sum(s, s_scal);
+        worst = fmax(worst, sqrt(s));
+      }
+      accept = worst <= prm.tau * prm.eps * r11;
+    }
+    if (accept) {
+      for (int t = tid; t < k * nr; t += WG) {
+        const int i = t / nr, q = t % nr;
+        Tm[t] = T(Y[size_t(k + q) * ld + i]);
+      }
+      break;
+    }
+    h *= 2;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    dyn.k[c] = k;
+    dyn.nr[c] = n - k;
+    dyn.h[c] = h < nF ? h : nF;
+    dyn.passes[c] = passes;
+  }
+}
+
+
+
+}  // namespace spalu

@@ -15,6 +15,7 @@
 
 #include "../../include/spalu.h"
 #include "kernels_factor.hpp"
+#include "kernels_id.hpp"
 #include "kernels_mlp.hpp"
 #include "kernels_solve.hpp"
 #include "layout.hpp"
@@ -51,6 +52,9 @@ struct LevelTabs {
   std::vector<DSepTerm> terms;
   size_t o_segs = 0, o_nbrs = 0, o_blks = 0, o_scale = 0, o_cons_ptr = 0, o_cons = 0, o_task_ptr = 0,
          o_tasks = 0, o_terms = 0, o_dyn = 0;
+  // ID launches of the level (bounds from the uncompressed sizes)
+  IdTiers tiers{0, 0};
+  bool id_b = false, id_c = false, id_old = false;
 };
 
 struct Layout {
@@ -121,6 +125,43 @@ struct spalu_factor_s {
 };
 
 namespace {
+
+// LDS limits of the column-parallel ID tiers (bytes of dynamic LDS).
+constexpr size_t ID_A_MAX_BYTES = 24 * 1024;  // 64-thread groups: six or more per CU
+constexpr size_t ID_B_MAX_BYTES = 60 * 1024;  // 256-thread groups: two per CU
+
+// Which ID launches a level needs and their LDS budgets.  The sizes known
+// here (uncompressed n, coupling-row bound rcap) bound the ones the kernels
+// see, so a segment whose bound fits a tier certainly lands in it; the
+// kernels themselves decide with the actual sizes.
+void plan_id_tiers(LevelTabs& T) {
+  size_t a = 0, b = 0;
+  bool beyond_a = false, beyond_b = false, wide = false;
+  for (const DSeg& D : T.segs) {
+    if (!((D.flags & SEG_REGULAR) && (D.flags & SEG_HAS_NBR))) continue;
+    const int cap = D.cap, R = D.rcap;
+    const size_t na = idc_lds_bytes(1, 1, std::min(cap, 64), R, true);
+    if (cap <= 64 && na <= ID_A_MAX_BYTES) {
+      a = std::max(a, na);
+      continue;
+    }
+    beyond_a = true;
+    const size_t nb = idc_lds_bytes(4, 2, std::min(cap, 128), R, true);
+    if (cap <= 128 && nb <= ID_B_MAX_BYTES) {
+      b = std::max(b, nb);
+      continue;
+    }
+    b = ID_B_MAX_BYTES;
+    beyond_b = true;
+    if (cap > 128) wide = true;
+  }
+  if (beyond_a) a = ID_A_MAX_BYTES;
+  T.tiers.budget_a = int(std::max(a, idc_lds_bytes(1, 1, 1, 1, true)));
+  T.tiers.budget_b = int(std::max(b, idc_lds_bytes(4, 2, 1, 1, true)));
+  T.id_b = beyond_a;
+  T.id_c = beyond_b;
+  T.id_old = wide;
+}
 
 // ---------------------------------------------------------------------------
 // Static layout of the factorization for one ND and precision.
@@ -206,11 +247,12 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
       var += size_t(cap * cap / 4 + 1);
       size_t need = size_t(2 * cap * cap);
       if ((D.flags & SEG_REGULAR) && (D.flags & SEG_HAS_NBR))
-        need = std::max(need, size_t((3 * rcap[c] + 9) * cap));
+        need = std::max({need, size_t((3 * rcap[c] + 9) * cap), idc_scratch_doubles(int(cap), int(rcap[c]))});
       D.scr_off = int64_t(level_pool);
       level_pool += need;
     }
     pool = std::max(pool, level_pool);
+    plan_id_tiers(T);
   }
 
   // merge tables l -> l-1
@@ -407,7 +449,6 @@ unsigned nblocks(int64_t n, int b = WG) { return unsigned(std::max<int64_t>(1, (
 
 constexpr size_t LDS_BYTES = size_t(LDS_DOUBLES) * 8;
 constexpr size_t LEAF_LDS_BYTES = size_t(LEAF_LDS_DOUBLES) * 8;
-constexpr size_t ID_LDS_BYTES = size_t(ID_LDS_DOUBLES) * 8;
 
 
 // ---------------------------------------------------------------------------
@@ -429,11 +470,13 @@ const char* const kNames[K_COUNT] = {
 
 struct PendingLaunch {
   int kid, level;
+  bool acct;  // carries the level's algorithmic work (false: a further launch of the same step)
   hipEvent_t a, b;
 };
 
 struct TimedLaunch {
   int kid, level, nrhs;
+  bool acct;
   double ms;
   int64_t nrows;
   std::shared_ptr<const Layout> lay;
@@ -459,9 +502,9 @@ struct Profiler {
 Profiler g_prof;
 const bool g_prof_verbose = std::getenv("SPALU_PROFILE_VERBOSE") != nullptr;
 
-int prof_begin(int kid, int level, hipStream_t st) {
+int prof_begin(int kid, int level, hipStream_t st, bool acct = true) {
   if (!g_prof.on) return -1;
-  PendingLaunch p{kid, level, nullptr, nullptr};
+  PendingLaunch p{kid, level, acct, nullptr, nullptr};
   if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return -1;
   (void)hipEventRecord(p.a, st);
   g_prof.pend.push_back(p);
@@ -478,6 +521,15 @@ void prof_end(int idx, hipStream_t st) {
     __VA_ARGS__;                                 \
     HIPCHK(hipGetLastError());                   \
     prof_end(pi_, st);                           \
+  } while (0)
+
+// A further launch of a step whose work the first launch already carries.
+#define LAUNCH_MORE(kid, level, ...)                    \
+  do {                                                  \
+    const int pi_ = prof_begin(kid, level, st, false);  \
+    __VA_ARGS__;                                        \
+    HIPCHK(hipGetLastError());                          \
+    prof_end(pi_, st);                                  \
   } while (0)
 
 // Algorithmic work of one launch (bytes that the step must move, flops it
@@ -639,7 +691,7 @@ void prof_flush(const spalu_factor_t* F, int nrhs) {
     float ms = 0.f;
     (void)hipEventSynchronize(p.b);
     if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) ms = 0.f;
-    g_prof.done.push_back(TimedLaunch{p.kid, p.level, nrhs, double(ms), F->n, F->lay_sp, F->dyn_host});
+    g_prof.done.push_back(TimedLaunch{p.kid, p.level, nrhs, p.acct, double(ms), F->n, F->lay_sp, F->dyn_host});
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
   }
@@ -649,7 +701,8 @@ void prof_flush(const spalu_factor_t* F, int nrhs) {
 void prof_account_pending() {
   for (auto& t : g_prof.done) {
     double by, fl;
-    account(*t.lay, *t.dyn, t.nrows, t.kid, t.level, t.nrhs, by, fl);
+    by = fl = 0.0;
+    if (t.acct) account(*t.lay, *t.dyn, t.nrows, t.kid, t.level, t.nrhs, by, fl);
     if (g_prof_verbose)
       std::fprintf(stderr, "spalu-prof %-16s level %2d  %9.4f ms  %12.0f B  %12.0f flop\n", kNames[t.kid], t.level,
                    t.ms, by, fl);
@@ -753,10 +806,21 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
         prm.h_init = hinit;
       }
     }
-    LAUNCH(K_ID, l, k_seg_id_lds<T><<<unsigned(ns), WG, ID_LDS_BYTES, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), blks,
-                                                                      F->g, iar, var, d, prm));
-    LAUNCH(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), blks, F->g, iar,
-                                                     var, scr, d, prm));
+    {
+      const DNbr* nb = tab<DNbr>(ws, T_.o_nbrs);
+      const IdTiers tz = T_.tiers;
+      LAUNCH(K_ID, l, k_seg_id_cols<T, 1, 1, false><<<unsigned(ns), 64, size_t(tz.budget_a), st>>>(
+          segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
+      if (T_.id_b)
+        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 4, 2, false><<<unsigned(ns), 256, size_t(tz.budget_b), st>>>(
+            segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
+      if (T_.id_c)
+        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 16, 2, true><<<unsigned(ns), 1024, idc_lds_bytes(16, 2, 128, 0, false),
+                                                             st>>>(segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
+      if (T_.id_old)
+        LAUNCH_MORE(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var, scr, d,
+                                                                       prm, tz));
+    }
     LAUNCH(K_LU, l, k_seg_lu<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, blks, iar, var, scr, d, status));
     if (!T_.scale_list.empty()) {
       LAUNCH(K_SCALE, l, k_blk_scale<T><<<unsigned(T_.scale_list.size()), WG, LDS_BYTES, st>>>(
