@@ -11,8 +11,9 @@
 //
 // Three tiers cover the segment sizes of a level:
 //   A  NW = 1,  Y and row table in LDS (fine levels: thousands of segments)
-//   B  NW = 4,  Y and row table in LDS (middle levels)
-//   C  NW = 16, Y and row table in the segment's global scratch (top levels,
+//   B  NW = 4,  Y and row table in LDS (middle levels), two groups per CU
+//   B2 the same kernel with up to 152 KB of LDS, one group per CU
+//   C  NW = 8,  Y and row table in the segment's global scratch (top levels,
 //      a few segments whose coupling rows exceed the LDS)
 // Segments wider than 128 columns take the block-cooperative kernel
 // k_seg_id.  Every tier computes the same tier function, so each segment is
@@ -35,40 +36,44 @@ struct IdRow {
   int32_t vh;      // 2 * vertex + half (half 1: a row of A_{c,d}^T)
 };
 
-// Sampling tiles: IDC_IC sample rows x idc_ft(NCOL) far rows per step.
-constexpr int IDC_IC = 8;
+// Sampling tiles: idc_ic(NCOL) sample rows x idc_ft(NCOL) far rows per step.
+__host__ __device__ constexpr int idc_ic(int ncol) { return ncol == 1 ? 8 : 4; }
 __host__ __device__ constexpr int idc_ft(int ncol) { return ncol == 1 ? 16 : 8; }
 
-// LDS bytes of one workgroup of a tier (rows_in_lds: Y and the row table).
-__host__ __device__ inline size_t idc_lds_bytes(int nw, int ncol, int n, int R, bool rows_in_lds) {
+// LDS bytes of one workgroup of a tier (rows_in_lds: Y, the far rows B_F in
+// the storage type (st bytes) and the row table).
+__host__ __device__ inline size_t idc_lds_bytes(int nw, int ncol, int n, int R, int st, bool rows_in_lds) {
   size_t b = 0;
-  if (rows_in_lds) b += size_t(R) * n * 8 + size_t(R) * (sizeof(IdRow) + 4);
+  if (rows_in_lds) b += size_t(R) * n * (8 + st) + size_t(R) * (sizeof(IdRow) + 4);
   b += size_t(ID_MAXPROBES) * n * 8;              // probe rows
-  b += size_t(nw) * IDC_IC * idc_ft(ncol) * 8;    // Gaussian tiles
+  b += size_t(nw) * idc_ic(ncol) * idc_ft(ncol) * 8;    // Gaussian tiles
   b += size_t(2) * nw * 64 * ncol * 8;            // norm and dot partials
   b += size_t(n) * 4 + 16;                        // position -> column
   return (b + 15) & ~size_t(15);
 }
 
-// Doubles of global scratch a tier-C segment uses (Y, then the row table
+// Doubles of global scratch a tier-C segment uses (Y, B_F, then the row table
 // and the row order).
 __host__ __device__ inline size_t idc_scratch_doubles(int n, int R) {
-  return size_t(R) * n + (size_t(R) * (sizeof(IdRow) + 4) + 7) / 8;
+  return 2 * size_t(R) * n + (size_t(R) * (sizeof(IdRow) + 4) + 7) / 8;
 }
 
 struct IdTiers {
-  int budget_a;  // LDS bytes of the tier-A launch
-  int budget_b;  // LDS bytes of the tier-B launch
+  int budget_a;   // LDS bytes of the tier-A launch
+  int budget_b;   // LDS bytes of the tier-B launch (two groups per CU)
+  int budget_b2;  // LDS bytes of the tier-B2 launch (one group per CU)
+  int st;         // bytes of the storage type
 };
 
-// 0: no ID (identity), 1/2/3: tiers A/B/C, 4: block-cooperative kernel.
+// 0: no ID (identity), 1: tier A, 2: B, 3: B2, 4: C, 5: block-cooperative kernel.
 __device__ inline int id_tier(const DSeg& S, int n, int R, double eps, IdTiers t) {
   const bool do_id = (S.flags & SEG_REGULAR) && (S.flags & SEG_HAS_NBR) && eps > 0.0 && n > 0;
   if (!do_id || R == 0) return 0;
-  if (n <= 64 && idc_lds_bytes(1, 1, n, R, true) <= size_t(t.budget_a)) return 1;
-  if (n <= 128 && idc_lds_bytes(4, 2, n, R, true) <= size_t(t.budget_b)) return 2;
-  if (n <= 128) return 3;
-  return 4;
+  if (n <= 64 && idc_lds_bytes(1, 1, n, R, t.st, true) <= size_t(t.budget_a)) return 1;
+  if (n <= 128 && idc_lds_bytes(4, 2, n, R, t.st, true) <= size_t(t.budget_b)) return 2;
+  if (n <= 128 && idc_lds_bytes(4, 2, n, R, t.st, true) <= size_t(t.budget_b2)) return 3;
+  if (n <= 128) return 4;
+  return 5;
 }
 
 template <int NW>
@@ -79,24 +84,86 @@ __device__ inline void grp_sync() {
     __syncthreads();
 }
 
-// Y[(y0 + p) * n + j] = A(row order[p]) for p in [0, cnt) (rows of the
-// waves' share), with the row list read forwards (near) or backwards (far).
-template <typename T, int NW, int NCOL>
-__device__ inline void idc_gather(const T* __restrict__ varena, const IdRow* rows, const int* order, int R,
-                                  bool backwards, int cnt, double* Y, int y0, int n) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// Fetches rows [0, cnt) of the list (near rows order[p], then far rows
+// order[R - 1 - f]): near row p goes to Y[p * n + j], far row f to
+// BF[f * n + j].  One (row, column) entry per thread and step, so every load
+// of a step is independent and in flight at once.
+template <typename T, int NT>
+__device__ inline void idc_fetch(const T* __restrict__ varena, const IdRow* rows, const int* order, int R, int nN,
+                                 int cnt, double* Y, T* BF, int n) {
 #pragma unroll 4
-  for (int p = w; p < cnt; p += NW) {
-    const IdRow m = rows[backwards ? order[R - 1 - p] : order[p]];
-#pragma unroll
-    for (int s = 0; s < NCOL; ++s) {
-      const int j = lane + 64 * s;
-      if (j < n) Y[size_t(y0 + p) * n + j] = double(varena[m.base + int64_t(j) * m.stride]);
-    }
+  for (int t = threadIdx.x; t < cnt * n; t += NT) {
+    const int p = t / n, j = t - p * n;
+    const bool near = p < nN;
+    const IdRow m = rows[near ? order[p] : order[R - 1 - (p - nN)]];
+    const T v = varena[m.base + int64_t(j) * m.stride];
+    if (near)
+      Y[t] = double(v);
+    else
+      BF[size_t(p - nN) * n + j] = v;
   }
 }
 
-template <typename T, int NW, int NCOL, bool YG>
+// Sum over this wave's rows i = i0, i0 + NW, ... < m of Y[i][a] * Y[i][b]
+// (row-major, ld n); UR rows are loaded before their products are summed, so
+// that many loads are in flight.
+template <int NW, int UR>
+__device__ inline double idc_rowdot(const double* Y, int n, int i0, int m, int a, int b) {
+  double acc[UR];
+#pragma unroll
+  for (int u = 0; u < UR; ++u) acc[u] = 0.0;
+  int i = i0;
+  for (; i + (UR - 1) * NW < m; i += UR * NW) {
+    double ya[UR], yb[UR];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      ya[u] = Y[size_t(i + u * NW) * n + a];
+      yb[u] = Y[size_t(i + u * NW) * n + b];
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u) acc[u] += ya[u] * yb[u];
+  }
+  for (; i < m; i += NW) acc[0] += Y[size_t(i) * n + a] * Y[size_t(i) * n + b];
+  double t = 0.0;
+#pragma unroll
+  for (int u = 0; u < UR; ++u) t += acc[u];
+  return t;
+}
+
+// Y[i][col] -= f * Y[i][q] over this wave's rows i = i0, i0 + NW, ... < m;
+// returns the sum of the squares of the updated entries.
+template <int NW, int UR>
+__device__ inline double idc_rowaxpy(double* Y, int n, int i0, int m, int col, int q, double f) {
+  double acc[UR];
+#pragma unroll
+  for (int u = 0; u < UR; ++u) acc[u] = 0.0;
+  int i = i0;
+  for (; i + (UR - 1) * NW < m; i += UR * NW) {
+    double yc[UR], yq[UR];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      yc[u] = Y[size_t(i + u * NW) * n + col];
+      yq[u] = Y[size_t(i + u * NW) * n + q];
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const double y = yc[u] - f * yq[u];
+      Y[size_t(i + u * NW) * n + col] = y;
+      acc[u] += y * y;
+    }
+  }
+  for (; i < m; i += NW) {
+    const double y = Y[size_t(i) * n + col] - f * Y[size_t(i) * n + q];
+    Y[size_t(i) * n + col] = y;
+    acc[0] += y * y;
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int u = 0; u < UR; ++u) t += acc[u];
+  return t;
+}
+
+template <typename T, int NW, int NCOL, bool YG, int TIER>
 __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int nseg, const DNbr* nbrs,
                                                          const DBlk* blks, GridGeom g, int32_t* iarena,
                                                          T* __restrict__ varena, double* __restrict__ scratch,
@@ -105,9 +172,9 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   __shared__ int s_cnt[2];
   __shared__ int s_acc;
   constexpr int NT = 64 * NW;
-  constexpr int TIER = YG ? 3 : (NW == 1 ? 1 : 2);
-  constexpr int IC = IDC_IC;
+  constexpr int IC = idc_ic(NCOL);
   constexpr int IDC_FT = idc_ft(NCOL);
+  constexpr int UR = YG ? 8 : 4;  // rows in flight per lane in the CPQR passes
   const int c = blockIdx.x;
   if (c >= nseg) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -135,13 +202,17 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   double* Y;
   IdRow* rows;
   int* order;
+  T* BF;  // far rows, row-major (ld n), in the storage type
   if constexpr (YG) {
     Y = scratch + S.scr_off;
-    rows = reinterpret_cast<IdRow*>(Y + size_t(R) * n);
+    BF = reinterpret_cast<T*>(Y + size_t(R) * n);
+    rows = reinterpret_cast<IdRow*>(Y + 2 * size_t(R) * n);
     order = reinterpret_cast<int*>(rows + R);
   } else {
     Y = reinterpret_cast<double*>(sp);
     sp += size_t(R) * n * 8;
+    BF = reinterpret_cast<T*>(sp);
+    sp += size_t(R) * n * sizeof(T);
     rows = reinterpret_cast<IdRow*>(sp);
     sp += size_t(R) * sizeof(IdRow);
   }
@@ -225,10 +296,12 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
     ++passes;
     const bool sampled = h < nF;
     const int m = nN + (sampled ? h : nF);
-    // ---- 2. Y = [B_N; G B_F / sqrt(h)] or the exact far rows ----
-    idc_gather<T, NW, NCOL>(varena, rows, order, R, false, nN, Y, 0, n);
+    // ---- 2. Y = [B_N; G B_F / sqrt(h)] or the exact far rows; B_F is
+    //         fetched once and kept for later passes ----
+    idc_fetch<T, NT>(varena, rows, order, R, nN, passes == 1 ? R : nN, Y, BF, n);
+    __syncthreads();
     if (!sampled) {
-      idc_gather<T, NW, NCOL>(varena, rows, order, R, true, nF, Y, nN, n);
+      for (int t = tid; t < nF * n; t += NT) Y[size_t(nN) * n + t] = double(BF[t]);
     } else {
       const double sc = 1.0 / sqrt(double(h));
       for (int stream = 0; stream < 2; ++stream) {
@@ -242,19 +315,6 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
             for (int s = 0; s < NCOL; ++s) acc[a][s] = 0.0;
           for (int f0 = w * IDC_FT; f0 < nF; f0 += NW * IDC_FT) {
             const int fw = nF - f0 < IDC_FT ? nF - f0 : IDC_FT;
-            double b[IDC_FT][NCOL];
-#pragma unroll
-            for (int ff = 0; ff < IDC_FT; ++ff) {
-              IdRow mr;
-              mr.base = 0;
-              mr.stride = 0;
-              if (ff < fw) mr = rows[order[R - 1 - (f0 + ff)]];
-#pragma unroll
-              for (int s = 0; s < NCOL; ++s) {
-                const int j = lane + 64 * s;
-                b[ff][s] = (ff < fw && j < n) ? double(varena[mr.base + int64_t(j) * mr.stride]) : 0.0;
-              }
-            }
             // Gaussian tile: IC rows x IDC_FT far rows, one Philox draw per row pair
             for (int t = lane; t < (IC / 2) * IDC_FT; t += 64) {
               const int pr = t / IDC_FT, ff = t % IDC_FT;
@@ -267,14 +327,21 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
               Gt[(2 * pr + 1) * IDC_FT + ff] = 2 * pr + 1 < ih ? od : 0.0;
             }
             wave_sync();
+#pragma unroll 4
+            for (int ff = 0; ff < IDC_FT; ++ff) {
+              double b[NCOL];
 #pragma unroll
-            for (int ff = 0; ff < IDC_FT; ++ff)
+              for (int s = 0; s < NCOL; ++s) {
+                const int j = lane + 64 * s;
+                b[s] = (ff < fw && j < n) ? double(BF[size_t(f0 + ff) * n + j]) : 0.0;
+              }
 #pragma unroll
               for (int a = 0; a < IC; ++a) {
                 const double gv = Gt[a * IDC_FT + ff];
 #pragma unroll
-                for (int s = 0; s < NCOL; ++s) acc[a][s] += gv * b[ff][s];
+                for (int s = 0; s < NCOL; ++s) acc[a][s] += gv * b[s];
               }
+            }
             wave_sync();
           }
           // combine the waves' partial sums in wave order
@@ -312,20 +379,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
 #pragma unroll
     for (int s = 0; s < NCOL; ++s) {
       const int j = lane + 64 * s;
-      double a0 = 0.0, a1 = 0.0;
-      if (j < n) {
-        int i = w;
-        for (; i + NW < m; i += 2 * NW) {
-          const double y0 = Y[size_t(i) * n + j], y1 = Y[size_t(i + NW) * n + j];
-          a0 += y0 * y0;
-          a1 += y1 * y1;
-        }
-        if (i < m) {
-          const double y0 = Y[size_t(i) * n + j];
-          a0 += y0 * y0;
-        }
-      }
-      pn[(w * NCOL + s) * 64 + lane] = a0 + a1;
+      pn[(w * NCOL + s) * 64 + lane] = j < n ? idc_rowdot<NW, UR>(Y, n, w, m, j, j) : 0.0;
     }
     __syncthreads();
     const int kmax = m < n ? m : n;
@@ -371,45 +425,27 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
 #pragma unroll
       for (int s = 0; s < NCOL; ++s) {
         const int col = lane + 64 * s;
-        double d0 = 0.0, d1 = 0.0;
+        double d = 0.0;
         if (act[s] && col != q) {
-          if (w == jown) d0 = v0 * Y[size_t(j) * n + col];
-          int i = i1;
-          for (; i + NW < m; i += 2 * NW) {
-            d0 += Y[size_t(i) * n + q] * Y[size_t(i) * n + col];
-            d1 += Y[size_t(i + NW) * n + q] * Y[size_t(i + NW) * n + col];
-          }
-          if (i < m) d0 += Y[size_t(i) * n + q] * Y[size_t(i) * n + col];
+          if (w == jown) d = v0 * Y[size_t(j) * n + col];
+          d += idc_rowdot<NW, UR>(Y, n, i1, m, q, col);
         }
-        pd[(w * NCOL + s) * 64 + lane] = d0 + d1;
+        pd[(w * NCOL + s) * 64 + lane] = d;
       }
       __syncthreads();
       // apply the reflector; accumulate the fresh norms of rows > j
 #pragma unroll
       for (int s = 0; s < NCOL; ++s) {
         const int col = lane + 64 * s;
-        double a0 = 0.0, a1 = 0.0;
+        double a = 0.0;
         if (act[s] && col != q) {
           double t = 0.0;
           for (int ww = 0; ww < NW; ++ww) t += pd[(ww * NCOL + s) * 64 + lane];
           const double f = 2.0 * t / vv;
           if (w == jown) Y[size_t(j) * n + col] -= f * v0;
-          int i = i1;
-          for (; i + NW < m; i += 2 * NW) {
-            const double y0 = Y[size_t(i) * n + col] - f * Y[size_t(i) * n + q];
-            const double y1 = Y[size_t(i + NW) * n + col] - f * Y[size_t(i + NW) * n + q];
-            Y[size_t(i) * n + col] = y0;
-            Y[size_t(i + NW) * n + col] = y1;
-            a0 += y0 * y0;
-            a1 += y1 * y1;
-          }
-          if (i < m) {
-            const double y0 = Y[size_t(i) * n + col] - f * Y[size_t(i) * n + q];
-            Y[size_t(i) * n + col] = y0;
-            a0 += y0 * y0;
-          }
+          a = idc_rowaxpy<NW, UR>(Y, n, i1, m, col, q, f);
         }
-        pn[(w * NCOL + s) * 64 + lane] = a0 + a1;
+        pn[(w * NCOL + s) * 64 + lane] = a;
       }
       if (w == jown && lane == ql) Y[size_t(j) * n + q] = -sg * alpha;
       done[qs] |= 1ull << ql;
@@ -448,26 +484,42 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
     }
     __syncthreads();
 
-    // ---- 5. a-posteriori check with the probe rows: E = P_r - P_s T ----
+    // ---- 5. a-posteriori check with the probe rows: E = P_r - P_s T
+    //         (one probe per wave, the columns of T over the lanes) ----
     bool accept = true;
     if (sampled) {
-      if (w == 0) {
-        double worst = 0.0;
-        for (int pr = 0; pr < probes; ++pr) {
-          double sv = 0.0;
+      for (int pr = w; pr < probes; pr += NW) {
+        double sv = 0.0;
 #pragma unroll
-          for (int s = 0; s < NCOL; ++s) {
-            const int qq = lane + 64 * s;
-            if (qq < nr) {
-              const int cq = pos2col[k + qq];
-              double e = P[size_t(pr) * n + cq];
-              for (int t = 0; t < k; ++t) e -= P[size_t(pr) * n + pos2col[t]] * Y[size_t(t) * n + cq];
-              sv += e * e;
+        for (int s = 0; s < NCOL; ++s) {
+          const int qq = lane + 64 * s;
+          if (qq < nr) {
+            const int cq = pos2col[k + qq];
+            const double* Pr = P + size_t(pr) * n;
+            double e = Pr[cq];
+            int t = 0;
+            for (; t + UR <= k; t += UR) {
+              double yv[UR], pv[UR];
+#pragma unroll
+              for (int u = 0; u < UR; ++u) {
+                yv[u] = Y[size_t(t + u) * n + cq];
+                pv[u] = Pr[pos2col[t + u]];
+              }
+#pragma unroll
+              for (int u = 0; u < UR; ++u) e -= pv[u] * yv[u];
             }
+            for (; t < k; ++t) e -= Pr[pos2col[t]] * Y[size_t(t) * n + cq];
+            sv += e * e;
           }
-          worst = fmax(worst, sqrt(wave_sum(sv)));
         }
-        if (lane == 0) s_acc = worst <= prm.tau * prm.eps * r11 ? 1 : 0;
+        sv = wave_sum(sv);
+        if (lane == 0) pn[pr] = sqrt(sv);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double worst = 0.0;
+        for (int pr = 0; pr < probes; ++pr) worst = fmax(worst, pn[pr]);
+        s_acc = worst <= prm.tau * prm.eps * r11 ? 1 : 0;
       }
       __syncthreads();
       accept = s_acc != 0;
@@ -607,7 +659,7 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
   const int n = dyn.n[c];
   int R = 0;
   for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += 2 * dyn.n[nbrs[e].d];
-  if (id_tier(S, n, R, prm.eps, tiers) != 4) return;
+  if (id_tier(S, n, R, prm.eps, tiers) != 5) return;
   int32_t* dofs = iarena + S.ioff;
   int32_t* perm = dofs + S.cap;
   int32_t* tag = perm + 2 * S.cap;  // after piv

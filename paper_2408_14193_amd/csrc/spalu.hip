@@ -53,8 +53,8 @@ struct LevelTabs {
   size_t o_segs = 0, o_nbrs = 0, o_blks = 0, o_scale = 0, o_cons_ptr = 0, o_cons = 0, o_task_ptr = 0,
          o_tasks = 0, o_terms = 0, o_dyn = 0;
   // ID launches of the level (bounds from the uncompressed sizes)
-  IdTiers tiers{0, 0};
-  bool id_b = false, id_c = false, id_old = false;
+  IdTiers tiers{0, 0, 0, 8};
+  bool id_b = false, id_b2 = false, id_c = false, id_old = false;
 };
 
 struct Layout {
@@ -126,40 +126,51 @@ struct spalu_factor_s {
 
 namespace {
 
-// LDS limits of the column-parallel ID tiers (bytes of dynamic LDS).
-constexpr size_t ID_A_MAX_BYTES = 24 * 1024;  // 64-thread groups: six or more per CU
-constexpr size_t ID_B_MAX_BYTES = 60 * 1024;  // 256-thread groups: two per CU
+// LDS limits of the column-parallel ID tiers (bytes of dynamic LDS; a gfx950
+// workgroup may hold up to 160 KB).
+constexpr size_t ID_A_MAX_BYTES = 24 * 1024;    // 64-thread groups: six or more per CU
+constexpr size_t ID_B_MAX_BYTES = 72 * 1024;    // 256-thread groups: two per CU
+constexpr size_t ID_B2_MAX_BYTES = 152 * 1024;  // 256-thread groups: one per CU
 
 // Which ID launches a level needs and their LDS budgets.  The sizes known
 // here (uncompressed n, coupling-row bound rcap) bound the ones the kernels
 // see, so a segment whose bound fits a tier certainly lands in it; the
 // kernels themselves decide with the actual sizes.
-void plan_id_tiers(LevelTabs& T) {
-  size_t a = 0, b = 0;
-  bool beyond_a = false, beyond_b = false, wide = false;
+void plan_id_tiers(LevelTabs& T, int st) {
+  size_t a = 0, b = 0, b2 = 0;
+  bool beyond_a = false, beyond_b = false, beyond_b2 = false, wide = false;
   for (const DSeg& D : T.segs) {
     if (!((D.flags & SEG_REGULAR) && (D.flags & SEG_HAS_NBR))) continue;
     const int cap = D.cap, R = D.rcap;
-    const size_t na = idc_lds_bytes(1, 1, std::min(cap, 64), R, true);
+    const size_t na = idc_lds_bytes(1, 1, std::min(cap, 64), R, st, true);
     if (cap <= 64 && na <= ID_A_MAX_BYTES) {
       a = std::max(a, na);
       continue;
     }
     beyond_a = true;
-    const size_t nb = idc_lds_bytes(4, 2, std::min(cap, 128), R, true);
+    const size_t nb = idc_lds_bytes(4, 2, std::min(cap, 128), R, st, true);
     if (cap <= 128 && nb <= ID_B_MAX_BYTES) {
       b = std::max(b, nb);
       continue;
     }
-    b = ID_B_MAX_BYTES;
     beyond_b = true;
+    if (cap <= 128 && nb <= ID_B2_MAX_BYTES) {
+      b2 = std::max(b2, nb);
+      continue;
+    }
+    beyond_b2 = true;
     if (cap > 128) wide = true;
   }
   if (beyond_a) a = ID_A_MAX_BYTES;
-  T.tiers.budget_a = int(std::max(a, idc_lds_bytes(1, 1, 1, 1, true)));
-  T.tiers.budget_b = int(std::max(b, idc_lds_bytes(4, 2, 1, 1, true)));
+  if (beyond_b) b = ID_B_MAX_BYTES;
+  if (beyond_b2) b2 = ID_B2_MAX_BYTES;
+  T.tiers.st = st;
+  T.tiers.budget_a = int(std::max(a, idc_lds_bytes(1, 1, 1, 2, st, true)));
+  T.tiers.budget_b = int(std::max(b, idc_lds_bytes(4, 2, 1, 2, st, true)));
+  T.tiers.budget_b2 = int(std::max<size_t>(b2, size_t(T.tiers.budget_b)));
   T.id_b = beyond_a;
-  T.id_c = beyond_b;
+  T.id_b2 = beyond_b;
+  T.id_c = beyond_b2;
   T.id_old = wide;
 }
 
@@ -252,7 +263,7 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
       level_pool += need;
     }
     pool = std::max(pool, level_pool);
-    plan_id_tiers(T);
+    plan_id_tiers(T, prec == SPALU_FP32 ? 4 : 8);
   }
 
   // merge tables l -> l-1
@@ -807,19 +818,34 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       }
     }
     {
+      static const bool lds_ok = [] {
+        // tier-B workgroups may take more than 64 KB of LDS
+        const bool b1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 4, 2, false, 2>),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            int(ID_B_MAX_BYTES)) == hipSuccess;
+        const bool b2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 4, 2, false, 3>),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            int(ID_B2_MAX_BYTES)) == hipSuccess;
+        return b1 && b2;
+      }();
+      if (!lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the ID kernel");
       const DNbr* nb = tab<DNbr>(ws, T_.o_nbrs);
       const IdTiers tz = T_.tiers;
-      LAUNCH(K_ID, l, k_seg_id_cols<T, 1, 1, false><<<unsigned(ns), 64, size_t(tz.budget_a), st>>>(
+      LAUNCH(K_ID, l, k_seg_id_cols<T, 1, 1, false, 1><<<unsigned(ns), 64, size_t(tz.budget_a), st>>>(
           segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       if (T_.id_b)
-        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 4, 2, false><<<unsigned(ns), 256, size_t(tz.budget_b), st>>>(
+        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 4, 2, false, 2><<<unsigned(ns), 256, size_t(tz.budget_b), st>>>(
+            segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
+      if (T_.id_b2)
+        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 4, 2, false, 3><<<unsigned(ns), 256, size_t(tz.budget_b2), st>>>(
             segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       if (T_.id_c)
-        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 16, 2, true><<<unsigned(ns), 1024, idc_lds_bytes(16, 2, 128, 0, false),
-                                                             st>>>(segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
+        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 8, 2, true, 4><<<unsigned(ns), 512,
+                                                               idc_lds_bytes(8, 2, 128, 0, tz.st, false), st>>>(
+            segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       if (T_.id_old)
         LAUNCH_MORE(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var, scr, d,
-                                                                       prm, tz));
+                                                                            prm, tz));
     }
     LAUNCH(K_LU, l, k_seg_lu<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, blks, iar, var, scr, d, status));
     if (!T_.scale_list.empty()) {
