@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="direct launches in every form")
+    ap.add_argument("--restart", type=int, default=8,
+                    help="refinement corrections by flexible GMRES(restart); 0: classical x += M r")
     return ap.parse_args()
 
 
@@ -53,7 +55,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True):
+def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8):
     import numpy as np
     import torch
     prec = S.FP64 if form == "plain" else S.FP32
@@ -72,7 +74,7 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True):
         t0 = time.perf_counter()
         F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec, rank_model=model)
         t1 = time.perf_counter()
-        info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(graph and form != "plain"))
+        info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(graph and form != "plain"), restart=restart)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return F, info, rr, t1 - t0, t2 - t1
@@ -171,7 +173,8 @@ def main():
     forms = a.forms.split(",")
     res = {}
     for i, f in enumerate(forms):
-        res[f] = run_form(S, P, nd, dev, f, a.steps, a.warmup, profile=(i == 0), graph=not a.no_graph)
+        res[f] = run_form(S, P, nd, dev, f, a.steps, a.warmup, profile=(i == 0), graph=not a.no_graph,
+                          restart=a.restart)
     head = forms[0]
     r = res[head]
     value = P.n / (r["ms_per_step"] * 1e-3)
@@ -194,6 +197,7 @@ def main():
         "config": {"workload": "%s %s, N=%d, %d RHS, eps=%g, refinement to %g, %s form"
                                % (P.name, "x".join(map(str, P.dims)), P.n, P.nrhs, P.eps, P.tol, head),
                    "n": P.n, "nrhs": P.nrhs, "eps": P.eps, "tol": P.tol, "levels": nd.L,
+                   "refinement": ("fgmres(%d)" % a.restart) if a.restart > 0 else "classical",
                    "nd_host_s": round(t_nd, 3)},
         "factor_ms": round(r["factor_ms"], 3),
         "solve_ms": round(r["solve_ms"], 3),

@@ -192,6 +192,14 @@ typedef struct {
                         replay it; the graph is cached on the ND handle and
                         keyed by every pointer it bakes in.  0: direct
                         launches.  NULL opts means 0.                    */
+  int32_t restart;   /* 0: classical refinement x += M r.  m > 0: each
+                        refinement step solves A d = r by flexible GMRES(m)
+                        with the factor as right preconditioner (FP64
+                        basis, Hessenberg and residual; the factor applied
+                        in its own precision) and stops its Arnoldi cycle as
+                        soon as every column's correction residual is below
+                        tol/2; max_iter then counts factor applications.
+                        1 <= m <= 32.                                     */
 } spalu_solve_opts;
 
 typedef struct {
@@ -200,8 +208,11 @@ typedef struct {
   double first_rel_residual; /* same after the direct solve               */
 } spalu_solve_info;
 
-/* Bytes of device workspace for nrhs right-hand sides. */
-int spalu_solve_workspace(const spalu_factor_t* f, int32_t nrhs, size_t* bytes);
+/* Bytes of device workspace for nrhs right-hand sides and the given options
+ * (NULL: direct solve / classical refinement; the GMRES basis of
+ * opts->restart > 0 takes (2 m + 1) n nrhs doubles more). */
+int spalu_solve_workspace(const spalu_factor_t* f, int32_t nrhs, const spalu_solve_opts* opts,
+                          size_t* bytes);
 
 /* Refinement stops early, with ENOCONV, when three consecutive steps fail to
  * reduce the largest column residual by 10 %, or when it is not finite.

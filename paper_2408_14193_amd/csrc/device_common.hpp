@@ -13,12 +13,11 @@ constexpr int WG = 256;      // threads per workgroup (4 wave64)
 constexpr int NWAVE = WG / 64;
 constexpr int LDS_DOUBLES = 4096;  // dynamic LDS staging buffer (32 KB)
 constexpr int LEAF_LDS_DOUBLES = 6144;  // leaf factorization staging (48 KB)
+constexpr int LEAF_MAX_NI = 512;        // interior vertices of a leaf box (7^3 = 343 in 3D)
 
-// Staging doubles of a leaf: LU + A_IB solve, then LU + inverse.
-__host__ __device__ inline int leaf_lds_need(int ni, int nb) {
-  const int a = ni * ni + ni * nb, b = 2 * ni * ni;
-  return a > b ? a : b;
-}
+// Staging doubles of a leaf: A_II (inverted in place), A_IB,
+// A_II^{-1} A_IB, one column and the boundary vertex list.
+__host__ __device__ inline int leaf_lds_need(int ni, int nb) { return ni * ni + 2 * ni * nb + ni + (nb + 1) / 2; }
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll

@@ -52,7 +52,10 @@ __global__ void k_check_pattern(GridGeom g, int64_t n, const int64_t* rowptr, co
 }
 
 // ---------------------------------------------------------------------------
-// Leaf elimination (eq. (4.8)): LU of A_II and S = A_BI A_II^{-1} A_IB.
+// Leaf elimination (eq. (4.8)): A_II^{-1} by Gauss-Jordan elimination with
+// partial pivoting (in place; the row interchanges become column
+// interchanges of the inverse), X = A_II^{-1} A_IB and S = A_BI X.  Three
+// barriers per pivot step.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nleaf, GridGeom g,
@@ -61,6 +64,8 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
                                                     double* gscratch, int64_t gscr_stride, int* status) {
   extern __shared__ double lds[];
   __shared__ int s_piv;
+  __shared__ double s_d;
+  __shared__ int s_pv[LEAF_MAX_NI];
   const int lf = blockIdx.x;
   if (lf >= nleaf) return;
   const DLeaf L = leaves[lf];
@@ -69,9 +74,13 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
   const int32_t* bverts = iarena + L.ioff;
   int32_t* piv = iarena + L.ioff + nb;
   const bool fits = leaf_lds_need(ni, nb) <= LEAF_LDS_DOUBLES;
-  double* A = fits ? lds : gscratch + size_t(lf) * gscr_stride;
-  double* X = A + ni * ni;
+  double* A = fits ? lds : gscratch + size_t(lf) * gscr_stride;  // A_II, then its inverse
+  double* B = A + ni * ni;                                        // A_IB
+  double* X = B + ni * nb;                                        // A_II^{-1} A_IB
+  double* f = X + ni * nb;                                        // column k before step k
+  int* bv = reinterpret_cast<int*>(f + ni);                       // boundary vertices
   for (int t = tid; t < ni * ni + ni * nb; t += WG) A[t] = 0.0;
+  for (int b = tid; b < nb; b += WG) bv[b] = bverts[b];
   __syncthreads();
   // interior rows: A_II and A_IB
   for (int i = tid; i < ni; i += WG) {
@@ -87,24 +96,96 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
         A[i * ni + j] = vals[e];
       } else {
         for (int b = 0; b < nb; ++b)
-          if (bverts[b] == w) {
-            X[i * nb + b] = vals[e];
+          if (bv[b] == w) {
+            B[i * nb + b] = vals[e];
             break;
           }
       }
     }
   }
   __syncthreads();
-  if (block_lu_window(A, ni, ni, 0, piv, &s_piv)) atomicOr(status, 1);
-  __syncthreads();
+  bool singular = false;
+  for (int k = 0; k < ni; ++k) {
+    // pivot: largest |a_ik|, i >= k (ties to the smaller row); keep column k
+    for (int i = tid; i < ni; i += WG) f[i] = A[i * ni + k];
+    if (tid < 64) {
+      double bv = -1.0;
+      int bi = 1 << 30;
+      for (int i = k + tid; i < ni; i += 64) {
+        const double a = fabs(A[i * ni + k]);
+        if (a > bv) {
+          bv = a;
+          bi = i;
+        }
+      }
+      wave_argmax(bv, bi);
+      if (tid == 0) {
+        const int pp = bi < ni ? bi : k;
+        s_piv = pp;
+        s_d = A[pp * ni + k];
+        s_pv[k] = pp;
+      }
+    }
+    __syncthreads();
+    const int p = s_piv;
+    const double d = s_d;
+    if (d == 0.0) {  // uniform: every thread read the same d
+      singular = true;
+      __syncthreads();
+      continue;
+    }
+    // swap rows k and p, scale the new row k (its entry k becomes 1/d)
+    for (int j = tid; j < ni; j += WG) {
+      const double ak = A[k * ni + j], ap = A[p * ni + j];
+      if (p != k) A[p * ni + j] = ak;
+      A[k * ni + j] = j == k ? 1.0 / d : ap / d;
+    }
+    __syncthreads();
+    // eliminate column k from every other row; the multiplier of row i is
+    // its entry in column k after the interchange.  Thread (r, j) = (tid /
+    // 64, tid % 64) updates column j (and j + 64, ...) of rows r, r + 4, ...
+    for (int j = tid & 63; j < ni; j += 64) {
+      const double akj = A[k * ni + j];
+      for (int i = tid >> 6; i < ni; i += WG / 64) {
+        if (i == k) continue;
+        const double mi = i == p ? f[k] : f[i];
+        if (j == k)
+          A[i * ni + j] = -mi * akj;
+        else
+          A[i * ni + j] -= mi * akj;
+      }
+    }
+    __syncthreads();
+  }
+  if (singular && tid == 0) atomicOr(status, 1);
+  for (int k = tid; k < ni; k += WG) piv[k] = s_pv[k];
+  // undo the row interchanges on the columns of the inverse, last first
+  for (int k = ni - 1; k >= 0; --k) {
+    const int p = s_pv[k];
+    if (p == k) continue;
+    for (int i = tid; i < ni; i += WG) {
+      const double t = A[i * ni + k];
+      A[i * ni + k] = A[i * ni + p];
+      A[i * ni + p] = t;
+    }
+    __syncthreads();
+  }
   // X = A_II^{-1} A_IB
-  block_lower_solve<double>(A, ni, piv, ni, X, nb, nb);
-  block_upper_solve<double>(A, ni, ni, X, nb, nb);
+  for (int t = tid; t < ni * nb; t += WG) {
+    const int i = t / nb, c = t - i * nb;
+    double acc = 0.0;
+    for (int q = 0; q < ni; ++q) acc += A[i * ni + q] * B[q * nb + c];
+    X[t] = acc;
+  }
+  // A_II^{-1} (the solve applies it as a product)
+  T* LUo = varena + L.lu_off;
+  for (int t = tid; t < ni * ni; t += WG) LUo[t] = T(A[t]);
+  __syncthreads();
   // S = A_BI X (boundary rows, sparse)
   T* S = varena + L.s_off;
   for (int t = tid; t < nb * nb; t += WG) {
     const int b = t / nb, c = t % nb;
-    const int u = bverts[b];
+    const int u = bv[b];
     double acc = 0.0;
     for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
       const int w = colind[e];
@@ -118,15 +199,6 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
     }
     S[t] = T(acc);
   }
-  // A_II^{-1} (stored in place of the LU; the solve applies it as a product)
-  __syncthreads();
-  double* Ai = A + ni * ni;
-  for (int t = tid; t < ni * ni; t += WG) Ai[t] = (t / ni == t % ni) ? 1.0 : 0.0;
-  __syncthreads();
-  block_lower_solve<double>(A, ni, piv, ni, Ai, ni, ni);
-  block_upper_solve<double>(A, ni, ni, Ai, ni, ni);
-  T* LUo = varena + L.lu_off;
-  for (int t = tid; t < ni * ni; t += WG) LUo[t] = T(Ai[t]);
 }
 
 // Level-L setup: sizes and DOF lists of the level-L segments.
@@ -196,7 +268,8 @@ struct IdParams {
 template <typename T>
 __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const DBlk* blks,
                                                int32_t* iarena, T* varena, double* scratch,
-                                               DLevelDyn dyn, int* status) {
+                                               DLevelDyn dyn, int* status, int need_lo, int need_hi,
+                                               int lds_doubles) {
   extern __shared__ double lds[];
   __shared__ int s_piv;
   const int c = blockIdx.x;
@@ -205,6 +278,10 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   const DSeg S = segs[c];
   const int n = dyn.n[c];
   if (n == 0) return;
+  // this launch takes the segments whose staging need 2 n^2 (doubles) lies
+  // in (need_lo, need_hi]; they work in LDS if it fits, else in scratch
+  const int need = 2 * n * n;
+  if (need <= need_lo || need > need_hi) return;
   const int k = dyn.k[c], nr = dyn.nr[c];
   const bool sp = dyn.passes[c] > 0;
   int32_t* dofs = iarena + S.ioff;
@@ -212,7 +289,7 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   int32_t* piv = perm + S.cap;
   int32_t* tmp = piv + S.cap;  // tag region, >= cap ints
   const T* M = varena + blks[S.diag_blk].off;
-  const bool inlds = 2 * size_t(n) * n <= LDS_DOUBLES;
+  const bool inlds = need <= lds_doubles;
   double* W = inlds ? lds : scratch + S.scr_off;
   double* X = W + size_t(n) * n;  // inverse workspace
   // gather in [r; s] order: o[p] = perm[k + p] (p < nr), perm[p - nr]
@@ -242,8 +319,14 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
     }
     __syncthreads();
   }
-  if (block_lu_window(W, n, n, sp ? nr : 0, piv, &s_piv)) atomicOr(status, 1);
+  // pivots in LDS while the LU runs (a global store before every barrier
+  // would stall each step), copied out afterwards
+  const bool pv_lds = inlds && need + (n + 1) / 2 <= lds_doubles;
+  int* pv = pv_lds ? reinterpret_cast<int*>(lds + need) : piv;
+  if (block_lu_window(W, n, n, sp ? nr : 0, pv, &s_piv)) atomicOr(status, 1);
   __syncthreads();
+  if (pv_lds)
+    for (int j = tid; j < n; j += WG) piv[j] = pv[j];
   // packed inverses: strictly lower part of L^{-1} (unit diagonal implied)
   // and upper part of U^{-1}, so every later application is a product
   T* LU = varena + S.lu_off;
@@ -255,6 +338,161 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   }
 }
 
+// One wave per segment of at most 64 DOFs (lane = column): the transform
+// and the two-stage LU of k_seg_lu with wave-level synchronisation only, and
+// every column of L^{-1} and U^{-1} computed by its own lane.  W and X
+// (n x n each, row-major) live in this wave's LDS.
+template <typename T>
+__global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, const DBlk* blks,
+                                                    int32_t* iarena, T* varena, DLevelDyn dyn, int* status,
+                                                    int nmax) {
+  extern __shared__ double lds[];
+  const int c = blockIdx.x;
+  if (c >= nseg) return;
+  const int lane = threadIdx.x;
+  const DSeg S = segs[c];
+  const int n = dyn.n[c];
+  if (n == 0 || n > nmax) return;
+  const int k = dyn.k[c], nr = dyn.nr[c];
+  const bool sp = dyn.passes[c] > 0;
+  int32_t* dofs = iarena + S.ioff;
+  int32_t* perm = dofs + S.cap;
+  int32_t* piv = perm + S.cap;
+  const T* M = varena + blks[S.diag_blk].off;
+  double* W = lds;
+  double* X = lds + size_t(n) * n;
+  // gather in [r; s] order: o[p] = perm[k + p] (p < nr), perm[p - nr]
+  for (int t = lane; t < n * n; t += 64) {
+    const int p = t / n, q = t - p * n;
+    const int op = sp ? (p < nr ? perm[k + p] : perm[p - nr]) : p;
+    const int oq = sp ? (q < nr ? perm[k + q] : perm[q - nr]) : q;
+    W[t] = double(M[size_t(op) * n + oq]);
+  }
+  wave_sync();
+  if (sp && nr > 0 && k > 0) {
+    // T (k x nr) staged in X
+    const T* Tm = varena + S.t_off;
+    for (int t = lane; t < k * nr; t += 64) X[t] = double(Tm[t]);
+    wave_sync();
+    // columns: W[:, q] -= W[:, nr:] T[:, q]  (lane q < nr)
+    if (lane < nr)
+      for (int p = 0; p < n; ++p) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s += W[p * n + nr + i] * X[i * nr + lane];
+        W[p * n + lane] -= s;
+      }
+    wave_sync();
+    // rows: W[p, :] -= T[:, p]^T W[nr:, :]  (lane = column)
+    if (lane < n)
+      for (int p = 0; p < nr; ++p) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s += X[i * nr + p] * W[(nr + i) * n + lane];
+        W[p * n + lane] -= s;
+      }
+    wave_sync();
+  }
+  // LU with partial pivoting; steps j < nr search rows [j, nr), later steps [j, n)
+  const int split = sp ? nr : 0;
+  bool singular = false;
+  for (int j = 0; j < n; ++j) {
+    const int hi = j < split ? split : n;
+    double bv = -1.0;
+    int bi = 1 << 30;
+    if (lane >= j && lane < hi) {
+      bv = fabs(W[lane * n + j]);
+      bi = lane;
+    }
+    wave_argmax(bv, bi);
+    const int p = bi < n ? bi : j;
+    if (lane == 0) piv[j] = p;
+    if (p != j && lane < n) {
+      const double t = W[j * n + lane];
+      W[j * n + lane] = W[p * n + lane];
+      W[p * n + lane] = t;
+    }
+    wave_sync();
+    const double d = W[j * n + j];
+    if (d == 0.0) {
+      singular = true;
+      continue;
+    }
+    if (lane > j && lane < n) W[lane * n + j] /= d;
+    wave_sync();
+    if (lane > j && lane < n) {
+      const double ujc = W[j * n + lane];
+      int i = j + 1;
+      for (; i + 3 < n; i += 4) {
+        double l[4], w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          l[u] = W[(i + u) * n + j];
+          w[u] = W[(i + u) * n + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) W[(i + u) * n + lane] = w[u] - l[u] * ujc;
+      }
+      for (; i < n; ++i) W[i * n + lane] -= W[i * n + j] * ujc;
+    }
+    wave_sync();
+  }
+  if (singular && lane == 0) atomicOr(status, 1);
+  // packed inverses, one column per lane: strictly lower L^{-1} (unit
+  // diagonal implied) and upper U^{-1}
+  T* LU = varena + S.lu_off;
+  if (lane < n) {
+    const int q = lane;
+    // column q of L^{-1}: e_q forward-substituted through the unit lower L
+    for (int i = 0; i < n; ++i) X[i * n + q] = i == q ? 1.0 : 0.0;
+    for (int j = q; j < n; ++j) {
+      const double xj = X[j * n + q];
+      int i = j + 1;
+      for (; i + 3 < n; i += 4) {
+        double l[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          l[u] = W[(i + u) * n + j];
+          x[u] = X[(i + u) * n + q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) X[(i + u) * n + q] = x[u] - l[u] * xj;
+      }
+      for (; i < n; ++i) X[i * n + q] -= W[i * n + j] * xj;
+    }
+    for (int i = q + 1; i < n; ++i) LU[size_t(i) * n + q] = T(X[i * n + q]);
+    // column q of U^{-1}: e_q back-substituted through U
+    for (int i = 0; i < n; ++i) X[i * n + q] = i == q ? 1.0 : 0.0;
+    for (int j = q; j >= 0; --j) {
+      const double xj = X[j * n + q] / W[j * n + j];
+      X[j * n + q] = xj;
+      int i = 0;
+      for (; i + 3 < j; i += 4) {
+        double uu[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          uu[u] = W[(i + u) * n + j];
+          x[u] = X[(i + u) * n + q];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) X[(i + u) * n + q] = x[u] - uu[u] * xj;
+      }
+      for (; i < j; ++i) X[i * n + q] -= W[i * n + j] * xj;
+    }
+    for (int i = 0; i <= q; ++i) LU[size_t(i) * n + q] = T(X[i * n + q]);
+  }
+  if (sp) {
+    int nd = 0;
+    if (lane < n) nd = dofs[lane < nr ? perm[k + lane] : perm[lane - nr]];
+    wave_sync();
+    if (lane < n) dofs[lane] = nd;
+  }
+}
+
+// LDS doubles of the one-wave coupling scaling of a kc x kd block.
+__host__ __device__ inline int blk_scale_wave_need(int kc, int kd) { return kc * kd + kc * kc + kd * kd + (kc + 1) / 2; }
+__host__ __device__ inline bool blk_scale_wave_fits(int kc, int kd, int lds_doubles) {
+  return kc <= 64 && kd <= 64 && blk_scale_wave_need(kc, kd) <= lds_doubles;
+}
+
 // Coupling scaling: A'_{cd} = L_ss,c^{-1} P_s,c A_cd[s_c, s_d] U_ss,d^{-1},
 // with the skeleton blocks of the packed inverses of c and d (the inverse of
 // a block triangular matrix has the inverse of its trailing diagonal block as
@@ -262,7 +500,7 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
 template <typename T>
 __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_t* blk_list, int nlist,
                                                   const DSeg* segs, const int32_t* iarena, T* varena,
-                                                  DLevelDyn dyn) {
+                                                  DLevelDyn dyn, int wave_lds_doubles) {
   extern __shared__ double lds[];
   const int bi = blockIdx.x;
   if (bi >= nlist) return;
@@ -273,6 +511,7 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
   const int kc = dyn.k[c], kd = dyn.k[d];
   const int nrc = dyn.nr[c], nrd = dyn.nr[d];
   if (kc == 0 || kd == 0) return;
+  if (blk_scale_wave_fits(kc, kd, wave_lds_doubles)) return;  // taken by k_blk_scale_wave
   const bool spc = dyn.passes[c] > 0, spd = dyn.passes[d] > 0;
   const int32_t* permc = iarena + segs[c].ioff + segs[c].cap;
   const int32_t* permd = iarena + segs[d].ioff + segs[d].cap;
@@ -344,6 +583,82 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
           v += double(out[size_t(i) * kd + u]) * double(Ud[size_t(nrd + u) * nd + nrd + j]);
         out[size_t(i) * kd + j] = T(v);
       }
+  }
+}
+
+// The same coupling scaling with one wave per block (skeletons of at most
+// 64 DOFs, staging within lds_doubles): the block, the skeleton part of
+// L_c^{-1} and of U_d^{-1} are fetched into LDS with independent loads; lane
+// j then owns column j of the block.
+template <typename T>
+__global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const int32_t* blk_list, int nlist,
+                                                       const DSeg* segs, const int32_t* iarena, T* varena,
+                                                       DLevelDyn dyn, int lds_doubles) {
+  extern __shared__ double lds[];
+  const int bi = blockIdx.x;
+  if (bi >= nlist) return;
+  const int lane = threadIdx.x;
+  const DBlk B = blks[blk_list[bi]];
+  const int c = B.c, d = B.d;
+  const int kc = dyn.k[c], kd = dyn.k[d];
+  if (!blk_scale_wave_fits(kc, kd, lds_doubles)) return;
+  const int nc = dyn.n[c], nd = dyn.n[d];
+  const int nrc = dyn.nr[c], nrd = dyn.nr[d];
+  if (kc == 0 || kd == 0) return;
+  const bool spc = dyn.passes[c] > 0, spd = dyn.passes[d] > 0;
+  const int32_t* permc = iarena + segs[c].ioff + segs[c].cap;
+  const int32_t* permd = iarena + segs[d].ioff + segs[d].cap;
+  const int32_t* pivc = permc + segs[c].cap;
+  const T* A = varena + B.off;
+  T* out = varena + B.soff;
+  const T* Lc = varena + segs[c].lu_off;
+  const T* Ud = varena + segs[d].lu_off;
+  double* X = lds;                            // kc x kd
+  double* Lb = X + kc * kd;                   // kc x kc (strict lower part used)
+  double* Ub = Lb + kc * kc;                  // kd x kd (upper part used)
+  int* rm = reinterpret_cast<int*>(Ub + kd * kd);  // kc
+  // row map of the skeleton-part pivots of c: row i of P_s X is row rm[i]
+  if (lane == 0) {
+    for (int i = 0; i < kc; ++i) rm[i] = i;
+    for (int j = 0; j < kc; ++j) {
+      const int p = pivc[nrc + j] - nrc;
+      const int t = rm[j];
+      rm[j] = rm[p];
+      rm[p] = t;
+    }
+  }
+  for (int t = lane; t < kc * kc; t += 64) {
+    const int i = t / kc, u = t - i * kc;
+    Lb[t] = u < i ? double(Lc[size_t(nrc + i) * nc + nrc + u]) : 0.0;
+  }
+  for (int t = lane; t < kd * kd; t += 64) {
+    const int u = t / kd, j = t - u * kd;
+    Ub[t] = u <= j ? double(Ud[size_t(nrd + u) * nd + nrd + j]) : 0.0;
+  }
+  wave_sync();
+  for (int t = lane; t < kc * kd; t += 64) {
+    const int i = t / kd, j = t - i * kd;
+    const int r = rm[i];
+    const int si = spc ? permc[r] : r, sj = spd ? permd[j] : j;
+    X[t] = double(A[size_t(si) * nd + sj]);
+  }
+  wave_sync();
+  if (lane < kd) {
+    const int j = lane;
+    // Y = L^{-1} X (unit lower), rows descending so X[u] (u < i) is still X
+    for (int i = kc - 1; i > 0; --i) {
+      double v = X[i * kd + j];
+      for (int u = 0; u < i; ++u) v += Lb[i * kc + u] * X[u * kd + j];
+      X[i * kd + j] = v;
+    }
+  }
+  wave_sync();
+  // out = Y U^{-1}
+  for (int t = lane; t < kc * kd; t += 64) {
+    const int i = t / kd, j = t - i * kd;
+    double v = 0.0;
+    for (int u = 0; u <= j; ++u) v += X[i * kd + u] * Ub[u * kd + j];
+    out[t] = T(v);
   }
 }
 

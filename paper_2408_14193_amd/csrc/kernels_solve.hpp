@@ -372,4 +372,142 @@ __global__ __launch_bounds__(WG) void k_reduce_cols(const double* part, int nblk
   if (threadIdx.x == 0) out[j] = s;
 }
 
+// ---------------------------------------------------------------------------
+// Flexible GMRES on the correction equation A d = r (GMRES-based iterative
+// refinement): the factor is the right preconditioner, applied in the storage
+// precision; the Krylov basis, the Hessenberg matrix and the residual are
+// FP64.  Every right-hand-side column has its own Krylov space and all
+// columns advance together.  Basis blocks V, Z hold vector i of column j at
+// [(i * nrhs + j) * n].  Per-column state (ks, kstate_doubles(m) each):
+// H ((m+1) x m, column-major), the rotations cs[m], sn[m], g[m+1], y[m], and
+// the reciprocal norm of the newest basis vector.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int kstate_doubles(int m) { return (m + 1) * m + 2 * m + (m + 1) + m + 1; }
+
+// Wc = A Zc (column-major, ld n).
+__global__ __launch_bounds__(WG) void k_spmv(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                                             const double* vals, const double* Zc, double* Wc) {
+  const int j = blockIdx.y;
+  const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
+  if (v >= n) return;
+  double ax = 0.0;
+  for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) ax += vals[e] * Zc[colind[e] + j * n];
+  Wc[v + j * n] = ax;
+}
+
+// Row-block partial sums of <w_j, V_i[:, j]> for i < cnt (blockIdx.z = i) and
+// of ||w_j||^2 (blockIdx.z = cnt); reduced by k_reduce_cols over the
+// (cnt + 1) * nrhs rows of part.
+__global__ __launch_bounds__(WG) void k_kdots(int64_t n, int nrhs, const double* V, int cnt, const double* Wc,
+                                              double* part) {
+  __shared__ double red[NWAVE];
+  const int j = blockIdx.y, i = blockIdx.z;
+  const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
+  double a = 0.0;
+  if (v < n) {
+    const double w = Wc[v + j * n];
+    a = w * (i < cnt ? V[(size_t(i) * nrhs + j) * n + v] : w);
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) part[(size_t(i) * nrhs + j) * gridDim.x + blockIdx.x] = a;
+}
+
+// w_j -= sum_{i < cnt} h[i * nrhs + j] V_i[:, j].
+__global__ __launch_bounds__(WG) void k_korth(int64_t n, int nrhs, const double* V, int cnt, const double* h,
+                                              double* Wc) {
+  const int j = blockIdx.y;
+  const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
+  if (v >= n) return;
+  double acc = Wc[v + j * n];
+  for (int i = 0; i < cnt; ++i) acc -= h[i * nrhs + j] * V[(size_t(i) * nrhs + j) * n + v];
+  Wc[v + j * n] = acc;
+}
+
+// Starts a cycle: g = (beta, 0, ...), beta = sqrt(nr[j]); the reciprocal
+// norm scales the residual into the first basis vector.
+__global__ void k_kstart(int nrhs, int m, const double* nr, double* ks) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrhs) return;
+  double* K = ks + size_t(j) * kstate_doubles(m);
+  double* g = K + (m + 1) * m + 2 * m;
+  const double beta = sqrt(fmax(nr[j], 0.0));
+  for (int i = 0; i <= m; ++i) g[i] = 0.0;
+  g[0] = beta;
+  K[kstate_doubles(m) - 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+}
+
+// Vi[:, j] = Wc[:, j] times the column's reciprocal norm.
+__global__ __launch_bounds__(WG) void k_kscale(int64_t n, int nrhs, int m, const double* ks, const double* Wc,
+                                               double* Vi) {
+  const int j = blockIdx.y;
+  const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
+  if (v >= n) return;
+  Vi[size_t(j) * n + v] = Wc[v + j * n] * ks[size_t(j) * kstate_doubles(m) + kstate_doubles(m) - 1];
+}
+
+// Arnoldi column c: H[0..c][c] = h1 + h2 (two classical Gram-Schmidt
+// passes), H[c+1][c] = sqrt(||w||^2 - |h2|^2); the previous Givens rotations
+// are applied, a new one annihilates H[c+1][c] and updates g; est[j] =
+// |g[c+1]|, the residual norm of the correction equation.
+__global__ void k_karnoldi(int nrhs, int m, int c, const double* h1, const double* h2, double* ks, double* est) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrhs) return;
+  double* K = ks + size_t(j) * kstate_doubles(m);
+  double* H = K + size_t(c) * (m + 1);
+  double* cs = K + (m + 1) * m;
+  double* sn = cs + m;
+  double* g = sn + m;
+  double s2 = 0.0;
+  for (int r = 0; r <= c; ++r) {
+    const double b = h2[r * nrhs + j];
+    H[r] = h1[r * nrhs + j] + b;
+    s2 += b * b;
+  }
+  const double hn = sqrt(fmax(h2[(c + 1) * nrhs + j] - s2, 0.0));
+  H[c + 1] = hn;
+  K[kstate_doubles(m) - 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+  for (int r = 0; r < c; ++r) {
+    const double t = cs[r] * H[r] + sn[r] * H[r + 1];
+    H[r + 1] = -sn[r] * H[r] + cs[r] * H[r + 1];
+    H[r] = t;
+  }
+  const double a = H[c], b = H[c + 1];
+  const double den = sqrt(a * a + b * b);
+  const double cc = den > 0.0 ? a / den : 1.0, ss = den > 0.0 ? b / den : 0.0;
+  cs[c] = cc;
+  sn[c] = ss;
+  H[c] = den;
+  H[c + 1] = 0.0;
+  g[c + 1] = -ss * g[c];
+  g[c] = cc * g[c];
+  est[j] = fabs(g[c + 1]);
+}
+
+// y = R^{-1} g over the first k columns (R: the rotated Hessenberg matrix).
+__global__ void k_ksolve(int nrhs, int m, int k, double* ks) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrhs) return;
+  double* K = ks + size_t(j) * kstate_doubles(m);
+  const double* g = K + (m + 1) * m + 2 * m;
+  double* y = K + (m + 1) * m + 2 * m + (m + 1);
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int t = i + 1; t < k; ++t) s -= K[size_t(t) * (m + 1) + i] * y[t];
+    const double d = K[size_t(i) * (m + 1) + i];
+    y[i] = d != 0.0 ? s / d : 0.0;
+  }
+}
+
+// X[:, j] += sum_{i < k} y_i Z_i[:, j].
+__global__ __launch_bounds__(WG) void k_kupdate(int64_t n, int nrhs, int m, int k, const double* ks,
+                                                const double* Zb, double* X, int64_t ldx) {
+  const int j = blockIdx.y;
+  const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
+  if (v >= n) return;
+  const double* y = ks + size_t(j) * kstate_doubles(m) + (m + 1) * m + 2 * m + (m + 1);
+  double acc = 0.0;
+  for (int i = 0; i < k; ++i) acc += y[i] * Zb[(size_t(i) * nrhs + j) * n + v];
+  X[v + j * ldx] += acc;
+}
+
 }  // namespace spalu

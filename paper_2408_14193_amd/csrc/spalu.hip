@@ -55,6 +55,9 @@ struct LevelTabs {
   // ID launches of the level (bounds from the uncompressed sizes)
   IdTiers tiers{0, 0, 0, 8};
   bool id_b = false, id_b2 = false, id_c = false, id_old = false;
+  int max_cap = 0;  // largest uncompressed segment
+  int scale_wave_lds = 0;    // LDS doubles of the one-wave coupling scaling
+  bool scale_block = false;  // some block may need the 256-thread version
 };
 
 struct Layout {
@@ -131,6 +134,8 @@ namespace {
 constexpr size_t ID_A_MAX_BYTES = 24 * 1024;    // 64-thread groups: six or more per CU
 constexpr size_t ID_B_MAX_BYTES = 72 * 1024;    // 256-thread groups: two per CU
 constexpr size_t ID_B2_MAX_BYTES = 152 * 1024;  // 256-thread groups: one per CU
+constexpr size_t SEGLU_MAX_BYTES = 152 * 1024;   // segment LU of large segments
+constexpr int SEGLU_WAVE_MAX_N = 32;             // segments up to this size: one wave each
 
 // Which ID launches a level needs and their LDS budgets.  The sizes known
 // here (uncompressed n, coupling-row bound rcap) bound the ones the kernels
@@ -264,6 +269,18 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
     }
     pool = std::max(pool, level_pool);
     plan_id_tiers(T, prec == SPALU_FP32 ? 4 : 8);
+    for (const DSeg& D : T.segs) T.max_cap = std::max(T.max_cap, int(D.cap));
+    {
+      constexpr int SCALE_WAVE_MAX = 6144;  // 48 KB of LDS per wave at most
+      int need = 0;
+      for (int32_t b : T.scale_list) {
+        const int cc = T.segs[T.blks[b].c].cap, cd = T.segs[T.blks[b].d].cap;
+        const int w = blk_scale_wave_need(std::min(cc, 64), std::min(cd, 64));
+        if (cc > 64 || cd > 64 || w > SCALE_WAVE_MAX) T.scale_block = true;
+        need = std::max(need, std::min(w, SCALE_WAVE_MAX));
+      }
+      T.scale_wave_lds = std::max(need, 1);
+    }
   }
 
   // merge tables l -> l-1
@@ -349,6 +366,8 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
       D.hi[a] = pl.hi[a];
     }
     D.ni = int32_t(pl.interior.size());
+    if (D.ni > LEAF_MAX_NI)
+      throw std::runtime_error("leaf boxes hold more than 512 vertices; use more ND levels");
     int nb = 0;
     for (int s : pl.bsegs) {
       bsoff[i].push_back(nb);
@@ -471,13 +490,13 @@ constexpr size_t LEAF_LDS_BYTES = size_t(LEAF_LDS_DOUBLES) * 8;
 enum KId {
   K_CHECK, K_INIT, K_LEAF, K_ASM, K_ID, K_LU, K_SCALE, K_MSIZE, K_MELIM,
   K_LSOLVE_F, K_SEPLEAF, K_SSOLVE_F, K_SEPFWD, K_SEPBWD, K_SSOLVE_B, K_LSOLVE_B,
-  K_RHSIN, K_RHSOUT, K_RESID, K_REDUCE, K_APPLY, K_FEAT, K_MLP, K_COUNT
+  K_RHSIN, K_RHSOUT, K_RESID, K_REDUCE, K_APPLY, K_FEAT, K_MLP, K_SPMV, K_KRYLOV, K_COUNT
 };
 const char* const kNames[K_COUNT] = {
     "check_pattern", "init_level", "leaf_factor", "assemble_leafL", "seg_id", "seg_lu", "blk_scale",
     "merge_sizes", "merge_elim", "leaf_solve_fwd", "sep_from_leaves", "seg_solve_fwd", "sep_fwd",
     "sep_bwd", "seg_solve_bwd", "leaf_solve_bwd", "rhs_in", "rhs_out", "residual", "reduce_cols",
-    "solve_sweep_graph", "features", "mlp_rank"};
+    "solve_sweep_graph", "features", "mlp_rank", "spmv", "krylov"};
 
 struct PendingLaunch {
   int kid, level;
@@ -674,6 +693,16 @@ void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, 
       by = double(nrows) * (nnzrow * 12.0 + 8.0) + 3.0 * double(nrows) * nrhs * 8.0;
       fl = 2.0 * double(nrows) * nnzrow * nrhs;
       break;
+    case K_SPMV:
+      by = double(nrows) * (nnzrow * 12.0 + 8.0) + 2.0 * double(nrows) * nrhs * 8.0;
+      fl = 2.0 * double(nrows) * nnzrow * nrhs;
+      break;
+    case K_KRYLOV:  // level = basis vectors the launch streams (< 0: per-column scalars only)
+      if (l >= 0) {
+        by = double(nrows) * nrhs * 8.0 * (l + 2);
+        fl = 2.0 * double(nrows) * nrhs * (l + 1);
+      }
+      break;
     case K_APPLY: {
       double a, b;
       for (int kid2 : {int(K_LSOLVE_F), int(K_SEPLEAF), int(K_LSOLVE_B)}) {
@@ -847,10 +876,32 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
         LAUNCH_MORE(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var, scr, d,
                                                                             prm, tz));
     }
-    LAUNCH(K_LU, l, k_seg_lu<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, blks, iar, var, scr, d, status));
+    {
+      // segments of up to 32 DOFs: one wave each; wider ones: one block each
+      // with up to 152 KB of LDS (scratch beyond that)
+      static const bool lu_lds_ok =
+          hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_lu<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              int(SEGLU_MAX_BYTES)) == hipSuccess;
+      if (!lu_lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the segment LU kernel");
+      const int nw = std::min(SEGLU_WAVE_MAX_N, T_.max_cap);
+      LAUNCH(K_LU, l, k_seg_lu_wave<T><<<unsigned(ns), 64, size_t(2) * nw * nw * 8, st>>>(segs, ns, blks, iar, var, d,
+                                                                                       status, nw));
+      if (T_.max_cap > SEGLU_WAVE_MAX_N) {
+        const int64_t cap = T_.max_cap;
+        const int big = int(std::min<int64_t>(2 * cap * cap + (cap + 1) / 2, int64_t(SEGLU_MAX_BYTES / 8)));
+        LAUNCH_MORE(K_LU, l, k_seg_lu<T><<<unsigned(ns), WG, size_t(big) * 8, st>>>(
+            segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, INT32_MAX, big));
+      }
+    }
     if (!T_.scale_list.empty()) {
-      LAUNCH(K_SCALE, l, k_blk_scale<T><<<unsigned(T_.scale_list.size()), WG, LDS_BYTES, st>>>(
-          blks, tab<int32_t>(ws, T_.o_scale), int(T_.scale_list.size()), segs, iar, var, d));
+      // one wave per block where the skeletons are small, a block of 256
+      // threads otherwise
+      const unsigned nsc = unsigned(T_.scale_list.size());
+      LAUNCH(K_SCALE, l, k_blk_scale_wave<T><<<nsc, 64, size_t(T_.scale_wave_lds) * 8, st>>>(
+          blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds));
+      if (T_.scale_block)
+        LAUNCH_MORE(K_SCALE, l, k_blk_scale<T><<<nsc, WG, LDS_BYTES, st>>>(
+            blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds));
     }
     if (l > 1) {
       const LevelTabs& U = Y.lv[l - 1];
@@ -872,11 +923,13 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
 }
 
 struct SolveWs {
-  size_t oW, oZ, oB0, oR, oPr, oPb, oNr, oNb, bytes;
+  size_t oW, oZ, oB0, oR, oPr, oPb, oNr, oNb;
+  size_t oV, oZk, oKs, oKp, oH1, oH2, oEst;  // flexible GMRES (restart > 0)
+  size_t bytes;
   unsigned rblk;
 };
 
-SolveWs solve_layout(const spalu_factor_t* F, int nrhs) {
+SolveWs solve_layout(const spalu_factor_t* F, int nrhs, int restart = 0) {
   SolveWs s{};
   const size_t vs = F->lay->vsize;
   const size_t nn = size_t(F->n) * nrhs;
@@ -895,6 +948,16 @@ SolveWs solve_layout(const spalu_factor_t* F, int nrhs) {
   s.oPb = put(size_t(s.rblk) * nrhs * 8);
   s.oNr = put(size_t(nrhs) * 8);
   s.oNb = put(size_t(nrhs) * 8);
+  if (restart > 0) {
+    const size_t m = size_t(restart);
+    s.oV = put((m + 1) * nn * 8);
+    s.oZk = put(m * nn * 8);
+    s.oKs = put(size_t(nrhs) * kstate_doubles(restart) * 8);
+    s.oKp = put((m + 1) * nrhs * s.rblk * 8);
+    s.oH1 = put((m + 1) * nrhs * 8);
+    s.oH2 = put((m + 1) * nrhs * 8);
+    s.oEst = put(size_t(nrhs) * 8);
+  }
   s.bytes = o;
   return s;
 }
@@ -984,7 +1047,7 @@ int apply(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, const char* sw, 
 template <typename T>
 int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, double* X, int64_t ldx,
               const spalu_solve_opts& so, char* sw, double* rel_res, spalu_solve_info* info) {
-  const SolveWs s = solve_layout(F, nrhs);
+  const SolveWs s = solve_layout(F, nrhs, so.restart);
   hipStream_t st = F->stream;
   T* W = reinterpret_cast<T*>(sw + s.oW);
   T* Z = reinterpret_cast<T*>(sw + s.oZ);
@@ -1050,12 +1113,59 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     slow = (prev >= 0.0 && !(worst <= 0.9 * prev)) ? slow + 1 : 0;
     prev = worst;
     if (slow >= 3) break;
-    // correction: solve with r as right-hand side, x += M r
-    LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(R, F->n, F->n, nrhs, B0));
-    rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);
-    if (rc) return rc;
-    LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 1));
-    ++it;
+    if (so.restart == 0) {
+      // correction: solve with r as right-hand side, x += M r
+      LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(R, F->n, F->n, nrhs, B0));
+      rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);
+      if (rc) return rc;
+      LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 1));
+      ++it;
+      continue;
+    }
+    // correction by one cycle of flexible GMRES(m) on A d = r, right
+    // preconditioned by the factor; x += Z y
+    const int m = so.restart;
+    double* V = reinterpret_cast<double*>(sw + s.oV);
+    double* Zk = reinterpret_cast<double*>(sw + s.oZk);
+    double* ks = reinterpret_cast<double*>(sw + s.oKs);
+    double* kp = reinterpret_cast<double*>(sw + s.oKp);
+    double* h1 = reinterpret_cast<double*>(sw + s.oH1);
+    double* h2 = reinterpret_cast<double*>(sw + s.oH2);
+    double* est = reinterpret_cast<double*>(sw + s.oEst);
+    const dim3 vgrid(s.rblk, unsigned(nrhs));
+    const unsigned cblk = unsigned((nrhs + 63) / 64);
+    LAUNCH(K_KRYLOV, -1, k_kstart<<<cblk, 64, 0, st>>>(nrhs, m, nr, ks));
+    LAUNCH(K_KRYLOV, 0, k_kscale<<<vgrid, WG, 0, st>>>(F->n, nrhs, m, ks, R, V));
+    int kdone = 0;
+    std::vector<double> he(nrhs);
+    for (int c = 0; c < m && it < so.max_iter; ++c) {
+      double* Vc = V + size_t(c) * nn;
+      double* Zc = Zk + size_t(c) * nn;
+      LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(Vc, F->n, F->n, nrhs, B0));
+      rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);
+      if (rc) return rc;
+      LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, Zc, F->n, 0));
+      ++it;
+      LAUNCH(K_SPMV, 0, k_spmv<<<vgrid, WG, 0, st>>>(F->n, F->rowptr, F->colind, F->vals, Zc, R));
+      for (int pass = 0; pass < 2; ++pass) {
+        double* h = pass == 0 ? h1 : h2;
+        LAUNCH(K_KRYLOV, c + 1, k_kdots<<<dim3(s.rblk, unsigned(nrhs), unsigned(c + 2)), WG, 0, st>>>(F->n, nrhs, V,
+                                                                                                 c + 1, R, kp));
+        LAUNCH(K_KRYLOV, -1, k_reduce_cols<<<unsigned((c + 2) * nrhs), WG, 0, st>>>(kp, int(s.rblk),
+                                                                                  (c + 2) * nrhs, h));
+        LAUNCH(K_KRYLOV, c + 1, k_korth<<<vgrid, WG, 0, st>>>(F->n, nrhs, V, c + 1, h, R));
+      }
+      LAUNCH(K_KRYLOV, -1, k_karnoldi<<<cblk, 64, 0, st>>>(nrhs, m, c, h1, h2, ks, est));
+      LAUNCH(K_KRYLOV, 0, k_kscale<<<vgrid, WG, 0, st>>>(F->n, nrhs, m, ks, R, V + size_t(c + 1) * nn));
+      kdone = c + 1;
+      HIPCHK(hipMemcpyAsync(he.data(), est, size_t(nrhs) * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      double wk = 0.0;
+      for (int j = 0; j < nrhs; ++j) wk = std::max(wk, he[j] / bnorm[j]);
+      if (!(wk > 0.5 * so.tol)) break;  // converged (or not finite: the outer check decides)
+    }
+    LAUNCH(K_KRYLOV, -1, k_ksolve<<<cblk, 64, 0, st>>>(nrhs, m, kdone, ks));
+    LAUNCH(K_KRYLOV, kdone, k_kupdate<<<vgrid, WG, 0, st>>>(F->n, nrhs, m, kdone, ks, Zk, X, ldx));
   }
   prof_flush(F, nrhs);
   if (info) {
@@ -1522,9 +1632,11 @@ int spalu_profile_read(spalu_kernel_stat* out, int32_t max, int32_t* count) {
   return SPALU_OK;
 }
 
-int spalu_solve_workspace(const spalu_factor_t* f, int32_t nrhs, size_t* bytes) {
+int spalu_solve_workspace(const spalu_factor_t* f, int32_t nrhs, const spalu_solve_opts* opts, size_t* bytes) {
   if (!f || !bytes || nrhs < 1) return fail(SPALU_EINVAL, "bad argument");
-  *bytes = solve_layout(f, nrhs).bytes;
+  const int m = opts ? opts->restart : 0;
+  if (m < 0 || m > 32) return fail(SPALU_EINVAL, "restart must be in 0..32");
+  *bytes = solve_layout(f, nrhs, m).bytes;
   return SPALU_OK;
 }
 
@@ -1533,10 +1645,12 @@ int spalu_solve(const spalu_factor_t* f, int32_t nrhs, const double* B, int64_t 
                 double* rel_res, spalu_solve_info* info) {
   if (!f || !B || !X || !workspace || nrhs < 1) return fail(SPALU_EINVAL, "bad argument");
   if (ldb < f->n || ldx < f->n) return fail(SPALU_EINVAL, "leading dimension < n");
-  if (workspace_bytes < solve_layout(f, nrhs).bytes) return fail(SPALU_ENOMEM, "workspace too small");
-  spalu_solve_opts so{0.0, 30, 0};
+  spalu_solve_opts so{0.0, 30, 0, 0};
   if (opts) so = *opts;
   if (so.max_iter < 0) return fail(SPALU_EINVAL, "bad max_iter");
+  if (so.restart < 0 || so.restart > 32) return fail(SPALU_EINVAL, "restart must be in 0..32");
+  if (so.tol <= 0.0) so.restart = 0;
+  if (workspace_bytes < solve_layout(f, nrhs, so.restart).bytes) return fail(SPALU_ENOMEM, "workspace too small");
   if (so.tol > 0.0 && X == B) return fail(SPALU_EINVAL, "refinement needs X != B");
   spalu_factor_t* F = const_cast<spalu_factor_t*>(f);
   hipStream_t keep = F->stream;

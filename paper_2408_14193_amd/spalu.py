@@ -61,7 +61,7 @@ class FactorInfo(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("graph", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("graph", C.c_int32), ("restart", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -93,7 +93,7 @@ _lib.spalu_factor_ranks.argtypes = [P, I32P, I32P, I32P, I32P]
 _lib.spalu_factor_work.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
 _lib.spalu_factor_free.argtypes = [P]
 _lib.spalu_factor_free.restype = None
-_lib.spalu_solve_workspace.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+_lib.spalu_solve_workspace.argtypes = [P, C.c_int32, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]
 _lib.spalu_solve.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64, C.POINTER(SolveOpts), P,
                              C.c_size_t, P, C.POINTER(C.c_double), C.POINTER(SolveInfo)]
 
@@ -259,25 +259,28 @@ class Factor:
         _check(_lib.spalu_factor_work(self._h, C.byref(fl), C.byref(by)))
         return fl.value, by.value
 
-    def solve_workspace(self, nrhs):
+    def solve_workspace(self, nrhs, restart=0):
         import torch
-        if nrhs not in self._solve_ws:
+        key = (nrhs, restart)
+        if key not in self._solve_ws:
             b = C.c_size_t()
-            _check(_lib.spalu_solve_workspace(self._h, nrhs, C.byref(b)))
-            self._solve_ws[nrhs] = torch.empty(b.value, dtype=torch.uint8,
-                                               device=self.workspace.device)
-        return self._solve_ws[nrhs]
+            _check(_lib.spalu_solve_workspace(self._h, nrhs, C.byref(SolveOpts(1.0, 0, 0, int(restart))),
+                                              C.byref(b)))
+            self._solve_ws[key] = torch.empty(b.value, dtype=torch.uint8, device=self.workspace.device)
+        return self._solve_ws[key]
 
-    def solve_into(self, Bt, Xt, tol=0.0, max_iter=30, stream=None, graph=True):
+    def solve_into(self, Bt, Xt, tol=0.0, max_iter=30, stream=None, graph=True, restart=0):
         """Bt, Xt: (nrhs, n) float64 contiguous device tensors (column-major
-        n x nrhs).  Returns (info dict, per-column relative residuals)."""
+        n x nrhs).  restart > 0: flexible GMRES(restart) corrections instead
+        of classical refinement.  Returns (info dict, per-column relative
+        residuals)."""
         nrhs, n = Bt.shape
-        ws = self.solve_workspace(nrhs)
+        ws = self.solve_workspace(nrhs, restart if tol > 0 else 0)
         s = self.stream if stream is None else stream
         rr = np.zeros(nrhs, np.float64)
         info = SolveInfo()
         rc = _lib.spalu_solve(self._h, nrhs, Bt.data_ptr(), n, Xt.data_ptr(), n,
-                              C.byref(SolveOpts(float(tol), int(max_iter), 1 if graph else 0)),
+                              C.byref(SolveOpts(float(tol), int(max_iter), 1 if graph else 0, int(restart))),
                               ws.data_ptr(),
                               ws.numel(), s.cuda_stream, _ptr(rr, C.c_double), C.byref(info))
         if rc not in (OK, ENOCONV):
@@ -286,13 +289,13 @@ class Factor:
         d["converged"] = rc == OK
         return d, rr
 
-    def solve(self, B, tol=0.0, max_iter=30, graph=True):
+    def solve(self, B, tol=0.0, max_iter=30, graph=True, restart=0):
         """B: (n, nrhs) or (n,) float64 device tensor.  Returns (X, info)."""
         import torch
         vec = B.dim() == 1
         Bt = (B[None, :] if vec else B.t()).contiguous()
         Xt = torch.empty_like(Bt)
-        info, rr = self.solve_into(Bt, Xt, tol, max_iter, graph=graph)
+        info, rr = self.solve_into(Bt, Xt, tol, max_iter, graph=graph, restart=restart)
         info["rel_res"] = rr
         X = Xt[0] if vec else Xt.t()
         return X, info

@@ -134,6 +134,30 @@ def test_mixed_fp32_refines_to_fp64_solution(S, cfg):
     assert err.max() <= 1e-7
 
 
+@pytest.mark.parametrize("cfg", [1, 4])
+def test_fgmres_corrections_match_refinement(S, cfg):
+    """Flexible GMRES corrections (factor as right preconditioner) reach the
+    same tolerance in no more factor applications than classical refinement,
+    and both land on the FP64 solution."""
+    print("case fgmres cfg=%d" % cfg, flush=True)
+    import torch
+    P = make_config(cfg, side=127, nrhs=4)
+    nd, F, B = gpu_factor(S, P, eps=P.eps, precision=S.FP32)
+    Xi, ii = F.solve(B, tol=1e-10, max_iter=40, restart=0)
+    Xg, ig = F.solve(B, tol=1e-10, max_iter=40, restart=8)
+    assert ii["converged"] and ig["converged"], (ii, ig)
+    Xi, Xg = Xi.cpu().numpy(), Xg.cpu().numpy()
+    assert rel_res(P, Xg).max() <= 1e-10
+    assert ig["iterations"] <= ii["iterations"]
+    Xe = spla.spsolve(P.scipy().tocsc(), P.rhs)
+    err = np.linalg.norm(Xg - Xe, axis=0) / np.linalg.norm(Xe, axis=0)
+    print("fgmres cfg %d: %d applications (refinement %d), error vs FP64 %.2e"
+          % (cfg, ig["iterations"], ii["iterations"], err.max()))
+    assert err.max() <= 1e-7
+    with pytest.raises(S.SpaluError):
+        F.solve(B, tol=1e-10, max_iter=40, restart=33)
+
+
 @pytest.mark.parametrize("dims,L", [((7, 7), 1), ((7, 7), 2), ((7, 7), 3), ((31, 15), 0),
                                     ((47, 33), 0)])
 def test_edge_grids(S, dims, L):
