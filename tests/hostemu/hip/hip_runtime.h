@@ -1,0 +1,124 @@
+// Host emulation of the HIP subset the library uses (test infrastructure):
+// every GPU thread of a block runs as a fiber on one OS thread, blocks run
+// one after another, block and wave barriers and wave exchanges (ballot,
+// shuffles, the FP64 16x16x4 matrix instruction) are emulated, and device
+// memory is host memory.  Built with AddressSanitizer, it checks the kernels'
+// memory accesses on the CPU.
+#pragma once
+#include <ucontext.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __align__(x) alignas(x)
+#define __shared__ static
+
+struct dim3 {
+  unsigned x, y, z;
+  dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+extern dim3 threadIdx, blockIdx, blockDim, gridDim;
+
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorLaunchFailure = 2 };
+typedef void* hipStream_t;
+struct EmuEvent { double t; };
+typedef EmuEvent* hipEvent_t;
+typedef std::vector<std::function<void()>>* hipGraph_t;
+typedef std::vector<std::function<void()>>* hipGraphExec_t;
+enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyDefault };
+enum { hipStreamNonBlocking = 1 };
+enum hipStreamCaptureMode { hipStreamCaptureModeGlobal, hipStreamCaptureModeThreadLocal, hipStreamCaptureModeRelaxed };
+enum { hipHostMallocDefault = 0 };
+enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize };
+
+namespace emu {
+void block_barrier();
+void wave_barrier();
+uint64_t ballot(bool p);
+double shfl_d(double v, int src);
+int shfl_i(int v, int src);
+void* dyn_smem();
+void run_grid(dim3 g, dim3 b, size_t shmem, const std::function<void()>& body);
+bool capturing();
+void record(std::function<void()> f);
+typedef double d4 __attribute__((ext_vector_type(4)));
+d4 mfma_f64_16x16x4(double a, double b, d4 c);
+
+template <typename K>
+struct Launch {
+  K k;
+  dim3 g, b;
+  size_t sh;
+  template <typename... A>
+  void operator()(A... args) {
+    K kk = k;
+    dim3 gg = g, bb = b;
+    size_t s = sh;
+    auto f = [=]() { run_grid(gg, bb, s, [=]() { kk(args...); }); };
+    if (capturing())
+      record(f);
+    else
+      f();
+  }
+};
+template <typename K>
+Launch<K> launch(K k, dim3 g, dim3 b, size_t sh = 0, hipStream_t = nullptr) {
+  return Launch<K>{k, g, b, sh};
+}
+}  // namespace emu
+
+inline void __syncthreads() { emu::block_barrier(); }
+inline void emu_amdgcn_wave_barrier() { emu::wave_barrier(); }
+inline void emu_amdgcn_fence(int, const char*) {}
+inline uint64_t __ballot(bool p) { return emu::ballot(p); }
+inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
+inline int __ffsll(unsigned long long x) { return __builtin_ffsll((long long)x); }
+inline double __shfl_xor(double v, int m, int = 64) {
+  return emu::shfl_d(v, (int(threadIdx.x) & 63) ^ m);
+}
+inline int __shfl_xor(int v, int m, int = 64) { return emu::shfl_i(v, (int(threadIdx.x) & 63) ^ m); }
+inline double __shfl(double v, int src, int = 64) { return emu::shfl_d(v, src & 63); }
+inline int __shfl(int v, int src, int = 64) { return emu::shfl_i(v, src & 63); }
+inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
+inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
+inline int atomicOr(int* p, int v) { int o = *p; *p |= v; return o; }
+inline emu::d4 emu_amdgcn_mfma_f64_16x16x4f64(double a, double b, emu::d4 c, int, int, int) {
+  return emu::mfma_f64_16x16x4(a, b, c);
+}
+
+// ---- runtime API ----
+hipError_t hipGetLastError();
+const char* hipGetErrorString(hipError_t);
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t = nullptr);
+hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind);
+hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t = nullptr);
+hipError_t hipStreamSynchronize(hipStream_t);
+hipError_t hipStreamCreateWithFlags(hipStream_t*, unsigned);
+hipError_t hipStreamDestroy(hipStream_t);
+hipError_t hipEventCreate(hipEvent_t*);
+hipError_t hipEventDestroy(hipEvent_t);
+hipError_t hipEventRecord(hipEvent_t, hipStream_t = nullptr);
+hipError_t hipEventSynchronize(hipEvent_t);
+hipError_t hipEventElapsedTime(float*, hipEvent_t, hipEvent_t);
+hipError_t hipHostMalloc(void**, size_t, unsigned = 0);
+hipError_t hipHostFree(void*);
+hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int);
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode);
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t*);
+hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, void*, char*, size_t);
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
+hipError_t hipGraphExecDestroy(hipGraphExec_t);
+hipError_t hipGraphDestroy(hipGraph_t);
+hipError_t hipMemcpy2DAsync(void* d, size_t dp, const void* s, size_t spitch, size_t w, size_t h, hipMemcpyKind,
+                            hipStream_t = nullptr);
