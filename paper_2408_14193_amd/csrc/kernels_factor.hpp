@@ -28,6 +28,23 @@ __device__ inline double csr_at(const int64_t* rowptr, const int32_t* colind, co
   return 0.0;
 }
 
+// Local index in a leaf box of grid vertex w, a stencil neighbour of the box
+// vertex u with local coordinates (ix, iy, iz) and local index i; -1 when w
+// lies outside the box.  The box is w0 x w1 x w2 and its local index runs x
+// fastest; the direction of w follows from w - u alone.
+__device__ inline int box_nbr(const GridGeom& g, int w0, int w1, int w2, int ix, int iy, int iz, int i, int u,
+                              int w) {
+  const int d = w - u, sxy = g.nx * g.ny;
+  if (d == 0) return i;
+  if (g.nx > 1 && d == 1) return ix + 1 < w0 ? i + 1 : -1;
+  if (g.nx > 1 && d == -1) return ix > 0 ? i - 1 : -1;
+  if (g.ny > 1 && d == g.nx) return iy + 1 < w1 ? i + w0 : -1;
+  if (g.ny > 1 && d == -g.nx) return iy > 0 ? i - w0 : -1;
+  if (g.nz > 1 && d == sxy) return iz + 1 < w2 ? i + w0 * w1 : -1;
+  if (g.nz > 1 && d == -sxy) return iz > 0 ? i - w0 * w1 : -1;
+  return -1;
+}
+
 // Every CSR entry must lie on the stencil (|dx|+|dy|+|dz| <= 1) and columns
 // must ascend; flags bit 1 otherwise.
 __global__ void k_check_pattern(GridGeom g, int64_t n, const int64_t* rowptr, const int32_t* colind,
@@ -177,9 +194,10 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
     for (int q = 0; q < ni; ++q) acc += A[i * ni + q] * B[q * nb + c];
     X[t] = acc;
   }
-  // A_II^{-1} (the solve applies it as a product)
+  // A_II^{-1}, stored transposed (entry (i, q) at q * ni + i) so that the
+  // solve's lanes, one per row, read consecutive addresses
   T* LUo = varena + L.lu_off;
-  for (int t = tid; t < ni * ni; t += WG) LUo[t] = T(A[t]);
+  for (int t = tid; t < ni * ni; t += WG) LUo[t] = T(A[(t % ni) * ni + t / ni]);
   __syncthreads();
   // S = A_BI X (boundary rows, sparse)
   T* S = varena + L.s_off;
@@ -198,6 +216,171 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
       }
     }
     S[t] = T(acc);
+  }
+}
+
+// One wave per leaf of at most 64 interior vertices: Gauss-Jordan
+// elimination with partial pivoting of [A_II | A_IB], lane i holding row i
+// in registers, so that the sweep needs no barriers.  Rows are never
+// swapped and the pivot row of step k is not divided by its pivot d_k during
+// the sweep (the multipliers carry 1/d_k); each row is divided by the pivot
+// of the step that chose it at the end.  The pivot column of every step sits
+// in register slot 0: after the update the row moves down one slot and the
+// new column of the inverse enters at the last one, so after ni steps slots
+// [0, nb) hold A_II^{-1} A_IB and slots [WC - ni, WC) the columns of the
+// inverse in pivot order.  Row r of the results sits in the lane chosen at
+// step r, and column k of the inverse there belongs to vertex piv[k].
+constexpr int LEAF_WAVE_MAX_NI = 64;
+
+// Register slots per lane for a leaf (0: the leaf needs the block kernel).
+__host__ __device__ inline int leaf_wave_slots(int ni, int nb) {
+  const int w = ni + nb;
+  if (ni > LEAF_WAVE_MAX_NI) return 0;
+  return w <= 48 ? 48 : w <= 80 ? 80 : w <= 96 ? 96 : 0;
+}
+
+// Dynamic LDS bytes of the one-wave kernel: the broadcast pivot row, X, the
+// boundary couplings, the pivot order and the boundary list.
+__host__ __device__ inline int leaf_wave_lds_bytes(int wc, int ni, int nb) {
+  return 8 * (wc + ni * nb + nb) + 4 * (ni + 2 * nb);
+}
+
+template <typename T, int WC>
+__global__ __launch_bounds__(64) void k_leaf_factor_wave(const DLeaf* leaves, int nleaf, GridGeom g,
+                                                         const int64_t* rowptr, const int32_t* colind,
+                                                         const double* vals, int32_t* iarena, T* varena,
+                                                         int* status) {
+  extern __shared__ double lds[];
+  const int lf = blockIdx.x;
+  if (lf >= nleaf) return;
+  const DLeaf L = leaves[lf];
+  const int ni = L.ni, nb = L.nb, lane = threadIdx.x;
+  const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1, w2 = L.hi[2] - L.lo[2] + 1;
+  double* prow = lds;                                  // pivot row of the step
+  double* X = lds + WC;                                // A_II^{-1} A_IB, ni x nb
+  double* ba = X + ni * nb;                            // a_bi of boundary vertex b
+  int* pord = reinterpret_cast<int*>(ba + nb);         // pivot vertex of step k
+  int* bvl = pord + ni;                                // boundary vertices
+  int* bi = bvl + nb;                                  // its interior neighbour i (-1: none)
+  const int32_t* bverts = iarena + L.ioff;
+  int32_t* piv = iarena + L.ioff + nb;
+  // boundary vertex b: its coupling a_bi into the box (a vertex outside a
+  // box is a stencil neighbour of at most one box vertex)
+  for (int b = lane; b < nb; b += 64) {
+    const int ub = bverts[b];
+    bvl[b] = ub;
+    int cb[3];
+    vcoords(g, ub, cb);
+    const int bx = cb[0] - L.lo[0], by = cb[1] - L.lo[1], bz = cb[2] - L.lo[2];
+    int ib = -1;
+    double a = 0.0;
+    for (int64_t e = rowptr[ub]; e < rowptr[ub + 1]; ++e) {
+      const int d = colind[e] - ub;
+      int jx = bx, jy = by, jz = bz;
+      if (g.nx > 1 && (d == 1 || d == -1)) jx += d;
+      else if (g.ny > 1 && (d == g.nx || d == -g.nx)) jy += d / g.nx;
+      else if (g.nz > 1 && (d == g.nx * g.ny || d == -g.nx * g.ny)) jz += d / (g.nx * g.ny);
+      else continue;
+      if (jx >= 0 && jx < w0 && jy >= 0 && jy < w1 && jz >= 0 && jz < w2) {
+        ib = jx + w0 * (jy + w1 * jz);
+        a = vals[e];
+      }
+    }
+    bi[b] = ib;
+    ba[b] = a;
+  }
+  wave_sync();
+  // lane i assembles row i of [A_II | A_IB]
+  double r[WC];
+#pragma unroll
+  for (int s = 0; s < WC; ++s) r[s] = 0.0;
+  if (lane < ni) {
+    const int ix = lane % w0, iy = (lane / w0) % w1, iz = lane / (w0 * w1);
+    const int u = (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz));
+    const int64_t e0 = rowptr[u], e1 = rowptr[u + 1];
+    for (int64_t e = e0; e < e1; ++e) {
+      const int w = colind[e];
+      int slot = box_nbr(g, w0, w1, w2, ix, iy, iz, lane, u, w);
+      if (slot < 0) {
+        for (int b = 0; b < nb; ++b)
+          if (bvl[b] == w) {
+            slot = ni + b;
+            break;
+          }
+      }
+      const double v = vals[e];
+#pragma unroll
+      for (int s = 0; s < WC; ++s) r[s] = s == slot ? v : r[s];
+    }
+  }
+  bool used = lane >= ni, singular = false;
+  int my_step = 0;
+  double my_d = 1.0;
+  for (int k = 0; k < ni; ++k) {
+    double a = used ? -1.0 : fabs(r[0]);
+    int ia = used ? (1 << 30) : lane;
+    wave_argmax(a, ia);
+    int p = __builtin_amdgcn_readfirstlane(ia);
+    if (p >= ni) {  // no comparable entry (NaN): take the first unused row
+      p = __ffsll((unsigned long long)__ballot(!used)) - 1;
+      singular = true;
+    }
+    wave_sync();
+    if (lane == p) {
+#pragma unroll
+      for (int s = 0; s < WC; ++s) prow[s] = r[s];
+    }
+    wave_sync();
+    const double d = prow[0];
+    if (!(d != 0.0)) singular = true;
+    const double inv_d = d != 0.0 ? 1.0 / d : 0.0;
+    const bool is_p = lane == p;
+    const double m = is_p ? 0.0 : r[0] * inv_d;
+    // in chunks of 16 slots; the empty asm statements pin each chunk's
+    // results before the next chunk's loads, so that the pivot row is never
+    // held in registers whole
+#pragma unroll
+    for (int s0 = 1; s0 < WC; s0 += 16) {
+#pragma unroll
+      for (int s = s0; s < s0 + 16 && s < WC; ++s) r[s - 1] = fma(-m, prow[s], r[s]);
+#pragma unroll
+      for (int s = s0; s < s0 + 16 && s < WC; ++s) asm volatile("" : "+v"(r[s - 1])::"memory");
+    }
+    r[WC - 1] = is_p ? 1.0 : -m;
+    if (is_p) {
+      used = true;
+      my_step = k;
+      my_d = d;
+    }
+    if (lane == 0) pord[k] = p;
+  }
+  wave_sync();
+  if (singular && lane == 0) atomicOr(status, 1);
+  for (int k = lane; k < ni; k += 64) piv[k] = pord[k];
+  if (lane < ni) {
+    const double sc = 1.0 / my_d;
+#pragma unroll
+    for (int s = 0; s < WC; ++s) r[s] *= sc;
+  }
+  // the inverse, transposed (entry (i, q) at q * ni + i), and X to LDS
+  T* Ainv = varena + L.lu_off;
+#pragma unroll
+  for (int s = 0; s < WC; ++s) {
+    const int k = s - (WC - ni);
+    if (k >= 0) {
+      const int q = pord[k];
+      if (lane < ni) Ainv[size_t(q) * ni + my_step] = T(r[s]);
+    } else if (s < nb) {
+      if (lane < ni) X[my_step * nb + s] = r[s];
+    }
+  }
+  wave_sync();
+  // S = A_BI X, one boundary row at a time, lane = column
+  T* S = varena + L.s_off;
+  for (int b = 0; b < nb; ++b) {
+    const int ib = bi[b];
+    const double a = ba[b];
+    for (int c = lane; c < nb; c += 64) S[size_t(b) * nb + c] = T(ib >= 0 ? a * X[ib * nb + c] : 0.0);
   }
 }
 

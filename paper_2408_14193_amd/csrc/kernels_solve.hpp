@@ -20,12 +20,6 @@ __global__ void k_rhs_in(const double* B, int64_t ldb, int64_t n, int nrhs, T* W
 }
 
 template <typename T>
-__global__ void k_copy(const T* src, T* dst, int64_t n) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < n) dst[t] = src[t];
-}
-
-template <typename T>
 __global__ void k_rhs_out(const T* W, int64_t n, int nrhs, double* X, int64_t ldx, int accumulate) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= n * nrhs) return;
@@ -39,7 +33,8 @@ __global__ void k_rhs_out(const T* W, int64_t n, int nrhs, double* X, int64_t ld
 
 // Leaf interiors: Z_I = A_II^{-1} W_I (forward) or
 // W_I = A_II^{-1} (B_I - A_IB W_B) (backward), with the stored inverse
-// staged in LDS (one coalesced load) and the right-hand sides beside it.
+// (transposed: entry (i, q) at q * ni + i) staged in LDS (one coalesced
+// load) and the right-hand sides beside it.
 template <typename T, bool BACKWARD>
 __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nleaf, GridGeom g,
                                                    const int64_t* rowptr, const int32_t* colind,
@@ -69,7 +64,7 @@ __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nlea
       const int u = (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz));
       double v;
       if (!BACKWARD) {
-        v = double(W[size_t(u) * nrhs + j0 + j]);
+        v = double(B0[size_t(u) * nrhs + j0 + j]);
       } else {
         v = double(B0[size_t(u) * nrhs + j0 + j]);
         for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
@@ -88,11 +83,9 @@ __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nlea
       const int i = t / nc, j = t % nc;
       double acc = 0.0;
       if (stage) {
-        const double* arow = sA + i * ni;
-        for (int q = 0; q < ni; ++q) acc += arow[q] * X[q * nc + j];
+        for (int q = 0; q < ni; ++q) acc += sA[q * ni + i] * X[q * nc + j];
       } else {
-        const T* arow = Ai + size_t(i) * ni;
-        for (int q = 0; q < ni; ++q) acc += double(arow[q]) * X[q * nc + j];
+        for (int q = 0; q < ni; ++q) acc += double(Ai[size_t(q) * ni + i]) * X[q * nc + j];
       }
       const int ix = i % w0, iy = (i / w0) % w1, iz = i / (w0 * w1);
       const int u = (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz));
@@ -105,21 +98,93 @@ __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nlea
   }
 }
 
-// W_u -= sum over leaf-interior neighbours i of a_ui Z_i, for separator u.
+// The same for leaves of at most 64 interior vertices, one wave each: lane q
+// gathers the right-hand sides of vertex q (a chunk of 16, zero beyond the
+// last one) into LDS, then lane i forms row i of A_II^{-1} times the chunk,
+// reading the transposed inverse from global memory (consecutive lanes,
+// consecutive addresses).
+constexpr int LEAF_SOLVE_CHUNK = 16;
+
+__host__ __device__ inline int leaf_solve_wave_lds_bytes(int ni) { return 8 * LEAF_SOLVE_CHUNK * ni; }
+
+template <typename T, bool BACKWARD>
+__global__ __launch_bounds__(64) void k_leaf_solve_wave(const DLeaf* leaves, int nleaf, GridGeom g,
+                                                        const int64_t* rowptr, const int32_t* colind,
+                                                        const double* vals, const T* varena, const T* B0,
+                                                        T* W, T* Z, int nrhs) {
+  extern __shared__ double lds[];
+  const int lf = blockIdx.x;
+  if (lf >= nleaf) return;
+  const DLeaf L = leaves[lf];
+  const int ni = L.ni, lane = threadIdx.x;
+  if (ni == 0) return;
+  const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1, w2 = L.hi[2] - L.lo[2] + 1;
+  double* X = lds;
+  const T* Ai = varena + L.lu_off;
+  const bool act = lane < ni;
+  const int ix = lane % w0, iy = (lane / w0) % w1, iz = lane / (w0 * w1);
+  const int u = act ? (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz)) : 0;
+  T* dst = BACKWARD ? W : Z;
+  for (int j0 = 0; j0 < nrhs; j0 += LEAF_SOLVE_CHUNK) {
+    const int nc = nrhs - j0 < LEAF_SOLVE_CHUNK ? nrhs - j0 : LEAF_SOLVE_CHUNK;
+    if (act) {
+      double v[LEAF_SOLVE_CHUNK];
+      const T* src = B0 + size_t(u) * nrhs + j0;
+#pragma unroll
+      for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) v[j] = j < nc ? double(src[j]) : 0.0;
+      if (BACKWARD) {
+        for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+          const int w = colind[e];
+          if (box_nbr(g, w0, w1, w2, ix, iy, iz, lane, u, w) >= 0) continue;
+          const double a = vals[e];
+          const T* ws = W + size_t(w) * nrhs + j0;
+#pragma unroll
+          for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j)
+            if (j < nc) v[j] -= a * double(ws[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) X[lane * LEAF_SOLVE_CHUNK + j] = v[j];
+    }
+    wave_sync();
+    if (act) {
+      double acc[LEAF_SOLVE_CHUNK];
+#pragma unroll
+      for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) acc[j] = 0.0;
+#pragma unroll 4
+      for (int q = 0; q < ni; ++q) {
+        const double a = double(Ai[size_t(q) * ni + lane]);
+        const double* xq = X + q * LEAF_SOLVE_CHUNK;
+#pragma unroll
+        for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) acc[j] = fma(a, xq[j], acc[j]);
+      }
+      T* out = dst + size_t(u) * nrhs + j0;
+#pragma unroll
+      for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j)
+        if (j < nc) out[j] = T(acc[j]);
+    }
+    wave_sync();
+  }
+}
+
+// W_u = B_u - sum over leaf-interior neighbours i of a_ui Z_i, for every
+// separator vertex u (the list sepv); leaf interiors of W are written only by
+// the backward leaf solve.
 template <typename T>
-__global__ void k_sep_from_leaves(int64_t n, const int8_t* seplev, const int64_t* rowptr,
-                                  const int32_t* colind, const double* vals, const T* Z, T* W, int nrhs) {
+__global__ void k_sep_from_leaves(int64_t nsep, const int32_t* sepv, const int8_t* seplev,
+                                  const int64_t* rowptr, const int32_t* colind, const double* vals,
+                                  const T* B0, const T* Z, T* W, int nrhs) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n * nrhs) return;
-  const int64_t u = t / nrhs;
+  if (t >= nsep * nrhs) return;
+  const int u = sepv[t / nrhs];
   const int j = int(t % nrhs);
-  if (seplev[u] == 0) return;
   double acc = 0.0;
   for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
     const int w = colind[e];
     if (seplev[w] == 0) acc += vals[e] * double(Z[size_t(w) * nrhs + j]);
   }
-  W[t] = T(double(W[t]) - acc);
+  const size_t idx = size_t(u) * nrhs + j;
+  W[idx] = T(double(B0[idx]) - acc);
 }
 
 // Per segment of level l: forward (U_T, then P and L^{-1}) or backward

@@ -68,12 +68,16 @@ struct Layout {
   std::vector<int32_t> lc_ptr;
   std::vector<DLeafContrib> lc;
   std::vector<int32_t> vptrL, vertsL;
-  size_t o_leaves = 0, o_lc_ptr = 0, o_lc = 0, o_vptrL = 0, o_vertsL = 0, o_seplev = 0;
+  size_t o_leaves = 0, o_lc_ptr = 0, o_lc = 0, o_vptrL = 0, o_vertsL = 0, o_seplev = 0, o_sepv = 0;
+  std::vector<int32_t> sepv;  // separator vertices, ascending
   size_t blob_bytes = 0;
   size_t o_iarena = 0, n_iarena = 0;
   size_t o_varena = 0, n_varena = 0;
   size_t o_scratch = 0, n_scratch = 0;
   size_t leaf_scr_stride = 0;
+  int leaf_wc = 0;                 // register slots of the one-wave leaf kernels (0: block kernels)
+  int leaf_wave_lds = 0;           // their dynamic LDS bytes (factor)
+  int leaf_ni_max = 0;
   size_t o_status = 0;
   size_t o_feats = 0, o_hinit = 0;  // rank predictor: features, start samples
   size_t bytes = 0;
@@ -190,7 +194,10 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
   const int L = P.L;
   Y.dim = P.dim;
   Y.L = L;
-  for (int8_t sl : P.seplev) Y.nsep_verts += sl > 0 ? 1.0 : 0.0;
+  Y.sepv.clear();
+  for (int64_t v = 0; v < int64_t(P.seplev.size()); ++v)
+    if (P.seplev[v] > 0) Y.sepv.push_back(int32_t(v));
+  Y.nsep_verts = double(Y.sepv.size());
   Y.lv.assign(L + 1, LevelTabs());
   size_t iar = 0, var = 0, pool = 0;
   Y.seg_base.assign(L + 2, 0);
@@ -382,6 +389,25 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
     var += size_t(nb) * nb;
     leaf_need = std::max(leaf_need, size_t(leaf_lds_need(D.ni, nb)));
   }
+  // one wave per leaf when every leaf fits its register row
+  Y.leaf_wc = 0;
+  Y.leaf_wave_lds = 0;
+  Y.leaf_ni_max = 0;
+  {
+    int wc = 0;
+    bool all = !Y.leaves.empty();
+    for (const DLeaf& D : Y.leaves) {
+      const int w = leaf_wave_slots(D.ni, D.nb);
+      if (w == 0) all = false;
+      wc = std::max(wc, w);
+      Y.leaf_ni_max = std::max(Y.leaf_ni_max, int(D.ni));
+    }
+    if (all) {
+      Y.leaf_wc = wc;
+      for (const DLeaf& D : Y.leaves)
+        Y.leaf_wave_lds = std::max(Y.leaf_wave_lds, leaf_wave_lds_bytes(wc, D.ni, D.nb));
+    }
+  }
   Y.leaf_i0 = Y.leaves.empty() ? iar : size_t(Y.leaves[0].ioff);
   Y.leaf_i1 = iar;
   if (leaf_need > size_t(LEAF_LDS_DOUBLES)) {
@@ -441,6 +467,7 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
   Y.o_vptrL = put(Y.vptrL.size() * 4);
   Y.o_vertsL = put(Y.vertsL.size() * 4);
   Y.o_seplev = put(size_t(P.N));
+  Y.o_sepv = put(Y.sepv.size() * 4);
   Y.blob_bytes = o;
   // dynamic per-level arrays (6 ints per segment)
   for (int l = 1; l <= L; ++l) Y.lv[l].o_dyn = put(6 * Y.lv[l].segs.size() * 4);
@@ -810,9 +837,24 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     LAUNCH(K_INIT, L, k_init_level<<<unsigned(TL.segs.size()), 64, 0, st>>>(tab<DSeg>(ws, TL.o_segs), int(TL.segs.size()),
                                                            tab<int32_t>(ws, Y.o_vptrL),
                                                            tab<int32_t>(ws, Y.o_vertsL), iar, dL));
-    LAUNCH(K_LEAF, L, k_leaf_factor<T><<<unsigned(Y.leaves.size()), WG, LEAF_LDS_BYTES, st>>>(
-        tab<DLeaf>(ws, Y.o_leaves), int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var,
-        scr, int64_t(Y.leaf_scr_stride), status));
+    {
+      const DLeaf* lt = tab<DLeaf>(ws, Y.o_leaves);
+      const unsigned nl = unsigned(Y.leaves.size());
+      const size_t wl = size_t(Y.leaf_wave_lds);
+      if (Y.leaf_wc == 48) {
+        LAUNCH(K_LEAF, L, k_leaf_factor_wave<T, 48><<<nl, 64, wl, st>>>(lt, int(nl), F->g, F->rowptr, F->colind,
+                                                                    F->vals, iar, var, status));
+      } else if (Y.leaf_wc == 80) {
+        LAUNCH(K_LEAF, L, k_leaf_factor_wave<T, 80><<<nl, 64, wl, st>>>(lt, int(nl), F->g, F->rowptr, F->colind,
+                                                                    F->vals, iar, var, status));
+      } else if (Y.leaf_wc == 96) {
+        LAUNCH(K_LEAF, L, k_leaf_factor_wave<T, 96><<<nl, 64, wl, st>>>(lt, int(nl), F->g, F->rowptr, F->colind,
+                                                                    F->vals, iar, var, status));
+      } else {
+        LAUNCH(K_LEAF, L, k_leaf_factor<T><<<nl, WG, LEAF_LDS_BYTES, st>>>(
+            lt, int(nl), F->g, F->rowptr, F->colind, F->vals, iar, var, scr, int64_t(Y.leaf_scr_stride), status));
+      }
+    }
     LAUNCH(K_ASM, L, k_assemble_leafL<T><<<unsigned(TL.blks.size()), WG, 0, st>>>(
         tab<DBlk>(ws, TL.o_blks), int(TL.blks.size()), tab<DSeg>(ws, TL.o_segs), iar, dL,
         tab<int32_t>(ws, Y.o_lc_ptr), tab<DLeafContrib>(ws, Y.o_lc), tab<DLeaf>(ws, Y.o_leaves),
@@ -971,14 +1013,20 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
   const int32_t* iar = reinterpret_cast<const int32_t*>(ws + Y.o_iarena);
   const T* var = reinterpret_cast<const T*>(ws + Y.o_varena);
   const int L = P.L;
-  const size_t nn = size_t(F->n) * nrhs;
-  k_copy<T><<<nblocks(int64_t(nn)), WG, 0, st>>>(B0, W, int64_t(nn));
-  HIPCHK(hipGetLastError());
   const DLeaf* leaves = tab<DLeaf>(ws, Y.o_leaves);
-  LAUNCH(K_LSOLVE_F, 0, k_leaf_solve<T, false><<<unsigned(Y.leaves.size()), WG, LDS_BYTES, st>>>(
-      leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var, B0, W, Z, nrhs));
-  LAUNCH(K_SEPLEAF, 0, k_sep_from_leaves<T><<<nblocks(int64_t(nn)), WG, 0, st>>>(F->n, tab<int8_t>(ws, Y.o_seplev), F->rowptr,
-                                                             F->colind, F->vals, Z, W, nrhs));
+  const bool wave_leaf = Y.leaf_ni_max <= LEAF_WAVE_MAX_NI;
+  const size_t lsl = size_t(leaf_solve_wave_lds_bytes(Y.leaf_ni_max));
+  if (wave_leaf) {
+    LAUNCH(K_LSOLVE_F, 0, k_leaf_solve_wave<T, false><<<unsigned(Y.leaves.size()), 64, lsl, st>>>(
+        leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, var, B0, W, Z, nrhs));
+  } else {
+    LAUNCH(K_LSOLVE_F, 0, k_leaf_solve<T, false><<<unsigned(Y.leaves.size()), WG, LDS_BYTES, st>>>(
+        leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var, B0, W, Z, nrhs));
+  }
+  const int64_t nsep = int64_t(Y.sepv.size());
+  LAUNCH(K_SEPLEAF, 0, k_sep_from_leaves<T><<<nblocks(nsep * nrhs), WG, 0, st>>>(
+      nsep, tab<int32_t>(ws, Y.o_sepv), tab<int8_t>(ws, Y.o_seplev), F->rowptr, F->colind, F->vals, B0, Z, W,
+      nrhs));
   for (int l = L; l >= 1; --l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
@@ -997,8 +1045,13 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
     LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, LDS_BYTES, st>>>(tab<DSeg>(ws, T_.o_segs), ns, iar, var, d, W,
                                                               nrhs));
   }
-  LAUNCH(K_LSOLVE_B, 0, k_leaf_solve<T, true><<<unsigned(Y.leaves.size()), WG, LDS_BYTES, st>>>(
-      leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var, B0, W, Z, nrhs));
+  if (wave_leaf) {
+    LAUNCH(K_LSOLVE_B, 0, k_leaf_solve_wave<T, true><<<unsigned(Y.leaves.size()), 64, lsl, st>>>(
+        leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, var, B0, W, Z, nrhs));
+  } else {
+    LAUNCH(K_LSOLVE_B, 0, k_leaf_solve<T, true><<<unsigned(Y.leaves.size()), WG, LDS_BYTES, st>>>(
+        leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, iar, var, B0, W, Z, nrhs));
+  }
   return SPALU_OK;
 }
 
@@ -1221,6 +1274,7 @@ static int build_image(const Plan& P, Layout* Y, double rho) {
   cp(Y->o_vptrL, Y->vptrL.data(), Y->vptrL.size() * 4);
   cp(Y->o_vertsL, Y->vertsL.data(), Y->vertsL.size() * 4);
   cp(Y->o_seplev, P.seplev.data(), size_t(P.N));
+  cp(Y->o_sepv, Y->sepv.data(), Y->sepv.size() * 4);
   // leaf boundary lists (then an unused piv range) in the int-arena layout
   int32_t* li = reinterpret_cast<int32_t*>(blob + Y->blob_bytes);
   std::memset(li, 0, (Y->leaf_i1 - Y->leaf_i0) * 4);

@@ -84,6 +84,10 @@ inline void emu_amdgcn_fence(int, const char*) {}
 inline uint64_t __ballot(bool p) { return emu::ballot(p); }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline int __ffsll(unsigned long long x) { return __builtin_ffsll((long long)x); }
+inline int emu_amdgcn_readfirstlane(int v) {
+  const uint64_t m = emu::ballot(true);
+  return emu::shfl_i(v, __builtin_ffsll((long long)m) - 1);
+}
 inline double __shfl_xor(double v, int m, int = 64) {
   return emu::shfl_d(v, (int(threadIdx.x) & 63) ^ m);
 }
