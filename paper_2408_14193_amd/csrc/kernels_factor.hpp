@@ -508,8 +508,19 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   int* pv = pv_lds ? reinterpret_cast<int*>(lds + need) : piv;
   if (block_lu_window(W, n, n, sp ? nr : 0, pv, &s_piv)) atomicOr(status, 1);
   __syncthreads();
-  if (pv_lds)
-    for (int j = tid; j < n; j += WG) piv[j] = pv[j];
+  // stored form of the interchanges: the composed row map (row i of P X is
+  // row piv[i] of X), each entry traced back through the interchanges
+  for (int i = tid; i < n; i += WG) {
+    int pos = i;
+    for (int r = n - 1; r >= 0; --r) {
+      const int p = pv[r];
+      pos = pos == r ? p : pos == p ? r : pos;
+    }
+    tmp[i] = pos;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += WG) piv[i] = tmp[i];
+  __syncthreads();
   // packed inverses: strictly lower part of L^{-1} (unit diagonal implied)
   // and upper part of U^{-1}, so every later application is a product
   T* LU = varena + S.lu_off;
@@ -577,6 +588,7 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
   // LU with partial pivoting; steps j < nr search rows [j, nr), later steps [j, n)
   const int split = sp ? nr : 0;
   bool singular = false;
+  int rm = lane;  // composed row map of the interchanges so far
   for (int j = 0; j < n; ++j) {
     const int hi = j < split ? split : n;
     double bv = -1.0;
@@ -586,8 +598,11 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
       bi = lane;
     }
     wave_argmax(bv, bi);
-    const int p = bi < n ? bi : j;
-    if (lane == 0) piv[j] = p;
+    const int p = __builtin_amdgcn_readfirstlane(bi < n ? bi : j);
+    if (p != j) {
+      const int a = __builtin_amdgcn_readlane(rm, j), b = __builtin_amdgcn_readlane(rm, p);
+      rm = lane == j ? b : lane == p ? a : rm;
+    }
     if (p != j && lane < n) {
       const double t = W[j * n + lane];
       W[j * n + lane] = W[p * n + lane];
@@ -619,6 +634,7 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
     wave_sync();
   }
   if (singular && lane == 0) atomicOr(status, 1);
+  if (lane < n) piv[lane] = rm;
   // packed inverses, one column per lane: strictly lower L^{-1} (unit
   // diagonal implied) and upper U^{-1}
   T* LU = varena + S.lu_off;
@@ -706,15 +722,7 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
   // row map of the skeleton-part pivots of c: row i of P_s X is row rm[i]
   __shared__ int s_rm[1024];
   int* rm = kc <= 1024 ? s_rm : reinterpret_cast<int*>(lds);
-  if (tid == 0) {
-    for (int i = 0; i < kc; ++i) rm[i] = i;
-    for (int j = 0; j < kc; ++j) {
-      const int p = pivc[nrc + j] - nrc;
-      const int t = rm[j];
-      rm[j] = rm[p];
-      rm[p] = t;
-    }
-  }
+  for (int i = tid; i < kc; i += WG) rm[i] = pivc[nrc + i] - nrc;
   __syncthreads();
   const bool inlds = 2 * size_t(kc) * kd <= LDS_DOUBLES && kc <= 1024;
   if (inlds) {
@@ -801,15 +809,7 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
   double* Ub = Lb + kc * kc;                  // kd x kd (upper part used)
   int* rm = reinterpret_cast<int*>(Ub + kd * kd);  // kc
   // row map of the skeleton-part pivots of c: row i of P_s X is row rm[i]
-  if (lane == 0) {
-    for (int i = 0; i < kc; ++i) rm[i] = i;
-    for (int j = 0; j < kc; ++j) {
-      const int p = pivc[nrc + j] - nrc;
-      const int t = rm[j];
-      rm[j] = rm[p];
-      rm[p] = t;
-    }
-  }
+  for (int i = lane; i < kc; i += 64) rm[i] = pivc[nrc + i] - nrc;
   for (int t = lane; t < kc * kc; t += 64) {
     const int i = t / kc, u = t - i * kc;
     Lb[t] = u < i ? double(Lc[size_t(nrc + i) * nc + nrc + u]) : 0.0;

@@ -244,15 +244,10 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
         }
         __syncthreads();
       }
-      for (int j = tid; j < nc; j += WG)
-        for (int r = 0; r < n; ++r) {
-          const int p = piv[r];
-          if (p != r) {
-            const double t = X[size_t(r) * nc + j];
-            X[size_t(r) * nc + j] = X[size_t(p) * nc + j];
-            X[size_t(p) * nc + j] = t;
-          }
-        }
+      // P: row i of P X is row piv[i] of X
+      for (int t = tid; t < n * nc; t += WG) Yb[t] = X[size_t(piv[t / nc]) * nc + t % nc];
+      __syncthreads();
+      for (int t = tid; t < n * nc; t += WG) X[t] = Yb[t];
       __syncthreads();
       for (int t = tid; t < n * nc; t += WG) {
         const int i = t / nc, j = t % nc;
@@ -298,6 +293,237 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
       }
     }
     __syncthreads();
+  }
+}
+
+// One wave per segment for levels whose segments hold at most 64 DOFs: lane
+// i keeps DOF i's chunk of 16 right-hand sides in registers, and rows are
+// exchanged through LDS only where a product needs other lanes' rows.  The
+// packed inverse and T are staged in LDS first (row strides made odd against
+// bank conflicts), in parallel with the gather of the right-hand sides, so
+// that a segment costs few dependent trips to memory.
+constexpr int SOLVE_WAVE_MAX_N = 64;
+
+template <typename T>
+__host__ __device__ inline int seg_solve_wave_lds_bytes(int cap) {
+  return 8 * LEAF_SOLVE_CHUNK * cap + int(sizeof(T)) * (cap * (cap | 1) + cap * ((cap / 2) | 1)) + 16;
+}
+
+template <typename T, bool BACKWARD>
+__global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nseg, const int32_t* iarena,
+                                                       const T* varena, DLevelDyn dyn, T* W, int nrhs) {
+  extern __shared__ double lds[];
+  constexpr int CH = LEAF_SOLVE_CHUNK;
+  const int c = blockIdx.x;
+  if (c >= nseg) return;
+  const DSeg S = segs[c];
+  const int n = dyn.n[c];
+  if (n == 0 || n > SOLVE_WAVE_MAX_N) return;
+  const int k = dyn.k[c], nr = dyn.nr[c];
+  const bool sp = dyn.passes[c] > 0 && nr > 0 && k > 0;
+  const int lane = threadIdx.x;
+  const bool act = lane < n;
+  const int32_t* dofs = iarena + S.ioff;
+  const T* Inv = varena + S.lu_off;
+  const T* Tm = varena + S.t_off;
+  double* X = lds;
+  const int ni = n | 1, ntr = nr | 1;
+  T* sI = reinterpret_cast<T*>(X + n * CH);                  // n x ni
+  T* sT = sI + n * ni;                                       // k x ntr
+  const int dof = act ? dofs[lane] : 0;
+  const int rm = act && !BACKWARD ? dofs[2 * S.cap + lane] : lane;  // row i of P X is row rm of X
+  for (int t = lane; t < n * n; t += 64) sI[(t / n) * ni + t % n] = Inv[t];
+  if (sp)
+    for (int t = lane; t < k * nr; t += 64) sT[(t / nr) * ntr + t % nr] = Tm[t];
+  for (int j0 = 0; j0 < nrhs; j0 += CH) {
+    const int nc = nrhs - j0 < CH ? nrhs - j0 : CH;
+    double x[CH];
+    const T* src = W + size_t(dof) * nrhs + j0;
+#pragma unroll
+    for (int j = 0; j < CH; ++j) x[j] = act && j < nc ? double(src[j]) : 0.0;
+    wave_sync();
+    if (act)
+#pragma unroll
+      for (int j = 0; j < CH; ++j) X[lane * CH + j] = x[j];
+    wave_sync();
+    if (!BACKWARD) {
+      if (sp) {
+        // remainder rows: x_q -= sum_i T_iq x_{nr+i}
+        if (lane < nr)
+          for (int i = 0; i < k; ++i) {
+            const double t = double(sT[i * ntr + lane]);
+            const double* xs = X + (nr + i) * CH;
+#pragma unroll
+            for (int j = 0; j < CH; ++j) x[j] = fma(-t, xs[j], x[j]);
+          }
+        wave_sync();
+        if (act)
+#pragma unroll
+          for (int j = 0; j < CH; ++j) X[lane * CH + j] = x[j];
+        wave_sync();
+      }
+      // P, then the unit lower L^{-1}: y_i = x'_i + sum_{u<i} (L^{-1})_iu x'_u
+      if (act)
+#pragma unroll
+        for (int j = 0; j < CH; ++j) x[j] = X[rm * CH + j];
+      wave_sync();
+      if (act)
+#pragma unroll
+        for (int j = 0; j < CH; ++j) X[lane * CH + j] = x[j];
+      wave_sync();
+      const T* row = sI + (act ? lane : 0) * ni;
+      for (int u = 0; u < n - 1; ++u) {
+        const double l = u < lane ? double(row[u]) : 0.0;
+        const double* xu = X + u * CH;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) x[j] = fma(l, xu[j], x[j]);
+      }
+    } else {
+      // y = U^{-1} x, then skeleton rows: y_{nr+i} -= sum_q T_iq y_q
+      double y[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) y[j] = 0.0;
+      const T* row = sI + (act ? lane : 0) * ni;
+      for (int u = 0; u < n; ++u) {
+        const double uu = u >= lane ? double(row[u]) : 0.0;
+        const double* xu = X + u * CH;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) y[j] = fma(uu, xu[j], y[j]);
+      }
+      if (sp) {
+        wave_sync();
+        if (act)
+#pragma unroll
+          for (int j = 0; j < CH; ++j) X[lane * CH + j] = y[j];
+        wave_sync();
+        if (act && lane >= nr) {
+          const T* trow = sT + (lane - nr) * ntr;
+          for (int q = 0; q < nr; ++q) {
+            const double t = double(trow[q]);
+            const double* xq = X + q * CH;
+#pragma unroll
+            for (int j = 0; j < CH; ++j) y[j] = fma(-t, xq[j], y[j]);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < CH; ++j) x[j] = y[j];
+    }
+    if (act) {
+      T* dst = W + size_t(dof) * nrhs + j0;
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (j < nc) dst[j] = T(x[j]);
+    }
+  }
+}
+
+// One wave per owner segment for levels whose segments hold at most 64 DOFs:
+// forward (owner = non-separator a, neighbours = the level's separators s):
+// W[skel_a] -= A'_{a,s} W[skel_s]; backward (owner = separator s, all its
+// neighbours b): W[skel_s] -= A'_{s,b} W[skel_b].  Lane e first reads
+// neighbour e's sizes and offsets; then every neighbour's skeleton rows
+// (stacked, K rows) and the owner's rows of the scaled blocks (ka x K, row
+// stride made odd) are staged in LDS with independent loads, and lane i
+// forms skeleton row i of the product.
+template <typename T>
+__host__ __device__ inline int sep_wave_lds_bytes(int rows, int cap) {
+  return 8 * LEAF_SOLVE_CHUNK * rows + int(sizeof(T)) * cap * (rows | 1) + 16;
+}
+
+template <typename T, bool FWD>
+__global__ __launch_bounds__(64) void k_sep_wave(const DSeg* segs, int nseg, const DNbr* nbrs, const DBlk* blks,
+                                                 const int32_t* iarena, const T* varena, DLevelDyn dyn, T* W,
+                                                 int nrhs) {
+  extern __shared__ double lds[];
+  constexpr int CH = LEAF_SOLVE_CHUNK;
+  const int a = blockIdx.x;
+  if (a >= nseg) return;
+  const DSeg S = segs[a];
+  const bool is_sep = (S.flags & SEG_IS_SEP) != 0;
+  if (FWD == is_sep) return;
+  const int ka = dyn.k[a], nra = dyn.nr[a];
+  if (ka == 0 || ka > SOLVE_WAVE_MAX_N) return;
+  const int lane = threadIdx.x;
+  const int ne = S.nbr_end - S.nbr_begin;
+  int kb = 0;
+  int64_t dofo = 0, soff = 0;
+  if (lane < ne) {
+    const DNbr nb = nbrs[S.nbr_begin + lane];
+    if (!FWD || nb.d_is_sep) {
+      kb = dyn.k[nb.d];
+      dofo = segs[nb.d].ioff + dyn.nr[nb.d];
+      soff = blks[nb.blk_cd].soff;
+    }
+  }
+  // exclusive prefix of the neighbours' row counts
+  int off = kb;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(off, o, 64);
+    if (lane >= o) off += v;
+  }
+  const int K = __builtin_amdgcn_readlane(off, 63);
+  off -= kb;
+  if (K == 0) return;
+  const bool act = lane < ka;
+  const int dof = act ? iarena[S.ioff + nra + lane] : 0;
+  const int Kp = K | 1;
+  double* X = lds;                                     // K x CH
+  T* sA = reinterpret_cast<T*>(X + size_t(K) * CH);    // ka x Kp
+  // the owner's rows of the scaled blocks, neighbour by neighbour
+  for (int e = 0; e < ne && e < 64; ++e) {
+    const int kbe = __builtin_amdgcn_readlane(kb, e);
+    if (kbe == 0) continue;
+    const int oe = __builtin_amdgcn_readlane(off, e);
+    const int64_t se = (int64_t(__builtin_amdgcn_readlane(int(soff >> 32), e)) << 32) |
+                       uint32_t(__builtin_amdgcn_readlane(int(soff & 0xffffffff), e));
+    const T* Ae = varena + se;
+    for (int t = lane; t < ka * kbe; t += 64) {
+      const int i = t / kbe, u = t - i * kbe;
+      sA[i * Kp + oe + u] = Ae[t];
+    }
+  }
+  for (int j0 = 0; j0 < nrhs; j0 += CH) {
+    const int nc = nrhs - j0 < CH ? nrhs - j0 : CH;
+    wave_sync();
+    for (int t0 = 0; t0 < K; t0 += 64) {
+      // neighbour of stacked row t: the last one with rows that starts at or before t
+      const int t = t0 + lane;
+      int oe = 0;
+      int64_t de = 0;
+      for (int f = 0; f < ne && f < 64; ++f) {
+        const int of = __builtin_amdgcn_readlane(off, f), kf = __builtin_amdgcn_readlane(kb, f);
+        const int64_t df = (int64_t(__builtin_amdgcn_readlane(int(dofo >> 32), f)) << 32) |
+                           uint32_t(__builtin_amdgcn_readlane(int(dofo & 0xffffffff), f));
+        if (kf > 0 && of <= t) {
+          oe = of;
+          de = df;
+        }
+      }
+      if (t < K) {
+        const T* src = W + size_t(iarena[de + (t - oe)]) * nrhs + j0;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) X[t * CH + j] = j < nc ? double(src[j]) : 0.0;
+      }
+    }
+    wave_sync();
+    if (act) {
+      double acc[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) acc[j] = 0.0;
+      const T* arow = sA + lane * Kp;
+      for (int t = 0; t < K; ++t) {
+        const double av = double(arow[t]);
+        const double* xt = X + t * CH;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) acc[j] = fma(av, xt[j], acc[j]);
+      }
+      T* dst = W + size_t(dof) * nrhs + j0;
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (j < nc) dst[j] = T(double(dst[j]) - acc[j]);
+    }
   }
 }
 

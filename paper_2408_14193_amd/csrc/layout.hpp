@@ -28,7 +28,8 @@ struct DSeg {
   int32_t thr;        // near-field Chebyshev radius
   int32_t rcap;       // bound on ID rows: 2 * sum of neighbour caps
   int32_t sep_level;  // level of the separator holding the segment
-  int64_t ioff;       // int arena: dofs[cap], perm[cap], piv[cap], tag[2*rcap]
+  int64_t ioff;       // int arena: dofs[cap], perm[cap], piv[cap], tag[2*rcap]; piv holds
+                      // the LU's row interchanges composed: row i of P X is row piv[i] of X
   int64_t lu_off;     // value arena: cap*cap
   int64_t t_off;      // value arena: floor(cap*cap/4)
   int64_t scr_off;    // scratch pool (doubles): 2*rcap*cap (regular segments)

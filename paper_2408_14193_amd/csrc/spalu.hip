@@ -56,6 +56,8 @@ struct LevelTabs {
   IdTiers tiers{0, 0, 0, 8};
   bool id_b = false, id_b2 = false, id_c = false, id_old = false;
   int max_cap = 0;  // largest uncompressed segment
+  int sep_rows = 0;          // largest sum of neighbour caps of a segment
+  int max_nbrs = 0;          // largest neighbour count of a segment
   int scale_wave_lds = 0;    // LDS doubles of the one-wave coupling scaling
   bool scale_block = false;  // some block may need the 256-thread version
 };
@@ -276,7 +278,13 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
     }
     pool = std::max(pool, level_pool);
     plan_id_tiers(T, prec == SPALU_FP32 ? 4 : 8);
-    for (const DSeg& D : T.segs) T.max_cap = std::max(T.max_cap, int(D.cap));
+    for (const DSeg& D : T.segs) {
+      T.max_cap = std::max(T.max_cap, int(D.cap));
+      int rows = 0;
+      for (int e = D.nbr_begin; e < D.nbr_end; ++e) rows += T.segs[T.nbrs[e].d].cap;
+      T.sep_rows = std::max(T.sep_rows, rows);
+      T.max_nbrs = std::max(T.max_nbrs, int(D.nbr_end - D.nbr_begin));
+    }
     {
       constexpr int SCALE_WAVE_MAX = 6144;  // 48 KB of LDS per wave at most
       int need = 0;
@@ -1027,23 +1035,44 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
   LAUNCH(K_SEPLEAF, 0, k_sep_from_leaves<T><<<nblocks(nsep * nrhs), WG, 0, st>>>(
       nsep, tab<int32_t>(ws, Y.o_sepv), tab<int8_t>(ws, Y.o_seplev), F->rowptr, F->colind, F->vals, B0, Z, W,
       nrhs));
+  // levels whose segments hold at most 64 DOFs (and whose staging fits
+  // 64 KB of LDS) take the one-wave kernels
+  auto wave_level = [&](const LevelTabs& T_, size_t& lds_solve, size_t& lds_sep) {
+    lds_solve = size_t(seg_solve_wave_lds_bytes<T>(T_.max_cap));
+    lds_sep = size_t(sep_wave_lds_bytes<T>(T_.sep_rows, T_.max_cap));
+    return T_.max_cap <= SOLVE_WAVE_MAX_N && T_.max_nbrs <= 64 && lds_solve <= 65536 && lds_sep <= 65536;
+  };
   for (int l = L; l >= 1; --l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
     DLevelDyn d = dyn_of(ws, Y, l);
-    LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, LDS_BYTES, st>>>(tab<DSeg>(ws, T_.o_segs), ns, iar, var, d, W,
-                                                               nrhs));
-    LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<unsigned(ns), WG, 0, st>>>(tab<DSeg>(ws, T_.o_segs), ns, tab<DNbr>(ws, T_.o_nbrs),
-                                             tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
+    const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
+    const DNbr* nbr = tab<DNbr>(ws, T_.o_nbrs);
+    const DBlk* bk = tab<DBlk>(ws, T_.o_blks);
+    size_t ls = 0, lp = 0;
+    if (wave_level(T_, ls, lp)) {
+      LAUNCH(K_SSOLVE_F, l, k_seg_solve_wave<T, false><<<unsigned(ns), 64, ls, st>>>(sg, ns, iar, var, d, W, nrhs));
+      LAUNCH(K_SEPFWD, l, k_sep_wave<T, true><<<unsigned(ns), 64, lp, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs));
+    } else {
+      LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, LDS_BYTES, st>>>(sg, ns, iar, var, d, W, nrhs));
+      LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs));
+    }
   }
   for (int l = 1; l <= L; ++l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
     DLevelDyn d = dyn_of(ws, Y, l);
-    LAUNCH(K_SEPBWD, l, k_sep_bwd<T><<<unsigned(ns), WG, 0, st>>>(tab<DSeg>(ws, T_.o_segs), ns, tab<DNbr>(ws, T_.o_nbrs),
-                                             tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
-    LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, LDS_BYTES, st>>>(tab<DSeg>(ws, T_.o_segs), ns, iar, var, d, W,
-                                                              nrhs));
+    const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
+    const DNbr* nbr = tab<DNbr>(ws, T_.o_nbrs);
+    const DBlk* bk = tab<DBlk>(ws, T_.o_blks);
+    size_t ls = 0, lp = 0;
+    if (wave_level(T_, ls, lp)) {
+      LAUNCH(K_SEPBWD, l, k_sep_wave<T, false><<<unsigned(ns), 64, lp, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs));
+      LAUNCH(K_SSOLVE_B, l, k_seg_solve_wave<T, true><<<unsigned(ns), 64, ls, st>>>(sg, ns, iar, var, d, W, nrhs));
+    } else {
+      LAUNCH(K_SEPBWD, l, k_sep_bwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs));
+      LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, LDS_BYTES, st>>>(sg, ns, iar, var, d, W, nrhs));
+    }
   }
   if (wave_leaf) {
     LAUNCH(K_LSOLVE_B, 0, k_leaf_solve_wave<T, true><<<unsigned(Y.leaves.size()), 64, lsl, st>>>(

@@ -84,6 +84,7 @@ inline void emu_amdgcn_fence(int, const char*) {}
 inline uint64_t __ballot(bool p) { return emu::ballot(p); }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline int __ffsll(unsigned long long x) { return __builtin_ffsll((long long)x); }
+inline int emu_amdgcn_readlane(int v, int l) { return emu::shfl_i(v, l & 63); }
 inline int emu_amdgcn_readfirstlane(int v) {
   const uint64_t m = emu::ballot(true);
   return emu::shfl_i(v, __builtin_ffsll((long long)m) - 1);
@@ -93,6 +94,10 @@ inline double __shfl_xor(double v, int m, int = 64) {
 }
 inline int __shfl_xor(int v, int m, int = 64) { return emu::shfl_i(v, (int(threadIdx.x) & 63) ^ m); }
 inline double __shfl(double v, int src, int = 64) { return emu::shfl_d(v, src & 63); }
+inline int __shfl_up(int v, unsigned d, int = 64) {
+  const int l = int(threadIdx.x) & 63;
+  return emu::shfl_i(v, l >= int(d) ? l - int(d) : l);
+}
 inline int __shfl(int v, int src, int = 64) { return emu::shfl_i(v, src & 63); }
 inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
 inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
