@@ -101,9 +101,42 @@ __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nlea
 // The same for leaves of at most 64 interior vertices, one wave each: lane q
 // gathers the right-hand sides of vertex q (a chunk of 16, zero beyond the
 // last one) into LDS, then lane i forms row i of A_II^{-1} times the chunk,
-// reading the transposed inverse from global memory (consecutive lanes,
-// consecutive addresses).
+// reading the transposed inverse (consecutive lanes, consecutive addresses)
+// in batches of loads issued together.
 constexpr int LEAF_SOLVE_CHUNK = 16;
+
+// store(t, src[t]) for t in [0, count), t = lane + stride * m: the loads of
+// a batch of NB are issued together (clamped addresses, guarded stores), so
+// a staging loop costs one trip to memory per batch instead of one per load.
+template <int NB, typename S, typename F>
+__device__ inline void stage_batched(const S* src, int count, int lane, int stride, F store) {
+  for (int t0 = 0; t0 < count; t0 += NB * stride) {
+    S v[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int t = t0 + b * stride + lane;
+      v[b] = src[t < count ? t : count - 1];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int t = t0 + b * stride + lane;
+      if (t < count) store(t, v[b]);
+    }
+  }
+}
+
+// x[j] = src[j] for j < nc (0 beyond): a full chunk loads unconditionally,
+// so that all its loads are in flight together.
+template <typename T>
+__device__ inline void load_chunk(const T* src, int nc, double x[LEAF_SOLVE_CHUNK]) {
+  if (nc == LEAF_SOLVE_CHUNK) {
+#pragma unroll
+    for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) x[j] = double(src[j]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) x[j] = j < nc ? double(src[j]) : 0.0;
+  }
+}
 
 __host__ __device__ inline int leaf_solve_wave_lds_bytes(int ni) { return 8 * LEAF_SOLVE_CHUNK * ni; }
 
@@ -113,6 +146,7 @@ __global__ __launch_bounds__(64) void k_leaf_solve_wave(const DLeaf* leaves, int
                                                         const double* vals, const T* varena, const T* B0,
                                                         T* W, T* Z, int nrhs) {
   extern __shared__ double lds[];
+  constexpr int CH = LEAF_SOLVE_CHUNK;
   const int lf = blockIdx.x;
   if (lf >= nleaf) return;
   const DLeaf L = leaves[lf];
@@ -120,47 +154,80 @@ __global__ __launch_bounds__(64) void k_leaf_solve_wave(const DLeaf* leaves, int
   if (ni == 0) return;
   const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1, w2 = L.hi[2] - L.lo[2] + 1;
   double* X = lds;
-  const T* Ai = varena + L.lu_off;
   const bool act = lane < ni;
   const int ix = lane % w0, iy = (lane / w0) % w1, iz = lane / (w0 * w1);
   const int u = act ? (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz)) : 0;
-  T* dst = BACKWARD ? W : Z;
-  for (int j0 = 0; j0 < nrhs; j0 += LEAF_SOLVE_CHUNK) {
-    const int nc = nrhs - j0 < LEAF_SOLVE_CHUNK ? nrhs - j0 : LEAF_SOLVE_CHUNK;
-    if (act) {
-      double v[LEAF_SOLVE_CHUNK];
-      const T* src = B0 + size_t(u) * nrhs + j0;
+  // stencil entries of row u (at most 8, |d| <= 1 in up to three axes):
+  // columns and values loaded together; outside couplings kept
+  constexpr int ME = 8;
+  int wo[ME];
+  double ao[ME];
+  if (BACKWARD) {
+    const int64_t e0 = act ? rowptr[u] : 0, e1 = act ? rowptr[u + 1] : 0;
+    int cols[ME];
+    double vv[ME];
 #pragma unroll
-      for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) v[j] = j < nc ? double(src[j]) : 0.0;
+    for (int m = 0; m < ME; ++m) {
+      const int64_t e = e0 + m < e1 ? e0 + m : (e1 > e0 ? e1 - 1 : 0);
+      cols[m] = act && e1 > e0 ? colind[e] : 0;
+      vv[m] = act && e1 > e0 ? vals[e] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < ME; ++m) {
+      const bool out = e0 + m < e1 && box_nbr(g, w0, w1, w2, ix, iy, iz, lane, u, cols[m]) < 0;
+      wo[m] = out ? cols[m] : u;
+      ao[m] = out ? vv[m] : 0.0;
+    }
+  }
+  const T* Ai = varena + L.lu_off + (act ? lane : 0);  // column lane of the transposed inverse
+  T* dst = BACKWARD ? W : Z;
+  for (int j0 = 0; j0 < nrhs; j0 += CH) {
+    const int nc = nrhs - j0 < CH ? nrhs - j0 : CH;
+    if (act) {
+      double v[CH];
+      load_chunk(B0 + size_t(u) * nrhs + j0, nc, v);
       if (BACKWARD) {
-        for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+        for (int m = 0; m < ME; ++m) {
+          if (ao[m] == 0.0) continue;
+          double wv[CH];
+          load_chunk(W + size_t(wo[m]) * nrhs + j0, nc, wv);
+#pragma unroll
+          for (int j = 0; j < CH; ++j) v[j] = fma(-ao[m], wv[j], v[j]);
+        }
+        for (int64_t e = rowptr[u] + ME; e < rowptr[u + 1]; ++e) {  // rows longer than ME
           const int w = colind[e];
           if (box_nbr(g, w0, w1, w2, ix, iy, iz, lane, u, w) >= 0) continue;
-          const double a = vals[e];
-          const T* ws = W + size_t(w) * nrhs + j0;
+          double wv[CH];
+          load_chunk(W + size_t(w) * nrhs + j0, nc, wv);
 #pragma unroll
-          for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j)
-            if (j < nc) v[j] -= a * double(ws[j]);
+          for (int j = 0; j < CH; ++j) v[j] = fma(-vals[e], wv[j], v[j]);
         }
       }
 #pragma unroll
-      for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) X[lane * LEAF_SOLVE_CHUNK + j] = v[j];
+      for (int j = 0; j < CH; ++j) X[lane * CH + j] = v[j];
     }
     wave_sync();
     if (act) {
-      double acc[LEAF_SOLVE_CHUNK];
+      double acc[CH];
 #pragma unroll
-      for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) acc[j] = 0.0;
-#pragma unroll 4
-      for (int q = 0; q < ni; ++q) {
-        const double a = double(Ai[size_t(q) * ni + lane]);
-        const double* xq = X + q * LEAF_SOLVE_CHUNK;
+      for (int j = 0; j < CH; ++j) acc[j] = 0.0;
+      // row lane of A_II^{-1} in batches of 16 loads issued together
+      for (int q0 = 0; q0 < ni; q0 += 16) {
+        T av[16];
 #pragma unroll
-        for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j) acc[j] = fma(a, xq[j], acc[j]);
+        for (int b = 0; b < 16; ++b) av[b] = Ai[size_t(q0 + b < ni ? q0 + b : ni - 1) * ni];
+#pragma unroll
+        for (int b = 0; b < 16; ++b)
+          if (q0 + b < ni) {
+            const double a = double(av[b]);
+            const double* xq = X + (q0 + b) * CH;
+#pragma unroll
+            for (int j = 0; j < CH; ++j) acc[j] = fma(a, xq[j], acc[j]);
+          }
       }
       T* out = dst + size_t(u) * nrhs + j0;
 #pragma unroll
-      for (int j = 0; j < LEAF_SOLVE_CHUNK; ++j)
+      for (int j = 0; j < CH; ++j)
         if (j < nc) out[j] = T(acc[j]);
     }
     wave_sync();
@@ -296,51 +363,60 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
   }
 }
 
-// One wave per segment for levels whose segments hold at most 64 DOFs: lane
-// i keeps DOF i's chunk of 16 right-hand sides in registers, and rows are
-// exchanged through LDS only where a product needs other lanes' rows.  The
-// packed inverse and T are staged in LDS first (row strides made odd against
-// bank conflicts), in parallel with the gather of the right-hand sides, so
-// that a segment costs few dependent trips to memory.
+// Groups of P lanes (P = 8, 16, 32 or 64) per segment, 64 / P segments per
+// wave, for levels whose segments hold at most P DOFs: lane i of a group
+// keeps DOF i's chunk of 16 right-hand sides in registers, and rows are
+// exchanged through the group's LDS only where a product needs other lanes'
+// rows.  The packed inverse and T are staged in LDS first (row strides made
+// odd against bank conflicts), in parallel with the gather of the right-hand
+// sides; several segments per wave keep more memory requests in flight.
 constexpr int SOLVE_WAVE_MAX_N = 64;
 
 template <typename T>
-__host__ __device__ inline int seg_solve_wave_lds_bytes(int cap) {
-  return 8 * LEAF_SOLVE_CHUNK * cap + int(sizeof(T)) * (cap * (cap | 1) + cap * ((cap / 2) | 1)) + 16;
+__host__ __device__ inline int seg_solve_grp_bytes(int P) {  // LDS of one group
+  return (8 * LEAF_SOLVE_CHUNK * P + int(sizeof(T)) * (P * (P | 1) + P * ((P / 2) | 1)) + 15) / 16 * 16;
 }
 
-template <typename T, bool BACKWARD>
+template <typename T, bool BACKWARD, int P>
 __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nseg, const int32_t* iarena,
                                                        const T* varena, DLevelDyn dyn, T* W, int nrhs) {
   extern __shared__ double lds[];
   constexpr int CH = LEAF_SOLVE_CHUNK;
-  const int c = blockIdx.x;
-  if (c >= nseg) return;
-  const DSeg S = segs[c];
-  const int n = dyn.n[c];
-  if (n == 0 || n > SOLVE_WAVE_MAX_N) return;
-  const int k = dyn.k[c], nr = dyn.nr[c];
-  const bool sp = dyn.passes[c] > 0 && nr > 0 && k > 0;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x % P, grp = threadIdx.x / P;
+  const int c = blockIdx.x * (64 / P) + grp;
+  int n = 0, k = 0, nr = 0;
+  bool sp = false;
+  DSeg S{};
+  if (c < nseg) {
+    S = segs[c];
+    n = dyn.n[c];
+    k = dyn.k[c];
+    nr = dyn.nr[c];
+    sp = dyn.passes[c] > 0 && nr > 0 && k > 0;
+  }
+  if (n > P) n = 0;  // never on a level launched with this P
   const bool act = lane < n;
-  const int32_t* dofs = iarena + S.ioff;
-  const T* Inv = varena + S.lu_off;
-  const T* Tm = varena + S.t_off;
-  double* X = lds;
+  double* X = reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + size_t(grp) * seg_solve_grp_bytes<T>(P));
   const int ni = n | 1, ntr = nr | 1;
-  T* sI = reinterpret_cast<T*>(X + n * CH);                  // n x ni
-  T* sT = sI + n * ni;                                       // k x ntr
+  T* sI = reinterpret_cast<T*>(X + n * CH);  // n x ni
+  T* sT = sI + n * ni;                       // k x ntr
+  const int32_t* dofs = iarena + S.ioff;
   const int dof = act ? dofs[lane] : 0;
   const int rm = act && !BACKWARD ? dofs[2 * S.cap + lane] : lane;  // row i of P X is row rm of X
-  for (int t = lane; t < n * n; t += 64) sI[(t / n) * ni + t % n] = Inv[t];
-  if (sp)
-    for (int t = lane; t < k * nr; t += 64) sT[(t / nr) * ntr + t % nr] = Tm[t];
+  if (n > 0) {
+    stage_batched<(P < 16 ? 8 : 16)>(varena + S.lu_off, n * n, lane, P,
+                                     [&](int t, T v) { sI[(t / n) * ni + t % n] = v; });
+    if (sp)
+      stage_batched<8>(varena + S.t_off, k * nr, lane, P, [&](int t, T v) { sT[(t / nr) * ntr + t % nr] = v; });
+  }
   for (int j0 = 0; j0 < nrhs; j0 += CH) {
     const int nc = nrhs - j0 < CH ? nrhs - j0 : CH;
     double x[CH];
-    const T* src = W + size_t(dof) * nrhs + j0;
+    if (act)
+      load_chunk(W + size_t(dof) * nrhs + j0, nc, x);
+    else
 #pragma unroll
-    for (int j = 0; j < CH; ++j) x[j] = act && j < nc ? double(src[j]) : 0.0;
+      for (int j = 0; j < CH; ++j) x[j] = 0.0;
     wave_sync();
     if (act)
 #pragma unroll
@@ -371,24 +447,28 @@ __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nse
 #pragma unroll
         for (int j = 0; j < CH; ++j) X[lane * CH + j] = x[j];
       wave_sync();
-      const T* row = sI + (act ? lane : 0) * ni;
-      for (int u = 0; u < n - 1; ++u) {
-        const double l = u < lane ? double(row[u]) : 0.0;
-        const double* xu = X + u * CH;
+      if (act) {
+        const T* row = sI + lane * ni;
+        for (int u = 0; u < lane; ++u) {
+          const double l = double(row[u]);
+          const double* xu = X + u * CH;
 #pragma unroll
-        for (int j = 0; j < CH; ++j) x[j] = fma(l, xu[j], x[j]);
+          for (int j = 0; j < CH; ++j) x[j] = fma(l, xu[j], x[j]);
+        }
       }
     } else {
       // y = U^{-1} x, then skeleton rows: y_{nr+i} -= sum_q T_iq y_q
       double y[CH];
 #pragma unroll
       for (int j = 0; j < CH; ++j) y[j] = 0.0;
-      const T* row = sI + (act ? lane : 0) * ni;
-      for (int u = 0; u < n; ++u) {
-        const double uu = u >= lane ? double(row[u]) : 0.0;
-        const double* xu = X + u * CH;
+      if (act) {
+        const T* row = sI + lane * ni;
+        for (int u = lane; u < n; ++u) {
+          const double uu = double(row[u]);
+          const double* xu = X + u * CH;
 #pragma unroll
-        for (int j = 0; j < CH; ++j) y[j] = fma(uu, xu[j], y[j]);
+          for (int j = 0; j < CH; ++j) y[j] = fma(uu, xu[j], y[j]);
+        }
       }
       if (sp) {
         wave_sync();
@@ -405,6 +485,9 @@ __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nse
             for (int j = 0; j < CH; ++j) y[j] = fma(-t, xq[j], y[j]);
           }
         }
+      } else {
+        wave_sync();
+        wave_sync();
       }
 #pragma unroll
       for (int j = 0; j < CH; ++j) x[j] = y[j];
@@ -418,34 +501,46 @@ __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nse
   }
 }
 
-// One wave per owner segment for levels whose segments hold at most 64 DOFs:
-// forward (owner = non-separator a, neighbours = the level's separators s):
+// Groups of P lanes per owner segment, 64 / P owners per wave, for levels
+// whose segments hold at most P DOFs and have at most P neighbours: forward
+// (owner = non-separator a, neighbours = the level's separators s):
 // W[skel_a] -= A'_{a,s} W[skel_s]; backward (owner = separator s, all its
-// neighbours b): W[skel_s] -= A'_{s,b} W[skel_b].  Lane e first reads
-// neighbour e's sizes and offsets; then every neighbour's skeleton rows
-// (stacked, K rows) and the owner's rows of the scaled blocks (ka x K, row
-// stride made odd) are staged in LDS with independent loads, and lane i
-// forms skeleton row i of the product.
+// neighbours b): W[skel_s] -= A'_{s,b} W[skel_b].  Lane e of a group reads
+// neighbour e's sizes and offsets into the group's LDS; then the neighbours'
+// skeleton rows (stacked, K rows, at most rows_cap) are gathered into LDS in
+// the storage type with independent loads, and lane i forms skeleton row i
+// of the product, reading its rows of the scaled blocks directly.
 template <typename T>
-__host__ __device__ inline int sep_wave_lds_bytes(int rows, int cap) {
-  return 8 * LEAF_SOLVE_CHUNK * rows + int(sizeof(T)) * cap * (rows | 1) + 16;
+__host__ __device__ inline int sep_grp_bytes(int P, int rows_cap) {  // LDS of one group
+  return (24 * P + int(sizeof(T)) * LEAF_SOLVE_CHUNK * rows_cap + 15) / 16 * 16;
 }
 
-template <typename T, bool FWD>
+template <typename T, bool FWD, int P>
 __global__ __launch_bounds__(64) void k_sep_wave(const DSeg* segs, int nseg, const DNbr* nbrs, const DBlk* blks,
                                                  const int32_t* iarena, const T* varena, DLevelDyn dyn, T* W,
-                                                 int nrhs) {
+                                                 int nrhs, int rows_cap) {
   extern __shared__ double lds[];
   constexpr int CH = LEAF_SOLVE_CHUNK;
-  const int a = blockIdx.x;
-  if (a >= nseg) return;
-  const DSeg S = segs[a];
-  const bool is_sep = (S.flags & SEG_IS_SEP) != 0;
-  if (FWD == is_sep) return;
-  const int ka = dyn.k[a], nra = dyn.nr[a];
-  if (ka == 0 || ka > SOLVE_WAVE_MAX_N) return;
-  const int lane = threadIdx.x;
-  const int ne = S.nbr_end - S.nbr_begin;
+  const int lane = threadIdx.x % P, grp = threadIdx.x / P;
+  const int a = blockIdx.x * (64 / P) + grp;
+  char* base = reinterpret_cast<char*>(lds) + size_t(grp) * sep_grp_bytes<T>(P, rows_cap);
+  int64_t* m_dofo = reinterpret_cast<int64_t*>(base);  // neighbour e: its skeleton DOF list
+  int64_t* m_soff = m_dofo + P;                        // its scaled block (owner rows)
+  int* m_off = reinterpret_cast<int*>(m_soff + P);     // first stacked row
+  int* m_kb = m_off + P;                               // skeleton size
+  T* X = reinterpret_cast<T*>(m_kb + P);               // stacked rows, K x CH
+  bool own = false;
+  int ka = 0, nra = 0, ne = 0;
+  DSeg S{};
+  if (a < nseg) {
+    S = segs[a];
+    own = FWD != ((S.flags & SEG_IS_SEP) != 0);
+    ka = dyn.k[a];
+    nra = dyn.nr[a];
+    ne = S.nbr_end - S.nbr_begin;
+  }
+  if (!own || ka > P || ne > P) ka = 0;  // never on a level launched with this P
+  if (ka == 0) ne = 0;
   int kb = 0;
   int64_t dofo = 0, soff = 0;
   if (lane < ne) {
@@ -456,73 +551,68 @@ __global__ __launch_bounds__(64) void k_sep_wave(const DSeg* segs, int nseg, con
       soff = blks[nb.blk_cd].soff;
     }
   }
-  // exclusive prefix of the neighbours' row counts
+  // inclusive prefix of the neighbours' row counts inside the group
   int off = kb;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int v = __shfl_up(off, o, 64);
+  for (int o = 1; o < P; o <<= 1) {
+    const int v = __shfl_up(off, o, P);
     if (lane >= o) off += v;
   }
-  const int K = __builtin_amdgcn_readlane(off, 63);
+  int K = __shfl(off, P - 1, P);
   off -= kb;
-  if (K == 0) return;
-  const bool act = lane < ka;
+  if (K > rows_cap) K = 0;  // the level's bound on neighbour sizes; never taken
+  m_off[lane] = off;
+  m_kb[lane] = kb;
+  m_dofo[lane] = dofo;
+  m_soff[lane] = soff;
+  const bool act = lane < ka && K > 0;
   const int dof = act ? iarena[S.ioff + nra + lane] : 0;
-  const int Kp = K | 1;
-  double* X = lds;                                     // K x CH
-  T* sA = reinterpret_cast<T*>(X + size_t(K) * CH);    // ka x Kp
-  // the owner's rows of the scaled blocks, neighbour by neighbour
-  for (int e = 0; e < ne && e < 64; ++e) {
-    const int kbe = __builtin_amdgcn_readlane(kb, e);
-    if (kbe == 0) continue;
-    const int oe = __builtin_amdgcn_readlane(off, e);
-    const int64_t se = (int64_t(__builtin_amdgcn_readlane(int(soff >> 32), e)) << 32) |
-                       uint32_t(__builtin_amdgcn_readlane(int(soff & 0xffffffff), e));
-    const T* Ae = varena + se;
-    for (int t = lane; t < ka * kbe; t += 64) {
-      const int i = t / kbe, u = t - i * kbe;
-      sA[i * Kp + oe + u] = Ae[t];
-    }
-  }
   for (int j0 = 0; j0 < nrhs; j0 += CH) {
     const int nc = nrhs - j0 < CH ? nrhs - j0 : CH;
+    double own_w[CH];
+    if (act)
+      load_chunk(W + size_t(dof) * nrhs + j0, nc, own_w);
     wave_sync();
-    for (int t0 = 0; t0 < K; t0 += 64) {
-      // neighbour of stacked row t: the last one with rows that starts at or before t
-      const int t = t0 + lane;
-      int oe = 0;
-      int64_t de = 0;
-      for (int f = 0; f < ne && f < 64; ++f) {
-        const int of = __builtin_amdgcn_readlane(off, f), kf = __builtin_amdgcn_readlane(kb, f);
-        const int64_t df = (int64_t(__builtin_amdgcn_readlane(int(dofo >> 32), f)) << 32) |
-                           uint32_t(__builtin_amdgcn_readlane(int(dofo & 0xffffffff), f));
-        if (kf > 0 && of <= t) {
-          oe = of;
-          de = df;
-        }
-      }
-      if (t < K) {
-        const T* src = W + size_t(iarena[de + (t - oe)]) * nrhs + j0;
+    // stacked row t belongs to the last neighbour with rows starting at or
+    // before t; two rows per lane per pass, their loads issued together
+    for (int t0 = lane; t0 < K; t0 += 2 * P) {
+      int dr[2];
 #pragma unroll
-        for (int j = 0; j < CH; ++j) X[t * CH + j] = j < nc ? double(src[j]) : 0.0;
+      for (int h = 0; h < 2; ++h) {
+        const int t = t0 + h * P < K ? t0 + h * P : t0;
+        int e = 0;
+        for (int f = 0; f < ne; ++f)
+          if (m_kb[f] > 0 && m_off[f] <= t) e = f;
+        dr[h] = iarena[m_dofo[e] + (t - m_off[e])];
       }
+      double xv[2][CH];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) load_chunk(W + size_t(dr[h]) * nrhs + j0, nc, xv[h]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (t0 + h * P < K)
+#pragma unroll
+          for (int j = 0; j < CH; ++j) X[(t0 + h * P) * CH + j] = T(xv[h][j]);
     }
     wave_sync();
     if (act) {
       double acc[CH];
 #pragma unroll
       for (int j = 0; j < CH; ++j) acc[j] = 0.0;
-      const T* arow = sA + lane * Kp;
-      for (int t = 0; t < K; ++t) {
-        const double av = double(arow[t]);
-        const double* xt = X + t * CH;
+      for (int e = 0; e < ne; ++e) {
+        const int kbe = m_kb[e];
+        const T* arow = varena + m_soff[e] + size_t(lane) * kbe;
+        const T* xe = X + m_off[e] * CH;
+        for (int u = 0; u < kbe; ++u) {
+          const double av = double(arow[u]);
 #pragma unroll
-        for (int j = 0; j < CH; ++j) acc[j] = fma(av, xt[j], acc[j]);
+          for (int j = 0; j < CH; ++j) acc[j] = fma(av, double(xe[u * CH + j]), acc[j]);
+        }
       }
       T* dst = W + size_t(dof) * nrhs + j0;
 #pragma unroll
       for (int j = 0; j < CH; ++j)
-        if (j < nc) dst[j] = T(double(dst[j]) - acc[j]);
+        if (j < nc) dst[j] = T(own_w[j] - acc[j]);
     }
   }
 }

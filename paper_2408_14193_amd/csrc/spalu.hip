@@ -1035,42 +1035,74 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
   LAUNCH(K_SEPLEAF, 0, k_sep_from_leaves<T><<<nblocks(nsep * nrhs), WG, 0, st>>>(
       nsep, tab<int32_t>(ws, Y.o_sepv), tab<int8_t>(ws, Y.o_seplev), F->rowptr, F->colind, F->vals, B0, Z, W,
       nrhs));
-  // levels whose segments hold at most 64 DOFs (and whose staging fits
-  // 64 KB of LDS) take the one-wave kernels
-  auto wave_level = [&](const LevelTabs& T_, size_t& lds_solve, size_t& lds_sep) {
-    lds_solve = size_t(seg_solve_wave_lds_bytes<T>(T_.max_cap));
-    lds_sep = size_t(sep_wave_lds_bytes<T>(T_.sep_rows, T_.max_cap));
-    return T_.max_cap <= SOLVE_WAVE_MAX_N && T_.max_nbrs <= 64 && lds_solve <= 65536 && lds_sep <= 65536;
+  // levels whose segments hold at most 64 DOFs (with at most as many
+  // neighbours) take the lane-group kernels, P lanes per segment
+  auto group_lanes = [](const LevelTabs& T_) {
+    const int m = std::max(T_.max_cap, T_.max_nbrs);
+    return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 0;
+  };
+  auto seg_solve_grp = [&](const LevelTabs& T_, int l, int P, bool bwd, DLevelDyn d) {
+    const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
+    const int ns = int(T_.segs.size());
+    const unsigned nb = unsigned((ns + 64 / P - 1) / (64 / P));
+    const size_t lb = size_t(64 / P) * seg_solve_grp_bytes<T>(P);
+#define SPALU_SSG(PP)                                                                                          \
+  if (bwd)                                                                                                     \
+    LAUNCH(K_SSOLVE_B, l, k_seg_solve_wave<T, true, PP><<<nb, 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs));  \
+  else                                                                                                         \
+    LAUNCH(K_SSOLVE_F, l, k_seg_solve_wave<T, false, PP><<<nb, 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs));
+    if (P == 8) { SPALU_SSG(8) } else if (P == 16) { SPALU_SSG(16) } else if (P == 32) { SPALU_SSG(32) } else { SPALU_SSG(64) }
+#undef SPALU_SSG
+    return int(SPALU_OK);
+  };
+  auto sep_grp = [&](const LevelTabs& T_, int l, int P, bool bwd, DLevelDyn d) {
+    const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
+    const DNbr* nbr = tab<DNbr>(ws, T_.o_nbrs);
+    const DBlk* bk = tab<DBlk>(ws, T_.o_blks);
+    const int ns = int(T_.segs.size());
+    const int rc = std::max(T_.sep_rows, 1);
+    const unsigned nb = unsigned((ns + 64 / P - 1) / (64 / P));
+    const size_t lb = size_t(64 / P) * sep_grp_bytes<T>(P, rc);
+#define SPALU_SG(PP)                                                                                           \
+  if (bwd)                                                                                                     \
+    LAUNCH(K_SEPBWD, l, k_sep_wave<T, false, PP><<<nb, 64, lb, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs, rc)); \
+  else                                                                                                         \
+    LAUNCH(K_SEPFWD, l, k_sep_wave<T, true, PP><<<nb, 64, lb, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs, rc));
+    if (P == 8) { SPALU_SG(8) } else if (P == 16) { SPALU_SG(16) } else if (P == 32) { SPALU_SG(32) } else { SPALU_SG(64) }
+#undef SPALU_SG
+    return int(SPALU_OK);
+  };
+  auto grp_ok = [&](const LevelTabs& T_, int P) {
+    return P > 0 && size_t(64 / P) * seg_solve_grp_bytes<T>(P) <= 65536 &&
+           size_t(64 / P) * sep_grp_bytes<T>(P, std::max(T_.sep_rows, 1)) <= 65536;
   };
   for (int l = L; l >= 1; --l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
     DLevelDyn d = dyn_of(ws, Y, l);
-    const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
-    const DNbr* nbr = tab<DNbr>(ws, T_.o_nbrs);
-    const DBlk* bk = tab<DBlk>(ws, T_.o_blks);
-    size_t ls = 0, lp = 0;
-    if (wave_level(T_, ls, lp)) {
-      LAUNCH(K_SSOLVE_F, l, k_seg_solve_wave<T, false><<<unsigned(ns), 64, ls, st>>>(sg, ns, iar, var, d, W, nrhs));
-      LAUNCH(K_SEPFWD, l, k_sep_wave<T, true><<<unsigned(ns), 64, lp, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs));
+    const int P = group_lanes(T_);
+    if (grp_ok(T_, P)) {
+      if (const int rc = seg_solve_grp(T_, l, P, false, d)) return rc;
+      if (const int rc = sep_grp(T_, l, P, false, d)) return rc;
     } else {
+      const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
       LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, LDS_BYTES, st>>>(sg, ns, iar, var, d, W, nrhs));
-      LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs));
+      LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
+                                                                   tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
     }
   }
   for (int l = 1; l <= L; ++l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
     DLevelDyn d = dyn_of(ws, Y, l);
-    const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
-    const DNbr* nbr = tab<DNbr>(ws, T_.o_nbrs);
-    const DBlk* bk = tab<DBlk>(ws, T_.o_blks);
-    size_t ls = 0, lp = 0;
-    if (wave_level(T_, ls, lp)) {
-      LAUNCH(K_SEPBWD, l, k_sep_wave<T, false><<<unsigned(ns), 64, lp, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs));
-      LAUNCH(K_SSOLVE_B, l, k_seg_solve_wave<T, true><<<unsigned(ns), 64, ls, st>>>(sg, ns, iar, var, d, W, nrhs));
+    const int P = group_lanes(T_);
+    if (grp_ok(T_, P)) {
+      if (const int rc = sep_grp(T_, l, P, true, d)) return rc;
+      if (const int rc = seg_solve_grp(T_, l, P, true, d)) return rc;
     } else {
-      LAUNCH(K_SEPBWD, l, k_sep_bwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs));
+      const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
+      LAUNCH(K_SEPBWD, l, k_sep_bwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
+                                                                   tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
       LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, LDS_BYTES, st>>>(sg, ns, iar, var, d, W, nrhs));
     }
   }

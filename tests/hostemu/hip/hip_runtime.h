@@ -93,12 +93,16 @@ inline double __shfl_xor(double v, int m, int = 64) {
   return emu::shfl_d(v, (int(threadIdx.x) & 63) ^ m);
 }
 inline int __shfl_xor(int v, int m, int = 64) { return emu::shfl_i(v, (int(threadIdx.x) & 63) ^ m); }
-inline double __shfl(double v, int src, int = 64) { return emu::shfl_d(v, src & 63); }
-inline int __shfl_up(int v, unsigned d, int = 64) {
-  const int l = int(threadIdx.x) & 63;
-  return emu::shfl_i(v, l >= int(d) ? l - int(d) : l);
+inline double __shfl(double v, int src, int w = 64) {
+  return emu::shfl_d(v, (int(threadIdx.x) & 63 & ~(w - 1)) + (src & (w - 1)));
 }
-inline int __shfl(int v, int src, int = 64) { return emu::shfl_i(v, src & 63); }
+inline int __shfl_up(int v, unsigned d, int w = 64) {
+  const int l = int(threadIdx.x) & 63;
+  return emu::shfl_i(v, (l & (w - 1)) >= int(d) ? l - int(d) : l);
+}
+inline int __shfl(int v, int src, int w = 64) {
+  return emu::shfl_i(v, (int(threadIdx.x) & 63 & ~(w - 1)) + (src & (w - 1)));
+}
 inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
 inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 inline int atomicOr(int* p, int v) { int o = *p; *p |= v; return o; }
