@@ -131,6 +131,19 @@ struct spalu_factor_s {
   GridGeom g{};
   // per level: n, k, nr, h, passes, off (host copy after the factorization)
   std::shared_ptr<std::vector<std::vector<int32_t>>> dyn_host;
+  // side streams of the factorization (default priority): the size tiers of
+  // a level's ID launches run concurrently, forked after the level's setup
+  // and joined before its segment LU
+  hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[3] = {nullptr, nullptr, nullptr};
+  ~spalu_factor_s() {
+    for (hipStream_t s : aux)
+      if (s) (void)hipStreamDestroy(s);
+    if (fork) (void)hipEventDestroy(fork);
+    for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -832,6 +845,13 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
   const Plan& P = F->nd->plan;
   char* ws = F->ws;
   hipStream_t st = F->stream;
+  if (!F->fork) {
+    HIPCHK(hipEventCreateWithFlags(&F->fork, hipEventDisableTiming));
+    for (int i = 0; i < 3; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&F->aux[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&F->join[i], hipEventDisableTiming));
+    }
+  }
   int32_t* iar = reinterpret_cast<int32_t*>(ws + Y.o_iarena);
   T* var = reinterpret_cast<T*>(ws + Y.o_varena);
   double* scr = reinterpret_cast<double*>(ws + Y.o_scratch);
@@ -910,21 +930,41 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       if (!lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the ID kernel");
       const DNbr* nb = tab<DNbr>(ws, T_.o_nbrs);
       const IdTiers tz = T_.tiers;
+      // tier A on the main stream, B, B2 and C (with the block kernel) on
+      // side streams: every segment belongs to exactly one tier
+      const bool side[3] = {T_.id_b, T_.id_b2, T_.id_c || T_.id_old};
+      if (side[0] || side[1] || side[2]) {
+        HIPCHK(hipEventRecord(F->fork, st));
+        for (int i = 0; i < 3; ++i)
+          if (side[i]) HIPCHK(hipStreamWaitEvent(F->aux[i], F->fork, 0));
+      }
       LAUNCH(K_ID, l, k_seg_id_cols<T, 1, 1, false, 1><<<unsigned(ns), 64, size_t(tz.budget_a), st>>>(
           segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
-      if (T_.id_b)
+      if (side[0]) {
+        hipStream_t st = F->aux[0];
         LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 4, 2, false, 2><<<unsigned(ns), 256, size_t(tz.budget_b), st>>>(
             segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
-      if (T_.id_b2)
+      }
+      if (side[1]) {
+        hipStream_t st = F->aux[1];
         LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 4, 2, false, 3><<<unsigned(ns), 256, size_t(tz.budget_b2), st>>>(
             segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
-      if (T_.id_c)
-        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 8, 2, true, 4><<<unsigned(ns), 512,
-                                                               idc_lds_bytes(8, 2, 128, 0, tz.st, false), st>>>(
-            segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
-      if (T_.id_old)
-        LAUNCH_MORE(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var, scr, d,
-                                                                            prm, tz));
+      }
+      if (side[2]) {
+        hipStream_t st = F->aux[2];
+        if (T_.id_c)
+          LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 8, 2, true, 4><<<unsigned(ns), 512,
+                                                                 idc_lds_bytes(8, 2, 128, 0, tz.st, false), st>>>(
+              segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
+        if (T_.id_old)
+          LAUNCH_MORE(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var,
+                                                                              scr, d, prm, tz));
+      }
+      for (int i = 0; i < 3; ++i)
+        if (side[i]) {
+          HIPCHK(hipEventRecord(F->join[i], F->aux[i]));
+          HIPCHK(hipStreamWaitEvent(st, F->join[i], 0));
+        }
     }
     {
       // segments of up to 32 DOFs: one wave each; wider ones: one block each

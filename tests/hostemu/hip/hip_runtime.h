@@ -37,7 +37,7 @@ typedef EmuEvent* hipEvent_t;
 typedef std::vector<std::function<void()>>* hipGraph_t;
 typedef std::vector<std::function<void()>>* hipGraphExec_t;
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyDefault };
-enum { hipStreamNonBlocking = 1 };
+enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2 };
 enum hipStreamCaptureMode { hipStreamCaptureModeGlobal, hipStreamCaptureModeThreadLocal, hipStreamCaptureModeRelaxed };
 enum { hipHostMallocDefault = 0 };
 enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize };
@@ -120,6 +120,8 @@ hipError_t hipStreamSynchronize(hipStream_t);
 hipError_t hipStreamCreateWithFlags(hipStream_t*, unsigned);
 hipError_t hipStreamDestroy(hipStream_t);
 hipError_t hipEventCreate(hipEvent_t*);
+hipError_t hipEventCreateWithFlags(hipEvent_t*, unsigned);
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned);
 hipError_t hipEventDestroy(hipEvent_t);
 hipError_t hipEventRecord(hipEvent_t, hipStream_t = nullptr);
 hipError_t hipEventSynchronize(hipEvent_t);
