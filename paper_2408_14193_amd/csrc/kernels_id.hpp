@@ -65,15 +65,21 @@ struct IdTiers {
   int st;         // bytes of the storage type
 };
 
-// 0: no ID (identity), 1: tier A, 2: B, 3: B2, 4: C, 5: block-cooperative kernel.
-__device__ inline int id_tier(const DSeg& S, int n, int R, double eps, IdTiers t) {
-  const bool do_id = (S.flags & SEG_REGULAR) && (S.flags & SEG_HAS_NBR) && eps > 0.0 && n > 0;
-  if (!do_id || R == 0) return 0;
+// Tier of a segment that gets an ID, from its sizes (n columns, R rows):
+// 1: tier A, 2: B, 3: B2, 4: C, 5: block-cooperative kernel.
+__host__ __device__ inline int id_tier_of_size(int n, int R, IdTiers t) {
   if (n <= 64 && idc_lds_bytes(1, 1, n, R, t.st, true) <= size_t(t.budget_a)) return 1;
   if (n <= 128 && idc_lds_bytes(4, 2, n, R, t.st, true) <= size_t(t.budget_b)) return 2;
   if (n <= 128 && idc_lds_bytes(4, 2, n, R, t.st, true) <= size_t(t.budget_b2)) return 3;
   if (n <= 128) return 4;
   return 5;
+}
+
+// 0: no ID (identity), else the tier of the sizes.
+__device__ inline int id_tier(const DSeg& S, int n, int R, double eps, IdTiers t) {
+  const bool do_id = (S.flags & SEG_REGULAR) && (S.flags & SEG_HAS_NBR) && eps > 0.0 && n > 0;
+  if (!do_id || R == 0) return 0;
+  return id_tier_of_size(n, R, t);
 }
 
 template <int NW>

@@ -538,12 +538,13 @@ constexpr size_t LEAF_LDS_BYTES = size_t(LEAF_LDS_DOUBLES) * 8;
 // and flops, computed from the actual segment sizes.
 // ---------------------------------------------------------------------------
 enum KId {
-  K_CHECK, K_INIT, K_LEAF, K_ASM, K_ID, K_LU, K_SCALE, K_MSIZE, K_MELIM,
+  K_CHECK, K_INIT, K_LEAF, K_ASM, K_ID, K_ID_B, K_ID_B2, K_ID_C, K_ID_BLK, K_LU, K_SCALE, K_MSIZE, K_MELIM,
   K_LSOLVE_F, K_SEPLEAF, K_SSOLVE_F, K_SEPFWD, K_SEPBWD, K_SSOLVE_B, K_LSOLVE_B,
   K_RHSIN, K_RHSOUT, K_RESID, K_REDUCE, K_APPLY, K_FEAT, K_MLP, K_SPMV, K_KRYLOV, K_COUNT
 };
 const char* const kNames[K_COUNT] = {
-    "check_pattern", "init_level", "leaf_factor", "assemble_leafL", "seg_id", "seg_lu", "blk_scale",
+    "check_pattern", "init_level", "leaf_factor", "assemble_leafL", "seg_id_a", "seg_id_b", "seg_id_b2",
+    "seg_id_c", "seg_id_blk", "seg_lu", "blk_scale",
     "merge_sizes", "merge_elim", "leaf_solve_fwd", "sep_from_leaves", "seg_solve_fwd", "sep_fwd",
     "sep_bwd", "seg_solve_bwd", "leaf_solve_bwd", "rhs_in", "rhs_out", "residual", "reduce_cols",
     "solve_sweep_graph", "features", "mlp_rank", "spmv", "krylov"};
@@ -639,13 +640,19 @@ void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, 
       }
       break;
     }
-    case K_ID: {
+    case K_ID:
+    case K_ID_B:
+    case K_ID_B2:
+    case K_ID_C:
+    case K_ID_BLK: {
+      // the segments of this launch's size tier (A, B, B2, C, block kernel)
       const LevelTabs& T = Y.lv[l];
       for (size_t c = 0; c < T.segs.size(); ++c) {
         if (dynv(l, 4, int(c)) <= 0) continue;
         const double n = dynv(l, 0, int(c)), k = dynv(l, 1, int(c)), h = dynv(l, 3, int(c));
         double R = 0.0;
         for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) R += 2.0 * dynv(l, 0, T.nbrs[e].d);
+        if (id_tier_of_size(int(n), int(R), T.tiers) != 1 + (kid - K_ID)) continue;
         by += R * n * vs + k * (n - k) * vs + n * 4.0;
         fl += 2.0 * h * R * n + 4.0 * (R < h ? R : h) * n * k + k * k * (n - k);
       }
@@ -833,7 +840,8 @@ void factor_work(const spalu_factor_t* F, double& fl, double& by) {
     fl += b;
   }
   for (int l = 1; l <= Y.L; ++l)
-    for (int kid : {int(K_ID), int(K_LU), int(K_SCALE), int(K_MSIZE), int(K_MELIM)}) {
+    for (int kid : {int(K_ID), int(K_ID_B), int(K_ID_B2), int(K_ID_C), int(K_ID_BLK), int(K_LU), int(K_SCALE),
+                    int(K_MSIZE), int(K_MELIM)}) {
       if (l == 1 && (kid == K_MSIZE || kid == K_MELIM)) continue;
       account(Y, dh, F->n, kid, l, 0, a, b);
       by += a;
@@ -944,22 +952,22 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
           segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       if (side[0]) {
         hipStream_t st = F->aux[0];
-        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 4, 2, false, 2><<<unsigned(ns), 256, size_t(tz.budget_b), st>>>(
+        LAUNCH(K_ID_B, l, k_seg_id_cols<T, 4, 2, false, 2><<<unsigned(ns), 256, size_t(tz.budget_b), st>>>(
             segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       }
       if (side[1]) {
         hipStream_t st = F->aux[1];
-        LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 4, 2, false, 3><<<unsigned(ns), 256, size_t(tz.budget_b2), st>>>(
+        LAUNCH(K_ID_B2, l, k_seg_id_cols<T, 4, 2, false, 3><<<unsigned(ns), 256, size_t(tz.budget_b2), st>>>(
             segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       }
       if (side[2]) {
         hipStream_t st = F->aux[2];
         if (T_.id_c)
-          LAUNCH_MORE(K_ID, l, k_seg_id_cols<T, 8, 2, true, 4><<<unsigned(ns), 512,
+          LAUNCH(K_ID_C, l, k_seg_id_cols<T, 8, 2, true, 4><<<unsigned(ns), 512,
                                                                  idc_lds_bytes(8, 2, 128, 0, tz.st, false), st>>>(
               segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
         if (T_.id_old)
-          LAUNCH_MORE(K_ID, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var,
+          LAUNCH(K_ID_BLK, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var,
                                                                               scr, d, prm, tz));
       }
       for (int i = 0; i < 3; ++i)
