@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="direct launches in every form")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device (4 dispatches of a plain copy kernel), to scale "
+                         "the FETCH_SIZE / WRITE_SIZE counters of a counter run")
     ap.add_argument("--restart", type=int, default=8,
                     help="refinement corrections by flexible GMRES(restart); 0: classical x += M r")
     return ap.parse_args()
@@ -113,6 +116,21 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8)
                 converged=all(r <= tol for r in res), profile=prof)
 
 
+def measured_traffic(name, form):
+    """HBM bytes per launch of kernel `name` from the committed counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
+    when there is none for this kernel and form or its sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
+    if form == "plain" or not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for src in d["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return d["traffic_bytes_per_launch"] if h.hexdigest() == d["sources_sha256"] else None
+
+
 def roofline(prof, form):
     """Dominant kernel by summed event time (the replayed solve graph, a
     composite of many kernels, is not a kernel); achieved = algorithmic bytes
@@ -125,7 +143,7 @@ def roofline(prof, form):
     tfs = fpl / (avg_ms * 1e-3) / 1e12
     peak_f = FP64_PEAK_TFS if form == "plain" else FP32_PEAK_TFS
     return dict(kernel=name, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None,
+                frac=round(gbs / HBM_PEAK_GBS, 5), traffic=measured_traffic(name, form),
                 launches=st["launches"], avg_launch_ms=round(avg_ms, 4),
                 bytes_per_launch=bpl, flops_per_launch=fpl,
                 achieved_tflops=round(tfs, 4), flop_frac=round(tfs / peak_f, 5),
@@ -162,9 +180,18 @@ def main():
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+    dev = torch.device("cuda:0")
+    if a.copy_calibration > 0:
+        nb = a.copy_calibration << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d bytes 4 times" % nb)
+        return
     from paper_2408_14193_amd import spalu as S
     from workloads import make_config
-    dev = torch.device("cuda:0")
     P = make_config(a.config, side=a.side, nrhs=a.nrhs)
     t0 = time.perf_counter()
     nd = S.ND(P.dims)
