@@ -48,7 +48,7 @@ __host__ __device__ inline size_t idc_lds_bytes(int nw, int ncol, int n, int R, 
   b += size_t(ID_MAXPROBES) * n * 8;              // probe rows
   b += size_t(nw) * idc_ic(ncol) * idc_ft(ncol) * 8;    // Gaussian tiles
   b += size_t(2) * nw * 64 * ncol * 8;            // norm and dot partials
-  b += size_t(n) * 4 + 16;                        // position -> column
+  b += size_t(2) * n * 4 + 16;                    // position <-> column
   return (b + 15) & ~size_t(15);
 }
 
@@ -235,6 +235,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
     sp += size_t(R) * 4;
   }
   int* pos2col = reinterpret_cast<int*>(sp);
+  int* col2pos = pos2col + n;
 
   // ---- 1. row table: near rows listed from the front, far rows from the back ----
   if (w == 0) {
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
         }
       }
     }
-    for (int i = tid; i < n; i += NT) pos2col[i] = i;
+    for (int i = tid; i < n; i += NT) pos2col[i] = col2pos[i] = i;
     __syncthreads();
 
     // ---- 3. CPQR (fresh norms, tie rule: smallest original column) ----
@@ -457,10 +458,11 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
       done[qs] |= 1ull << ql;
       if (tid == 0) {
         // position j takes column q; the column there moves to q's old position
-        int qp = j;
-        while (pos2col[qp] != q) ++qp;
-        pos2col[qp] = pos2col[j];
+        const int qp = col2pos[q], cj = pos2col[j];
+        pos2col[qp] = cj;
+        col2pos[cj] = qp;
         pos2col[j] = q;
+        col2pos[q] = j;
       }
       __syncthreads();
     }
