@@ -36,9 +36,10 @@ struct IdRow {
   int32_t vh;      // 2 * vertex + half (half 1: a row of A_{c,d}^T)
 };
 
-// Sampling tiles: idc_ic(NCOL) sample rows x idc_ft(NCOL) far rows per step.
+// Sampling tiles: idc_ic(NCOL) sample rows x idc_ft(NCOL) far rows per step
+// (a tile's row pairs times its far rows is 64: one Philox draw per lane).
 __host__ __device__ constexpr int idc_ic(int ncol) { return ncol == 1 ? 8 : 4; }
-__host__ __device__ constexpr int idc_ft(int ncol) { return ncol == 1 ? 16 : 8; }
+__host__ __device__ constexpr int idc_ft(int ncol) { return ncol == 1 ? 16 : 32; }
 
 // LDS bytes of one workgroup of a tier (rows_in_lds: Y, the far rows B_F in
 // the storage type (st bytes) and the row table).
