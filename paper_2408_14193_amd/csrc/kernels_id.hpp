@@ -352,27 +352,51 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
             }
             wave_sync();
           }
-          // combine the waves' partial sums in wave order
-          for (int ww = 0; ww < NW; ++ww) {
-            if (w == ww) {
+          if constexpr (NW == 1) {
 #pragma unroll
-              for (int a = 0; a < IC; ++a) {
-                if (a < ih) {
-                  const int row = i0 + a;
+            for (int a = 0; a < IC; ++a) {
+              if (a < ih) {
+                const int row = i0 + a;
 #pragma unroll
-                  for (int s = 0; s < NCOL; ++s) {
-                    const int j = lane + 64 * s;
-                    if (j < n) {
-                      double* dst = stream == 0 ? &Y[size_t(nN + row) * n + j] : &P[size_t(row) * n + j];
-                      const double prev = ww == 0 ? 0.0 : *dst;
-                      const double v = prev + acc[a][s];
-                      *dst = (ww == NW - 1 && stream == 0) ? v * sc : v;
-                    }
+                for (int s = 0; s < NCOL; ++s) {
+                  const int j = lane + 64 * s;
+                  if (j < n) {
+                    if (stream == 0)
+                      Y[size_t(nN + row) * n + j] = acc[a][s] * sc;
+                    else
+                      P[size_t(row) * n + j] = acc[a][s];
                   }
                 }
               }
             }
-            if (NW > 1) __syncthreads();
+            wave_sync();
+          } else {
+            // combine the waves' partial sums (in wave order), two rows at a
+            // time through the norm/dot partial buffers, which the CPQR
+            // only uses later: NW * 2 rows * 64 * NCOL doubles
+            double* buf = pn;
+#pragma unroll
+            for (int hf = 0; hf < IC / 2; ++hf) {
+#pragma unroll
+              for (int ra = 0; ra < 2; ++ra)
+#pragma unroll
+                for (int s = 0; s < NCOL; ++s)
+                  buf[((w * 2 + ra) * NCOL + s) * 64 + lane] = acc[2 * hf + ra][s];
+              __syncthreads();
+              for (int t = tid; t < 2 * n; t += NT) {
+                const int ra = t / n, j = t - ra * n, a = 2 * hf + ra;
+                if (a < ih) {
+                  double v = 0.0;
+                  for (int ww = 0; ww < NW; ++ww) v += buf[((ww * 2 + ra) * NCOL + (j >> 6)) * 64 + (j & 63)];
+                  const int row = i0 + a;
+                  if (stream == 0)
+                    Y[size_t(nN + row) * n + j] = v * sc;
+                  else
+                    P[size_t(row) * n + j] = v;
+                }
+              }
+              __syncthreads();
+            }
           }
         }
       }
