@@ -372,9 +372,9 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
 // sides; several segments per wave keep more memory requests in flight.
 constexpr int SOLVE_WAVE_MAX_N = 64;
 
-template <typename T>
-__host__ __device__ inline int seg_solve_grp_bytes(int P) {  // LDS of one group
-  return (8 * LEAF_SOLVE_CHUNK * P + int(sizeof(T)) * (P * (P | 1) + P * ((P / 2) | 1)) + 15) / 16 * 16;
+// LDS bytes of one group (vs: bytes of the storage type).
+__host__ __device__ inline int seg_solve_grp_bytes(int P, int vs) {
+  return (8 * LEAF_SOLVE_CHUNK * P + vs * (P * (P | 1) + P * ((P / 2) | 1)) + 15) / 16 * 16;
 }
 
 template <typename T, bool BACKWARD, int P>
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nse
   }
   if (n > P) n = 0;  // never on a level launched with this P
   const bool act = lane < n;
-  double* X = reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + size_t(grp) * seg_solve_grp_bytes<T>(P));
+  double* X = reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + size_t(grp) * seg_solve_grp_bytes(P, int(sizeof(T))));
   const int ni = n | 1, ntr = nr | 1;
   T* sI = reinterpret_cast<T*>(X + n * CH);  // n x ni
   T* sT = sI + n * ni;                       // k x ntr
@@ -510,9 +510,9 @@ __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nse
 // skeleton rows (stacked, K rows, at most rows_cap) are gathered into LDS in
 // the storage type with independent loads, and lane i forms skeleton row i
 // of the product, reading its rows of the scaled blocks directly.
-template <typename T>
-__host__ __device__ inline int sep_grp_bytes(int P, int rows_cap) {  // LDS of one group
-  return (24 * P + int(sizeof(T)) * LEAF_SOLVE_CHUNK * rows_cap + 15) / 16 * 16;
+// LDS bytes of one group (vs: bytes of the storage type).
+__host__ __device__ inline int sep_grp_bytes(int P, int rows_cap, int vs) {
+  return (24 * P + vs * LEAF_SOLVE_CHUNK * rows_cap + 15) / 16 * 16;
 }
 
 template <typename T, bool FWD, int P>
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(64) void k_sep_wave(const DSeg* segs, int nseg, con
   constexpr int CH = LEAF_SOLVE_CHUNK;
   const int lane = threadIdx.x % P, grp = threadIdx.x / P;
   const int a = blockIdx.x * (64 / P) + grp;
-  char* base = reinterpret_cast<char*>(lds) + size_t(grp) * sep_grp_bytes<T>(P, rows_cap);
+  char* base = reinterpret_cast<char*>(lds) + size_t(grp) * sep_grp_bytes(P, rows_cap, int(sizeof(T)));
   int64_t* m_dofo = reinterpret_cast<int64_t*>(base);  // neighbour e: its skeleton DOF list
   int64_t* m_soff = m_dofo + P;                        // its scaled block (owner rows)
   int* m_off = reinterpret_cast<int*>(m_soff + P);     // first stacked row

@@ -56,7 +56,6 @@ struct LevelTabs {
   IdTiers tiers{0, 0, 0, 8};
   bool id_b = false, id_b2 = false, id_c = false, id_old = false;
   int max_cap = 0;  // largest uncompressed segment
-  int sep_rows = 0;          // largest sum of neighbour caps of a segment
   int max_nbrs = 0;          // largest neighbour count of a segment
   int scale_wave_lds = 0;    // LDS doubles of the one-wave coupling scaling
   bool scale_block = false;  // some block may need the 256-thread version
@@ -103,6 +102,7 @@ struct Layout {
 struct SweepGraph {
   const void *ws, *sw, *rowptr, *colind, *vals;
   int nrhs, prec;
+  std::vector<int> shape;  // launch shapes baked in (per level: lanes, rows)
   hipGraphExec_t exec;
 };
 
@@ -131,6 +131,10 @@ struct spalu_factor_s {
   GridGeom g{};
   // per level: n, k, nr, h, passes, off (host copy after the factorization)
   std::shared_ptr<std::vector<std::vector<int32_t>>> dyn_host;
+  // launch shapes of the solve sweeps from the actual sizes, per level: lanes
+  // per segment of the lane-group kernels (0: 256-thread kernels) and the
+  // largest stacked neighbour skeleton of an owner
+  std::vector<int> solve_P, solve_rows;
   // side streams of the factorization (default priority): the size tiers of
   // a level's ID launches run concurrently, forked after the level's setup
   // and joined before its segment LU
@@ -295,9 +299,6 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
     plan_id_tiers(T, prec == SPALU_FP32 ? 4 : 8);
     for (const DSeg& D : T.segs) {
       T.max_cap = std::max(T.max_cap, int(D.cap));
-      int rows = 0;
-      for (int e = D.nbr_begin; e < D.nbr_end; ++e) rows += T.segs[T.nbrs[e].d].cap;
-      T.sep_rows = std::max(T.sep_rows, rows);
       T.max_nbrs = std::max(T.max_nbrs, int(D.nbr_end - D.nbr_begin));
     }
     {
@@ -825,6 +826,29 @@ int read_dyn_host(spalu_factor_t* F) {
     std::memcpy((*dh)[l].data(), raw.data() + (Y.lv[l].o_dyn - lo), (*dh)[l].size() * 4);
   }
   F->dyn_host = dh;
+  // lane groups of P = 8..64 lanes for levels whose segments and neighbour
+  // counts fit P and whose staging fits 64 KB of LDS
+  F->solve_P.assign(size_t(L) + 1, 0);
+  F->solve_rows.assign(size_t(L) + 1, 1);
+  const int vs = int(Y.vsize);
+  for (int l = 1; l <= L; ++l) {
+    const LevelTabs& T = Y.lv[l];
+    const size_t ns = T.segs.size();
+    const int32_t* nv = (*dh)[l].data();
+    const int32_t* kv = nv + ns;
+    int mx = T.max_nbrs, rows = 1;
+    for (size_t c = 0; c < ns; ++c) {
+      mx = std::max(mx, int(nv[c]));
+      int r = 0;
+      for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) r += kv[T.nbrs[e].d];
+      rows = std::max(rows, r);
+    }
+    const int P = mx <= 8 ? 8 : mx <= 16 ? 16 : mx <= 32 ? 32 : mx <= 64 ? 64 : 0;
+    if (P && size_t(64 / P) * seg_solve_grp_bytes(P, vs) <= 65536 &&
+        size_t(64 / P) * sep_grp_bytes(P, rows, vs) <= 65536)
+      F->solve_P[l] = P;
+    F->solve_rows[l] = rows;
+  }
   return SPALU_OK;
 }
 
@@ -1085,17 +1109,13 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
   LAUNCH(K_SEPLEAF, 0, k_sep_from_leaves<T><<<nblocks(nsep * nrhs), WG, 0, st>>>(
       nsep, tab<int32_t>(ws, Y.o_sepv), tab<int8_t>(ws, Y.o_seplev), F->rowptr, F->colind, F->vals, B0, Z, W,
       nrhs));
-  // levels whose segments hold at most 64 DOFs (with at most as many
-  // neighbours) take the lane-group kernels, P lanes per segment
-  auto group_lanes = [](const LevelTabs& T_) {
-    const int m = std::max(T_.max_cap, T_.max_nbrs);
-    return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : m <= 64 ? 64 : 0;
-  };
+  // levels whose segments (by their actual sizes) fit lane groups of P
+  // lanes take the lane-group kernels
   auto seg_solve_grp = [&](const LevelTabs& T_, int l, int P, bool bwd, DLevelDyn d) {
     const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
     const int ns = int(T_.segs.size());
     const unsigned nb = unsigned((ns + 64 / P - 1) / (64 / P));
-    const size_t lb = size_t(64 / P) * seg_solve_grp_bytes<T>(P);
+    const size_t lb = size_t(64 / P) * seg_solve_grp_bytes(P, int(sizeof(T)));
 #define SPALU_SSG(PP)                                                                                          \
   if (bwd)                                                                                                     \
     LAUNCH(K_SSOLVE_B, l, k_seg_solve_wave<T, true, PP><<<nb, 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs));  \
@@ -1110,9 +1130,9 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
     const DNbr* nbr = tab<DNbr>(ws, T_.o_nbrs);
     const DBlk* bk = tab<DBlk>(ws, T_.o_blks);
     const int ns = int(T_.segs.size());
-    const int rc = std::max(T_.sep_rows, 1);
+    const int rc = F->solve_rows[l];
     const unsigned nb = unsigned((ns + 64 / P - 1) / (64 / P));
-    const size_t lb = size_t(64 / P) * sep_grp_bytes<T>(P, rc);
+    const size_t lb = size_t(64 / P) * sep_grp_bytes(P, rc, int(sizeof(T)));
 #define SPALU_SG(PP)                                                                                           \
   if (bwd)                                                                                                     \
     LAUNCH(K_SEPBWD, l, k_sep_wave<T, false, PP><<<nb, 64, lb, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs, rc)); \
@@ -1122,16 +1142,12 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
 #undef SPALU_SG
     return int(SPALU_OK);
   };
-  auto grp_ok = [&](const LevelTabs& T_, int P) {
-    return P > 0 && size_t(64 / P) * seg_solve_grp_bytes<T>(P) <= 65536 &&
-           size_t(64 / P) * sep_grp_bytes<T>(P, std::max(T_.sep_rows, 1)) <= 65536;
-  };
   for (int l = L; l >= 1; --l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
     DLevelDyn d = dyn_of(ws, Y, l);
-    const int P = group_lanes(T_);
-    if (grp_ok(T_, P)) {
+    const int P = F->solve_P[l];
+    if (P) {
       if (const int rc = seg_solve_grp(T_, l, P, false, d)) return rc;
       if (const int rc = sep_grp(T_, l, P, false, d)) return rc;
     } else {
@@ -1145,8 +1161,8 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
     DLevelDyn d = dyn_of(ws, Y, l);
-    const int P = group_lanes(T_);
-    if (grp_ok(T_, P)) {
+    const int P = F->solve_P[l];
+    if (P) {
       if (const int rc = sep_grp(T_, l, P, true, d)) return rc;
       if (const int rc = seg_solve_grp(T_, l, P, true, d)) return rc;
     } else {
@@ -1174,9 +1190,11 @@ int apply(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, const char* sw, 
   if (!graph) return apply_inverse<T>(F, B0, W, Z, nrhs, st);
   spalu_nd_t* nd = const_cast<spalu_nd_t*>(F->nd);
   hipGraphExec_t exec = nullptr;
+  std::vector<int> shape(F->solve_P);
+  shape.insert(shape.end(), F->solve_rows.begin(), F->solve_rows.end());
   for (auto& gph : nd->graphs)
     if (gph.ws == F->ws && gph.sw == sw && gph.rowptr == F->rowptr && gph.colind == F->colind &&
-        gph.vals == F->vals && gph.nrhs == nrhs && gph.prec == F->prec)
+        gph.vals == F->vals && gph.nrhs == nrhs && gph.prec == F->prec && gph.shape == shape)
       exec = gph.exec;
   if (!exec) {
     if (!nd->capture_stream) HIPCHK(hipStreamCreateWithFlags(&nd->capture_stream, hipStreamNonBlocking));
@@ -1200,7 +1218,7 @@ int apply(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, const char* sw, 
       (void)hipGraphExecDestroy(nd->graphs.front().exec);
       nd->graphs.erase(nd->graphs.begin());
     }
-    nd->graphs.push_back(SweepGraph{F->ws, sw, F->rowptr, F->colind, F->vals, nrhs, F->prec, exec});
+    nd->graphs.push_back(SweepGraph{F->ws, sw, F->rowptr, F->colind, F->vals, nrhs, F->prec, shape, exec});
   }
   const int pi = prof_begin(K_APPLY, 0, st);
   HIPCHK(hipGraphLaunch(exec, st));
@@ -1491,7 +1509,7 @@ void spalu_factor_opts_default(spalu_factor_opts* o) {
   o->h_init = nullptr;
   o->rank_model = nullptr;
   o->features_out = nullptr;
-  o->rank_margin = 1.1f;
+  o->rank_margin = 1.0f;
   o->rank_pad = 5;
 }
 
