@@ -404,8 +404,8 @@ __global__ void k_init_level(const DSeg* segs, int nseg, const int32_t* verts_pt
 }
 
 // Level-L blocks: A restricted to (c, d) minus the leaf Schur contributions.
-template <typename T>
-__global__ __launch_bounds__(WG) void k_assemble_leafL(const DBlk* blks, int nblk, const DSeg* segs,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_assemble_leafL(const DBlk* blks, int nblk, const DSeg* segs,
                                                        const int32_t* iarena_c, const DLevelDyn dyn,
                                                        const int32_t* lc_ptr, const DLeafContrib* lc,
                                                        const DLeaf* leaves, const int64_t* rowptr,
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(WG) void k_assemble_leafL(const DBlk* blks, int nbl
   const int32_t* dc = iarena_c + segs[B.c].ioff;
   const int32_t* dd = iarena_c + segs[B.d].ioff;
   T* out = varena + B.off;
-  for (int t = threadIdx.x; t < nc * nd; t += WG) {
+  for (int t = threadIdx.x; t < nc * nd; t += NT) {
     const int i = t / nd, j = t % nd;
     double v = csr_at(rowptr, colind, vals, dc[i], dd[j]);
     for (int q = lc_ptr[b]; q < lc_ptr[b + 1]; ++q) {
@@ -881,8 +881,8 @@ __global__ void k_merge_sizes(const DSeg* useg, int nuseg, const int32_t* cons_p
 // Separator elimination fused with the merge: every level-(l-1) block is
 // assembled from identity / scaled level-l blocks minus A'_{c,s} A'_{s,d}
 // for the level-l separators s next to both c and d (Z_l, Z_u, E_(l)).
-template <typename T>
-__global__ __launch_bounds__(WG) void k_merge_elim(const DBlk* ublks, int nublk, const int32_t* task_ptr,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk, const int32_t* task_ptr,
                                                    const DTask* tasks, const DSepTerm* terms,
                                                    const DBlk* blks, T* varena, DLevelDyn dyn,
                                                    DLevelDyn udyn) {
@@ -892,14 +892,14 @@ __global__ __launch_bounds__(WG) void k_merge_elim(const DBlk* ublks, int nublk,
   const DBlk U = ublks[b];
   const int nC = udyn.n[U.c], nD = udyn.n[U.d];
   T* out = varena + U.off;
-  for (int t = tid; t < nC * nD; t += WG) out[t] = T(0);
+  for (int t = tid; t < nC * nD; t += NT) out[t] = T(0);
   __syncthreads();
   for (int q = task_ptr[b]; q < task_ptr[b + 1]; ++q) {
     const DTask tk = tasks[q];
     const int kc = dyn.k[tk.c], kd = dyn.k[tk.d];
     const int oc = dyn.off[tk.c], od = dyn.off[tk.d];
     const T* src = tk.src >= 0 ? varena + blks[tk.src].soff : nullptr;
-    for (int t = tid; t < kc * kd; t += WG) {
+    for (int t = tid; t < kc * kd; t += NT) {
       const int i = t / kd, j = t % kd;
       double v = tk.src == -2 ? (i == j ? 1.0 : 0.0) : (src ? double(src[t]) : 0.0);
       for (int e = tk.sep_begin; e < tk.sep_end; ++e) {

@@ -917,10 +917,17 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
             lt, int(nl), F->g, F->rowptr, F->colind, F->vals, iar, var, scr, int64_t(Y.leaf_scr_stride), status));
       }
     }
-    LAUNCH(K_ASM, L, k_assemble_leafL<T><<<unsigned(TL.blks.size()), WG, 0, st>>>(
-        tab<DBlk>(ws, TL.o_blks), int(TL.blks.size()), tab<DSeg>(ws, TL.o_segs), iar, dL,
-        tab<int32_t>(ws, Y.o_lc_ptr), tab<DLeafContrib>(ws, Y.o_lc), tab<DLeaf>(ws, Y.o_leaves),
-        F->rowptr, F->colind, F->vals, var));
+    // blocks of small segments: one wave each
+    if (TL.max_cap <= 32)
+      LAUNCH(K_ASM, L, k_assemble_leafL<T, 64><<<unsigned(TL.blks.size()), 64, 0, st>>>(
+          tab<DBlk>(ws, TL.o_blks), int(TL.blks.size()), tab<DSeg>(ws, TL.o_segs), iar, dL,
+          tab<int32_t>(ws, Y.o_lc_ptr), tab<DLeafContrib>(ws, Y.o_lc), tab<DLeaf>(ws, Y.o_leaves),
+          F->rowptr, F->colind, F->vals, var));
+    else
+      LAUNCH(K_ASM, L, k_assemble_leafL<T, WG><<<unsigned(TL.blks.size()), WG, 0, st>>>(
+          tab<DBlk>(ws, TL.o_blks), int(TL.blks.size()), tab<DSeg>(ws, TL.o_segs), iar, dL,
+          tab<int32_t>(ws, Y.o_lc_ptr), tab<DLeafContrib>(ws, Y.o_lc), tab<DLeaf>(ws, Y.o_leaves),
+          F->rowptr, F->colind, F->vals, var));
   }
   for (int l = L; l >= 1; --l) {
     const LevelTabs& T_ = Y.lv[l];
@@ -1033,9 +1040,15 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       LAUNCH(K_MSIZE, l, k_merge_sizes<<<unsigned(U.segs.size()), 64, 0, st>>>(
           tab<DSeg>(ws, U.o_segs), int(U.segs.size()), tab<int32_t>(ws, T_.o_cons_ptr),
           tab<int32_t>(ws, T_.o_cons), segs, iar, d, du));
-      LAUNCH(K_MELIM, l, k_merge_elim<T><<<unsigned(U.blks.size()), WG, 0, st>>>(
-          tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
-          tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du));
+      // blocks of small segments: one wave each
+      if (U.max_cap <= 32)
+        LAUNCH(K_MELIM, l, k_merge_elim<T, 64><<<unsigned(U.blks.size()), 64, 0, st>>>(
+            tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
+            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du));
+      else
+        LAUNCH(K_MELIM, l, k_merge_elim<T, WG><<<unsigned(U.blks.size()), WG, 0, st>>>(
+            tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
+            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du));
     }
   }
   HIPCHK(hipMemcpyAsync(status_host, status, 4, hipMemcpyDeviceToHost, st));
