@@ -189,9 +189,9 @@ void plan_id_tiers(LevelTabs& T, int st) {
     beyond_b2 = true;
     if (cap > 128) wide = true;
   }
-  // a tier's budget is the largest bound among the segments that fit it:
   // segments beyond a tier by bound may still land in it by their actual
-  // sizes, and a tight budget keeps more groups per CU
+  // sizes: such levels give the tier its full budget
+  if (beyond_a) a = ID_A_MAX_BYTES;
   if (beyond_b) b = ID_B_MAX_BYTES;
   if (beyond_b2) b2 = ID_B2_MAX_BYTES;
   T.tiers.st = st;
