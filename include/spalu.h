@@ -124,7 +124,7 @@ typedef struct {
   float* features_out;   /* optional device array (segments x 12 floats,
                             index seg_base[l] + c) receiving every level's
                             predictor features (training data)            */
-  float rank_margin;     /* default 1.1                                     */
+  float rank_margin;     /* default 1.0                                     */
   int32_t rank_pad;      /* default 5 (the oversampling p of Section 4.2.3) */
 } spalu_factor_opts;
 
@@ -142,7 +142,7 @@ typedef struct {
 } spalu_factor_info;
 
 /* Default options (eps 1e-6, FP64, seed 1234, rho 0.5, h0 8, 5 probes,
- * tau 10, no rank predictor, margin 1.1, pad 5). */
+ * tau 10, no rank predictor, margin 1.0, pad 5). */
 void spalu_factor_opts_default(spalu_factor_opts* o);
 
 /* Bytes of device workspace that spalu_factor needs for this ND and

@@ -186,7 +186,7 @@ class ND:
 
 
 def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, tau=10.0,
-                h_init=None, rank_model=None, features_out=None, rank_margin=1.1, rank_pad=5):
+                h_init=None, rank_model=None, features_out=None, rank_margin=1.0, rank_pad=5):
     o = FactorOpts()
     _lib.spalu_factor_opts_default(C.byref(o))
     o.eps, o.precision, o.seed, o.rho, o.h0, o.probes, o.tau = (
