@@ -730,9 +730,23 @@ __global__ __launch_bounds__(WG) void k_residual(int64_t n, int nrhs, const int6
   const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
   double r = 0.0, b = 0.0;
   if (v < n) {
+    // the row's stencil entries (at most 8) read together, then the products
+    constexpr int ME = 8;
+    const int64_t e0 = rowptr[v], e1 = rowptr[v + 1];
+    const double* x = X + j * ldx;
     b = B[v + j * ldb];
+    int cols[ME];
+    double vv[ME];
+#pragma unroll
+    for (int m = 0; m < ME; ++m) {
+      const bool in = e0 + m < e1;
+      cols[m] = in ? colind[e0 + m] : int(v);
+      vv[m] = in ? vals[e0 + m] : 0.0;
+    }
     double ax = 0.0;
-    for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) ax += vals[e] * X[colind[e] + j * ldx];
+#pragma unroll
+    for (int m = 0; m < ME; ++m) ax += vv[m] * x[cols[m]];
+    for (int64_t e = e0 + ME; e < e1; ++e) ax += vals[e] * x[colind[e]];  // rows longer than ME
     r = b - ax;
     R[v + j * n] = r;
   }
@@ -765,15 +779,31 @@ __global__ __launch_bounds__(WG) void k_reduce_cols(const double* part, int nblk
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int kstate_doubles(int m) { return (m + 1) * m + 2 * m + (m + 1) + m + 1; }
 
-// Wc = A Zc (column-major, ld n).
-__global__ __launch_bounds__(WG) void k_spmv(int64_t n, const int64_t* rowptr, const int32_t* colind,
+// Wc = A Zc (column-major, ld n): one thread per row; the row's stencil
+// entries (at most 8) are read once into registers, then every right-hand
+// side in turn, its loads independent of each other.
+__global__ __launch_bounds__(WG) void k_spmv(int64_t n, int nrhs, const int64_t* rowptr, const int32_t* colind,
                                              const double* vals, const double* Zc, double* Wc) {
-  const int j = blockIdx.y;
+  constexpr int ME = 8;
   const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
   if (v >= n) return;
-  double ax = 0.0;
-  for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) ax += vals[e] * Zc[colind[e] + j * n];
-  Wc[v + j * n] = ax;
+  const int64_t e0 = rowptr[v], e1 = rowptr[v + 1];
+  int cols[ME];
+  double vv[ME];
+#pragma unroll
+  for (int m = 0; m < ME; ++m) {
+    const bool in = e0 + m < e1;
+    cols[m] = in ? colind[e0 + m] : int(v);
+    vv[m] = in ? vals[e0 + m] : 0.0;
+  }
+  for (int j = 0; j < nrhs; ++j) {
+    const double* z = Zc + size_t(j) * n;
+    double ax = 0.0;
+#pragma unroll
+    for (int m = 0; m < ME; ++m) ax += vv[m] * z[cols[m]];
+    for (int64_t e = e0 + ME; e < e1; ++e) ax += vals[e] * z[colind[e]];  // rows longer than ME
+    Wc[v + size_t(j) * n] = ax;
+  }
 }
 
 // Row-block partial sums of <w_j, V_i[:, j]> for i < cnt (blockIdx.z = i) and

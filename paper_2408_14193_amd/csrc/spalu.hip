@@ -1341,7 +1341,7 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
       if (rc) return rc;
       LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, Zc, F->n, 0));
       ++it;
-      LAUNCH(K_SPMV, 0, k_spmv<<<vgrid, WG, 0, st>>>(F->n, F->rowptr, F->colind, F->vals, Zc, R));
+      LAUNCH(K_SPMV, 0, k_spmv<<<s.rblk, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Zc, R));
       for (int pass = 0; pass < 2; ++pass) {
         double* h = pass == 0 ? h1 : h2;
         LAUNCH(K_KRYLOV, c + 1, k_kdots<<<dim3(s.rblk, unsigned(nrhs), unsigned(c + 2)), WG, 0, st>>>(F->n, nrhs, V,
