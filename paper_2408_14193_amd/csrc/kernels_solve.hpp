@@ -256,7 +256,10 @@ __global__ void k_sep_from_leaves(int64_t nsep, const int32_t* sepv, const int8_
 
 // Per segment of level l: forward (U_T, then P and L^{-1}) or backward
 // (U^{-1}, then L_T) on its DOFs in [remainder; skeleton] order, with the
-// packed inverses of the two-stage LU (and T) staged in LDS when they fit.
+// packed inverses of the two-stage LU (and T) staged in LDS, in the storage
+// type, when they fit SEG_SOLVE_LDS_BYTES beside two right-hand-side columns.
+constexpr int SEG_SOLVE_LDS_BYTES = 65536;
+
 template <typename T, bool BACKWARD>
 __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, const int32_t* iarena,
                                                   const T* varena, DLevelDyn dyn, T* W, int nrhs) {
@@ -274,21 +277,22 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
   const T* Inv = varena + S.lu_off;
   const T* Tm = varena + S.t_off;
   const int nt = sp ? k * nr : 0;
-  const bool stage = n * n + nt + 2 * n <= LDS_DOUBLES;
-  if (!stage && 2 * n > LDS_DOUBLES) {
+  const int sbytes = ((n * n + nt) * int(sizeof(T)) + 15) & ~15;  // staged inverse and T
+  const bool stage = sbytes + 2 * n * 8 <= SEG_SOLVE_LDS_BYTES;
+  if (!stage && 2 * n * 8 > SEG_SOLVE_LDS_BYTES) {
     // too large for the staging buffer: poison the result so the residual
     // check reports the failure instead of returning a wrong solution
     for (int t = tid; t < n * nrhs; t += WG) W[size_t(dofs[t / nrhs]) * nrhs + t % nrhs] = T(NAN);
     return;
   }
-  double* sI = lds;                      // packed inverse (staged)
-  double* sT = lds + n * n;              // T (staged)
-  double* X = stage ? sT + nt : lds;
-  const int room = stage ? LDS_DOUBLES - n * n - nt : LDS_DOUBLES;
+  T* sI = reinterpret_cast<T*>(lds);  // packed inverse (staged)
+  T* sT = sI + n * n;                 // T (staged)
+  double* X = stage ? reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + sbytes) : lds;
+  const int room = (SEG_SOLVE_LDS_BYTES - (stage ? sbytes : 0)) / 8;
   const int jc = room / (2 * n) < nrhs ? room / (2 * n) : nrhs;
   if (stage) {
-    for (int t = tid; t < n * n; t += WG) sI[t] = double(Inv[t]);
-    for (int t = tid; t < nt; t += WG) sT[t] = double(Tm[t]);
+    stage_batched<8>(Inv, n * n, tid, WG, [&](int t, T v) { sI[t] = v; });
+    if (nt > 0) stage_batched<8>(Tm, nt, tid, WG, [&](int t, T v) { sT[t] = v; });
   }
   for (int j0 = 0; j0 < nrhs; j0 += jc) {
     const int nc = nrhs - j0 < jc ? nrhs - j0 : jc;
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
         const int i = t / nc, j = t % nc;
         double v = X[t];
         if (stage) {
-          const double* row = sI + i * n;
+          const T* row = sI + i * n;
           for (int u = 0; u < i; ++u) v += row[u] * X[size_t(u) * nc + j];
         } else {
           const T* row = Inv + size_t(i) * n;
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
         const int i = t / nc, j = t % nc;
         double v = 0.0;
         if (stage) {
-          const double* row = sI + i * n;
+          const T* row = sI + i * n;
           for (int u = i; u < n; ++u) v += row[u] * X[size_t(u) * nc + j];
         } else {
           const T* row = Inv + size_t(i) * n;

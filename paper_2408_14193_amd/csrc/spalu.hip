@@ -1165,7 +1165,7 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
       if (const int rc = sep_grp(T_, l, P, false, d)) return rc;
     } else {
       const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
-      LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, LDS_BYTES, st>>>(sg, ns, iar, var, d, W, nrhs));
+      LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
       LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
                                                                    tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
     }
@@ -1182,7 +1182,7 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
       const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
       LAUNCH(K_SEPBWD, l, k_sep_bwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
                                                                    tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
-      LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, LDS_BYTES, st>>>(sg, ns, iar, var, d, W, nrhs));
+      LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
     }
   }
   if (wave_leaf) {
