@@ -10,6 +10,49 @@
 
 namespace spalu {
 
+// store(t, load(t)) for t in [0, count), t = lane + stride * m: the loads
+// of a batch of NB are issued together, so a staging loop costs one trip to
+// memory per batch instead of one per load; a last batch of one row loads
+// that row only.
+template <int NB, typename L, typename F>
+__device__ inline void load_batched(int count, int lane, int stride, L load, F store) {
+  using V = decltype(load(0));
+  int t0 = 0;
+  for (; t0 + NB * stride <= count; t0 += NB * stride) {
+    V v[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) v[b] = load(t0 + b * stride + lane);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) store(t0 + b * stride + lane, v[b]);
+  }
+  if (t0 < count) {
+    // the last, partial batch: only the rows of the range are loaded
+    // when they fit in one row, else all NB with clamped indices
+    if (count - t0 <= stride) {
+      const int t = t0 + lane;
+      if (t < count) store(t, load(t));
+    } else {
+      V v[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int t = t0 + b * stride + lane;
+        v[b] = load(t < count ? t : count - 1);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int t = t0 + b * stride + lane;
+        if (t < count) store(t, v[b]);
+      }
+    }
+  }
+}
+
+// store(t, src[t]) for t in [0, count), in batches as above.
+template <int NB, typename S, typename F>
+__device__ inline void stage_batched(const S* src, int count, int lane, int stride, F store) {
+  load_batched<NB>(count, lane, stride, [&](int t) { return src[t]; }, store);
+}
+
 struct GridGeom {
   int nx, ny, nz;
 };
@@ -444,6 +487,112 @@ struct IdParams {
   const int32_t* h_init;  // optional start samples (learned form)
 };
 
+// LU with partial pivoting of the row-major n x n A (in place) by one block,
+// three barriers per step and no division per trailing element: the update
+// scales the pivot row by 1 / A[j][j] and reads column j unscaled, and
+// column j is divided by its pivot in the next step, by all threads, while
+// wave 0 searches the next pivot.  Steps j < split search rows [j, split),
+// later steps rows [j, n); ties go to the smaller row.  piv[j] = row swapped
+// with row j.  Returns 1 if a pivot was zero (that step is skipped).
+__device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s_piv) {
+  const int tid = threadIdx.x;
+  int singular = 0;
+  double dprev = 0.0;  // pivot of the previous step (0: nothing to scale)
+  for (int j = 0; j < n; ++j) {
+    if (tid < 64) {
+      const int hi = j < split ? split : n;
+      double bv = -1.0;
+      int bi = 1 << 30;
+      for (int i = j + tid; i < hi; i += 64) {
+        const double a = fabs(A[i * n + j]);
+        if (a > bv) {
+          bv = a;
+          bi = i;
+        }
+      }
+      wave_argmax(bv, bi);
+      if (tid == 0) *s_piv = bi < n ? bi : j;
+    }
+    if (dprev != 0.0)
+      for (int i = j + tid; i < n; i += WG) A[i * n + j - 1] /= dprev;
+    __syncthreads();
+    const int p = *s_piv;
+    if (p != j)
+      for (int c = tid; c < n; c += WG) {
+        const double t = A[j * n + c];
+        A[j * n + c] = A[p * n + c];
+        A[p * n + c] = t;
+      }
+    if (tid == 0) piv[j] = p;
+    __syncthreads();
+    const double d = A[j * n + j];
+    dprev = d;
+    if (d == 0.0) {
+      singular = 1;
+      continue;  // uniform; column j stays unscaled
+    }
+    const int m = n - j - 1;
+    if (m > 0 && m <= WG) {
+      const int rstep = WG / m, r0 = tid / m, col = j + 1 + (tid - r0 * m);
+      if (r0 < rstep) {
+        const double u = A[j * n + col] / d;
+        for (int i = j + 1 + r0; i < n; i += rstep) A[i * n + col] -= A[i * n + j] * u;
+      }
+    } else if (m > WG) {
+      for (int col = j + 1 + tid; col < n; col += WG) {
+        const double u = A[j * n + col] / d;
+        for (int i = j + 1; i < n; ++i) A[i * n + col] -= A[i * n + j] * u;
+      }
+    }
+    __syncthreads();
+  }
+  // column n-1 has no rows below its pivot
+  return singular;
+}
+
+// Packed inverses of the unit-lower L and upper U held in W (row-major
+// n x n): out[i][c] = (L^{-1})[i][c] for i > c, (U^{-1})[i][c] for i <= c.
+// L^{-1} by forward elimination of the identity and U^{-1} = (D^{-1} U)^{-1}
+// D^{-1} by back elimination, both in X (n x n): step s eliminates column s
+// of L and column n-1-s of U (disjoint triangles of X, one barrier per
+// step).  The diagonal of X holds 1 / U[i][i]; the unit diagonals are
+// implied.
+template <typename TO>
+__device__ inline void seg_block_inverse(const double* W, int n, double* X, TO* out) {
+  const int tid = threadIdx.x;
+  for (int t = tid; t < n * n; t += WG) {
+    const int i = t / n, c = t - i * n;
+    X[t] = i == c ? 1.0 / W[t] : 0.0;
+  }
+  __syncthreads();
+  for (int s = 0; s < n - 1; ++s) {
+    const int jl = s, ju = n - 1 - s;
+    const int R = n - 1 - s, C = s + 1;  // rows and columns of both updates
+    for (int c0 = 0; c0 < C; c0 += WG) {
+      const int cw = C - c0 < WG ? C - c0 : WG;
+      const int rstep = WG / cw, r0 = tid / cw, cq = c0 + tid - r0 * cw;
+      if (r0 < rstep) {
+        // L: X[jl+1+r][cq] -= L[jl+1+r][jl] X[jl][cq]  (X[jl][jl] = 1)
+        const double xl = cq == jl ? 1.0 : X[jl * n + cq];
+        // U: X[r][ju+cq] -= (U[r][ju] / U[r][r]) X[ju][ju+cq]  (X[ju][ju] = 1)
+        const int cu = ju + cq;
+        const double xu = cq == 0 ? 1.0 : X[ju * n + cu];
+        for (int r = r0; r < R; r += rstep) {
+          const int il = jl + 1 + r;
+          X[il * n + cq] -= W[il * n + jl] * xl;
+          X[r * n + cu] -= W[r * n + ju] * X[r * n + r] * xu;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < n * n; t += WG) {
+    const int i = t / n, c = t - i * n;
+    out[t] = TO(i > c ? X[t] : (i == c ? 1.0 : X[t]) * X[c * n + c]);
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // Transform U_t A L_t of the diagonal block and two-stage LU (eqs. (2.7),
 // (4.10)); the DOF list is reordered to [remainder; skeleton].
@@ -474,30 +623,38 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   const T* M = varena + blks[S.diag_blk].off;
   const bool inlds = need <= lds_doubles;
   double* W = inlds ? lds : scratch + S.scr_off;
-  double* X = W + size_t(n) * n;  // inverse workspace
-  // gather in [r; s] order: o[p] = perm[k + p] (p < nr), perm[p - nr]
-  for (int t = tid; t < n * n; t += WG) {
-    const int p = t / n, q = t % n;
-    const int op = sp ? (p < nr ? perm[k + p] : perm[p - nr]) : p;
-    const int oq = sp ? (q < nr ? perm[k + q] : perm[q - nr]) : q;
-    W[t] = double(M[size_t(op) * n + oq]);
-  }
+  double* X = W + size_t(n) * n;  // gather map, then T, then the inverse workspace
+  int* om = reinterpret_cast<int*>(X);
+  // gather in [r; s] order: row/column p of W is om[p] = perm[k + p]
+  // (p < nr), perm[p - nr] (p >= nr) of the block; the block's entries are
+  // loaded in batches
+  for (int p = tid; p < n; p += WG) om[p] = sp ? (p < nr ? perm[k + p] : perm[p - nr]) : p;
+  __syncthreads();
+  load_batched<8>(
+      n * n, tid, WG,
+      [&](int t) {
+        const int p = t / n, q = t - p * n;
+        return M[size_t(om[p]) * n + om[q]];
+      },
+      [&](int t, T v) { W[t] = double(v); });
   __syncthreads();
   if (sp && nr > 0 && k > 0) {
-    const T* Tm = varena + S.t_off;  // k x nr
+    // T (k x nr) staged next to W
+    stage_batched<8>(varena + S.t_off, k * nr, tid, WG, [&](int t, T v) { X[t] = double(v); });
+    __syncthreads();
     // columns: W[:, q] -= W[:, nr:] T[:, q]
     for (int t = tid; t < n * nr; t += WG) {
-      const int p = t / nr, q = t % nr;
+      const int p = t / nr, q = t - p * nr;
       double s = 0.0;
-      for (int i = 0; i < k; ++i) s += W[size_t(p) * n + nr + i] * double(Tm[size_t(i) * nr + q]);
+      for (int i = 0; i < k; ++i) s += W[size_t(p) * n + nr + i] * X[i * nr + q];
       W[size_t(p) * n + q] -= s;
     }
     __syncthreads();
     // rows: W[p, :] -= T[:, p]^T W[nr:, :]
     for (int t = tid; t < nr * n; t += WG) {
-      const int p = t / n, q = t % n;
+      const int p = t / n, q = t - p * n;
       double s = 0.0;
-      for (int i = 0; i < k; ++i) s += double(Tm[size_t(i) * nr + p]) * W[size_t(nr + i) * n + q];
+      for (int i = 0; i < k; ++i) s += X[i * nr + p] * W[size_t(nr + i) * n + q];
       W[size_t(p) * n + q] -= s;
     }
     __syncthreads();
@@ -506,7 +663,7 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   // would stall each step), copied out afterwards
   const bool pv_lds = inlds && need + (n + 1) / 2 <= lds_doubles;
   int* pv = pv_lds ? reinterpret_cast<int*>(lds + need) : piv;
-  if (block_lu_window(W, n, n, sp ? nr : 0, pv, &s_piv)) atomicOr(status, 1);
+  if (seg_block_lu(W, n, sp ? nr : 0, pv, &s_piv)) atomicOr(status, 1);
   __syncthreads();
   // stored form of the interchanges: the composed row map (row i of P X is
   // row piv[i] of X), each entry traced back through the interchanges
@@ -524,7 +681,7 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   // packed inverses: strictly lower part of L^{-1} (unit diagonal implied)
   // and upper part of U^{-1}, so every later application is a product
   T* LU = varena + S.lu_off;
-  block_packed_inverse(W, n, X, LU);
+  seg_block_inverse(W, n, X, LU);
   if (sp) {
     for (int p = tid; p < n; p += WG) tmp[p] = dofs[p < nr ? perm[k + p] : perm[p - nr]];
     __syncthreads();
@@ -532,21 +689,24 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   }
 }
 
-// One wave per segment of at most 64 DOFs (lane = column): the transform
-// and the two-stage LU of k_seg_lu with wave-level synchronisation only, and
-// every column of L^{-1} and U^{-1} computed by its own lane.  W and X
-// (n x n each, row-major) live in this wave's LDS.
-template <typename T>
+// One wave per segment of at most 64 * CPL DOFs, lane l owning columns (and
+// rows) l, l + 64, ...: the transform and the two-stage LU of k_seg_lu with
+// wave-level synchronisation only, then the packed inverses formed in place.
+// LDS: W (n x n, row-major), then T (k x nr), which first holds the gather
+// map.  Segments with nmin < n <= nmax take part.
+__host__ __device__ inline int seglu_wave_lds_doubles(int nw) { return nw * nw + (nw * nw + 3) / 4 + 1; }
+
+template <typename T, int CPL>
 __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, const DBlk* blks,
                                                     int32_t* iarena, T* varena, DLevelDyn dyn, int* status,
-                                                    int nmax) {
+                                                    int nmin, int nmax) {
   extern __shared__ double lds[];
   const int c = blockIdx.x;
   if (c >= nseg) return;
   const int lane = threadIdx.x;
   const DSeg S = segs[c];
   const int n = dyn.n[c];
-  if (n == 0 || n > nmax) return;
+  if (n == 0 || n <= nmin || n > nmax) return;
   const int k = dyn.k[c], nr = dyn.nr[c];
   const bool sp = dyn.passes[c] > 0;
   int32_t* dofs = iarena + S.ioff;
@@ -555,58 +715,100 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
   const T* M = varena + blks[S.diag_blk].off;
   double* W = lds;
   double* X = lds + size_t(n) * n;
-  // gather in [r; s] order: o[p] = perm[k + p] (p < nr), perm[p - nr]
-  for (int t = lane; t < n * n; t += 64) {
-    const int p = t / n, q = t - p * n;
-    const int op = sp ? (p < nr ? perm[k + p] : perm[p - nr]) : p;
-    const int oq = sp ? (q < nr ? perm[k + q] : perm[q - nr]) : q;
-    W[t] = double(M[size_t(op) * n + oq]);
+  int* om = reinterpret_cast<int*>(X);
+  // gather in [r; s] order: row/column p of W is om[p] = perm[k + p]
+  // (p < nr), perm[p - nr] (p >= nr) of the block
+  {
+    int ov[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int p = lane + 64 * u < n ? lane + 64 * u : n - 1;
+      ov[u] = sp ? (p < nr ? perm[k + p] : perm[p - nr]) : p;
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      if (lane + 64 * u < n) om[lane + 64 * u] = ov[u];
   }
   wave_sync();
+  load_batched<8>(
+      n * n, lane, 64,
+      [&](int t) {
+        const int p = t / n, q = t - p * n;
+        return M[size_t(om[p]) * n + om[q]];
+      },
+      [&](int t, T v) { W[t] = double(v); });
+  wave_sync();
   if (sp && nr > 0 && k > 0) {
-    // T (k x nr) staged in X
     const T* Tm = varena + S.t_off;
-    for (int t = lane; t < k * nr; t += 64) X[t] = double(Tm[t]);
+    load_batched<8>(k * nr, lane, 64, [&](int t) { return Tm[t]; }, [&](int t, T v) { X[t] = double(v); });
     wave_sync();
-    // columns: W[:, q] -= W[:, nr:] T[:, q]  (lane q < nr)
-    if (lane < nr)
-      for (int p = 0; p < n; ++p) {
-        double s = 0.0;
-        for (int i = 0; i < k; ++i) s += W[p * n + nr + i] * X[i * nr + lane];
-        W[p * n + lane] -= s;
-      }
+    // columns: W[:, q] -= W[:, nr:] T[:, q]  (q < nr)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int q = lane + 64 * u;
+      if (q < nr)
+        for (int p = 0; p < n; ++p) {
+          double s = 0.0;
+          for (int i = 0; i < k; ++i) s += W[p * n + nr + i] * X[i * nr + q];
+          W[p * n + q] -= s;
+        }
+    }
     wave_sync();
-    // rows: W[p, :] -= T[:, p]^T W[nr:, :]  (lane = column)
-    if (lane < n)
-      for (int p = 0; p < nr; ++p) {
-        double s = 0.0;
-        for (int i = 0; i < k; ++i) s += X[i * nr + p] * W[(nr + i) * n + lane];
-        W[p * n + lane] -= s;
-      }
+    // rows: W[p, :] -= T[:, p]^T W[nr:, :]  (p < nr)
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int q = lane + 64 * u;
+      if (q < n)
+        for (int p = 0; p < nr; ++p) {
+          double s = 0.0;
+          for (int i = 0; i < k; ++i) s += X[i * nr + p] * W[(nr + i) * n + q];
+          W[p * n + q] -= s;
+        }
+    }
     wave_sync();
   }
-  // LU with partial pivoting; steps j < nr search rows [j, nr), later steps [j, n)
+  // LU with partial pivoting; steps j < nr search rows [j, nr), later steps
+  // [j, n); ties go to the smaller row
   const int split = sp ? nr : 0;
   bool singular = false;
-  int rm = lane;  // composed row map of the interchanges so far
+  int rm[CPL];  // composed row map of the interchanges so far, rows l + 64 u
+#pragma unroll
+  for (int u = 0; u < CPL; ++u) rm[u] = lane + 64 * u;
   for (int j = 0; j < n; ++j) {
     const int hi = j < split ? split : n;
     double bv = -1.0;
     int bi = 1 << 30;
-    if (lane >= j && lane < hi) {
-      bv = fabs(W[lane * n + j]);
-      bi = lane;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int r = lane + 64 * u;
+      if (r >= j && r < hi) {
+        const double a = fabs(W[r * n + j]);
+        if (a > bv) {
+          bv = a;
+          bi = r;
+        }
+      }
     }
     wave_argmax(bv, bi);
     const int p = __builtin_amdgcn_readfirstlane(bi < n ? bi : j);
     if (p != j) {
-      const int a = __builtin_amdgcn_readlane(rm, j), b = __builtin_amdgcn_readlane(rm, p);
-      rm = lane == j ? b : lane == p ? a : rm;
-    }
-    if (p != j && lane < n) {
-      const double t = W[j * n + lane];
-      W[j * n + lane] = W[p * n + lane];
-      W[p * n + lane] = t;
+      int a = 0, b = 0;
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) {
+        const int va = __builtin_amdgcn_readlane(rm[u], j & 63), vb = __builtin_amdgcn_readlane(rm[u], p & 63);
+        if ((j >> 6) == u) a = va;
+        if ((p >> 6) == u) b = vb;
+      }
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) {
+        const int r = lane + 64 * u;
+        rm[u] = r == j ? b : r == p ? a : rm[u];
+        if (r < n) {
+          const double t = W[j * n + r];
+          W[j * n + r] = W[p * n + r];
+          W[p * n + r] = t;
+        }
+      }
     }
     wave_sync();
     const double d = W[j * n + j];
@@ -614,80 +816,121 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
       singular = true;
       continue;
     }
-    if (lane > j && lane < n) W[lane * n + j] /= d;
-    wave_sync();
-    if (lane > j && lane < n) {
-      const double ujc = W[j * n + lane];
-      int i = j + 1;
-      for (; i + 3 < n; i += 4) {
-        double l[4], w[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          l[u] = W[(i + u) * n + j];
-          w[u] = W[(i + u) * n + lane];
+    for (int u = 0; u < CPL; ++u) {
+      const int r = lane + 64 * u;
+      if (r > j && r < n) W[r * n + j] /= d;
+    }
+    wave_sync();
+    // trailing update of the columns owned by this lane; inactive columns
+    // read a valid column and do not store
+    bool act[CPL], any = false;
+    int cc[CPL];
+    double ujc[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int col = lane + 64 * u;
+      act[u] = col > j && col < n;
+      any = any || act[u];
+      cc[u] = act[u] ? col : j;
+      ujc[u] = W[j * n + cc[u]];
+    }
+    if (any) {
+      int i = j + 1;
+      for (; i + 7 < n; i += 8) {
+        double l[8], w[8][CPL];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          l[v] = W[(i + v) * n + j];
+#pragma unroll
+          for (int u = 0; u < CPL; ++u) w[v][u] = W[(i + v) * n + cc[u]];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) W[(i + u) * n + lane] = w[u] - l[u] * ujc;
+        for (int v = 0; v < 8; ++v)
+#pragma unroll
+          for (int u = 0; u < CPL; ++u)
+            if (act[u]) W[(i + v) * n + cc[u]] = w[v][u] - l[v] * ujc[u];
       }
-      for (; i < n; ++i) W[i * n + lane] -= W[i * n + j] * ujc;
+      for (; i < n; ++i) {
+        const double lv = W[i * n + j];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+          if (act[u]) W[i * n + cc[u]] -= lv * ujc[u];
+      }
     }
     wave_sync();
   }
   if (singular && lane == 0) atomicOr(status, 1);
-  if (lane < n) piv[lane] = rm;
-  // packed inverses, one column per lane: strictly lower L^{-1} (unit
-  // diagonal implied) and upper U^{-1}
-  T* LU = varena + S.lu_off;
-  if (lane < n) {
-    const int q = lane;
-    // column q of L^{-1}: e_q forward-substituted through the unit lower L
-    for (int i = 0; i < n; ++i) X[i * n + q] = i == q ? 1.0 : 0.0;
-    for (int j = q; j < n; ++j) {
-      const double xj = X[j * n + q];
-      int i = j + 1;
-      for (; i + 3 < n; i += 4) {
-        double l[4], x[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          l[u] = W[(i + u) * n + j];
-          x[u] = X[(i + u) * n + q];
+  for (int u = 0; u < CPL; ++u)
+    if (lane + 64 * u < n) piv[lane + 64 * u] = rm[u];
+  // packed inverses in place: step s forms row s of L^{-1} (columns < s,
+  // from the finished rows above it) and row n-1-s of U^{-1} (columns
+  // >= n-1-s, from the finished rows below it); the two touch disjoint
+  // triangles, and each row is written only after every lane has read it
+  for (int s = 0; s < n; ++s) {
+    const int il = s, iu = n - 1 - s;
+    const double du = W[iu * n + iu];
+    double sl[CPL], su[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int col = lane + 64 * u;
+      const bool al = col < il, au = col >= iu && col < n;
+      const int cl = al ? col : 0, cu = au ? col : iu;
+      // L: X[il][col] = -(L[il][col] + sum_{col < m < il} L[il][m] X[m][col])
+      // U: Y[iu][col] = (delta - sum_{iu < m <= col} U[iu][m] Y[m][col]) / U[iu][iu]
+      const int nl = al ? il - 1 - cl : 0, nu = au ? cu - iu : 0;
+      const int len = nl > nu ? nl : nu;
+      double accl = al ? W[il * n + cl] : 0.0, accu = 0.0;
+      for (int t = 0; t < len; t += 4) {
+        double a[4], b[4], e[4], f[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ml = t + v < nl ? cl + 1 + t + v : cl;
+          const int mu = t + v < nu ? iu + 1 + t + v : iu;
+          a[v] = W[il * n + ml];
+          b[v] = W[ml * n + cl];
+          e[v] = W[iu * n + mu];
+          f[v] = W[mu * n + cu];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) X[(i + u) * n + q] = x[u] - l[u] * xj;
-      }
-      for (; i < n; ++i) X[i * n + q] -= W[i * n + j] * xj;
-    }
-    for (int i = q + 1; i < n; ++i) LU[size_t(i) * n + q] = T(X[i * n + q]);
-    // column q of U^{-1}: e_q back-substituted through U
-    for (int i = 0; i < n; ++i) X[i * n + q] = i == q ? 1.0 : 0.0;
-    for (int j = q; j >= 0; --j) {
-      const double xj = X[j * n + q] / W[j * n + j];
-      X[j * n + q] = xj;
-      int i = 0;
-      for (; i + 3 < j; i += 4) {
-        double uu[4], x[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          uu[u] = W[(i + u) * n + j];
-          x[u] = X[(i + u) * n + q];
+        for (int v = 0; v < 4; ++v) {
+          accl += t + v < nl ? a[v] * b[v] : 0.0;
+          accu += t + v < nu ? e[v] * f[v] : 0.0;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) X[(i + u) * n + q] = x[u] - uu[u] * xj;
       }
-      for (; i < j; ++i) X[i * n + q] -= W[i * n + j] * xj;
+      sl[u] = -accl;
+      su[u] = ((col == iu ? 1.0 : 0.0) - accu) / du;
     }
-    for (int i = 0; i <= q; ++i) LU[size_t(i) * n + q] = T(X[i * n + q]);
-  }
-  if (sp) {
-    int nd = 0;
-    if (lane < n) nd = dofs[lane < nr ? perm[k + lane] : perm[lane - nr]];
     wave_sync();
-    if (lane < n) dofs[lane] = nd;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int col = lane + 64 * u;
+      if (col < il) W[il * n + col] = sl[u];
+      if (col >= iu && col < n) W[iu * n + col] = su[u];
+    }
+    wave_sync();
+  }
+  T* LU = varena + S.lu_off;
+  for (int t = lane; t < n * n; t += 64) LU[t] = T(W[t]);
+  if (sp) {
+    int nd[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+      const int p = lane + 64 * u < n ? lane + 64 * u : n - 1;
+      nd[u] = dofs[p < nr ? perm[k + p] : perm[p - nr]];
+    }
+    wave_sync();
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      if (lane + 64 * u < n) dofs[lane + 64 * u] = nd[u];
   }
 }
 
 // LDS doubles of the one-wave coupling scaling of a kc x kd block.
-__host__ __device__ inline int blk_scale_wave_need(int kc, int kd) { return kc * kd + kc * kc + kd * kd + (kc + 1) / 2; }
+__host__ __device__ inline int blk_scale_wave_need(int kc, int kd) {
+  return kc * kd + kc * kc + kd * kd + (kc + kd + 1) / 2;
+}
 __host__ __device__ inline bool blk_scale_wave_fits(int kc, int kd, int lds_doubles) {
   return kc <= 64 && kd <= 64 && blk_scale_wave_need(kc, kd) <= lds_doubles;
 }
@@ -807,24 +1050,47 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
   double* X = lds;                            // kc x kd
   double* Lb = X + kc * kd;                   // kc x kc (strict lower part used)
   double* Ub = Lb + kc * kc;                  // kd x kd (upper part used)
-  int* rm = reinterpret_cast<int*>(Ub + kd * kd);  // kc
-  // row map of the skeleton-part pivots of c: row i of P_s X is row rm[i]
-  for (int i = lane; i < kc; i += 64) rm[i] = pivc[nrc + i] - nrc;
-  for (int t = lane; t < kc * kc; t += 64) {
-    const int i = t / kc, u = t - i * kc;
-    Lb[t] = u < i ? double(Lc[size_t(nrc + i) * nc + nrc + u]) : 0.0;
-  }
-  for (int t = lane; t < kd * kd; t += 64) {
-    const int u = t / kd, j = t - u * kd;
-    Ub[t] = u <= j ? double(Ud[size_t(nrd + u) * nd + nrd + j]) : 0.0;
-  }
-  wave_sync();
-  for (int t = lane; t < kc * kd; t += 64) {
-    const int i = t / kd, j = t - i * kd;
-    const int r = rm[i];
+  int* rs = reinterpret_cast<int*>(Ub + kd * kd);  // kc: block row of row i of P_s X
+  int* cs = rs + kc;                               // kd: block column of column j
+  // row map of the skeleton-part pivots of c (row i of P_s X is row
+  // pivc[nrc + i] - nrc of X), composed with the skeleton DOF positions
+  {
+    const int i = lane < kc ? lane : kc - 1, j = lane < kd ? lane : kd - 1;
+    const int r = pivc[nrc + i] - nrc;
     const int si = spc ? permc[r] : r, sj = spd ? permd[j] : j;
-    X[t] = double(A[size_t(si) * nd + sj]);
+    if (lane < kc) rs[lane] = si;
+    if (lane < kd) cs[lane] = sj;
   }
+  // triangles of the packed inverses: every load issued (clamped rows and
+  // columns), zeros stored outside the triangle
+  load_batched<8>(
+      kc * kc, lane, 64,
+      [&](int t) {
+        const int i = t / kc, u = t - i * kc;
+        return Lc[size_t(nrc + i) * nc + nrc + u];
+      },
+      [&](int t, T v) {
+        const int i = t / kc, u = t - i * kc;
+        Lb[t] = u < i ? double(v) : 0.0;
+      });
+  load_batched<8>(
+      kd * kd, lane, 64,
+      [&](int t) {
+        const int u = t / kd, j = t - u * kd;
+        return Ud[size_t(nrd + u) * nd + nrd + j];
+      },
+      [&](int t, T v) {
+        const int u = t / kd, j = t - u * kd;
+        Ub[t] = u <= j ? double(v) : 0.0;
+      });
+  wave_sync();
+  load_batched<8>(
+      kc * kd, lane, 64,
+      [&](int t) {
+        const int i = t / kd, j = t - i * kd;
+        return A[size_t(rs[i]) * nd + cs[j]];
+      },
+      [&](int t, T v) { X[t] = double(v); });
   wave_sync();
   if (lane < kd) {
     const int j = lane;
@@ -881,11 +1147,15 @@ __global__ void k_merge_sizes(const DSeg* useg, int nuseg, const int32_t* cons_p
 // Separator elimination fused with the merge: every level-(l-1) block is
 // assembled from identity / scaled level-l blocks minus A'_{c,s} A'_{s,d}
 // for the level-l separators s next to both c and d (Z_l, Z_u, E_(l)).
+// With lds_bytes > 0, a task whose blocks fit keeps its kc x kd result in
+// LDS and stages both factors of every term there with batched loads;
+// otherwise the products read the factors from memory.
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk, const int32_t* task_ptr,
                                                    const DTask* tasks, const DSepTerm* terms,
                                                    const DBlk* blks, T* varena, DLevelDyn dyn,
-                                                   DLevelDyn udyn) {
+                                                   DLevelDyn udyn, int lds_bytes) {
+  extern __shared__ double lds[];
   const int b = blockIdx.x;
   if (b >= nublk) return;
   const int tid = threadIdx.x;
@@ -899,6 +1169,51 @@ __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk,
     const int kc = dyn.k[tk.c], kd = dyn.k[tk.d];
     const int oc = dyn.off[tk.c], od = dyn.off[tk.d];
     const T* src = tk.src >= 0 ? varena + blks[tk.src].soff : nullptr;
+    int ksmax = 0;
+    for (int e = tk.sep_begin; e < tk.sep_end; ++e) {
+      const int ks = dyn.k[terms[e].s];
+      ksmax = ks > ksmax ? ks : ksmax;
+    }
+    const int acc_bytes = (kc * kd * 8 + 15) & ~15;
+    const bool staged = lds_bytes > 0 && tk.sep_end > tk.sep_begin &&
+                        acc_bytes + (kc + kd) * ksmax * int(sizeof(T)) <= lds_bytes;
+    if constexpr (NT == WG) {
+      if (staged) {
+        double* acc = lds;  // kc x kd, element t touched by thread t % NT only
+        T* sA = reinterpret_cast<T*>(reinterpret_cast<char*>(lds) + acc_bytes);
+        if (tk.src == -2 || !src)
+          for (int t = tid; t < kc * kd; t += NT) acc[t] = tk.src == -2 && t / kd == t % kd ? 1.0 : 0.0;
+        else
+          stage_batched<8>(src, kc * kd, tid, NT, [&](int t, T v) { acc[t] = double(v); });
+        for (int e = tk.sep_begin; e < tk.sep_end; ++e) {
+          const DSepTerm st = terms[e];
+          const int ks = dyn.k[st.s];
+          T* sB = sA + kc * ks;
+          __syncthreads();  // the previous term's factors are no longer read
+          stage_batched<8>(varena + blks[st.blk_cs].soff, kc * ks, tid, NT, [&](int t, T v) { sA[t] = v; });
+          stage_batched<8>(varena + blks[st.blk_sd].soff, ks * kd, tid, NT, [&](int t, T v) { sB[t] = v; });
+          __syncthreads();
+          for (int t = tid; t < kc * kd; t += NT) {
+            const int i = t / kd, j = t - i * kd;
+            const T* ar = sA + i * ks;
+            double s0 = 0.0, s1 = 0.0;
+            int u = 0;
+            for (; u + 1 < ks; u += 2) {
+              s0 += double(ar[u]) * double(sB[u * kd + j]);
+              s1 += double(ar[u + 1]) * double(sB[(u + 1) * kd + j]);
+            }
+            if (u < ks) s0 += double(ar[u]) * double(sB[u * kd + j]);
+            acc[t] -= s0 + s1;
+          }
+        }
+        for (int t = tid; t < kc * kd; t += NT) {
+          const int i = t / kd, j = t - i * kd;
+          out[size_t(oc + i) * nD + od + j] = T(acc[t]);
+        }
+        __syncthreads();  // the next task restages
+        continue;
+      }
+    }
     for (int t = tid; t < kc * kd; t += NT) {
       const int i = t / kd, j = t % kd;
       double v = tk.src == -2 ? (i == j ? 1.0 : 0.0) : (src ? double(src[t]) : 0.0);

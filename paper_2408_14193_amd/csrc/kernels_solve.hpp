@@ -105,26 +105,6 @@ __global__ __launch_bounds__(WG) void k_leaf_solve(const DLeaf* leaves, int nlea
 // in batches of loads issued together.
 constexpr int LEAF_SOLVE_CHUNK = 16;
 
-// store(t, src[t]) for t in [0, count), t = lane + stride * m: the loads of
-// a batch of NB are issued together (clamped addresses, guarded stores), so
-// a staging loop costs one trip to memory per batch instead of one per load.
-template <int NB, typename S, typename F>
-__device__ inline void stage_batched(const S* src, int count, int lane, int stride, F store) {
-  for (int t0 = 0; t0 < count; t0 += NB * stride) {
-    S v[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int t = t0 + b * stride + lane;
-      v[b] = src[t < count ? t : count - 1];
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int t = t0 + b * stride + lane;
-      if (t < count) store(t, v[b]);
-    }
-  }
-}
-
 // x[j] = src[j] for j < nc (0 beyond): a full chunk loads unconditionally,
 // so that all its loads are in flight together.
 template <typename T>

@@ -159,6 +159,7 @@ constexpr size_t ID_B_MAX_BYTES = 72 * 1024;    // 256-thread groups: two per CU
 constexpr size_t ID_B2_MAX_BYTES = 152 * 1024;  // 256-thread groups: one per CU
 constexpr size_t SEGLU_MAX_BYTES = 152 * 1024;   // segment LU of large segments
 constexpr int SEGLU_WAVE_MAX_N = 32;             // segments up to this size: one wave each
+constexpr size_t MELIM_LDS_BYTES = 64 * 1024;   // staged separator terms of the merge
 
 // Which ID launches a level needs and their LDS budgets.  The sizes known
 // here (uncompressed n, coupling-row bound rcap) bound the ones the kernels
@@ -1015,11 +1016,11 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
                               int(SEGLU_MAX_BYTES)) == hipSuccess;
       if (!lu_lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the segment LU kernel");
       const int nw = std::min(SEGLU_WAVE_MAX_N, T_.max_cap);
-      LAUNCH(K_LU, l, k_seg_lu_wave<T><<<unsigned(ns), 64, size_t(2) * nw * nw * 8, st>>>(segs, ns, blks, iar, var, d,
-                                                                                       status, nw));
+      LAUNCH(K_LU, l, k_seg_lu_wave<T, 1><<<unsigned(ns), 64, size_t(seglu_wave_lds_doubles(nw)) * 8, st>>>(
+          segs, ns, blks, iar, var, d, status, 0, nw));
       if (T_.max_cap > SEGLU_WAVE_MAX_N) {
         const int64_t cap = T_.max_cap;
-        const int big = int(std::min<int64_t>(2 * cap * cap + (cap + 1) / 2, int64_t(SEGLU_MAX_BYTES / 8)));
+        const int big = int(std::min<int64_t>(2 * cap * cap + cap, int64_t(SEGLU_MAX_BYTES / 8)));
         LAUNCH_MORE(K_LU, l, k_seg_lu<T><<<unsigned(ns), WG, size_t(big) * 8, st>>>(
             segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, INT32_MAX, big));
       }
@@ -1044,11 +1045,12 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       if (U.max_cap <= 32)
         LAUNCH(K_MELIM, l, k_merge_elim<T, 64><<<unsigned(U.blks.size()), 64, 0, st>>>(
             tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
-            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du));
+            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du, 0));
       else
-        LAUNCH(K_MELIM, l, k_merge_elim<T, WG><<<unsigned(U.blks.size()), WG, 0, st>>>(
+        LAUNCH(K_MELIM, l, k_merge_elim<T, WG><<<unsigned(U.blks.size()), WG, MELIM_LDS_BYTES, st>>>(
             tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
-            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du));
+            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du,
+            int(MELIM_LDS_BYTES)));
     }
   }
   HIPCHK(hipMemcpyAsync(status_host, status, 4, hipMemcpyDeviceToHost, st));
