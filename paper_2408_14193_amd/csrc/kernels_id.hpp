@@ -59,6 +59,11 @@ __host__ __device__ inline size_t idc_scratch_doubles(int n, int R) {
   return 2 * size_t(R) * n + (size_t(R) * (sizeof(IdRow) + 4) + 7) / 8;
 }
 
+// Waves of a tier-B workgroup (two per CU) and of a tier-B2 workgroup (one
+// per CU).
+constexpr int ID_B_WAVES = 4;
+constexpr int ID_B2_WAVES = 8;
+
 struct IdTiers {
   int budget_a;   // LDS bytes of the tier-A launch
   int budget_b;   // LDS bytes of the tier-B launch (two groups per CU)
@@ -70,8 +75,8 @@ struct IdTiers {
 // 1: tier A, 2: B, 3: B2, 4: C, 5: block-cooperative kernel.
 __host__ __device__ inline int id_tier_of_size(int n, int R, IdTiers t) {
   if (n <= 64 && idc_lds_bytes(1, 1, n, R, t.st, true) <= size_t(t.budget_a)) return 1;
-  if (n <= 128 && idc_lds_bytes(4, 2, n, R, t.st, true) <= size_t(t.budget_b)) return 2;
-  if (n <= 128 && idc_lds_bytes(4, 2, n, R, t.st, true) <= size_t(t.budget_b2)) return 3;
+  if (n <= 128 && idc_lds_bytes(ID_B_WAVES, 2, n, R, t.st, true) <= size_t(t.budget_b)) return 2;
+  if (n <= 128 && idc_lds_bytes(ID_B2_WAVES, 2, n, R, t.st, true) <= size_t(t.budget_b2)) return 3;
   if (n <= 128) return 4;
   return 5;
 }

@@ -156,7 +156,7 @@ namespace {
 // workgroup may hold up to 160 KB).
 constexpr size_t ID_A_MAX_BYTES = 24 * 1024;    // 64-thread groups: six or more per CU
 constexpr size_t ID_B_MAX_BYTES = 72 * 1024;    // 256-thread groups: two per CU
-constexpr size_t ID_B2_MAX_BYTES = 152 * 1024;  // 256-thread groups: one per CU
+constexpr size_t ID_B2_MAX_BYTES = 152 * 1024;  // tier-B2 groups: one per CU
 constexpr size_t SEGLU_MAX_BYTES = 152 * 1024;   // segment LU of large segments
 constexpr int SEGLU_WAVE_MAX_N = 32;             // segments up to this size: one wave each
 constexpr size_t MELIM_LDS_BYTES = 64 * 1024;   // staged separator terms of the merge
@@ -177,14 +177,15 @@ void plan_id_tiers(LevelTabs& T, int st) {
       continue;
     }
     beyond_a = true;
-    const size_t nb = idc_lds_bytes(4, 2, std::min(cap, 128), R, st, true);
+    const size_t nb = idc_lds_bytes(ID_B_WAVES, 2, std::min(cap, 128), R, st, true);
     if (cap <= 128 && nb <= ID_B_MAX_BYTES) {
       b = std::max(b, nb);
       continue;
     }
     beyond_b = true;
-    if (cap <= 128 && nb <= ID_B2_MAX_BYTES) {
-      b2 = std::max(b2, nb);
+    const size_t nb2 = idc_lds_bytes(ID_B2_WAVES, 2, std::min(cap, 128), R, st, true);
+    if (cap <= 128 && nb2 <= ID_B2_MAX_BYTES) {
+      b2 = std::max(b2, nb2);
       continue;
     }
     beyond_b2 = true;
@@ -197,8 +198,8 @@ void plan_id_tiers(LevelTabs& T, int st) {
   if (beyond_b2) b2 = ID_B2_MAX_BYTES;
   T.tiers.st = st;
   T.tiers.budget_a = int(std::max(a, idc_lds_bytes(1, 1, 1, 2, st, true)));
-  T.tiers.budget_b = int(std::max(b, idc_lds_bytes(4, 2, 1, 2, st, true)));
-  T.tiers.budget_b2 = int(std::max<size_t>(b2, size_t(T.tiers.budget_b)));
+  T.tiers.budget_b = int(std::max(b, idc_lds_bytes(ID_B_WAVES, 2, 1, 2, st, true)));
+  T.tiers.budget_b2 = int(std::max(b2, idc_lds_bytes(ID_B2_WAVES, 2, 1, 2, st, true)));
   T.id_b = beyond_a;
   T.id_b2 = beyond_b;
   T.id_c = beyond_b2;
@@ -961,10 +962,10 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     {
       static const bool lds_ok = [] {
         // tier-B workgroups may take more than 64 KB of LDS
-        const bool b1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 4, 2, false, 2>),
+        const bool b1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B_WAVES, 2, false, 2>),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                             int(ID_B_MAX_BYTES)) == hipSuccess;
-        const bool b2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 4, 2, false, 3>),
+        const bool b2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B2_WAVES, 2, false, 3>),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                             int(ID_B2_MAX_BYTES)) == hipSuccess;
         return b1 && b2;
@@ -984,12 +985,14 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
           segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       if (side[0]) {
         hipStream_t st = F->aux[0];
-        LAUNCH(K_ID_B, l, k_seg_id_cols<T, 4, 2, false, 2><<<unsigned(ns), 256, size_t(tz.budget_b), st>>>(
+        LAUNCH(K_ID_B, l, k_seg_id_cols<T, ID_B_WAVES, 2, false, 2><<<unsigned(ns), 64 * ID_B_WAVES,
+                                                                      size_t(tz.budget_b), st>>>(
             segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       }
       if (side[1]) {
         hipStream_t st = F->aux[1];
-        LAUNCH(K_ID_B2, l, k_seg_id_cols<T, 4, 2, false, 3><<<unsigned(ns), 256, size_t(tz.budget_b2), st>>>(
+        LAUNCH(K_ID_B2, l, k_seg_id_cols<T, ID_B2_WAVES, 2, false, 3><<<unsigned(ns), 64 * ID_B2_WAVES,
+                                                                        size_t(tz.budget_b2), st>>>(
             segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       }
       if (side[2]) {
