@@ -703,42 +703,44 @@ __global__ __launch_bounds__(WG) void k_sep_bwd(const DSeg* segs, int nseg, cons
   }
 }
 
-// r = b - A x in FP64 (column-major, ld n), per-block partial sums of
-// ||r_j||^2 (and ||b_j||^2 when want_b) for a deterministic reduction.
+// r = b - A x in FP64 (column-major, ld n) and per-wave partial sums of
+// ||r_j||^2 and ||b_j||^2 (part[j * nparts + wave], nparts = 4 per block)
+// for a deterministic reduction: one thread per row, its stencil entries
+// (at most 8) read once, then every right-hand side in turn.
 __global__ __launch_bounds__(WG) void k_residual(int64_t n, int nrhs, const int64_t* rowptr,
                                                  const int32_t* colind, const double* vals,
                                                  const double* B, int64_t ldb, const double* X,
-                                                 int64_t ldx, double* R, double* part_r, double* part_b) {
-  __shared__ double red[NWAVE];
-  const int j = blockIdx.y;
+                                                 int64_t ldx, double* R, double* part_r, double* part_b,
+                                                 int nparts) {
+  constexpr int ME = 8;
   const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
-  double r = 0.0, b = 0.0;
-  if (v < n) {
-    // the row's stencil entries (at most 8) read together, then the products
-    constexpr int ME = 8;
-    const int64_t e0 = rowptr[v], e1 = rowptr[v + 1];
-    const double* x = X + j * ldx;
-    b = B[v + j * ldb];
-    int cols[ME];
-    double vv[ME];
+  const int lane = threadIdx.x & 63, pidx = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+  const bool live = v < n;
+  const int64_t vr = live ? v : n - 1;
+  const int64_t e0 = rowptr[vr], e1 = rowptr[vr + 1];
+  int cols[ME];
+  double vv[ME];
 #pragma unroll
-    for (int m = 0; m < ME; ++m) {
-      const bool in = e0 + m < e1;
-      cols[m] = in ? colind[e0 + m] : int(v);
-      vv[m] = in ? vals[e0 + m] : 0.0;
-    }
+  for (int m = 0; m < ME; ++m) {
+    const bool in = e0 + m < e1;
+    cols[m] = in ? colind[e0 + m] : int(vr);
+    vv[m] = in ? vals[e0 + m] : 0.0;
+  }
+  for (int j = 0; j < nrhs; ++j) {
+    const double* x = X + j * ldx;
+    const double b = B[vr + j * ldb];
     double ax = 0.0;
 #pragma unroll
     for (int m = 0; m < ME; ++m) ax += vv[m] * x[cols[m]];
     for (int64_t e = e0 + ME; e < e1; ++e) ax += vals[e] * x[colind[e]];  // rows longer than ME
-    r = b - ax;
-    R[v + j * n] = r;
-  }
-  const double sr = block_sum(r * r, red);
-  const double sb = block_sum(b * b, red);
-  if (threadIdx.x == 0) {
-    part_r[size_t(j) * gridDim.x + blockIdx.x] = sr;
-    part_b[size_t(j) * gridDim.x + blockIdx.x] = sb;
+    const double r = b - ax;
+    if (live) R[v + j * n] = r;
+    const double sr = wave_sum(live ? r * r : 0.0);
+    const double sb = wave_sum(live ? b * b : 0.0);
+    if (lane == 0) {
+      part_r[size_t(j) * nparts + pidx] = sr;
+      part_b[size_t(j) * nparts + pidx] = sb;
+    }
   }
 }
 
@@ -790,32 +792,113 @@ __global__ __launch_bounds__(WG) void k_spmv(int64_t n, int nrhs, const int64_t*
   }
 }
 
-// Row-block partial sums of <w_j, V_i[:, j]> for i < cnt (blockIdx.z = i) and
-// of ||w_j||^2 (blockIdx.z = cnt); reduced by k_reduce_cols over the
-// (cnt + 1) * nrhs rows of part.
-__global__ __launch_bounds__(WG) void k_kdots(int64_t n, int nrhs, const double* V, int cnt, const double* Wc,
-                                              double* part) {
-  __shared__ double red[NWAVE];
-  const int j = blockIdx.y, i = blockIdx.z;
-  const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
-  double a = 0.0;
-  if (v < n) {
-    const double w = Wc[v + j * n];
-    a = w * (i < cnt ? V[(size_t(i) * nrhs + j) * n + v] : w);
+// Rows per thread of the Gram-Schmidt kernels; their per-wave partial sums
+// go to part[(i * nrhs + j) * nparts + wave] with nparts = 4 per block of
+// KRY_ROWS * 256 rows.
+constexpr int KRY_ROWS = 4;
+
+// One wave-level partial of each of <w_j, V_i[:, j]> (i < cnt) and
+// ||w_j||^2 (i = cnt) over this thread's rows, w read once.
+__device__ inline void kry_dots(const double (&w)[KRY_ROWS], const double* V, int64_t n, int nrhs, int j,
+                                int cnt, int64_t base, double* part, int nparts) {
+  const int lane = threadIdx.x & 63, pidx = blockIdx.x * NWAVE + (threadIdx.x >> 6);
+  for (int i = 0; i <= cnt; ++i) {
+    double a = 0.0;
+    if (i < cnt) {
+      const double* Vi = V + (size_t(i) * nrhs + j) * n;
+      double y[KRY_ROWS];
+#pragma unroll
+      for (int r = 0; r < KRY_ROWS; ++r) {
+        const int64_t v = base + r * WG;
+        y[r] = Vi[v < n ? v : n - 1];
+      }
+#pragma unroll
+      for (int r = 0; r < KRY_ROWS; ++r) a += w[r] * y[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < KRY_ROWS; ++r) a += w[r] * w[r];
+    }
+    a = wave_sum(a);
+    if (lane == 0) part[(size_t(i) * nrhs + j) * nparts + pidx] = a;
   }
-  a = block_sum(a, red);
-  if (threadIdx.x == 0) part[(size_t(i) * nrhs + j) * gridDim.x + blockIdx.x] = a;
 }
 
-// w_j -= sum_{i < cnt} h[i * nrhs + j] V_i[:, j].
-__global__ __launch_bounds__(WG) void k_korth(int64_t n, int nrhs, const double* V, int cnt, const double* h,
-                                              double* Wc) {
+// Partial sums of <w_j, V_i[:, j]> for i < cnt and of ||w_j||^2; reduced by
+// k_reduce_cols over the (cnt + 1) * nrhs rows of part.
+__global__ __launch_bounds__(WG) void k_kdots(int64_t n, int nrhs, const double* V, int cnt, const double* Wc,
+                                              double* part, int nparts) {
   const int j = blockIdx.y;
-  const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
-  if (v >= n) return;
-  double acc = Wc[v + j * n];
-  for (int i = 0; i < cnt; ++i) acc -= h[i * nrhs + j] * V[(size_t(i) * nrhs + j) * n + v];
-  Wc[v + j * n] = acc;
+  const int64_t base = int64_t(blockIdx.x) * WG * KRY_ROWS + threadIdx.x;
+  double w[KRY_ROWS];
+#pragma unroll
+  for (int r = 0; r < KRY_ROWS; ++r) {
+    const int64_t v = base + r * WG;
+    w[r] = v < n ? Wc[v + j * n] : 0.0;
+  }
+  kry_dots(w, V, n, nrhs, j, cnt, base, part, nparts);
+}
+
+// First Gram-Schmidt pass fused with the dots of the second:
+// w_j -= sum_{i < cnt} h[i * nrhs + j] V_i[:, j] (written back), then the
+// partial sums of k_kdots for the new w_j.
+__global__ __launch_bounds__(WG) void k_korth_dots(int64_t n, int nrhs, const double* V, int cnt,
+                                                   const double* h, double* Wc, double* part, int nparts) {
+  const int j = blockIdx.y;
+  const int64_t base = int64_t(blockIdx.x) * WG * KRY_ROWS + threadIdx.x;
+  double w[KRY_ROWS];
+#pragma unroll
+  for (int r = 0; r < KRY_ROWS; ++r) {
+    const int64_t v = base + r * WG;
+    w[r] = v < n ? Wc[v + j * n] : 0.0;
+  }
+  for (int i = 0; i < cnt; ++i) {
+    const double* Vi = V + (size_t(i) * nrhs + j) * n;
+    const double hi = h[i * nrhs + j];
+#pragma unroll
+    for (int r = 0; r < KRY_ROWS; ++r) {
+      const int64_t v = base + r * WG;
+      const double y = Vi[v < n ? v : n - 1];  // rows past n keep w = 0
+      w[r] -= v < n ? hi * y : 0.0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < KRY_ROWS; ++r) {
+    const int64_t v = base + r * WG;
+    if (v < n) Wc[v + j * n] = w[r];
+  }
+  kry_dots(w, V, n, nrhs, j, cnt, base, part, nparts);
+}
+
+// Second Gram-Schmidt pass fused with the normalisation:
+// Vout[:, j] = (w_j - sum_{i < cnt} h[i * nrhs + j] V_i[:, j]) times the
+// column's reciprocal norm (w_j itself is left as it is).
+__global__ __launch_bounds__(WG) void k_korth_scale(int64_t n, int nrhs, int m, const double* V, int cnt,
+                                                    const double* h, const double* ks, const double* Wc,
+                                                    double* Vout) {
+  const int j = blockIdx.y;
+  const int64_t base = int64_t(blockIdx.x) * WG * KRY_ROWS + threadIdx.x;
+  double w[KRY_ROWS];
+#pragma unroll
+  for (int r = 0; r < KRY_ROWS; ++r) {
+    const int64_t v = base + r * WG;
+    w[r] = v < n ? Wc[v + j * n] : 0.0;
+  }
+  for (int i = 0; i < cnt; ++i) {
+    const double* Vi = V + (size_t(i) * nrhs + j) * n;
+    const double hi = h[i * nrhs + j];
+#pragma unroll
+    for (int r = 0; r < KRY_ROWS; ++r) {
+      const int64_t v = base + r * WG;
+      const double y = Vi[v < n ? v : n - 1];  // rows past n keep w = 0
+      w[r] -= v < n ? hi * y : 0.0;
+    }
+  }
+  const double inv = ks[size_t(j) * kstate_doubles(m) + kstate_doubles(m) - 1];
+#pragma unroll
+  for (int r = 0; r < KRY_ROWS; ++r) {
+    const int64_t v = base + r * WG;
+    if (v < n) Vout[size_t(j) * n + v] = w[r] * inv;
+  }
 }
 
 // Starts a cycle: g = (beta, 0, ...), beta = sqrt(nr[j]); the reciprocal

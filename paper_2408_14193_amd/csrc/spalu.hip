@@ -1068,7 +1068,9 @@ struct SolveWs {
   size_t oW, oZ, oB0, oR, oPr, oPb, oNr, oNb;
   size_t oV, oZk, oKs, oKp, oH1, oH2, oEst;  // flexible GMRES (restart > 0)
   size_t bytes;
-  unsigned rblk;
+  unsigned rblk;       // blocks of one row per thread
+  unsigned kblk;       // blocks of the Gram-Schmidt kernels (KRY_ROWS rows per thread)
+  int rparts, kparts;  // per-wave partial sums of those launches
 };
 
 SolveWs solve_layout(const spalu_factor_t* F, int nrhs, int restart = 0) {
@@ -1082,12 +1084,15 @@ SolveWs solve_layout(const spalu_factor_t* F, int nrhs, int restart = 0) {
     return r;
   };
   s.rblk = nblocks(F->n);
+  s.kblk = unsigned((F->n + int64_t(WG) * KRY_ROWS - 1) / (int64_t(WG) * KRY_ROWS));
+  s.rparts = int(s.rblk) * NWAVE;
+  s.kparts = int(s.kblk) * NWAVE;
   s.oW = put(nn * vs);
   s.oZ = put(nn * vs);
   s.oB0 = put(nn * vs);
   s.oR = put(nn * 8);
-  s.oPr = put(size_t(s.rblk) * nrhs * 8);
-  s.oPb = put(size_t(s.rblk) * nrhs * 8);
+  s.oPr = put(size_t(s.rparts) * nrhs * 8);
+  s.oPb = put(size_t(s.rparts) * nrhs * 8);
   s.oNr = put(size_t(nrhs) * 8);
   s.oNb = put(size_t(nrhs) * 8);
   if (restart > 0) {
@@ -1095,7 +1100,7 @@ SolveWs solve_layout(const spalu_factor_t* F, int nrhs, int restart = 0) {
     s.oV = put((m + 1) * nn * 8);
     s.oZk = put(m * nn * 8);
     s.oKs = put(size_t(nrhs) * kstate_doubles(restart) * 8);
-    s.oKp = put((m + 1) * nrhs * s.rblk * 8);
+    s.oKp = put((m + 1) * nrhs * size_t(s.kparts) * 8);
     s.oH1 = put((m + 1) * nrhs * 8);
     s.oH2 = put((m + 1) * nrhs * 8);
     s.oEst = put(size_t(nrhs) * 8);
@@ -1285,12 +1290,11 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
   int it = 0, slow = 0;
   std::vector<double> bnorm;
   while (true) {
-    dim3 grid(s.rblk, unsigned(nrhs));
-    LAUNCH(K_RESID, 0, k_residual<<<grid, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Bsrc, ldbres, X, ldx, R,
-                                    pr, pb));
-    LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pr, int(s.rblk), nrhs, nr));
+    LAUNCH(K_RESID, 0, k_residual<<<s.rblk, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Bsrc, ldbres, X,
+                                                          ldx, R, pr, pb, s.rparts));
+    LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pr, s.rparts, nrhs, nr));
     if (bnorm.empty()) {
-      LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pb, int(s.rblk), nrhs, nb));
+      LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pb, s.rparts, nrhs, nb));
       HIPCHK(hipMemcpyAsync(hb.data(), nb, size_t(nrhs) * 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipMemcpyAsync(hr.data(), nr, size_t(nrhs) * 8, hipMemcpyDeviceToHost, st));
@@ -1347,16 +1351,16 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
       LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, Zc, F->n, 0));
       ++it;
       LAUNCH(K_SPMV, 0, k_spmv<<<s.rblk, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Zc, R));
-      for (int pass = 0; pass < 2; ++pass) {
-        double* h = pass == 0 ? h1 : h2;
-        LAUNCH(K_KRYLOV, c + 1, k_kdots<<<dim3(s.rblk, unsigned(nrhs), unsigned(c + 2)), WG, 0, st>>>(F->n, nrhs, V,
-                                                                                                 c + 1, R, kp));
-        LAUNCH(K_KRYLOV, -1, k_reduce_cols<<<unsigned((c + 2) * nrhs), WG, 0, st>>>(kp, int(s.rblk),
-                                                                                  (c + 2) * nrhs, h));
-        LAUNCH(K_KRYLOV, c + 1, k_korth<<<vgrid, WG, 0, st>>>(F->n, nrhs, V, c + 1, h, R));
-      }
+      // two classical Gram-Schmidt passes: the dots of w; w -= V h1 with
+      // the dots of the result; then V_{c+1} = (w - V h2) / H[c+1][c]
+      const dim3 kgrid(s.kblk, unsigned(nrhs));
+      LAUNCH(K_KRYLOV, c + 1, k_kdots<<<kgrid, WG, 0, st>>>(F->n, nrhs, V, c + 1, R, kp, s.kparts));
+      LAUNCH(K_KRYLOV, -1, k_reduce_cols<<<unsigned((c + 2) * nrhs), WG, 0, st>>>(kp, s.kparts, (c + 2) * nrhs, h1));
+      LAUNCH(K_KRYLOV, c + 1, k_korth_dots<<<kgrid, WG, 0, st>>>(F->n, nrhs, V, c + 1, h1, R, kp, s.kparts));
+      LAUNCH(K_KRYLOV, -1, k_reduce_cols<<<unsigned((c + 2) * nrhs), WG, 0, st>>>(kp, s.kparts, (c + 2) * nrhs, h2));
       LAUNCH(K_KRYLOV, -1, k_karnoldi<<<cblk, 64, 0, st>>>(nrhs, m, c, h1, h2, ks, est));
-      LAUNCH(K_KRYLOV, 0, k_kscale<<<vgrid, WG, 0, st>>>(F->n, nrhs, m, ks, R, V + size_t(c + 1) * nn));
+      LAUNCH(K_KRYLOV, c + 1, k_korth_scale<<<kgrid, WG, 0, st>>>(F->n, nrhs, m, V, c + 1, h2, ks, R,
+                                                                   V + size_t(c + 1) * nn));
       kdone = c + 1;
       HIPCHK(hipMemcpyAsync(he.data(), est, size_t(nrhs) * 8, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
