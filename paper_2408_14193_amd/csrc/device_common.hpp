@@ -146,124 +146,4 @@ __device__ inline double gauss_entry(uint32_t seed, int level, int stream, int r
   return (row & 1) ? r * sin(ang) : r * cos(ang);
 }
 
-// LU with partial pivoting, row-major A (n x n, leading dimension ld), in
-// place.  Steps j < split search rows [j, split), later steps rows [j, n)
-// (remainder first, then skeleton).  piv[j] = row swapped with row j.
-// Ties in |a| go to the smaller row.  Returns 1 if a pivot was zero.
-__device__ inline int block_lu_window(double* A, int n, int ld, int split, int* piv, int* s_piv) {
-  int singular = 0;
-  const int tid = threadIdx.x;
-  for (int j = 0; j < n; ++j) {
-    const int hi = j < split ? split : n;
-    if (tid < 64) {
-      double bv = -1.0;
-      int bi = 1 << 30;
-      for (int i = j + tid; i < hi; i += 64) {
-        const double a = fabs(A[size_t(i) * ld + j]);
-        if (a > bv) {
-          bv = a;
-          bi = i;
-        }
-      }
-      wave_argmax(bv, bi);
-      if (tid == 0) *s_piv = bi < n ? bi : j;
-    }
-    __syncthreads();
-    const int p = *s_piv;
-    if (p != j)
-      for (int c = tid; c < n; c += WG) {
-        const double t = A[size_t(j) * ld + c];
-        A[size_t(j) * ld + c] = A[size_t(p) * ld + c];
-        A[size_t(p) * ld + c] = t;
-      }
-    if (tid == 0) piv[j] = p;
-    __syncthreads();
-    const double d = A[size_t(j) * ld + j];
-    if (d == 0.0) {
-      singular = 1;
-      continue;  // uniform: every thread read the same d
-    }
-    for (int i = j + 1 + tid; i < n; i += WG) A[size_t(i) * ld + j] /= d;
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int t = tid; t < m * m; t += WG) {
-      const int i = j + 1 + t / m, c = j + 1 + t % m;
-      A[size_t(i) * ld + c] -= A[size_t(i) * ld + j] * A[size_t(j) * ld + c];
-    }
-    __syncthreads();
-  }
-  return singular;
-}
-
-// X (n x ncol, row-major, ld) <- L^{-1} P X with the unit-lower L and the
-// swaps piv of a packed LU (row-major, ldl).  Threads own columns of X for
-// the swaps, then (row, column) pairs per elimination step.
-template <typename TL>
-__device__ inline void block_lower_solve(const TL* LU, int ldl, const int* piv, int n, double* X, int ldx,
-                                         int ncol) {
-  const int tid = threadIdx.x;
-  for (int c = tid; c < ncol; c += WG)
-    for (int j = 0; j < n; ++j) {
-      const int p = piv[j];
-      if (p != j) {
-        const double t = X[size_t(j) * ldx + c];
-        X[size_t(j) * ldx + c] = X[size_t(p) * ldx + c];
-        X[size_t(p) * ldx + c] = t;
-      }
-    }
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const int m = n - j - 1;
-    for (int t = tid; t < m * ncol; t += WG) {
-      const int i = j + 1 + t / ncol, c = t % ncol;
-      X[size_t(i) * ldx + c] -= double(LU[size_t(i) * ldl + j]) * X[size_t(j) * ldx + c];
-    }
-    __syncthreads();
-  }
-}
-
-// X (n x ncol) <- U^{-1} X with the upper triangle of a packed LU.
-template <typename TL>
-__device__ inline void block_upper_solve(const TL* LU, int ldl, int n, double* X, int ldx, int ncol) {
-  const int tid = threadIdx.x;
-  for (int j = n - 1; j >= 0; --j) {
-    for (int c = tid; c < ncol; c += WG) X[size_t(j) * ldx + c] /= double(LU[size_t(j) * ldl + j]);
-    __syncthreads();
-    for (int t = tid; t < j * ncol; t += WG) {
-      const int i = t / ncol, c = t % ncol;
-      X[size_t(i) * ldx + c] -= double(LU[size_t(i) * ldl + j]) * X[size_t(j) * ldx + c];
-    }
-    __syncthreads();
-  }
-}
-
-// Packed inverses of a unit-lower / upper LU (row-major n x n in W):
-// out[i][j] = (L^{-1})[i][j] for i > j, (U^{-1})[i][j] for i <= j.  X is an
-// n x n double workspace.
-template <typename TO>
-__device__ inline void block_packed_inverse(const double* W, int n, double* X, TO* out) {
-  const int tid = threadIdx.x;
-  // L^{-1}: forward elimination on the identity (columns c <= j are live)
-  for (int t = tid; t < n * n; t += WG) X[t] = (t / n == t % n) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const int m = n - j - 1;
-    for (int t = tid; t < m * (j + 1); t += WG) {
-      const int i = j + 1 + t / (j + 1), cidx = t % (j + 1);
-      X[size_t(i) * n + cidx] -= W[size_t(i) * n + j] * X[size_t(j) * n + cidx];
-    }
-    __syncthreads();
-  }
-  for (int t = tid; t < n * n; t += WG)
-    if (t / n > t % n) out[t] = TO(X[t]);
-  __syncthreads();
-  // U^{-1}: back substitution on the identity
-  for (int t = tid; t < n * n; t += WG) X[t] = (t / n == t % n) ? 1.0 : 0.0;
-  __syncthreads();
-  block_upper_solve<double>(W, n, n, X, n, n);
-  for (int t = tid; t < n * n; t += WG)
-    if (t / n <= t % n) out[t] = TO(X[t]);
-  __syncthreads();
-}
-
 }  // namespace spalu
