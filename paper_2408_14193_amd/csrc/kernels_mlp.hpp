@@ -122,32 +122,64 @@ __global__ __launch_bounds__(64) void k_features(const DSeg* segs, int nseg, con
 
 // BF16 inference: weights and activations rounded to bfloat16, products
 // accumulated in FP32; writes the start sample count of every regular
-// segment (0 for the others).
+// segment (0 for the others).  A group of MLP_G lanes per segment (16
+// segments per block): lane l of a group forms hidden units 4l .. 4l+3 of
+// each layer from the transposed weights in LDS (conflict-free rows), the
+// group shares its activations through LDS, and its first lane sums the
+// output layer; every sum keeps the order of the plain loop.
+constexpr int MLP_G = 16;
+constexpr int MLP_UPL = MLP_H / MLP_G;  // hidden units per lane
+
 __global__ __launch_bounds__(256) void k_mlp_rank(const float* feats, int nseg, const float* params,
                                                   const DSeg* segs, DLevelDyn dyn, float margin, int pad,
                                                   int32_t* h_out) {
-  __shared__ float sW[MLP_NPARAM];
-  for (int t = threadIdx.x; t < MLP_NPARAM; t += blockDim.x)
-    sW[t] = t < MLP_OFF_W1 ? params[t] : bf16_round(params[t]);
+  constexpr int NGRP = 256 / MLP_G;
+  __shared__ float sW[MLP_NPARAM];      // mu, sd, W1^T, b1, W2^T, b2, W3, b3 (BF16-rounded weights)
+  __shared__ float sA[NGRP][2][MLP_H];  // per group: layer-1 and layer-2 activations
+  for (int t = threadIdx.x; t < MLP_NPARAM; t += blockDim.x) {
+    int d = t;  // destination: W1 and W2 transposed
+    if (t >= MLP_OFF_W1 && t < MLP_OFF_B1) {
+      const int o = (t - MLP_OFF_W1) / MLP_NF, k = (t - MLP_OFF_W1) % MLP_NF;
+      d = MLP_OFF_W1 + k * MLP_H + o;
+    } else if (t >= MLP_OFF_W2 && t < MLP_OFF_B2) {
+      const int o = (t - MLP_OFF_W2) / MLP_H, k = (t - MLP_OFF_W2) % MLP_H;
+      d = MLP_OFF_W2 + k * MLP_H + o;
+    }
+    sW[d] = t < MLP_OFF_W1 ? params[t] : bf16_round(params[t]);
+  }
   __syncthreads();
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nseg) return;
+  const int grp = threadIdx.x / MLP_G, l = threadIdx.x % MLP_G;
+  const int c = blockIdx.x * NGRP + grp;
+  if (c >= nseg) return;  // whole groups leave together
   float x[MLP_NF];
+#pragma unroll
   for (int k = 0; k < MLP_NF; ++k)
     x[k] = bf16_round((feats[size_t(c) * MLP_NF + k] - sW[MLP_OFF_MU + k]) / sW[MLP_OFF_SD + k]);
-  float h1[MLP_H];
-  for (int o = 0; o < MLP_H; ++o) {
-    float acc = sW[MLP_OFF_B1 + o];
-    for (int k = 0; k < MLP_NF; ++k) acc += sW[MLP_OFF_W1 + o * MLP_NF + k] * x[k];
-    h1[o] = bf16_round(acc > 0.f ? acc : 0.f);
+  float* a1 = sA[grp][0];
+  float* a2 = sA[grp][1];
+  float acc[MLP_UPL];
+#pragma unroll
+  for (int u = 0; u < MLP_UPL; ++u) acc[u] = sW[MLP_OFF_B1 + l * MLP_UPL + u];
+#pragma unroll
+  for (int k = 0; k < MLP_NF; ++k)
+#pragma unroll
+    for (int u = 0; u < MLP_UPL; ++u) acc[u] += sW[MLP_OFF_W1 + k * MLP_H + l * MLP_UPL + u] * x[k];
+#pragma unroll
+  for (int u = 0; u < MLP_UPL; ++u) a1[l * MLP_UPL + u] = bf16_round(acc[u] > 0.f ? acc[u] : 0.f);
+  wave_sync();
+#pragma unroll
+  for (int u = 0; u < MLP_UPL; ++u) acc[u] = sW[MLP_OFF_B2 + l * MLP_UPL + u];
+  for (int k = 0; k < MLP_H; ++k) {
+    const float hk = a1[k];
+#pragma unroll
+    for (int u = 0; u < MLP_UPL; ++u) acc[u] += sW[MLP_OFF_W2 + k * MLP_H + l * MLP_UPL + u] * hk;
   }
+#pragma unroll
+  for (int u = 0; u < MLP_UPL; ++u) a2[l * MLP_UPL + u] = bf16_round(acc[u] > 0.f ? acc[u] : 0.f);
+  wave_sync();
+  if (l != 0) return;
   float z = sW[MLP_OFF_B3];
-  for (int o = 0; o < MLP_H; ++o) {
-    float acc = sW[MLP_OFF_B2 + o];
-    for (int k = 0; k < MLP_H; ++k) acc += sW[MLP_OFF_W2 + o * MLP_H + k] * h1[k];
-    const float h2 = bf16_round(acc > 0.f ? acc : 0.f);
-    z += sW[MLP_OFF_W3 + o] * h2;
-  }
+  for (int o = 0; o < MLP_H; ++o) z += sW[MLP_OFF_W3 + o] * a2[o];
   const float y = 1.f / (1.f + expf(-z));
   const int n = dyn.n[c];
   const bool reg = (segs[c].flags & SEG_REGULAR) && (segs[c].flags & SEG_HAS_NBR);

@@ -954,8 +954,9 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
                                                                 feats));
       if (o.rank_model) {
         int32_t* hinit = reinterpret_cast<int32_t*>(ws + Y.o_hinit);
-        LAUNCH(K_MLP, l, k_mlp_rank<<<nblocks(ns), WG, 0, st>>>(feats, ns, o.rank_model, segs, d, o.rank_margin,
-                                                                 o.rank_pad, hinit + Y.seg_base[l]));
+        const unsigned mblk = unsigned((ns + WG / MLP_G - 1) / (WG / MLP_G));
+        LAUNCH(K_MLP, l, k_mlp_rank<<<mblk, WG, 0, st>>>(feats, ns, o.rank_model, segs, d, o.rank_margin, o.rank_pad,
+                                                         hinit + Y.seg_base[l]));
         prm.h_init = hinit;
       }
     }
