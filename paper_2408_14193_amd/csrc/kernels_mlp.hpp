@@ -30,59 +30,98 @@ __device__ inline float bf16_round(float x) {
   return __uint_as_float(u);
 }
 
+// Per-vertex parts of the features, once per factorization (a vertex shows
+// up again at every coarser level its skeleton survives to): vf[3v] =
+// (S - a_vv) m / S with S the sum of |a_vw| over its m off-diagonal entries
+// (-inf when S = 0), vf[3v+1] = log(|a_vv| h^2 / 2dim) (0 without a
+// diagonal), vf[3v+2] = sum |a_vw - a_wv| / sum (|a_vw| + |a_wv|) (0 when
+// that is 0/0).
+__global__ __launch_bounds__(WG) void k_vertex_features(int64_t nv, const int64_t* rowptr, const int32_t* colind,
+                                                        const double* vals, GridGeom g, int dim, double* vf) {
+  const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
+  if (v >= nv) return;
+  const double h = 1.0 / double((g.nx > g.ny ? (g.nx > g.nz ? g.nx : g.nz) : (g.ny > g.nz ? g.ny : g.nz)) + 1);
+  double Ssum = 0.0, diag = 0.0, num = 0.0, den = 0.0;
+  int m = 0;
+  for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+    const int j = colind[e];
+    const double a = vals[e];
+    if (j == v) {
+      diag = a;
+    } else {
+      Ssum += fabs(a);
+      ++m;
+      const double at = csr_at(rowptr, colind, vals, j, int(v));
+      num += fabs(a - at);
+      den += fabs(a) + fabs(at);
+    }
+  }
+  vf[3 * v] = Ssum > 0.0 ? (Ssum - diag) * m / Ssum : -INFINITY;
+  vf[3 * v + 1] = diag != 0.0 ? log(fabs(diag) * h * h / (2.0 * dim)) : 0.0;
+  vf[3 * v + 2] = den > 0.0 ? num / den : 0.0;
+}
+
 // Features of every segment of a level; one wave per segment: log2(n+1),
 // log2(span), wavelengths across the segment, log2(coupled DOFs + 1),
 // near-row fraction, l/L, log10(1/eps)/16, on-separator flag, boundary
 // contact, mean and std of log(a_vv h^2 / 2dim), mean stencil asymmetry.
+// The per-vertex parts come from k_vertex_features; the neighbours' DOFs are
+// spread over the lanes as one list (neighbour sizes prefix-summed).
 __global__ __launch_bounds__(64) void k_features(const DSeg* segs, int nseg, const DNbr* nbrs, GridGeom g,
                                                  int dim, int L, int level, double eps, const int32_t* iarena,
-                                                 DLevelDyn dyn, const int64_t* rowptr, const int32_t* colind,
-                                                 const double* vals, float* feats) {
+                                                 DLevelDyn dyn, const double* vf, float* feats) {
   const int c = blockIdx.x;
   if (c >= nseg) return;
   const int lane = threadIdx.x;
   const DSeg S = segs[c];
   const int n = dyn.n[c];
   const int32_t* dofs = iarena + S.ioff;
-  const double h = 1.0 / double((g.nx > g.ny ? (g.nx > g.nz ? g.nx : g.nz) : (g.ny > g.nz ? g.ny : g.nz)) + 1);
   double kh2 = 0.0, gs = 0.0, gs2 = 0.0, as = 0.0;
   for (int i = lane; i < n; i += 64) {
     const int v = dofs[i];
-    double Ssum = 0.0, diag = 0.0, num = 0.0, den = 0.0;
-    int m = 0;
-    for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
-      const int j = colind[e];
-      const double a = vals[e];
-      if (j == v) {
-        diag = a;
-      } else {
-        Ssum += fabs(a);
-        ++m;
-        const double at = csr_at(rowptr, colind, vals, j, v);
-        num += fabs(a - at);
-        den += fabs(a) + fabs(at);
-      }
-    }
-    if (Ssum > 0.0) kh2 = fmax(kh2, (Ssum - diag) * m / Ssum);
-    const double gv = diag != 0.0 ? log(fabs(diag) * h * h / (2.0 * dim)) : 0.0;
+    const double kv = vf[3 * size_t(v)], gv = vf[3 * size_t(v) + 1], av = vf[3 * size_t(v) + 2];
+    kh2 = fmax(kh2, kv);
     gs += gv;
     gs2 += gv * gv;
-    as += den > 0.0 ? num / den : 0.0;
+    as += av;
   }
   kh2 = wave_max(kh2);
   gs = wave_sum(gs);
   gs2 = wave_sum(gs2);
   as = wave_sum(as);
+  // neighbour b0 + lane of a batch of 64: its size and DOF list offset,
+  // and where its DOFs start in the batch's list
+  __shared__ int64_t s_ioff[64];
+  __shared__ int s_excl[64];
+  const int nnb = S.nbr_end - S.nbr_begin;
   double nV = 0.0, nearc = 0.0;
-  for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
-    const int d = nbrs[e].d;
-    const int nd = dyn.n[d];
-    nV += nd;
-    const int32_t* dd = iarena + segs[d].ioff;
+  for (int b0 = 0; b0 < nnb; b0 += 64) {
+    const int e = b0 + lane, nb = nnb - b0 < 64 ? nnb - b0 : 64;
+    int nd = 0;
+    int64_t io = 0;
+    if (e < nnb) {
+      const int d = nbrs[S.nbr_begin + e].d;
+      nd = dyn.n[d];
+      io = segs[d].ioff;
+    }
+    int incl = nd;  // inclusive prefix sum of the sizes over the lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    const int tot = __shfl(incl, 63, 64);
+    s_ioff[lane] = io;
+    s_excl[lane] = incl - nd;
+    wave_sync();
+    nV += double(tot);
     double cnt = 0.0;
-    for (int i = lane; i < nd; i += 64) {
+    for (int t = lane; t < tot; t += 64) {
+      int owner = 0;  // the last neighbour whose list starts at or before t
+      for (int q = 1; q < nb; ++q)
+        if (s_excl[q] <= t) owner = q;
       int cv[3];
-      vcoords(g, dd[i], cv);
+      vcoords(g, iarena[s_ioff[owner] + (t - s_excl[owner])], cv);
       int dist = 0;
       for (int a = 0; a < 3; ++a) {
         int da = S.lo[a] - cv[a];
@@ -92,6 +131,7 @@ __global__ __launch_bounds__(64) void k_features(const DSeg* segs, int nseg, con
       cnt += dist <= S.thr ? 1.0 : 0.0;
     }
     nearc += 2.0 * wave_sum(cnt);
+    wave_sync();
   }
   if (lane == 0) {
     int span = 0;

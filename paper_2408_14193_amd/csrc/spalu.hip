@@ -81,6 +81,7 @@ struct Layout {
   int leaf_ni_max = 0;
   size_t o_status = 0;
   size_t o_feats = 0, o_hinit = 0;  // rank predictor: features, start samples
+  size_t o_vfeat = 0;               // rank predictor: per-vertex feature parts (3 doubles)
   size_t bytes = 0;
   int64_t nseg_total = 0;
   std::vector<int64_t> seg_base;  // per level
@@ -500,6 +501,7 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
   Y.o_status = put(64);
   Y.o_feats = put(size_t(Y.nseg_total) * MLP_NF * 4);
   Y.o_hinit = put(size_t(Y.nseg_total) * 4);
+  Y.o_vfeat = put(size_t(P.N) * 3 * 8);
   Y.o_iarena = put(iar * 4);
   Y.n_iarena = iar;
   Y.o_varena = put(var * Y.vsize);
@@ -931,6 +933,10 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
           tab<int32_t>(ws, Y.o_lc_ptr), tab<DLeafContrib>(ws, Y.o_lc), tab<DLeaf>(ws, Y.o_leaves),
           F->rowptr, F->colind, F->vals, var));
   }
+  double* vfeat = reinterpret_cast<double*>(ws + Y.o_vfeat);
+  if (o.rank_model || o.features_out)
+    LAUNCH(K_FEAT, -1, k_vertex_features<<<nblocks(F->n), WG, 0, st>>>(F->n, F->rowptr, F->colind, F->vals, F->g,
+                                                                      P.dim, vfeat));
   for (int l = L; l >= 1; --l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
@@ -950,8 +956,7 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       float* feats = (o.features_out ? o.features_out : reinterpret_cast<float*>(ws + Y.o_feats)) +
                      size_t(Y.seg_base[l]) * MLP_NF;
       LAUNCH(K_FEAT, l, k_features<<<unsigned(ns), 64, 0, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), F->g, P.dim, L,
-                                                                l, o.eps, iar, d, F->rowptr, F->colind, F->vals,
-                                                                feats));
+                                                                l, o.eps, iar, d, vfeat, feats));
       if (o.rank_model) {
         int32_t* hinit = reinterpret_cast<int32_t*>(ws + Y.o_hinit);
         const unsigned mblk = unsigned((ns + WG / MLP_G - 1) / (WG / MLP_G));
