@@ -10,25 +10,52 @@
 
 namespace spalu {
 
+// Layout changes between the caller's column-major FP64 vectors (ld) and
+// the DOF-major working layout W[v * nrhs + j] in the storage type, through
+// an LDS tile of RHS_TV vertices x RHS_TJ columns (grid: vertex tiles x
+// column tiles), so both sides are read and written with consecutive
+// addresses.
+constexpr int RHS_TV = 64;
+constexpr int RHS_TJ = 32;
+
 template <typename T>
-__global__ void k_rhs_in(const double* B, int64_t ldb, int64_t n, int nrhs, T* W) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n * nrhs) return;
-  const int64_t v = t / nrhs;
-  const int j = int(t % nrhs);
-  W[t] = T(B[v + j * ldb]);
+__global__ __launch_bounds__(WG) void k_rhs_in(const double* B, int64_t ldb, int64_t n, int nrhs, T* W) {
+  __shared__ double tile[RHS_TJ][RHS_TV + 1];
+  const int64_t v0 = int64_t(blockIdx.x) * RHS_TV;
+  const int j0 = blockIdx.y * RHS_TJ;
+  const int nv = n - v0 < RHS_TV ? int(n - v0) : RHS_TV;
+  const int nj = nrhs - j0 < RHS_TJ ? nrhs - j0 : RHS_TJ;
+  for (int t = threadIdx.x; t < RHS_TV * RHS_TJ; t += WG) {
+    const int j = t / RHS_TV, vl = t % RHS_TV;
+    if (j < nj && vl < nv) tile[j][vl] = B[v0 + vl + (j0 + j) * ldb];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nv * nj; t += WG) {
+    const int vl = t / nj, j = t - vl * nj;
+    W[(v0 + vl) * nrhs + j0 + j] = T(tile[j][vl]);
+  }
 }
 
 template <typename T>
-__global__ void k_rhs_out(const T* W, int64_t n, int nrhs, double* X, int64_t ldx, int accumulate) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n * nrhs) return;
-  const int64_t v = t / nrhs;
-  const int j = int(t % nrhs);
-  if (accumulate)
-    X[v + j * ldx] += double(W[t]);
-  else
-    X[v + j * ldx] = double(W[t]);
+__global__ __launch_bounds__(WG) void k_rhs_out(const T* W, int64_t n, int nrhs, double* X, int64_t ldx,
+                                                int accumulate) {
+  __shared__ double tile[RHS_TJ][RHS_TV + 1];
+  const int64_t v0 = int64_t(blockIdx.x) * RHS_TV;
+  const int j0 = blockIdx.y * RHS_TJ;
+  const int nv = n - v0 < RHS_TV ? int(n - v0) : RHS_TV;
+  const int nj = nrhs - j0 < RHS_TJ ? nrhs - j0 : RHS_TJ;
+  for (int t = threadIdx.x; t < nv * nj; t += WG) {
+    const int vl = t / nj, j = t - vl * nj;
+    tile[j][vl] = double(W[(v0 + vl) * nrhs + j0 + j]);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < RHS_TV * RHS_TJ; t += WG) {
+    const int j = t / RHS_TV, vl = t % RHS_TV;
+    if (j < nj && vl < nv) {
+      double* x = X + v0 + vl + (j0 + j) * ldx;
+      *x = accumulate ? *x + tile[j][vl] : tile[j][vl];
+    }
+  }
 }
 
 // Leaf interiors: Z_I = A_II^{-1} W_I (forward) or

@@ -1070,6 +1070,11 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
   return SPALU_OK;
 }
 
+// Grid of the layout-change kernels: vertex tiles x column tiles.
+inline dim3 rhs_grid(int64_t n, int nrhs) {
+  return dim3(unsigned((n + RHS_TV - 1) / RHS_TV), unsigned((nrhs + RHS_TJ - 1) / RHS_TJ));
+}
+
 struct SolveWs {
   size_t oW, oZ, oB0, oR, oPr, oPb, oNr, oNb;
   size_t oV, oZk, oKs, oKp, oH1, oH2, oEst;  // flexible GMRES (restart > 0)
@@ -1282,11 +1287,11 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     Bsrc = R;
     ldbres = F->n;
   }
-  LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(B, ldb, F->n, nrhs, B0));
+  LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<rhs_grid(F->n, nrhs), WG, 0, st>>>(B, ldb, F->n, nrhs, B0));
   const bool graph = so.graph != 0;
   int rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);
   if (rc) return rc;
-  LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 0));
+  LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<rhs_grid(F->n, nrhs), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 0));
   if (!want_res) {
     prof_flush(F, nrhs);
     return SPALU_OK;
@@ -1325,10 +1330,10 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     if (slow >= 3) break;
     if (so.restart == 0) {
       // correction: solve with r as right-hand side, x += M r
-      LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(R, F->n, F->n, nrhs, B0));
+      LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<rhs_grid(F->n, nrhs), WG, 0, st>>>(R, F->n, F->n, nrhs, B0));
       rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);
       if (rc) return rc;
-      LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 1));
+      LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<rhs_grid(F->n, nrhs), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 1));
       ++it;
       continue;
     }
@@ -1351,10 +1356,10 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     for (int c = 0; c < m && it < so.max_iter; ++c) {
       double* Vc = V + size_t(c) * nn;
       double* Zc = Zk + size_t(c) * nn;
-      LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<nblocks(nn), WG, 0, st>>>(Vc, F->n, F->n, nrhs, B0));
+      LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<rhs_grid(F->n, nrhs), WG, 0, st>>>(Vc, F->n, F->n, nrhs, B0));
       rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);
       if (rc) return rc;
-      LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<nblocks(nn), WG, 0, st>>>(W, F->n, nrhs, Zc, F->n, 0));
+      LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<rhs_grid(F->n, nrhs), WG, 0, st>>>(W, F->n, nrhs, Zc, F->n, 0));
       ++it;
       LAUNCH(K_SPMV, 0, k_spmv<<<s.rblk, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Zc, R));
       // two classical Gram-Schmidt passes: the dots of w; w -= V h1 with
