@@ -271,6 +271,12 @@ typedef struct {
 
 void spalu_profile(int32_t on);
 
+/* Restricts the event timing of spalu_profile to the launches of one kernel
+ * step (a name as spalu_profile_read reports it), so that a timed region
+ * carries the events of that step only; NULL or "" times every step again
+ * (so does spalu_profile).  Returns SPALU_EINVAL for an unknown name. */
+int spalu_profile_only(const char* name);
+
 /* Copies up to max per-kernel totals into out (host); *count = kernels with
  * at least one launch.  out may be NULL to query the count. */
 int spalu_profile_read(spalu_kernel_stat* out, int32_t max, int32_t* count);

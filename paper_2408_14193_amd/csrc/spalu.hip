@@ -571,15 +571,30 @@ struct TimedLaunch {
 
 struct Profiler {
   bool on = false;
+  int only = -1;  // >= 0: time the launches of this step only
   std::vector<PendingLaunch> pend;
   std::vector<TimedLaunch> done;  // accounted lazily in spalu_profile_read
+  std::vector<hipEvent_t> spare;  // events of harvested launches, reused (creating one per launch
+                                  // costs host time inside the timed region)
   int64_t launches[K_COUNT] = {};
   double ms[K_COUNT] = {}, bytes[K_COUNT] = {}, flops[K_COUNT] = {};
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!spare.empty()) {
+      e = spare.back();
+      spare.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
   void reset() {
     for (auto& p : pend) {
       (void)hipEventDestroy(p.a);
       (void)hipEventDestroy(p.b);
     }
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+    spare.clear();
     pend.clear();
     done.clear();
     for (int k = 0; k < K_COUNT; ++k) launches[k] = 0, ms[k] = bytes[k] = flops[k] = 0.0;
@@ -589,9 +604,13 @@ Profiler g_prof;
 const bool g_prof_verbose = std::getenv("SPALU_PROFILE_VERBOSE") != nullptr;
 
 int prof_begin(int kid, int level, hipStream_t st, bool acct = true) {
-  if (!g_prof.on) return -1;
-  PendingLaunch p{kid, level, acct, nullptr, nullptr};
-  if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return -1;
+  if (!g_prof.on || (g_prof.only >= 0 && kid != g_prof.only)) return -1;
+  PendingLaunch p{kid, level, acct, g_prof.take(), g_prof.take()};
+  if (!p.a || !p.b) {
+    if (p.a) g_prof.spare.push_back(p.a);
+    if (p.b) g_prof.spare.push_back(p.b);
+    return -1;
+  }
   (void)hipEventRecord(p.a, st);
   g_prof.pend.push_back(p);
   return int(g_prof.pend.size()) - 1;
@@ -794,8 +813,8 @@ void prof_flush(const spalu_factor_t* F, int nrhs) {
     (void)hipEventSynchronize(p.b);
     if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) ms = 0.f;
     g_prof.done.push_back(TimedLaunch{p.kid, p.level, nrhs, p.acct, double(ms), F->n, F->lay_sp, F->dyn_host});
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
+    g_prof.spare.push_back(p.a);
+    g_prof.spare.push_back(p.b);
   }
   g_prof.pend.clear();
 }
@@ -1826,6 +1845,20 @@ int spalu_mlp_train_step(float* params, float* adam_m, float* adam_v, const floa
 void spalu_profile(int32_t on) {
   g_prof.reset();
   g_prof.on = on != 0;
+  g_prof.only = -1;
+}
+
+int spalu_profile_only(const char* name) {
+  if (!name || !name[0]) {
+    g_prof.only = -1;
+    return SPALU_OK;
+  }
+  for (int k = 0; k < K_COUNT; ++k)
+    if (std::strcmp(kNames[k], name) == 0) {
+      g_prof.only = k;
+      return SPALU_OK;
+    }
+  return fail(SPALU_EINVAL, "unknown kernel step name");
 }
 
 int spalu_profile_read(spalu_kernel_stat* out, int32_t max, int32_t* count) {

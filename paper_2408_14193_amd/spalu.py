@@ -109,6 +109,8 @@ _lib.spalu_mlp_train_step.argtypes = [P, P, P, P, P, C.c_int32, C.c_float, C.c_i
                                       C.c_size_t, P]
 _lib.spalu_profile.argtypes = [C.c_int32]
 _lib.spalu_profile.restype = None
+_lib.spalu_profile_only.argtypes = [C.c_char_p]
+_lib.spalu_profile_only.restype = C.c_int
 _lib.spalu_profile_read.argtypes = [C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]
 
 EXPORTED = ["spalu_nd_order", "spalu_nd_info", "spalu_nd_perm", "spalu_nd_etree",
@@ -116,7 +118,8 @@ EXPORTED = ["spalu_nd_order", "spalu_nd_info", "spalu_nd_perm", "spalu_nd_etree"
             "spalu_factor_workspace", "spalu_factor_seg_base", "spalu_factor",
             "spalu_factor_ranks", "spalu_factor_work", "spalu_factor_free", "spalu_solve_workspace", "spalu_solve",
             "spalu_mlp_param_count", "spalu_mlp_workspace", "spalu_mlp_forward",
-            "spalu_mlp_train_step", "spalu_profile", "spalu_profile_read", "spalu_last_error"]
+            "spalu_mlp_train_step", "spalu_profile", "spalu_profile_only", "spalu_profile_read",
+            "spalu_last_error"]
 
 
 def _check(rc):
@@ -304,6 +307,11 @@ class Factor:
 def profile(on=True):
     """Enable (and clear) or disable per-kernel event timing in the library."""
     _lib.spalu_profile(1 if on else 0)
+
+
+def profile_only(name=None):
+    """Restrict the event timing to one kernel step (None: every step)."""
+    _check(_lib.spalu_profile_only(name.encode() if name else None))
 
 
 def profile_read():
