@@ -88,12 +88,18 @@ struct Layout {
   size_t leaf_i0 = 0, leaf_i1 = 0;  // int-arena range of the leaf lists
   int dim = 2, L = 0;
   double nsep_verts = 0.0;  // vertices on separators (all levels)
-  // host image of the tables (pinned), rebuilt only when rho changes
+  // host image of the tables (pinned), rebuilt only when rho changes, and
+  // its copy in device memory (device dimage_dev), from which every
+  // factorization's workspace is filled by a device-to-device copy
   char* image = nullptr;
   size_t image_bytes = 0;
   double image_rho = -1.0;
+  char* dimage = nullptr;
+  int dimage_dev = -1;
+  double dimage_rho = -1.0;
   ~Layout() {
     if (image) (void)hipHostFree(image);
+    if (dimage) (void)hipFree(dimage);
   }
 };
 
@@ -1640,10 +1646,26 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   Layout* YM = const_cast<Layout*>(Y);
   const int irc = build_image(P, YM, o.rho);
   if (irc) return irc;
-  HIPCHK(hipMemcpyAsync(F->ws, YM->image, Y->blob_bytes, hipMemcpyHostToDevice, F->stream));
+  // the tables reach the workspace from the device copy of the image (kept
+  // per layout and device; rebuilt when rho changes)
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const size_t img_bytes = Y->blob_bytes + (Y->leaf_i1 - Y->leaf_i0) * 4;
+  if (!YM->dimage || YM->dimage_dev != dev || YM->dimage_rho != o.rho) {
+    if (YM->dimage) {
+      HIPCHK(hipDeviceSynchronize());  // earlier factorizations may still be reading it
+      (void)hipFree(YM->dimage);
+      YM->dimage = nullptr;
+    }
+    HIPCHK(hipMalloc(reinterpret_cast<void**>(&YM->dimage), std::max<size_t>(img_bytes, 1)));
+    HIPCHK(hipMemcpy(YM->dimage, YM->image, img_bytes, hipMemcpyHostToDevice));
+    YM->dimage_dev = dev;
+    YM->dimage_rho = o.rho;
+  }
+  HIPCHK(hipMemcpyAsync(F->ws, YM->dimage, Y->blob_bytes, hipMemcpyDeviceToDevice, F->stream));
   if (Y->leaf_i1 > Y->leaf_i0)
-    HIPCHK(hipMemcpyAsync(F->ws + Y->o_iarena + Y->leaf_i0 * 4, YM->image + Y->blob_bytes,
-                          (Y->leaf_i1 - Y->leaf_i0) * 4, hipMemcpyHostToDevice, F->stream));
+    HIPCHK(hipMemcpyAsync(F->ws + Y->o_iarena + Y->leaf_i0 * 4, YM->dimage + Y->blob_bytes,
+                          (Y->leaf_i1 - Y->leaf_i0) * 4, hipMemcpyDeviceToDevice, F->stream));
   int status = 0;
   int rc = o.precision == SPALU_FP64 ? run_factor<double>(F.get(), o, &status)
                                      : run_factor<float>(F.get(), o, &status);

@@ -253,6 +253,19 @@ hipError_t hipHostMalloc(void** p, size_t n, unsigned) {
   *p = std::malloc(n ? n : 1);
   return hipSuccess;
 }
+hipError_t hipMalloc(void** p, size_t n) {
+  *p = std::malloc(n ? n : 1);
+  return hipSuccess;
+}
+hipError_t hipFree(void* p) {
+  std::free(p);
+  return hipSuccess;
+}
+hipError_t hipGetDevice(int* d) {
+  *d = 0;
+  return hipSuccess;
+}
+hipError_t hipDeviceSynchronize() { return hipSuccess; }
 hipError_t hipHostFree(void* p) {
   std::free(p);
   return hipSuccess;

@@ -127,6 +127,10 @@ hipError_t hipEventRecord(hipEvent_t, hipStream_t = nullptr);
 hipError_t hipEventSynchronize(hipEvent_t);
 hipError_t hipEventElapsedTime(float*, hipEvent_t, hipEvent_t);
 hipError_t hipHostMalloc(void**, size_t, unsigned = 0);
+hipError_t hipMalloc(void**, size_t);
+hipError_t hipFree(void*);
+hipError_t hipGetDevice(int*);
+hipError_t hipDeviceSynchronize();
 hipError_t hipHostFree(void*);
 hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int);
 hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode);
