@@ -88,6 +88,13 @@ __device__ inline int id_tier(const DSeg& S, int n, int R, double eps, IdTiers t
   return id_tier_of_size(n, R, t);
 }
 
+// 64-bit value of lane src (two 32-bit shuffles).
+__device__ inline int64_t shfl_i64(int64_t v, int src) {
+  const int lo = __shfl(int(uint32_t(uint64_t(v))), src, 64);
+  const int hi = __shfl(int(uint32_t(uint64_t(v) >> 32)), src, 64);
+  return int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo));
+}
+
 template <int NW>
 __device__ inline void grp_sync() {
   if constexpr (NW == 1)
@@ -246,48 +253,110 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   // ---- 1. row table: near rows listed from the front, far rows from the back ----
   if (w == 0) {
     int nN = 0, nF = 0, r0 = 0;
+    const int nnb = S.nbr_end - S.nbr_begin;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
-      const DNbr nb = nbrs[e];
-      const int nd = dyn.n[nb.d];
-      const int32_t* dd = iarena + segs[nb.d].ioff;
-      const int64_t off0 = blks[nb.blk_dc].off, off1 = blks[nb.blk_cd].off;
-      for (int half = 0; half < 2; ++half) {
-        for (int i0 = 0; i0 < nd; i0 += 64) {
-          const int i = i0 + lane;
-          const bool valid = i < nd;
-          int v = 0;
-          bool near = false;
-          if (valid) {
-            v = dd[i];
-            int cv[3];
-            vcoords(g, v, cv);
-            int dist = 0;
-            for (int a = 0; a < 3; ++a) {
-              int da = S.lo[a] - cv[a];
-              if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
-              if (da > dist) dist = da;
-            }
-            near = dist <= S.thr;
-          }
-          const uint64_t mn = __ballot(valid && near), mf = __ballot(valid && !near);
-          if (valid) {
-            const int r = r0 + half * nd + i;
-            IdRow m;
-            m.base = half == 0 ? off0 + int64_t(i) * n : off1 + i;
-            m.stride = half == 0 ? 1 : nd;
-            m.vh = 2 * v + half;
-            rows[r] = m;
-            if (near)
-              order[nN + __popcll(mn & below)] = r;
-            else
-              order[R - 1 - (nF + __popcll(mf & below))] = r;
-          }
-          nN += __popcll(mn);
-          nF += __popcll(mf);
-        }
+    if (nnb <= 64) {
+      // neighbour e = lane: its size, DOF list and block offsets, loaded
+      // together; its rows start at rs (exclusive prefix sum of 2 n_d).
+      // Row r of the table (neighbour, half, index) is then found by each
+      // lane from these, so the whole table costs one more trip to memory
+      int nd_l = 0;
+      int64_t io_l = 0, o0_l = 0, o1_l = 0;
+      if (lane < nnb) {
+        const DNbr nb = nbrs[S.nbr_begin + lane];
+        nd_l = dyn.n[nb.d];
+        io_l = segs[nb.d].ioff;
+        o0_l = blks[nb.blk_dc].off;
+        o1_l = blks[nb.blk_cd].off;
       }
-      r0 += 2 * nd;
+      int rs = 2 * nd_l;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(rs, o, 64);
+        if (lane >= o) rs += t;
+      }
+      rs -= 2 * nd_l;
+      for (int rb = 0; rb < R; rb += 64) {
+        const int r = rb + lane;
+        const bool valid = r < R;
+        int owner = 0;  // the last neighbour whose rows start at or before r
+        for (int q = 1; q < nnb; ++q)
+          if (r >= __shfl(rs, q, 64)) owner = q;
+        const int nd = __shfl(nd_l, owner, 64), rr = r - __shfl(rs, owner, 64);
+        const int half = rr >= nd ? 1 : 0, i = rr - half * nd;
+        const int64_t io = shfl_i64(io_l, owner), off0 = shfl_i64(o0_l, owner), off1 = shfl_i64(o1_l, owner);
+        int v = 0;
+        bool near = false;
+        if (valid) {
+          v = iarena[io + i];
+          int cv[3];
+          vcoords(g, v, cv);
+          int dist = 0;
+          for (int a = 0; a < 3; ++a) {
+            int da = S.lo[a] - cv[a];
+            if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
+            if (da > dist) dist = da;
+          }
+          near = dist <= S.thr;
+        }
+        const uint64_t mn = __ballot(valid && near), mf = __ballot(valid && !near);
+        if (valid) {
+          IdRow m;
+          m.base = half == 0 ? off0 + int64_t(i) * n : off1 + i;
+          m.stride = half == 0 ? 1 : nd;
+          m.vh = 2 * v + half;
+          rows[r] = m;
+          if (near)
+            order[nN + __popcll(mn & below)] = r;
+          else
+            order[R - 1 - (nF + __popcll(mf & below))] = r;
+        }
+        nN += __popcll(mn);
+        nF += __popcll(mf);
+      }
+    } else {
+      for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+        const DNbr nb = nbrs[e];
+        const int nd = dyn.n[nb.d];
+        const int32_t* dd = iarena + segs[nb.d].ioff;
+        const int64_t off0 = blks[nb.blk_dc].off, off1 = blks[nb.blk_cd].off;
+        for (int half = 0; half < 2; ++half) {
+          for (int i0 = 0; i0 < nd; i0 += 64) {
+            const int i = i0 + lane;
+            const bool valid = i < nd;
+            int v = 0;
+            bool near = false;
+            if (valid) {
+              v = dd[i];
+              int cv[3];
+              vcoords(g, v, cv);
+              int dist = 0;
+              for (int a = 0; a < 3; ++a) {
+                int da = S.lo[a] - cv[a];
+                if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
+                if (da > dist) dist = da;
+              }
+              near = dist <= S.thr;
+            }
+            const uint64_t mn = __ballot(valid && near), mf = __ballot(valid && !near);
+            if (valid) {
+              const int r = r0 + half * nd + i;
+              IdRow m;
+              m.base = half == 0 ? off0 + int64_t(i) * n : off1 + i;
+              m.stride = half == 0 ? 1 : nd;
+              m.vh = 2 * v + half;
+              rows[r] = m;
+              if (near)
+                order[nN + __popcll(mn & below)] = r;
+              else
+                order[R - 1 - (nF + __popcll(mf & below))] = r;
+            }
+            nN += __popcll(mn);
+            nF += __popcll(mf);
+          }
+        }
+        r0 += 2 * nd;
+      }
     }
     if (lane == 0) {
       s_cnt[0] = nN;
