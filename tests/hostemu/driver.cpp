@@ -104,7 +104,13 @@ int main(int argc, char** argv) {
     spalu_solve_opts so{tol, 30, 1, restart};
     spalu_solve_workspace(F, nrhs, &so, &sb);
     void* sw = guarded(sb);
-    std::memset(sw, 0x5A, sb);
+    {
+      // NaN bytes by default: a value read before it is written, even one
+      // multiplied by zero, poisons the result
+      const char* gf = std::getenv("EMU_SOLVE_FILL");
+      const int fill = gf ? std::atoi(gf) : 0xFF;
+      std::memset(sw, fill, sb);
+    }
     spalu_solve_info si{};
     rc = spalu_solve(F, nrhs, B, n, X, n, &so, sw, sb, nullptr, nullptr, &si);
     std::printf("solve rc %d (%s) iters %d first %.3e final %.3e\n", rc, rc ? spalu_last_error() : "ok",
