@@ -20,9 +20,13 @@
  *     the caller's stream (a hipStream_t passed as void*, NULL = the null
  *     stream); calls return after their last host read, so results are
  *     ready once the caller synchronises that stream.
- *   - The library allocates no device memory: the caller queries a size,
- *     allocates (for example through PyTorch's caching allocator) and
- *     passes the buffer, which must stay alive until the matching free.
+ *   - Working memory is the caller's: the caller queries a size, allocates
+ *     (for example through PyTorch's caching allocator) and passes the
+ *     buffer, which must stay alive until the matching free.  The library
+ *     itself allocates only one device copy of an ordering's static tables
+ *     per precision and device (at the first spalu_factor), from which
+ *     every factorization's workspace is filled; spalu_nd_free releases
+ *     it.
  *   - Vertex ids: interior grid node (x, y, z) has id x + nx*(y + ny*z).
  */
 #ifndef SPALU_H
