@@ -494,6 +494,7 @@ struct IdParams {
 // wave 0 searches the next pivot.  Steps j < split search rows [j, split),
 // later steps rows [j, n); ties go to the smaller row.  piv[j] = row swapped
 // with row j.  Returns 1 if a pivot was zero (that step is skipped).
+template <int NT>
 __device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s_piv) {
   const int tid = threadIdx.x;
   int singular = 0;
@@ -514,11 +515,11 @@ __device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s
       if (tid == 0) *s_piv = bi < n ? bi : j;
     }
     if (dprev != 0.0)
-      for (int i = j + tid; i < n; i += WG) A[i * n + j - 1] /= dprev;
+      for (int i = j + tid; i < n; i += NT) A[i * n + j - 1] /= dprev;
     __syncthreads();
     const int p = *s_piv;
     if (p != j)
-      for (int c = tid; c < n; c += WG) {
+      for (int c = tid; c < n; c += NT) {
         const double t = A[j * n + c];
         A[j * n + c] = A[p * n + c];
         A[p * n + c] = t;
@@ -532,14 +533,14 @@ __device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s
       continue;  // uniform; column j stays unscaled
     }
     const int m = n - j - 1;
-    if (m > 0 && m <= WG) {
-      const int rstep = WG / m, r0 = tid / m, col = j + 1 + (tid - r0 * m);
+    if (m > 0 && m <= NT) {
+      const int rstep = NT / m, r0 = tid / m, col = j + 1 + (tid - r0 * m);
       if (r0 < rstep) {
         const double u = A[j * n + col] / d;
         for (int i = j + 1 + r0; i < n; i += rstep) A[i * n + col] -= A[i * n + j] * u;
       }
-    } else if (m > WG) {
-      for (int col = j + 1 + tid; col < n; col += WG) {
+    } else if (m > NT) {
+      for (int col = j + 1 + tid; col < n; col += NT) {
         const double u = A[j * n + col] / d;
         for (int i = j + 1; i < n; ++i) A[i * n + col] -= A[i * n + j] * u;
       }
@@ -557,10 +558,10 @@ __device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s
 // of L and column n-1-s of U (disjoint triangles of X, one barrier per
 // step).  The diagonal of X holds 1 / U[i][i]; the unit diagonals are
 // implied.
-template <typename TO>
+template <int NT, typename TO>
 __device__ inline void seg_block_inverse(const double* W, int n, double* X, TO* out) {
   const int tid = threadIdx.x;
-  for (int t = tid; t < n * n; t += WG) {
+  for (int t = tid; t < n * n; t += NT) {
     const int i = t / n, c = t - i * n;
     X[t] = i == c ? 1.0 / W[t] : 0.0;
   }
@@ -568,9 +569,9 @@ __device__ inline void seg_block_inverse(const double* W, int n, double* X, TO* 
   for (int s = 0; s < n - 1; ++s) {
     const int jl = s, ju = n - 1 - s;
     const int R = n - 1 - s, C = s + 1;  // rows and columns of both updates
-    for (int c0 = 0; c0 < C; c0 += WG) {
-      const int cw = C - c0 < WG ? C - c0 : WG;
-      const int rstep = WG / cw, r0 = tid / cw, cq = c0 + tid - r0 * cw;
+    for (int c0 = 0; c0 < C; c0 += NT) {
+      const int cw = C - c0 < NT ? C - c0 : NT;
+      const int rstep = NT / cw, r0 = tid / cw, cq = c0 + tid - r0 * cw;
       if (r0 < rstep) {
         // L: X[jl+1+r][cq] -= L[jl+1+r][jl] X[jl][cq]  (X[jl][jl] = 1)
         const double xl = cq == jl ? 1.0 : X[jl * n + cq];
@@ -586,7 +587,7 @@ __device__ inline void seg_block_inverse(const double* W, int n, double* X, TO* 
     }
     __syncthreads();
   }
-  for (int t = tid; t < n * n; t += WG) {
+  for (int t = tid; t < n * n; t += NT) {
     const int i = t / n, c = t - i * n;
     out[t] = TO(i > c ? X[t] : (i == c ? 1.0 : X[t]) * X[c * n + c]);
   }
@@ -597,8 +598,8 @@ __device__ inline void seg_block_inverse(const double* W, int n, double* X, TO* 
 // Transform U_t A L_t of the diagonal block and two-stage LU (eqs. (2.7),
 // (4.10)); the DOF list is reordered to [remainder; skeleton].
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const DBlk* blks,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_seg_lu(const DSeg* segs, int nseg, const DBlk* blks,
                                                int32_t* iarena, T* varena, double* scratch,
                                                DLevelDyn dyn, int* status, int need_lo, int need_hi,
                                                int lds_doubles) {
@@ -628,10 +629,10 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   // gather in [r; s] order: row/column p of W is om[p] = perm[k + p]
   // (p < nr), perm[p - nr] (p >= nr) of the block; the block's entries are
   // loaded in batches
-  for (int p = tid; p < n; p += WG) om[p] = sp ? (p < nr ? perm[k + p] : perm[p - nr]) : p;
+  for (int p = tid; p < n; p += NT) om[p] = sp ? (p < nr ? perm[k + p] : perm[p - nr]) : p;
   __syncthreads();
   load_batched<8>(
-      n * n, tid, WG,
+      n * n, tid, NT,
       [&](int t) {
         const int p = t / n, q = t - p * n;
         return M[size_t(om[p]) * n + om[q]];
@@ -640,10 +641,10 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   __syncthreads();
   if (sp && nr > 0 && k > 0) {
     // T (k x nr) staged next to W
-    stage_batched<8>(varena + S.t_off, k * nr, tid, WG, [&](int t, T v) { X[t] = double(v); });
+    stage_batched<8>(varena + S.t_off, k * nr, tid, NT, [&](int t, T v) { X[t] = double(v); });
     __syncthreads();
     // columns: W[:, q] -= W[:, nr:] T[:, q]
-    for (int t = tid; t < n * nr; t += WG) {
+    for (int t = tid; t < n * nr; t += NT) {
       const int p = t / nr, q = t - p * nr;
       double s = 0.0;
       for (int i = 0; i < k; ++i) s += W[size_t(p) * n + nr + i] * X[i * nr + q];
@@ -651,7 +652,7 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
     }
     __syncthreads();
     // rows: W[p, :] -= T[:, p]^T W[nr:, :]
-    for (int t = tid; t < nr * n; t += WG) {
+    for (int t = tid; t < nr * n; t += NT) {
       const int p = t / n, q = t - p * n;
       double s = 0.0;
       for (int i = 0; i < k; ++i) s += X[i * nr + p] * W[size_t(nr + i) * n + q];
@@ -663,11 +664,11 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
   // would stall each step), copied out afterwards
   const bool pv_lds = inlds && need + (n + 1) / 2 <= lds_doubles;
   int* pv = pv_lds ? reinterpret_cast<int*>(lds + need) : piv;
-  if (seg_block_lu(W, n, sp ? nr : 0, pv, &s_piv)) atomicOr(status, 1);
+  if (seg_block_lu<NT>(W, n, sp ? nr : 0, pv, &s_piv)) atomicOr(status, 1);
   __syncthreads();
   // stored form of the interchanges: the composed row map (row i of P X is
   // row piv[i] of X), each entry traced back through the interchanges
-  for (int i = tid; i < n; i += WG) {
+  for (int i = tid; i < n; i += NT) {
     int pos = i;
     for (int r = n - 1; r >= 0; --r) {
       const int p = pv[r];
@@ -676,16 +677,16 @@ __global__ __launch_bounds__(WG) void k_seg_lu(const DSeg* segs, int nseg, const
     tmp[i] = pos;
   }
   __syncthreads();
-  for (int i = tid; i < n; i += WG) piv[i] = tmp[i];
+  for (int i = tid; i < n; i += NT) piv[i] = tmp[i];
   __syncthreads();
   // packed inverses: strictly lower part of L^{-1} (unit diagonal implied)
   // and upper part of U^{-1}, so every later application is a product
   T* LU = varena + S.lu_off;
-  seg_block_inverse(W, n, X, LU);
+  seg_block_inverse<NT>(W, n, X, LU);
   if (sp) {
-    for (int p = tid; p < n; p += WG) tmp[p] = dofs[p < nr ? perm[k + p] : perm[p - nr]];
+    for (int p = tid; p < n; p += NT) tmp[p] = dofs[p < nr ? perm[k + p] : perm[p - nr]];
     __syncthreads();
-    for (int p = tid; p < n; p += WG) dofs[p] = tmp[p];
+    for (int p = tid; p < n; p += NT) dofs[p] = tmp[p];
   }
 }
 

@@ -166,6 +166,7 @@ constexpr size_t ID_B_MAX_BYTES = 72 * 1024;    // 256-thread groups: two per CU
 constexpr size_t ID_B2_MAX_BYTES = 152 * 1024;  // tier-B2 groups: one per CU
 constexpr size_t SEGLU_MAX_BYTES = 152 * 1024;   // segment LU of large segments
 constexpr int SEGLU_WAVE_MAX_N = 32;             // segments up to this size: one wave each
+constexpr int SEGLU_BLOCK_NT = 256;              // threads of the block segment LU (one block per CU)
 constexpr size_t MELIM_LDS_BYTES = 64 * 1024;   // staged separator terms of the merge
 
 // Which ID launches a level needs and their LDS budgets.  The sizes known
@@ -1046,8 +1047,8 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       // segments of up to 32 DOFs: one wave each; wider ones: one block each
       // with up to 152 KB of LDS (scratch beyond that)
       static const bool lu_lds_ok =
-          hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_lu<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              int(SEGLU_MAX_BYTES)) == hipSuccess;
+          hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_lu<T, SEGLU_BLOCK_NT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(SEGLU_MAX_BYTES)) == hipSuccess;
       if (!lu_lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the segment LU kernel");
       const int nw = std::min(SEGLU_WAVE_MAX_N, T_.max_cap);
       LAUNCH(K_LU, l, k_seg_lu_wave<T, 1><<<unsigned(ns), 64, size_t(seglu_wave_lds_doubles(nw)) * 8, st>>>(
@@ -1055,7 +1056,7 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       if (T_.max_cap > SEGLU_WAVE_MAX_N) {
         const int64_t cap = T_.max_cap;
         const int big = int(std::min<int64_t>(2 * cap * cap + cap, int64_t(SEGLU_MAX_BYTES / 8)));
-        LAUNCH_MORE(K_LU, l, k_seg_lu<T><<<unsigned(ns), WG, size_t(big) * 8, st>>>(
+        LAUNCH_MORE(K_LU, l, k_seg_lu<T, SEGLU_BLOCK_NT><<<unsigned(ns), SEGLU_BLOCK_NT, size_t(big) * 8, st>>>(
             segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, INT32_MAX, big));
       }
     }
