@@ -148,11 +148,16 @@ struct spalu_factor_s {
   hipStream_t aux[3] = {nullptr, nullptr, nullptr};
   hipEvent_t fork = nullptr;
   hipEvent_t join[3] = {nullptr, nullptr, nullptr};
+  // after a level's segment LU, the merge sizes and the next level's
+  // features and predictions run on aux[0] beside the coupling scaling
+  hipEvent_t lu_done = nullptr, msize_done = nullptr, pre_done = nullptr;
   ~spalu_factor_s() {
     for (hipStream_t s : aux)
       if (s) (void)hipStreamDestroy(s);
     if (fork) (void)hipEventDestroy(fork);
     for (hipEvent_t e : join)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {lu_done, msize_done, pre_done})
       if (e) (void)hipEventDestroy(e);
   }
 };
@@ -915,6 +920,9 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       HIPCHK(hipStreamCreateWithFlags(&F->aux[i], hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&F->join[i], hipEventDisableTiming));
     }
+    HIPCHK(hipEventCreateWithFlags(&F->lu_done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&F->msize_done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&F->pre_done, hipEventDisableTiming));
   }
   int32_t* iar = reinterpret_cast<int32_t*>(ws + Y.o_iarena);
   T* var = reinterpret_cast<T*>(ws + Y.o_varena);
@@ -960,9 +968,30 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
           F->rowptr, F->colind, F->vals, var));
   }
   double* vfeat = reinterpret_cast<double*>(ws + Y.o_vfeat);
-  if (o.rank_model || o.features_out)
+  const bool predict = o.rank_model || o.features_out;
+  if (predict)
     LAUNCH(K_FEAT, -1, k_vertex_features<<<nblocks(F->n), WG, 0, st>>>(F->n, F->rowptr, F->colind, F->vals, F->g,
                                                                       P.dim, vfeat));
+  // features of level lv's segments and (with a model) their start samples,
+  // on stream sst
+  auto features_and_predictions = [&](int lv, hipStream_t sst) -> int {
+    hipStream_t st = sst;
+    const LevelTabs& TV = Y.lv[lv];
+    const int nsv = int(TV.segs.size());
+    const DSeg* segv = tab<DSeg>(ws, TV.o_segs);
+    DLevelDyn dv = dyn_of(ws, Y, lv);
+    float* feats = (o.features_out ? o.features_out : reinterpret_cast<float*>(ws + Y.o_feats)) +
+                   size_t(Y.seg_base[lv]) * MLP_NF;
+    LAUNCH(K_FEAT, lv, k_features<<<unsigned(nsv), 64, 0, st>>>(segv, nsv, tab<DNbr>(ws, TV.o_nbrs), F->g, P.dim, L,
+                                                                lv, o.eps, iar, dv, vfeat, feats));
+    if (o.rank_model) {
+      int32_t* hinit = reinterpret_cast<int32_t*>(ws + Y.o_hinit);
+      const unsigned mblk = unsigned((nsv + WG / MLP_G - 1) / (WG / MLP_G));
+      LAUNCH(K_MLP, lv, k_mlp_rank<<<mblk, WG, 0, st>>>(feats, nsv, o.rank_model, segv, dv, o.rank_margin,
+                                                          o.rank_pad, hinit + Y.seg_base[lv]));
+    }
+    return int(SPALU_OK);
+  };
   for (int l = L; l >= 1; --l) {
     const LevelTabs& T_ = Y.lv[l];
     const int ns = int(T_.segs.size());
@@ -978,18 +1007,16 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     prm.level = l;
     prm.seg_base = int(Y.seg_base[l]);
     prm.h_init = o.h_init;
-    if (o.rank_model || o.features_out) {
-      float* feats = (o.features_out ? o.features_out : reinterpret_cast<float*>(ws + Y.o_feats)) +
-                     size_t(Y.seg_base[l]) * MLP_NF;
-      LAUNCH(K_FEAT, l, k_features<<<unsigned(ns), 64, 0, st>>>(segs, ns, tab<DNbr>(ws, T_.o_nbrs), F->g, P.dim, L,
-                                                                l, o.eps, iar, d, vfeat, feats));
-      if (o.rank_model) {
-        int32_t* hinit = reinterpret_cast<int32_t*>(ws + Y.o_hinit);
-        const unsigned mblk = unsigned((ns + WG / MLP_G - 1) / (WG / MLP_G));
-        LAUNCH(K_MLP, l, k_mlp_rank<<<mblk, WG, 0, st>>>(feats, ns, o.rank_model, segs, d, o.rank_margin, o.rank_pad,
-                                                         hinit + Y.seg_base[l]));
-        prm.h_init = hinit;
+    if (predict) {
+      // the finest level here; the others were done on aux[0] during the
+      // level below
+      if (l == L) {
+        const int rc = features_and_predictions(L, st);
+        if (rc) return rc;
+      } else {
+        HIPCHK(hipStreamWaitEvent(st, F->pre_done, 0));
       }
+      if (o.rank_model) prm.h_init = reinterpret_cast<int32_t*>(ws + Y.o_hinit);
     }
     {
       static const bool lds_ok = [] {
@@ -1060,6 +1087,23 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
             segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, INT32_MAX, big));
       }
     }
+    if (l > 1) {
+      // merge sizes (they need the LU's DOF order) and the next level's
+      // features and predictions on aux[0], beside the coupling scaling
+      HIPCHK(hipEventRecord(F->lu_done, st));
+      hipStream_t st = F->aux[0];
+      HIPCHK(hipStreamWaitEvent(st, F->lu_done, 0));
+      const LevelTabs& U = Y.lv[l - 1];
+      LAUNCH(K_MSIZE, l, k_merge_sizes<<<unsigned(U.segs.size()), 64, 0, st>>>(
+          tab<DSeg>(ws, U.o_segs), int(U.segs.size()), tab<int32_t>(ws, T_.o_cons_ptr),
+          tab<int32_t>(ws, T_.o_cons), segs, iar, d, dyn_of(ws, Y, l - 1)));
+      HIPCHK(hipEventRecord(F->msize_done, st));
+      if (predict) {
+        const int rc = features_and_predictions(l - 1, st);
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(F->pre_done, st));
+      }
+    }
     if (!T_.scale_list.empty()) {
       // one wave per block where the skeletons are small, a block of 256
       // threads otherwise
@@ -1073,9 +1117,7 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     if (l > 1) {
       const LevelTabs& U = Y.lv[l - 1];
       DLevelDyn du = dyn_of(ws, Y, l - 1);
-      LAUNCH(K_MSIZE, l, k_merge_sizes<<<unsigned(U.segs.size()), 64, 0, st>>>(
-          tab<DSeg>(ws, U.o_segs), int(U.segs.size()), tab<int32_t>(ws, T_.o_cons_ptr),
-          tab<int32_t>(ws, T_.o_cons), segs, iar, d, du));
+      HIPCHK(hipStreamWaitEvent(st, F->msize_done, 0));
       // blocks of small segments: one wave each
       if (U.max_cap <= 32)
         LAUNCH(K_MELIM, l, k_merge_elim<T, 64><<<unsigned(U.blks.size()), 64, 0, st>>>(
