@@ -610,14 +610,20 @@ __global__ __launch_bounds__(64) void k_sep_wave(const DSeg* segs, int nseg, con
       double acc[CH];
 #pragma unroll
       for (int j = 0; j < CH; ++j) acc[j] = 0.0;
+      // this lane's row of each scaled block, 8 entries per trip to memory
       for (int e = 0; e < ne; ++e) {
         const int kbe = m_kb[e];
         const T* arow = varena + m_soff[e] + size_t(lane) * kbe;
         const T* xe = X + m_off[e] * CH;
-        for (int u = 0; u < kbe; ++u) {
-          const double av = double(arow[u]);
+        for (int u0 = 0; u0 < kbe; u0 += 8) {
+          T av[8];
 #pragma unroll
-          for (int j = 0; j < CH; ++j) acc[j] = fma(av, double(xe[u * CH + j]), acc[j]);
+          for (int b = 0; b < 8; ++b) av[b] = arow[u0 + b < kbe ? u0 + b : kbe - 1];
+#pragma unroll
+          for (int b = 0; b < 8; ++b)
+            if (u0 + b < kbe)
+#pragma unroll
+              for (int j = 0; j < CH; ++j) acc[j] = fma(double(av[b]), double(xe[(u0 + b) * CH + j]), acc[j]);
         }
       }
       T* dst = W + size_t(dof) * nrhs + j0;
@@ -643,8 +649,12 @@ __device__ inline void gathered_gemm_acc(const T* A, int lda, int i0, int ib, in
   for (int u0 = 0; u0 < K; u0 += GG_TILE) {
     const int kt = K - u0 < GG_TILE ? K - u0 : GG_TILE;
     __syncthreads();
-    for (int t = tid; t < ib * kt; t += WG) sA[t] = double(A[size_t(i0 + t / kt) * lda + u0 + t % kt]);
-    for (int t = tid; t < kt * nc; t += WG) sX[t] = double(W[size_t(idx[u0 + t / nc]) * nrhs + j0 + t % nc]);
+    load_batched<4>(
+        ib * kt, tid, WG, [&](int t) { return A[size_t(i0 + t / kt) * lda + u0 + t % kt]; },
+        [&](int t, T v) { sA[t] = double(v); });
+    load_batched<2>(
+        kt * nc, tid, WG, [&](int t) { return W[size_t(idx[u0 + t / nc]) * nrhs + j0 + t % nc]; },
+        [&](int t, T v) { sX[t] = double(v); });
     __syncthreads();
     int a = 0;
     for (int t = tid; t < ib * nc; t += WG, ++a) {
