@@ -1178,42 +1178,40 @@ __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk,
     const int acc_bytes = (kc * kd * 8 + 15) & ~15;
     const bool staged = lds_bytes > 0 && tk.sep_end > tk.sep_begin &&
                         acc_bytes + (kc + kd) * ksmax * int(sizeof(T)) <= lds_bytes;
-    if constexpr (NT == WG) {
-      if (staged) {
-        double* acc = lds;  // kc x kd, element t touched by thread t % NT only
-        T* sA = reinterpret_cast<T*>(reinterpret_cast<char*>(lds) + acc_bytes);
-        if (tk.src == -2 || !src)
-          for (int t = tid; t < kc * kd; t += NT) acc[t] = tk.src == -2 && t / kd == t % kd ? 1.0 : 0.0;
-        else
-          stage_batched<8>(src, kc * kd, tid, NT, [&](int t, T v) { acc[t] = double(v); });
-        for (int e = tk.sep_begin; e < tk.sep_end; ++e) {
-          const DSepTerm st = terms[e];
-          const int ks = dyn.k[st.s];
-          T* sB = sA + kc * ks;
-          __syncthreads();  // the previous term's factors are no longer read
-          stage_batched<8>(varena + blks[st.blk_cs].soff, kc * ks, tid, NT, [&](int t, T v) { sA[t] = v; });
-          stage_batched<8>(varena + blks[st.blk_sd].soff, ks * kd, tid, NT, [&](int t, T v) { sB[t] = v; });
-          __syncthreads();
-          for (int t = tid; t < kc * kd; t += NT) {
-            const int i = t / kd, j = t - i * kd;
-            const T* ar = sA + i * ks;
-            double s0 = 0.0, s1 = 0.0;
-            int u = 0;
-            for (; u + 1 < ks; u += 2) {
-              s0 += double(ar[u]) * double(sB[u * kd + j]);
-              s1 += double(ar[u + 1]) * double(sB[(u + 1) * kd + j]);
-            }
-            if (u < ks) s0 += double(ar[u]) * double(sB[u * kd + j]);
-            acc[t] -= s0 + s1;
-          }
-        }
+    if (staged) {
+      double* acc = lds;  // kc x kd, element t touched by thread t % NT only
+      T* sA = reinterpret_cast<T*>(reinterpret_cast<char*>(lds) + acc_bytes);
+      if (tk.src == -2 || !src)
+        for (int t = tid; t < kc * kd; t += NT) acc[t] = tk.src == -2 && t / kd == t % kd ? 1.0 : 0.0;
+      else
+        stage_batched<8>(src, kc * kd, tid, NT, [&](int t, T v) { acc[t] = double(v); });
+      for (int e = tk.sep_begin; e < tk.sep_end; ++e) {
+        const DSepTerm st = terms[e];
+        const int ks = dyn.k[st.s];
+        T* sB = sA + kc * ks;
+        __syncthreads();  // the previous term's factors are no longer read
+        stage_batched<8>(varena + blks[st.blk_cs].soff, kc * ks, tid, NT, [&](int t, T v) { sA[t] = v; });
+        stage_batched<8>(varena + blks[st.blk_sd].soff, ks * kd, tid, NT, [&](int t, T v) { sB[t] = v; });
+        __syncthreads();
         for (int t = tid; t < kc * kd; t += NT) {
           const int i = t / kd, j = t - i * kd;
-          out[size_t(oc + i) * nD + od + j] = T(acc[t]);
+          const T* ar = sA + i * ks;
+          double s0 = 0.0, s1 = 0.0;
+          int u = 0;
+          for (; u + 1 < ks; u += 2) {
+            s0 += double(ar[u]) * double(sB[u * kd + j]);
+            s1 += double(ar[u + 1]) * double(sB[(u + 1) * kd + j]);
+          }
+          if (u < ks) s0 += double(ar[u]) * double(sB[u * kd + j]);
+          acc[t] -= s0 + s1;
         }
-        __syncthreads();  // the next task restages
-        continue;
       }
+      for (int t = tid; t < kc * kd; t += NT) {
+        const int i = t / kd, j = t - i * kd;
+        out[size_t(oc + i) * nD + od + j] = T(acc[t]);
+      }
+      __syncthreads();  // the next task restages
+      continue;
     }
     for (int t = tid; t < kc * kd; t += NT) {
       const int i = t / kd, j = t % kd;

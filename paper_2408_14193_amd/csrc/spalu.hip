@@ -1119,10 +1119,14 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       DLevelDyn du = dyn_of(ws, Y, l - 1);
       HIPCHK(hipStreamWaitEvent(st, F->msize_done, 0));
       // blocks of small segments: one wave each
-      if (U.max_cap <= 32)
-        LAUNCH(K_MELIM, l, k_merge_elim<T, 64><<<unsigned(U.blks.size()), 64, 0, st>>>(
+      if (U.max_cap <= 32) {
+        // staged terms with LDS for this level's largest skeletons
+        const int cap = T_.max_cap;
+        const int lb = ((cap * cap * 8 + 15) & ~15) + 2 * cap * cap * int(sizeof(T));
+        LAUNCH(K_MELIM, l, k_merge_elim<T, 64><<<unsigned(U.blks.size()), 64, size_t(lb), st>>>(
             tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
-            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du, 0));
+            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du, lb));
+      }
       else
         LAUNCH(K_MELIM, l, k_merge_elim<T, WG><<<unsigned(U.blks.size()), WG, MELIM_LDS_BYTES, st>>>(
             tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
