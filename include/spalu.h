@@ -27,6 +27,9 @@
  *     per precision and device (at the first spalu_factor), from which
  *     every factorization's workspace is filled; spalu_nd_free releases
  *     it.
+ *   - An ordering handle (spalu_nd_t) caches host and device state of its
+ *     factorizations (tables, staging buffers, captured solve graphs): calls
+ *     that use one handle must not run concurrently from several threads.
  *   - Vertex ids: interior grid node (x, y, z) has id x + nx*(y + ny*z).
  */
 #ifndef SPALU_H

@@ -97,9 +97,12 @@ struct Layout {
   char* dimage = nullptr;
   int dimage_dev = -1;
   double dimage_rho = -1.0;
+  // pinned staging of the read-back of the per-level size arrays
+  mutable char* dyn_pinned = nullptr;
   ~Layout() {
     if (image) (void)hipHostFree(image);
     if (dimage) (void)hipFree(dimage);
+    if (dyn_pinned) (void)hipHostFree(dyn_pinned);
   }
 };
 
@@ -853,12 +856,15 @@ int read_dyn_host(spalu_factor_t* F) {
   const Layout& Y = *F->lay;
   const int L = F->nd->plan.L;
   const size_t lo = Y.lv[1].o_dyn, hi = Y.lv[L].o_dyn + 6 * Y.lv[L].segs.size() * 4;
-  std::vector<char> raw(hi - lo);
-  HIPCHK(hipMemcpy(raw.data(), F->ws + lo, raw.size(), hipMemcpyDeviceToHost));
+  if (!Y.dyn_pinned)
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&Y.dyn_pinned), std::max<size_t>(hi - lo, 1), hipHostMallocDefault));
+  const char* raw = Y.dyn_pinned;
+  HIPCHK(hipMemcpyAsync(Y.dyn_pinned, F->ws + lo, hi - lo, hipMemcpyDeviceToHost, F->stream));
+  HIPCHK(hipStreamSynchronize(F->stream));
   auto dh = std::make_shared<DynHost>(size_t(L) + 1);
   for (int l = 1; l <= L; ++l) {
     (*dh)[l].resize(6 * Y.lv[l].segs.size());
-    std::memcpy((*dh)[l].data(), raw.data() + (Y.lv[l].o_dyn - lo), (*dh)[l].size() * 4);
+    std::memcpy((*dh)[l].data(), raw + (Y.lv[l].o_dyn - lo), (*dh)[l].size() * 4);
   }
   F->dyn_host = dh;
   // lane groups of P = 8..64 lanes for levels whose segments and neighbour
