@@ -44,6 +44,9 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct LevelTabs {
   std::vector<DSeg> segs;
   std::vector<DNbr> nbrs;
+  // host adjacency as flat arrays (segment c's neighbours are
+  // adj_d[adj_ptr[c] .. adj_ptr[c+1])), built at the first read-back
+  mutable std::vector<int32_t> adj_ptr, adj_d;
   std::vector<DBlk> blks;
   std::vector<int32_t> scale_list;
   std::vector<int32_t> cons_ptr, cons;  // merge into level l-1 (l >= 2)
@@ -877,11 +880,22 @@ int read_dyn_host(spalu_factor_t* F) {
     const size_t ns = T.segs.size();
     const int32_t* nv = (*dh)[l].data();
     const int32_t* kv = nv + ns;
+    if (T.adj_ptr.size() != ns + 1) {
+      T.adj_ptr.resize(ns + 1);
+      T.adj_d.clear();
+      for (size_t c = 0; c < ns; ++c) {
+        T.adj_ptr[c] = int32_t(T.adj_d.size());
+        for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) T.adj_d.push_back(T.nbrs[e].d);
+      }
+      T.adj_ptr[ns] = int32_t(T.adj_d.size());
+    }
+    const int32_t* ap = T.adj_ptr.data();
+    const int32_t* ad = T.adj_d.data();
     int mx = T.max_nbrs, rows = 1;
     for (size_t c = 0; c < ns; ++c) {
       mx = std::max(mx, int(nv[c]));
       int r = 0;
-      for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) r += kv[T.nbrs[e].d];
+      for (int e = ap[c]; e < ap[c + 1]; ++e) r += kv[ad[e]];
       rows = std::max(rows, r);
     }
     const int P = mx <= 8 ? 8 : mx <= 16 ? 16 : mx <= 32 ? 32 : mx <= 64 ? 64 : 0;
