@@ -119,11 +119,31 @@ struct SweepGraph {
   hipGraphExec_t exec;
 };
 
+// Side streams (default priority) and events of a factorization, created
+// once per ordering handle and shared by its factorizations (which do not
+// run concurrently): a level's ID size tiers run concurrently, forked after
+// the level's setup and joined before its segment LU; after the segment LU,
+// the merge sizes and the next level's features and predictions run on
+// aux[0] beside the coupling scaling.
+struct FactorStreams {
+  hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t lu_done = nullptr, msize_done = nullptr, pre_done = nullptr;
+  ~FactorStreams() {
+    for (hipStream_t s : aux)
+      if (s) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : {fork, join[0], join[1], join[2], lu_done, msize_done, pre_done})
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 struct spalu_nd_s {
   Plan plan;
   std::shared_ptr<Layout> layout[2];
   std::vector<SweepGraph> graphs;  // most recent last
   hipStream_t capture_stream = nullptr;
+  FactorStreams fs;
   ~spalu_nd_s() {
     for (auto& gph : graphs) (void)hipGraphExecDestroy(gph.exec);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
@@ -148,24 +168,8 @@ struct spalu_factor_s {
   // per segment of the lane-group kernels (0: 256-thread kernels) and the
   // largest stacked neighbour skeleton of an owner
   std::vector<int> solve_P, solve_rows;
-  // side streams of the factorization (default priority): the size tiers of
-  // a level's ID launches run concurrently, forked after the level's setup
-  // and joined before its segment LU
-  hipStream_t aux[3] = {nullptr, nullptr, nullptr};
-  hipEvent_t fork = nullptr;
-  hipEvent_t join[3] = {nullptr, nullptr, nullptr};
-  // after a level's segment LU, the merge sizes and the next level's
-  // features and predictions run on aux[0] beside the coupling scaling
-  hipEvent_t lu_done = nullptr, msize_done = nullptr, pre_done = nullptr;
-  ~spalu_factor_s() {
-    for (hipStream_t s : aux)
-      if (s) (void)hipStreamDestroy(s);
-    if (fork) (void)hipEventDestroy(fork);
-    for (hipEvent_t e : join)
-      if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {lu_done, msize_done, pre_done})
-      if (e) (void)hipEventDestroy(e);
-  }
+  // side streams and events (owned by the ordering handle)
+  FactorStreams* fs = nullptr;
 };
 
 namespace {
@@ -934,16 +938,18 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
   const Plan& P = F->nd->plan;
   char* ws = F->ws;
   hipStream_t st = F->stream;
-  if (!F->fork) {
-    HIPCHK(hipEventCreateWithFlags(&F->fork, hipEventDisableTiming));
+  FactorStreams& FS = const_cast<spalu_nd_t*>(F->nd)->fs;
+  if (!FS.fork) {
+    HIPCHK(hipEventCreateWithFlags(&FS.fork, hipEventDisableTiming));
     for (int i = 0; i < 3; ++i) {
-      HIPCHK(hipStreamCreateWithFlags(&F->aux[i], hipStreamNonBlocking));
-      HIPCHK(hipEventCreateWithFlags(&F->join[i], hipEventDisableTiming));
+      HIPCHK(hipStreamCreateWithFlags(&FS.aux[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&FS.join[i], hipEventDisableTiming));
     }
-    HIPCHK(hipEventCreateWithFlags(&F->lu_done, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&F->msize_done, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&F->pre_done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&FS.lu_done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&FS.msize_done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&FS.pre_done, hipEventDisableTiming));
   }
+  F->fs = &FS;
   int32_t* iar = reinterpret_cast<int32_t*>(ws + Y.o_iarena);
   T* var = reinterpret_cast<T*>(ws + Y.o_varena);
   double* scr = reinterpret_cast<double*>(ws + Y.o_scratch);
@@ -1034,7 +1040,7 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
         const int rc = features_and_predictions(L, st);
         if (rc) return rc;
       } else {
-        HIPCHK(hipStreamWaitEvent(st, F->pre_done, 0));
+        HIPCHK(hipStreamWaitEvent(st, F->fs->pre_done, 0));
       }
       if (o.rank_model) prm.h_init = reinterpret_cast<int32_t*>(ws + Y.o_hinit);
     }
@@ -1056,26 +1062,26 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       // side streams: every segment belongs to exactly one tier
       const bool side[3] = {T_.id_b, T_.id_b2, T_.id_c || T_.id_old};
       if (side[0] || side[1] || side[2]) {
-        HIPCHK(hipEventRecord(F->fork, st));
+        HIPCHK(hipEventRecord(F->fs->fork, st));
         for (int i = 0; i < 3; ++i)
-          if (side[i]) HIPCHK(hipStreamWaitEvent(F->aux[i], F->fork, 0));
+          if (side[i]) HIPCHK(hipStreamWaitEvent(F->fs->aux[i], F->fs->fork, 0));
       }
       LAUNCH(K_ID, l, k_seg_id_cols<T, 1, 1, false, 1><<<unsigned(ns), 64, size_t(tz.budget_a), st>>>(
           segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       if (side[0]) {
-        hipStream_t st = F->aux[0];
+        hipStream_t st = F->fs->aux[0];
         LAUNCH(K_ID_B, l, k_seg_id_cols<T, ID_B_WAVES, 2, false, 2><<<unsigned(ns), 64 * ID_B_WAVES,
                                                                       size_t(tz.budget_b), st>>>(
             segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       }
       if (side[1]) {
-        hipStream_t st = F->aux[1];
+        hipStream_t st = F->fs->aux[1];
         LAUNCH(K_ID_B2, l, k_seg_id_cols<T, ID_B2_WAVES, 2, false, 3><<<unsigned(ns), 64 * ID_B2_WAVES,
                                                                         size_t(tz.budget_b2), st>>>(
             segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       }
       if (side[2]) {
-        hipStream_t st = F->aux[2];
+        hipStream_t st = F->fs->aux[2];
         if (T_.id_c)
           LAUNCH(K_ID_C, l, k_seg_id_cols<T, 8, 2, true, 4><<<unsigned(ns), 512,
                                                                  idc_lds_bytes(8, 2, 128, 0, tz.st, false), st>>>(
@@ -1086,8 +1092,8 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       }
       for (int i = 0; i < 3; ++i)
         if (side[i]) {
-          HIPCHK(hipEventRecord(F->join[i], F->aux[i]));
-          HIPCHK(hipStreamWaitEvent(st, F->join[i], 0));
+          HIPCHK(hipEventRecord(F->fs->join[i], F->fs->aux[i]));
+          HIPCHK(hipStreamWaitEvent(st, F->fs->join[i], 0));
         }
     }
     {
@@ -1110,18 +1116,18 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     if (l > 1) {
       // merge sizes (they need the LU's DOF order) and the next level's
       // features and predictions on aux[0], beside the coupling scaling
-      HIPCHK(hipEventRecord(F->lu_done, st));
-      hipStream_t st = F->aux[0];
-      HIPCHK(hipStreamWaitEvent(st, F->lu_done, 0));
+      HIPCHK(hipEventRecord(F->fs->lu_done, st));
+      hipStream_t st = F->fs->aux[0];
+      HIPCHK(hipStreamWaitEvent(st, F->fs->lu_done, 0));
       const LevelTabs& U = Y.lv[l - 1];
       LAUNCH(K_MSIZE, l, k_merge_sizes<<<unsigned(U.segs.size()), 64, 0, st>>>(
           tab<DSeg>(ws, U.o_segs), int(U.segs.size()), tab<int32_t>(ws, T_.o_cons_ptr),
           tab<int32_t>(ws, T_.o_cons), segs, iar, d, dyn_of(ws, Y, l - 1)));
-      HIPCHK(hipEventRecord(F->msize_done, st));
+      HIPCHK(hipEventRecord(F->fs->msize_done, st));
       if (predict) {
         const int rc = features_and_predictions(l - 1, st);
         if (rc) return rc;
-        HIPCHK(hipEventRecord(F->pre_done, st));
+        HIPCHK(hipEventRecord(F->fs->pre_done, st));
       }
     }
     if (!T_.scale_list.empty()) {
@@ -1137,7 +1143,7 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     if (l > 1) {
       const LevelTabs& U = Y.lv[l - 1];
       DLevelDyn du = dyn_of(ws, Y, l - 1);
-      HIPCHK(hipStreamWaitEvent(st, F->msize_done, 0));
+      HIPCHK(hipStreamWaitEvent(st, F->fs->msize_done, 0));
       // blocks of small segments: one wave each
       if (U.max_cap <= 32) {
         // staged terms with LDS for this level's largest skeletons
