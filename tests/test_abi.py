@@ -26,6 +26,18 @@ def test_exports_every_declared_symbol():
         assert hasattr(S._lib, name)
 
 
+def test_profile_only_names():
+    """Host-only calls: restricting the event timing to one kernel step
+    accepts the step names the profile reports and rejects others."""
+    S = _lib()
+    S.profile(True)
+    for name in ("seg_id_c", "solve_sweep_graph", "krylov", None, ""):
+        S.profile_only(name)
+    with pytest.raises(RuntimeError):
+        S.profile_only("no_such_step")
+    S.profile(False)
+
+
 @pytest.mark.parametrize("dims,L", [((7, 7), 3), ((7, 7), 1), ((15, 15), 0), ((63, 63), 0),
                                     ((31, 15), 0), ((47, 33), 0), ((255, 255), 0),
                                     ((15, 15, 15), 0), ((31, 31, 31), 0), ((15, 31, 15), 0)])
