@@ -781,7 +781,8 @@ __global__ __launch_bounds__(WG) void k_residual(int64_t n, int nrhs, const int6
   }
 }
 
-__global__ __launch_bounds__(WG) void k_reduce_cols(const double* part, int nblk, int nrhs, double* out) {
+// out[j] = sum of the nblk partial sums part[j * nblk + b] (one block per j).
+__global__ __launch_bounds__(WG) void k_reduce_cols(const double* part, int nblk, double* out) {
   __shared__ double red[NWAVE];
   const int j = blockIdx.x;
   double s = 0.0;
@@ -952,8 +953,7 @@ __global__ void k_kstart(int nrhs, int m, const double* nr, double* ks) {
 }
 
 // Vi[:, j] = Wc[:, j] times the column's reciprocal norm.
-__global__ __launch_bounds__(WG) void k_kscale(int64_t n, int nrhs, int m, const double* ks, const double* Wc,
-                                               double* Vi) {
+__global__ __launch_bounds__(WG) void k_kscale(int64_t n, int m, const double* ks, const double* Wc, double* Vi) {
   const int j = blockIdx.y;
   const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
   if (v >= n) return;

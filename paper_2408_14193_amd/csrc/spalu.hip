@@ -1401,9 +1401,9 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
   while (true) {
     LAUNCH(K_RESID, 0, k_residual<<<s.rblk, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Bsrc, ldbres, X,
                                                           ldx, R, pr, pb, s.rparts));
-    LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pr, s.rparts, nrhs, nr));
+    LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pr, s.rparts, nr));
     if (bnorm.empty()) {
-      LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pb, s.rparts, nrhs, nb));
+      LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pb, s.rparts, nb));
       HIPCHK(hipMemcpyAsync(hb.data(), nb, size_t(nrhs) * 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipMemcpyAsync(hr.data(), nr, size_t(nrhs) * 8, hipMemcpyDeviceToHost, st));
@@ -1448,7 +1448,7 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     const dim3 vgrid(s.rblk, unsigned(nrhs));
     const unsigned cblk = unsigned((nrhs + 63) / 64);
     LAUNCH(K_KRYLOV, -1, k_kstart<<<cblk, 64, 0, st>>>(nrhs, m, nr, ks));
-    LAUNCH(K_KRYLOV, 0, k_kscale<<<vgrid, WG, 0, st>>>(F->n, nrhs, m, ks, R, V));
+    LAUNCH(K_KRYLOV, 0, k_kscale<<<vgrid, WG, 0, st>>>(F->n, m, ks, R, V));
     int kdone = 0;
     std::vector<double> he(nrhs);
     for (int c = 0; c < m && it < so.max_iter; ++c) {
@@ -1464,9 +1464,9 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
       // the dots of the result; then V_{c+1} = (w - V h2) / H[c+1][c]
       const dim3 kgrid(s.kblk, unsigned(nrhs));
       LAUNCH(K_KRYLOV, c + 1, k_kdots<<<kgrid, WG, 0, st>>>(F->n, nrhs, V, c + 1, R, kp, s.kparts));
-      LAUNCH(K_KRYLOV, -1, k_reduce_cols<<<unsigned((c + 2) * nrhs), WG, 0, st>>>(kp, s.kparts, (c + 2) * nrhs, h1));
+      LAUNCH(K_KRYLOV, -1, k_reduce_cols<<<unsigned((c + 2) * nrhs), WG, 0, st>>>(kp, s.kparts, h1));
       LAUNCH(K_KRYLOV, c + 1, k_korth_dots<<<kgrid, WG, 0, st>>>(F->n, nrhs, V, c + 1, h1, R, kp, s.kparts));
-      LAUNCH(K_KRYLOV, -1, k_reduce_cols<<<unsigned((c + 2) * nrhs), WG, 0, st>>>(kp, s.kparts, (c + 2) * nrhs, h2));
+      LAUNCH(K_KRYLOV, -1, k_reduce_cols<<<unsigned((c + 2) * nrhs), WG, 0, st>>>(kp, s.kparts, h2));
       LAUNCH(K_KRYLOV, -1, k_karnoldi<<<cblk, 64, 0, st>>>(nrhs, m, c, h1, h2, ks, est));
       LAUNCH(K_KRYLOV, c + 1, k_korth_scale<<<kgrid, WG, 0, st>>>(F->n, nrhs, m, V, c + 1, h2, ks, R,
                                                                    V + size_t(c + 1) * nn));
