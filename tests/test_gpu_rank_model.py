@@ -133,3 +133,65 @@ def test_trained_predictor_saves_sampling_passes(S):
     Xp, ip = Fp.solve(B, tol=1e-8, max_iter=40)
     assert il["converged"] and ip["converged"]
     assert rel_res(P, Xl.cpu().numpy()).max() <= 1e-8
+
+
+def _bf16(x):
+    """Round float32 values to the nearest bfloat16 (ties to even)."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def _fma32(a, b, c):
+    # float32 fused multiply-add: the product is exact in float64
+    return (np.float64(a) * np.float64(b) + np.float64(c)).astype(np.float32)
+
+
+def test_inference_start_samples_match_bf16_definition(S):
+    """The device inference (weights and activations rounded to bfloat16,
+    float32 sums in the plain loop order) against the same arithmetic
+    written out here on the features the device computed: every segment's
+    first sample count ceil(margin n y) + pad, up to a rounding tie of the
+    sigmoid at a ceiling boundary."""
+    import torch
+    p, _, _ = _data(seed=3)
+    P = make_config(1, side=127, nrhs=1)
+    nd = S.ND(P.dims)
+    rp, ci, v, _ = to_device(P)
+    feats = torch.zeros(nd.nsegments * M.NF, dtype=torch.float32, device="cuda")
+    F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=S.FP32, rank_model=torch.from_numpy(p).cuda(),
+                 features_out=feats)
+    nb, rk, hh, ps = F.ranks()
+    f = feats.cpu().numpy().reshape(-1, M.NF)
+    q = M.unpack(p)
+    sel = np.nonzero(ps == 1)[0]
+    assert sel.size > 100
+    W1, W2 = _bf16(q["W1"]), _bf16(q["W2"])
+    b1, b2, w3, b3 = _bf16(q["b1"]), _bf16(q["b2"]), _bf16(q["w3"]), _bf16(np.float32(q["b3"]))
+    diff, uncapped = [], []
+    for s in sel:
+        x = _bf16((f[s] - q["mu"]) / q["sd"])
+        a1 = np.empty(M.H, np.float32)
+        for o in range(M.H):
+            acc = b1[o]
+            for k in range(M.NF):
+                acc = _fma32(W1[o, k], x[k], acc)
+            a1[o] = _bf16(max(acc, np.float32(0)))
+        z = b3
+        for o in range(M.H):
+            acc = b2[o]
+            for k in range(M.H):
+                acc = _fma32(W2[o, k], a1[k], acc)
+            z = _fma32(w3[o], _bf16(max(acc, np.float32(0))), z)
+        y = np.float32(1) / (np.float32(1) + np.exp(-z, dtype=np.float32))
+        h = int(np.ceil(np.float32(1.0) * np.float32(nb[s]) * y)) + 5
+        # the ID reports min(h, far rows); the far-row count follows from the
+        # features: nV = 2^f3 - 1 coupled DOFs, 2 nV rows, a fraction f4 near
+        nv = int(round(2.0 ** float(f[s, 3]) - 1.0))
+        n_far = int(round(2 * nv * (1.0 - float(f[s, 4]))))
+        diff.append(int(hh[s]) - min(h, n_far))
+        uncapped.append(h < n_far)
+    diff = np.array(diff)
+    assert np.mean(uncapped) >= 0.5  # most counts come from the prediction itself
+    assert np.abs(diff).max() <= 1
+    assert (diff == 0).mean() >= 0.99
