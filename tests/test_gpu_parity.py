@@ -184,6 +184,18 @@ def test_many_rhs(S, nrhs):
     assert info["converged"] and rel_res(P, X).max() <= 1e-10
 
 
+@pytest.mark.parametrize("nrhs", [40, 33])
+def test_many_rhs_fgmres_fp32(S, nrhs):
+    """FP32 storage with flexible GMRES refinement on a right-hand-side
+    count that leaves partial column tiles and chunks (32 and 16 wide)."""
+    print("case fgmres fp32 nrhs=%d" % nrhs, flush=True)
+    P = make_config(1, side=63, nrhs=nrhs)
+    nd, F, B = gpu_factor(S, P, eps=1e-4, precision=S.FP32)
+    X, info = F.solve(B, tol=1e-10, max_iter=40, restart=8)
+    X = X.cpu().numpy()
+    assert info["converged"] and rel_res(P, X).max() <= 1e-10
+
+
 def test_in_place_direct_solve_and_determinism(S):
     import torch
     P = make_config(0, nrhs=2)
