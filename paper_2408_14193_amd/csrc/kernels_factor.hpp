@@ -405,8 +405,10 @@ __global__ __launch_bounds__(64) void k_leaf_factor_wave(const DLeaf* leaves, in
 #pragma unroll
     for (int s = 0; s < WC; ++s) r[s] *= sc;
   }
-  // the inverse, transposed (entry (i, q) at q * ni + i), and X to LDS
+  // the inverse, transposed (entry (i, q) at q * ni + i), and X to LDS and,
+  // transposed the same way, to memory for the backward solve
   T* Ainv = varena + L.lu_off;
+  T* Xo = varena + L.x_off;
 #pragma unroll
   for (int s = 0; s < WC; ++s) {
     const int k = s - (WC - ni);
@@ -414,7 +416,10 @@ __global__ __launch_bounds__(64) void k_leaf_factor_wave(const DLeaf* leaves, in
       const int q = pord[k];
       if (lane < ni) Ainv[size_t(q) * ni + my_step] = T(r[s]);
     } else if (s < nb) {
-      if (lane < ni) X[my_step * nb + s] = r[s];
+      if (lane < ni) {
+        X[my_step * nb + s] = r[s];
+        Xo[size_t(s) * ni + my_step] = T(r[s]);
+      }
     }
   }
   wave_sync();

@@ -374,6 +374,65 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
   }
 }
 
+// Backward leaf solve from the forward result: x_I = y_I - X x_B with
+// X = A_II^{-1} A_IB (stored transposed by the one-wave leaf factor) and x_B
+// the boundary values; one wave per leaf, lane i = interior vertex i.  The
+// boundary values of a chunk of right-hand sides are staged in LDS, X is read
+// in batches of 16 loads.
+__host__ __device__ inline int leaf_bwd_x_lds_bytes(int nb) { return 8 * LEAF_SOLVE_CHUNK * (nb > 0 ? nb : 1); }
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_leaf_solve_bwd_x(const DLeaf* leaves, int nleaf, GridGeom g,
+                                                         const int32_t* iarena, const T* varena, T* W,
+                                                         const T* Z, int nrhs) {
+  extern __shared__ double lds[];
+  constexpr int CH = LEAF_SOLVE_CHUNK;
+  const int lf = blockIdx.x;
+  if (lf >= nleaf) return;
+  const DLeaf L = leaves[lf];
+  const int ni = L.ni, nb = L.nb, lane = threadIdx.x;
+  if (ni == 0) return;
+  const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1;
+  const bool act = lane < ni;
+  const int ix = lane % w0, iy = (lane / w0) % w1, iz = lane / (w0 * w1);
+  const int u = act ? (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz)) : 0;
+  const int32_t* bverts = iarena + L.ioff;
+  const T* Xt = varena + L.x_off + (act ? lane : 0);  // column lane of X^T: X[lane][b] at b * ni
+  double* XB = lds;                                   // nb x CH boundary values
+  for (int j0 = 0; j0 < nrhs; j0 += CH) {
+    const int nc = nrhs - j0 < CH ? nrhs - j0 : CH;
+    double y[CH];
+    if (act) load_chunk(Z + size_t(u) * nrhs + j0, nc, y);
+    for (int b = lane; b < nb; b += 64) {
+      double xb[CH];
+      load_chunk(W + size_t(bverts[b]) * nrhs + j0, nc, xb);
+#pragma unroll
+      for (int j = 0; j < CH; ++j) XB[b * CH + j] = xb[j];
+    }
+    wave_sync();
+    if (act) {
+      for (int b0 = 0; b0 < nb; b0 += 16) {
+        T xv[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) xv[t] = Xt[size_t(b0 + t < nb ? b0 + t : nb - 1) * ni];
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+          if (b0 + t < nb) {
+            const double a = double(xv[t]);
+            const double* xb = XB + (b0 + t) * CH;
+#pragma unroll
+            for (int j = 0; j < CH; ++j) y[j] = fma(-a, xb[j], y[j]);
+          }
+      }
+      T* out = W + size_t(u) * nrhs + j0;
+#pragma unroll
+      for (int j = 0; j < CH; ++j)
+        if (j < nc) out[j] = T(y[j]);
+    }
+    wave_sync();
+  }
+}
+
 // Groups of P lanes (P = 8, 16, 32 or 64) per segment, 64 / P segments per
 // wave, for levels whose segments hold at most P DOFs: lane i of a group
 // keeps DOF i's chunk of 16 right-hand sides in registers, and rows are

@@ -70,6 +70,7 @@ struct DLeaf {
   int64_t ioff;      // int arena: bverts[nb], piv[ni]
   int64_t lu_off;    // value arena: ni*ni
   int64_t s_off;     // value arena: nb*nb (Schur contribution)
+  int64_t x_off;     // value arena: ni*nb, A_II^{-1} A_IB transposed (one-wave leaf factor)
 };
 
 // Level-L block assembly: contribution of a leaf to block (c, d).

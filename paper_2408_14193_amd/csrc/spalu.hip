@@ -82,6 +82,7 @@ struct Layout {
   int leaf_wc = 0;                 // register slots of the one-wave leaf kernels (0: block kernels)
   int leaf_wave_lds = 0;           // their dynamic LDS bytes (factor)
   int leaf_ni_max = 0;
+  int leaf_nb_max = 0;
   size_t o_status = 0;
   size_t o_feats = 0, o_hinit = 0;  // rank predictor: features, start samples
   size_t o_vfeat = 0;               // rank predictor: per-vertex feature parts (3 doubles)
@@ -436,6 +437,8 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
     var += size_t(D.ni) * D.ni;
     D.s_off = int64_t(var);
     var += size_t(nb) * nb;
+    D.x_off = int64_t(var);
+    var += size_t(D.ni) * nb;
     leaf_need = std::max(leaf_need, size_t(leaf_lds_need(D.ni, nb)));
   }
   // one wave per leaf when every leaf fits its register row
@@ -450,6 +453,7 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
       if (w == 0) all = false;
       wc = std::max(wc, w);
       Y.leaf_ni_max = std::max(Y.leaf_ni_max, int(D.ni));
+      Y.leaf_nb_max = std::max(Y.leaf_nb_max, int(D.nb));
     }
     if (all) {
       Y.leaf_wc = wc;
@@ -746,13 +750,22 @@ void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, 
       break;
     }
     case K_LSOLVE_F:
-    case K_LSOLVE_B:
+    case K_LSOLVE_B: {
+      // the backward pass from the stored A_II^{-1} A_IB when the one-wave
+      // leaf factor ran and the leaves fit a wave
+      const bool from_x = kid == K_LSOLVE_B && Y.leaf_wc != 0 && Y.leaf_ni_max <= LEAF_WAVE_MAX_NI;
       for (auto& L : Y.leaves) {
         const double ni = L.ni, nb = L.nb;
-        by += ni * ni * vs + 2.0 * ni * nrhs * vs + (kid == K_LSOLVE_B ? nb * nrhs * vs + ni * nnzrow * 12.0 : 0.0);
-        fl += 2.0 * ni * ni * nrhs;
+        if (from_x) {
+          by += ni * nb * vs + 2.0 * ni * nrhs * vs + nb * nrhs * vs;
+          fl += 2.0 * ni * nb * nrhs;
+        } else {
+          by += ni * ni * vs + 2.0 * ni * nrhs * vs + (kid == K_LSOLVE_B ? nb * nrhs * vs + ni * nnzrow * 12.0 : 0.0);
+          fl += 2.0 * ni * ni * nrhs;
+        }
       }
       break;
+    }
     case K_SEPLEAF: {
       const double nsep = Y.nsep_verts;
       by = nsep * (nnzrow * 12.0 + 8.0 + 3.0 * nrhs * vs);
@@ -1304,7 +1317,12 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
       LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
     }
   }
-  if (wave_leaf) {
+  if (wave_leaf && Y.leaf_wc != 0) {
+    // x_I = y_I - (A_II^{-1} A_IB) x_B with y_I from the forward pass
+    LAUNCH(K_LSOLVE_B, 0, k_leaf_solve_bwd_x<T><<<unsigned(Y.leaves.size()), 64,
+                                                  size_t(leaf_bwd_x_lds_bytes(Y.leaf_nb_max)), st>>>(
+        leaves, int(Y.leaves.size()), F->g, iar, var, W, Z, nrhs));
+  } else if (wave_leaf) {
     LAUNCH(K_LSOLVE_B, 0, k_leaf_solve_wave<T, true><<<unsigned(Y.leaves.size()), 64, lsl, st>>>(
         leaves, int(Y.leaves.size()), F->g, F->rowptr, F->colind, F->vals, var, B0, W, Z, nrhs));
   } else {
