@@ -699,7 +699,9 @@ __global__ __launch_bounds__(NT) void k_seg_lu(const DSeg* segs, int nseg, const
 // rows) l, l + 64, ...: the transform and the two-stage LU of k_seg_lu with
 // wave-level synchronisation only, then the packed inverses formed in place.
 // LDS: W (n x n, row-major), then T (k x nr), which first holds the gather
-// map.  Segments with nmin < n <= nmax take part.
+// map.  Segments with nmin < n <= nmax take part.  The factorization launches
+// it with one column per lane for segments of up to 32 DOFs; wider ones go to
+// the 256-thread k_seg_lu, which is faster there.
 __host__ __device__ inline int seglu_wave_lds_doubles(int nw) { return nw * nw + (nw * nw + 3) / 4 + 1; }
 
 template <typename T, int CPL>
