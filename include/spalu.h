@@ -149,7 +149,7 @@ typedef struct {
 } spalu_factor_info;
 
 /* Default options (eps 1e-6, FP64, seed 1234, rho 0.5, h0 8, 5 probes,
- * tau 10, no rank predictor, margin 1.0, pad 5). */
+ * tau 1, no rank predictor, margin 1.0, pad 5). */
 void spalu_factor_opts_default(spalu_factor_opts* o);
 
 /* Bytes of device workspace that spalu_factor needs for this ND and

@@ -110,11 +110,6 @@ def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return p, m, v
 
 
-def h_from_prediction(n, yhat, margin=1.1, p=5):
-    """Start sample count: ceil(margin * n * yhat) + p."""
-    return int(math.ceil(margin * n * float(yhat))) + p
-
-
 def segment_features(nd, A, lev, c, cur, eps):
     """The 12 features of segment c of level lev given the current DOF lists
     ``cur`` (segment -> vertex ids) of that level (see the module docstring)."""

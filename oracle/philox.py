@@ -62,6 +62,17 @@ def philox4x32_10_np(c0, c1, c2, c3, k0, k1):
     return c0, c1, c2, c3
 
 
+def uniform53(hi, lo):
+    """The uniform number in (0, 1] of two 32-bit words: the top 53 bits of
+    hi:lo scaled by 2^-53, shifted by half a step (2^-54) so that 0 is never
+    reached and the logarithm of Box-Muller stays finite (the largest word
+    rounds to exactly 1, which gives a radius of 0)."""
+    hi = np.asarray(hi, dtype=np.uint64)
+    lo = np.asarray(lo, dtype=np.uint64)
+    w = ((hi << np.uint64(32)) | lo) >> np.uint64(11)
+    return w.astype(np.float64) * 2.0 ** -53 + 2.0 ** -54
+
+
 def gaussian(seed, level, stream, rows, verts, segment, halves):
     """Matrix of normals g[i, j] for row indices ``rows`` (length h) and
     columns given by (verts[j], halves[j]) of one segment."""
@@ -72,11 +83,8 @@ def gaussian(seed, level, stream, rows, verts, segment, halves):
     _, H = np.meshgrid(rows, halves, indexing="ij")
     x0, x1, x2, x3 = philox4x32_10_np(R >> np.uint64(1), V, np.uint64(segment), H,
                                       np.uint64(seed), np.uint64(2 * level + stream))
-    two53 = 2.0 ** -53
-    u1 = ((x1 << np.uint64(32)) | x0) >> np.uint64(11)
-    u2 = ((x3 << np.uint64(32)) | x2) >> np.uint64(11)
-    u1 = u1.astype(np.float64) * two53 + 2.0 ** -54
-    u2 = u2.astype(np.float64) * two53 + 2.0 ** -54
+    u1 = uniform53(x1, x0)
+    u2 = uniform53(x3, x2)
     rad = np.sqrt(-2.0 * np.log(u1))
     ang = 2.0 * math.pi * u2
     even = (R & np.uint64(1)) == 0

@@ -27,8 +27,15 @@ Readings of points the paper leaves open (each is a documented choice):
   * the rank test is relative: stop at the first |R_jj| <= eps |R_11|;
   * samples: h starts at h0 = 8 (or a predicted value), doubles while an
     a-posteriori test with 5 Gaussian probes of the far rows fails
-    (max_i ||w_i^T (B_F P_r - B_F P_s T)|| > tau * eps * |R_11|, tau = 10),
-    and once h >= |F| the exact far rows are used;
+    (max_i ||w_i^T (B_F P_r - B_F P_s T)|| > tau * eps * |R_11|, tau = 1:
+    the probes must show the far-field error under the same threshold the
+    CPQR truncation applies to every column; by the bound of Halko,
+    Martinsson and Tropp (2011, Section 4.3) the accepted error is then at
+    most 10 sqrt(2/pi) eps |R_11| with probability 1 - 10^-probes), and
+    once h >= |F| the exact far rows are used;
+  * a rank hint (learned form) gives the first h; a negative hint keeps the
+    segment whole (k = n, no ID): skipping compression is exact, it only
+    gives up the reduction in size;
   * merged segments list their constituents' surviving DOFs one after
     another, constituents ordered by smallest original vertex id (ascending
     vertex ids along 2D separators), skeletons in pivot order.
@@ -54,8 +61,10 @@ class Opts:
     rho: float = 0.5
     h0: int = 8
     probes: int = 5
-    tau: float = 10.0
-    rank_hint: object = None   # callable (level, seg, info) -> initial h, or None
+    tau: float = 1.0
+    rank_hint: object = None   # callable (level, seg, info) -> initial h (< 0: keep whole), or None
+    no_id: frozenset = frozenset()   # (level, segment) pairs kept whole (locality checks)
+    trace: object = None       # callable (level, dict) receiving each level's blocks (checks)
 
 
 @dataclasses.dataclass
@@ -112,14 +121,14 @@ def _dense(A, rows, cols):
     return A[rows][:, cols].toarray()
 
 
-def segment_id(nd, lev, c, blocks, cur, opts, sym):
-    """Hybrid-sampled CPQR ID of one segment (Sections 4.1-4.2); returns
-    (k, perm, T, h, passes, margin) or None when the segment has no coupling
-    rows; margin is the closest of its rank and check decisions to the
-    threshold (relative)."""
+def coupling_rows(nd, lev, c, blocks, cur, opts):
+    """Rows of the stacked coupling matrix [A_{n,c}; A_{c,n}^T] of segment c
+    (eq. (4.12)), split into near rows B_N and far rows B_F (Section 4.2.3,
+    hybrid sampling); also the vertex id and half (0: a row of A_{n,c}, 1: a
+    row of A_{c,n}^T) of every far row, which key its Gaussian entries.
+    Returns None when the segment has no coupling rows."""
     lvl = nd.levels[lev]
     seg = lvl.segs[c]
-    n = len(cur[c])
     nbrs = [d for (a, d) in lvl.pairs if a == c and d != c]
     rows, verts, halves = [], [], []
     for d in nbrs:
@@ -129,20 +138,27 @@ def segment_id(nd, lev, c, blocks, cur, opts, sym):
         verts.append(cur[d]); halves.append(np.zeros(len(cur[d]), dtype=np.int64))
         rows.append(blocks[(c, d)].T)
         verts.append(cur[d]); halves.append(np.ones(len(cur[d]), dtype=np.int64))
-    if not rows or n == 0:
+    if not rows or len(cur[c]) == 0:
         return None
     Bm = np.vstack(rows)
     verts = np.concatenate(verts)
     halves = np.concatenate(halves)
     lo, hi = np.array(seg.bbox_lo), np.array(seg.bbox_hi)
     span = int((hi - lo + 1).max())
-    thr = max(1, int(math.ceil(opts.rho * span)))
+    reach = opts.rho * span
+    thr = max(1, int(math.ceil(reach))) if math.isfinite(reach) else math.inf
     near = _cheb_to_box(_coords(nd, verts), lo, hi) <= thr
-    BN, BF = Bm[near], Bm[~near]
-    vf, hf = verts[~near], halves[~near]
-    h = opts.h0
-    if opts.rank_hint is not None:
-        h = int(opts.rank_hint(lev, c, dict(n=n, nnear=int(near.sum()), nfar=len(BF))))
+    return Bm[near], Bm[~near], verts[~near], halves[~near]
+
+
+def sampled_id(BN, BF, vf, hf, lev, c, h, opts):
+    """Hybrid-sampled CPQR ID (Sections 4.1-4.2) of the columns of
+    [B_N; B_F]: Y = [B_N; G B_F / sqrt(h)] with G Gaussian (h x |F|, entries
+    keyed by (seed, level, row, vf, c, hf)), CPQR of Y, and the a-posteriori
+    probe check of the far rows; h doubles until the check passes, and once
+    h >= |F| the exact far rows are used (then no check is needed).  Returns
+    (k, perm, T, h, passes, margin); margin is the closest of the rank and
+    check decisions to its threshold (relative)."""
     passes = 0
     margins = []
     while True:
@@ -163,6 +179,24 @@ def segment_id(nd, lev, c, blocks, cur, opts, sym):
         if err <= opts.tau * opts.eps * r11:
             return k, perm, T, h, passes, min(margins, default=float("inf"))
         h *= 2
+
+
+def segment_id(nd, lev, c, blocks, cur, opts, sym):
+    """ID of segment c of level lev against the level-start blocks; returns
+    the result of sampled_id, or None when the segment has no coupling rows
+    or a negative rank hint keeps it whole."""
+    rows = coupling_rows(nd, lev, c, blocks, cur, opts)
+    if rows is None:
+        return None
+    BN, BF, vf, hf = rows
+    h = opts.h0
+    if opts.rank_hint is not None:
+        h = int(opts.rank_hint(lev, c, dict(n=len(cur[c]), nnear=len(BN), nfar=len(BF))))
+        if h < 0:
+            return None
+        if h == 0:
+            h = opts.h0
+    return sampled_id(BN, BF, vf, hf, lev, c, h, opts)
 
 
 def _scale_block(X, rc, rd):
@@ -218,7 +252,7 @@ def factor(nd, A, opts=None):
         ids = {}
         if opts.eps > 0:
             for c, sg in enumerate(lvl.segs):
-                if sg.regular:
+                if sg.regular and (lev, c) not in opts.no_id:
                     r = segment_id(nd, lev, c, blocks, cur, opts, sym)
                     if r is not None:
                         ids[c] = r
@@ -263,6 +297,8 @@ def factor(nd, A, opts=None):
         levels[lev] = LevelRec(level=lev, segs=recs, sep_coup=sep_coup,
                                n_before=[len(cur[c]) for c in range(nseg)],
                                k_after=[len(recs[c].skel) for c in range(nseg)])
+        if opts.trace is not None:
+            opts.trace(lev, dict(blocks=blocks, cur=cur, ids=ids, recs=recs, scaled=scaled))
         if lev == 1:
             break
         # d./e. eliminate the level-l separators while merging into level l-1

@@ -1654,7 +1654,7 @@ void spalu_factor_opts_default(spalu_factor_opts* o) {
   o->rho = 0.5;
   o->h0 = 8;
   o->probes = 5;
-  o->tau = 10.0;
+  o->tau = 1.0;
   o->h_init = nullptr;
   o->rank_model = nullptr;
   o->features_out = nullptr;

@@ -188,7 +188,7 @@ class ND:
         return b
 
 
-def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, tau=10.0,
+def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, tau=1.0,
                 h_init=None, rank_model=None, features_out=None, rank_margin=1.0, rank_pad=5):
     o = FactorOpts()
     _lib.spalu_factor_opts_default(C.byref(o))
@@ -211,7 +211,7 @@ class Factor:
     """spaLU factorization of a CSR matrix held in device memory (torch)."""
 
     def __init__(self, nd, rowptr, colind, vals, eps=1e-6, precision=FP64, seed=1234, rho=0.5,
-                 h0=8, probes=5, tau=10.0, h_init=None, rank_model=None, features_out=None,
+                 h0=8, probes=5, tau=1.0, h_init=None, rank_model=None, features_out=None,
                  stream=None):
         import torch
         assert rowptr.is_cuda and rowptr.dtype == torch.int64

@@ -52,9 +52,47 @@ def test_adam_recurrence_and_frozen_normalisation():
     assert np.array_equal(p1[:M.OFF_W1], p[:M.OFF_W1])
 
 
-def test_sigmoid_output_range():
-    p = _params()
-    y, _ = M.forward(p, np.random.default_rng(2).standard_normal((50, M.NF)) * 10)
+def test_forward_closed_form():
+    """A hand-set network: standardisation, the orientation of W1 and W2
+    (row = output unit), both ReLUs, the output weights and the sigmoid each
+    change the value in a way that is written out here."""
+    p = np.zeros(M.NPARAM)
+    mu = np.arange(M.NF, dtype=float)
+    sd = np.full(M.NF, 2.0)
+    p[M.OFF_MU:M.OFF_MU + M.NF] = mu
+    p[M.OFF_SD:M.OFF_SD + M.NF] = sd
+    W1 = np.zeros((M.H, M.NF))
+    W1[1, 3] = 1.0          # hidden unit 1 reads feature 3
+    W1[2, 5] = -1.0         # hidden unit 2 reads minus feature 5
+    b1 = np.zeros(M.H)
+    b1[2] = 0.25
+    W2 = np.zeros((M.H, M.H))
+    W2[4, 1] = 2.0          # unit 4 of layer 2 reads unit 1 of layer 1
+    W2[4, 2] = 1.0
+    W2[6, 1] = -1.0         # unit 6 is negative whenever unit 1 is positive
+    b2 = np.zeros(M.H)
+    b2[6] = 0.5
+    w3 = np.zeros(M.H)
+    w3[4] = 3.0
+    w3[6] = -2.0
+    p[M.OFF_W1:M.OFF_B1] = W1.ravel()
+    p[M.OFF_B1:M.OFF_W2] = b1
+    p[M.OFF_W2:M.OFF_B2] = W2.ravel()
+    p[M.OFF_B2:M.OFF_W3] = b2
+    p[M.OFF_W3:M.OFF_B3] = w3
+    p[M.OFF_B3] = -1.0
+    X = np.tile(mu, (4, 1))
+    X[0, 3] = mu[3] + 2.0     # xn3 = 1: h1 = 1, h2 = relu(0.25) = .25
+    X[0, 5] = mu[5] + 0.0     #          z2_4 = 2.25, z2_6 = -0.5 -> 0
+    X[1, 3] = mu[3] - 2.0     # xn3 = -1: h1 = 0; xn5 = 0: h2 = .25
+    X[2, 5] = mu[5] + 1.0     # xn5 = .5: h2 = relu(-.25) = 0, h1 = 0
+    X[3, 3] = mu[3] + 0.5     # xn3 = .25: h1 = .25, h2 = .25; z2_6 = .25
+    z = np.array([3 * 2.25 - 1.0,
+                  3 * 0.25 - 2 * 0.5 - 1.0,
+                  -2 * 0.5 - 1.0,
+                  3 * 0.75 - 2 * 0.25 - 1.0])
+    y, _ = M.forward(p, X)
+    assert np.allclose(y, 1.0 / (1.0 + np.exp(-z)), rtol=1e-15, atol=0)
     assert np.all((y > 0) & (y < 1))
 
 

@@ -36,11 +36,38 @@ def test_philox_known_answers():
         assert tuple(int(o[0]) for o in out) == tuple(w[6:10])
 
 
-def test_gaussian_moments():
+def test_uniform53_bit_window():
+    """The uniform of two Philox words uses bits 63..11 of hi:lo: bit 11 is
+    the lowest counted bit (one step of 2^-53), bits 10..0 are dropped, the
+    top bit is worth 1/2, and half a step keeps the value away from 0."""
+    u = philox.uniform53
+    assert u(0, 0) == 2.0 ** -54
+    assert u(0, (1 << 11) - 1) == 2.0 ** -54
+    assert u(0, 1 << 11) == 2.0 ** -53 + 2.0 ** -54
+    assert u(1 << 31, 0) == 0.5 + 2.0 ** -54
+    assert u(1, 0) == 2.0 ** -32 + 2.0 ** -54
+    assert u(0xFFFFFFFF, 0xFFFFFFFF) == 1.0          # 1 - 2^-54 rounds to 1
+
+
+def test_gaussian_law():
+    """Entries of G follow N(0, 1) (Kolmogorov-Smirnov, also for even and odd
+    rows apart); the two entries of one draw are independent normals, so
+    their squared radius / 2 is Exp(1) and their angle is uniform; entries
+    depend only on their coordinates."""
+    from scipy import stats
     g = philox.gaussian(7, 3, 0, np.arange(64), np.arange(4000), 5, np.zeros(4000, np.int64))
-    assert abs(g.mean()) < 0.01
-    assert abs(g.std() - 1.0) < 0.01
-    # entries depend only on their coordinates
+    assert stats.kstest(g.ravel(), "norm").pvalue > 1e-3
+    assert stats.kstest(g[0::2].ravel(), "norm").pvalue > 1e-3
+    assert stats.kstest(g[1::2].ravel(), "norm").pvalue > 1e-3
+    ev, od = g[0::2].ravel(), g[1::2].ravel()
+    assert stats.kstest((ev ** 2 + od ** 2) / 2, "expon").pvalue > 1e-3
+    assert stats.kstest(np.arctan2(od, ev), stats.uniform(-math.pi, 2 * math.pi).cdf).pvalue > 1e-3
+    assert abs(np.corrcoef(ev, od)[0, 1]) < 0.01
+    # the other half, segment, stream and level give independent entries
+    for args in ((7, 3, 0, 5, 1), (7, 3, 0, 6, 0), (7, 3, 1, 5, 0), (7, 4, 0, 5, 0), (8, 3, 0, 5, 0)):
+        s_, l_, st_, c_, h_ = args
+        g2 = philox.gaussian(s_, l_, st_, np.arange(64), np.arange(4000), c_, np.full(4000, h_))
+        assert abs(np.corrcoef(g.ravel(), g2.ravel())[0, 1]) < 0.01
     g2 = philox.gaussian(7, 3, 0, np.arange(8, 16), np.arange(100, 200), 5, np.zeros(100, np.int64))
     assert np.array_equal(g2, g[8:16, 100:200])
 
@@ -184,6 +211,29 @@ def test_cpqr_exact_rank():
         assert np.abs(err).max() <= 1e-12 * np.abs(Y).max()
 
 
+def test_cpqr_tie_rule():
+    """Column norms within TIE_REL of the maximum are tied and the smallest
+    original column wins, also when that column sits at a later position
+    after an earlier swap."""
+    a = np.array([1.0, 2.0, 2.0, 0.0, 0.0])
+    b = np.array([2.0, 1.0, 0.0, 2.0, 0.0])
+    c = np.array([0.0, 0.0, 0.0, 0.0, 9.0])
+    # step 0: columns 1 and 3 tie (norm 3), column 1 wins
+    Y = np.stack([0.1 * c, a, 0.2 * c, b], axis=1)
+    k, perm, T, r11 = dense.cpqr_id(Y, 0.0, max_rank=1)
+    assert perm[0] == 1
+    # step 0 takes column 3 (norm 9), which moves column 0 to position 3;
+    # step 1: columns 0 (position 3) and 2 (position 2) tie, column 0 wins
+    Y = np.stack([a, 0.01 * c + 0.0 * a, b, c], axis=1)
+    Y[:, 1] = np.array([0.0, 0.0, 0.0, 0.5, 0.0])
+    k, perm, T, r11 = dense.cpqr_id(Y, 0.0, max_rank=2)
+    assert perm[0] == 3 and perm[1] == 0
+    # one part in 1e9 is not a tie: the larger column wins
+    Y = np.stack([a, b * (1 + 1e-9)], axis=1)
+    k, perm, T, r11 = dense.cpqr_id(Y, 0.0, max_rank=1)
+    assert perm[0] == 1
+
+
 def test_cpqr_gu_eisenstat_bracket():
     """|R_{k+1,k+1}| brackets sigma_{k+1} within sqrt(1 + n k (n-k))
     (eq. (4.15)); sigma_k(R_11) >= sigma_k / sqrt(1 + n k (n-k))."""
@@ -246,26 +296,278 @@ def test_compressed_residual_within_10_eps(eps):
 
 @pytest.mark.parametrize("cfg", [1, 2, 4])
 def test_compressed_other_families(cfg):
+    """The loss of about one digit (Section 6) as a normwise backward error
+    ||b - A x|| / (||A||_2 ||x||) <= 10 eps for every family, and as the
+    relative residual R_es <= 10 eps for the well-conditioned ones (the
+    indefinite Helmholtz operator at 10 points per wavelength multiplies
+    the residual by its condition number); refinement then reaches 1e-10."""
     P = make_config(cfg, side=63, nrhs=2)
-    F = spalu.factor(nd_order(P.dims), P.scipy(), spalu.Opts(eps=P.eps))
+    A = P.scipy()
+    F = spalu.factor(nd_order(P.dims), A, spalu.Opts(eps=P.eps))
     x, it, hist = spalu.solve(F, P.rhs, tol=1e-10, max_iter=30)
     assert hist[-1].max() <= 1e-10
+    x0 = spalu.apply_inverse(F, P.rhs)
+    normA = np.linalg.norm(A.toarray(), 2)
+    back = np.linalg.norm(P.rhs - A @ x0, axis=0) / (normA * np.linalg.norm(x0, axis=0))
+    assert back.max() <= 10 * P.eps
     if cfg != 4:
-        assert hist[0].max() <= 100 * P.eps
+        assert hist[0].max() <= 10 * P.eps
 
 
-def test_remainder_decoupled_and_locality():
-    """After sparsification the remainder DOFs of a segment have no
-    coupling left (eq. (2.7)), and blocks that do not touch the segment are
-    unchanged (A_ff, A_nf stay as they are)."""
-    P = make_config(0, side=31)
+def test_compression_stats():
+    """q~ = max_l e'_l / e_l (Section 6): no segment is sparsified with
+    eps = 0; with compression the per-level maximum sizes satisfy the
+    sparsity assumption e'_l <= q e_l + sigma_e with q = 2^(-1/3) and
+    sigma_e = 7 (one leaf side: segments that small may stay whole), the
+    largest segments shrink, and q~ is the largest ratio."""
+    P = make_config(0, side=127)
     nd = nd_order(P.dims)
-    F = spalu.factor(nd, P.scipy(), spalu.Opts(eps=1e-6))
-    for lev, rec in F.levels.items():
-        for s, lst in rec.sep_coup.items():
-            for (d, Ads, Asd) in lst:
-                assert Ads.shape == (len(rec.segs[d].skel), len(rec.segs[s].skel))
-                assert Asd.shape == (len(rec.segs[s].skel), len(rec.segs[d].skel))
+    F0 = spalu.factor(nd, P.scipy(), spalu.Opts(eps=0.0))
+    assert spalu.compression_stats(F0) == ({}, 0.0)
+    F = spalu.factor(nd, P.scipy(), spalu.Opts(eps=1e-4))
+    st, q = spalu.compression_stats(F)
+    for lev, (e, e2) in st.items():
+        sizes = [F.levels[lev].n_before[i] for i, r in enumerate(F.levels[lev].segs) if r.sparsified]
+        kept = [len(r.skel) for r in F.levels[lev].segs if r.sparsified]
+        assert (e, e2) == (max(sizes), max(kept))
+        assert e2 <= 2 ** (-1 / 3) * e + 7
+    top = max(st, key=lambda l: st[l][0])
+    assert st[top][1] < st[top][0]
+    assert q == max(e2 / e for e, e2 in st.values())
+
+
+# ----------------------------------------------------------------- sampled ID
+def _id_rows(rng, m_near, m_far, n, k0):
+    """Near and far rows of an exact rank-k0 coupling matrix, with far-row
+    keys (vertex ids and halves) for the Gaussian entries."""
+    C = rng.standard_normal((k0, n)) * np.logspace(0, -1, n)[None, :]
+    BN = rng.standard_normal((m_near, k0)) @ C
+    BF = rng.standard_normal((m_far, k0)) @ C
+    vf = rng.permutation(10 * m_far)[:m_far]
+    hf = rng.integers(0, 2, m_far)
+    return BN, BF, vf, hf
+
+
+@pytest.mark.parametrize("m_near", [0, 6])
+def test_sampled_id_range_finder(m_near):
+    """Randomised range finder (Section 4.2.3; Halko, Martinsson, Tropp
+    2011): when the far rows have rank k0 < h, G B_F has the row space of
+    B_F, so one pass finds k = k0 and T reconstructs the true far rows (not
+    only the sampled ones) and the near rows to rounding."""
+    rng = np.random.default_rng(11)
+    BN, BF, vf, hf = _id_rows(rng, m_near, 120, 18, 5)
+    o = spalu.Opts(eps=1e-10)
+    k, perm, T, h, passes, _ = spalu.sampled_id(BN, BF, vf, hf, 3, 7, 8, o)
+    assert (k, h, passes) == (5, 8, 1)
+    for B in (BF, BN):
+        if len(B):
+            E = B[:, perm[k:]] - B[:, perm[:k]] @ T
+            assert np.abs(E).max() <= 1e-11 * np.abs(B).max()
+
+
+def test_sampled_id_doubles_until_the_check_passes():
+    """Far rows of rank 20 sampled with h = 8 cannot pass the probe check;
+    h doubles (8, 16, 32) and the accepted ID reconstructs the far rows."""
+    rng = np.random.default_rng(12)
+    BN, BF, vf, hf = _id_rows(rng, 0, 200, 30, 20)
+    o = spalu.Opts(eps=1e-10)
+    k, perm, T, h, passes, _ = spalu.sampled_id(BN, BF, vf, hf, 2, 1, 8, o)
+    assert (k, h, passes) == (20, 32, 3)
+    E = BF[:, perm[k:]] - BF[:, perm[:k]] @ T
+    assert np.abs(E).max() <= 1e-9 * np.abs(BF).max()
+
+
+def _scipy_id(Y, eps):
+    """Pivoted QR ID by LAPACK (scipy): rank = first |R_jj| <= eps |R_00|."""
+    _, R, p = sla.qr(Y, pivoting=True, mode="economic")
+    d = np.abs(np.diag(R))
+    small = np.nonzero(d <= eps * d[0])[0]
+    k = int(small[0]) if len(small) else len(d)
+    T = sla.solve_triangular(R[:k, :k], R[:k, k:])
+    return k, p, T
+
+
+def test_sampled_id_at_the_cap_is_the_exact_id():
+    """With h at the cap (h >= |F|) the ID is taken on the exact rows
+    [B_N; B_F], i.e. the unsampled ID: pivots, rank and T equal LAPACK's
+    pivoted QR of the stacked matrix (tie-free input)."""
+    rng = np.random.default_rng(13)
+    BN = rng.standard_normal((9, 16)) * np.logspace(0, -8, 16)[None, :]
+    BF = rng.standard_normal((14, 16)) * np.logspace(0, -8, 16)[None, :]
+    vf = np.arange(14)
+    hf = np.zeros(14, np.int64)
+    eps = 1e-5
+    k, perm, T, h, passes, _ = spalu.sampled_id(BN, BF, vf, hf, 1, 0, 14, spalu.Opts(eps=eps))
+    ks, ps, Ts = _scipy_id(np.vstack([BN, BF]), eps)
+    assert (h, passes) == (14, 1)
+    assert k == ks and np.array_equal(perm, ps)
+    assert np.allclose(T, Ts, rtol=1e-9, atol=1e-12)
+
+
+def _level_schur(A, nd, lev):
+    """Dense Schur complement onto the DOFs that are still present at the
+    start of level lev when nothing is compressed (eps = 0): every vertex
+    of the leaves and of separators of level > lev is eliminated."""
+    A = A.toarray()
+    lvl = nd.levels[lev]
+    keep = np.nonzero(lvl.seg_of >= 0)[0]
+    elim = np.nonzero(lvl.seg_of < 0)[0]
+    S = A[np.ix_(keep, keep)] - A[np.ix_(keep, elim)] @ np.linalg.solve(
+        A[np.ix_(elim, elim)], A[np.ix_(elim, keep)])
+    pos = np.full(A.shape[0], -1)
+    pos[keep] = np.arange(len(keep))
+    return S, pos
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_level_L_ids_are_ids_of_the_exact_stacked_couplings(cfg):
+    """Stacking (eq. (4.12)): with every row near (rho large) each level-L ID
+    is the pivoted QR ID of [S_{n,c}; S_{c,n}^T] taken from the dense Schur
+    complement of the leaves (computed here with numpy), for the symmetric
+    GRF diffusion and the non-symmetric convection-diffusion matrix (where
+    the two halves differ, so a transposed or missing half shows)."""
+    P = make_config(cfg, side=31)
+    nd = nd_order(P.dims)
+    A = P.scipy()
+    seen = {}
+    o = spalu.Opts(eps=P.eps, rho=1e9, trace=lambda lev, d: seen.setdefault(lev, d))
+    spalu.factor(nd, A, o)
+    L = nd.L
+    S, pos = _level_schur(A, nd, L)
+    lvl = nd.levels[L]
+    tr = seen[L]
+    checked = 0
+    for c, sg in enumerate(lvl.segs):
+        if c not in tr["ids"]:
+            continue
+        k, perm, T, h, passes, _ = tr["ids"][c]
+        vc = pos[tr["cur"][c]]
+        rows = []
+        for (a, d) in lvl.pairs:
+            if a == c and d != c:
+                vd = pos[tr["cur"][d]]
+                rows += [S[np.ix_(vd, vc)], S[np.ix_(vc, vd)].T]
+        Y = np.vstack(rows)
+        ks, ps, Ts = _scipy_id(Y, P.eps)
+        assert (k, passes) == (ks, 1)
+        _check_pivots(Y, perm, k, ps)
+        if np.array_equal(perm, ps):
+            assert np.allclose(T, Ts, rtol=1e-7, atol=1e-9)
+        if k < len(perm):     # residual columns = those of R_22, each <= eps |R_11|
+            E = Y[:, perm[k:]] - Y[:, perm[:k]] @ T
+            assert np.linalg.norm(E, axis=0).max() <= P.eps * np.linalg.norm(Y, axis=0).max()
+        checked += 1
+    assert checked >= 8
+
+
+def _check_pivots(Y, perm, k, lapack_perm):
+    """Each pivot of the first k steps has the largest norm of the columns
+    projected off the pivots before it (fresh norms, by an orthogonal
+    projection computed here); where LAPACK's pivot order first departs,
+    its choice is tied with the oracle's and the oracle took the smaller
+    original column."""
+    same = True
+    for j in range(k):
+        if j:
+            Q, _ = np.linalg.qr(Y[:, perm[:j]])
+            Z = Y - Q @ (Q.T @ Y)
+        else:
+            Z = Y
+        nrm = np.linalg.norm(Z, axis=0)
+        nrm[perm[:j]] = 0.0
+        mx = nrm.max()
+        assert nrm[perm[j]] >= mx * (1 - 1e-10)
+        if same and lapack_perm[j] != perm[j]:
+            assert nrm[lapack_perm[j]] >= mx * (1 - 1e-10)
+            assert perm[j] < lapack_perm[j]
+            same = False
+
+
+def _transform(M, perm, k, T):
+    """U_t M L_t of eq. (2.7) as dense products: L_t is the identity except
+    (L_t)[s_i, r_j] = -T[i, j] (column r_j := r_j - sum_i T[i, j] s_i) and
+    U_t = L_t^T; returned in [remainder; skeleton] order."""
+    n = len(perm)
+    Lt = np.eye(n)
+    Lt[np.ix_(perm[:k], perm[k:])] = -T
+    order = np.concatenate([perm[k:], perm[:k]])
+    return (Lt.T @ M @ Lt)[np.ix_(order, order)]
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+def test_sparsify_decouples_the_remainder(cfg):
+    """Schur sparsification (eq. (2.7), Section 2.3.2): after the transform
+    every coupling of a segment's remainder DOFs to its neighbours is of
+    the order of eps (what the method drops), the remainder DOFs never
+    appear again (the next level holds skeletons only), and the two-stage
+    LU of the transformed diagonal block keeps its pivots inside the
+    remainder for the first n_r steps and reproduces the block."""
+    P = make_config(cfg, side=63)
+    nd = nd_order(P.dims)
+    seen = {}
+    spalu.factor(nd, P.scipy(), spalu.Opts(eps=P.eps, trace=lambda lev, d: seen.setdefault(lev, d)))
+    nchecked = 0
+    for lev, tr in seen.items():
+        lvl = nd.levels[lev]
+        B, cur = tr["blocks"], tr["cur"]
+        dropped = set()
+        for c, (k, perm, T, h, passes, _) in tr["ids"].items():
+            nr = len(perm) - k
+            rec = tr["recs"][c]
+            assert rec.nr == nr
+            nbr = [d for (a, d) in lvl.pairs if a == c and d != c and len(cur[d])]
+            Y = np.vstack([np.vstack([B[(d, c)], B[(c, d)].T]) for d in nbr])
+            scale = np.linalg.norm(Y, axis=0).max()
+            worst = 0.0
+            for d in nbr:
+                Edc = B[(d, c)][:, perm[k:]] - B[(d, c)][:, perm[:k]] @ T
+                Ecd = B[(c, d)][perm[k:], :] - T.T @ B[(c, d)][perm[:k], :]
+                worst = max(worst, np.abs(Edc).max(initial=0.0), np.abs(Ecd).max(initial=0.0))
+                assert tr["scaled"][(c, d)].shape == (k, len(tr["recs"][d].skel))
+            assert worst <= 10 * P.eps * scale
+            M2 = _transform(B[(c, c)], perm, k, T)
+            LU, piv = rec.LU, rec.piv
+            assert np.all(piv[:nr] < nr)
+            L = np.tril(LU, -1) + np.eye(len(perm))
+            U = np.triu(LU)
+            PM = dense.apply_row_pivots(piv, M2)
+            assert np.linalg.norm(PM - L @ U) <= 1e-12 * np.linalg.norm(M2)
+            dropped |= set(rec.dofs[:nr].tolist())
+            nchecked += nr > 0
+        if lev - 1 in seen:
+            nxt = set(np.concatenate([v for v in seen[lev - 1]["cur"].values()]).tolist())
+            assert not (nxt & dropped)
+    assert nchecked >= 10
+
+
+def test_sparsification_is_local_and_simultaneous():
+    """Sparsifying a segment changes only the blocks in its own row and
+    column (A_ff and A_nf stay as they are, Section 2.3.2): with the ID of
+    one segment switched off, every scaled coupling of that level between
+    two other segments is bit-identical; every ID of the level sees the
+    level-start matrix (the simultaneous reading), so the neighbours'
+    skeletons are unchanged too."""
+    P = make_config(2, side=63)
+    nd = nd_order(P.dims)
+    base, off = {}, {}
+    spalu.factor(nd, P.scipy(), spalu.Opts(eps=P.eps, trace=lambda lev, d: base.setdefault(lev, d)))
+    nr, lev, c0 = max((len(r[1]) - r[0], l, c) for l in base for c, r in base[l]["ids"].items())
+    assert nr > 0
+    o = spalu.Opts(eps=P.eps, no_id=frozenset({(lev, c0)}),
+                   trace=lambda l, d: off.setdefault(l, d))
+    spalu.factor(nd, P.scipy(), o)
+    a, b = base[lev], off[lev]
+    assert c0 in a["ids"] and c0 not in b["ids"]
+    assert set(a["ids"]) - {c0} == set(b["ids"])
+    for c in b["ids"]:
+        assert np.array_equal(a["ids"][c][1], b["ids"][c][1])
+    touched = 0
+    for key in a["scaled"]:
+        if c0 in key:
+            touched += a["scaled"][key].shape != b["scaled"][key].shape
+            continue
+        assert np.array_equal(a["scaled"][key], b["scaled"][key])
+    assert touched > 0
 
 
 def test_error_bound_eq_4_14():
