@@ -117,7 +117,9 @@ typedef struct {
   double rho;          /* near field: Chebyshev distance <= max(1, rho*span)  */
   int32_t h0;          /* first number of samples of the adaptive ID          */
   int32_t probes;      /* Gaussian probes of the a-posteriori ID check        */
-  double tau;          /* accept if max probe error <= tau * eps * |R_11|     */
+  double tau;          /* accept the sampled ID if the largest probe error
+                          is <= tau * sqrt(n - k) * eps * |R_11| (the
+                          Frobenius bound of the unsampled truncation)  */
   const int32_t* h_init; /* optional device array, per (level, segment) start
                             samples; index = seg_base[l] + c, see
                             spalu_factor_seg_base; <= 0 entries use h0     */

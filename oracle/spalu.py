@@ -26,13 +26,17 @@ Readings of points the paper leaves open (each is a documented choice):
     0.5 by default; the rest is the far field F;
   * the rank test is relative: stop at the first |R_jj| <= eps |R_11|;
   * samples: h starts at h0 = 8 (or a predicted value), doubles while an
-    a-posteriori test with 5 Gaussian probes of the far rows fails
-    (max_i ||w_i^T (B_F P_r - B_F P_s T)|| > tau * eps * |R_11|, tau = 1:
-    the probes must show the far-field error under the same threshold the
-    CPQR truncation applies to every column; by the bound of Halko,
-    Martinsson and Tropp (2011, Section 4.3) the accepted error is then at
-    most 10 sqrt(2/pi) eps |R_11| with probability 1 - 10^-probes), and
-    once h >= |F| the exact far rows are used;
+    a-posteriori test with 5 Gaussian probes of the far rows fails,
+        max_i ||w_i^T E|| > tau * sqrt(n - k) * eps * |R_11|,
+        E = B_F P_r - B_F P_s T,  tau = 1,
+    and once h >= |F| the exact far rows are used.  For a standard Gaussian
+    w, E ||w^T E||^2 = ||E||_F^2, so each probe estimates the Frobenius norm
+    of the far-field residual; the unsampled ID accepted by the rank test
+    leaves n - k residual columns of norm at most eps |R_11| each, i.e.
+    ||E||_F <= sqrt(n - k) eps |R_11|, and the test holds the sampled ID to
+    that same bound (by Halko, Martinsson and Tropp 2011, Section 4.3, the
+    accepted ||E||_2 is then at most 10 sqrt(2/pi) times the bound with
+    probability 1 - 10^-probes);
   * a rank hint (learned form) gives the first h; a negative hint keeps the
     segment whole (k = n, no ID): skipping compression is exact, it only
     gives up the reduction in size;
@@ -174,9 +178,10 @@ def sampled_id(BN, BF, vf, hf, lev, c, h, opts):
         P = Om @ BF
         E = P[:, perm[k:]] - P[:, perm[:k]] @ T
         err = float(np.sqrt((E ** 2).sum(axis=1)).max()) if E.size else 0.0
-        if r11 > 0:
-            margins.append(abs(err / (opts.tau * opts.eps * r11) - 1.0))
-        if err <= opts.tau * opts.eps * r11:
+        bound = opts.tau * math.sqrt(len(perm) - k) * opts.eps * r11
+        if bound > 0:
+            margins.append(abs(err / bound - 1.0))
+        if err <= bound:
             return k, perm, T, h, passes, min(margins, default=float("inf"))
         h *= 2
 

@@ -89,6 +89,14 @@ __device__ inline int block_scan_flag(bool f, int* wtot /* NWAVE */, int* total)
   return off + inwave;
 }
 
+// A zero pivot in a diagonal block of the given level (L + 1 for a leaf):
+// bit 0 of status[0] is set and status[1] keeps the largest such level, the
+// first one in elimination order.
+__device__ inline void flag_singular(int* status, int level) {
+  atomicOr(status, 1);
+  atomicMax(status + 1, level);
+}
+
 // Philox4x32-10 (Salmon et al., SC'11).
 __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 #pragma unroll

@@ -121,7 +121,8 @@ template <typename T>
 __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nleaf, GridGeom g,
                                                     const int64_t* rowptr, const int32_t* colind,
                                                     const double* vals, int32_t* iarena, T* varena,
-                                                    double* gscratch, int64_t gscr_stride, int* status) {
+                                                    double* gscratch, int64_t gscr_stride, int* status,
+                                                    int level) {
   extern __shared__ double lds[];
   __shared__ int s_piv;
   __shared__ double s_d;
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
     }
     __syncthreads();
   }
-  if (singular && tid == 0) atomicOr(status, 1);
+  if (singular && tid == 0) flag_singular(status, level);
   for (int k = tid; k < ni; k += WG) piv[k] = s_pv[k];
   // undo the row interchanges on the columns of the inverse, last first
   for (int k = ni - 1; k >= 0; --k) {
@@ -292,7 +293,7 @@ template <typename T, int WC>
 __global__ __launch_bounds__(64) void k_leaf_factor_wave(const DLeaf* leaves, int nleaf, GridGeom g,
                                                          const int64_t* rowptr, const int32_t* colind,
                                                          const double* vals, int32_t* iarena, T* varena,
-                                                         int* status) {
+                                                         int* status, int level) {
   extern __shared__ double lds[];
   const int lf = blockIdx.x;
   if (lf >= nleaf) return;
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(64) void k_leaf_factor_wave(const DLeaf* leaves, in
     if (lane == 0) pord[k] = p;
   }
   wave_sync();
-  if (singular && lane == 0) atomicOr(status, 1);
+  if (singular && lane == 0) flag_singular(status, level);
   for (int k = lane; k < ni; k += 64) piv[k] = pord[k];
   if (lane < ni) {
     const double sc = 1.0 / my_d;
@@ -607,7 +608,7 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_seg_lu(const DSeg* segs, int nseg, const DBlk* blks,
                                                int32_t* iarena, T* varena, double* scratch,
                                                DLevelDyn dyn, int* status, int need_lo, int need_hi,
-                                               int lds_doubles) {
+                                               int lds_doubles, int level) {
   extern __shared__ double lds[];
   __shared__ int s_piv;
   const int c = blockIdx.x;
@@ -669,7 +670,7 @@ __global__ __launch_bounds__(NT) void k_seg_lu(const DSeg* segs, int nseg, const
   // would stall each step), copied out afterwards
   const bool pv_lds = inlds && need + (n + 1) / 2 <= lds_doubles;
   int* pv = pv_lds ? reinterpret_cast<int*>(lds + need) : piv;
-  if (seg_block_lu<NT>(W, n, sp ? nr : 0, pv, &s_piv)) atomicOr(status, 1);
+  if (seg_block_lu<NT>(W, n, sp ? nr : 0, pv, &s_piv)) flag_singular(status, level);
   __syncthreads();
   // stored form of the interchanges: the composed row map (row i of P X is
   // row piv[i] of X), each entry traced back through the interchanges
@@ -707,7 +708,7 @@ __host__ __device__ inline int seglu_wave_lds_doubles(int nw) { return nw * nw +
 template <typename T, int CPL>
 __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, const DBlk* blks,
                                                     int32_t* iarena, T* varena, DLevelDyn dyn, int* status,
-                                                    int nmin, int nmax) {
+                                                    int nmin, int nmax, int level) {
   extern __shared__ double lds[];
   const int c = blockIdx.x;
   if (c >= nseg) return;
@@ -868,7 +869,7 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
     }
     wave_sync();
   }
-  if (singular && lane == 0) atomicOr(status, 1);
+  if (singular && lane == 0) flag_singular(status, level);
 #pragma unroll
   for (int u = 0; u < CPL; ++u)
     if (lane + 64 * u < n) piv[lane + 64 * u] = rm[u];

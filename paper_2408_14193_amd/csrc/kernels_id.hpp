@@ -626,7 +626,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
       if (tid == 0) {
         double worst = 0.0;
         for (int pr = 0; pr < probes; ++pr) worst = fmax(worst, pn[pr]);
-        s_acc = worst <= prm.tau * prm.eps * r11 ? 1 : 0;
+        s_acc = worst <= prm.tau * sqrt(double(nr)) * prm.eps * r11 ? 1 : 0;
       }
       __syncthreads();
       accept = s_acc != 0;
@@ -944,7 +944,7 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
         s = block_sum(s, s_scal);
         worst = fmax(worst, sqrt(s));
       }
-      accept = worst <= prm.tau * prm.eps * r11;
+      accept = worst <= prm.tau * sqrt(double(nr)) * prm.eps * r11;
     }
     if (accept) {
       for (int t = tid; t < k * nr; t += WG) {

@@ -101,11 +101,20 @@ struct Layout {
   char* dimage = nullptr;
   int dimage_dev = -1;
   double dimage_rho = -1.0;
+  // one event per stream that copied out of dimage, recorded after its last
+  // copy: a replaced image is freed once every such copy is done (not by a
+  // device-wide synchronisation)
+  std::vector<std::pair<hipStream_t, hipEvent_t>> dimage_read;
+  void wait_image_readers() const {
+    for (const auto& se : dimage_read) (void)hipEventSynchronize(se.second);
+  }
   // pinned staging of the read-back of the per-level size arrays
   mutable char* dyn_pinned = nullptr;
   ~Layout() {
     if (image) (void)hipHostFree(image);
+    wait_image_readers();
     if (dimage) (void)hipFree(dimage);
+    for (const auto& se : dimage_read) (void)hipEventDestroy(se.second);
     if (dyn_pinned) (void)hipHostFree(dyn_pinned);
   }
 };
@@ -982,16 +991,17 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       const size_t wl = size_t(Y.leaf_wave_lds);
       if (Y.leaf_wc == 48) {
         LAUNCH(K_LEAF, L, k_leaf_factor_wave<T, 48><<<nl, 64, wl, st>>>(lt, int(nl), F->g, F->rowptr, F->colind,
-                                                                    F->vals, iar, var, status));
+                                                                    F->vals, iar, var, status, L + 1));
       } else if (Y.leaf_wc == 80) {
         LAUNCH(K_LEAF, L, k_leaf_factor_wave<T, 80><<<nl, 64, wl, st>>>(lt, int(nl), F->g, F->rowptr, F->colind,
-                                                                    F->vals, iar, var, status));
+                                                                    F->vals, iar, var, status, L + 1));
       } else if (Y.leaf_wc == 96) {
         LAUNCH(K_LEAF, L, k_leaf_factor_wave<T, 96><<<nl, 64, wl, st>>>(lt, int(nl), F->g, F->rowptr, F->colind,
-                                                                    F->vals, iar, var, status));
+                                                                    F->vals, iar, var, status, L + 1));
       } else {
         LAUNCH(K_LEAF, L, k_leaf_factor<T><<<nl, WG, LEAF_LDS_BYTES, st>>>(
-            lt, int(nl), F->g, F->rowptr, F->colind, F->vals, iar, var, scr, int64_t(Y.leaf_scr_stride), status));
+            lt, int(nl), F->g, F->rowptr, F->colind, F->vals, iar, var, scr, int64_t(Y.leaf_scr_stride), status,
+            L + 1));
       }
     }
     // blocks of small segments: one wave each
@@ -1118,12 +1128,12 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       if (!lu_lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the segment LU kernel");
       const int nw = std::min(SEGLU_WAVE_MAX_N, T_.max_cap);
       LAUNCH(K_LU, l, k_seg_lu_wave<T, 1><<<unsigned(ns), 64, size_t(seglu_wave_lds_doubles(nw)) * 8, st>>>(
-          segs, ns, blks, iar, var, d, status, 0, nw));
+          segs, ns, blks, iar, var, d, status, 0, nw, l));
       if (T_.max_cap > SEGLU_WAVE_MAX_N) {
         const int64_t cap = T_.max_cap;
         const int big = int(std::min<int64_t>(2 * cap * cap + cap, int64_t(SEGLU_MAX_BYTES / 8)));
         LAUNCH_MORE(K_LU, l, k_seg_lu<T, SEGLU_BLOCK_NT><<<unsigned(ns), SEGLU_BLOCK_NT, size_t(big) * 8, st>>>(
-            segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, INT32_MAX, big));
+            segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, INT32_MAX, big, l));
       }
     }
     if (l > 1) {
@@ -1173,7 +1183,7 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
             int(MELIM_LDS_BYTES)));
     }
   }
-  HIPCHK(hipMemcpyAsync(status_host, status, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(status_host, status, 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const int rc = read_dyn_host(F);
   if (rc) return rc;
@@ -1744,7 +1754,8 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   const size_t img_bytes = Y->blob_bytes + (Y->leaf_i1 - Y->leaf_i0) * 4;
   if (!YM->dimage || YM->dimage_dev != dev || YM->dimage_rho != o.rho) {
     if (YM->dimage) {
-      HIPCHK(hipDeviceSynchronize());  // earlier factorizations may still be reading it
+      // copies of earlier factorizations (any stream) may still read it
+      YM->wait_image_readers();
       (void)hipFree(YM->dimage);
       YM->dimage = nullptr;
     }
@@ -1757,10 +1768,21 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   if (Y->leaf_i1 > Y->leaf_i0)
     HIPCHK(hipMemcpyAsync(F->ws + Y->o_iarena + Y->leaf_i0 * 4, YM->dimage + Y->blob_bytes,
                           (Y->leaf_i1 - Y->leaf_i0) * 4, hipMemcpyDeviceToDevice, F->stream));
-  int status = 0;
-  int rc = o.precision == SPALU_FP64 ? run_factor<double>(F.get(), o, &status)
-                                     : run_factor<float>(F.get(), o, &status);
+  {
+    hipEvent_t ev = nullptr;
+    for (const auto& se : YM->dimage_read)
+      if (se.first == F->stream) ev = se.second;
+    if (!ev) {
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      YM->dimage_read.emplace_back(F->stream, ev);
+    }
+    HIPCHK(hipEventRecord(ev, F->stream));
+  }
+  int stat[2] = {0, 0};
+  int rc = o.precision == SPALU_FP64 ? run_factor<double>(F.get(), o, stat)
+                                     : run_factor<float>(F.get(), o, stat);
   if (rc) return rc;
+  const int status = stat[0];
   if (status & 2) return fail(SPALU_EUNSUPPORTED, "matrix pattern is not inside the grid stencil");
   // statistics
   if (info) {
@@ -1798,8 +1820,8 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
     info->q_tilde = q;
   }
   if (status & 1) {
-    if (info) info->singular_level = 0;
-    return fail(SPALU_ESINGULAR, "zero pivot in a diagonal block");
+    if (info) info->singular_level = stat[1];
+    return fail(SPALU_ESINGULAR, "zero pivot in a diagonal block of level " + std::to_string(stat[1]));
   }
   *out = F.release();
   return SPALU_OK;

@@ -122,9 +122,11 @@ EXPORTED = ["spalu_nd_order", "spalu_nd_info", "spalu_nd_perm", "spalu_nd_etree"
             "spalu_last_error"]
 
 
-def _check(rc):
+def _check(rc, info=None):
     if rc != OK:
-        raise SpaluError(rc, _lib.spalu_last_error().decode())
+        e = SpaluError(rc, _lib.spalu_last_error().decode())
+        e.info = info.as_dict() if info is not None else None
+        raise e
 
 
 def _ptr(a, ctype):
@@ -238,7 +240,7 @@ class Factor:
         _check(_lib.spalu_factor(nd.handle, nd.n, self.csr[0].data_ptr(), self.csr[1].data_ptr(),
                                  self.csr[2].data_ptr(), C.byref(self.opts),
                                  self.workspace.data_ptr(), nbytes, s.cuda_stream, C.byref(h),
-                                 C.byref(info)))
+                                 C.byref(info)), info)
         self._h = h
         self.info = info.as_dict()
         self._solve_ws = {}

@@ -20,7 +20,7 @@
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(...)
-#define __align__(x) alignas(x)
+#define __align__(x) __attribute__((aligned(x)))
 #define __shared__ static
 
 struct dim3 {
@@ -106,6 +106,7 @@ inline int __shfl(int v, int src, int w = 64) {
 inline float __uint_as_float(uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; }
 inline uint32_t __float_as_uint(float f) { uint32_t u; std::memcpy(&u, &f, 4); return u; }
 inline int atomicOr(int* p, int v) { int o = *p; *p |= v; return o; }
+inline int atomicMax(int* p, int v) { int o = *p; if (v > o) *p = v; return o; }
 inline emu::d4 emu_amdgcn_mfma_f64_16x16x4f64(double a, double b, emu::d4 c, int, int, int) {
   return emu::mfma_f64_16x16x4(a, b, c);
 }
@@ -130,6 +131,8 @@ hipError_t hipHostMalloc(void**, size_t, unsigned = 0);
 hipError_t hipMalloc(void**, size_t);
 hipError_t hipFree(void*);
 hipError_t hipGetDevice(int*);
+#define HIP_SYMBOL(x) (&(x))
+inline hipError_t hipGetSymbolAddress(void** p, const void* sym) { *p = const_cast<void*>(sym); return hipSuccess; }
 hipError_t hipDeviceSynchronize();
 hipError_t hipHostFree(void*);
 hipError_t hipFuncSetAttribute(const void*, hipFuncAttribute, int);

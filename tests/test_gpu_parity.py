@@ -110,7 +110,7 @@ def test_fp64_ranks_and_solution_match_oracle(S, cfg, side):
     X, info = gpu_solve(F, B)
     if len(stable) == nd.L:
         Xo = O.apply_inverse(OF, P.rhs)
-        assert np.linalg.norm(X - Xo) <= 1e-10 * np.linalg.norm(Xo)
+        assert _col_err(X, Xo).max() <= 1e-10
     Xr, info = gpu_solve(F, B, tol=1e-10)
     assert info["converged"]
     assert rel_res(P, Xr).max() <= 1e-10
@@ -223,10 +223,22 @@ def test_error_paths(S):
     with pytest.raises(S.SpaluError) as e:
         S.Factor(nd, rp, torch.from_numpy(ix).cuda(), v, eps=1e-6)
     assert e.value.code == S.EUNSUPPORTED
-    # singular leaf block
+    # singular leaf block: reported at the leaf level L + 1
     with pytest.raises(S.SpaluError) as e:
         S.Factor(nd, rp, ci, torch.zeros_like(v), eps=1e-6)
     assert e.value.code == S.ESINGULAR
+    assert e.value.info["singular_level"] == nd.L + 1
+    # zero rows of one level-L separator: the leaves stay regular and the
+    # separator's diagonal block is zero when level L factors its segments
+    ptr, verts, flags, parent, pairs = nd.segments(nd.L)
+    c = int(np.nonzero(flags & 2)[0][0])
+    z = P.data.copy()
+    for r in verts[ptr[c]:ptr[c + 1]]:
+        z[P.indptr[r]:P.indptr[r + 1]] = 0.0
+    with pytest.raises(S.SpaluError) as e:
+        S.Factor(nd, rp, ci, torch.from_numpy(z).cuda(), eps=1e-6)
+    assert e.value.code == S.ESINGULAR
+    assert e.value.info["singular_level"] == nd.L
     # refinement that cannot converge
     F = S.Factor(nd, rp, ci, v, eps=1e-2)
     X, info = F.solve(B, tol=1e-30, max_iter=1)
@@ -250,3 +262,126 @@ def test_graph_replays_match_direct_launches(S):
         assert torch.equal(Xd, Xg)
         assert i1["iterations"] == i2["iterations"] == i3["iterations"]
         assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
+
+
+def _id_work(S):
+    """Algorithmic bytes per ID launch kind since profiling was switched on
+    (work is credited to the tier that took each segment)."""
+    prof = S.profile_read()
+    return {k: v["bytes"] for k, v in prof.items() if k.startswith("seg_id")}
+
+
+def _col_err(X, Y):
+    return np.linalg.norm(X - Y, axis=0) / np.linalg.norm(Y, axis=0)
+
+
+@pytest.mark.parametrize("cfg", [1, 4])
+def test_fp64_parity_where_the_wide_id_tiers_run(S, cfg):
+    """255 x 255 FP64: the eight-wave ID tier and the tier with its rows in
+    global scratch take segments (the kernels that dominate at full size);
+    sizes, ranks, samples and passes equal the oracle's on every level whose
+    decisions the oracle itself reproduces under a 1e-15 perturbation; the
+    direct solve equals the oracle's per column within 1e-10 when every
+    level is reproducible, and is otherwise as close to the exact solution
+    as the oracle's."""
+    print("case wide tiers fp64 cfg=%d" % cfg, flush=True)
+    P = make_config(cfg, side=255, nrhs=3)
+    S.profile(True)
+    nd, F, B = gpu_factor(S, P, eps=P.eps, seed=1234)
+    work = _id_work(S)
+    S.profile(False)
+    print("ID work by tier:", work)
+    assert work.get("seg_id_c", 0) > 0 and work.get("seg_id_b2", 0) > 0
+    OF = O.factor(nd_order(P.dims), P.scipy(), O.Opts(eps=P.eps, seed=1234))
+    ora = _oracle_ranks(OF, nd)
+    stable = oracle_stable_levels(P, nd, ora, P.eps)
+    print("levels reproducible in the oracle:", stable)
+    if cfg == 1:
+        assert len(stable) == nd.L
+    assert len(stable) >= 2     # Helmholtz: only the finest levels are reproducible
+    compare_ranks(nd, F.ranks(), ora, stable)
+    X, info = gpu_solve(F, B)
+    Xo = O.apply_inverse(OF, P.rhs)
+    if len(stable) == nd.L:
+        assert _col_err(X, Xo).max() <= 1e-10
+    else:
+        Xe = spla.spsolve(P.scipy().tocsc(), P.rhs)
+        assert np.all(_col_err(X, Xe) <= 2 * _col_err(Xo, Xe) + 1e-12)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_fp32_parity_where_the_wide_id_tiers_run(S, cfg):
+    """255 x 255 with FP32 storage (mixed form): the tier with its rows in
+    global scratch runs; on the finest levels (same sizes on both sides) the
+    ranks equal the FP64 oracle's for nearly every segment and differ by at
+    most one elsewhere (decisions at the threshold move with rounding); the
+    direct solve is as close to the exact solution as the oracle's, per
+    column, up to the FP32 storage rounding."""
+    print("case wide tiers fp32 cfg=%d" % cfg, flush=True)
+    P = make_config(cfg, side=255, nrhs=3)
+    S.profile(True)
+    nd, F, B = gpu_factor(S, P, eps=P.eps, seed=1234, precision=S.FP32)
+    work = _id_work(S)
+    S.profile(False)
+    print("ID work by tier:", work)
+    assert work.get("seg_id_c", 0) > 0
+    OF = O.factor(nd_order(P.dims), P.scipy(), O.Opts(eps=P.eps, seed=1234))
+    ora = _oracle_ranks(OF, nd)
+    nb, rk, hh, ps = F.ranks()
+    base = nd.seg_base()
+    nlev = 0
+    for lev in range(nd.L, 0, -1):
+        s = slice(base[lev], base[lev + 1])
+        if not np.array_equal(nb[s], ora[0][s]):
+            break
+        same = np.mean(rk[s] == ora[1][s])
+        print("level %d: rank agreement %.4f" % (lev, same))
+        assert same >= 0.97 and np.abs(rk[s] - ora[1][s]).max() <= 1
+        nlev += 1
+    assert nlev >= 3
+    X, info = gpu_solve(F, B)
+    Xo = O.apply_inverse(OF, P.rhs)
+    Xe = spla.spsolve(P.scipy().tocsc(), P.rhs)
+    e32, eo = _col_err(X, Xe), _col_err(Xo, Xe)
+    print("direct solve error vs exact: fp32 %s, oracle %s" % (e32, eo))
+    assert np.all(e32 <= 2 * eo + 1e-6)
+
+
+def test_3d_eps0_equals_dense_lu(S):
+    """15^3 7-point Laplacian, compression off: 343-vertex leaves (the
+    global-memory leaf kernel) and plane separators; the solve equals a
+    dense LU solve to 1e-12."""
+    print("case 3d eps0", flush=True)
+    P = make_config(3, side=15, nrhs=3)
+    nd, F, B = gpu_factor(S, P, eps=0.0)
+    X, info = gpu_solve(F, B)
+    Xe = np.linalg.solve(P.scipy().toarray(), P.rhs)
+    assert _col_err(X, Xe).max() <= 1e-12
+
+
+@pytest.mark.parametrize("side", [15, 31])
+def test_3d_fp64_ranks_and_solution_match_oracle(S, side):
+    """3D FP64 with compression: sizes, ranks, samples and passes equal the
+    oracle's on its reproducible levels, and the direct solve equals the
+    oracle's per column within 1e-10 when every level is reproducible; at
+    31^3 segments wider than 128 DOFs take the block-cooperative ID."""
+    print("case 3d parity side=%d" % side, flush=True)
+    P = make_config(3, side=side, nrhs=2)
+    S.profile(True)
+    nd, F, B = gpu_factor(S, P, eps=P.eps, seed=1234)
+    work = _id_work(S)
+    S.profile(False)
+    print("ID work by tier:", work)
+    if side == 31:
+        assert work.get("seg_id_blk", 0) > 0
+    OF = O.factor(nd_order(P.dims), P.scipy(), O.Opts(eps=P.eps, seed=1234))
+    ora = _oracle_ranks(OF, nd)
+    stable = oracle_stable_levels(P, nd, ora, P.eps)
+    print("levels reproducible in the oracle:", stable)
+    compare_ranks(nd, F.ranks(), ora, stable)
+    X, info = gpu_solve(F, B)
+    Xo = O.apply_inverse(OF, P.rhs)
+    if len(stable) == nd.L:
+        assert _col_err(X, Xo).max() <= 1e-10
+    Xr, info = gpu_solve(F, B, tol=1e-10)
+    assert info["converged"] and rel_res(P, Xr).max() <= 1e-10

@@ -77,3 +77,14 @@ def test_fp32_3d_global_leaf_path(exe, tmp_path):
     _write(P, str(tmp_path))
     it, first, final = _run(exe, str(tmp_path), 32, 0, 1e-4, 2, 1e-10, 8)
     assert final <= 1e-10
+
+
+def test_wide_id_tiers_fp64(exe, tmp_path):
+    """127 x 127 GRF diffusion in FP64: the stacked coupling rows of the
+    top-level segments exceed the LDS budgets, so the eight-wave tier and
+    the tier with its rows in global scratch run (their bounds checked here
+    on the CPU)."""
+    P = make_config(1, side=127, nrhs=1)
+    _write(P, str(tmp_path))
+    it, first, final = _run(exe, str(tmp_path), 64, 0, 1e-4, 2, 1e-10, 8)
+    assert final <= 1e-10
