@@ -236,6 +236,22 @@ int spalu_solve(const spalu_factor_t* f, int32_t nrhs, const double* B, int64_t 
                 int64_t ldx, const spalu_solve_opts* opts, void* workspace,
                 size_t workspace_bytes, void* stream, double* rel_res, spalu_solve_info* info);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): spalu_solve with its
+ * working memory in a static device buffer of the library instead of a
+ * caller workspace.  The buffer holds 64 MiB on each device the library runs
+ * on and is kept until the process ends; a solve whose working memory
+ * (spalu_solve_workspace) exceeds it fails with SPALU_ENOMEM.  The call
+ * allocates no device memory and launches directly (opts->graph is
+ * ignored); nothing in the buffer needs to start at zero, and it keeps the
+ * last call's contents.  Every call on one device shares that device's
+ * buffer: calls that overlap on one GPU (concurrent streams or threads)
+ * race and must be serialised by the caller.  Arguments, results and
+ * errors otherwise as spalu_solve. */
+int spalu_solve_static(const spalu_factor_t* f, int32_t nrhs, const double* B, int64_t ldb, double* X,
+                       int64_t ldx, const spalu_solve_opts* opts, void* stream, double* rel_res,
+                       spalu_solve_info* info);
+
 /* ---------------------------------------------------------------------------
  * Rank predictor training (FP32 HIP kernels).  Parameters (device floats):
  * mu[12], sd[12] (input standardisation, never trained), W1[64x12], b1[64],

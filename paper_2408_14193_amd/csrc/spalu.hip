@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -1521,6 +1522,34 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
 }  // namespace
 
 
+// Working memory of the allocation-free solve (spalu_solve_static): one
+// file-scope device array, which every GPU the library runs on holds until
+// the process ends.  In host code its name stands for the host-side shadow,
+// not a device address: kernels get the address that hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+constexpr size_t SPALU_STATIC_SOLVE_BYTES = size_t(64) << 20;
+static __device__ __align__(256) char scratch[SPALU_STATIC_SOLVE_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;  // device -> address of scratch there
+
+int scratch_on_device(char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(SPALU_EDEVICE, "hipGetSymbolAddress returned no address for the solve scratch");
+    it = g_scratch_ptr.emplace(dev, static_cast<char*>(p)).first;
+  }
+  *out = it->second;
+  return SPALU_OK;
+}
+}  // namespace
+
 // Host image of every table plus the leaf boundary lists, in pinned memory
 // so the upload of a factorization is two asynchronous copies.  Rebuilt only
 // when the near-field radius option changes.
@@ -2042,6 +2071,35 @@ int spalu_solve(const spalu_factor_t* f, int32_t nrhs, const double* B, int64_t 
   int rc = f->prec == SPALU_FP64
                ? run_solve<double>(f, nrhs, B, ldb, X, ldx, so, static_cast<char*>(workspace), rel_res, info)
                : run_solve<float>(f, nrhs, B, ldb, X, ldx, so, static_cast<char*>(workspace), rel_res, info);
+  F->stream = keep;
+  return rc;
+}
+
+int spalu_solve_static(const spalu_factor_t* f, int32_t nrhs, const double* B, int64_t ldb, double* X,
+                       int64_t ldx, const spalu_solve_opts* opts, void* stream, double* rel_res,
+                       spalu_solve_info* info) {
+  if (!f || !B || !X || nrhs < 1) return fail(SPALU_EINVAL, "bad argument");
+  if (ldb < f->n || ldx < f->n) return fail(SPALU_EINVAL, "leading dimension < n");
+  spalu_solve_opts so{0.0, 30, 0, 0};
+  if (opts) so = *opts;
+  so.graph = 0;  // direct launches: instantiating a graph may allocate
+  if (so.max_iter < 0) return fail(SPALU_EINVAL, "bad max_iter");
+  if (so.restart < 0 || so.restart > 32) return fail(SPALU_EINVAL, "restart must be in 0..32");
+  if (so.tol <= 0.0) so.restart = 0;
+  if (so.tol > 0.0 && X == B) return fail(SPALU_EINVAL, "refinement needs X != B");
+  const size_t need = solve_layout(f, nrhs, so.restart).bytes;
+  if (need > SPALU_STATIC_SOLVE_BYTES)
+    return fail(SPALU_ENOMEM, "solve needs " + std::to_string(need) + " bytes of working memory; the static "
+                "buffer of spalu_solve_static holds " + std::to_string(SPALU_STATIC_SOLVE_BYTES) +
+                " (use spalu_solve with a workspace)");
+  char* sw = nullptr;
+  const int src = scratch_on_device(&sw);
+  if (src) return src;
+  spalu_factor_t* F = const_cast<spalu_factor_t*>(f);
+  hipStream_t keep = F->stream;
+  F->stream = static_cast<hipStream_t>(stream);
+  int rc = f->prec == SPALU_FP64 ? run_solve<double>(f, nrhs, B, ldb, X, ldx, so, sw, rel_res, info)
+                                 : run_solve<float>(f, nrhs, B, ldb, X, ldx, so, sw, rel_res, info);
   F->stream = keep;
   return rc;
 }

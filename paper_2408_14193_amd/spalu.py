@@ -96,6 +96,8 @@ _lib.spalu_factor_free.restype = None
 _lib.spalu_solve_workspace.argtypes = [P, C.c_int32, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]
 _lib.spalu_solve.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64, C.POINTER(SolveOpts), P,
                              C.c_size_t, P, C.POINTER(C.c_double), C.POINTER(SolveInfo)]
+_lib.spalu_solve_static.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64, C.POINTER(SolveOpts), P,
+                                    C.POINTER(C.c_double), C.POINTER(SolveInfo)]
 
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double),
@@ -117,6 +119,7 @@ EXPORTED = ["spalu_nd_order", "spalu_nd_info", "spalu_nd_perm", "spalu_nd_etree"
             "spalu_nd_segments", "spalu_nd_free", "spalu_factor_opts_default",
             "spalu_factor_workspace", "spalu_factor_seg_base", "spalu_factor",
             "spalu_factor_ranks", "spalu_factor_work", "spalu_factor_free", "spalu_solve_workspace", "spalu_solve",
+            "spalu_solve_static",
             "spalu_mlp_param_count", "spalu_mlp_workspace", "spalu_mlp_forward",
             "spalu_mlp_train_step", "spalu_profile", "spalu_profile_only", "spalu_profile_read",
             "spalu_last_error"]
