@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (4 dispatches of a plain copy kernel), to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of a counter run")
+    ap.add_argument("--rho", type=float, default=0.5,
+                    help="near-field radius factor of the hybrid sampling (near: distance <= max(1, rho * span))")
     ap.add_argument("--restart", type=int, default=8,
                     help="refinement corrections by flexible GMRES(restart); 0: classical x += M r")
     return ap.parse_args()
@@ -58,7 +60,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8):
+def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8, rho=0.5):
     import numpy as np
     import torch
     prec = S.FP64 if form == "plain" else S.FP32
@@ -75,7 +77,7 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8)
 
     def step():
         t0 = time.perf_counter()
-        F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec, rank_model=model)
+        F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec, rank_model=model, rho=rho)
         t1 = time.perf_counter()
         info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(graph and form != "plain"), restart=restart)
         torch.cuda.synchronize()
@@ -227,7 +229,7 @@ def main():
     res = {}
     for i, f in enumerate(forms):
         res[f] = run_form(S, P, nd, dev, f, a.steps, a.warmup, profile=(i == 0), graph=not a.no_graph,
-                          restart=a.restart)
+                          restart=a.restart, rho=a.rho)
     head = forms[0]
     r = res[head]
     value = P.n / (r["ms_per_step"] * 1e-3)

@@ -135,6 +135,10 @@ typedef struct {
                             predictor features (training data)            */
   float rank_margin;     /* default 1.0                                     */
   int32_t rank_pad;      /* default 5 (the oversampling p of Section 4.2.3) */
+  float rank_skip;       /* learned form: a segment whose predicted rank n y
+                            is at least n - rank_skip is kept whole, without
+                            an ID (exact: only its compression is given up);
+                            0 = never; default 0.5                       */
 } spalu_factor_opts;
 
 typedef struct {

@@ -81,10 +81,13 @@ __host__ __device__ inline int id_tier_of_size(int n, int R, IdTiers t) {
   return 5;
 }
 
-// 0: no ID (identity), else the tier of the sizes.
-__device__ inline int id_tier(const DSeg& S, int n, int R, double eps, IdTiers t) {
-  const bool do_id = (S.flags & SEG_REGULAR) && (S.flags & SEG_HAS_NBR) && eps > 0.0 && n > 0;
+// 0: no ID (identity: no coupling rows, compression off, or a start sample
+// count below zero, which keeps the segment whole), else the tier of the
+// sizes.
+__device__ inline int id_tier(const DSeg& S, int n, int R, const IdParams& prm, int c, IdTiers t) {
+  const bool do_id = (S.flags & SEG_REGULAR) && (S.flags & SEG_HAS_NBR) && prm.eps > 0.0 && n > 0;
   if (!do_id || R == 0) return 0;
+  if (prm.h_init && prm.h_init[prm.seg_base + c] < 0) return 0;
   return id_tier_of_size(n, R, t);
 }
 
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   const int n = dyn.n[c];
   int R = 0;
   for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += 2 * dyn.n[nbrs[e].d];
-  const int tier = id_tier(S, n, R, prm.eps, tiers);
+  const int tier = id_tier(S, n, R, prm, c, tiers);
   int32_t* dofs = iarena + S.ioff;
   int32_t* perm_out = dofs + S.cap;
   if (TIER == 1 && tier == 0) {
@@ -766,7 +769,7 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
   const int n = dyn.n[c];
   int R = 0;
   for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += 2 * dyn.n[nbrs[e].d];
-  if (id_tier(S, n, R, prm.eps, tiers) != 5) return;
+  if (id_tier(S, n, R, prm, c, tiers) != 5) return;
   int32_t* dofs = iarena + S.ioff;
   int32_t* perm = dofs + S.cap;
   int32_t* tag = perm + 2 * S.cap;  // after piv

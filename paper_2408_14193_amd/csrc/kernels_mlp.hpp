@@ -162,7 +162,8 @@ __global__ __launch_bounds__(64) void k_features(const DSeg* segs, int nseg, con
 
 // BF16 inference: weights and activations rounded to bfloat16, products
 // accumulated in FP32; writes the start sample count of every regular
-// segment (0 for the others).  A group of MLP_G lanes per segment (16
+// segment (0 for the others, -1 for a segment predicted incompressible, which
+// the ID launches then keep whole).  A group of MLP_G lanes per segment (16
 // segments per block): lane l of a group forms hidden units 4l .. 4l+3 of
 // each layer from the transposed weights in LDS (conflict-free rows), the
 // group shares its activations through LDS, and its first lane sums the
@@ -172,7 +173,7 @@ constexpr int MLP_UPL = MLP_H / MLP_G;  // hidden units per lane
 
 __global__ __launch_bounds__(256) void k_mlp_rank(const float* feats, int nseg, const float* params,
                                                   const DSeg* segs, DLevelDyn dyn, float margin, int pad,
-                                                  int32_t* h_out) {
+                                                  float skip, int32_t* h_out) {
   constexpr int NGRP = 256 / MLP_G;
   __shared__ float sW[MLP_NPARAM];      // mu, sd, W1^T, b1, W2^T, b2, W3, b3 (BF16-rounded weights)
   __shared__ float sA[NGRP][2][MLP_H];  // per group: layer-1 and layer-2 activations
@@ -223,7 +224,9 @@ __global__ __launch_bounds__(256) void k_mlp_rank(const float* feats, int nseg, 
   const float y = 1.f / (1.f + expf(-z));
   const int n = dyn.n[c];
   const bool reg = (segs[c].flags & SEG_REGULAR) && (segs[c].flags & SEG_HAS_NBR);
-  h_out[c] = reg ? int(ceilf(margin * float(n) * y)) + pad : 0;
+  // predicted incompressible (rank n y within skip of n): kept whole, -1
+  const bool keep = skip > 0.f && float(n) * y >= float(n) - skip;
+  h_out[c] = !reg ? 0 : keep ? -1 : int(ceilf(margin * float(n) * y)) + pad;
 }
 
 // ---------------------------------------------------------------------------

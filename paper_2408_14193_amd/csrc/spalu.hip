@@ -1038,7 +1038,7 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       int32_t* hinit = reinterpret_cast<int32_t*>(ws + Y.o_hinit);
       const unsigned mblk = unsigned((nsv + WG / MLP_G - 1) / (WG / MLP_G));
       LAUNCH(K_MLP, lv, k_mlp_rank<<<mblk, WG, 0, st>>>(feats, nsv, o.rank_model, segv, dv, o.rank_margin,
-                                                          o.rank_pad, hinit + Y.seg_base[lv]));
+                                                          o.rank_pad, o.rank_skip, hinit + Y.seg_base[lv]));
     }
     return int(SPALU_OK);
   };
@@ -1699,6 +1699,7 @@ void spalu_factor_opts_default(spalu_factor_opts* o) {
   o->features_out = nullptr;
   o->rank_margin = 1.0f;
   o->rank_pad = 5;
+  o->rank_skip = 0.5f;
 }
 
 static const Layout* get_layout(const spalu_nd_t* nd, int prec) {
@@ -1751,7 +1752,7 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   if (opts) o = *opts;
   if (o.precision != SPALU_FP64 && o.precision != SPALU_FP32) return fail(SPALU_EINVAL, "bad precision");
   if (!(o.eps >= 0.0) || !(o.rho >= 0.0) || o.h0 < 1 || o.probes < 1 || o.probes > 8 || !(o.tau > 0.0) ||
-      !(o.rank_margin > 0.0f) || o.rank_pad < 1)
+      !(o.rank_margin > 0.0f) || o.rank_pad < 1 || !(o.rank_skip >= 0.0f))
     return fail(SPALU_EINVAL, "bad factor options");
   const Layout* Y;
   try {

@@ -46,7 +46,8 @@ class FactorOpts(C.Structure):
     _fields_ = [("eps", C.c_double), ("precision", C.c_int32), ("seed", C.c_uint32),
                 ("rho", C.c_double), ("h0", C.c_int32), ("probes", C.c_int32),
                 ("tau", C.c_double), ("h_init", C.c_void_p), ("rank_model", C.c_void_p),
-                ("features_out", C.c_void_p), ("rank_margin", C.c_float), ("rank_pad", C.c_int32)]
+                ("features_out", C.c_void_p), ("rank_margin", C.c_float), ("rank_pad", C.c_int32),
+                ("rank_skip", C.c_float)]
 
 
 class FactorInfo(C.Structure):
@@ -194,7 +195,8 @@ class ND:
 
 
 def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, tau=1.0,
-                h_init=None, rank_model=None, features_out=None, rank_margin=1.0, rank_pad=5):
+                h_init=None, rank_model=None, features_out=None, rank_margin=1.0, rank_pad=5,
+                rank_skip=0.5):
     o = FactorOpts()
     _lib.spalu_factor_opts_default(C.byref(o))
     o.eps, o.precision, o.seed, o.rho, o.h0, o.probes, o.tau = (
@@ -202,7 +204,7 @@ def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, ta
     o.h_init = None if h_init is None else int(h_init.data_ptr())
     o.rank_model = None if rank_model is None else int(rank_model.data_ptr())
     o.features_out = None if features_out is None else int(features_out.data_ptr())
-    o.rank_margin, o.rank_pad = float(rank_margin), int(rank_pad)
+    o.rank_margin, o.rank_pad, o.rank_skip = float(rank_margin), int(rank_pad), float(rank_skip)
     return o
 
 
@@ -217,7 +219,7 @@ class Factor:
 
     def __init__(self, nd, rowptr, colind, vals, eps=1e-6, precision=FP64, seed=1234, rho=0.5,
                  h0=8, probes=5, tau=1.0, h_init=None, rank_model=None, features_out=None,
-                 stream=None):
+                 stream=None, rank_skip=0.5):
         import torch
         assert rowptr.is_cuda and rowptr.dtype == torch.int64
         assert colind.is_cuda and colind.dtype == torch.int32
@@ -233,7 +235,7 @@ class Factor:
             assert features_out.is_cuda and features_out.dtype == torch.float32
             assert features_out.numel() >= nd.nsegments * 12
         self.opts = factor_opts(eps, precision, seed, rho, h0, probes, tau, h_init, rank_model,
-                                features_out)
+                                features_out, rank_skip=rank_skip)
         nbytes = factor_workspace_bytes(nd, self.opts)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=rowptr.device)
         s = torch.cuda.current_stream() if stream is None else stream

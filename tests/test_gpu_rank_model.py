@@ -151,8 +151,9 @@ def test_inference_start_samples_match_bf16_definition(S):
     """The device inference (weights and activations rounded to bfloat16,
     float32 sums in the plain loop order) against the same arithmetic
     written out here on the features the device computed: every segment's
-    first sample count ceil(margin n y) + pad, up to a rounding tie of the
-    sigmoid at a ceiling boundary."""
+    first sample count ceil(margin n y) + pad, and the segments kept whole
+    (predicted rank n y >= n - rank_skip), up to a rounding tie of the
+    sigmoid at a boundary."""
     import torch
     p, _, _ = _data(seed=3)
     P = make_config(1, side=127, nrhs=1)
@@ -168,6 +169,58 @@ def test_inference_start_samples_match_bf16_definition(S):
     assert sel.size > 100
     W1, W2 = _bf16(q["W1"]), _bf16(q["W2"])
     b1, b2, w3, b3 = _bf16(q["b1"]), _bf16(q["b2"]), _bf16(q["w3"]), _bf16(np.float32(q["b3"]))
+
+    def predict(f, q, s):
+        W1, W2 = _bf16(q["W1"]), _bf16(q["W2"])
+        b1, b2, w3, b3 = _bf16(q["b1"]), _bf16(q["b2"]), _bf16(q["w3"]), _bf16(np.float32(q["b3"]))
+        x = _bf16((f[s] - q["mu"]) / q["sd"])
+        a1 = np.empty(M.H, np.float32)
+        for o in range(M.H):
+            acc = b1[o]
+            for k in range(M.NF):
+                acc = _fma32(W1[o, k], x[k], acc)
+            a1[o] = _bf16(max(acc, np.float32(0)))
+        z = b3
+        for o in range(M.H):
+            acc = b2[o]
+            for k in range(M.H):
+                acc = _fma32(W2[o, k], a1[k], acc)
+            z = _fma32(w3[o], _bf16(max(acc, np.float32(0))), z)
+        return np.float32(1) / (np.float32(1) + np.exp(-z, dtype=np.float32))
+
+    # kept whole: exactly the regular, coupled segments whose predicted rank
+    # n y reaches n - rank_skip (up to a rounding tie of the sigmoid); with
+    # rank_skip 1 this network keeps some segments and not others
+    p2 = p.copy()
+    skip = np.float32(1.0)
+    feats2 = torch.zeros_like(feats)
+    F2 = S.Factor(nd, rp, ci, v, eps=P.eps, precision=S.FP32, rank_model=torch.from_numpy(p2).cuda(),
+                  features_out=feats2, rank_skip=float(skip))
+    nb2, rk2, hh2, ps2 = F2.ranks()
+    f2 = feats2.cpu().numpy().reshape(-1, M.NF)
+    q2 = M.unpack(p2)
+    base = nd.seg_base()
+    kept, ided, ties = 0, 0, 0
+    for lev in range(1, nd.L + 1):
+        ptr, verts, flags, parent, pairs = nd.segments(lev)
+        coupled = {int(a) for a, d in pairs if a != d}
+        for c in range(len(ptr) - 1):
+            s_ = base[lev] + c
+            if not (flags[c] & 1) or c not in coupled or nb2[s_] == 0 or f2[s_, 3] == 0.0:
+                continue
+            t = np.float32(nb2[s_]) * predict(f2, q2, s_) - (np.float32(nb2[s_]) - skip)
+            if abs(t) <= 1e-5 * nb2[s_]:
+                ties += 1
+                continue
+            if ps2[s_] == 0:
+                kept += 1
+                assert t >= 0, (lev, c)
+            else:
+                ided += 1
+                assert t < 0, (lev, c)
+    print("kept whole %d, through the ID %d, ties %d" % (kept, ided, ties))
+    assert kept > 100 and ided > 100
+
     diff, uncapped = [], []
     for s in sel:
         x = _bf16((f[s] - q["mu"]) / q["sd"])
@@ -195,3 +248,39 @@ def test_inference_start_samples_match_bf16_definition(S):
     assert np.mean(uncapped) >= 0.5  # most counts come from the prediction itself
     assert np.abs(diff).max() <= 1
     assert (diff == 0).mean() >= 0.99
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(os.path.dirname(os.path.dirname(__file__)),
+                                                    "paper_2408_14193_amd", "rank_model.npy")),
+                    reason="trained weights not present")
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_trained_predictor_keeps_incompressible_segments_whole(S, cfg):
+    """The learned form keeps a segment whole when its predicted rank is
+    within half a DOF of its size.  Against the same factorization with
+    every ID run (rank_skip 0): the kept segments are mostly ones the ID
+    leaves at full rank, the compression given up is at most a tenth of
+    what the IDs remove, the skipped work is most of the finest levels'
+    IDs, and the refined solution reaches the tolerance."""
+    from paper_2408_14193_amd import rank_model
+    P = make_config(cfg, side=255, nrhs=2)
+    nd = S.ND(P.dims)
+    rp, ci, v, B = to_device(P)
+    w = rank_model.load()
+    Fk = S.Factor(nd, rp, ci, v, eps=P.eps, precision=S.FP32, rank_model=w)
+    Fa = S.Factor(nd, rp, ci, v, eps=P.eps, precision=S.FP32, rank_model=w, rank_skip=0.0)
+    nk, rkk, hk, pk = Fk.ranks()
+    na, rka, ha, pa = Fa.ranks()
+    kept = (pk == 0) & (pa > 0)
+    full = rka[kept] == na[kept]
+    removed = (na - rka)[pa > 0].sum()          # DOFs the IDs remove when every ID runs
+    lost = (na - rka)[kept].sum()               # of those, in segments kept whole
+    print("kept whole %d of %d IDs; full rank in the run with every ID: %.4f; compression given up "
+          "%d of %d DOFs" % (kept.sum(), (pa > 0).sum(), full.mean(), lost, removed))
+    assert kept.sum() >= 0.3 * (pa > 0).sum()
+    assert full.mean() >= 0.9
+    assert lost <= 0.1 * removed
+    base = nd.seg_base()
+    finest = slice(base[nd.L], base[nd.L + 1])
+    assert kept[finest].sum() >= 0.9 * (pa[finest] > 0).sum()
+    X, info = Fk.solve(B, tol=P.tol, max_iter=40)
+    assert info["converged"] and rel_res(P, X.cpu().numpy()).max() <= P.tol
