@@ -7,15 +7,17 @@ iterative refinement to the workload's tolerance.  The matrix, right-hand
 sides and nested-dissection plan are resident before the timed region
 (nested dissection is a closed-form host step, timed and reported apart).
 
-Default workload: -div(a grad u) on the 1023 x 1023 interior grid, a =
-exp(Gaussian random field, correlation length 0.05, std 1), 16 right-hand
-sides uniform in [-1, 1], eps = 1e-4, refinement to 1e-10.  The headline
-`value` is the learned form: FP32 storage and products (FP64 pivoted LU of
-diagonal blocks, ID triangular solve and refinement residual), the solve
+Default workload: the non-symmetric convection-diffusion operator
+-0.01 Lap u + (1, 0.5) . grad u, first-order upwind, on the 2047 x 2047
+interior grid (N = 4,190,209), eps = 1e-5, 64 right-hand sides uniform in
+[-1, 1], refinement to 1e-8.  The headline `value` is the learned form:
+FP32 storage of the factor (FP64 arithmetic in the kernels, FP64 pivoted LU
+of diagonal blocks, ID triangular solve and refinement residual), the solve
 sweeps captured as a HIP graph, and the trained rank predictor choosing each
-segment's first sample count.  Beside it: the mixed form (the same without
-the predictor) and the plain form (FP64 everywhere, adaptive sampling,
-direct per-level launches).
+segment's first sample count or keeping a segment whole when it predicts no
+compression.  Beside it: the mixed form (the same without the predictor)
+and the plain form (FP64 storage, adaptive sampling, direct per-level
+launches).
 """
 from __future__ import annotations
 
@@ -30,7 +32,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
-FP32_PEAK_TFS = 157.3
 
 
 def parse():
@@ -38,7 +39,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--side", type=int, default=None)
     ap.add_argument("--nrhs", type=int, default=None)
     ap.add_argument("--forms", default="learned,mixed,plain")
@@ -168,7 +169,7 @@ def roofline(prof, form):
     fpl = st["flops"] / st["launches"]
     gbs = bpl / (avg_ms * 1e-3) / 1e9
     tfs = fpl / (avg_ms * 1e-3) / 1e12
-    peak_f = FP64_PEAK_TFS if form == "plain" else FP32_PEAK_TFS
+    peak_f = FP64_PEAK_TFS   # every form computes in FP64 (the mixed forms store FP32)
     return dict(kernel=name, bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 5), traffic=measured_traffic(name, form),
                 launches=st["launches"], avg_launch_ms=round(avg_ms, 4),
@@ -177,26 +178,44 @@ def roofline(prof, form):
                 share_of_step=None)
 
 
-def cpu_baseline(cfg, side):
-    """The FP64 oracle on a bounded sample of the same workload family."""
-    from threadpoolctl import threadpool_limits
+def host_cpu():
+    """Logical CPUs of this host and the processor model (lscpu)."""
+    import subprocess
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return os.cpu_count() or 1, model
+
+
+def cpu_baseline(cfg, side, nrhs=None):
+    """The FP64 oracle on a bounded sample of the same workload family, with
+    the BLAS thread pool on every host core (the oracle's loops are Python
+    and single-threaded; its dense products use the pool)."""
+    from threadpoolctl import threadpool_info
     from oracle import spalu as O
     from oracle.nd import nd_order
     from workloads import make_config
-    P = make_config(cfg, side=side)
+    P = make_config(cfg, side=side, nrhs=nrhs)
     nd = nd_order(P.dims)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        F = O.factor(nd, P.scipy(), O.Opts(eps=P.eps))
-        t1 = time.perf_counter()
-        x, it, hist = O.solve(F, P.rhs, tol=P.tol, max_iter=50)
-        t2 = time.perf_counter()
+    ncpu, model = host_cpu()
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    t0 = time.perf_counter()
+    F = O.factor(nd, P.scipy(), O.Opts(eps=P.eps))
+    t1 = time.perf_counter()
+    x, it, hist = O.solve(F, P.rhs, tol=P.tol, max_iter=50)
+    t2 = time.perf_counter()
     n = P.n
-    return dict(value=round(n / (t2 - t0), 2), unit="DOF/s", cores=1, kind="oracle",
+    return dict(value=round(n / (t2 - t0), 2), unit="DOF/s", cores=threads, kind="oracle",
+                host=dict(nproc=ncpu, model=model),
                 sample="%s %s (%d DOF), %d RHS, eps %g, FP64, refinement to %g: factor %.1f s, "
-                       "solve %.1f s (%d refinement steps, residual %.1e)"
-                       % (P.name, "x".join(map(str, P.dims)), n, P.nrhs, P.eps, P.tol,
-                          t1 - t0, t2 - t1, it, hist[-1].max()))
+                       "solve %.1f s (%d refinement steps, residual %.1e); BLAS threads %d of %d logical "
+                       "CPUs (%s)" % (P.name, "x".join(map(str, P.dims)), n, P.nrhs, P.eps, P.tol,
+                                      t1 - t0, t2 - t1, it, hist[-1].max(), threads, ncpu, model))
 
 
 def main():
@@ -248,7 +267,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp64" if head == "plain" else "fp32",
+        "dtype": "f64",
+        "storage": "f64" if head == "plain" else "f32",
         "data": "synthetic",
         "config": {"workload": "%s %s, N=%d, %d RHS, eps=%g, refinement to %g, %s form"
                                % (P.name, "x".join(map(str, P.dims)), P.n, P.nrhs, P.eps, P.tol, head),

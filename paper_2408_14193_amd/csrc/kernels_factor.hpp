@@ -449,6 +449,7 @@ __global__ void k_init_level(const DSeg* segs, int nseg, const int32_t* verts_pt
     dyn.h[c] = 0;
     dyn.passes[c] = 0;
     dyn.off[c] = 0;
+    dyn.nfar[c] = 0;
   }
 }
 
@@ -1150,6 +1151,7 @@ __global__ void k_merge_sizes(const DSeg* useg, int nuseg, const int32_t* cons_p
     udyn.h[C] = 0;
     udyn.passes[C] = 0;
     udyn.off[C] = 0;
+    udyn.nfar[C] = 0;
   }
 }
 

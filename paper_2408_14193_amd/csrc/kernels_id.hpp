@@ -214,6 +214,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
       dyn.nr[c] = 0;
       dyn.h[c] = 0;
       dyn.passes[c] = 0;
+      dyn.nfar[c] = 0;
     }
     return;
   }
@@ -651,6 +652,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
     dyn.nr[c] = n - k;
     dyn.h[c] = h < nF ? h : nF;
     dyn.passes[c] = passes;
+    dyn.nfar[c] = nF;
   }
 }
 
@@ -841,6 +843,7 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
       dyn.nr[c] = 0;
       dyn.h[c] = 0;
       dyn.passes[c] = 0;
+      dyn.nfar[c] = 0;
     }
     return;
   }
@@ -964,6 +967,7 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
     dyn.nr[c] = n - k;
     dyn.h[c] = h < nF ? h : nF;
     dyn.passes[c] = passes;
+    dyn.nfar[c] = nF;
   }
 }
 

@@ -88,6 +88,9 @@ struct DLevelDyn {
   int32_t* h;       // samples of the accepted pass
   int32_t* passes;  // ID passes
   int32_t* off;     // offset inside the parent segment (merge)
+  int32_t* nfar;    // far rows of the accepted ID (0 without an ID)
 };
+
+constexpr int DYN_ARRAYS = 7;  // int32 arrays of DLevelDyn, each one entry per segment
 
 }  // namespace spalu

@@ -533,7 +533,7 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
   Y.o_sepv = put(Y.sepv.size() * 4);
   Y.blob_bytes = o;
   // dynamic per-level arrays (6 ints per segment)
-  for (int l = 1; l <= L; ++l) Y.lv[l].o_dyn = put(6 * Y.lv[l].segs.size() * 4);
+  for (int l = 1; l <= L; ++l) Y.lv[l].o_dyn = put(DYN_ARRAYS * Y.lv[l].segs.size() * 4);
   Y.o_status = put(64);
   Y.o_feats = put(size_t(Y.nseg_total) * MLP_NF * 4);
   Y.o_hinit = put(size_t(Y.nseg_total) * 4);
@@ -558,6 +558,7 @@ DLevelDyn dyn_of(char* ws, const Layout& Y, int l) {
   d.h = base + 3 * ns;
   d.passes = base + 4 * ns;
   d.off = base + 5 * ns;
+  d.nfar = base + 6 * ns;
   return d;
 }
 
@@ -713,8 +714,11 @@ void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, 
         double R = 0.0;
         for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) R += 2.0 * dynv(l, 0, T.nbrs[e].d);
         if (id_tier_of_size(int(n), int(R), T.tiers) != 1 + (kid - K_ID)) continue;
+        // sketch G B_F of the far rows (none once h reaches them: exact rows),
+        // CPQR of the |N| + h stacked rows, T = R11^-1 R12
+        const double nf = dynv(l, 6, int(c)), nn = R - nf;
         by += R * n * vs + k * (n - k) * vs + n * 4.0;
-        fl += 2.0 * h * R * n + 4.0 * (R < h ? R : h) * n * k + k * k * (n - k);
+        fl += (h < nf ? 2.0 * h * nf * n : 0.0) + 4.0 * (nn + h) * n * k + k * k * (n - k);
       }
       break;
     }
@@ -885,7 +889,7 @@ void prof_account_pending() {
 int read_dyn_host(spalu_factor_t* F) {
   const Layout& Y = *F->lay;
   const int L = F->nd->plan.L;
-  const size_t lo = Y.lv[1].o_dyn, hi = Y.lv[L].o_dyn + 6 * Y.lv[L].segs.size() * 4;
+  const size_t lo = Y.lv[1].o_dyn, hi = Y.lv[L].o_dyn + DYN_ARRAYS * Y.lv[L].segs.size() * 4;
   if (!Y.dyn_pinned)
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&Y.dyn_pinned), std::max<size_t>(hi - lo, 1), hipHostMallocDefault));
   const char* raw = Y.dyn_pinned;
@@ -893,7 +897,7 @@ int read_dyn_host(spalu_factor_t* F) {
   HIPCHK(hipStreamSynchronize(F->stream));
   auto dh = std::make_shared<DynHost>(size_t(L) + 1);
   for (int l = 1; l <= L; ++l) {
-    (*dh)[l].resize(6 * Y.lv[l].segs.size());
+    (*dh)[l].resize(DYN_ARRAYS * Y.lv[l].segs.size());
     std::memcpy((*dh)[l].data(), raw + (Y.lv[l].o_dyn - lo), (*dh)[l].size() * 4);
   }
   F->dyn_host = dh;
@@ -1863,7 +1867,7 @@ int spalu_factor_ranks(const spalu_factor_t* f, int32_t* n_before, int32_t* rank
   HIPCHK(hipStreamSynchronize(f->stream));
   for (int l = 1; l <= f->nd->plan.L; ++l) {
     const size_t ns = Y.lv[l].segs.size();
-    std::vector<int32_t> dv(6 * ns);
+    std::vector<int32_t> dv(DYN_ARRAYS * ns);
     HIPCHK(hipMemcpy(dv.data(), f->ws + Y.lv[l].o_dyn, dv.size() * 4, hipMemcpyDeviceToHost));
     const size_t b = size_t(Y.seg_base[l]);
     for (size_t c = 0; c < ns; ++c) {
