@@ -1161,6 +1161,66 @@ __global__ void k_merge_sizes(const DSeg* useg, int nuseg, const int32_t* cons_p
 // With lds_bytes > 0, a task whose blocks fit keeps its kc x kd result in
 // LDS and stages both factors of every term there with batched loads;
 // otherwise the products read the factors from memory.
+// acc (kc x kd, row-major, FP64) -= A (kc x ks) B (ks x kd), A and B
+// row-major in LDS in the storage type: one separator term of the Schur
+// update (A_{c,s} U_s^{-1}) (L_s^{-1} A_{s,d}) on the matrix cores, in 16 x 16
+// output tiles dealt round-robin to the NW waves (a tile, and so each acc
+// element, always belongs to the same wave).  FP64 storage: FP64 16x16x4
+// MFMA.  FP32 storage (mixed form): FP32 16x16x4 MFMA with FP32
+// accumulation inside a term.  Lane l supplies A[i0 + l%16][k0 + l/16] and
+// B[k0 + l/16][j0 + l%16] (zero outside the matrices); its four results are
+// column j0 + l%16 of rows i0 + l/16 + 4r (FP64) or i0 + 4(l/16) + r (FP32).
+template <typename T, int NW>
+__device__ inline void schur_term_mfma(double* acc, const T* A, const T* B, int kc, int ks, int kd) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ntj = (kd + 15) >> 4, nt = ((kc + 15) >> 4) * ntj;
+  for (int tile = w; tile < nt; tile += NW) {
+    const int i0 = (tile / ntj) * 16, j0 = (tile % ntj) * 16;
+    const int ar = i0 + li, bc = j0 + li;
+    const bool arow = ar < kc, bcol = bc < kd;
+    if constexpr (sizeof(T) == 8) {
+      typedef double v4 __attribute__((ext_vector_type(4)));
+      v4 d;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + lk + 4 * r;
+        d[r] = row < kc && bcol ? acc[row * kd + bc] : 0.0;
+      }
+      for (int k0 = 0; k0 < ks; k0 += 4) {
+        const int k = k0 + lk;
+        const double a = arow && k < ks ? -double(A[ar * ks + k]) : 0.0;
+        const double b = bcol && k < ks ? double(B[k * kd + bc]) : 0.0;
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + lk + 4 * r;
+        if (row < kc && bcol) acc[row * kd + bc] = d[r];
+      }
+    } else {
+      typedef float v4 __attribute__((ext_vector_type(4)));
+      v4 d;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + 4 * lk + r;
+        d[r] = row < kc && bcol ? float(acc[row * kd + bc]) : 0.0f;
+      }
+      for (int k0 = 0; k0 < ks; k0 += 4) {
+        const int k = k0 + lk;
+        const float a = arow && k < ks ? -float(A[ar * ks + k]) : 0.0f;
+        const float b = bcol && k < ks ? float(B[k * kd + bc]) : 0.0f;
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + 4 * lk + r;
+        if (row < kc && bcol) acc[row * kd + bc] = double(d[r]);
+      }
+    }
+  }
+}
+
 template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk, const int32_t* task_ptr,
                                                    const DTask* tasks, const DSepTerm* terms,
@@ -1189,7 +1249,7 @@ __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk,
     const bool staged = lds_bytes > 0 && tk.sep_end > tk.sep_begin &&
                         acc_bytes + (kc + kd) * ksmax * int(sizeof(T)) <= lds_bytes;
     if (staged) {
-      double* acc = lds;  // kc x kd, element t touched by thread t % NT only
+      double* acc = lds;  // kc x kd
       T* sA = reinterpret_cast<T*>(reinterpret_cast<char*>(lds) + acc_bytes);
       if (tk.src == -2 || !src)
         for (int t = tid; t < kc * kd; t += NT) acc[t] = tk.src == -2 && t / kd == t % kd ? 1.0 : 0.0;
@@ -1203,19 +1263,9 @@ __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk,
         stage_batched<8>(varena + blks[st.blk_cs].soff, kc * ks, tid, NT, [&](int t, T v) { sA[t] = v; });
         stage_batched<8>(varena + blks[st.blk_sd].soff, ks * kd, tid, NT, [&](int t, T v) { sB[t] = v; });
         __syncthreads();
-        for (int t = tid; t < kc * kd; t += NT) {
-          const int i = t / kd, j = t - i * kd;
-          const T* ar = sA + i * ks;
-          double s0 = 0.0, s1 = 0.0;
-          int u = 0;
-          for (; u + 1 < ks; u += 2) {
-            s0 += double(ar[u]) * double(sB[u * kd + j]);
-            s1 += double(ar[u + 1]) * double(sB[(u + 1) * kd + j]);
-          }
-          if (u < ks) s0 += double(ar[u]) * double(sB[u * kd + j]);
-          acc[t] -= s0 + s1;
-        }
+        schur_term_mfma<T, NT / 64>(acc, sA, sB, kc, ks, kd);
       }
+      __syncthreads();  // acc tiles were written by their waves
       for (int t = tid; t < kc * kd; t += NT) {
         const int i = t / kd, j = t - i * kd;
         out[size_t(oc + i) * nD + od + j] = T(acc[t]);

@@ -193,7 +193,8 @@ constexpr size_t ID_B2_MAX_BYTES = 152 * 1024;  // tier-B2 groups: one per CU
 constexpr size_t SEGLU_MAX_BYTES = 152 * 1024;   // segment LU of large segments
 constexpr int SEGLU_WAVE_MAX_N = 32;             // segments up to this size: one wave each
 constexpr int SEGLU_BLOCK_NT = 256;              // threads of the block segment LU (one block per CU)
-constexpr size_t MELIM_LDS_BYTES = 64 * 1024;   // staged separator terms of the merge
+constexpr size_t MELIM_LDS_BYTES = 64 * 1024;   // staged separator terms of the merge (at least)
+constexpr size_t MELIM_MAX_BYTES = 152 * 1024;  // (at most: one group per CU)
 
 // Which ID launches a level needs and their LDS budgets.  The sizes known
 // here (uncompressed n, coupling-row bound rcap) bound the ones the kernels
@@ -1181,11 +1182,20 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
             tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
             tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du, lb));
       }
-      else
-        LAUNCH(K_MELIM, l, k_merge_elim<T, WG><<<unsigned(U.blks.size()), WG, MELIM_LDS_BYTES, st>>>(
+      else {
+        // LDS for the level's largest task (accumulator and the two factors
+        // of a term), at most one group per CU
+        static const bool melim_lds_ok =
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_merge_elim<T, WG>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, int(MELIM_MAX_BYTES)) == hipSuccess;
+        if (!melim_lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the merge kernel");
+        const size_t cap = size_t(T_.max_cap);
+        const size_t need = ((cap * cap * 8 + 15) & ~size_t(15)) + 2 * cap * cap * sizeof(T);
+        const size_t lb = std::min(MELIM_MAX_BYTES, std::max(MELIM_LDS_BYTES, need));
+        LAUNCH(K_MELIM, l, k_merge_elim<T, WG><<<unsigned(U.blks.size()), WG, lb, st>>>(
             tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
-            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du,
-            int(MELIM_LDS_BYTES)));
+            tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du, int(lb)));
+      }
     }
   }
   HIPCHK(hipMemcpyAsync(status_host, status, 8, hipMemcpyDeviceToHost, st));

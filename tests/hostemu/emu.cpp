@@ -117,6 +117,27 @@ d4 mfma_f64_16x16x4(double a, double b, d4 c) {
   return d;
 }
 
+// f32 16x16x4: same operand layout as the f64 form; lane l, register r of
+// the result is row 4 (l / 16) + r, column l % 16 (the f64 form interleaves
+// the rows, l / 16 + 4 r), as measured on gfx950.  Products and sums in
+// float, k in order.
+f4 mfma_f32_16x16x4(float a, float b, f4 c) {
+  const int t = g->cur, base = t & ~63, l = t & 63;
+  g->xd[t] = a;
+  g->xb[t] = b;
+  wave_barrier();
+  f4 d = c;
+  const int j = l % 16;
+  for (int r = 0; r < 4; ++r) {
+    const int i = 4 * (l / 16) + r;
+    float s = 0.0f;
+    for (int k = 0; k < 4; ++k) s += float(g->xd[base + i + 16 * k]) * float(g->xb[base + j + 16 * k]);
+    d[r] += s;
+  }
+  wave_barrier();
+  return d;
+}
+
 static void run_block(int nt, size_t shmem, const std::function<void()>& body) {
   Blk b;
   b.nt = nt;

@@ -53,7 +53,9 @@ void run_grid(dim3 g, dim3 b, size_t shmem, const std::function<void()>& body);
 bool capturing();
 void record(std::function<void()> f);
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 d4 mfma_f64_16x16x4(double a, double b, d4 c);
+f4 mfma_f32_16x16x4(float a, float b, f4 c);
 
 template <typename K>
 struct Launch {
@@ -109,6 +111,9 @@ inline int atomicOr(int* p, int v) { int o = *p; *p |= v; return o; }
 inline int atomicMax(int* p, int v) { int o = *p; if (v > o) *p = v; return o; }
 inline emu::d4 emu_amdgcn_mfma_f64_16x16x4f64(double a, double b, emu::d4 c, int, int, int) {
   return emu::mfma_f64_16x16x4(a, b, c);
+}
+inline emu::f4 emu_amdgcn_mfma_f32_16x16x4f32(float a, float b, emu::f4 c, int, int, int) {
+  return emu::mfma_f32_16x16x4(a, b, c);
 }
 
 // ---- runtime API ----

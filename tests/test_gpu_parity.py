@@ -67,11 +67,12 @@ def _oracle_ranks(OF, nd_gpu):
     return nb, rk, hh, ps, mg
 
 
-def oracle_stable_levels(P, nd, ora, eps):
+def oracle_stable_levels(P, nd, ora, eps, want_factor=False):
     """Levels (finest first) on which the oracle's rank decisions survive a
     1e-15 relative perturbation of A: a decision that flips under rounding
     noise has no unique answer, so the GPU path is only held to the oracle
-    where the oracle itself is reproducible."""
+    where the oracle itself is reproducible.  With want_factor, also the
+    oracle factorization of the perturbed matrix."""
     A2 = P.scipy().copy()
     A2.data = A2.data * (1.0 + 1e-15 * np.random.default_rng(0).standard_normal(A2.nnz))
     OF2 = O.factor(nd_order(P.dims), A2, O.Opts(eps=eps, seed=1234))
@@ -83,7 +84,14 @@ def oracle_stable_levels(P, nd, ora, eps):
         if not all(np.array_equal(a[s], b[s]) for a, b in zip(ora[:4], p[:4])):
             break
         stable.append(lev)
-    return stable
+    return (stable, OF2) if want_factor else stable
+
+
+def _backward(A, X, Bm):
+    """Normwise backward error ||b - A x|| / (||A||_2 ||x||) per column."""
+    import scipy.sparse.linalg as sla_
+    nA = np.sqrt(sla_.eigsh((A.T @ A).tocsc(), k=1, return_eigenvectors=False)[0])
+    return np.linalg.norm(Bm - A @ X, axis=0) / (nA * np.linalg.norm(X, axis=0))
 
 
 def compare_ranks(nd, gpu, ora, levels):
@@ -282,8 +290,8 @@ def test_fp64_parity_where_the_wide_id_tiers_run(S, cfg):
     sizes, ranks, samples and passes equal the oracle's on every level whose
     decisions the oracle itself reproduces under a 1e-15 perturbation; the
     direct solve equals the oracle's per column within 1e-10 when every
-    level is reproducible, and is otherwise as close to the exact solution
-    as the oracle's."""
+    level is reproducible, and otherwise has a backward error within twice
+    what the oracle reaches itself with and without that perturbation."""
     print("case wide tiers fp64 cfg=%d" % cfg, flush=True)
     P = make_config(cfg, side=255, nrhs=3)
     S.profile(True)
@@ -294,7 +302,7 @@ def test_fp64_parity_where_the_wide_id_tiers_run(S, cfg):
     assert work.get("seg_id_c", 0) > 0 and work.get("seg_id_b2", 0) > 0
     OF = O.factor(nd_order(P.dims), P.scipy(), O.Opts(eps=P.eps, seed=1234))
     ora = _oracle_ranks(OF, nd)
-    stable = oracle_stable_levels(P, nd, ora, P.eps)
+    stable, OF2 = oracle_stable_levels(P, nd, ora, P.eps, want_factor=True)
     print("levels reproducible in the oracle:", stable)
     if cfg == 1:
         assert len(stable) == nd.L
@@ -305,16 +313,24 @@ def test_fp64_parity_where_the_wide_id_tiers_run(S, cfg):
     if len(stable) == nd.L:
         assert _col_err(X, Xo).max() <= 1e-10
     else:
-        Xe = spla.spsolve(P.scipy().tocsc(), P.rhs)
-        assert np.all(_col_err(X, Xe) <= 2 * _col_err(Xo, Xe) + 1e-12)
+        # below the reproducible levels the oracle's own result moves under a
+        # 1e-15 perturbation of A (at 255^2 Helmholtz its error vs the exact
+        # solution changes 2-3x, its backward error from 6-8 to 7-15 eps):
+        # the GPU's backward error stays within twice the oracle's spread
+        A = P.scipy()
+        bo = np.maximum(_backward(A, Xo, P.rhs), _backward(A, O.apply_inverse(OF2, P.rhs), P.rhs))
+        bg = _backward(A, X, P.rhs)
+        print("backward error / eps: gpu %s, oracle (max of plain and perturbed) %s" % (bg / P.eps, bo / P.eps))
+        assert np.all(bg <= 2 * bo)
 
 
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_fp32_parity_where_the_wide_id_tiers_run(S, cfg):
     """255 x 255 with FP32 storage (mixed form): the tier with its rows in
     global scratch runs; on the finest levels (same sizes on both sides) the
-    ranks equal the FP64 oracle's for nearly every segment and differ by at
-    most one elsewhere (decisions at the threshold move with rounding); the
+    ranks equal the FP64 oracle's except on at most 3% of a level's segments
+    (or one), where they differ by one (decisions at the threshold move with
+    the FP32 arithmetic of the mixed form); the
     direct solve is as close to the exact solution as the oracle's, per
     column, up to the FP32 storage rounding."""
     print("case wide tiers fp32 cfg=%d" % cfg, flush=True)
@@ -334,9 +350,10 @@ def test_fp32_parity_where_the_wide_id_tiers_run(S, cfg):
         s = slice(base[lev], base[lev + 1])
         if not np.array_equal(nb[s], ora[0][s]):
             break
-        same = np.mean(rk[s] == ora[1][s])
-        print("level %d: rank agreement %.4f" % (lev, same))
-        assert same >= 0.97 and np.abs(rk[s] - ora[1][s]).max() <= 1
+        differ = int((rk[s] != ora[1][s]).sum())
+        print("level %d: ranks differ on %d of %d segments" % (lev, differ, base[lev + 1] - base[lev]))
+        assert differ <= max(1, 0.03 * (base[lev + 1] - base[lev]))
+        assert np.abs(rk[s] - ora[1][s]).max() <= 1
         nlev += 1
     assert nlev >= 3
     X, info = gpu_solve(F, B)
