@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (4 dispatches of a plain copy kernel), to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of a counter run")
+    ap.add_argument("--eps", type=float, default=None, help="override the workload's ID tolerance")
     ap.add_argument("--rho", type=float, default=0.5,
                     help="near-field radius factor of the hybrid sampling (near: distance <= max(1, rho * span))")
     ap.add_argument("--restart", type=int, default=8,
@@ -239,6 +240,8 @@ def main():
     from paper_2408_14193_amd import spalu as S
     from workloads import make_config
     P = make_config(a.config, side=a.side, nrhs=a.nrhs)
+    if a.eps is not None:
+        P.eps = a.eps
     t0 = time.perf_counter()
     nd = S.ND(P.dims)
     t_nd = time.perf_counter() - t0

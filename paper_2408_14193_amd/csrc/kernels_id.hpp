@@ -13,8 +13,10 @@
 //   A  NW = 1,  Y and row table in LDS (fine levels: thousands of segments)
 //   B  NW = 4,  Y and row table in LDS (middle levels), two groups per CU
 //   B2 the same kernel with up to 152 KB of LDS, one group per CU
-//   C  NW = 8,  Y and row table in the segment's global scratch (top levels,
-//      a few segments whose coupling rows exceed the LDS)
+//   C  NW = 8,  the far rows and the row table in the segment's global
+//      scratch (top levels, a few segments whose coupling rows exceed the
+//      LDS); Y, the m = |N| + h rows of a pass, in LDS when they fit there,
+//      else in global scratch too
 // Segments wider than 128 columns take the block-cooperative kernel
 // k_seg_id.  Every tier computes the same tier function, so each segment is
 // handled by exactly one launch; tier A also writes the identity result of
@@ -69,6 +71,7 @@ struct IdTiers {
   int budget_b;   // LDS bytes of the tier-B launch (two groups per CU)
   int budget_b2;  // LDS bytes of the tier-B2 launch (one group per CU)
   int st;         // bytes of the storage type
+  int lds_c;      // LDS bytes of the tier-C launch (Y of the passes that fit)
 };
 
 // Tier of a segment that gets an ID, from its sizes (n columns, R rows):
@@ -185,6 +188,127 @@ __device__ inline double idc_rowaxpy(double* Y, int n, int i0, int m, int col, i
   return t;
 }
 
+// Row table of the stacked coupling matrix of segment c, built by one wave:
+// rows[r] (block offset, column stride, vertex and half) for r < R, and
+// order[]: the near rows from the front, the far rows from the back (far row
+// f is order[R - 1 - f]); s_cnt receives (|N|, |F|).  The near field is the
+// neighbour DOFs within Chebyshev distance S.thr of the segment's box.
+__device__ inline void idc_row_table(const DSeg& S, const DSeg* segs, const DNbr* nbrs, const DBlk* blks,
+                                     GridGeom g, const int32_t* iarena, const DLevelDyn& dyn, int n, int R,
+                                     IdRow* rows, int* order, int* s_cnt) {
+  const int lane = threadIdx.x & 63;
+  int nN = 0, nF = 0, r0 = 0;
+  const int nnb = S.nbr_end - S.nbr_begin;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  if (nnb <= 64) {
+    // neighbour e = lane: its size, DOF list and block offsets, loaded
+    // together; its rows start at rs (exclusive prefix sum of 2 n_d).
+    // Row r of the table (neighbour, half, index) is then found by each
+    // lane from these, so the whole table costs one more trip to memory
+    int nd_l = 0;
+    int64_t io_l = 0, o0_l = 0, o1_l = 0;
+    if (lane < nnb) {
+      const DNbr nb = nbrs[S.nbr_begin + lane];
+      nd_l = dyn.n[nb.d];
+      io_l = segs[nb.d].ioff;
+      o0_l = blks[nb.blk_dc].off;
+      o1_l = blks[nb.blk_cd].off;
+    }
+    int rs = 2 * nd_l;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(rs, o, 64);
+      if (lane >= o) rs += t;
+    }
+    rs -= 2 * nd_l;
+    for (int rb = 0; rb < R; rb += 64) {
+      const int r = rb + lane;
+      const bool valid = r < R;
+      int owner = 0;  // the last neighbour whose rows start at or before r
+      for (int q = 1; q < nnb; ++q)
+        if (r >= __shfl(rs, q, 64)) owner = q;
+      const int nd = __shfl(nd_l, owner, 64), rr = r - __shfl(rs, owner, 64);
+      const int half = rr >= nd ? 1 : 0, i = rr - half * nd;
+      const int64_t io = shfl_i64(io_l, owner), off0 = shfl_i64(o0_l, owner), off1 = shfl_i64(o1_l, owner);
+      int v = 0;
+      bool near = false;
+      if (valid) {
+        v = iarena[io + i];
+        int cv[3];
+        vcoords(g, v, cv);
+        int dist = 0;
+        for (int a = 0; a < 3; ++a) {
+          int da = S.lo[a] - cv[a];
+          if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
+          if (da > dist) dist = da;
+        }
+        near = dist <= S.thr;
+      }
+      const uint64_t mn = __ballot(valid && near), mf = __ballot(valid && !near);
+      if (valid) {
+        IdRow m;
+        m.base = half == 0 ? off0 + int64_t(i) * n : off1 + i;
+        m.stride = half == 0 ? 1 : nd;
+        m.vh = 2 * v + half;
+        rows[r] = m;
+        if (near)
+          order[nN + __popcll(mn & below)] = r;
+        else
+          order[R - 1 - (nF + __popcll(mf & below))] = r;
+      }
+      nN += __popcll(mn);
+      nF += __popcll(mf);
+    }
+  } else {
+    for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+      const DNbr nb = nbrs[e];
+      const int nd = dyn.n[nb.d];
+      const int32_t* dd = iarena + segs[nb.d].ioff;
+      const int64_t off0 = blks[nb.blk_dc].off, off1 = blks[nb.blk_cd].off;
+      for (int half = 0; half < 2; ++half) {
+        for (int i0 = 0; i0 < nd; i0 += 64) {
+          const int i = i0 + lane;
+          const bool valid = i < nd;
+          int v = 0;
+          bool near = false;
+          if (valid) {
+            v = dd[i];
+            int cv[3];
+            vcoords(g, v, cv);
+            int dist = 0;
+            for (int a = 0; a < 3; ++a) {
+              int da = S.lo[a] - cv[a];
+              if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
+              if (da > dist) dist = da;
+            }
+            near = dist <= S.thr;
+          }
+          const uint64_t mn = __ballot(valid && near), mf = __ballot(valid && !near);
+          if (valid) {
+            const int r = r0 + half * nd + i;
+            IdRow m;
+            m.base = half == 0 ? off0 + int64_t(i) * n : off1 + i;
+            m.stride = half == 0 ? 1 : nd;
+            m.vh = 2 * v + half;
+            rows[r] = m;
+            if (near)
+              order[nN + __popcll(mn & below)] = r;
+            else
+              order[R - 1 - (nF + __popcll(mf & below))] = r;
+          }
+          nN += __popcll(mn);
+          nF += __popcll(mf);
+        }
+      }
+      r0 += 2 * nd;
+    }
+  }
+  if (lane == 0) {
+    s_cnt[0] = nN;
+    s_cnt[1] = nF;
+  }
+}
+
 template <typename T, int NW, int NCOL, bool YG, int TIER>
 __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int nseg, const DNbr* nbrs,
                                                          const DBlk* blks, GridGeom g, int32_t* iarena,
@@ -223,13 +347,15 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   // ---- memory carve-up ----
   char* sp = smem;
   double* Y;
+  double* Yg = nullptr;  // tier C: room for all R rows of Y in global scratch
   IdRow* rows;
   int* order;
   T* BF;  // far rows, row-major (ld n), in the storage type
   if constexpr (YG) {
-    Y = scratch + S.scr_off;
-    BF = reinterpret_cast<T*>(Y + size_t(R) * n);
-    rows = reinterpret_cast<IdRow*>(Y + 2 * size_t(R) * n);
+    Yg = scratch + S.scr_off;
+    Y = Yg;
+    BF = reinterpret_cast<T*>(Yg + size_t(R) * n);
+    rows = reinterpret_cast<IdRow*>(Yg + 2 * size_t(R) * n);
     order = reinterpret_cast<int*>(rows + R);
   } else {
     Y = reinterpret_cast<double*>(sp);
@@ -253,120 +379,20 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   }
   int* pos2col = reinterpret_cast<int*>(sp);
   int* col2pos = pos2col + n;
-
-  // ---- 1. row table: near rows listed from the front, far rows from the back ----
-  if (w == 0) {
-    int nN = 0, nF = 0, r0 = 0;
-    const int nnb = S.nbr_end - S.nbr_begin;
-    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    if (nnb <= 64) {
-      // neighbour e = lane: its size, DOF list and block offsets, loaded
-      // together; its rows start at rs (exclusive prefix sum of 2 n_d).
-      // Row r of the table (neighbour, half, index) is then found by each
-      // lane from these, so the whole table costs one more trip to memory
-      int nd_l = 0;
-      int64_t io_l = 0, o0_l = 0, o1_l = 0;
-      if (lane < nnb) {
-        const DNbr nb = nbrs[S.nbr_begin + lane];
-        nd_l = dyn.n[nb.d];
-        io_l = segs[nb.d].ioff;
-        o0_l = blks[nb.blk_dc].off;
-        o1_l = blks[nb.blk_cd].off;
-      }
-      int rs = 2 * nd_l;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(rs, o, 64);
-        if (lane >= o) rs += t;
-      }
-      rs -= 2 * nd_l;
-      for (int rb = 0; rb < R; rb += 64) {
-        const int r = rb + lane;
-        const bool valid = r < R;
-        int owner = 0;  // the last neighbour whose rows start at or before r
-        for (int q = 1; q < nnb; ++q)
-          if (r >= __shfl(rs, q, 64)) owner = q;
-        const int nd = __shfl(nd_l, owner, 64), rr = r - __shfl(rs, owner, 64);
-        const int half = rr >= nd ? 1 : 0, i = rr - half * nd;
-        const int64_t io = shfl_i64(io_l, owner), off0 = shfl_i64(o0_l, owner), off1 = shfl_i64(o1_l, owner);
-        int v = 0;
-        bool near = false;
-        if (valid) {
-          v = iarena[io + i];
-          int cv[3];
-          vcoords(g, v, cv);
-          int dist = 0;
-          for (int a = 0; a < 3; ++a) {
-            int da = S.lo[a] - cv[a];
-            if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
-            if (da > dist) dist = da;
-          }
-          near = dist <= S.thr;
-        }
-        const uint64_t mn = __ballot(valid && near), mf = __ballot(valid && !near);
-        if (valid) {
-          IdRow m;
-          m.base = half == 0 ? off0 + int64_t(i) * n : off1 + i;
-          m.stride = half == 0 ? 1 : nd;
-          m.vh = 2 * v + half;
-          rows[r] = m;
-          if (near)
-            order[nN + __popcll(mn & below)] = r;
-          else
-            order[R - 1 - (nF + __popcll(mf & below))] = r;
-        }
-        nN += __popcll(mn);
-        nF += __popcll(mf);
-      }
-    } else {
-      for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
-        const DNbr nb = nbrs[e];
-        const int nd = dyn.n[nb.d];
-        const int32_t* dd = iarena + segs[nb.d].ioff;
-        const int64_t off0 = blks[nb.blk_dc].off, off1 = blks[nb.blk_cd].off;
-        for (int half = 0; half < 2; ++half) {
-          for (int i0 = 0; i0 < nd; i0 += 64) {
-            const int i = i0 + lane;
-            const bool valid = i < nd;
-            int v = 0;
-            bool near = false;
-            if (valid) {
-              v = dd[i];
-              int cv[3];
-              vcoords(g, v, cv);
-              int dist = 0;
-              for (int a = 0; a < 3; ++a) {
-                int da = S.lo[a] - cv[a];
-                if (cv[a] - S.hi[a] > da) da = cv[a] - S.hi[a];
-                if (da > dist) dist = da;
-              }
-              near = dist <= S.thr;
-            }
-            const uint64_t mn = __ballot(valid && near), mf = __ballot(valid && !near);
-            if (valid) {
-              const int r = r0 + half * nd + i;
-              IdRow m;
-              m.base = half == 0 ? off0 + int64_t(i) * n : off1 + i;
-              m.stride = half == 0 ? 1 : nd;
-              m.vh = 2 * v + half;
-              rows[r] = m;
-              if (near)
-                order[nN + __popcll(mn & below)] = r;
-              else
-                order[R - 1 - (nF + __popcll(mf & below))] = r;
-            }
-            nN += __popcll(mn);
-            nF += __popcll(mf);
-          }
-        }
-        r0 += 2 * nd;
-      }
-    }
-    if (lane == 0) {
-      s_cnt[0] = nN;
-      s_cnt[1] = nF;
+  // tier C: the rest of the launch's LDS holds Y in the passes whose m rows
+  // fit (m <= ylds_rows), the others use Yg
+  double* Ylds = nullptr;
+  int ylds_rows = 0;
+  if constexpr (YG) {
+    const size_t used = (size_t(reinterpret_cast<char*>(col2pos + n) - smem) + 15) & ~size_t(15);
+    if (size_t(tiers.lds_c) > used + size_t(n) * 8) {
+      Ylds = reinterpret_cast<double*>(smem + used);
+      ylds_rows = int((size_t(tiers.lds_c) - used) / (size_t(n) * 8));
     }
   }
+
+  // ---- 1. row table: near rows listed from the front, far rows from the back ----
+  if (w == 0) idc_row_table(S, segs, nbrs, blks, g, iarena, dyn, n, R, rows, order, s_cnt);
   __syncthreads();
   const int nN = s_cnt[0], nF = s_cnt[1];
 
@@ -382,6 +408,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
     ++passes;
     const bool sampled = h < nF;
     const int m = nN + (sampled ? h : nF);
+    if constexpr (YG) Y = m <= ylds_rows ? Ylds : Yg;
     // ---- 2. Y = [B_N; G B_F / sqrt(h)] or the exact far rows; B_F is
     //         fetched once and kept for later passes ----
     idc_fetch<T, NT>(varena, rows, order, R, nN, passes == 1 ? R : nN, Y, BF, n);

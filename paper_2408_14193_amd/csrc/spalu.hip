@@ -235,6 +235,7 @@ void plan_id_tiers(LevelTabs& T, int st) {
   T.tiers.budget_a = int(std::max(a, idc_lds_bytes(1, 1, 1, 2, st, true)));
   T.tiers.budget_b = int(std::max(b, idc_lds_bytes(ID_B_WAVES, 2, 1, 2, st, true)));
   T.tiers.budget_b2 = int(std::max(b2, idc_lds_bytes(ID_B2_WAVES, 2, 1, 2, st, true)));
+  T.tiers.lds_c = int(ID_B2_MAX_BYTES);
   T.id_b = beyond_a;
   T.id_b2 = beyond_b;
   T.id_c = beyond_b2;
@@ -1082,7 +1083,10 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
         const bool b2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B2_WAVES, 2, false, 3>),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                             int(ID_B2_MAX_BYTES)) == hipSuccess;
-        return b1 && b2;
+        const bool c = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 4>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           int(ID_B2_MAX_BYTES)) == hipSuccess;
+        return b1 && b2 && c;
       }();
       if (!lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the ID kernel");
       const DNbr* nb = tab<DNbr>(ws, T_.o_nbrs);
@@ -1112,8 +1116,7 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       if (side[2]) {
         hipStream_t st = F->fs->aux[2];
         if (T_.id_c)
-          LAUNCH(K_ID_C, l, k_seg_id_cols<T, 8, 2, true, 4><<<unsigned(ns), 512,
-                                                                 idc_lds_bytes(8, 2, 128, 0, tz.st, false), st>>>(
+          LAUNCH(K_ID_C, l, k_seg_id_cols<T, 8, 2, true, 4><<<unsigned(ns), 512, size_t(tz.lds_c), st>>>(
               segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
         if (T_.id_old)
           LAUNCH(K_ID_BLK, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var,
