@@ -9,14 +9,15 @@
 // one wave reduction.  Pivoting never moves data: lane j keeps original
 // column j, and a position -> column table records the order.
 //
-// Three tiers cover the segment sizes of a level:
+// Four tiers cover the segment sizes of a level:
 //   A  NW = 1,  Y and row table in LDS (fine levels: thousands of segments)
 //   B  NW = 4,  Y and row table in LDS (middle levels), two groups per CU
 //   B2 the same kernel with up to 152 KB of LDS, one group per CU
-//   C  NW = 8,  the far rows and the row table in the segment's global
-//      scratch (top levels, a few segments whose coupling rows exceed the
-//      LDS); Y, the m = |N| + h rows of a pass, in LDS when they fit there,
-//      else in global scratch too
+//   C  NW = 8,  152 KB of LDS, for segments whose coupling rows exceed it:
+//      the far rows and the row table in LDS when they leave room for
+//      enough of Y, else in the segment's global scratch; Y, the
+//      m = |N| + h rows of a pass, split: its first rows (at least min(m,
+//      n), all that fit) in LDS, the rest in global scratch
 // Segments wider than 128 columns take the block-cooperative kernel
 // k_seg_id.  Every tier computes the same tier function, so each segment is
 // handled by exactly one launch; tier A also writes the identity result of
@@ -38,10 +39,9 @@ struct IdRow {
   int32_t vh;      // 2 * vertex + half (half 1: a row of A_{c,d}^T)
 };
 
-// Sampling tiles: idc_ic(NCOL) sample rows x idc_ft(NCOL) far rows per step
-// (a tile's row pairs times its far rows is 64: one Philox draw per lane).
-__host__ __device__ constexpr int idc_ic(int ncol) { return ncol == 1 ? 8 : 4; }
-__host__ __device__ constexpr int idc_ft(int ncol) { return ncol == 1 ? 16 : 32; }
+// Gaussian tile of one wave: the entries of a pair of sample rows for 64 far
+// rows (one Philox draw per lane).
+constexpr int ID_GTILE = 128;
 
 // LDS bytes of one workgroup of a tier (rows_in_lds: Y, the far rows B_F in
 // the storage type (st bytes) and the row table).
@@ -49,10 +49,16 @@ __host__ __device__ inline size_t idc_lds_bytes(int nw, int ncol, int n, int R, 
   size_t b = 0;
   if (rows_in_lds) b += size_t(R) * n * (8 + st) + size_t(R) * (sizeof(IdRow) + 4);
   b += size_t(ID_MAXPROBES) * n * 8;              // probe rows
-  b += size_t(nw) * idc_ic(ncol) * idc_ft(ncol) * 8;    // Gaussian tiles
+  b += size_t(nw) * ID_GTILE * 8;                 // Gaussian tiles
   b += size_t(2) * nw * 64 * ncol * 8;            // norm and dot partials
   b += size_t(2) * n * 4 + 16;                    // position <-> column
   return (b + 15) & ~size_t(15);
+}
+
+// LDS bytes of the far rows B_F (storage type), row table and row order of a
+// segment with R coupling rows.
+__host__ __device__ inline size_t idc_table_bytes(int n, int R, int st) {
+  return ((size_t(R) * n * st + 15) & ~size_t(15)) + size_t(R) * sizeof(IdRow) + ((size_t(R) * 4 + 15) & ~size_t(15));
 }
 
 // Doubles of global scratch a tier-C segment uses (Y, B_F, then the row table
@@ -75,12 +81,18 @@ struct IdTiers {
 };
 
 // Tier of a segment that gets an ID, from its sizes (n columns, R rows):
-// 1: tier A, 2: B, 3: B2, 4: C, 5: block-cooperative kernel.
+// 1: tier A, 2: B, 3: B2, 4: C with the far rows and row tables in LDS
+// (when they leave room there for max(n, R / 2) rows of Y), 6: C with them
+// in global scratch, 5: block-cooperative kernel.
 __host__ __device__ inline int id_tier_of_size(int n, int R, IdTiers t) {
   if (n <= 64 && idc_lds_bytes(1, 1, n, R, t.st, true) <= size_t(t.budget_a)) return 1;
   if (n <= 128 && idc_lds_bytes(ID_B_WAVES, 2, n, R, t.st, true) <= size_t(t.budget_b)) return 2;
   if (n <= 128 && idc_lds_bytes(ID_B2_WAVES, 2, n, R, t.st, true) <= size_t(t.budget_b2)) return 3;
-  if (n <= 128) return 4;
+  const size_t yrows = size_t(n > R / 2 ? n : R / 2);
+  if (n <= 128 && idc_lds_bytes(ID_B2_WAVES, 2, n, 0, t.st, false) + idc_table_bytes(n, R, t.st) +
+                      yrows * n * 8 <= size_t(t.lds_c))
+    return 4;
+  if (n <= 128) return 6;
   return 5;
 }
 
@@ -110,12 +122,12 @@ __device__ inline void grp_sync() {
 }
 
 // Fetches rows [0, cnt) of the list (near rows order[p], then far rows
-// order[R - 1 - f]): near row p goes to Y[p * n + j], far row f to
-// BF[f * n + j].  One (row, column) entry per thread and step, so every load
-// of a step is independent and in flight at once.
+// order[R - 1 - f]): near row p goes to row p of Y (Ya below row yl, Yb from
+// there on), far row f to BF[f * n + j].  One (row, column) entry per thread
+// and step, so every load of a step is independent and in flight at once.
 template <typename T, int NT>
 __device__ inline void idc_fetch(const T* __restrict__ varena, const IdRow* rows, const int* order, int R, int nN,
-                                 int cnt, double* Y, T* BF, int n) {
+                                 int cnt, double* Ya, double* Yb, int yl, T* BF, int n) {
 #pragma unroll 4
   for (int t = threadIdx.x; t < cnt * n; t += NT) {
     const int p = t / n, j = t - p * n;
@@ -123,10 +135,17 @@ __device__ inline void idc_fetch(const T* __restrict__ varena, const IdRow* rows
     const IdRow m = rows[near ? order[p] : order[R - 1 - (p - nN)]];
     const T v = varena[m.base + int64_t(j) * m.stride];
     if (near)
-      Y[t] = double(v);
+      (p < yl ? Ya : Yb)[t] = double(v);
     else
       BF[size_t(p - nN) * n + j] = v;
   }
+}
+
+// First row at or after lo that belongs to the same wave as row i0 (rows
+// i0, i0 + NW, ...).
+template <int NW>
+__device__ inline int idc_next_row(int i0, int lo) {
+  return i0 >= lo ? i0 : i0 + (lo - i0 + NW - 1) / NW * NW;
 }
 
 // Sum over this wave's rows i = i0, i0 + NW, ... < m of Y[i][a] * Y[i][b]
@@ -309,7 +328,7 @@ __device__ inline void idc_row_table(const DSeg& S, const DSeg* segs, const DNbr
   }
 }
 
-template <typename T, int NW, int NCOL, bool YG, int TIER>
+template <typename T, int NW, int NCOL, bool YG, int TIER, bool TABS = false>
 __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int nseg, const DNbr* nbrs,
                                                          const DBlk* blks, GridGeom g, int32_t* iarena,
                                                          T* __restrict__ varena, double* __restrict__ scratch,
@@ -318,8 +337,6 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   __shared__ int s_cnt[2];
   __shared__ int s_acc;
   constexpr int NT = 64 * NW;
-  constexpr int IC = idc_ic(NCOL);
-  constexpr int IDC_FT = idc_ft(NCOL);
   constexpr int UR = YG ? 8 : 4;  // rows in flight per lane in the CPQR passes
   const int c = blockIdx.x;
   if (c >= nseg) return;
@@ -351,7 +368,17 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   IdRow* rows;
   int* order;
   T* BF;  // far rows, row-major (ld n), in the storage type
-  if constexpr (YG) {
+  if constexpr (YG && TABS) {
+    // far rows, row table and order in LDS; Y in LDS when a pass fits
+    Yg = scratch + S.scr_off;
+    Y = Yg;
+    BF = reinterpret_cast<T*>(sp);
+    sp += (size_t(R) * n * sizeof(T) + 15) & ~size_t(15);
+    rows = reinterpret_cast<IdRow*>(sp);
+    sp += size_t(R) * sizeof(IdRow);
+    order = reinterpret_cast<int*>(sp);
+    sp += (size_t(R) * 4 + 15) & ~size_t(15);
+  } else if constexpr (YG) {
     Yg = scratch + S.scr_off;
     Y = Yg;
     BF = reinterpret_cast<T*>(Yg + size_t(R) * n);
@@ -367,8 +394,8 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   }
   double* P = reinterpret_cast<double*>(sp);  // probe rows, row-major (probes x n)
   sp += size_t(ID_MAXPROBES) * n * 8;
-  double* Gt = reinterpret_cast<double*>(sp) + size_t(w) * IC * IDC_FT;  // this wave's Gaussian tile
-  sp += size_t(NW) * IC * IDC_FT * 8;
+  double* Gt = reinterpret_cast<double*>(sp) + size_t(w) * ID_GTILE;  // this wave's Gaussian tile
+  sp += size_t(NW) * ID_GTILE * 8;
   double* pn = reinterpret_cast<double*>(sp);  // norm partials [NW][NCOL][64]
   sp += size_t(NW) * 64 * NCOL * 8;
   double* pd = reinterpret_cast<double*>(sp);  // dot partials [NW][NCOL][64]
@@ -379,8 +406,8 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   }
   int* pos2col = reinterpret_cast<int*>(sp);
   int* col2pos = pos2col + n;
-  // tier C: the rest of the launch's LDS holds Y in the passes whose m rows
-  // fit (m <= ylds_rows), the others use Yg
+  // tier C: the rest of the launch's LDS holds the first ylds_rows rows of
+  // Y, the rows after them go to Yg
   double* Ylds = nullptr;
   int ylds_rows = 0;
   if constexpr (YG) {
@@ -408,269 +435,257 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
     ++passes;
     const bool sampled = h < nF;
     const int m = nN + (sampled ? h : nF);
-    if constexpr (YG) Y = m <= ylds_rows ? Ylds : Yg;
-    // ---- 2. Y = [B_N; G B_F / sqrt(h)] or the exact far rows; B_F is
-    //         fetched once and kept for later passes ----
-    idc_fetch<T, NT>(varena, rows, order, R, nN, passes == 1 ? R : nN, Y, BF, n);
-    __syncthreads();
-    if (!sampled) {
-      for (int t = tid; t < nF * n; t += NT) Y[size_t(nN) * n + t] = double(BF[t]);
-    } else {
-      const double sc = 1.0 / sqrt(double(h));
-      for (int stream = 0; stream < 2; ++stream) {
-        const int nrows = stream == 0 ? h : probes;
-        for (int i0 = 0; i0 < nrows; i0 += IC) {
-          const int ih = nrows - i0 < IC ? nrows - i0 : IC;
-          double acc[IC][NCOL];
-#pragma unroll
-          for (int a = 0; a < IC; ++a)
-#pragma unroll
-            for (int s = 0; s < NCOL; ++s) acc[a][s] = 0.0;
-          for (int f0 = w * IDC_FT; f0 < nF; f0 += NW * IDC_FT) {
-            const int fw = nF - f0 < IDC_FT ? nF - f0 : IDC_FT;
-            // Gaussian tile: IC rows x IDC_FT far rows, one Philox draw per row pair
-            for (int t = lane; t < (IC / 2) * IDC_FT; t += 64) {
-              const int pr = t / IDC_FT, ff = t % IDC_FT;
-              double ev = 0.0, od = 0.0;
-              if (ff < fw && 2 * pr < ih) {
-                const int vh = rows[order[R - 1 - (f0 + ff)]].vh;
-                gauss_pair(prm.seed, prm.level, stream, (i0 >> 1) + pr, vh >> 1, c, vh & 1, &ev, &od);
-              }
-              Gt[(2 * pr) * IDC_FT + ff] = ev;
-              Gt[(2 * pr + 1) * IDC_FT + ff] = 2 * pr + 1 < ih ? od : 0.0;
+    // one pass on the stacked rows: rows below yl at Y (in LDS; for tier C
+    // in global scratch when not even the first min(m, n) rows fit there),
+    // tier C's rows from yl on at Yb (global scratch, row i at Yb + i n).
+    // Every row the pivot steps, T and the check touch lies below
+    // min(m, n) <= yl.  Called at one site per memory layout so that each
+    // inlined copy uses its spaces' own instructions.  True when the ID is
+    // accepted.
+    auto pass = [&](double* Y, double* Yb, int yl) -> bool {
+      const int mi = m < yl ? m : yl;
+      // ---- 2. Y = [B_N; G B_F / sqrt(h)] or the exact far rows; B_F is
+      //         fetched once and kept for later passes ----
+      idc_fetch<T, NT>(varena, rows, order, R, nN, passes == 1 ? R : nN, Y, Yb, yl, BF, n);
+      __syncthreads();
+      if (!sampled) {
+        for (int t = tid; t < nF * n; t += NT) (nN + t / n < yl ? Y : Yb)[size_t(nN) * n + t] = double(BF[t]);
+      } else {
+        // rows of the sketch (stream 0, scaled by 1 / sqrt(h)) and of the
+        // probes (stream 1) in pairs, one Philox draw per pair and far row:
+        // pair p by wave p mod NW, over all far rows in order (the wave's
+        // Gaussian tile holds the entries of 64 far rows), written by that
+        // wave alone (no barrier)
+        const double sc = 1.0 / sqrt(double(h));
+        const int hp = (h + 1) / 2, pp = (probes + 1) / 2;
+        double* Gw = Gt;  // this wave's tile: 64 far rows x 2 rows
+        for (int p = w; p < hp + pp; p += NW) {
+          const int stream = p < hp ? 0 : 1;
+          const int pair = stream == 0 ? p : p - hp;
+          const int nrows = stream == 0 ? h : probes;
+          const int r0 = 2 * pair;
+          double a0[NCOL], a1[NCOL];
+  #pragma unroll
+          for (int s2 = 0; s2 < NCOL; ++s2) a0[s2] = a1[s2] = 0.0;
+          for (int f0 = 0; f0 < nF; f0 += 64) {
+            const int ff = f0 + lane;
+            double ev = 0.0, od = 0.0;
+            if (ff < nF) {
+              const int vh = rows[order[R - 1 - ff]].vh;
+              gauss_pair(prm.seed, prm.level, stream, pair, vh >> 1, c, vh & 1, &ev, &od);
             }
+            Gw[2 * lane] = ev;
+            Gw[2 * lane + 1] = od;
             wave_sync();
-#pragma unroll 4
-            for (int ff = 0; ff < IDC_FT; ++ff) {
-              double b[NCOL];
-#pragma unroll
-              for (int s = 0; s < NCOL; ++s) {
-                const int j = lane + 64 * s;
-                b[s] = (ff < fw && j < n) ? double(BF[size_t(f0 + ff) * n + j]) : 0.0;
-              }
-#pragma unroll
-              for (int a = 0; a < IC; ++a) {
-                const double gv = Gt[a * IDC_FT + ff];
-#pragma unroll
-                for (int s = 0; s < NCOL; ++s) acc[a][s] += gv * b[s];
+            const int fw = nF - f0 < 64 ? nF - f0 : 64;
+  #pragma unroll 4
+            for (int t = 0; t < fw; ++t) {
+              const double g0 = Gw[2 * t], g1 = Gw[2 * t + 1];
+  #pragma unroll
+              for (int s2 = 0; s2 < NCOL; ++s2) {
+                const int j = lane + 64 * s2;
+                const double b = j < n ? double(BF[size_t(f0 + t) * n + j]) : 0.0;
+                a0[s2] += g0 * b;
+                a1[s2] += g1 * b;
               }
             }
             wave_sync();
           }
-          if constexpr (NW == 1) {
-#pragma unroll
-            for (int a = 0; a < IC; ++a) {
-              if (a < ih) {
-                const int row = i0 + a;
-#pragma unroll
-                for (int s = 0; s < NCOL; ++s) {
-                  const int j = lane + 64 * s;
-                  if (j < n) {
-                    if (stream == 0)
-                      Y[size_t(nN + row) * n + j] = acc[a][s] * sc;
-                    else
-                      P[size_t(row) * n + j] = acc[a][s];
-                  }
-                }
+  #pragma unroll
+          for (int s2 = 0; s2 < NCOL; ++s2) {
+            const int j = lane + 64 * s2;
+            if (j < n) {
+              if (stream == 0) {
+                (nN + r0 < yl ? Y : Yb)[size_t(nN + r0) * n + j] = a0[s2] * sc;
+                if (r0 + 1 < nrows) (nN + r0 + 1 < yl ? Y : Yb)[size_t(nN + r0 + 1) * n + j] = a1[s2] * sc;
+              } else {
+                P[size_t(r0) * n + j] = a0[s2];
+                if (r0 + 1 < nrows) P[size_t(r0 + 1) * n + j] = a1[s2];
               }
-            }
-            wave_sync();
-          } else {
-            // combine the waves' partial sums (in wave order), two rows at a
-            // time through the norm/dot partial buffers, which the CPQR
-            // only uses later: NW * 2 rows * 64 * NCOL doubles
-            double* buf = pn;
-#pragma unroll
-            for (int hf = 0; hf < IC / 2; ++hf) {
-#pragma unroll
-              for (int ra = 0; ra < 2; ++ra)
-#pragma unroll
-                for (int s = 0; s < NCOL; ++s)
-                  buf[((w * 2 + ra) * NCOL + s) * 64 + lane] = acc[2 * hf + ra][s];
-              __syncthreads();
-              for (int t = tid; t < 2 * n; t += NT) {
-                const int ra = t / n, j = t - ra * n, a = 2 * hf + ra;
-                if (a < ih) {
-                  double v = 0.0;
-                  for (int ww = 0; ww < NW; ++ww) v += buf[((ww * 2 + ra) * NCOL + (j >> 6)) * 64 + (j & 63)];
-                  const int row = i0 + a;
-                  if (stream == 0)
-                    Y[size_t(nN + row) * n + j] = v * sc;
-                  else
-                    P[size_t(row) * n + j] = v;
-                }
-              }
-              __syncthreads();
             }
           }
         }
       }
-    }
-    for (int i = tid; i < n; i += NT) pos2col[i] = col2pos[i] = i;
-    __syncthreads();
+      for (int i = tid; i < n; i += NT) pos2col[i] = col2pos[i] = i;
+      __syncthreads();
 
-    // ---- 3. CPQR (fresh norms, tie rule: smallest original column) ----
-    uint64_t done[NCOL];
-#pragma unroll
-    for (int s = 0; s < NCOL; ++s) done[s] = 0ull;
-#pragma unroll
-    for (int s = 0; s < NCOL; ++s) {
-      const int j = lane + 64 * s;
-      pn[(w * NCOL + s) * 64 + lane] = j < n ? idc_rowdot<NW, UR>(Y, n, w, m, j, j) : 0.0;
-    }
-    __syncthreads();
-    const int kmax = m < n ? m : n;
-    k = kmax;
-    for (int j = 0; j < kmax; ++j) {
-      double nv[NCOL];
-      bool act[NCOL];
-      double mxl = 0.0;
-#pragma unroll
+      // ---- 3. CPQR (fresh norms, tie rule: smallest original column) ----
+      uint64_t done[NCOL];
+  #pragma unroll
+      for (int s = 0; s < NCOL; ++s) done[s] = 0ull;
+  #pragma unroll
       for (int s = 0; s < NCOL; ++s) {
-        const int col = lane + 64 * s;
-        act[s] = col < n && !((done[s] >> lane) & 1ull);
+        const int j = lane + 64 * s;
         double t = 0.0;
-        for (int ww = 0; ww < NW; ++ww) t += pn[(ww * NCOL + s) * 64 + lane];
-        nv[s] = sqrt(t);
-        if (act[s]) mxl = fmax(mxl, nv[s]);
-      }
-      const double mx = wave_max(mxl);
-      int q = -1;
-#pragma unroll
-      for (int s = 0; s < NCOL; ++s) {
-        const uint64_t cm = __ballot(act[s] && nv[s] >= mx * (1.0 - 1e-12));
-        if (q < 0 && cm) q = 64 * s + __ffsll((unsigned long long)cm) - 1;
-      }
-      if (j == 0) r11 = mx;
-      if (mx == 0.0 || mx <= prm.eps * r11 || q < 0) {
-        k = j;
-        break;
-      }
-      const int qs = q >> 6, ql = q & 63;
-      double nq = nv[0];
-#pragma unroll
-      for (int s = 1; s < NCOL; ++s)
-        if (qs == s) nq = nv[s];
-      const double alpha = __shfl(nq, ql, 64);
-      const double x0 = Y[size_t(j) * n + q];
-      const double sg = x0 >= 0.0 ? 1.0 : -1.0;
-      const double v0 = x0 + sg * alpha;
-      const double vv = 2.0 * alpha * (alpha + fabs(x0));
-      const int jown = j % NW;
-      const int i1 = j + 1 + ((w - (j + 1) % NW) + NW) % NW;  // this wave's first row below j
-      // dot products of the reflector with every live column
-#pragma unroll
-      for (int s = 0; s < NCOL; ++s) {
-        const int col = lane + 64 * s;
-        double d = 0.0;
-        if (act[s] && col != q) {
-          if (w == jown) d = v0 * Y[size_t(j) * n + col];
-          d += idc_rowdot<NW, UR>(Y, n, i1, m, q, col);
+        if (j < n) {
+          t = idc_rowdot<NW, UR>(Y, n, w, mi, j, j);
+          if constexpr (YG) t += idc_rowdot<NW, UR>(Yb, n, idc_next_row<NW>(w, yl), m, j, j);
         }
-        pd[(w * NCOL + s) * 64 + lane] = d;
+        pn[(w * NCOL + s) * 64 + lane] = t;
       }
       __syncthreads();
-      // apply the reflector; accumulate the fresh norms of rows > j
-#pragma unroll
-      for (int s = 0; s < NCOL; ++s) {
-        const int col = lane + 64 * s;
-        double a = 0.0;
-        if (act[s] && col != q) {
+      const int kmax = m < n ? m : n;
+      k = kmax;
+      for (int j = 0; j < kmax; ++j) {
+        double nv[NCOL];
+        bool act[NCOL];
+        double mxl = 0.0;
+  #pragma unroll
+        for (int s = 0; s < NCOL; ++s) {
+          const int col = lane + 64 * s;
+          act[s] = col < n && !((done[s] >> lane) & 1ull);
           double t = 0.0;
-          for (int ww = 0; ww < NW; ++ww) t += pd[(ww * NCOL + s) * 64 + lane];
-          const double f = 2.0 * t / vv;
-          if (w == jown) Y[size_t(j) * n + col] -= f * v0;
-          a = idc_rowaxpy<NW, UR>(Y, n, i1, m, col, q, f);
+          for (int ww = 0; ww < NW; ++ww) t += pn[(ww * NCOL + s) * 64 + lane];
+          nv[s] = sqrt(t);
+          if (act[s]) mxl = fmax(mxl, nv[s]);
         }
-        pn[(w * NCOL + s) * 64 + lane] = a;
-      }
-      if (w == jown && lane == ql) Y[size_t(j) * n + q] = -sg * alpha;
-      done[qs] |= 1ull << ql;
-      if (tid == 0) {
-        // position j takes column q; the column there moves to q's old position
-        const int qp = col2pos[q], cj = pos2col[j];
-        pos2col[qp] = cj;
-        col2pos[cj] = qp;
-        pos2col[j] = q;
-        col2pos[q] = j;
-      }
-      __syncthreads();
-    }
-
-    // ---- 4. T = R11^{-1} R12, in place in rows < k of the remaining columns ----
-    const int nr = n - k;
-    for (int i = k - 1; i >= 0; --i) {
-      const int ci = pos2col[i];
-      const double rii = Y[size_t(i) * n + ci];
-      double tq[NCOL];
-#pragma unroll
-      for (int s = 0; s < NCOL; ++s) {
-        const int qq = lane + 64 * s;
-        tq[s] = qq < nr ? Y[size_t(i) * n + pos2col[k + qq]] / rii : 0.0;
-      }
-      grp_sync<NW>();
-#pragma unroll
-      for (int s = 0; s < NCOL; ++s) {
-        const int qq = lane + 64 * s;
-        if (qq < nr) {
-          const int cq = pos2col[k + qq];
-          if (w == i % NW) Y[size_t(i) * n + cq] = tq[s];
-          for (int t = w; t < i; t += NW) Y[size_t(t) * n + cq] -= Y[size_t(t) * n + ci] * tq[s];
+        const double mx = wave_max(mxl);
+        int q = -1;
+  #pragma unroll
+        for (int s = 0; s < NCOL; ++s) {
+          const uint64_t cm = __ballot(act[s] && nv[s] >= mx * (1.0 - 1e-12));
+          if (q < 0 && cm) q = 64 * s + __ffsll((unsigned long long)cm) - 1;
         }
+        if (j == 0) r11 = mx;
+        if (mx == 0.0 || mx <= prm.eps * r11 || q < 0) {
+          k = j;
+          break;
+        }
+        const int qs = q >> 6, ql = q & 63;
+        double nq = nv[0];
+  #pragma unroll
+        for (int s = 1; s < NCOL; ++s)
+          if (qs == s) nq = nv[s];
+        const double alpha = __shfl(nq, ql, 64);
+        const double x0 = Y[size_t(j) * n + q];
+        const double sg = x0 >= 0.0 ? 1.0 : -1.0;
+        const double v0 = x0 + sg * alpha;
+        const double vv = 2.0 * alpha * (alpha + fabs(x0));
+        const int jown = j % NW;
+        const int i1 = j + 1 + ((w - (j + 1) % NW) + NW) % NW;  // this wave's first row below j
+        // dot products of the reflector with every live column
+  #pragma unroll
+        for (int s = 0; s < NCOL; ++s) {
+          const int col = lane + 64 * s;
+          double d = 0.0;
+          if (act[s] && col != q) {
+            if (w == jown) d = v0 * Y[size_t(j) * n + col];
+            d += idc_rowdot<NW, UR>(Y, n, i1, mi, q, col);
+            if constexpr (YG) d += idc_rowdot<NW, UR>(Yb, n, idc_next_row<NW>(i1, yl), m, q, col);
+          }
+          pd[(w * NCOL + s) * 64 + lane] = d;
+        }
+        __syncthreads();
+        // apply the reflector; accumulate the fresh norms of rows > j
+  #pragma unroll
+        for (int s = 0; s < NCOL; ++s) {
+          const int col = lane + 64 * s;
+          double a = 0.0;
+          if (act[s] && col != q) {
+            double t = 0.0;
+            for (int ww = 0; ww < NW; ++ww) t += pd[(ww * NCOL + s) * 64 + lane];
+            const double f = 2.0 * t / vv;
+            if (w == jown) Y[size_t(j) * n + col] -= f * v0;
+            a = idc_rowaxpy<NW, UR>(Y, n, i1, mi, col, q, f);
+            if constexpr (YG) a += idc_rowaxpy<NW, UR>(Yb, n, idc_next_row<NW>(i1, yl), m, col, q, f);
+          }
+          pn[(w * NCOL + s) * 64 + lane] = a;
+        }
+        if (w == jown && lane == ql) Y[size_t(j) * n + q] = -sg * alpha;
+        done[qs] |= 1ull << ql;
+        if (tid == 0) {
+          // position j takes column q; the column there moves to q's old position
+          const int qp = col2pos[q], cj = pos2col[j];
+          pos2col[qp] = cj;
+          col2pos[cj] = qp;
+          pos2col[j] = q;
+          col2pos[q] = j;
+        }
+        __syncthreads();
       }
-      grp_sync<NW>();
-    }
-    __syncthreads();
 
-    // ---- 5. a-posteriori check with the probe rows: E = P_r - P_s T
-    //         (one probe per wave, the columns of T over the lanes) ----
-    bool accept = true;
-    if (sampled) {
-      for (int pr = w; pr < probes; pr += NW) {
-        double sv = 0.0;
-#pragma unroll
+      // ---- 4. T = R11^{-1} R12, in place in rows < k of the remaining columns ----
+      const int nr = n - k;
+      for (int i = k - 1; i >= 0; --i) {
+        const int ci = pos2col[i];
+        const double rii = Y[size_t(i) * n + ci];
+        double tq[NCOL];
+  #pragma unroll
+        for (int s = 0; s < NCOL; ++s) {
+          const int qq = lane + 64 * s;
+          tq[s] = qq < nr ? Y[size_t(i) * n + pos2col[k + qq]] / rii : 0.0;
+        }
+        grp_sync<NW>();
+  #pragma unroll
         for (int s = 0; s < NCOL; ++s) {
           const int qq = lane + 64 * s;
           if (qq < nr) {
             const int cq = pos2col[k + qq];
-            const double* Pr = P + size_t(pr) * n;
-            double e = Pr[cq];
-            int t = 0;
-            for (; t + UR <= k; t += UR) {
-              double yv[UR], pv[UR];
-#pragma unroll
-              for (int u = 0; u < UR; ++u) {
-                yv[u] = Y[size_t(t + u) * n + cq];
-                pv[u] = Pr[pos2col[t + u]];
-              }
-#pragma unroll
-              for (int u = 0; u < UR; ++u) e -= pv[u] * yv[u];
-            }
-            for (; t < k; ++t) e -= Pr[pos2col[t]] * Y[size_t(t) * n + cq];
-            sv += e * e;
+            if (w == i % NW) Y[size_t(i) * n + cq] = tq[s];
+            for (int t = w; t < i; t += NW) Y[size_t(t) * n + cq] -= Y[size_t(t) * n + ci] * tq[s];
           }
         }
-        sv = wave_sum(sv);
-        if (lane == 0) pn[pr] = sqrt(sv);
+        grp_sync<NW>();
       }
       __syncthreads();
-      if (tid == 0) {
-        double worst = 0.0;
-        for (int pr = 0; pr < probes; ++pr) worst = fmax(worst, pn[pr]);
-        s_acc = worst <= prm.tau * sqrt(double(nr)) * prm.eps * r11 ? 1 : 0;
+
+      // ---- 5. a-posteriori check with the probe rows: E = P_r - P_s T
+      //         (one probe per wave, the columns of T over the lanes) ----
+      bool accept = true;
+      if (sampled) {
+        for (int pr = w; pr < probes; pr += NW) {
+          double sv = 0.0;
+  #pragma unroll
+          for (int s = 0; s < NCOL; ++s) {
+            const int qq = lane + 64 * s;
+            if (qq < nr) {
+              const int cq = pos2col[k + qq];
+              const double* Pr = P + size_t(pr) * n;
+              double e = Pr[cq];
+              int t = 0;
+              for (; t + UR <= k; t += UR) {
+                double yv[UR], pv[UR];
+  #pragma unroll
+                for (int u = 0; u < UR; ++u) {
+                  yv[u] = Y[size_t(t + u) * n + cq];
+                  pv[u] = Pr[pos2col[t + u]];
+                }
+  #pragma unroll
+                for (int u = 0; u < UR; ++u) e -= pv[u] * yv[u];
+              }
+              for (; t < k; ++t) e -= Pr[pos2col[t]] * Y[size_t(t) * n + cq];
+              sv += e * e;
+            }
+          }
+          sv = wave_sum(sv);
+          if (lane == 0) pn[pr] = sqrt(sv);
+        }
+        __syncthreads();
+        if (tid == 0) {
+          double worst = 0.0;
+          for (int pr = 0; pr < probes; ++pr) worst = fmax(worst, pn[pr]);
+          s_acc = worst <= prm.tau * sqrt(double(nr)) * prm.eps * r11 ? 1 : 0;
+        }
+        __syncthreads();
+        accept = s_acc != 0;
       }
-      __syncthreads();
-      accept = s_acc != 0;
-    }
-    if (accept) {
-      T* Tm = varena + S.t_off;
-      for (int t = tid; t < k * nr; t += NT) {
-        const int i = t / nr, qq = t % nr;
-        Tm[t] = T(Y[size_t(i) * n + pos2col[k + qq]]);
+      if (accept) {
+        T* Tm = varena + S.t_off;
+        for (int t = tid; t < k * nr; t += NT) {
+          const int i = t / nr, qq = t % nr;
+          Tm[t] = T(Y[size_t(i) * n + pos2col[k + qq]]);
+        }
+        for (int i = tid; i < n; i += NT) perm_out[i] = pos2col[i];
+        return true;
       }
-      for (int i = tid; i < n; i += NT) perm_out[i] = pos2col[i];
-      break;
-    }
+      return false;
+    };
+    bool accepted;
+    if constexpr (YG)
+      accepted = ylds_rows >= (m < n ? m : n) ? pass(Ylds, Yg, ylds_rows) : pass(Yg, Yg, m);
+    else
+      accepted = pass(Y, Y, m);
+    if (accepted) break;
     h *= 2;
     __syncthreads();
   }

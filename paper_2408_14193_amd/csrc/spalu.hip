@@ -58,7 +58,7 @@ struct LevelTabs {
          o_tasks = 0, o_terms = 0, o_dyn = 0;
   // ID launches of the level (bounds from the uncompressed sizes)
   IdTiers tiers{0, 0, 0, 8};
-  bool id_b = false, id_b2 = false, id_c = false, id_old = false;
+  bool id_b = false, id_b2 = false, id_c = false, id_cg = false, id_old = false;
   int max_cap = 0;  // largest uncompressed segment
   int max_nbrs = 0;          // largest neighbour count of a segment
   int scale_wave_lds = 0;    // LDS doubles of the one-wave coupling scaling
@@ -202,7 +202,7 @@ constexpr size_t MELIM_MAX_BYTES = 152 * 1024;  // (at most: one group per CU)
 // kernels themselves decide with the actual sizes.
 void plan_id_tiers(LevelTabs& T, int st) {
   size_t a = 0, b = 0, b2 = 0;
-  bool beyond_a = false, beyond_b = false, beyond_b2 = false, wide = false;
+  bool beyond_a = false, beyond_b = false, beyond_b2 = false, tabs_global = false, wide = false;
   for (const DSeg& D : T.segs) {
     if (!((D.flags & SEG_REGULAR) && (D.flags & SEG_HAS_NBR))) continue;
     const int cap = D.cap, R = D.rcap;
@@ -224,6 +224,10 @@ void plan_id_tiers(LevelTabs& T, int st) {
       continue;
     }
     beyond_b2 = true;
+    const int nc = std::min(cap, 128);
+    if (idc_lds_bytes(ID_B2_WAVES, 2, nc, 0, st, false) + idc_table_bytes(nc, R, st) +
+            size_t(std::max(nc, R / 2)) * nc * 8 > ID_B2_MAX_BYTES)
+      tabs_global = true;
     if (cap > 128) wide = true;
   }
   // segments beyond a tier by bound may still land in it by their actual
@@ -239,6 +243,7 @@ void plan_id_tiers(LevelTabs& T, int st) {
   T.id_b = beyond_a;
   T.id_b2 = beyond_b;
   T.id_c = beyond_b2;
+  T.id_cg = tabs_global;
   T.id_old = wide;
 }
 
@@ -708,14 +713,16 @@ void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, 
     case K_ID_B2:
     case K_ID_C:
     case K_ID_BLK: {
-      // the segments of this launch's size tier (A, B, B2, C, block kernel)
+      // the segments of this launch's size tier (A, B, B2, C in both
+      // variants, block kernel)
       const LevelTabs& T = Y.lv[l];
       for (size_t c = 0; c < T.segs.size(); ++c) {
         if (dynv(l, 4, int(c)) <= 0) continue;
         const double n = dynv(l, 0, int(c)), k = dynv(l, 1, int(c)), h = dynv(l, 3, int(c));
         double R = 0.0;
         for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) R += 2.0 * dynv(l, 0, T.nbrs[e].d);
-        if (id_tier_of_size(int(n), int(R), T.tiers) != 1 + (kid - K_ID)) continue;
+        const int tier = id_tier_of_size(int(n), int(R), T.tiers);
+        if ((tier == 6 ? 4 : tier) != 1 + (kid - K_ID)) continue;
         // sketch G B_F of the far rows (none once h reaches them: exact rows),
         // CPQR of the |N| + h stacked rows, T = R11^-1 R12
         const double nf = dynv(l, 6, int(c)), nn = R - nf;
@@ -1083,17 +1090,22 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
         const bool b2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B2_WAVES, 2, false, 3>),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                             int(ID_B2_MAX_BYTES)) == hipSuccess;
-        const bool c = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 4>),
+        const bool c = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 4, true>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            int(ID_B2_MAX_BYTES)) == hipSuccess;
-        return b1 && b2 && c;
+        const bool cg = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 6>),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            int(ID_B2_MAX_BYTES)) == hipSuccess;
+        return b1 && b2 && c && cg;
       }();
       if (!lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the ID kernel");
       const DNbr* nb = tab<DNbr>(ws, T_.o_nbrs);
       const IdTiers tz = T_.tiers;
-      // tier A on the main stream, B, B2 and C (with the block kernel) on
-      // side streams: every segment belongs to exactly one tier
-      const bool side[3] = {T_.id_b, T_.id_b2, T_.id_c || T_.id_old};
+      // tier A on the main stream, B (then C with its tables in global
+      // scratch), B2 and C (then the block kernel) on side streams: every
+      // segment belongs to exactly one tier.  Tier B and the global-table
+      // C tier share a stream since they rarely both have work on a level
+      const bool side[3] = {T_.id_b || T_.id_cg, T_.id_b2, T_.id_c || T_.id_old};
       if (side[0] || side[1] || side[2]) {
         HIPCHK(hipEventRecord(F->fs->fork, st));
         for (int i = 0; i < 3; ++i)
@@ -1103,9 +1115,13 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
           segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       if (side[0]) {
         hipStream_t st = F->fs->aux[0];
-        LAUNCH(K_ID_B, l, k_seg_id_cols<T, ID_B_WAVES, 2, false, 2><<<unsigned(ns), 64 * ID_B_WAVES,
-                                                                      size_t(tz.budget_b), st>>>(
-            segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
+        if (T_.id_b)
+          LAUNCH(K_ID_B, l, k_seg_id_cols<T, ID_B_WAVES, 2, false, 2><<<unsigned(ns), 64 * ID_B_WAVES,
+                                                                        size_t(tz.budget_b), st>>>(
+              segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
+        if (T_.id_cg)
+          LAUNCH_MORE(K_ID_C, l, k_seg_id_cols<T, 8, 2, true, 6><<<unsigned(ns), 512, size_t(tz.lds_c), st>>>(
+              segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
       }
       if (side[1]) {
         hipStream_t st = F->fs->aux[1];
@@ -1116,7 +1132,7 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       if (side[2]) {
         hipStream_t st = F->fs->aux[2];
         if (T_.id_c)
-          LAUNCH(K_ID_C, l, k_seg_id_cols<T, 8, 2, true, 4><<<unsigned(ns), 512, size_t(tz.lds_c), st>>>(
+          LAUNCH(K_ID_C, l, k_seg_id_cols<T, 8, 2, true, 4, true><<<unsigned(ns), 512, size_t(tz.lds_c), st>>>(
               segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
         if (T_.id_old)
           LAUNCH(K_ID_BLK, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var,

@@ -74,6 +74,7 @@ int main(int argc, char** argv) {
   o.seed = seed;
   o.precision = prec == 32 ? SPALU_FP32 : SPALU_FP64;
   if (model) o.rank_model = to_guarded(pm);
+  if (const char* h0 = std::getenv("EMU_H0")) o.h0 = std::atoi(h0);
   size_t wb = 0;
   rc = spalu_factor_workspace(nd, &o, &wb);
   std::printf("workspace %zu bytes rc %d\n", wb, rc);

@@ -67,7 +67,7 @@ def _oracle_ranks(OF, nd_gpu):
     return nb, rk, hh, ps, mg
 
 
-def oracle_stable_levels(P, nd, ora, eps, want_factor=False):
+def oracle_stable_levels(P, nd, ora, eps, want_factor=False, **okw):
     """Levels (finest first) on which the oracle's rank decisions survive a
     1e-15 relative perturbation of A: a decision that flips under rounding
     noise has no unique answer, so the GPU path is only held to the oracle
@@ -75,7 +75,7 @@ def oracle_stable_levels(P, nd, ora, eps, want_factor=False):
     oracle factorization of the perturbed matrix."""
     A2 = P.scipy().copy()
     A2.data = A2.data * (1.0 + 1e-15 * np.random.default_rng(0).standard_normal(A2.nnz))
-    OF2 = O.factor(nd_order(P.dims), A2, O.Opts(eps=eps, seed=1234))
+    OF2 = O.factor(nd_order(P.dims), A2, O.Opts(eps=eps, seed=1234, **okw))
     p = _oracle_ranks(OF2, nd)
     base = nd.seg_base()
     stable = []
@@ -322,6 +322,31 @@ def test_fp64_parity_where_the_wide_id_tiers_run(S, cfg):
         bg = _backward(A, X, P.rhs)
         print("backward error / eps: gpu %s, oracle (max of plain and perturbed) %s" % (bg / P.eps, bo / P.eps))
         assert np.all(bg <= 2 * bo)
+
+
+def test_fp64_parity_with_exact_rows_split_between_lds_and_scratch(S):
+    """255 x 255 GRF diffusion in FP64 with a first sample count above every
+    far-row count, on both sides: every ID is the CPQR of all R stacked rows
+    (the exact case of the hybrid sampling, no random numbers), so the
+    widest tier-C segments keep the rows of Y beyond their LDS in global
+    scratch.  Sizes, ranks, samples and passes equal the oracle's on every
+    level, and the direct solve equals the oracle's per column within
+    1e-10."""
+    print("case exact rows fp64 cfg=1", flush=True)
+    P = make_config(1, side=255, nrhs=3)
+    S.profile(True)
+    nd, F, B = gpu_factor(S, P, eps=P.eps, seed=1234, h0=100000)
+    work = _id_work(S)
+    S.profile(False)
+    print("ID work by tier:", work)
+    assert work.get("seg_id_c", 0) > 0
+    OF = O.factor(nd_order(P.dims), P.scipy(), O.Opts(eps=P.eps, seed=1234, h0=100000))
+    ora = _oracle_ranks(OF, nd)
+    stable = oracle_stable_levels(P, nd, ora, P.eps, h0=100000)
+    assert len(stable) == nd.L
+    compare_ranks(nd, F.ranks(), ora, stable)
+    X, info = gpu_solve(F, B)
+    assert _col_err(X, O.apply_inverse(OF, P.rhs)).max() <= 1e-10
 
 
 @pytest.mark.parametrize("cfg", [1, 2])

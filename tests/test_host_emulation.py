@@ -41,8 +41,10 @@ def _write(P, d, params=None):
     (params if params is not None else np.zeros(1, np.float32)).tofile(os.path.join(d, "params.bin"))
 
 
-def _run(exe, d, prec, model, eps, nrhs, tol, restart):
+def _run(exe, d, prec, model, eps, nrhs, tol, restart, h0=None):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    if h0 is not None:
+        env["EMU_H0"] = str(h0)
     r = subprocess.run([exe, d, str(prec), str(model), repr(eps), str(nrhs), repr(tol), "1234", str(restart)],
                        capture_output=True, text=True, timeout=900, env=env)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
@@ -79,12 +81,25 @@ def test_fp32_3d_global_leaf_path(exe, tmp_path):
     assert final <= 1e-10
 
 
-def test_wide_id_tiers_fp64(exe, tmp_path):
-    """127 x 127 GRF diffusion in FP64: the stacked coupling rows of the
-    top-level segments exceed the LDS budgets, so the eight-wave tier and
-    the tier with its rows in global scratch run (their bounds checked here
-    on the CPU)."""
-    P = make_config(1, side=127, nrhs=1)
+@pytest.mark.parametrize("cfg", [1, 4])
+def test_wide_id_tiers_fp64(exe, tmp_path, cfg):
+    """127 x 127 in FP64: the stacked coupling rows of the top-level
+    segments exceed the LDS budgets, so the eight-wave tier and tier C run,
+    with its far rows and row tables in LDS (both cases) and, for the widest
+    Helmholtz segments, in global scratch too (bounds checked here on the
+    CPU)."""
+    P = make_config(cfg, side=127, nrhs=1)
     _write(P, str(tmp_path))
-    it, first, final = _run(exe, str(tmp_path), 64, 0, 1e-4, 2, 1e-10, 8)
+    it, first, final = _run(exe, str(tmp_path), 64, 0, P.eps, 2, 1e-10, 8)
+    assert final <= 1e-10
+
+
+def test_exact_rows_split_between_lds_and_scratch(exe, tmp_path):
+    """127 x 127 Helmholtz in FP64 with a first sample count above every
+    far-row count: every ID is taken on all R stacked rows (the exact case
+    of the hybrid sampling), so the widest tier-C segments hold more rows of
+    Y than their LDS and keep the rest in global scratch."""
+    P = make_config(4, side=127, nrhs=1)
+    _write(P, str(tmp_path))
+    it, first, final = _run(exe, str(tmp_path), 64, 0, P.eps, 2, 1e-10, 8, h0=100000)
     assert final <= 1e-10
