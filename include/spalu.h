@@ -139,6 +139,13 @@ typedef struct {
                             is at least n - rank_skip is kept whole, without
                             an ID (exact: only its compression is given up);
                             0 = never; default 0.5                       */
+  int32_t graph;         /* 1: the level sweep is captured as a HIP graph the
+                            first time these pointers (workspace, matrix,
+                            h_init, rank_model, features_out) and options
+                            are seen on the ordering handle, and replayed on
+                            later calls with the same ones (batching form;
+                            up to 4 graphs per handle, not while profiling);
+                            0 (default): direct launches                  */
 } spalu_factor_opts;
 
 typedef struct {
@@ -155,7 +162,7 @@ typedef struct {
 } spalu_factor_info;
 
 /* Default options (eps 1e-6, FP64, seed 1234, rho 0.5, h0 8, 5 probes,
- * tau 1, no rank predictor, margin 1.0, pad 5). */
+ * tau 1, no rank predictor, margin 1.0, pad 5, skip 0.5, no graph). */
 void spalu_factor_opts_default(spalu_factor_opts* o);
 
 /* Bytes of device workspace that spalu_factor needs for this ND and

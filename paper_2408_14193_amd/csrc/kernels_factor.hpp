@@ -88,6 +88,12 @@ __device__ inline int box_nbr(const GridGeom& g, int w0, int w1, int w2, int ix,
   return -1;
 }
 
+// Zeroes n ints (a kernel, not a memset, so that it can sit in a captured
+// graph).
+__global__ void k_zero_i32(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 // Every CSR entry must lie on the stencil (|dx|+|dy|+|dz| <= 1) and columns
 // must ascend; flags bit 1 otherwise.
 __global__ void k_check_pattern(GridGeom g, int64_t n, const int64_t* rowptr, const int32_t* colind,

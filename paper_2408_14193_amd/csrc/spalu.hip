@@ -149,14 +149,22 @@ struct FactorStreams {
   }
 };
 
+// Captured factorizations: one graph per key (factor_graph_key).
+struct FactorGraph {
+  std::vector<uint64_t> key;
+  hipGraphExec_t exec;
+};
+
 struct spalu_nd_s {
   Plan plan;
   std::shared_ptr<Layout> layout[2];
-  std::vector<SweepGraph> graphs;  // most recent last
+  std::vector<SweepGraph> graphs;    // most recent last
+  std::vector<FactorGraph> fgraphs;  // most recent last
   hipStream_t capture_stream = nullptr;
   FactorStreams fs;
   ~spalu_nd_s() {
     for (auto& gph : graphs) (void)hipGraphExecDestroy(gph.exec);
+    for (auto& gph : fgraphs) (void)hipGraphExecDestroy(gph.exec);
     if (capture_stream) (void)hipStreamDestroy(capture_stream);
   }
 };
@@ -969,29 +977,17 @@ void factor_work(const spalu_factor_t* F, double& fl, double& by) {
 }
 
 template <typename T>
-int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) {
+int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) {
   const Layout& Y = *F->lay;
   const Plan& P = F->nd->plan;
   char* ws = F->ws;
-  hipStream_t st = F->stream;
-  FactorStreams& FS = const_cast<spalu_nd_t*>(F->nd)->fs;
-  if (!FS.fork) {
-    HIPCHK(hipEventCreateWithFlags(&FS.fork, hipEventDisableTiming));
-    for (int i = 0; i < 3; ++i) {
-      HIPCHK(hipStreamCreateWithFlags(&FS.aux[i], hipStreamNonBlocking));
-      HIPCHK(hipEventCreateWithFlags(&FS.join[i], hipEventDisableTiming));
-    }
-    HIPCHK(hipEventCreateWithFlags(&FS.lu_done, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&FS.msize_done, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&FS.pre_done, hipEventDisableTiming));
-  }
-  F->fs = &FS;
   int32_t* iar = reinterpret_cast<int32_t*>(ws + Y.o_iarena);
   T* var = reinterpret_cast<T*>(ws + Y.o_varena);
   double* scr = reinterpret_cast<double*>(ws + Y.o_scratch);
   int* status = reinterpret_cast<int*>(ws + Y.o_status);
   const int L = P.L;
-  HIPCHK(hipMemsetAsync(status, 0, 64, st));
+  k_zero_i32<<<1, 64, 0, st>>>(status, 16);
+  HIPCHK(hipGetLastError());
   LAUNCH(K_CHECK, 0, k_check_pattern<<<nblocks(F->n), WG, 0, st>>>(F->g, F->n, F->rowptr, F->colind, status));
   {
     const LevelTabs& TL = Y.lv[L];
@@ -1082,23 +1078,6 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       if (o.rank_model) prm.h_init = reinterpret_cast<int32_t*>(ws + Y.o_hinit);
     }
     {
-      static const bool lds_ok = [] {
-        // tier-B workgroups may take more than 64 KB of LDS
-        const bool b1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B_WAVES, 2, false, 2>),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            int(ID_B_MAX_BYTES)) == hipSuccess;
-        const bool b2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B2_WAVES, 2, false, 3>),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            int(ID_B2_MAX_BYTES)) == hipSuccess;
-        const bool c = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 4, true>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           int(ID_B2_MAX_BYTES)) == hipSuccess;
-        const bool cg = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 6>),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            int(ID_B2_MAX_BYTES)) == hipSuccess;
-        return b1 && b2 && c && cg;
-      }();
-      if (!lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the ID kernel");
       const DNbr* nb = tab<DNbr>(ws, T_.o_nbrs);
       const IdTiers tz = T_.tiers;
       // tier A on the main stream, B (then C with its tables in global
@@ -1147,10 +1126,6 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
     {
       // segments of up to 32 DOFs: one wave each; wider ones: one block each
       // with up to 152 KB of LDS (scratch beyond that)
-      static const bool lu_lds_ok =
-          hipFuncSetAttribute(reinterpret_cast<const void*>(&k_seg_lu<T, SEGLU_BLOCK_NT>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(SEGLU_MAX_BYTES)) == hipSuccess;
-      if (!lu_lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the segment LU kernel");
       const int nw = std::min(SEGLU_WAVE_MAX_N, T_.max_cap);
       LAUNCH(K_LU, l, k_seg_lu_wave<T, 1><<<unsigned(ns), 64, size_t(seglu_wave_lds_doubles(nw)) * 8, st>>>(
           segs, ns, blks, iar, var, d, status, 0, nw, l));
@@ -1204,10 +1179,6 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       else {
         // LDS for the level's largest task (accumulator and the two factors
         // of a term), at most one group per CU
-        static const bool melim_lds_ok =
-            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_merge_elim<T, WG>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(MELIM_MAX_BYTES)) == hipSuccess;
-        if (!melim_lds_ok) return fail(SPALU_EDEVICE, "cannot raise the LDS limit of the merge kernel");
         const size_t cap = size_t(T_.max_cap);
         const size_t need = ((cap * cap * 8 + 15) & ~size_t(15)) + 2 * cap * cap * sizeof(T);
         const size_t lb = std::min(MELIM_MAX_BYTES, std::max(MELIM_LDS_BYTES, need));
@@ -1217,9 +1188,100 @@ int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) 
       }
     }
   }
+  return SPALU_OK;
+}
+
+// Raises the LDS limits of the factorization kernels that take more than
+// 64 KB (once per process and storage type, before any launch or capture).
+template <typename T>
+int factor_kernel_setup() {
+  static const bool ok = [] {
+    auto lds = [](const void* k, size_t b) {
+      return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(b)) == hipSuccess;
+    };
+    bool r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B_WAVES, 2, false, 2>), ID_B_MAX_BYTES);
+    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B2_WAVES, 2, false, 3>), ID_B2_MAX_BYTES) && r;
+    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 4, true>), ID_B2_MAX_BYTES) && r;
+    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 6>), ID_B2_MAX_BYTES) && r;
+    r = lds(reinterpret_cast<const void*>(&k_seg_lu<T, SEGLU_BLOCK_NT>), SEGLU_MAX_BYTES) && r;
+    r = lds(reinterpret_cast<const void*>(&k_merge_elim<T, WG>), MELIM_MAX_BYTES) && r;
+    return r;
+  }();
+  return ok ? int(SPALU_OK) : fail(SPALU_EDEVICE, "cannot raise the LDS limit of a factorization kernel");
+}
+
+// Everything a factorization's launches bake in: the workspace and matrix
+// pointers, the layout and every option.
+std::vector<uint64_t> factor_graph_key(const spalu_factor_t* F, const spalu_factor_opts& o) {
+  auto u = [](const void* p) { return uint64_t(reinterpret_cast<uintptr_t>(p)); };
+  auto d = [](double x) {
+    uint64_t b;
+    std::memcpy(&b, &x, 8);
+    return b;
+  };
+  return {u(F->ws), u(F->rowptr), u(F->colind), u(F->vals), uint64_t(F->n), u(F->lay), uint64_t(o.precision),
+          d(o.eps), uint64_t(o.seed), d(o.rho), uint64_t(uint32_t(o.h0)), uint64_t(uint32_t(o.probes)), d(o.tau),
+          u(o.h_init), u(o.rank_model), u(o.features_out), d(o.rank_margin), uint64_t(uint32_t(o.rank_pad)),
+          d(o.rank_skip)};
+}
+
+// A factorization: its launches issued directly on the factor's stream,
+// or (with o.graph, profiling off) replayed from a HIP graph captured the
+// first time these pointers and options are seen; then the status and the
+// per-level sizes come back to the host.
+template <typename T>
+int run_factor(spalu_factor_t* F, const spalu_factor_opts& o, int* status_host) {
+  spalu_nd_t* nd = const_cast<spalu_nd_t*>(F->nd);
+  FactorStreams& FS = nd->fs;
+  if (!FS.fork) {
+    HIPCHK(hipEventCreateWithFlags(&FS.fork, hipEventDisableTiming));
+    for (int i = 0; i < 3; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&FS.aux[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&FS.join[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&FS.lu_done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&FS.msize_done, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&FS.pre_done, hipEventDisableTiming));
+  }
+  F->fs = &FS;
+  int rc = factor_kernel_setup<T>();
+  if (rc) return rc;
+  hipStream_t st = F->stream;
+  if (o.graph && !g_prof.on) {
+    const std::vector<uint64_t> key = factor_graph_key(F, o);
+    hipGraphExec_t exec = nullptr;
+    for (auto& gph : nd->fgraphs)
+      if (gph.key == key) exec = gph.exec;
+    if (!exec) {
+      if (!nd->capture_stream) HIPCHK(hipStreamCreateWithFlags(&nd->capture_stream, hipStreamNonBlocking));
+      hipStream_t cs = nd->capture_stream;
+      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      rc = issue_factor<T>(F, o, cs);
+      hipGraph_t graph_ = nullptr;
+      const hipError_t e = hipStreamEndCapture(cs, &graph_);
+      if (rc) {
+        if (graph_) (void)hipGraphDestroy(graph_);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(SPALU_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      const hipError_t e2 = hipGraphInstantiate(&exec, graph_, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph_);
+      if (e2 != hipSuccess) return fail(SPALU_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+      if (nd->fgraphs.size() >= 4) {
+        (void)hipGraphExecDestroy(nd->fgraphs.front().exec);
+        nd->fgraphs.erase(nd->fgraphs.begin());
+      }
+      nd->fgraphs.push_back(FactorGraph{key, exec});
+    }
+    HIPCHK(hipGraphLaunch(exec, st));
+  } else {
+    rc = issue_factor<T>(F, o, st);
+    if (rc) return rc;
+  }
+  const int* status = reinterpret_cast<const int*>(F->ws + F->lay->o_status);
   HIPCHK(hipMemcpyAsync(status_host, status, 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  const int rc = read_dyn_host(F);
+  rc = read_dyn_host(F);
   if (rc) return rc;
   prof_flush(F, 0);
   return SPALU_OK;
@@ -1733,6 +1795,7 @@ void spalu_factor_opts_default(spalu_factor_opts* o) {
   o->rank_margin = 1.0f;
   o->rank_pad = 5;
   o->rank_skip = 0.5f;
+  o->graph = 0;
 }
 
 static const Layout* get_layout(const spalu_nd_t* nd, int prec) {
@@ -1785,7 +1848,7 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   if (opts) o = *opts;
   if (o.precision != SPALU_FP64 && o.precision != SPALU_FP32) return fail(SPALU_EINVAL, "bad precision");
   if (!(o.eps >= 0.0) || !(o.rho >= 0.0) || o.h0 < 1 || o.probes < 1 || o.probes > 8 || !(o.tau > 0.0) ||
-      !(o.rank_margin > 0.0f) || o.rank_pad < 1 || !(o.rank_skip >= 0.0f))
+      !(o.rank_margin > 0.0f) || o.rank_pad < 1 || !(o.rank_skip >= 0.0f) || (o.graph != 0 && o.graph != 1))
     return fail(SPALU_EINVAL, "bad factor options");
   const Layout* Y;
   try {

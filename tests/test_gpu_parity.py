@@ -272,6 +272,45 @@ def test_graph_replays_match_direct_launches(S):
         assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
 
 
+@pytest.mark.parametrize("form", ["plain", "learned"])
+def test_factor_graph_replays_match_direct_launches(S, form):
+    """The factorization's level sweep captured as a HIP graph (first call
+    with a workspace and options) and replayed (later calls) gives bitwise
+    the factor of direct launches: sizes, ranks, samples and passes, and
+    the direct solve.  Eager work and synchronisations run between the
+    replays, and a change of options on the same workspace captures a new
+    graph.  The learned form's predictions run on a side stream inside the
+    graph."""
+    import torch
+    from paper_2408_14193_amd import rank_model
+    print("case factor graph form=%s" % form, flush=True)
+    P = make_config(2, side=127, nrhs=2)
+    nd = S.ND(P.dims)
+    rp, ci, v, B = to_device(P)
+    kw = dict(precision=S.FP64) if form == "plain" else dict(precision=S.FP32, rank_model=rank_model.load())
+    Bt = B.t().contiguous()
+
+    def result(F):
+        X = torch.empty_like(Bt)
+        F.solve_into(Bt, X, tol=0.0, max_iter=1, graph=False)
+        torch.cuda.synchronize()
+        return F.ranks(), X.cpu().numpy()
+
+    ws = None
+    for eps in (P.eps, 10 * P.eps):
+        ref_ranks, ref_x = result(S.Factor(nd, rp, ci, v, eps=eps, **kw))
+        for rep in range(3):
+            F = S.Factor(nd, rp, ci, v, eps=eps, graph=True, workspace=ws, **kw)
+            ws = F.workspace
+            ranks, x = result(F)
+            for a, b in zip(ranks, ref_ranks):
+                assert np.array_equal(a, b), "eps %g replay %d: ranks differ" % (eps, rep)
+            assert np.array_equal(x, ref_x), "eps %g replay %d: solve differs" % (eps, rep)
+            # eager work on the same stream between replays
+            (Bt * 2.0).sum().item()
+            del F
+
+
 def _id_work(S):
     """Algorithmic bytes per ID launch kind since profiling was switched on
     (work is credited to the tier that took each segment)."""
