@@ -11,13 +11,14 @@ Default workload: the non-symmetric convection-diffusion operator
 -0.01 Lap u + (1, 0.5) . grad u, first-order upwind, on the 2047 x 2047
 interior grid (N = 4,190,209), eps = 1e-5, 64 right-hand sides uniform in
 [-1, 1], refinement to 1e-8.  The headline `value` is the learned form:
-FP32 storage of the factor (FP64 arithmetic in the kernels, FP64 pivoted LU
-of diagonal blocks, ID triangular solve and refinement residual), the solve
-sweeps captured as a HIP graph, and the trained rank predictor choosing each
-segment's first sample count or keeping a segment whole when it predicts no
-compression.  Beside it: the mixed form (the same without the predictor)
-and the plain form (FP64 storage, adaptive sampling, direct per-level
-launches).
+FP32 storage of the factor and FP32 MFMA separator Schur products (FP64
+pivoted LU of diagonal blocks, ID CPQR and triangular solve, and refinement
+residual), the solve sweeps captured as a HIP graph, and the trained rank
+predictor choosing each segment's first sample count or keeping a segment
+whole when it predicts no compression.  Beside it: the mixed form (the same
+without the predictor) and the plain form (FP64 storage and FP64 MFMA,
+adaptive sampling, direct per-level launches).  Each form uses the launch
+shapes the autotuner cached for its workload, if any.
 """
 from __future__ import annotations
 
@@ -47,6 +48,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="direct launches in every form")
+    ap.add_argument("--tune", action="store_true",
+                    help="search the launch shapes of each form before its warm-up (untimed) and cache them")
+    ap.add_argument("--no-tuning", action="store_true", help="the library's default launch shapes, not the cache")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device (4 dispatches of a plain copy kernel), to scale "
                          "the FETCH_SIZE / WRITE_SIZE counters of a counter run")
@@ -62,7 +66,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8, rho=0.5):
+def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8, rho=0.5, tuning="cache"):
     import numpy as np
     import torch
     prec = S.FP64 if form == "plain" else S.FP32
@@ -85,6 +89,25 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8,
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return F, info, rr, t1 - t0, t2 - t1
+
+    # launch shapes: the autotuner's cached choice for this workload (or,
+    # with --tune, a fresh search before the warm-up), else the defaults
+    from paper_2408_14193_amd import autotune
+    key = autotune.workload_key(P.dims, prec, form == "learned", P.nrhs, P.eps)
+    if tuning == "tune":
+        def one():
+            t = time.perf_counter()
+            F, info, rr, _, _ = step()
+            del F
+            return time.perf_counter() - t, bool(info["converged"])
+        shapes, source = autotune.tune(one, key, reps=3, log=log), "tuned"
+    else:
+        shapes = autotune.apply_cached(key) if tuning == "cache" else None
+        source = "cache" if shapes is not None else "default"
+        if shapes is None:
+            shapes = S.set_tuning(**S.tuning_default())
+    changed = {k: v for k, v in shapes.items() if v != S.tuning_default()[k]}
+    log("[%s] launch shapes: %s %s" % (form, source, changed or "(defaults)"))
 
     # with profiling, the last warm-up step (untimed) times every kernel to
     # find the dominant one; the timed steps carry the events of that kernel
@@ -136,7 +159,8 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8,
                 refine_iters=its, max_rel_residual=max(res), factor_info=finfo,
                 converged=all(r <= tol for r in res), profile=prof,
                 breakdown=breakdown if breakdown is not None else prof,
-                breakdown_steps=1 if breakdown is not None else steps)
+                breakdown_steps=1 if breakdown is not None else steps,
+                tuning=dict(source=source, key=key, changed=changed))
 
 
 def measured_traffic(name, form):
@@ -251,7 +275,8 @@ def main():
     res = {}
     for i, f in enumerate(forms):
         res[f] = run_form(S, P, nd, dev, f, a.steps, a.warmup, profile=(i == 0), graph=not a.no_graph,
-                          restart=a.restart, rho=a.rho)
+                          restart=a.restart, rho=a.rho,
+                          tuning="tune" if a.tune else "off" if a.no_tuning else "cache")
     head = forms[0]
     r = res[head]
     value = P.n / (r["ms_per_step"] * 1e-3)
@@ -283,6 +308,7 @@ def main():
         "refine_iters": r["refine_iters"],
         "max_rel_residual": r["max_rel_residual"],
         "converged": r["converged"],
+        "launch_shapes": r["tuning"],
         "roofline": roof,
         # per-kernel event times of one fully profiled, untimed warm-up step
         "kernel_ms_per_step": {k: round(v["ms"] / bsteps, 4) for k, v in
@@ -298,7 +324,8 @@ def main():
         out["%s_form" % f] = {"value": round(vf, 1), "ms_per_step": round(rf["ms_per_step"], 3),
                               "factor_ms": round(rf["factor_ms"], 3), "solve_ms": round(rf["solve_ms"], 3),
                               "refine_iters": rf["refine_iters"],
-                              "max_rel_residual": rf["max_rel_residual"], "converged": rf["converged"]}
+                              "max_rel_residual": rf["max_rel_residual"], "converged": rf["converged"],
+                              "launch_shapes": rf["tuning"]}
         out["ratio_%s_vs_%s" % (head, f)] = round(value / vf, 3)
     if not a.no_cpu:
         log("cpu baseline: oracle on a %dx%d sample ..." % (a.cpu_side, a.cpu_side))

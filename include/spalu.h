@@ -165,6 +165,36 @@ typedef struct {
  * tau 1, no rank predictor, margin 1.0, pad 5, skip 0.5, no graph). */
 void spalu_factor_opts_default(spalu_factor_opts* o);
 
+/* Launch-shape choices of the factorization and the solve, for callers that
+ * tune them (the package's autotuner): they change how the work of a level is
+ * mapped onto workgroups, not what is computed (results may differ by
+ * rounding where a segment moves to a tier with another summation order).
+ * Process-wide; factorizations started after spalu_tuning_set use them. */
+typedef struct {
+  int32_t id_lds_a;        /* LDS bytes of ID tier A (one wave per segment),
+                              4096..65536; default 24576                    */
+  int32_t id_lds_b;        /* tier B (four waves), 16384..155648; default 73728 */
+  int32_t id_lds_b2;       /* tier B2 (eight waves), 16384..155648; default 155648 */
+  int32_t id_lds_c;        /* tier C (eight waves, rows of Y beyond it in
+                              scratch), 32768..155648; default 155648       */
+  int32_t id_c_ydiv;       /* tier C keeps far rows and row tables in LDS when
+                              they leave room for max(n, R / id_c_ydiv) rows
+                              of Y: 1, 2 or 4; default 2                    */
+  int32_t melim_lds;       /* least LDS of a 256-thread merge group,
+                              16384..155648; default 65536                  */
+  int32_t melim_wave_cap;  /* merge targets of at most this many DOFs take one
+                              wave each, 8..32; default 32                   */
+  int32_t solve_lanes_min; /* narrowest lane group of the solve sweeps (8, 16,
+                              32 or 64); default 8                           */
+  int32_t solve_lanes_max; /* widest (levels with larger segments take the
+                              block kernels); default 64                     */
+} spalu_tuning;
+
+void spalu_tuning_default(spalu_tuning* t);
+int spalu_tuning_get(spalu_tuning* t);
+/* SPALU_EINVAL (nothing changed) when a value is out of range. */
+int spalu_tuning_set(const spalu_tuning* t);
+
 /* Bytes of device workspace that spalu_factor needs for this ND and
  * options (static layout sized by uncompressed segment sizes). */
 int spalu_factor_workspace(const spalu_nd_t* nd, const spalu_factor_opts* opts, size_t* bytes);

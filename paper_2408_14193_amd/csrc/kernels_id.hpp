@@ -78,17 +78,20 @@ struct IdTiers {
   int budget_b2;  // LDS bytes of the tier-B2 launch (one group per CU)
   int st;         // bytes of the storage type
   int lds_c;      // LDS bytes of the tier-C launch (Y of the passes that fit)
+  int c_ydiv;     // tier C keeps its far rows and tables in LDS when they
+                  // leave room for max(n, R / c_ydiv) rows of Y
 };
 
 // Tier of a segment that gets an ID, from its sizes (n columns, R rows):
 // 1: tier A, 2: B, 3: B2, 4: C with the far rows and row tables in LDS
-// (when they leave room there for max(n, R / 2) rows of Y), 6: C with them
-// in global scratch, 5: block-cooperative kernel.
+// (when they leave room there for max(n, R / c_ydiv) rows of Y), 6: C with
+// them in global scratch, 5: block-cooperative kernel.
 __host__ __device__ inline int id_tier_of_size(int n, int R, IdTiers t) {
   if (n <= 64 && idc_lds_bytes(1, 1, n, R, t.st, true) <= size_t(t.budget_a)) return 1;
   if (n <= 128 && idc_lds_bytes(ID_B_WAVES, 2, n, R, t.st, true) <= size_t(t.budget_b)) return 2;
   if (n <= 128 && idc_lds_bytes(ID_B2_WAVES, 2, n, R, t.st, true) <= size_t(t.budget_b2)) return 3;
-  const size_t yrows = size_t(n > R / 2 ? n : R / 2);
+  const int ry = R / t.c_ydiv;
+  const size_t yrows = size_t(n > ry ? n : ry);
   if (n <= 128 && idc_lds_bytes(ID_B2_WAVES, 2, n, 0, t.st, false) + idc_table_bytes(n, R, t.st) +
                       yrows * n * 8 <= size_t(t.lds_c))
     return 4;

@@ -57,7 +57,8 @@ struct LevelTabs {
   size_t o_segs = 0, o_nbrs = 0, o_blks = 0, o_scale = 0, o_cons_ptr = 0, o_cons = 0, o_task_ptr = 0,
          o_tasks = 0, o_terms = 0, o_dyn = 0;
   // ID launches of the level (bounds from the uncompressed sizes)
-  IdTiers tiers{0, 0, 0, 8};
+  IdTiers tiers{0, 0, 0, 8, 0, 2};
+  int tiers_gen = -1;  // tuning generation the tiers were planned with
   bool id_b = false, id_b2 = false, id_c = false, id_cg = false, id_old = false;
   int max_cap = 0;  // largest uncompressed segment
   int max_nbrs = 0;          // largest neighbour count of a segment
@@ -195,59 +196,65 @@ namespace {
 
 // LDS limits of the column-parallel ID tiers (bytes of dynamic LDS; a gfx950
 // workgroup may hold up to 160 KB).
-constexpr size_t ID_A_MAX_BYTES = 24 * 1024;    // 64-thread groups: six or more per CU
-constexpr size_t ID_B_MAX_BYTES = 72 * 1024;    // 256-thread groups: two per CU
-constexpr size_t ID_B2_MAX_BYTES = 152 * 1024;  // tier-B2 groups: one per CU
+constexpr size_t ID_LDS_LIMIT = 152 * 1024;  // largest LDS of one group (one per CU)
 constexpr size_t SEGLU_MAX_BYTES = 152 * 1024;   // segment LU of large segments
 constexpr int SEGLU_WAVE_MAX_N = 32;             // segments up to this size: one wave each
 constexpr int SEGLU_BLOCK_NT = 256;              // threads of the block segment LU (one block per CU)
-constexpr size_t MELIM_LDS_BYTES = 64 * 1024;   // staged separator terms of the merge (at least)
-constexpr size_t MELIM_MAX_BYTES = 152 * 1024;  // (at most: one group per CU)
+constexpr size_t MELIM_MAX_BYTES = 152 * 1024;  // staged separator terms of the merge (at most: one group per CU)
+
+// Launch-shape choices (the autotuner's search space); the defaults are the
+// measured hand choices: ID tier A groups of at most 24 KB (six or more per
+// CU), tier B 72 KB (two per CU), B2 and C 152 KB (one per CU).
+spalu_tuning g_tuning = {24 * 1024, 72 * 1024, 152 * 1024, 152 * 1024, 2, 64 * 1024, 32, 8, 64};
+int g_tuning_gen = 0;
 
 // Which ID launches a level needs and their LDS budgets.  The sizes known
 // here (uncompressed n, coupling-row bound rcap) bound the ones the kernels
 // see, so a segment whose bound fits a tier certainly lands in it; the
 // kernels themselves decide with the actual sizes.
 void plan_id_tiers(LevelTabs& T, int st) {
+  const spalu_tuning& tu = g_tuning;
   size_t a = 0, b = 0, b2 = 0;
   bool beyond_a = false, beyond_b = false, beyond_b2 = false, tabs_global = false, wide = false;
   for (const DSeg& D : T.segs) {
     if (!((D.flags & SEG_REGULAR) && (D.flags & SEG_HAS_NBR))) continue;
     const int cap = D.cap, R = D.rcap;
     const size_t na = idc_lds_bytes(1, 1, std::min(cap, 64), R, st, true);
-    if (cap <= 64 && na <= ID_A_MAX_BYTES) {
+    if (cap <= 64 && na <= size_t(tu.id_lds_a)) {
       a = std::max(a, na);
       continue;
     }
     beyond_a = true;
     const size_t nb = idc_lds_bytes(ID_B_WAVES, 2, std::min(cap, 128), R, st, true);
-    if (cap <= 128 && nb <= ID_B_MAX_BYTES) {
+    if (cap <= 128 && nb <= size_t(tu.id_lds_b)) {
       b = std::max(b, nb);
       continue;
     }
     beyond_b = true;
     const size_t nb2 = idc_lds_bytes(ID_B2_WAVES, 2, std::min(cap, 128), R, st, true);
-    if (cap <= 128 && nb2 <= ID_B2_MAX_BYTES) {
+    if (cap <= 128 && nb2 <= size_t(tu.id_lds_b2)) {
       b2 = std::max(b2, nb2);
       continue;
     }
     beyond_b2 = true;
     const int nc = std::min(cap, 128);
     if (idc_lds_bytes(ID_B2_WAVES, 2, nc, 0, st, false) + idc_table_bytes(nc, R, st) +
-            size_t(std::max(nc, R / 2)) * nc * 8 > ID_B2_MAX_BYTES)
+            size_t(std::max(nc, R / tu.id_c_ydiv)) * nc * 8 > size_t(tu.id_lds_c))
       tabs_global = true;
     if (cap > 128) wide = true;
   }
   // segments beyond a tier by bound may still land in it by their actual
   // sizes: such levels give the tier its full budget
-  if (beyond_a) a = ID_A_MAX_BYTES;
-  if (beyond_b) b = ID_B_MAX_BYTES;
-  if (beyond_b2) b2 = ID_B2_MAX_BYTES;
+  if (beyond_a) a = size_t(tu.id_lds_a);
+  if (beyond_b) b = size_t(tu.id_lds_b);
+  if (beyond_b2) b2 = size_t(tu.id_lds_b2);
   T.tiers.st = st;
   T.tiers.budget_a = int(std::max(a, idc_lds_bytes(1, 1, 1, 2, st, true)));
   T.tiers.budget_b = int(std::max(b, idc_lds_bytes(ID_B_WAVES, 2, 1, 2, st, true)));
   T.tiers.budget_b2 = int(std::max(b2, idc_lds_bytes(ID_B2_WAVES, 2, 1, 2, st, true)));
-  T.tiers.lds_c = int(ID_B2_MAX_BYTES);
+  T.tiers.lds_c = tu.id_lds_c;
+  T.tiers.c_ydiv = tu.id_c_ydiv;
+  T.tiers_gen = g_tuning_gen;
   T.id_b = beyond_a;
   T.id_b2 = beyond_b;
   T.id_c = beyond_b2;
@@ -946,7 +953,9 @@ int read_dyn_host(spalu_factor_t* F) {
       for (int e = ap[c]; e < ap[c + 1]; ++e) r += kv[ad[e]];
       rows = std::max(rows, r);
     }
-    const int P = mx <= 8 ? 8 : mx <= 16 ? 16 : mx <= 32 ? 32 : mx <= 64 ? 64 : 0;
+    int P = g_tuning.solve_lanes_min;
+    while (P < mx) P *= 2;
+    if (P > g_tuning.solve_lanes_max) P = 0;
     if (P && size_t(64 / P) * seg_solve_grp_bytes(P, vs) <= 65536 &&
         size_t(64 / P) * sep_grp_bytes(P, rows, vs) <= 65536)
       F->solve_P[l] = P;
@@ -1168,7 +1177,7 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
       DLevelDyn du = dyn_of(ws, Y, l - 1);
       HIPCHK(hipStreamWaitEvent(st, F->fs->msize_done, 0));
       // blocks of small segments: one wave each
-      if (U.max_cap <= 32) {
+      if (U.max_cap <= g_tuning.melim_wave_cap) {
         // staged terms with LDS for this level's largest skeletons
         const int cap = T_.max_cap;
         const int lb = ((cap * cap * 8 + 15) & ~15) + 2 * cap * cap * int(sizeof(T));
@@ -1181,7 +1190,7 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
         // of a term), at most one group per CU
         const size_t cap = size_t(T_.max_cap);
         const size_t need = ((cap * cap * 8 + 15) & ~size_t(15)) + 2 * cap * cap * sizeof(T);
-        const size_t lb = std::min(MELIM_MAX_BYTES, std::max(MELIM_LDS_BYTES, need));
+        const size_t lb = std::min(MELIM_MAX_BYTES, std::max(size_t(g_tuning.melim_lds), need));
         LAUNCH(K_MELIM, l, k_merge_elim<T, WG><<<unsigned(U.blks.size()), WG, lb, st>>>(
             tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
             tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du, int(lb)));
@@ -1199,10 +1208,11 @@ int factor_kernel_setup() {
     auto lds = [](const void* k, size_t b) {
       return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(b)) == hipSuccess;
     };
-    bool r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B_WAVES, 2, false, 2>), ID_B_MAX_BYTES);
-    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B2_WAVES, 2, false, 3>), ID_B2_MAX_BYTES) && r;
-    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 4, true>), ID_B2_MAX_BYTES) && r;
-    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 6>), ID_B2_MAX_BYTES) && r;
+    bool r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, 1, 1, false, 1>), 64 * 1024);
+    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B_WAVES, 2, false, 2>), ID_LDS_LIMIT) && r;
+    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, ID_B2_WAVES, 2, false, 3>), ID_LDS_LIMIT) && r;
+    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 4, true>), ID_LDS_LIMIT) && r;
+    r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 6>), ID_LDS_LIMIT) && r;
     r = lds(reinterpret_cast<const void*>(&k_seg_lu<T, SEGLU_BLOCK_NT>), SEGLU_MAX_BYTES) && r;
     r = lds(reinterpret_cast<const void*>(&k_merge_elim<T, WG>), MELIM_MAX_BYTES) && r;
     return r;
@@ -1222,7 +1232,7 @@ std::vector<uint64_t> factor_graph_key(const spalu_factor_t* F, const spalu_fact
   return {u(F->ws), u(F->rowptr), u(F->colind), u(F->vals), uint64_t(F->n), u(F->lay), uint64_t(o.precision),
           d(o.eps), uint64_t(o.seed), d(o.rho), uint64_t(uint32_t(o.h0)), uint64_t(uint32_t(o.probes)), d(o.tau),
           u(o.h_init), u(o.rank_model), u(o.features_out), d(o.rank_margin), uint64_t(uint32_t(o.rank_pad)),
-          d(o.rank_skip)};
+          d(o.rank_skip), uint64_t(g_tuning_gen)};
 }
 
 // A factorization: its launches issued directly on the factor's stream,
@@ -1798,6 +1808,31 @@ void spalu_factor_opts_default(spalu_factor_opts* o) {
   o->graph = 0;
 }
 
+void spalu_tuning_default(spalu_tuning* t) {
+  if (t) *t = spalu_tuning{24 * 1024, 72 * 1024, 152 * 1024, 152 * 1024, 2, 64 * 1024, 32, 8, 64};
+}
+
+int spalu_tuning_get(spalu_tuning* t) {
+  if (!t) return fail(SPALU_EINVAL, "t is NULL");
+  *t = g_tuning;
+  return SPALU_OK;
+}
+
+int spalu_tuning_set(const spalu_tuning* t) {
+  if (!t) return fail(SPALU_EINVAL, "t is NULL");
+  const int64_t lim = int64_t(ID_LDS_LIMIT);
+  auto in = [](int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi; };
+  auto pow2 = [](int v) { return v == 8 || v == 16 || v == 32 || v == 64; };
+  if (!in(t->id_lds_a, 4096, 65536) || !in(t->id_lds_b, 16384, lim) || !in(t->id_lds_b2, 16384, lim) ||
+      !in(t->id_lds_c, 32768, lim) || !(t->id_c_ydiv == 1 || t->id_c_ydiv == 2 || t->id_c_ydiv == 4) ||
+      !in(t->melim_lds, 16384, lim) || !in(t->melim_wave_cap, 8, 32) || !pow2(t->solve_lanes_min) ||
+      !pow2(t->solve_lanes_max) || t->solve_lanes_min > t->solve_lanes_max)
+    return fail(SPALU_EINVAL, "tuning value out of range");
+  g_tuning = *t;
+  ++g_tuning_gen;
+  return SPALU_OK;
+}
+
 static const Layout* get_layout(const spalu_nd_t* nd, int prec) {
   spalu_nd_t* m = const_cast<spalu_nd_t*>(nd);
   if (!m->layout[prec]) m->layout[prec] = build_layout(nd->plan, prec);
@@ -1857,6 +1892,11 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
     return fail(SPALU_EUNSUPPORTED, e.what());
   }
   if (workspace_bytes < Y->bytes) return fail(SPALU_ENOMEM, "workspace too small");
+  if (Y->lv[nd->plan.L].tiers_gen != g_tuning_gen) {
+    // the launch shapes were changed since this layout's tiers were planned
+    Layout* YT = const_cast<Layout*>(Y);
+    for (int l = 1; l <= nd->plan.L; ++l) plan_id_tiers(YT->lv[l], o.precision == SPALU_FP32 ? 4 : 8);
+  }
   auto F = std::make_unique<spalu_factor_t>();
   F->nd = nd;
   F->lay = Y;

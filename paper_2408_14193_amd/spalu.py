@@ -50,6 +50,16 @@ class FactorOpts(C.Structure):
                 ("rank_skip", C.c_float), ("graph", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("id_lds_a", C.c_int32), ("id_lds_b", C.c_int32), ("id_lds_b2", C.c_int32),
+                ("id_lds_c", C.c_int32), ("id_c_ydiv", C.c_int32), ("melim_lds", C.c_int32),
+                ("melim_wave_cap", C.c_int32), ("solve_lanes_min", C.c_int32),
+                ("solve_lanes_max", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class FactorInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("levels", C.c_int32), ("segments", C.c_int64),
                 ("sparsified", C.c_int64), ("sample_passes", C.c_int64),
@@ -87,6 +97,10 @@ _lib.spalu_nd_free.restype = None
 _lib.spalu_factor_opts_default.argtypes = [C.POINTER(FactorOpts)]
 _lib.spalu_factor_opts_default.restype = None
 _lib.spalu_factor_workspace.argtypes = [P, C.POINTER(FactorOpts), C.POINTER(C.c_size_t)]
+_lib.spalu_tuning_default.argtypes = [C.POINTER(Tuning)]
+_lib.spalu_tuning_default.restype = None
+_lib.spalu_tuning_get.argtypes = [C.POINTER(Tuning)]
+_lib.spalu_tuning_set.argtypes = [C.POINTER(Tuning)]
 _lib.spalu_factor_seg_base.argtypes = [P, I64P]
 _lib.spalu_factor.argtypes = [P, C.c_int64, P, P, P, C.POINTER(FactorOpts), P, C.c_size_t, P,
                               C.POINTER(P), C.POINTER(FactorInfo)]
@@ -120,7 +134,7 @@ EXPORTED = ["spalu_nd_order", "spalu_nd_info", "spalu_nd_perm", "spalu_nd_etree"
             "spalu_nd_segments", "spalu_nd_free", "spalu_factor_opts_default",
             "spalu_factor_workspace", "spalu_factor_seg_base", "spalu_factor",
             "spalu_factor_ranks", "spalu_factor_work", "spalu_factor_free", "spalu_solve_workspace", "spalu_solve",
-            "spalu_solve_static",
+            "spalu_solve_static", "spalu_tuning_default", "spalu_tuning_get", "spalu_tuning_set",
             "spalu_mlp_param_count", "spalu_mlp_workspace", "spalu_mlp_forward",
             "spalu_mlp_train_step", "spalu_profile", "spalu_profile_only", "spalu_profile_read",
             "spalu_last_error"]
@@ -207,6 +221,32 @@ def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, ta
     o.rank_margin, o.rank_pad, o.rank_skip = float(rank_margin), int(rank_pad), float(rank_skip)
     o.graph = 1 if graph else 0
     return o
+
+
+def tuning_default():
+    """The library's default launch shapes (a dict of spalu_tuning)."""
+    t = Tuning()
+    _lib.spalu_tuning_default(C.byref(t))
+    return t.as_dict()
+
+
+def get_tuning():
+    """The launch shapes in use (a dict of spalu_tuning)."""
+    t = Tuning()
+    _check(_lib.spalu_tuning_get(C.byref(t)))
+    return t.as_dict()
+
+
+def set_tuning(**kw):
+    """Changes the named launch shapes (the others keep their values) for
+    the factorizations started afterwards; returns the full set."""
+    cur = get_tuning()
+    unknown = set(kw) - set(cur)
+    if unknown:
+        raise KeyError("unknown tuning fields: %s" % sorted(unknown))
+    cur.update({k: int(v) for k, v in kw.items()})
+    _check(_lib.spalu_tuning_set(C.byref(Tuning(**cur))))
+    return cur
 
 
 def factor_workspace_bytes(nd, opts):

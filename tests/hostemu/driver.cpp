@@ -75,6 +75,16 @@ int main(int argc, char** argv) {
   o.precision = prec == 32 ? SPALU_FP32 : SPALU_FP64;
   if (model) o.rank_model = to_guarded(pm);
   if (const char* h0 = std::getenv("EMU_H0")) o.h0 = std::atoi(h0);
+  if (const char* tu = std::getenv("EMU_TUNING")) {
+    // nine comma-separated spalu_tuning fields
+    spalu_tuning t;
+    int32_t* f = &t.id_lds_a;
+    for (int i = 0; i < 9; ++i) f[i] = std::atoi(tu), tu = std::strchr(tu, ',') ? std::strchr(tu, ',') + 1 : tu;
+    if (spalu_tuning_set(&t)) {
+      std::printf("tuning refused: %s\n", spalu_last_error());
+      return 1;
+    }
+  }
   size_t wb = 0;
   rc = spalu_factor_workspace(nd, &o, &wb);
   std::printf("workspace %zu bytes rc %d\n", wb, rc);

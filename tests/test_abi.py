@@ -90,3 +90,24 @@ def test_workspace_query_without_gpu():
     b64 = S.factor_workspace_bytes(nd, S.factor_opts(precision=S.FP64))
     b32 = S.factor_workspace_bytes(nd, S.factor_opts(precision=S.FP32))
     assert 0 < b32 < b64
+
+
+def test_tuning_roundtrip_and_validation():
+    """Launch shapes: the defaults are the library's, a change reads back,
+    an out-of-range value is refused and changes nothing."""
+    S = _lib()
+    d = S.tuning_default()
+    assert S.get_tuning() == d
+    try:
+        t = S.set_tuning(id_lds_c=80 * 1024, id_c_ydiv=4, solve_lanes_min=16)
+        assert S.get_tuning() == t and t["id_lds_c"] == 80 * 1024 and t["solve_lanes_min"] == 16
+        for bad in (dict(id_c_ydiv=3), dict(id_lds_a=1 << 20), dict(solve_lanes_min=64, solve_lanes_max=32),
+                    dict(melim_wave_cap=64), dict(solve_lanes_max=24)):
+            with pytest.raises(S.SpaluError):
+                S.set_tuning(**bad)
+            assert S.get_tuning() == t
+        with pytest.raises(KeyError):
+            S.set_tuning(no_such_field=1)
+    finally:
+        S.set_tuning(**d)
+    assert S.get_tuning() == d

@@ -388,6 +388,35 @@ def test_fp64_parity_with_exact_rows_split_between_lds_and_scratch(S):
     assert _col_err(X, O.apply_inverse(OF, P.rhs)).max() <= 1e-10
 
 
+def test_fp64_parity_under_the_smallest_launch_shapes(S):
+    """255 x 255 GRF diffusion in FP64 with the smallest launch shapes the
+    tuning API accepts (most IDs in tier C with little LDS, more block
+    kernels in the merge and the solve): sizes, ranks, samples and passes
+    equal the oracle's on every level and the direct solve equals the
+    oracle's per column within 1e-10, as with the default shapes."""
+    print("case smallest launch shapes fp64 cfg=1", flush=True)
+    P = make_config(1, side=255, nrhs=3)
+    d = S.tuning_default()
+    S.set_tuning(id_lds_a=4096, id_lds_b=16384, id_lds_b2=16384, id_lds_c=32768, id_c_ydiv=4,
+                 melim_lds=16384, melim_wave_cap=16, solve_lanes_min=16, solve_lanes_max=32)
+    try:
+        S.profile(True)
+        nd, F, B = gpu_factor(S, P, eps=P.eps, seed=1234)
+        work = _id_work(S)
+        S.profile(False)
+        print("ID work by tier:", work)
+        assert work.get("seg_id_c", 0) > 0
+        X, info = gpu_solve(F, B)
+    finally:
+        S.set_tuning(**d)
+    OF = O.factor(nd_order(P.dims), P.scipy(), O.Opts(eps=P.eps, seed=1234))
+    ora = _oracle_ranks(OF, nd)
+    stable = oracle_stable_levels(P, nd, ora, P.eps)
+    assert len(stable) == nd.L
+    compare_ranks(nd, F.ranks(), ora, stable)
+    assert _col_err(X, O.apply_inverse(OF, P.rhs)).max() <= 1e-10
+
+
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_fp32_parity_where_the_wide_id_tiers_run(S, cfg):
     """255 x 255 with FP32 storage (mixed form): the tier with its rows in

@@ -41,10 +41,12 @@ def _write(P, d, params=None):
     (params if params is not None else np.zeros(1, np.float32)).tofile(os.path.join(d, "params.bin"))
 
 
-def _run(exe, d, prec, model, eps, nrhs, tol, restart, h0=None):
+def _run(exe, d, prec, model, eps, nrhs, tol, restart, h0=None, tuning=None):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
     if h0 is not None:
         env["EMU_H0"] = str(h0)
+    if tuning is not None:
+        env["EMU_TUNING"] = ",".join(str(int(x)) for x in tuning)
     r = subprocess.run([exe, d, str(prec), str(model), repr(eps), str(nrhs), repr(tol), "1234", str(restart)],
                        capture_output=True, text=True, timeout=900, env=env)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
@@ -102,4 +104,23 @@ def test_exact_rows_split_between_lds_and_scratch(exe, tmp_path):
     P = make_config(4, side=127, nrhs=1)
     _write(P, str(tmp_path))
     it, first, final = _run(exe, str(tmp_path), 64, 0, P.eps, 2, 1e-10, 8, h0=100000)
+    assert final <= 1e-10
+
+
+# id_lds_a, id_lds_b, id_lds_b2, id_lds_c, id_c_ydiv, melim_lds, melim_wave_cap,
+# solve_lanes_min, solve_lanes_max: the smallest ID budgets (tier C without
+# room for min(m, n) rows of Y: all of Y in scratch), 256-thread merges from
+# 16 DOFs on, and lane groups of 16 to 32 only
+SMALL_SHAPES = (4096, 16384, 16384, 32768, 4, 16384, 16, 16, 32)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_smallest_launch_shapes(exe, tmp_path, prec):
+    """127 x 127 Helmholtz with the smallest launch shapes the tuning API
+    accepts: most IDs land in tier C with little LDS, the merge and the
+    solve take their block kernels on more levels (bounds checked here on
+    the CPU before any GPU run of these shapes)."""
+    P = make_config(4, side=127, nrhs=1)
+    _write(P, str(tmp_path))
+    it, first, final = _run(exe, str(tmp_path), prec, 0, P.eps, 2, 1e-10, 8, tuning=SMALL_SHAPES)
     assert final <= 1e-10
