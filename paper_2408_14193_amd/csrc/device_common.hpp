@@ -138,6 +138,24 @@ __device__ inline void gauss_pair(uint32_t seed, int level, int stream, int pair
   *odd = r * sin(ang);
 }
 
+// The same pair with the Box-Muller step in single precision (the uniforms
+// rounded to float): for factors stored in FP32, whose far rows carry FP32
+// rounding already.
+__device__ inline void gauss_pair_f32(uint32_t seed, int level, int stream, int pair, int vert, int seg, int half,
+                                      float* even, float* odd) {
+  uint32_t c[4] = {uint32_t(pair), uint32_t(vert), uint32_t(seg), uint32_t(half)};
+  philox4x32_10(c, seed, uint32_t(2 * level + stream));
+  const uint64_t a = ((uint64_t(c[1]) << 32) | c[0]) >> 11;
+  const uint64_t b = ((uint64_t(c[3]) << 32) | c[2]) >> 11;
+  const float u1 = float(double(a) * 0x1p-53 + 0x1p-54);
+  const float u2 = float(double(b) * 0x1p-53 + 0x1p-54);
+  const float r = sqrtf(-2.0f * logf(u1));
+  float sn, cs;
+  sincospif(2.0f * u2, &sn, &cs);
+  *even = r * cs;
+  *odd = r * sn;
+}
+
 // Normal number of row `row` for the DOF (vert, half) of segment `seg`:
 // key (seed, 2*level+stream), counter (row>>1, vert, seg, half), two 53-bit
 // uniforms, Box-Muller (cos branch for even rows, sin for odd).

@@ -475,21 +475,72 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
             double ev = 0.0, od = 0.0;
             if (ff < nF) {
               const int vh = rows[order[R - 1 - ff]].vh;
-              gauss_pair(prm.seed, prm.level, stream, pair, vh >> 1, c, vh & 1, &ev, &od);
+              if constexpr (sizeof(T) == 4) {
+                float e32, o32;
+                gauss_pair_f32(prm.seed, prm.level, stream, pair, vh >> 1, c, vh & 1, &e32, &o32);
+                ev = e32;
+                od = o32;
+              } else {
+                gauss_pair(prm.seed, prm.level, stream, pair, vh >> 1, c, vh & 1, &ev, &od);
+              }
             }
             Gw[2 * lane] = ev;
             Gw[2 * lane + 1] = od;
             wave_sync();
             const int fw = nF - f0 < 64 ? nF - f0 : 64;
-  #pragma unroll 4
-            for (int t = 0; t < fw; ++t) {
-              const double g0 = Gw[2 * t], g1 = Gw[2 * t + 1];
+            // columns past n read column n - 1 (their sums are never
+            // stored): no branch around the loads, so they go out together
+            const T* bf = BF + size_t(f0) * n;
+            int jc[NCOL];
   #pragma unroll
-              for (int s2 = 0; s2 < NCOL; ++s2) {
-                const int j = lane + 64 * s2;
-                const double b = j < n ? double(BF[size_t(f0 + t) * n + j]) : 0.0;
-                a0[s2] += g0 * b;
-                a1[s2] += g1 * b;
+            for (int s2 = 0; s2 < NCOL; ++s2) jc[s2] = lane + 64 * s2 < n ? lane + 64 * s2 : n - 1;
+            // FB far rows per batch, all loads first, then the products
+            // (tier C in FP64 keeps one row per step: the batch's registers
+            // would not fit beside its CPQR's)
+            constexpr bool BATCH = sizeof(T) == 4 || !YG;
+            constexpr int FB = sizeof(T) == 4 ? 8 : 4;
+            int t = 0;
+            if constexpr (BATCH)
+            for (; t + FB <= fw; t += FB) {
+              T bv[FB][NCOL];
+              double gv[2 * FB];
+  #pragma unroll
+              for (int u = 0; u < FB; ++u)
+  #pragma unroll
+                for (int s2 = 0; s2 < NCOL; ++s2) bv[u][s2] = bf[size_t(t + u) * n + jc[s2]];
+  #pragma unroll
+              for (int u = 0; u < 2 * FB; ++u) gv[u] = Gw[2 * t + u];
+  #pragma unroll
+              for (int u = 0; u < FB; ++u) {
+                const double g0 = gv[2 * u], g1 = gv[2 * u + 1];
+  #pragma unroll
+                for (int s2 = 0; s2 < NCOL; ++s2) {
+                  a0[s2] += g0 * double(bv[u][s2]);
+                  a1[s2] += g1 * double(bv[u][s2]);
+                }
+              }
+            }
+            if constexpr (BATCH) {
+              for (; t < fw; ++t) {
+                const double g0 = Gw[2 * t], g1 = Gw[2 * t + 1];
+  #pragma unroll
+                for (int s2 = 0; s2 < NCOL; ++s2) {
+                  const double b = double(bf[size_t(t) * n + jc[s2]]);
+                  a0[s2] += g0 * b;
+                  a1[s2] += g1 * b;
+                }
+              }
+            } else {
+  #pragma unroll 4
+              for (; t < fw; ++t) {
+                const double g0 = Gw[2 * t], g1 = Gw[2 * t + 1];
+  #pragma unroll
+                for (int s2 = 0; s2 < NCOL; ++s2) {
+                  const int j = lane + 64 * s2;
+                  const double b = j < n ? double(bf[size_t(t) * n + j]) : 0.0;
+                  a0[s2] += g0 * b;
+                  a1[s2] += g1 * b;
+                }
               }
             }
             wave_sync();

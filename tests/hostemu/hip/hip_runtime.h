@@ -15,6 +15,17 @@
 #include <functional>
 #include <vector>
 
+// sine and cosine of pi x (device math functions that the host library
+// does not provide)
+inline void sincospi(double x, double* s, double* c) {
+  *s = std::sin(M_PI * x);
+  *c = std::cos(M_PI * x);
+}
+inline void sincospif(float x, float* s, float* c) {
+  *s = std::sin(float(M_PI) * x);
+  *c = std::cos(float(M_PI) * x);
+}
+
 #define __global__
 #define __device__
 #define __host__
