@@ -415,14 +415,18 @@ __global__ __launch_bounds__(64) void k_leaf_solve_bwd_x(const DLeaf* leaves, in
         T xv[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t) xv[t] = Xt[size_t(b0 + t < nb ? b0 + t : nb - 1) * ni];
+        // rows past nb: row nb - 1 times zero (no branch around the loads)
 #pragma unroll
-        for (int t = 0; t < 16; ++t)
-          if (b0 + t < nb) {
-            const double a = double(xv[t]);
-            const double* xb = XB + (b0 + t) * CH;
+        for (int t = 0; t < 16; ++t) {
+          const bool in = b0 + t < nb;
+          const double a = in ? double(xv[t]) : 0.0;
+          const double* xb = XB + (in ? b0 + t : nb - 1) * CH;
+          double bv[CH];
 #pragma unroll
-            for (int j = 0; j < CH; ++j) y[j] = fma(-a, xb[j], y[j]);
-          }
+          for (int j = 0; j < CH; ++j) bv[j] = xb[j];
+#pragma unroll
+          for (int j = 0; j < CH; ++j) y[j] = fma(-a, bv[j], y[j]);
+        }
       }
       T* out = W + size_t(u) * nrhs + j0;
 #pragma unroll
@@ -499,8 +503,11 @@ __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nse
           for (int i = 0; i < k; ++i) {
             const double t = double(sT[i * ntr + lane]);
             const double* xs = X + (nr + i) * CH;
+            double xv[CH];
 #pragma unroll
-            for (int j = 0; j < CH; ++j) x[j] = fma(-t, xs[j], x[j]);
+            for (int j = 0; j < CH; ++j) xv[j] = xs[j];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) x[j] = fma(-t, xv[j], x[j]);
           }
         wave_sync();
         if (act)
@@ -522,8 +529,11 @@ __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nse
         for (int u = 0; u < lane; ++u) {
           const double l = double(row[u]);
           const double* xu = X + u * CH;
+          double xv[CH];
 #pragma unroll
-          for (int j = 0; j < CH; ++j) x[j] = fma(l, xu[j], x[j]);
+          for (int j = 0; j < CH; ++j) xv[j] = xu[j];
+#pragma unroll
+          for (int j = 0; j < CH; ++j) x[j] = fma(l, xv[j], x[j]);
         }
       }
     } else {
@@ -536,8 +546,11 @@ __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nse
         for (int u = lane; u < n; ++u) {
           const double uu = double(row[u]);
           const double* xu = X + u * CH;
+          double xv[CH];
 #pragma unroll
-          for (int j = 0; j < CH; ++j) y[j] = fma(uu, xu[j], y[j]);
+          for (int j = 0; j < CH; ++j) xv[j] = xu[j];
+#pragma unroll
+          for (int j = 0; j < CH; ++j) y[j] = fma(uu, xv[j], y[j]);
         }
       }
       if (sp) {
@@ -551,8 +564,11 @@ __global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nse
           for (int q = 0; q < nr; ++q) {
             const double t = double(trow[q]);
             const double* xq = X + q * CH;
+            double xv[CH];
 #pragma unroll
-            for (int j = 0; j < CH; ++j) y[j] = fma(-t, xq[j], y[j]);
+            for (int j = 0; j < CH; ++j) xv[j] = xq[j];
+#pragma unroll
+            for (int j = 0; j < CH; ++j) y[j] = fma(-t, xv[j], y[j]);
           }
         }
       } else {
@@ -678,11 +694,28 @@ __global__ __launch_bounds__(64) void k_sep_wave(const DSeg* segs, int nseg, con
           T av[8];
 #pragma unroll
           for (int b = 0; b < 8; ++b) av[b] = arow[u0 + b < kbe ? u0 + b : kbe - 1];
+          if constexpr (sizeof(T) == 4) {
+            // rows past kbe: row kbe - 1 times zero (no branch around the
+            // loads, so they are issued together)
 #pragma unroll
-          for (int b = 0; b < 8; ++b)
-            if (u0 + b < kbe)
+            for (int b = 0; b < 8; ++b) {
+              const bool in = u0 + b < kbe;
+              const double a = in ? double(av[b]) : 0.0;
+              const T* xr = xe + (in ? u0 + b : kbe - 1) * CH;
+              T xv[CH];
 #pragma unroll
-              for (int j = 0; j < CH; ++j) acc[j] = fma(double(av[b]), double(xe[(u0 + b) * CH + j]), acc[j]);
+              for (int j = 0; j < CH; ++j) xv[j] = xr[j];
+#pragma unroll
+              for (int j = 0; j < CH; ++j) acc[j] = fma(a, double(xv[j]), acc[j]);
+            }
+          } else {
+            // (FP64: the batch's registers would halve the waves per SIMD)
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+              if (u0 + b < kbe)
+#pragma unroll
+                for (int j = 0; j < CH; ++j) acc[j] = fma(double(av[b]), double(xe[(u0 + b) * CH + j]), acc[j]);
+          }
         }
       }
       T* dst = W + size_t(dof) * nrhs + j0;
