@@ -24,6 +24,8 @@
 // segments without an ID.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "kernels_factor.hpp"
 #include "layout.hpp"
@@ -43,11 +45,16 @@ struct IdRow {
 // rows (one Philox draw per lane).
 constexpr int ID_GTILE = 128;
 
+// Bytes of one entry of the stacked matrix Y for factors stored with st
+// bytes per value: FP32 storage keeps Y in FP32 (all arithmetic on it in
+// FP64), FP64 storage in FP64.
+__host__ __device__ inline int idc_ye(int st) { return st == 4 ? 4 : 8; }
+
 // LDS bytes of one workgroup of a tier (rows_in_lds: Y, the far rows B_F in
 // the storage type (st bytes) and the row table).
 __host__ __device__ inline size_t idc_lds_bytes(int nw, int ncol, int n, int R, int st, bool rows_in_lds) {
   size_t b = 0;
-  if (rows_in_lds) b += size_t(R) * n * (8 + st) + size_t(R) * (sizeof(IdRow) + 4);
+  if (rows_in_lds) b += size_t(R) * n * (idc_ye(st) + st) + size_t(R) * (sizeof(IdRow) + 4);
   b += size_t(ID_MAXPROBES) * n * 8;              // probe rows
   b += size_t(nw) * ID_GTILE * 8;                 // Gaussian tiles
   b += size_t(2) * nw * 64 * ncol * 8;            // norm and dot partials
@@ -93,7 +100,7 @@ __host__ __device__ inline int id_tier_of_size(int n, int R, IdTiers t) {
   const int ry = R / t.c_ydiv;
   const size_t yrows = size_t(n > ry ? n : ry);
   if (n <= 128 && idc_lds_bytes(ID_B2_WAVES, 2, n, 0, t.st, false) + idc_table_bytes(n, R, t.st) +
-                      yrows * n * 8 <= size_t(t.lds_c))
+                      yrows * n * idc_ye(t.st) <= size_t(t.lds_c))
     return 4;
   if (n <= 128) return 6;
   return 5;
@@ -128,9 +135,9 @@ __device__ inline void grp_sync() {
 // order[R - 1 - f]): near row p goes to row p of Y (Ya below row yl, Yb from
 // there on), far row f to BF[f * n + j].  One (row, column) entry per thread
 // and step, so every load of a step is independent and in flight at once.
-template <typename T, int NT>
+template <typename T, int NT, typename YE>
 __device__ inline void idc_fetch(const T* __restrict__ varena, const IdRow* rows, const int* order, int R, int nN,
-                                 int cnt, double* Ya, double* Yb, int yl, T* BF, int n) {
+                                 int cnt, YE* Ya, YE* Yb, int yl, T* BF, int n) {
 #pragma unroll 4
   for (int t = threadIdx.x; t < cnt * n; t += NT) {
     const int p = t / n, j = t - p * n;
@@ -138,7 +145,7 @@ __device__ inline void idc_fetch(const T* __restrict__ varena, const IdRow* rows
     const IdRow m = rows[near ? order[p] : order[R - 1 - (p - nN)]];
     const T v = varena[m.base + int64_t(j) * m.stride];
     if (near)
-      (p < yl ? Ya : Yb)[t] = double(v);
+      (p < yl ? Ya : Yb)[t] = YE(v);
     else
       BF[size_t(p - nN) * n + j] = v;
   }
@@ -154,8 +161,8 @@ __device__ inline int idc_next_row(int i0, int lo) {
 // Sum over this wave's rows i = i0, i0 + NW, ... < m of Y[i][a] * Y[i][b]
 // (row-major, ld n); UR rows are loaded before their products are summed, so
 // that many loads are in flight.
-template <int NW, int UR>
-__device__ inline double idc_rowdot(const double* Y, int n, int i0, int m, int a, int b) {
+template <int NW, int UR, typename YE>
+__device__ inline double idc_rowdot(const YE* Y, int n, int i0, int m, int a, int b) {
   double acc[UR];
 #pragma unroll
   for (int u = 0; u < UR; ++u) acc[u] = 0.0;
@@ -164,23 +171,24 @@ __device__ inline double idc_rowdot(const double* Y, int n, int i0, int m, int a
     double ya[UR], yb[UR];
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
-      ya[u] = Y[size_t(i + u * NW) * n + a];
-      yb[u] = Y[size_t(i + u * NW) * n + b];
+      ya[u] = double(Y[size_t(i + u * NW) * n + a]);
+      yb[u] = double(Y[size_t(i + u * NW) * n + b]);
     }
 #pragma unroll
     for (int u = 0; u < UR; ++u) acc[u] += ya[u] * yb[u];
   }
-  for (; i < m; i += NW) acc[0] += Y[size_t(i) * n + a] * Y[size_t(i) * n + b];
+  for (; i < m; i += NW) acc[0] += double(Y[size_t(i) * n + a]) * double(Y[size_t(i) * n + b]);
   double t = 0.0;
 #pragma unroll
   for (int u = 0; u < UR; ++u) t += acc[u];
   return t;
 }
 
-// Y[i][col] -= f * Y[i][q] over this wave's rows i = i0, i0 + NW, ... < m;
-// returns the sum of the squares of the updated entries.
-template <int NW, int UR>
-__device__ inline double idc_rowaxpy(double* Y, int n, int i0, int m, int col, int q, double f) {
+// Y[i][col] -= f * Y[i][q] over this wave's rows i = i0, i0 + NW, ... < m
+// (in FP64, stored in Y's type); returns the sum of the squares of the
+// updated entries as stored.
+template <int NW, int UR, typename YE>
+__device__ inline double idc_rowaxpy(YE* Y, int n, int i0, int m, int col, int q, double f) {
   double acc[UR];
 #pragma unroll
   for (int u = 0; u < UR; ++u) acc[u] = 0.0;
@@ -189,20 +197,20 @@ __device__ inline double idc_rowaxpy(double* Y, int n, int i0, int m, int col, i
     double yc[UR], yq[UR];
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
-      yc[u] = Y[size_t(i + u * NW) * n + col];
-      yq[u] = Y[size_t(i + u * NW) * n + q];
+      yc[u] = double(Y[size_t(i + u * NW) * n + col]);
+      yq[u] = double(Y[size_t(i + u * NW) * n + q]);
     }
 #pragma unroll
     for (int u = 0; u < UR; ++u) {
-      const double y = yc[u] - f * yq[u];
+      const YE y = YE(yc[u] - f * yq[u]);
       Y[size_t(i + u * NW) * n + col] = y;
-      acc[u] += y * y;
+      acc[u] += double(y) * double(y);
     }
   }
   for (; i < m; i += NW) {
-    const double y = Y[size_t(i) * n + col] - f * Y[size_t(i) * n + q];
+    const YE y = YE(double(Y[size_t(i) * n + col]) - f * double(Y[size_t(i) * n + q]));
     Y[size_t(i) * n + col] = y;
-    acc[0] += y * y;
+    acc[0] += double(y) * double(y);
   }
   double t = 0.0;
 #pragma unroll
@@ -365,15 +373,17 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   if (tier != TIER) return;
 
   // ---- memory carve-up ----
+  // Y's entries: FP32 for FP32 storage, FP64 otherwise (arithmetic in FP64)
+  using YE = typename std::conditional<sizeof(T) == 4, float, double>::type;
   char* sp = smem;
-  double* Y;
-  double* Yg = nullptr;  // tier C: room for all R rows of Y in global scratch
+  YE* Y;
+  YE* Yg = nullptr;  // tier C: room for all R rows of Y in global scratch
   IdRow* rows;
   int* order;
   T* BF;  // far rows, row-major (ld n), in the storage type
   if constexpr (YG && TABS) {
     // far rows, row table and order in LDS; Y in LDS when a pass fits
-    Yg = scratch + S.scr_off;
+    Yg = reinterpret_cast<YE*>(scratch + S.scr_off);
     Y = Yg;
     BF = reinterpret_cast<T*>(sp);
     sp += (size_t(R) * n * sizeof(T) + 15) & ~size_t(15);
@@ -382,14 +392,15 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
     order = reinterpret_cast<int*>(sp);
     sp += (size_t(R) * 4 + 15) & ~size_t(15);
   } else if constexpr (YG) {
-    Yg = scratch + S.scr_off;
+    // scratch: Y, B_F and the tables at the offsets of R n doubles each
+    Yg = reinterpret_cast<YE*>(scratch + S.scr_off);
     Y = Yg;
-    BF = reinterpret_cast<T*>(Yg + size_t(R) * n);
-    rows = reinterpret_cast<IdRow*>(Yg + 2 * size_t(R) * n);
+    BF = reinterpret_cast<T*>(scratch + S.scr_off + size_t(R) * n);
+    rows = reinterpret_cast<IdRow*>(scratch + S.scr_off + 2 * size_t(R) * n);
     order = reinterpret_cast<int*>(rows + R);
   } else {
-    Y = reinterpret_cast<double*>(sp);
-    sp += size_t(R) * n * 8;
+    Y = reinterpret_cast<YE*>(sp);
+    sp += size_t(R) * n * sizeof(YE);
     BF = reinterpret_cast<T*>(sp);
     sp += size_t(R) * n * sizeof(T);
     rows = reinterpret_cast<IdRow*>(sp);
@@ -411,13 +422,13 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   int* col2pos = pos2col + n;
   // tier C: the rest of the launch's LDS holds the first ylds_rows rows of
   // Y, the rows after them go to Yg
-  double* Ylds = nullptr;
+  YE* Ylds = nullptr;
   int ylds_rows = 0;
   if constexpr (YG) {
     const size_t used = (size_t(reinterpret_cast<char*>(col2pos + n) - smem) + 15) & ~size_t(15);
-    if (size_t(tiers.lds_c) > used + size_t(n) * 8) {
-      Ylds = reinterpret_cast<double*>(smem + used);
-      ylds_rows = int((size_t(tiers.lds_c) - used) / (size_t(n) * 8));
+    if (size_t(tiers.lds_c) > used + size_t(n) * sizeof(YE)) {
+      Ylds = reinterpret_cast<YE*>(smem + used);
+      ylds_rows = int((size_t(tiers.lds_c) - used) / (size_t(n) * sizeof(YE)));
     }
   }
 
@@ -445,14 +456,14 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
     // min(m, n) <= yl.  Called at one site per memory layout so that each
     // inlined copy uses its spaces' own instructions.  True when the ID is
     // accepted.
-    auto pass = [&](double* Y, double* Yb, int yl) -> bool {
+    auto pass = [&](YE* Y, YE* Yb, int yl) -> bool {
       const int mi = m < yl ? m : yl;
       // ---- 2. Y = [B_N; G B_F / sqrt(h)] or the exact far rows; B_F is
       //         fetched once and kept for later passes ----
       idc_fetch<T, NT>(varena, rows, order, R, nN, passes == 1 ? R : nN, Y, Yb, yl, BF, n);
       __syncthreads();
       if (!sampled) {
-        for (int t = tid; t < nF * n; t += NT) (nN + t / n < yl ? Y : Yb)[size_t(nN) * n + t] = double(BF[t]);
+        for (int t = tid; t < nF * n; t += NT) (nN + t / n < yl ? Y : Yb)[size_t(nN) * n + t] = YE(BF[t]);
       } else {
         // rows of the sketch (stream 0, scaled by 1 / sqrt(h)) and of the
         // probes (stream 1) in pairs, one Philox draw per pair and far row:
@@ -550,8 +561,8 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
             const int j = lane + 64 * s2;
             if (j < n) {
               if (stream == 0) {
-                (nN + r0 < yl ? Y : Yb)[size_t(nN + r0) * n + j] = a0[s2] * sc;
-                if (r0 + 1 < nrows) (nN + r0 + 1 < yl ? Y : Yb)[size_t(nN + r0 + 1) * n + j] = a1[s2] * sc;
+                (nN + r0 < yl ? Y : Yb)[size_t(nN + r0) * n + j] = YE(a0[s2] * sc);
+                if (r0 + 1 < nrows) (nN + r0 + 1 < yl ? Y : Yb)[size_t(nN + r0 + 1) * n + j] = YE(a1[s2] * sc);
               } else {
                 P[size_t(r0) * n + j] = a0[s2];
                 if (r0 + 1 < nrows) P[size_t(r0 + 1) * n + j] = a1[s2];
@@ -611,7 +622,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
         for (int s = 1; s < NCOL; ++s)
           if (qs == s) nq = nv[s];
         const double alpha = __shfl(nq, ql, 64);
-        const double x0 = Y[size_t(j) * n + q];
+        const double x0 = double(Y[size_t(j) * n + q]);
         const double sg = x0 >= 0.0 ? 1.0 : -1.0;
         const double v0 = x0 + sg * alpha;
         const double vv = 2.0 * alpha * (alpha + fabs(x0));
@@ -623,7 +634,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
           const int col = lane + 64 * s;
           double d = 0.0;
           if (act[s] && col != q) {
-            if (w == jown) d = v0 * Y[size_t(j) * n + col];
+            if (w == jown) d = v0 * double(Y[size_t(j) * n + col]);
             d += idc_rowdot<NW, UR>(Y, n, i1, mi, q, col);
             if constexpr (YG) d += idc_rowdot<NW, UR>(Yb, n, idc_next_row<NW>(i1, yl), m, q, col);
           }
@@ -639,13 +650,13 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
             double t = 0.0;
             for (int ww = 0; ww < NW; ++ww) t += pd[(ww * NCOL + s) * 64 + lane];
             const double f = 2.0 * t / vv;
-            if (w == jown) Y[size_t(j) * n + col] -= f * v0;
+            if (w == jown) Y[size_t(j) * n + col] = YE(double(Y[size_t(j) * n + col]) - f * v0);
             a = idc_rowaxpy<NW, UR>(Y, n, i1, mi, col, q, f);
             if constexpr (YG) a += idc_rowaxpy<NW, UR>(Yb, n, idc_next_row<NW>(i1, yl), m, col, q, f);
           }
           pn[(w * NCOL + s) * 64 + lane] = a;
         }
-        if (w == jown && lane == ql) Y[size_t(j) * n + q] = -sg * alpha;
+        if (w == jown && lane == ql) Y[size_t(j) * n + q] = YE(-sg * alpha);
         done[qs] |= 1ull << ql;
         if (tid == 0) {
           // position j takes column q; the column there moves to q's old position
@@ -662,12 +673,12 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
       const int nr = n - k;
       for (int i = k - 1; i >= 0; --i) {
         const int ci = pos2col[i];
-        const double rii = Y[size_t(i) * n + ci];
+        const double rii = double(Y[size_t(i) * n + ci]);
         double tq[NCOL];
   #pragma unroll
         for (int s = 0; s < NCOL; ++s) {
           const int qq = lane + 64 * s;
-          tq[s] = qq < nr ? Y[size_t(i) * n + pos2col[k + qq]] / rii : 0.0;
+          tq[s] = qq < nr ? double(Y[size_t(i) * n + pos2col[k + qq]]) / rii : 0.0;
         }
         grp_sync<NW>();
   #pragma unroll
@@ -675,8 +686,9 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
           const int qq = lane + 64 * s;
           if (qq < nr) {
             const int cq = pos2col[k + qq];
-            if (w == i % NW) Y[size_t(i) * n + cq] = tq[s];
-            for (int t = w; t < i; t += NW) Y[size_t(t) * n + cq] -= Y[size_t(t) * n + ci] * tq[s];
+            if (w == i % NW) Y[size_t(i) * n + cq] = YE(tq[s]);
+            for (int t = w; t < i; t += NW)
+              Y[size_t(t) * n + cq] = YE(double(Y[size_t(t) * n + cq]) - double(Y[size_t(t) * n + ci]) * tq[s]);
           }
         }
         grp_sync<NW>();
@@ -701,13 +713,13 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
                 double yv[UR], pv[UR];
   #pragma unroll
                 for (int u = 0; u < UR; ++u) {
-                  yv[u] = Y[size_t(t + u) * n + cq];
+                  yv[u] = double(Y[size_t(t + u) * n + cq]);
                   pv[u] = Pr[pos2col[t + u]];
                 }
   #pragma unroll
                 for (int u = 0; u < UR; ++u) e -= pv[u] * yv[u];
               }
-              for (; t < k; ++t) e -= Pr[pos2col[t]] * Y[size_t(t) * n + cq];
+              for (; t < k; ++t) e -= Pr[pos2col[t]] * double(Y[size_t(t) * n + cq]);
               sv += e * e;
             }
           }

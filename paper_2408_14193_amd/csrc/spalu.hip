@@ -239,7 +239,7 @@ void plan_id_tiers(LevelTabs& T, int st) {
     beyond_b2 = true;
     const int nc = std::min(cap, 128);
     if (idc_lds_bytes(ID_B2_WAVES, 2, nc, 0, st, false) + idc_table_bytes(nc, R, st) +
-            size_t(std::max(nc, R / tu.id_c_ydiv)) * nc * 8 > size_t(tu.id_lds_c))
+            size_t(std::max(nc, R / tu.id_c_ydiv)) * nc * idc_ye(st) > size_t(tu.id_lds_c))
       tabs_global = true;
     if (cap > 128) wide = true;
   }
