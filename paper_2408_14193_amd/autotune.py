@@ -34,9 +34,11 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.j
 
 
 def device_name():
+    """The GPU architecture (the marketing name is not reported on every
+    machine, the architecture is)."""
     import torch
     p = torch.cuda.get_device_properties(0)
-    return ("%s %s" % (p.name, getattr(p, "gcnArchName", ""))).strip()
+    return getattr(p, "gcnArchName", "") or p.name
 
 
 def workload_key(dims, precision, learned, nrhs, eps, device=None):

@@ -571,13 +571,19 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
           }
         }
       }
-      for (int i = tid; i < n; i += NT) pos2col[i] = col2pos[i] = i;
       __syncthreads();
 
       // ---- 3. CPQR (fresh norms, tie rule: smallest original column) ----
+      // The position <-> column tables live in registers during the pivot
+      // steps: every wave keeps the same copy, lane l holding the entries
+      // l + 64 s, so no step waits on a single thread's LDS updates.
       uint64_t done[NCOL];
+      int p2c[NCOL], c2p[NCOL];
   #pragma unroll
-      for (int s = 0; s < NCOL; ++s) done[s] = 0ull;
+      for (int s = 0; s < NCOL; ++s) {
+        done[s] = 0ull;
+        p2c[s] = c2p[s] = lane + 64 * s;
+      }
   #pragma unroll
       for (int s = 0; s < NCOL; ++s) {
         const int j = lane + 64 * s;
@@ -599,8 +605,12 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
         for (int s = 0; s < NCOL; ++s) {
           const int col = lane + 64 * s;
           act[s] = col < n && !((done[s] >> lane) & 1ull);
+          double pv[NW];
+  #pragma unroll
+          for (int ww = 0; ww < NW; ++ww) pv[ww] = pn[(ww * NCOL + s) * 64 + lane];
           double t = 0.0;
-          for (int ww = 0; ww < NW; ++ww) t += pn[(ww * NCOL + s) * 64 + lane];
+  #pragma unroll
+          for (int ww = 0; ww < NW; ++ww) t += pv[ww];
           nv[s] = sqrt(t);
           if (act[s]) mxl = fmax(mxl, nv[s]);
         }
@@ -647,8 +657,12 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
           const int col = lane + 64 * s;
           double a = 0.0;
           if (act[s] && col != q) {
+            double pv[NW];
+  #pragma unroll
+            for (int ww = 0; ww < NW; ++ww) pv[ww] = pd[(ww * NCOL + s) * 64 + lane];
             double t = 0.0;
-            for (int ww = 0; ww < NW; ++ww) t += pd[(ww * NCOL + s) * 64 + lane];
+  #pragma unroll
+            for (int ww = 0; ww < NW; ++ww) t += pv[ww];
             const double f = 2.0 * t / vv;
             if (w == jown) Y[size_t(j) * n + col] = YE(double(Y[size_t(j) * n + col]) - f * v0);
             a = idc_rowaxpy<NW, UR>(Y, n, i1, mi, col, q, f);
@@ -658,16 +672,31 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
         }
         if (w == jown && lane == ql) Y[size_t(j) * n + q] = YE(-sg * alpha);
         done[qs] |= 1ull << ql;
-        if (tid == 0) {
+        {
           // position j takes column q; the column there moves to q's old position
-          const int qp = col2pos[q], cj = pos2col[j];
-          pos2col[qp] = cj;
-          col2pos[cj] = qp;
-          pos2col[j] = q;
-          col2pos[q] = j;
+          int c2pq = c2p[0], p2cj = p2c[0];
+  #pragma unroll
+          for (int s = 1; s < NCOL; ++s) {
+            if (qs == s) c2pq = c2p[s];
+            if ((j >> 6) == s) p2cj = p2c[s];
+          }
+          const int qp = __shfl(c2pq, ql, 64), cj = __shfl(p2cj, j & 63, 64);
+  #pragma unroll
+          for (int s = 0; s < NCOL; ++s) {
+            const int idx = lane + 64 * s;
+            if (idx == qp) p2c[s] = cj;
+            if (idx == cj) c2p[s] = qp;
+            if (idx == j) p2c[s] = q;
+            if (idx == q) c2p[s] = j;
+          }
         }
         __syncthreads();
       }
+      if (w == 0)
+  #pragma unroll
+        for (int s = 0; s < NCOL; ++s)
+          if (lane + 64 * s < n) pos2col[lane + 64 * s] = p2c[s];
+      __syncthreads();
 
       // ---- 4. T = R11^{-1} R12, in place in rows < k of the remaining columns ----
       const int nr = n - k;
