@@ -147,6 +147,43 @@ __device__ inline void load_chunk(const T* src, int nc, double x[LEAF_SOLVE_CHUN
 
 __host__ __device__ inline int leaf_solve_wave_lds_bytes(int ni) { return 8 * LEAF_SOLVE_CHUNK * ni; }
 
+// One 16 x 16 output tile (rows i0.., all 16 columns of a chunk) of the
+// product A X on the matrix cores, one wave: A (rows x K) with entry (i, k)
+// at A[k * lda + i] (the transposed storage of the leaf matrices), X (K x 16)
+// row-major in LDS, zero outside [0, rows) x [0, K).  FP64 16x16x4 MFMA for
+// both storage types (the solve accumulates in FP64, as the refinement's
+// last digits need).  Lane l supplies A[i0 + l%16][k0 + l/16] and
+// X[k0 + l/16][l%16] (clamped addresses, zero outside) and receives column
+// l % 16 of rows leaf_tile_row(i0, r).
+template <typename T>
+__device__ inline void leaf_tile_mfma(const T* A, int lda, int rows, int K, const double* X, int i0, double out[4]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int i = i0 + li;
+  const bool irow = i < rows;
+  const int ic = irow ? i : rows - 1;
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  v4 d = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + lk;
+    const bool kin = k < K;
+    const int kc = kin ? k : K - 1;
+    const double a = double(A[size_t(kc) * lda + ic]);
+    const double b = X[kc * LEAF_SOLVE_CHUNK + li];
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(irow && kin ? a : 0.0, kin ? b : 0.0, d, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[r] = d[r];
+}
+
+// Row of result r of this lane in a tile of leaf_tile_mfma.
+__device__ inline int leaf_tile_row(int i0, int r) { return i0 + ((threadIdx.x & 63) >> 4) + 4 * r; }
+
+// Vertex of interior row i of a leaf box.
+__device__ inline int leaf_vertex(const DLeaf& L, GridGeom g, int w0, int w1, int i) {
+  const int ix = i % w0, iy = (i / w0) % w1, iz = i / (w0 * w1);
+  return (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz));
+}
+
 template <typename T, bool BACKWARD>
 __global__ __launch_bounds__(64) void k_leaf_solve_wave(const DLeaf* leaves, int nleaf, GridGeom g,
                                                         const int64_t* rowptr, const int32_t* colind,
@@ -214,7 +251,19 @@ __global__ __launch_bounds__(64) void k_leaf_solve_wave(const DLeaf* leaves, int
       for (int j = 0; j < CH; ++j) X[lane * CH + j] = v[j];
     }
     wave_sync();
-    if (act) {
+    if (!BACKWARD) {
+      // Z = A_II^{-1} X on the matrix cores, 16 rows at a time
+      const int jj = lane & 15;
+      for (int i0 = 0; i0 < ni; i0 += 16) {
+        double o[4];
+        leaf_tile_mfma<T>(varena + L.lu_off, ni, ni, ni, X, i0, o);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = leaf_tile_row(i0, r);
+          if (row < ni && jj < nc) dst[size_t(leaf_vertex(L, g, w0, w1, row)) * nrhs + j0 + jj] = T(o[r]);
+        }
+      }
+    } else if (act) {
       double acc[CH];
 #pragma unroll
       for (int j = 0; j < CH; ++j) acc[j] = 0.0;
@@ -376,9 +425,9 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
 
 // Backward leaf solve from the forward result: x_I = y_I - X x_B with
 // X = A_II^{-1} A_IB (stored transposed by the one-wave leaf factor) and x_B
-// the boundary values; one wave per leaf, lane i = interior vertex i.  The
-// boundary values of a chunk of right-hand sides are staged in LDS, X is read
-// in batches of 16 loads.
+// the boundary values; one wave per leaf of at most 64 interior vertices.
+// The boundary values of a chunk of right-hand sides are staged in LDS and
+// X x_B is formed on the matrix cores, 16 rows at a time.
 __host__ __device__ inline int leaf_bwd_x_lds_bytes(int nb) { return 8 * LEAF_SOLVE_CHUNK * (nb > 0 ? nb : 1); }
 
 template <typename T>
@@ -393,16 +442,10 @@ __global__ __launch_bounds__(64) void k_leaf_solve_bwd_x(const DLeaf* leaves, in
   const int ni = L.ni, nb = L.nb, lane = threadIdx.x;
   if (ni == 0) return;
   const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1;
-  const bool act = lane < ni;
-  const int ix = lane % w0, iy = (lane / w0) % w1, iz = lane / (w0 * w1);
-  const int u = act ? (L.lo[0] + ix) + g.nx * ((L.lo[1] + iy) + g.ny * (L.lo[2] + iz)) : 0;
   const int32_t* bverts = iarena + L.ioff;
-  const T* Xt = varena + L.x_off + (act ? lane : 0);  // column lane of X^T: X[lane][b] at b * ni
-  double* XB = lds;                                   // nb x CH boundary values
+  double* XB = lds;  // nb x CH boundary values
   for (int j0 = 0; j0 < nrhs; j0 += CH) {
     const int nc = nrhs - j0 < CH ? nrhs - j0 : CH;
-    double y[CH];
-    if (act) load_chunk(Z + size_t(u) * nrhs + j0, nc, y);
     for (int b = lane; b < nb; b += 64) {
       double xb[CH];
       load_chunk(W + size_t(bverts[b]) * nrhs + j0, nc, xb);
@@ -410,28 +453,19 @@ __global__ __launch_bounds__(64) void k_leaf_solve_bwd_x(const DLeaf* leaves, in
       for (int j = 0; j < CH; ++j) XB[b * CH + j] = xb[j];
     }
     wave_sync();
-    if (act) {
-      for (int b0 = 0; b0 < nb; b0 += 16) {
-        T xv[16];
+    // x_I = y_I - X x_B on the matrix cores, 16 rows at a time
+    const int jj = lane & 15;
+    for (int i0 = 0; i0 < ni; i0 += 16) {
+      double o[4];
+      leaf_tile_mfma<T>(varena + L.x_off, ni, ni, nb, XB, i0, o);
 #pragma unroll
-        for (int t = 0; t < 16; ++t) xv[t] = Xt[size_t(b0 + t < nb ? b0 + t : nb - 1) * ni];
-        // rows past nb: row nb - 1 times zero (no branch around the loads)
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const bool in = b0 + t < nb;
-          const double a = in ? double(xv[t]) : 0.0;
-          const double* xb = XB + (in ? b0 + t : nb - 1) * CH;
-          double bv[CH];
-#pragma unroll
-          for (int j = 0; j < CH; ++j) bv[j] = xb[j];
-#pragma unroll
-          for (int j = 0; j < CH; ++j) y[j] = fma(-a, bv[j], y[j]);
+      for (int r = 0; r < 4; ++r) {
+        const int row = leaf_tile_row(i0, r);
+        if (row < ni && jj < nc) {
+          const size_t at = size_t(leaf_vertex(L, g, w0, w1, row)) * nrhs + j0 + jj;
+          W[at] = T(double(Z[at]) - o[r]);
         }
       }
-      T* out = W + size_t(u) * nrhs + j0;
-#pragma unroll
-      for (int j = 0; j < CH; ++j)
-        if (j < nc) out[j] = T(y[j]);
     }
     wave_sync();
   }
