@@ -162,7 +162,7 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8,
                 converged=all(r <= tol for r in res), profile=prof,
                 breakdown=breakdown if breakdown is not None else prof,
                 breakdown_steps=1 if breakdown is not None else steps,
-                tuning=dict(source=source, key=key, changed=changed))
+                tuning=dict(source=source, key=key, changed=changed), X=X.clone())
 
 
 def measured_traffic(name, form):
@@ -322,6 +322,18 @@ def main():
                          ("sparsified", "sample_passes", "resampled", "max_front", "q_tilde",
                           "flops", "bytes", "workspace_bytes")},
     }
+    # each form's solution against the plain FP64 form's (largest relative
+    # difference over the right-hand sides), when the plain form ran
+    err = {}
+    if "plain" in res:
+        import torch
+        Xp = res["plain"]["X"]
+        nrm = torch.linalg.vector_norm(Xp, dim=1)
+        for f in forms:
+            if f != "plain":
+                d = torch.linalg.vector_norm(res[f]["X"] - Xp, dim=1) / nrm
+                err[f] = float(d.max())
+        out["max_rel_diff_vs_plain_fp64"] = err.get(head)
     for f in forms[1:]:
         rf = res[f]
         vf = P.n / (rf["ms_per_step"] * 1e-3)
@@ -330,6 +342,8 @@ def main():
                               "refine_iters": rf["refine_iters"],
                               "max_rel_residual": rf["max_rel_residual"], "converged": rf["converged"],
                               "launch_shapes": rf["tuning"]}
+        if f in err:
+            out["%s_form" % f]["max_rel_diff_vs_plain_fp64"] = err[f]
         out["ratio_%s_vs_%s" % (head, f)] = round(value / vf, 3)
     if not a.no_cpu:
         log("cpu baseline: oracle on a %dx%d sample ..." % (a.cpu_side, a.cpu_side))
