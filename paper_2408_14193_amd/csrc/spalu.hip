@@ -469,8 +469,10 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
     var += size_t(D.ni) * D.ni;
     D.s_off = int64_t(var);
     var += size_t(nb) * nb;
+    // X = A_II^{-1} A_IB (transposed) is written by the one-wave leaf factor
+    // only: no room for leaves beyond it (3D leaves)
     D.x_off = int64_t(var);
-    var += size_t(D.ni) * nb;
+    if (leaf_wave_slots(D.ni, nb) != 0) var += size_t(D.ni) * nb;
     leaf_need = std::max(leaf_need, size_t(leaf_lds_need(D.ni, nb)));
   }
   // one wave per leaf when every leaf fits its register row
