@@ -760,72 +760,116 @@ __global__ __launch_bounds__(64) void k_sep_wave(const DSeg* segs, int nseg, con
   }
 }
 
-// acc[a] += sum_u A[(i0+i)*lda + u] * W[idx[u]*nrhs + j0 + j] for the
-// (i, j) outputs this thread owns (t = tid + a*WG < ib*nc), u < K.  Operand
-// tiles of 32 columns of A and 32 gathered rows of W are staged in LDS.
+// acc[c] += A[i0 + rows, 0:K] W[idx[0:K], j0 + 16c + cols] on the matrix
+// cores (FP64 16x16x4 for both storage types): wave w of the block owns
+// output rows 16w..16w+15 of the pass of ib <= GG_ROWS rows, and acc[c]
+// holds, in lane l, column 16c + l%16 of rows 16w + l/16 + 4r (r < 4), as
+// gg_row/gg_col give.  A is row-major with leading dimension lda.  Tiles of
+// GG_TILE columns of A and GG_TILE gathered rows of W go through LDS, zero
+// padded to full tiles; the next tile's loads are issued before the current
+// tile's products, so their latency hides behind the matrix cores.
 constexpr int GG_TILE = 32;
-constexpr int GG_ROWS = 64;   // output rows per pass
-constexpr int GG_COLS = 16;   // output right-hand sides per pass (<= 4 per thread)
+constexpr int GG_ROWS = 64;                // 4 waves x 16 rows
+constexpr int GG_COLS = 64;                // 4 column tiles of 16
+constexpr int GG_LDA = GG_TILE + 2;        // A tile row stride: a half-wave's reads hit distinct banks
+constexpr int GG_LDX = GG_COLS + 16;       // W tile row stride: rows k and k+1 on opposite bank halves
+constexpr int GG_LDS_DOUBLES = GG_ROWS * GG_LDA + GG_TILE * GG_LDX;
+typedef double gg_v4 __attribute__((ext_vector_type(4)));
+
+__device__ inline int gg_row(int r) { return ((threadIdx.x >> 6) << 4) + ((threadIdx.x & 63) >> 4) + 4 * r; }
+__device__ inline int gg_col(int c) { return 16 * c + (threadIdx.x & 15); }
 
 template <typename T>
 __device__ inline void gathered_gemm_acc(const T* A, int lda, int i0, int ib, int K, const int32_t* idx,
                                          const T* W, int nrhs, int j0, int nc, double* sA, double* sX,
-                                         double acc[4]) {
-  const int tid = threadIdx.x;
+                                         gg_v4 acc[4]) {
+  if (K <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  // staging: A rows ar + 8m at column ac, W rows xr + 4m at column xc (m < 8)
+  const int ac = tid & 31, ar = tid >> 5, xc = tid & 63, xr = tid >> 6;
+  T ra[8], rx[8];
+  auto fetch = [&](int u0) {
+    const int kt = K - u0 < GG_TILE ? K - u0 : GG_TILE;
+    const int u = u0 + (ac < kt ? ac : kt - 1);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int i = ar + 8 * m;
+      ra[m] = A[size_t(i0 + (i < ib ? i : ib - 1)) * lda + u];
+    }
+    const int j = j0 + (xc < nc ? xc : nc - 1);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int r = xr + 4 * m;
+      rx[m] = W[size_t(idx[u0 + (r < kt ? r : kt - 1)]) * nrhs + j];
+    }
+  };
+  fetch(0);
   for (int u0 = 0; u0 < K; u0 += GG_TILE) {
     const int kt = K - u0 < GG_TILE ? K - u0 : GG_TILE;
+    __syncthreads();  // the previous tile is consumed
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int i = ar + 8 * m, r = xr + 4 * m;
+      sA[i * GG_LDA + ac] = i < ib && ac < kt ? double(ra[m]) : 0.0;
+      sX[r * GG_LDX + xc] = r < kt && xc < nc ? double(rx[m]) : 0.0;
+    }
     __syncthreads();
-    load_batched<4>(
-        ib * kt, tid, WG, [&](int t) { return A[size_t(i0 + t / kt) * lda + u0 + t % kt]; },
-        [&](int t, T v) { sA[t] = double(v); });
-    load_batched<2>(
-        kt * nc, tid, WG, [&](int t) { return W[size_t(idx[u0 + t / nc]) * nrhs + j0 + t % nc]; },
-        [&](int t, T v) { sX[t] = double(v); });
-    __syncthreads();
-    int a = 0;
-    for (int t = tid; t < ib * nc; t += WG, ++a) {
-      const int i = t / nc, j = t % nc;
-      double s = 0.0;
-      for (int u = 0; u < kt; ++u) s += sA[i * kt + u] * sX[u * nc + j];
-      acc[a] += s;
+    if (u0 + GG_TILE < K) fetch(u0 + GG_TILE);
+    if (16 * w < ib) {
+      const double* pa = sA + (16 * w + li) * GG_LDA + lk;
+      const double* px = sX + lk * GG_LDX + li;
+      for (int k0 = 0; k0 < kt; k0 += 4) {
+        const double a = pa[k0];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (16 * c < nc) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, px[k0 * GG_LDX + 16 * c], acc[c], 0, 0, 0);
+      }
     }
   }
 }
 
 // Forward separator elimination (Z_l): owner = non-separator segment a,
 // W[skel_a] -= sum over level-l separators s next to a of A'_{a,s} W[skel_s].
+// Block (a, y) takes skeleton rows 64y .. 64y+63 of segment a.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_sep_fwd(const DSeg* segs, int nseg, const DNbr* nbrs,
                                                 const DBlk* blks, const int32_t* iarena, const T* varena,
                                                 DLevelDyn dyn, T* W, int nrhs) {
-  __shared__ double sA[GG_ROWS * GG_TILE];
-  __shared__ double sX[GG_TILE * GG_COLS];
+  __shared__ double sA[GG_ROWS * GG_LDA];
+  __shared__ double sX[GG_TILE * GG_LDX];
   const int a = blockIdx.x;
   if (a >= nseg) return;
   const DSeg S = segs[a];
   if (S.flags & SEG_IS_SEP) return;
+  const int ka = dyn.k[a], nra = dyn.nr[a];
+  const int i0 = int(blockIdx.y) * GG_ROWS;
+  if (i0 >= ka) return;
   bool any = false;
   for (int e = S.nbr_begin; e < S.nbr_end; ++e) any |= nbrs[e].d_is_sep != 0;
   if (!any) return;
-  const int ka = dyn.k[a], nra = dyn.nr[a];
   const int32_t* da = iarena + S.ioff + nra;
+  const int ib = ka - i0 < GG_ROWS ? ka - i0 : GG_ROWS;
   for (int j0 = 0; j0 < nrhs; j0 += GG_COLS) {
     const int nc = nrhs - j0 < GG_COLS ? nrhs - j0 : GG_COLS;
-    for (int i0 = 0; i0 < ka; i0 += GG_ROWS) {
-      const int ib = ka - i0 < GG_ROWS ? ka - i0 : GG_ROWS;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
-        const DNbr nb = nbrs[e];
-        if (!nb.d_is_sep) continue;
-        const int ks = dyn.k[nb.d], nrs = dyn.nr[nb.d];
-        gathered_gemm_acc(varena + blks[nb.blk_cd].soff, ks, i0, ib, ks, iarena + segs[nb.d].ioff + nrs, W,
-                          nrhs, j0, nc, sA, sX, acc);
-      }
-      int q = 0;
-      for (int t = threadIdx.x; t < ib * nc; t += WG, ++q) {
-        const int i = t / nc, j = t % nc;
-        const size_t idx = size_t(da[i0 + i]) * nrhs + j0 + j;
-        W[idx] = T(double(W[idx]) - acc[q]);
+    gg_v4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = gg_v4{0.0, 0.0, 0.0, 0.0};
+    for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+      const DNbr nb = nbrs[e];
+      if (!nb.d_is_sep) continue;
+      const int ks = dyn.k[nb.d], nrs = dyn.nr[nb.d];
+      gathered_gemm_acc(varena + blks[nb.blk_cd].soff, ks, i0, ib, ks, iarena + segs[nb.d].ioff + nrs, W,
+                        nrhs, j0, nc, sA, sX, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = gg_row(r);
+      if (i >= ib) continue;
+      const size_t base = size_t(da[i0 + i]) * nrhs + j0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int j = gg_col(c);
+        if (j < nc) W[base + j] = T(double(W[base + j]) - acc[c][r]);
       }
     }
   }
@@ -833,34 +877,42 @@ __global__ __launch_bounds__(WG) void k_sep_fwd(const DSeg* segs, int nseg, cons
 
 // Backward separator elimination (Z_u): owner = separator s,
 // W[skel_s] -= sum over its neighbours b of A'_{s,b} W[skel_b].
+// Block (s, y) takes skeleton rows 64y .. 64y+63 of separator s.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_sep_bwd(const DSeg* segs, int nseg, const DNbr* nbrs,
                                                 const DBlk* blks, const int32_t* iarena, const T* varena,
                                                 DLevelDyn dyn, T* W, int nrhs) {
-  __shared__ double sA[GG_ROWS * GG_TILE];
-  __shared__ double sX[GG_TILE * GG_COLS];
+  __shared__ double sA[GG_ROWS * GG_LDA];
+  __shared__ double sX[GG_TILE * GG_LDX];
   const int s = blockIdx.x;
   if (s >= nseg) return;
   const DSeg S = segs[s];
   if (!(S.flags & SEG_IS_SEP)) return;
   const int ks = dyn.k[s], nrs = dyn.nr[s];
+  const int i0 = int(blockIdx.y) * GG_ROWS;
+  if (i0 >= ks) return;
   const int32_t* ds = iarena + S.ioff + nrs;
+  const int ib = ks - i0 < GG_ROWS ? ks - i0 : GG_ROWS;
   for (int j0 = 0; j0 < nrhs; j0 += GG_COLS) {
     const int nc = nrhs - j0 < GG_COLS ? nrhs - j0 : GG_COLS;
-    for (int i0 = 0; i0 < ks; i0 += GG_ROWS) {
-      const int ib = ks - i0 < GG_ROWS ? ks - i0 : GG_ROWS;
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
-        const DNbr nb = nbrs[e];
-        const int kb = dyn.k[nb.d], nrb = dyn.nr[nb.d];
-        gathered_gemm_acc(varena + blks[nb.blk_cd].soff, kb, i0, ib, kb, iarena + segs[nb.d].ioff + nrb, W,
-                          nrhs, j0, nc, sA, sX, acc);
-      }
-      int q = 0;
-      for (int t = threadIdx.x; t < ib * nc; t += WG, ++q) {
-        const int i = t / nc, j = t % nc;
-        const size_t idx = size_t(ds[i0 + i]) * nrhs + j0 + j;
-        W[idx] = T(double(W[idx]) - acc[q]);
+    gg_v4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = gg_v4{0.0, 0.0, 0.0, 0.0};
+    for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
+      const DNbr nb = nbrs[e];
+      const int kb = dyn.k[nb.d], nrb = dyn.nr[nb.d];
+      gathered_gemm_acc(varena + blks[nb.blk_cd].soff, kb, i0, ib, kb, iarena + segs[nb.d].ioff + nrb, W,
+                        nrhs, j0, nc, sA, sX, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = gg_row(r);
+      if (i >= ib) continue;
+      const size_t base = size_t(ds[i0 + i]) * nrhs + j0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int j = gg_col(c);
+        if (j < nc) W[base + j] = T(double(W[base + j]) - acc[c][r]);
       }
     }
   }

@@ -127,7 +127,7 @@ struct Layout {
 struct SweepGraph {
   const void *ws, *sw, *rowptr, *colind, *vals;
   int nrhs, prec;
-  std::vector<int> shape;  // launch shapes baked in (per level: lanes, rows)
+  std::vector<int> shape;  // launch shapes baked in (per level: lanes, rows, largest skeleton)
   hipGraphExec_t exec;
 };
 
@@ -186,8 +186,9 @@ struct spalu_factor_s {
   std::shared_ptr<std::vector<std::vector<int32_t>>> dyn_host;
   // launch shapes of the solve sweeps from the actual sizes, per level: lanes
   // per segment of the lane-group kernels (0: 256-thread kernels) and the
-  // largest stacked neighbour skeleton of an owner
-  std::vector<int> solve_P, solve_rows;
+  // largest stacked neighbour skeleton of an owner, and the largest skeleton
+  // (the row passes of the 256-thread separator kernels)
+  std::vector<int> solve_P, solve_rows, solve_kmax;
   // side streams and events (owned by the ordering handle)
   FactorStreams* fs = nullptr;
 };
@@ -931,6 +932,7 @@ int read_dyn_host(spalu_factor_t* F) {
   // counts fit P and whose staging fits 64 KB of LDS
   F->solve_P.assign(size_t(L) + 1, 0);
   F->solve_rows.assign(size_t(L) + 1, 1);
+  F->solve_kmax.assign(size_t(L) + 1, 1);
   const int vs = int(Y.vsize);
   for (int l = 1; l <= L; ++l) {
     const LevelTabs& T = Y.lv[l];
@@ -948,9 +950,10 @@ int read_dyn_host(spalu_factor_t* F) {
     }
     const int32_t* ap = T.adj_ptr.data();
     const int32_t* ad = T.adj_d.data();
-    int mx = T.max_nbrs, rows = 1;
+    int mx = T.max_nbrs, rows = 1, kmax = 1;
     for (size_t c = 0; c < ns; ++c) {
       mx = std::max(mx, int(nv[c]));
+      kmax = std::max(kmax, int(kv[c]));
       int r = 0;
       for (int e = ap[c]; e < ap[c + 1]; ++e) r += kv[ad[e]];
       rows = std::max(rows, r);
@@ -962,6 +965,7 @@ int read_dyn_host(spalu_factor_t* F) {
         size_t(64 / P) * sep_grp_bytes(P, rows, vs) <= 65536)
       F->solve_P[l] = P;
     F->solve_rows[l] = rows;
+    F->solve_kmax[l] = kmax;
   }
   return SPALU_OK;
 }
@@ -1416,7 +1420,8 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
     } else {
       const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
       LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
-      LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
+      const dim3 gsep(unsigned(ns), unsigned((F->solve_kmax[l] + GG_ROWS - 1) / GG_ROWS));
+      LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<gsep, WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
                                                                    tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
     }
   }
@@ -1430,7 +1435,8 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
       if (const int rc = seg_solve_grp(T_, l, P, true, d)) return rc;
     } else {
       const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
-      LAUNCH(K_SEPBWD, l, k_sep_bwd<T><<<unsigned(ns), WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
+      const dim3 gsep(unsigned(ns), unsigned((F->solve_kmax[l] + GG_ROWS - 1) / GG_ROWS));
+      LAUNCH(K_SEPBWD, l, k_sep_bwd<T><<<gsep, WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
                                                                    tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
       LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
     }
@@ -1460,6 +1466,7 @@ int apply(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, const char* sw, 
   hipGraphExec_t exec = nullptr;
   std::vector<int> shape(F->solve_P);
   shape.insert(shape.end(), F->solve_rows.begin(), F->solve_rows.end());
+  shape.insert(shape.end(), F->solve_kmax.begin(), F->solve_kmax.end());
   for (auto& gph : nd->graphs)
     if (gph.ws == F->ws && gph.sw == sw && gph.rowptr == F->rowptr && gph.colind == F->colind &&
         gph.vals == F->vals && gph.nrhs == nrhs && gph.prec == F->prec && gph.shape == shape)

@@ -2,6 +2,7 @@
 // written by tests/test_host_emulation.py, optionally solves, and prints the
 // results.  Every device buffer sits between large inaccessible regions so
 // an access that leaves it traps.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -105,6 +106,20 @@ int main(int argc, char** argv) {
               rc ? spalu_last_error() : "ok", (long long)info.sparsified, (long long)info.sample_passes,
               (long long)info.resampled, (long long)info.max_front);
   if (rc) return 1;
+  {
+    // largest skeleton over the levels (row passes of the separator kernels)
+    int64_t nn = 0, nnodes = 0, nsegs = 0;
+    int32_t L = 0;
+    spalu_nd_info(nd, &nn, &L, &nnodes, &nsegs);
+    std::vector<int64_t> base(size_t(L) + 2);
+    spalu_factor_seg_base(nd, base.data());
+    const size_t ns = size_t(base[size_t(L) + 1]);
+    std::vector<int32_t> nb(ns), rk(ns), hh(ns), ps(ns);
+    int kmax = 0;
+    if (spalu_factor_ranks(F, nb.data(), rk.data(), hh.data(), ps.data()) == 0)
+      for (size_t i = 0; i < ns; ++i) kmax = std::max(kmax, int(rk[i]));
+    std::printf("max_rank %d\n", kmax);
+  }
   if (nrhs > 0) {
     std::vector<double> Bv(size_t(n) * nrhs);
     srand(7);

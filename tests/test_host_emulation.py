@@ -41,7 +41,7 @@ def _write(P, d, params=None):
     (params if params is not None else np.zeros(1, np.float32)).tofile(os.path.join(d, "params.bin"))
 
 
-def _run(exe, d, prec, model, eps, nrhs, tol, restart, h0=None, tuning=None):
+def _run(exe, d, prec, model, eps, nrhs, tol, restart, h0=None, tuning=None, max_rank=None):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
     if h0 is not None:
         env["EMU_H0"] = str(h0)
@@ -54,6 +54,8 @@ def _run(exe, d, prec, model, eps, nrhs, tol, restart, h0=None, tuning=None):
     assert m and int(m.group(1)) == 0, r.stdout
     s = re.search(r"solve rc (-?\d+) .* iters (\d+) first (\S+) final (\S+)", r.stdout)
     assert s and int(s.group(1)) == 0, r.stdout
+    if max_rank is not None:
+        max_rank.append(int(re.search(r"max_rank (\d+)", r.stdout).group(1)))
     return int(s.group(2)), float(s.group(3)), float(s.group(4))
 
 
@@ -123,4 +125,20 @@ def test_smallest_launch_shapes(exe, tmp_path, prec):
     P = make_config(4, side=127, nrhs=1)
     _write(P, str(tmp_path))
     it, first, final = _run(exe, str(tmp_path), prec, 0, P.eps, 2, 1e-10, 8, tuning=SMALL_SHAPES)
+    assert final <= 1e-10
+
+
+def test_block_separator_solve_many_rhs(exe, tmp_path):
+    """127 x 127 Helmholtz in FP32 with 70 right-hand sides and lane groups
+    of at most 32: the coarse levels take the 256-thread separator kernels
+    on the matrix cores, with skeletons above 64 rows (several row passes
+    per segment) and a full and a ragged chunk of right-hand-side columns."""
+    P = make_config(4, side=127, nrhs=1)
+    _write(P, str(tmp_path))
+    mr = []
+    it, first, final = _run(exe, str(tmp_path), 32, 0, P.eps, 70, 1e-10, 8, tuning=SMALL_SHAPES, max_rank=mr)
+    assert mr[0] > 64, mr
+    # the factor alone already solves to about 3e-3 (a wrong row pass or
+    # column chunk would leave whole skeleton blocks unsolved)
+    assert first <= 1e-2 and it <= 5, (first, it)
     assert final <= 1e-10
