@@ -184,10 +184,13 @@ typedef struct {
                               16384..155648; default 65536                  */
   int32_t melim_wave_cap;  /* merge targets of at most this many DOFs take one
                               wave each, 8..32; default 32                   */
-  int32_t solve_lanes_min; /* narrowest lane group of the solve sweeps (8, 16,
-                              32 or 64); default 8                           */
-  int32_t solve_lanes_max; /* widest (levels with larger segments take the
-                              block kernels); default 64                     */
+  int32_t solve_lanes_min; /* solve sweeps: the segment-size bound P of a
+                              level starts here (8, 16, 32 or 64) and doubles
+                              until the level's segments and neighbour
+                              counts fit; default 8                          */
+  int32_t solve_lanes_max; /* levels with P up to this take the one-wave
+                              matrix-core kernels (16-row tiles), larger
+                              ones the block kernels; default 64             */
 } spalu_tuning;
 
 void spalu_tuning_default(spalu_tuning* t);

@@ -4,6 +4,7 @@
 // reads nrhs contiguous values per DOF.
 #pragma once
 
+#include <type_traits>
 #include "device_common.hpp"
 #include "kernels_factor.hpp"
 #include "layout.hpp"
@@ -471,295 +472,6 @@ __global__ __launch_bounds__(64) void k_leaf_solve_bwd_x(const DLeaf* leaves, in
   }
 }
 
-// Groups of P lanes (P = 8, 16, 32 or 64) per segment, 64 / P segments per
-// wave, for levels whose segments hold at most P DOFs: lane i of a group
-// keeps DOF i's chunk of 16 right-hand sides in registers, and rows are
-// exchanged through the group's LDS only where a product needs other lanes'
-// rows.  The packed inverse and T are staged in LDS first (row strides made
-// odd against bank conflicts), in parallel with the gather of the right-hand
-// sides; several segments per wave keep more memory requests in flight.
-constexpr int SOLVE_WAVE_MAX_N = 64;
-
-// LDS bytes of one group (vs: bytes of the storage type).
-__host__ __device__ inline int seg_solve_grp_bytes(int P, int vs) {
-  return (8 * LEAF_SOLVE_CHUNK * P + vs * (P * (P | 1) + P * ((P / 2) | 1)) + 15) / 16 * 16;
-}
-
-template <typename T, bool BACKWARD, int P>
-__global__ __launch_bounds__(64) void k_seg_solve_wave(const DSeg* segs, int nseg, const int32_t* iarena,
-                                                       const T* varena, DLevelDyn dyn, T* W, int nrhs) {
-  extern __shared__ double lds[];
-  constexpr int CH = LEAF_SOLVE_CHUNK;
-  const int lane = threadIdx.x % P, grp = threadIdx.x / P;
-  const int c = blockIdx.x * (64 / P) + grp;
-  int n = 0, k = 0, nr = 0;
-  bool sp = false;
-  DSeg S{};
-  if (c < nseg) {
-    S = segs[c];
-    n = dyn.n[c];
-    k = dyn.k[c];
-    nr = dyn.nr[c];
-    sp = dyn.passes[c] > 0 && nr > 0 && k > 0;
-  }
-  if (n > P) n = 0;  // never on a level launched with this P
-  const bool act = lane < n;
-  double* X = reinterpret_cast<double*>(reinterpret_cast<char*>(lds) + size_t(grp) * seg_solve_grp_bytes(P, int(sizeof(T))));
-  const int ni = n | 1, ntr = nr | 1;
-  T* sI = reinterpret_cast<T*>(X + n * CH);  // n x ni
-  T* sT = sI + n * ni;                       // k x ntr
-  const int32_t* dofs = iarena + S.ioff;
-  const int dof = act ? dofs[lane] : 0;
-  const int rm = act && !BACKWARD ? dofs[2 * S.cap + lane] : lane;  // row i of P X is row rm of X
-  if (n > 0) {
-    stage_batched<(P < 16 ? 8 : 16)>(varena + S.lu_off, n * n, lane, P,
-                                     [&](int t, T v) { sI[(t / n) * ni + t % n] = v; });
-    if (sp)
-      stage_batched<8>(varena + S.t_off, k * nr, lane, P, [&](int t, T v) { sT[(t / nr) * ntr + t % nr] = v; });
-  }
-  for (int j0 = 0; j0 < nrhs; j0 += CH) {
-    const int nc = nrhs - j0 < CH ? nrhs - j0 : CH;
-    double x[CH];
-    if (act)
-      load_chunk(W + size_t(dof) * nrhs + j0, nc, x);
-    else
-#pragma unroll
-      for (int j = 0; j < CH; ++j) x[j] = 0.0;
-    wave_sync();
-    if (act)
-#pragma unroll
-      for (int j = 0; j < CH; ++j) X[lane * CH + j] = x[j];
-    wave_sync();
-    if (!BACKWARD) {
-      if (sp) {
-        // remainder rows: x_q -= sum_i T_iq x_{nr+i}
-        if (lane < nr)
-          for (int i = 0; i < k; ++i) {
-            const double t = double(sT[i * ntr + lane]);
-            const double* xs = X + (nr + i) * CH;
-            double xv[CH];
-#pragma unroll
-            for (int j = 0; j < CH; ++j) xv[j] = xs[j];
-#pragma unroll
-            for (int j = 0; j < CH; ++j) x[j] = fma(-t, xv[j], x[j]);
-          }
-        wave_sync();
-        if (act)
-#pragma unroll
-          for (int j = 0; j < CH; ++j) X[lane * CH + j] = x[j];
-        wave_sync();
-      }
-      // P, then the unit lower L^{-1}: y_i = x'_i + sum_{u<i} (L^{-1})_iu x'_u
-      if (act)
-#pragma unroll
-        for (int j = 0; j < CH; ++j) x[j] = X[rm * CH + j];
-      wave_sync();
-      if (act)
-#pragma unroll
-        for (int j = 0; j < CH; ++j) X[lane * CH + j] = x[j];
-      wave_sync();
-      if (act) {
-        const T* row = sI + lane * ni;
-        for (int u = 0; u < lane; ++u) {
-          const double l = double(row[u]);
-          const double* xu = X + u * CH;
-          double xv[CH];
-#pragma unroll
-          for (int j = 0; j < CH; ++j) xv[j] = xu[j];
-#pragma unroll
-          for (int j = 0; j < CH; ++j) x[j] = fma(l, xv[j], x[j]);
-        }
-      }
-    } else {
-      // y = U^{-1} x, then skeleton rows: y_{nr+i} -= sum_q T_iq y_q
-      double y[CH];
-#pragma unroll
-      for (int j = 0; j < CH; ++j) y[j] = 0.0;
-      if (act) {
-        const T* row = sI + lane * ni;
-        for (int u = lane; u < n; ++u) {
-          const double uu = double(row[u]);
-          const double* xu = X + u * CH;
-          double xv[CH];
-#pragma unroll
-          for (int j = 0; j < CH; ++j) xv[j] = xu[j];
-#pragma unroll
-          for (int j = 0; j < CH; ++j) y[j] = fma(uu, xv[j], y[j]);
-        }
-      }
-      if (sp) {
-        wave_sync();
-        if (act)
-#pragma unroll
-          for (int j = 0; j < CH; ++j) X[lane * CH + j] = y[j];
-        wave_sync();
-        if (act && lane >= nr) {
-          const T* trow = sT + (lane - nr) * ntr;
-          for (int q = 0; q < nr; ++q) {
-            const double t = double(trow[q]);
-            const double* xq = X + q * CH;
-            double xv[CH];
-#pragma unroll
-            for (int j = 0; j < CH; ++j) xv[j] = xq[j];
-#pragma unroll
-            for (int j = 0; j < CH; ++j) y[j] = fma(-t, xv[j], y[j]);
-          }
-        }
-      } else {
-        wave_sync();
-        wave_sync();
-      }
-#pragma unroll
-      for (int j = 0; j < CH; ++j) x[j] = y[j];
-    }
-    if (act) {
-      T* dst = W + size_t(dof) * nrhs + j0;
-#pragma unroll
-      for (int j = 0; j < CH; ++j)
-        if (j < nc) dst[j] = T(x[j]);
-    }
-  }
-}
-
-// Groups of P lanes per owner segment, 64 / P owners per wave, for levels
-// whose segments hold at most P DOFs and have at most P neighbours: forward
-// (owner = non-separator a, neighbours = the level's separators s):
-// W[skel_a] -= A'_{a,s} W[skel_s]; backward (owner = separator s, all its
-// neighbours b): W[skel_s] -= A'_{s,b} W[skel_b].  Lane e of a group reads
-// neighbour e's sizes and offsets into the group's LDS; then the neighbours'
-// skeleton rows (stacked, K rows, at most rows_cap) are gathered into LDS in
-// the storage type with independent loads, and lane i forms skeleton row i
-// of the product, reading its rows of the scaled blocks directly.
-// LDS bytes of one group (vs: bytes of the storage type).
-__host__ __device__ inline int sep_grp_bytes(int P, int rows_cap, int vs) {
-  return (24 * P + vs * LEAF_SOLVE_CHUNK * rows_cap + 15) / 16 * 16;
-}
-
-template <typename T, bool FWD, int P>
-__global__ __launch_bounds__(64) void k_sep_wave(const DSeg* segs, int nseg, const DNbr* nbrs, const DBlk* blks,
-                                                 const int32_t* iarena, const T* varena, DLevelDyn dyn, T* W,
-                                                 int nrhs, int rows_cap) {
-  extern __shared__ double lds[];
-  constexpr int CH = LEAF_SOLVE_CHUNK;
-  const int lane = threadIdx.x % P, grp = threadIdx.x / P;
-  const int a = blockIdx.x * (64 / P) + grp;
-  char* base = reinterpret_cast<char*>(lds) + size_t(grp) * sep_grp_bytes(P, rows_cap, int(sizeof(T)));
-  int64_t* m_dofo = reinterpret_cast<int64_t*>(base);  // neighbour e: its skeleton DOF list
-  int64_t* m_soff = m_dofo + P;                        // its scaled block (owner rows)
-  int* m_off = reinterpret_cast<int*>(m_soff + P);     // first stacked row
-  int* m_kb = m_off + P;                               // skeleton size
-  T* X = reinterpret_cast<T*>(m_kb + P);               // stacked rows, K x CH
-  bool own = false;
-  int ka = 0, nra = 0, ne = 0;
-  DSeg S{};
-  if (a < nseg) {
-    S = segs[a];
-    own = FWD != ((S.flags & SEG_IS_SEP) != 0);
-    ka = dyn.k[a];
-    nra = dyn.nr[a];
-    ne = S.nbr_end - S.nbr_begin;
-  }
-  if (!own || ka > P || ne > P) ka = 0;  // never on a level launched with this P
-  if (ka == 0) ne = 0;
-  int kb = 0;
-  int64_t dofo = 0, soff = 0;
-  if (lane < ne) {
-    const DNbr nb = nbrs[S.nbr_begin + lane];
-    if (!FWD || nb.d_is_sep) {
-      kb = dyn.k[nb.d];
-      dofo = segs[nb.d].ioff + dyn.nr[nb.d];
-      soff = blks[nb.blk_cd].soff;
-    }
-  }
-  // inclusive prefix of the neighbours' row counts inside the group
-  int off = kb;
-#pragma unroll
-  for (int o = 1; o < P; o <<= 1) {
-    const int v = __shfl_up(off, o, P);
-    if (lane >= o) off += v;
-  }
-  int K = __shfl(off, P - 1, P);
-  off -= kb;
-  if (K > rows_cap) K = 0;  // the level's bound on neighbour sizes; never taken
-  m_off[lane] = off;
-  m_kb[lane] = kb;
-  m_dofo[lane] = dofo;
-  m_soff[lane] = soff;
-  const bool act = lane < ka && K > 0;
-  const int dof = act ? iarena[S.ioff + nra + lane] : 0;
-  for (int j0 = 0; j0 < nrhs; j0 += CH) {
-    const int nc = nrhs - j0 < CH ? nrhs - j0 : CH;
-    double own_w[CH];
-    if (act)
-      load_chunk(W + size_t(dof) * nrhs + j0, nc, own_w);
-    wave_sync();
-    // stacked row t belongs to the last neighbour with rows starting at or
-    // before t; two rows per lane per pass, their loads issued together
-    for (int t0 = lane; t0 < K; t0 += 2 * P) {
-      int dr[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int t = t0 + h * P < K ? t0 + h * P : t0;
-        int e = 0;
-        for (int f = 0; f < ne; ++f)
-          if (m_kb[f] > 0 && m_off[f] <= t) e = f;
-        dr[h] = iarena[m_dofo[e] + (t - m_off[e])];
-      }
-      double xv[2][CH];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) load_chunk(W + size_t(dr[h]) * nrhs + j0, nc, xv[h]);
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-        if (t0 + h * P < K)
-#pragma unroll
-          for (int j = 0; j < CH; ++j) X[(t0 + h * P) * CH + j] = T(xv[h][j]);
-    }
-    wave_sync();
-    if (act) {
-      double acc[CH];
-#pragma unroll
-      for (int j = 0; j < CH; ++j) acc[j] = 0.0;
-      // this lane's row of each scaled block, 8 entries per trip to memory
-      for (int e = 0; e < ne; ++e) {
-        const int kbe = m_kb[e];
-        const T* arow = varena + m_soff[e] + size_t(lane) * kbe;
-        const T* xe = X + m_off[e] * CH;
-        for (int u0 = 0; u0 < kbe; u0 += 8) {
-          T av[8];
-#pragma unroll
-          for (int b = 0; b < 8; ++b) av[b] = arow[u0 + b < kbe ? u0 + b : kbe - 1];
-          if constexpr (sizeof(T) == 4) {
-            // rows past kbe: row kbe - 1 times zero (no branch around the
-            // loads, so they are issued together)
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-              const bool in = u0 + b < kbe;
-              const double a = in ? double(av[b]) : 0.0;
-              const T* xr = xe + (in ? u0 + b : kbe - 1) * CH;
-              T xv[CH];
-#pragma unroll
-              for (int j = 0; j < CH; ++j) xv[j] = xr[j];
-#pragma unroll
-              for (int j = 0; j < CH; ++j) acc[j] = fma(a, double(xv[j]), acc[j]);
-            }
-          } else {
-            // (FP64: the batch's registers would halve the waves per SIMD)
-#pragma unroll
-            for (int b = 0; b < 8; ++b)
-              if (u0 + b < kbe)
-#pragma unroll
-                for (int j = 0; j < CH; ++j) acc[j] = fma(double(av[b]), double(xe[(u0 + b) * CH + j]), acc[j]);
-          }
-        }
-      }
-      T* dst = W + size_t(dof) * nrhs + j0;
-#pragma unroll
-      for (int j = 0; j < CH; ++j)
-        if (j < nc) dst[j] = T(own_w[j] - acc[j]);
-    }
-  }
-}
-
 // acc[c] += A[i0 + rows, 0:K] W[idx[0:K], j0 + 16c + cols] on the matrix
 // cores (FP64 16x16x4 for both storage types): wave w of the block owns
 // output rows 16w..16w+15 of the pass of ib <= GG_ROWS rows, and acc[c]
@@ -915,6 +627,319 @@ __global__ __launch_bounds__(WG) void k_sep_bwd(const DSeg* segs, int nseg, cons
         if (j < nc) W[base + j] = T(double(W[base + j]) - acc[c][r]);
       }
     }
+  }
+}
+
+// One-wave products on the matrix cores for the levels of small segments:
+// acc[c] += sum over u in [u0, u1) of a(i, u) b(u, 16c + l%16) for the
+// 16-row tile at i0, FP64 16x16x4 MFMA.  Lane l of a k-step supplies
+// a(i0 + l%16, u) and b(u, .) for u = k0 + l/16 (a() loads with clamped
+// addresses and returns 0 outside the operator, b() reads clamped rows);
+// the operator entries of SW_KS k-steps are loaded together before their
+// products.  Lane l receives column 16c + l%16 of rows i0 + l/16 + 4r.
+constexpr int SW_KS = 8;
+constexpr int SW_LD = GG_LDX;  // FP64 LDS row of 64 right-hand sides
+
+template <typename AF, typename BF>
+__device__ inline void wave_tile_mfma(AF a, BF b, int i0, int u0, int u1, int nct, gg_v4 acc[4]) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int i = i0 + li;
+  for (int ub = u0; ub < u1; ub += 4 * SW_KS) {
+    double av[SW_KS];
+#pragma unroll
+    for (int s = 0; s < SW_KS; ++s) av[s] = ub + 4 * s < u1 ? a(i, ub + 4 * s + lk) : 0.0;
+#pragma unroll
+    for (int s = 0; s < SW_KS; ++s) {
+      if (ub + 4 * s >= u1) break;
+      const int u = ub + 4 * s + lk;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (c < nct) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], b(u, 16 * c + li), acc[c], 0, 0, 0);
+    }
+  }
+}
+
+// One wave per segment of at most 16 * RT DOFs (the fine levels): forward
+// (U_T, then P and L^{-1}) or backward (U^{-1}, then L_T) on its DOFs in
+// [remainder; skeleton] order.  The segment's rows of 64 right-hand sides
+// are staged in LDS in FP64; every product runs on the matrix cores, its
+// operator entries (T, the packed inverses) read from global memory.
+__host__ __device__ inline int seg_solve_mfma_lds_bytes(int RT) { return 8 * 16 * RT * SW_LD; }
+
+template <typename T, bool BACKWARD, int RT>
+__global__ __launch_bounds__(64) void k_seg_solve_mfma(const DSeg* segs, int nseg, const int32_t* iarena,
+                                                       const T* varena, DLevelDyn dyn, T* W, int nrhs) {
+  extern __shared__ double lds[];
+  const int c = blockIdx.x;
+  if (c >= nseg) return;
+  const int n = dyn.n[c];
+  if (n == 0 || n > 16 * RT) return;  // (never on a level launched with this RT)
+  const DSeg S = segs[c];
+  const int k = dyn.k[c], nr = dyn.nr[c];
+  const bool sp = dyn.passes[c] > 0 && nr > 0 && k > 0;
+  const int32_t* dofs = iarena + S.ioff;
+  const T* Inv = varena + S.lu_off;
+  const T* Tm = varena + S.t_off;
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+  // lane i < n keeps DOF i and piv[i] (row i of P X is row piv[i] of X)
+  const int mdof = lane < n ? dofs[lane] : 0;
+  const int mpiv = lane < n ? dofs[2 * S.cap + lane] : 0;
+  double* X = lds;
+  auto xrow = [&](int u, int col) { return X[(u < n ? u : n - 1) * SW_LD + col]; };
+  for (int j0 = 0; j0 < nrhs; j0 += 64) {
+    const int nc = nrhs - j0 < 64 ? nrhs - j0 : 64;
+    const int nct = (nc + 15) >> 4;
+    const int col = lane < nc ? lane : nc - 1;
+    for (int i0 = 0; i0 < n; i0 += 16) {
+      T v[16];
+#pragma unroll
+      for (int b = 0; b < 16; ++b) v[b] = W[size_t(__shfl(mdof, i0 + b < n ? i0 + b : n - 1)) * nrhs + j0 + col];
+#pragma unroll
+      for (int b = 0; b < 16; ++b)
+        if (i0 + b < n) X[(i0 + b) * SW_LD + lane] = lane < nc ? double(v[b]) : 0.0;
+    }
+    wave_sync();
+    if (!BACKWARD) {
+      if (sp) {
+        // remainder rows: x_q -= sum_i T_iq x_{nr+i} (reads skeleton rows only)
+        for (int q0 = 0; q0 < nr; q0 += 16) {
+          gg_v4 acc[4] = {};
+          wave_tile_mfma(
+              [&](int q, int i) {
+                const double t = double(Tm[size_t(i < k ? i : k - 1) * nr + (q < nr ? q : nr - 1)]);
+                return q < nr && i < k ? t : 0.0;
+              },
+              [&](int i, int cc) { return xrow(nr + i, cc); }, q0, 0, k, nct, acc);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int q = q0 + lk + 4 * r;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+              if (q < nr && cc < nct) X[q * SW_LD + 16 * cc + li] -= acc[cc][r];
+          }
+        }
+        wave_sync();
+      }
+      // P, then the unit lower L^{-1}: y_i = x_piv[i] + sum_{u<i} (L^{-1})_iu x_piv[u]
+      for (int i0 = 0; i0 < n; i0 += 16) {
+        gg_v4 acc[4] = {};
+        wave_tile_mfma(
+            [&](int i, int u) {
+              const double l = double(Inv[size_t(i < n ? i : n - 1) * n + (u < n ? u : n - 1)]);
+              return i < n && u < i ? l : (i < n && u == i ? 1.0 : 0.0);
+            },
+            [&](int u, int cc) { return X[__shfl(mpiv, u < n ? u : n - 1) * SW_LD + cc]; }, i0,
+            0, i0 + 16 < n ? i0 + 16 : n, nct, acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + lk + 4 * r;
+          const size_t base = size_t(__shfl(mdof, i < n ? i : n - 1)) * nrhs + j0;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            const int j = 16 * cc + li;
+            if (i < n && j < nc) W[base + j] = T(acc[cc][r]);
+          }
+        }
+      }
+    } else {
+      // y = U^{-1} x, top tile first: tile i0 reads rows u >= i0 only, so
+      // its result replaces rows i0.. of X
+      for (int i0 = 0; i0 < n; i0 += 16) {
+        gg_v4 acc[4] = {};
+        wave_tile_mfma(
+            [&](int i, int u) {
+              const double v = double(Inv[size_t(i < n ? i : n - 1) * n + (u < n ? u : n - 1)]);
+              return i < n && u >= i && u < n ? v : 0.0;
+            },
+            xrow, i0, i0, n, nct, acc);
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + lk + 4 * r;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc)
+            if (i < n && cc < nct) X[i * SW_LD + 16 * cc + li] = acc[cc][r];
+        }
+        wave_sync();
+      }
+      if (sp) {
+        // skeleton rows: y_{nr+i} -= sum_q T_iq y_q (reads remainder rows only)
+        for (int i0 = 0; i0 < k; i0 += 16) {
+          gg_v4 acc[4] = {};
+          wave_tile_mfma(
+              [&](int i, int q) {
+                const double t = double(Tm[size_t(i < k ? i : k - 1) * nr + (q < nr ? q : nr - 1)]);
+                return i < k && q < nr ? t : 0.0;
+              },
+              xrow, i0, 0, nr, nct, acc);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = i0 + lk + 4 * r;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+              if (i < k && cc < nct) X[(nr + i) * SW_LD + 16 * cc + li] -= acc[cc][r];
+          }
+        }
+        wave_sync();
+      }
+      for (int i = 0; i < n; ++i) {
+        const size_t d = size_t(__shfl(mdof, i));
+        if (lane < nc) W[d * nrhs + j0 + lane] = T(X[i * SW_LD + lane]);
+      }
+    }
+    wave_sync();
+  }
+}
+
+// One wave per owner segment with at most 64 neighbours, for levels whose
+// skeletons hold at most 64 DOFs; block (a, y) forms skeleton rows
+// 16 RT y .. 16 RT (y+1) - 1 of owner a: forward (owner = non-separator a,
+// neighbours = the level's separators s): W[skel_a] -= A'_{a,s} W[skel_s];
+// backward (owner = separator s, all its neighbours b):
+// W[skel_s] -= A'_{s,b} W[skel_b].  A table of the stacked neighbour rows
+// (K <= rows_cap: DOF, offset of the column in the neighbour's scaled block,
+// that block's row length) is built in LDS first; then each k-step of the
+// matrix-core product loads its operator entries and right-hand-side rows
+// straight from global memory, SEP_KS k-steps at a time.
+constexpr int SEP_KS = 4;  // k-steps whose loads are issued together
+
+__host__ __device__ inline int sep_mfma_lds_bytes(int rows_cap) { return 16 * (rows_cap > 0 ? rows_cap : 1); }
+
+template <typename T, bool FWD, int RT>
+__global__ __launch_bounds__(64) void k_sep_mfma(const DSeg* segs, int nseg, const DNbr* nbrs, const DBlk* blks,
+                                                 const int32_t* iarena, const T* varena, DLevelDyn dyn, T* W,
+                                                 int nrhs, int rows_cap) {
+  extern __shared__ double lds[];
+  __shared__ int m_off[64], m_kb[64];
+  __shared__ int64_t m_dofo[64], m_soff[64];
+  int64_t* t_ao = reinterpret_cast<int64_t*>(lds);
+  int* t_dof = reinterpret_cast<int*>(t_ao + rows_cap);
+  int* t_ld = t_dof + rows_cap;
+  const int a = blockIdx.x;
+  if (a >= nseg) return;
+  const DSeg S = segs[a];
+  if (FWD == ((S.flags & SEG_IS_SEP) != 0)) return;  // not an owner on this pass
+  const int ka = dyn.k[a], nra = dyn.nr[a];
+  const int r0 = int(blockIdx.y) * 16 * RT;
+  const int ne = S.nbr_end - S.nbr_begin;
+  if (r0 >= ka || ne > 64) return;  // (more neighbours never on a level launched with this kernel)
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+  int kb = 0;
+  int64_t dofo = 0, soff = 0;
+  if (lane < ne) {
+    const DNbr nb = nbrs[S.nbr_begin + lane];
+    if (!FWD || nb.d_is_sep) {
+      kb = dyn.k[nb.d];
+      dofo = segs[nb.d].ioff + dyn.nr[nb.d];
+      soff = blks[nb.blk_cd].soff;
+    }
+  }
+  // inclusive prefix of the neighbours' row counts
+  int off = kb;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(off, o);
+    if (lane >= o) off += v;
+  }
+  const int K = __shfl(off, 63);
+  if (K == 0 || K > rows_cap) return;  // (K > rows_cap never: the level's bound)
+  m_off[lane] = off - kb;
+  m_kb[lane] = kb;
+  m_dofo[lane] = dofo;
+  m_soff[lane] = soff;
+  wave_sync();
+  // stacked row t belongs to the last neighbour with rows starting at or
+  // before t; four rows per lane per pass, their loads issued together
+  for (int t0 = 0; t0 < K; t0 += 256) {
+    int e4[4], d4[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int t = t0 + lane + 64 * h < K ? t0 + lane + 64 * h : K - 1;
+      int e = 0;
+      for (int f = 0; f < ne; ++f)
+        if (m_kb[f] > 0 && m_off[f] <= t) e = f;
+      e4[h] = e;
+      d4[h] = iarena[m_dofo[e] + (t - m_off[e])];
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int t = t0 + lane + 64 * h;
+      if (t < K) {
+        t_dof[t] = d4[h];
+        t_ao[t] = m_soff[e4[h]] + (t - m_off[e4[h]]);
+        t_ld[t] = m_kb[e4[h]];
+      }
+    }
+  }
+  wave_sync();
+  const int32_t* da = iarena + S.ioff + nra;
+  for (int j0 = 0; j0 < nrhs; j0 += 64) {
+    const int nc = nrhs - j0 < 64 ? nrhs - j0 : 64;
+    const int nct = (nc + 15) >> 4;
+    gg_v4 acc[RT][4] = {};
+    // full chunks read columns j0 + 16c + l%16 at constant offsets; a last,
+    // partial chunk clamps them to its nc columns
+    auto tiles = [&](auto full) {
+      for (int u0 = 0; u0 < K; u0 += 4 * SEP_KS) {
+        int dof[SEP_KS], ld[SEP_KS];
+        int64_t ao[SEP_KS];
+#pragma unroll
+        for (int s = 0; s < SEP_KS; ++s) {
+          const int t = u0 + 4 * s + lk < K ? u0 + 4 * s + lk : K - 1;
+          dof[s] = t_dof[t];
+          ao[s] = t_ao[t];
+          ld[s] = t_ld[t];
+        }
+        T bv[SEP_KS][4], av[RT][SEP_KS];
+#pragma unroll
+        for (int s = 0; s < SEP_KS; ++s) {
+          const T* wr = W + size_t(dof[s]) * nrhs + j0;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            const int j = 16 * cc + li;
+            bv[s][cc] = decltype(full)::value ? wr[j] : wr[j < nc ? j : nc - 1];
+          }
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int s = 0; s < SEP_KS; ++s) {
+            const int i = r0 + 16 * rt + li;
+            av[rt][s] = varena[ao[s] + int64_t(i < ka ? i : ka - 1) * ld[s]];
+          }
+#pragma unroll
+        for (int s = 0; s < SEP_KS; ++s) {
+          if (u0 + 4 * s >= K) break;
+          const bool in = u0 + 4 * s + lk < K;
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+            if (r0 + 16 * rt >= ka) break;
+            const double av_ = in && r0 + 16 * rt + li < ka ? double(av[rt][s]) : 0.0;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+              if (cc < nct)
+                acc[rt][cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av_, double(bv[s][cc]), acc[rt][cc], 0, 0, 0);
+          }
+        }
+      }
+    };
+    if (nc == 64)
+      tiles(std::true_type{});
+    else
+      tiles(std::false_type{});
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + 16 * rt + lk + 4 * r;
+        if (i >= ka) continue;
+        const size_t base = size_t(da[i]) * nrhs + j0;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int j = 16 * cc + li;
+          if (j < nc) W[base + j] = T(double(W[base + j]) - acc[rt][cc][r]);
+        }
+      }
   }
 }
 

@@ -184,10 +184,10 @@ struct spalu_factor_s {
   GridGeom g{};
   // per level: n, k, nr, h, passes, off (host copy after the factorization)
   std::shared_ptr<std::vector<std::vector<int32_t>>> dyn_host;
-  // launch shapes of the solve sweeps from the actual sizes, per level: lanes
-  // per segment of the lane-group kernels (0: 256-thread kernels) and the
-  // largest stacked neighbour skeleton of an owner, and the largest skeleton
-  // (the row passes of the 256-thread separator kernels)
+  // launch shapes of the solve sweeps from the actual sizes, per level: the
+  // segment-size bound P of the one-wave kernels (0: 256-thread kernels),
+  // the largest stacked neighbour skeleton of an owner, and the largest
+  // skeleton (the row passes of the 256-thread separator kernels)
   std::vector<int> solve_P, solve_rows, solve_kmax;
   // side streams and events (owned by the ordering handle)
   FactorStreams* fs = nullptr;
@@ -928,12 +928,12 @@ int read_dyn_host(spalu_factor_t* F) {
     std::memcpy((*dh)[l].data(), raw + (Y.lv[l].o_dyn - lo), (*dh)[l].size() * 4);
   }
   F->dyn_host = dh;
-  // lane groups of P = 8..64 lanes for levels whose segments and neighbour
-  // counts fit P and whose staging fits 64 KB of LDS
+  // one-wave kernels for levels whose segments and neighbour counts fit
+  // P <= solve_lanes_max (a power of two from solve_lanes_min up; 16-row
+  // tiles, so P <= 16 is one tile) and whose stacked-row table fits 48 KB
   F->solve_P.assign(size_t(L) + 1, 0);
   F->solve_rows.assign(size_t(L) + 1, 1);
   F->solve_kmax.assign(size_t(L) + 1, 1);
-  const int vs = int(Y.vsize);
   for (int l = 1; l <= L; ++l) {
     const LevelTabs& T = Y.lv[l];
     const size_t ns = T.segs.size();
@@ -961,9 +961,7 @@ int read_dyn_host(spalu_factor_t* F) {
     int P = g_tuning.solve_lanes_min;
     while (P < mx) P *= 2;
     if (P > g_tuning.solve_lanes_max) P = 0;
-    if (P && size_t(64 / P) * seg_solve_grp_bytes(P, vs) <= 65536 &&
-        size_t(64 / P) * sep_grp_bytes(P, rows, vs) <= 65536)
-      F->solve_P[l] = P;
+    if (P && sep_mfma_lds_bytes(rows) <= 49152) F->solve_P[l] = P;
     F->solve_rows[l] = rows;
     F->solve_kmax[l] = kmax;
   }
@@ -1376,19 +1374,20 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
   LAUNCH(K_SEPLEAF, 0, k_sep_from_leaves<T><<<nblocks(nsep * nrhs), WG, 0, st>>>(
       nsep, tab<int32_t>(ws, Y.o_sepv), tab<int8_t>(ws, Y.o_seplev), F->rowptr, F->colind, F->vals, B0, Z, W,
       nrhs));
-  // levels whose segments (by their actual sizes) fit lane groups of P
-  // lanes take the lane-group kernels
+  // levels whose segments (by their actual sizes) hold at most P <= 64 DOFs
+  // and neighbours take the one-wave matrix-core kernels
   auto seg_solve_grp = [&](const LevelTabs& T_, int l, int P, bool bwd, DLevelDyn d) {
     const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
     const int ns = int(T_.segs.size());
-    const unsigned nb = unsigned((ns + 64 / P - 1) / (64 / P));
-    const size_t lb = size_t(64 / P) * seg_solve_grp_bytes(P, int(sizeof(T)));
-#define SPALU_SSG(PP)                                                                                          \
-  if (bwd)                                                                                                     \
-    LAUNCH(K_SSOLVE_B, l, k_seg_solve_wave<T, true, PP><<<nb, 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs));  \
-  else                                                                                                         \
-    LAUNCH(K_SSOLVE_F, l, k_seg_solve_wave<T, false, PP><<<nb, 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs));
-    if (P == 8) { SPALU_SSG(8) } else if (P == 16) { SPALU_SSG(16) } else if (P == 32) { SPALU_SSG(32) } else { SPALU_SSG(64) }
+#define SPALU_SSG(RT)                                                                                          \
+  {                                                                                                            \
+    const size_t lb = size_t(seg_solve_mfma_lds_bytes(RT));                                                    \
+    if (bwd)                                                                                                   \
+      LAUNCH(K_SSOLVE_B, l, k_seg_solve_mfma<T, true, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs)); \
+    else                                                                                                       \
+      LAUNCH(K_SSOLVE_F, l, k_seg_solve_mfma<T, false, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs)); \
+  }
+    if (P <= 16) SPALU_SSG(1) else if (P == 32) SPALU_SSG(2) else SPALU_SSG(4)
 #undef SPALU_SSG
     return int(SPALU_OK);
   };
@@ -1398,14 +1397,16 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
     const DBlk* bk = tab<DBlk>(ws, T_.o_blks);
     const int ns = int(T_.segs.size());
     const int rc = F->solve_rows[l];
-    const unsigned nb = unsigned((ns + 64 / P - 1) / (64 / P));
-    const size_t lb = size_t(64 / P) * sep_grp_bytes(P, rc, int(sizeof(T)));
-#define SPALU_SG(PP)                                                                                           \
-  if (bwd)                                                                                                     \
-    LAUNCH(K_SEPBWD, l, k_sep_wave<T, false, PP><<<nb, 64, lb, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs, rc)); \
-  else                                                                                                         \
-    LAUNCH(K_SEPFWD, l, k_sep_wave<T, true, PP><<<nb, 64, lb, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs, rc));
-    if (P == 8) { SPALU_SG(8) } else if (P == 16) { SPALU_SG(16) } else if (P == 32) { SPALU_SG(32) } else { SPALU_SG(64) }
+    const size_t lb = size_t(sep_mfma_lds_bytes(rc));
+#define SPALU_SG(RT, NY)                                                                                       \
+  {                                                                                                            \
+    const dim3 g(unsigned(ns), NY);                                                                            \
+    if (bwd)                                                                                                   \
+      LAUNCH(K_SEPBWD, l, k_sep_mfma<T, false, RT><<<g, 64, lb, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs, rc)); \
+    else                                                                                                       \
+      LAUNCH(K_SEPFWD, l, k_sep_mfma<T, true, RT><<<g, 64, lb, st>>>(sg, ns, nbr, bk, iar, var, d, W, nrhs, rc)); \
+  }
+    if (P <= 16) SPALU_SG(1, 1) else if (P == 32) SPALU_SG(2, 1) else SPALU_SG(2, 2)
 #undef SPALU_SG
     return int(SPALU_OK);
   };
