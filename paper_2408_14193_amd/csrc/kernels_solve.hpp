@@ -659,81 +659,101 @@ __device__ inline void wave_tile_mfma(AF a, BF b, int i0, int u0, int u1, int nc
   }
 }
 
-// One wave per segment of at most 16 * RT DOFs (the fine levels): forward
-// (U_T, then P and L^{-1}) or backward (U^{-1}, then L_T) on its DOFs in
-// [remainder; skeleton] order.  The segment's rows of 64 right-hand sides
-// are staged in LDS in FP64; every product runs on the matrix cores, its
-// operator entries (T, the packed inverses) read from global memory.
-__host__ __device__ inline int seg_solve_mfma_lds_bytes(int RT) { return 8 * 16 * RT * SW_LD; }
+// NW waves per segment of at most 16 * NW * TPW DOFs: forward (U_T, then P
+// and L^{-1}) or backward (U^{-1}, then L_T) on its DOFs in [remainder;
+// skeleton] order.  The segment's rows of 64 right-hand sides are staged in
+// LDS in FP64; every product runs on the matrix cores in 16 x 64 output
+// tiles (tile t on wave t % NW), its operator entries (T, the packed
+// inverses) read from global memory.  One wave (NW = 1) serves the fine
+// levels' many small segments, four waves the coarse levels' larger ones.
+__host__ __device__ inline int seg_solve_mfma_lds_bytes(int rows) { return 8 * rows * SW_LD; }
+constexpr int SEG_MFMA_BLOCK_N = 128;  // largest segment of the four-wave shape (4 waves x 2 tiles)
 
-template <typename T, bool BACKWARD, int RT>
-__global__ __launch_bounds__(64) void k_seg_solve_mfma(const DSeg* segs, int nseg, const int32_t* iarena,
-                                                       const T* varena, DLevelDyn dyn, T* W, int nrhs) {
+template <typename T, bool BACKWARD, int NW, int TPW>
+__global__ __launch_bounds__(64 * NW) void k_seg_solve_mfma(const DSeg* segs, int nseg, const int32_t* iarena,
+                                                            const T* varena, DLevelDyn dyn, T* W, int nrhs) {
   extern __shared__ double lds[];
+  constexpr int NMAX = 16 * NW * TPW;
   const int c = blockIdx.x;
   if (c >= nseg) return;
   const int n = dyn.n[c];
-  if (n == 0 || n > 16 * RT) return;  // (never on a level launched with this RT)
+  if (n == 0 || n > NMAX) return;  // (never on a level launched with this shape)
   const DSeg S = segs[c];
   const int k = dyn.k[c], nr = dyn.nr[c];
   const bool sp = dyn.passes[c] > 0 && nr > 0 && k > 0;
   const int32_t* dofs = iarena + S.ioff;
+  const int32_t* piv = dofs + 2 * S.cap;
   const T* Inv = varena + S.lu_off;
   const T* Tm = varena + S.t_off;
-  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
-  // lane i < n keeps DOF i and piv[i] (row i of P X is row piv[i] of X)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  auto sync = [] {
+    if constexpr (NW == 1)
+      wave_sync();
+    else
+      __syncthreads();
+  };
+  // a row's DOF and permutation source: from lanes of the wave when the
+  // segment fits one wave's lanes, else from memory
   const int mdof = lane < n ? dofs[lane] : 0;
-  const int mpiv = lane < n ? dofs[2 * S.cap + lane] : 0;
+  const int mpiv = lane < n ? piv[lane] : 0;
+  auto dof_of = [&](int i) { return NMAX <= 64 ? __shfl(mdof, i) : dofs[i]; };
+  auto piv_of = [&](int i) { return NMAX <= 64 ? __shfl(mpiv, i) : piv[i]; };
   double* X = lds;
   auto xrow = [&](int u, int col) { return X[(u < n ? u : n - 1) * SW_LD + col]; };
+  const int ntile = (n + 15) >> 4;
   for (int j0 = 0; j0 < nrhs; j0 += 64) {
     const int nc = nrhs - j0 < 64 ? nrhs - j0 : 64;
     const int nct = (nc + 15) >> 4;
     const int col = lane < nc ? lane : nc - 1;
-    for (int i0 = 0; i0 < n; i0 += 16) {
+    // rows i = w + NW * b of the segment, 16 loads in flight per lane
+    for (int i0 = w; i0 < n; i0 += 16 * NW) {
       T v[16];
 #pragma unroll
-      for (int b = 0; b < 16; ++b) v[b] = W[size_t(__shfl(mdof, i0 + b < n ? i0 + b : n - 1)) * nrhs + j0 + col];
+      for (int b = 0; b < 16; ++b) {
+        const int i = i0 + NW * b < n ? i0 + NW * b : n - 1;
+        v[b] = W[size_t(dof_of(i)) * nrhs + j0 + col];
+      }
 #pragma unroll
       for (int b = 0; b < 16; ++b)
-        if (i0 + b < n) X[(i0 + b) * SW_LD + lane] = lane < nc ? double(v[b]) : 0.0;
+        if (i0 + NW * b < n) X[(i0 + NW * b) * SW_LD + lane] = lane < nc ? double(v[b]) : 0.0;
     }
-    wave_sync();
+    sync();
     if (!BACKWARD) {
       if (sp) {
         // remainder rows: x_q -= sum_i T_iq x_{nr+i} (reads skeleton rows only)
-        for (int q0 = 0; q0 < nr; q0 += 16) {
+        for (int t = w; 16 * t < nr; t += NW) {
           gg_v4 acc[4] = {};
           wave_tile_mfma(
               [&](int q, int i) {
-                const double t = double(Tm[size_t(i < k ? i : k - 1) * nr + (q < nr ? q : nr - 1)]);
-                return q < nr && i < k ? t : 0.0;
+                const double tv = double(Tm[size_t(i < k ? i : k - 1) * nr + (q < nr ? q : nr - 1)]);
+                return q < nr && i < k ? tv : 0.0;
               },
-              [&](int i, int cc) { return xrow(nr + i, cc); }, q0, 0, k, nct, acc);
+              [&](int i, int cc) { return xrow(nr + i, cc); }, 16 * t, 0, k, nct, acc);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int q = q0 + lk + 4 * r;
+            const int q = 16 * t + lk + 4 * r;
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc)
               if (q < nr && cc < nct) X[q * SW_LD + 16 * cc + li] -= acc[cc][r];
           }
         }
-        wave_sync();
+        sync();
       }
       // P, then the unit lower L^{-1}: y_i = x_piv[i] + sum_{u<i} (L^{-1})_iu x_piv[u]
-      for (int i0 = 0; i0 < n; i0 += 16) {
+      for (int t = w; t < ntile; t += NW) {
+        const int i0 = 16 * t;
         gg_v4 acc[4] = {};
         wave_tile_mfma(
             [&](int i, int u) {
               const double l = double(Inv[size_t(i < n ? i : n - 1) * n + (u < n ? u : n - 1)]);
               return i < n && u < i ? l : (i < n && u == i ? 1.0 : 0.0);
             },
-            [&](int u, int cc) { return X[__shfl(mpiv, u < n ? u : n - 1) * SW_LD + cc]; }, i0,
-            0, i0 + 16 < n ? i0 + 16 : n, nct, acc);
+            [&](int u, int cc) { return X[piv_of(u < n ? u : n - 1) * SW_LD + cc]; }, i0, 0,
+            i0 + 16 < n ? i0 + 16 : n, nct, acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = i0 + lk + 4 * r;
-          const size_t base = size_t(__shfl(mdof, i < n ? i : n - 1)) * nrhs + j0;
+          const size_t base = size_t(dof_of(i < n ? i : n - 1)) * nrhs + j0;
 #pragma unroll
           for (int cc = 0; cc < 4; ++cc) {
             const int j = 16 * cc + li;
@@ -742,34 +762,63 @@ __global__ __launch_bounds__(64) void k_seg_solve_mfma(const DSeg* segs, int nse
         }
       }
     } else {
-      // y = U^{-1} x, top tile first: tile i0 reads rows u >= i0 only, so
-      // its result replaces rows i0.. of X
-      for (int i0 = 0; i0 < n; i0 += 16) {
-        gg_v4 acc[4] = {};
-        wave_tile_mfma(
-            [&](int i, int u) {
-              const double v = double(Inv[size_t(i < n ? i : n - 1) * n + (u < n ? u : n - 1)]);
-              return i < n && u >= i && u < n ? v : 0.0;
-            },
-            xrow, i0, i0, n, nct, acc);
-        wave_sync();
+      // y = U^{-1} x: tile t reads rows u >= 16 t only
+      if constexpr (NW == 1) {
+        // one wave, top tile first: each result replaces rows no later tile reads
+        for (int t = 0; t < ntile; ++t) {
+          const int i0 = 16 * t;
+          gg_v4 acc[4] = {};
+          wave_tile_mfma(
+              [&](int i, int u) {
+                const double v = double(Inv[size_t(i < n ? i : n - 1) * n + (u < n ? u : n - 1)]);
+                return i < n && u >= i && u < n ? v : 0.0;
+              },
+              xrow, i0, i0, n, nct, acc);
+          wave_sync();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = i0 + lk + 4 * r;
+          for (int r = 0; r < 4; ++r) {
+            const int i = i0 + lk + 4 * r;
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc)
-            if (i < n && cc < nct) X[i * SW_LD + 16 * cc + li] = acc[cc][r];
+            for (int cc = 0; cc < 4; ++cc)
+              if (i < n && cc < nct) X[i * SW_LD + 16 * cc + li] = acc[cc][r];
+          }
+          wave_sync();
         }
-        wave_sync();
+      } else {
+        // several waves: every tile of the block first, then the results
+        gg_v4 acc[TPW][4] = {};
+#pragma unroll
+        for (int p = 0; p < TPW; ++p) {
+          const int i0 = 16 * (w + NW * p);
+          if (i0 < n)
+            wave_tile_mfma(
+                [&](int i, int u) {
+                  const double v = double(Inv[size_t(i < n ? i : n - 1) * n + (u < n ? u : n - 1)]);
+                  return i < n && u >= i && u < n ? v : 0.0;
+                },
+                xrow, i0, i0, n, nct, acc[p]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < TPW; ++p)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * (w + NW * p) + lk + 4 * r;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc)
+              if (i < n && cc < nct) X[i * SW_LD + 16 * cc + li] = acc[p][cc][r];
+          }
+        __syncthreads();
       }
       if (sp) {
         // skeleton rows: y_{nr+i} -= sum_q T_iq y_q (reads remainder rows only)
-        for (int i0 = 0; i0 < k; i0 += 16) {
+        for (int t = w; 16 * t < k; t += NW) {
+          const int i0 = 16 * t;
           gg_v4 acc[4] = {};
           wave_tile_mfma(
               [&](int i, int q) {
-                const double t = double(Tm[size_t(i < k ? i : k - 1) * nr + (q < nr ? q : nr - 1)]);
-                return i < k && q < nr ? t : 0.0;
+                const double tv = double(Tm[size_t(i < k ? i : k - 1) * nr + (q < nr ? q : nr - 1)]);
+                return i < k && q < nr ? tv : 0.0;
               },
               xrow, i0, 0, nr, nct, acc);
 #pragma unroll
@@ -780,14 +829,14 @@ __global__ __launch_bounds__(64) void k_seg_solve_mfma(const DSeg* segs, int nse
               if (i < k && cc < nct) X[(nr + i) * SW_LD + 16 * cc + li] -= acc[cc][r];
           }
         }
-        wave_sync();
+        sync();
       }
-      for (int i = 0; i < n; ++i) {
-        const size_t d = size_t(__shfl(mdof, i));
+      for (int i = w; i < n; i += NW) {
+        const size_t d = size_t(dof_of(i));
         if (lane < nc) W[d * nrhs + j0 + lane] = T(X[i * SW_LD + lane]);
       }
     }
-    wave_sync();
+    sync();
   }
 }
 
@@ -943,10 +992,41 @@ __global__ __launch_bounds__(64) void k_sep_mfma(const DSeg* segs, int nseg, con
   }
 }
 
+// Sum over the 64 lanes of a wave by DPP lane moves (no LDS traffic):
+// pairs, quads, half rows and rows, then row 0 into row 1 and rows 0-1 into
+// rows 2-3, so that lane 63 ends with the total, which is broadcast.
+union DppF64 {
+  double d;
+  int i[2];
+};
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move_f64(double x) {
+  DppF64 u, o;
+  u.d = x;
+  o.i[0] = __builtin_amdgcn_update_dpp(0, u.i[0], CTRL, ROWS, 0xF, false);
+  o.i[1] = __builtin_amdgcn_update_dpp(0, u.i[1], CTRL, ROWS, 0xF, false);
+  return o.d;
+}
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp_move_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move_f64<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_move_f64<0x140, 0xF>(v);  // row_mirror
+  v += dpp_move_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  DppF64 u, o;
+  u.d = v;
+  o.i[0] = __builtin_amdgcn_readlane(u.i[0], 63);
+  o.i[1] = __builtin_amdgcn_readlane(u.i[1], 63);
+  return o.d;
+}
+
 // r = b - A x in FP64 (column-major, ld n) and per-wave partial sums of
 // ||r_j||^2 and ||b_j||^2 (part[j * nparts + wave], nparts = 4 per block)
 // for a deterministic reduction: one thread per row, its stencil entries
-// (at most 8) read once, then every right-hand side in turn.
+// (at most 8 held in registers) read once, then every right-hand side in
+// turn, the next column's loads issued before this column's sums; entries
+// past a row's length are not loaded.
 __global__ __launch_bounds__(WG) void k_residual(int64_t n, int nrhs, const int64_t* rowptr,
                                                  const int32_t* colind, const double* vals,
                                                  const double* B, int64_t ldb, const double* X,
@@ -958,25 +1038,42 @@ __global__ __launch_bounds__(WG) void k_residual(int64_t n, int nrhs, const int6
   const bool live = v < n;
   const int64_t vr = live ? v : n - 1;
   const int64_t e0 = rowptr[vr], e1 = rowptr[vr + 1];
+  const int cnt = e1 - e0 < ME ? int(e1 - e0) : ME;
   int cols[ME];
   double vv[ME];
 #pragma unroll
   for (int m = 0; m < ME; ++m) {
-    const bool in = e0 + m < e1;
+    const bool in = m < cnt;
     cols[m] = in ? colind[e0 + m] : int(vr);
     vv[m] = in ? vals[e0 + m] : 0.0;
   }
-  for (int j = 0; j < nrhs; ++j) {
+  double xn[ME], bn;
+  auto fetch = [&](int j) {
     const double* x = X + j * ldx;
-    const double b = B[vr + j * ldb];
+    bn = B[vr + j * ldb];
+#pragma unroll
+    for (int m = 0; m < ME; ++m)
+      if (m < cnt) xn[m] = x[cols[m]];
+  };
+  fetch(0);
+  for (int j = 0; j < nrhs; ++j) {
+    double xc[ME];
+#pragma unroll
+    for (int m = 0; m < ME; ++m) xc[m] = xn[m];
+    const double b = bn;
+    if (j + 1 < nrhs) fetch(j + 1);
     double ax = 0.0;
 #pragma unroll
-    for (int m = 0; m < ME; ++m) ax += vv[m] * x[cols[m]];
-    for (int64_t e = e0 + ME; e < e1; ++e) ax += vals[e] * x[colind[e]];  // rows longer than ME
+    for (int m = 0; m < ME; ++m)
+      if (m < cnt) ax += vv[m] * xc[m];
+    if (e1 - e0 > ME) {  // rows longer than ME
+      const double* x = X + j * ldx;
+      for (int64_t e = e0 + ME; e < e1; ++e) ax += vals[e] * x[colind[e]];
+    }
     const double r = b - ax;
     if (live) R[v + j * n] = r;
-    const double sr = wave_sum(live ? r * r : 0.0);
-    const double sb = wave_sum(live ? b * b : 0.0);
+    const double sr = wave_sum_dpp(live ? r * r : 0.0);
+    const double sb = wave_sum_dpp(live ? b * b : 0.0);
     if (lane == 0) {
       part_r[size_t(j) * nparts + pidx] = sr;
       part_b[size_t(j) * nparts + pidx] = sb;

@@ -127,7 +127,7 @@ struct Layout {
 struct SweepGraph {
   const void *ws, *sw, *rowptr, *colind, *vals;
   int nrhs, prec;
-  std::vector<int> shape;  // launch shapes baked in (per level: lanes, rows, largest skeleton)
+  std::vector<int> shape;  // launch shapes baked in (per level: lanes, rows, largest skeleton and segment)
   hipGraphExec_t exec;
 };
 
@@ -186,9 +186,10 @@ struct spalu_factor_s {
   std::shared_ptr<std::vector<std::vector<int32_t>>> dyn_host;
   // launch shapes of the solve sweeps from the actual sizes, per level: the
   // segment-size bound P of the one-wave kernels (0: 256-thread kernels),
-  // the largest stacked neighbour skeleton of an owner, and the largest
-  // skeleton (the row passes of the 256-thread separator kernels)
-  std::vector<int> solve_P, solve_rows, solve_kmax;
+  // the largest stacked neighbour skeleton of an owner, the largest
+  // skeleton (the row passes of the 256-thread separator kernels) and the
+  // largest segment (the 256-thread segment kernel and its LDS)
+  std::vector<int> solve_P, solve_rows, solve_kmax, solve_nmax;
   // side streams and events (owned by the ordering handle)
   FactorStreams* fs = nullptr;
 };
@@ -934,6 +935,7 @@ int read_dyn_host(spalu_factor_t* F) {
   F->solve_P.assign(size_t(L) + 1, 0);
   F->solve_rows.assign(size_t(L) + 1, 1);
   F->solve_kmax.assign(size_t(L) + 1, 1);
+  F->solve_nmax.assign(size_t(L) + 1, 1);
   for (int l = 1; l <= L; ++l) {
     const LevelTabs& T = Y.lv[l];
     const size_t ns = T.segs.size();
@@ -950,9 +952,10 @@ int read_dyn_host(spalu_factor_t* F) {
     }
     const int32_t* ap = T.adj_ptr.data();
     const int32_t* ad = T.adj_d.data();
-    int mx = T.max_nbrs, rows = 1, kmax = 1;
+    int mx = T.max_nbrs, rows = 1, kmax = 1, nmax = 1;
     for (size_t c = 0; c < ns; ++c) {
       mx = std::max(mx, int(nv[c]));
+      nmax = std::max(nmax, int(nv[c]));
       kmax = std::max(kmax, int(kv[c]));
       int r = 0;
       for (int e = ap[c]; e < ap[c + 1]; ++e) r += kv[ad[e]];
@@ -964,6 +967,7 @@ int read_dyn_host(spalu_factor_t* F) {
     if (P && sep_mfma_lds_bytes(rows) <= 49152) F->solve_P[l] = P;
     F->solve_rows[l] = rows;
     F->solve_kmax[l] = kmax;
+    F->solve_nmax[l] = nmax;
   }
   return SPALU_OK;
 }
@@ -1219,6 +1223,9 @@ int factor_kernel_setup() {
     r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 6>), ID_LDS_LIMIT) && r;
     r = lds(reinterpret_cast<const void*>(&k_seg_lu<T, SEGLU_BLOCK_NT>), SEGLU_MAX_BYTES) && r;
     r = lds(reinterpret_cast<const void*>(&k_merge_elim<T, WG>), MELIM_MAX_BYTES) && r;
+    const size_t sb = size_t(seg_solve_mfma_lds_bytes(SEG_MFMA_BLOCK_N));
+    r = lds(reinterpret_cast<const void*>(&k_seg_solve_mfma<T, false, 4, 2>), sb) && r;
+    r = lds(reinterpret_cast<const void*>(&k_seg_solve_mfma<T, true, 4, 2>), sb) && r;
     return r;
   }();
   return ok ? int(SPALU_OK) : fail(SPALU_EDEVICE, "cannot raise the LDS limit of a factorization kernel");
@@ -1352,6 +1359,12 @@ SolveWs solve_layout(const spalu_factor_t* F, int nrhs, int restart = 0) {
 }
 
 // One application of the factor: W <- M^{-1} B0 (both in the working layout).
+// LDS of the four-wave segment solve on level l: the FP64 rows of its
+// largest segment, rounded up to whole 16-row tiles.
+size_t seg_mfma_block_lds(const spalu_factor_t* F, int l) {
+  return size_t(seg_solve_mfma_lds_bytes((F->solve_nmax[l] + 15) / 16 * 16));
+}
+
 template <typename T>
 int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStream_t st) {
   const Layout& Y = *F->lay;
@@ -1381,11 +1394,11 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
     const int ns = int(T_.segs.size());
 #define SPALU_SSG(RT)                                                                                          \
   {                                                                                                            \
-    const size_t lb = size_t(seg_solve_mfma_lds_bytes(RT));                                                    \
+    const size_t lb = size_t(seg_solve_mfma_lds_bytes(16 * RT));                                               \
     if (bwd)                                                                                                   \
-      LAUNCH(K_SSOLVE_B, l, k_seg_solve_mfma<T, true, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs)); \
+      LAUNCH(K_SSOLVE_B, l, k_seg_solve_mfma<T, true, 1, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs)); \
     else                                                                                                       \
-      LAUNCH(K_SSOLVE_F, l, k_seg_solve_mfma<T, false, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs)); \
+      LAUNCH(K_SSOLVE_F, l, k_seg_solve_mfma<T, false, 1, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs)); \
   }
     if (P <= 16) SPALU_SSG(1) else if (P == 32) SPALU_SSG(2) else SPALU_SSG(4)
 #undef SPALU_SSG
@@ -1420,7 +1433,11 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
       if (const int rc = sep_grp(T_, l, P, false, d)) return rc;
     } else {
       const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
-      LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
+      if (F->solve_nmax[l] <= SEG_MFMA_BLOCK_N)
+        LAUNCH(K_SSOLVE_F, l, k_seg_solve_mfma<T, false, 4, 2><<<unsigned(ns), WG, seg_mfma_block_lds(F, l), st>>>(
+                                  sg, ns, iar, var, d, W, nrhs));
+      else
+        LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
       const dim3 gsep(unsigned(ns), unsigned((F->solve_kmax[l] + GG_ROWS - 1) / GG_ROWS));
       LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<gsep, WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
                                                                    tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
@@ -1439,7 +1456,11 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
       const dim3 gsep(unsigned(ns), unsigned((F->solve_kmax[l] + GG_ROWS - 1) / GG_ROWS));
       LAUNCH(K_SEPBWD, l, k_sep_bwd<T><<<gsep, WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
                                                                    tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
-      LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
+      if (F->solve_nmax[l] <= SEG_MFMA_BLOCK_N)
+        LAUNCH(K_SSOLVE_B, l, k_seg_solve_mfma<T, true, 4, 2><<<unsigned(ns), WG, seg_mfma_block_lds(F, l), st>>>(
+                                  sg, ns, iar, var, d, W, nrhs));
+      else
+        LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
     }
   }
   if (wave_leaf && Y.leaf_wc != 0) {
@@ -1468,6 +1489,7 @@ int apply(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, const char* sw, 
   std::vector<int> shape(F->solve_P);
   shape.insert(shape.end(), F->solve_rows.begin(), F->solve_rows.end());
   shape.insert(shape.end(), F->solve_kmax.begin(), F->solve_kmax.end());
+  shape.insert(shape.end(), F->solve_nmax.begin(), F->solve_nmax.end());
   for (auto& gph : nd->graphs)
     if (gph.ws == F->ws && gph.sw == sw && gph.rowptr == F->rowptr && gph.colind == F->colind &&
         gph.vals == F->vals && gph.nrhs == nrhs && gph.prec == F->prec && gph.shape == shape)

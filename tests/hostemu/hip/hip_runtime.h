@@ -98,6 +98,25 @@ inline uint64_t __ballot(bool p) { return emu::ballot(p); }
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline int __ffsll(unsigned long long x) { return __builtin_ffsll((long long)x); }
 inline int emu_amdgcn_readlane(int v, int l) { return emu::shfl_i(v, l & 63); }
+// DPP lane moves of the controls the kernels use (quad_perm, row_shl/shr,
+// row_mirror, row_half_mirror, row_bcast:15, row_bcast:31); lanes outside
+// row_mask or with no valid source keep old (bound_ctrl false).
+inline int emu_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int, bool bound_ctrl) {
+  const int l = int(threadIdx.x) & 63, row = l >> 4, rl = l & 15;
+  int s = -1;
+  if (ctrl < 0x100) s = (l & ~3) + ((ctrl >> (2 * (l & 3))) & 3);
+  else if (ctrl >= 0x101 && ctrl <= 0x10F) s = rl + (ctrl - 0x100) < 16 ? l + (ctrl - 0x100) : -1;
+  else if (ctrl >= 0x111 && ctrl <= 0x11F) s = rl >= ctrl - 0x110 ? l - (ctrl - 0x110) : -1;
+  else if (ctrl == 0x140) s = (l & ~15) + 15 - rl;
+  else if (ctrl == 0x141) s = (l & ~7) + 7 - (l & 7);
+  else if (ctrl == 0x142) s = row >= 1 ? (l & ~15) - 1 : -1;
+  else if (ctrl == 0x143) s = row >= 2 ? 31 : -1;
+  else std::abort();
+  const int v = emu::shfl_i(src, s >= 0 ? s : l);  // every lane takes part
+  if (!((row_mask >> row) & 1)) return old;
+  if (s < 0) return bound_ctrl ? 0 : old;
+  return v;
+}
 inline int emu_amdgcn_readfirstlane(int v) {
   const uint64_t m = emu::ballot(true);
   return emu::shfl_i(v, __builtin_ffsll((long long)m) - 1);
