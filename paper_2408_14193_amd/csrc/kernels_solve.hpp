@@ -1021,18 +1021,22 @@ __device__ inline double wave_sum_dpp(double v) {
   return o.d;
 }
 
-// r = b - A x in FP64 (column-major, ld n) and per-wave partial sums of
-// ||r_j||^2 and ||b_j||^2 (part[j * nparts + wave], nparts = 4 per block)
-// for a deterministic reduction: one thread per row, its stencil entries
-// (at most 8 held in registers) read once, then every right-hand side in
-// turn, the next column's loads issued before this column's sums; entries
-// past a row's length are not loaded.
+// r = b - A x in FP64 and per-wave partial sums of ||r_j||^2 and ||b_j||^2
+// (part[j * nparts + wave], nparts = 4 per block) for a deterministic
+// reduction: one thread per row, its stencil entries (at most 8 held in
+// registers) read once, then every right-hand side in turn, the next
+// column's loads issued before this column's sums; entries past a row's
+// length are not loaded.  r goes to R (FP64, column-major, ld n), or, with
+// TO_RHS, straight into the solve's right-hand side (row-major, storage
+// type T) through an LDS transpose of 128-byte row pieces.
+template <typename T, bool TO_RHS>
 __global__ __launch_bounds__(WG) void k_residual(int64_t n, int nrhs, const int64_t* rowptr,
                                                  const int32_t* colind, const double* vals,
                                                  const double* B, int64_t ldb, const double* X,
-                                                 int64_t ldx, double* R, double* part_r, double* part_b,
+                                                 int64_t ldx, double* R, T* Rw, double* part_r, double* part_b,
                                                  int nparts) {
   constexpr int ME = 8;
+  constexpr int JT = 128 / int(sizeof(T));  // columns per transposed piece
   const int64_t v = int64_t(blockIdx.x) * WG + threadIdx.x;
   const int lane = threadIdx.x & 63, pidx = blockIdx.x * NWAVE + (threadIdx.x >> 6);
   const bool live = v < n;
@@ -1071,7 +1075,23 @@ __global__ __launch_bounds__(WG) void k_residual(int64_t n, int nrhs, const int6
       for (int64_t e = e0 + ME; e < e1; ++e) ax += vals[e] * x[colind[e]];
     }
     const double r = b - ax;
-    if (live) R[v + j * n] = r;
+    if constexpr (TO_RHS) {
+      __shared__ T tile[WG][JT + 1];
+      const int jj = j % JT;
+      tile[threadIdx.x][jj] = T(r);
+      if (jj == JT - 1 || j == nrhs - 1) {
+        __syncthreads();
+        const int jc = jj + 1, jb = j - jj;
+        const int64_t v0 = int64_t(blockIdx.x) * WG;
+        for (int t = threadIdx.x; t < WG * jc; t += WG) {
+          const int vl = t / jc, cc = t - vl * jc;
+          if (v0 + vl < n) Rw[(v0 + vl) * nrhs + jb + cc] = tile[vl][cc];
+        }
+        __syncthreads();
+      }
+    } else {
+      if (live) R[v + j * n] = r;
+    }
     const double sr = wave_sum_dpp(live ? r * r : 0.0);
     const double sb = wave_sum_dpp(live ? b * b : 0.0);
     if (lane == 0) {

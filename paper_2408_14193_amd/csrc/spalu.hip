@@ -848,7 +848,9 @@ void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, 
       by = double(nrows) * nrhs * (8.0 + vs);
       break;
     case K_RESID:
-      by = double(nrows) * (nnzrow * 12.0 + 8.0) + 3.0 * double(nrows) * nrhs * 8.0;
+      // b and x read in FP64; r written in FP64, or (l = 1) into the next
+      // right-hand side in the storage type
+      by = double(nrows) * (nnzrow * 12.0 + 8.0) + double(nrows) * nrhs * (16.0 + (l == 1 ? vs : 8.0));
       fl = 2.0 * double(nrows) * nnzrow * nrhs;
       break;
     case K_SPMV:
@@ -1564,9 +1566,17 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
   double first = -1.0, worst = 0.0, prev = -1.0;
   int it = 0, slow = 0;
   std::vector<double> bnorm;
+  // classical refinement writes each residual straight into B0, the next
+  // correction's right-hand side
+  const bool r_to_b0 = so.restart == 0 && !alias;
   while (true) {
-    LAUNCH(K_RESID, 0, k_residual<<<s.rblk, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Bsrc, ldbres, X,
-                                                          ldx, R, pr, pb, s.rparts));
+    if (r_to_b0)
+      LAUNCH(K_RESID, 1, k_residual<T, true><<<s.rblk, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals, Bsrc,
+                                                                   ldbres, X, ldx, nullptr, B0, pr, pb, s.rparts));
+    else
+      LAUNCH(K_RESID, 0, k_residual<double, false><<<s.rblk, WG, 0, st>>>(F->n, nrhs, F->rowptr, F->colind, F->vals,
+                                                                         Bsrc, ldbres, X, ldx, R, nullptr, pr, pb,
+                                                                         s.rparts));
     LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pr, s.rparts, nr));
     if (bnorm.empty()) {
       LAUNCH(K_REDUCE, 0, k_reduce_cols<<<unsigned(nrhs), WG, 0, st>>>(pb, s.rparts, nb));
@@ -1593,8 +1603,7 @@ int run_solve(const spalu_factor_t* F, int nrhs, const double* B, int64_t ldb, d
     prev = worst;
     if (slow >= 3) break;
     if (so.restart == 0) {
-      // correction: solve with r as right-hand side, x += M r
-      LAUNCH(K_RHSIN, 0, k_rhs_in<T><<<rhs_grid(F->n, nrhs), WG, 0, st>>>(R, F->n, F->n, nrhs, B0));
+      // correction: solve with r (already in B0) as right-hand side, x += M r
       rc = apply<T>(F, B0, W, Z, nrhs, sw, graph, st);
       if (rc) return rc;
       LAUNCH(K_RHSOUT, 0, k_rhs_out<T><<<rhs_grid(F->n, nrhs), WG, 0, st>>>(W, F->n, nrhs, X, ldx, 1));

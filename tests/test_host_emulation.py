@@ -129,16 +129,19 @@ def test_smallest_launch_shapes(exe, tmp_path, prec):
 
 
 def test_block_separator_solve_many_rhs(exe, tmp_path):
-    """127 x 127 Helmholtz in FP32 with 70 right-hand sides and lane groups
-    of at most 32: the coarse levels take the 256-thread separator kernels
-    on the matrix cores, with skeletons above 64 rows (several row passes
-    per segment) and a full and a ragged chunk of right-hand-side columns."""
+    """127 x 127 Helmholtz in FP32 with 70 right-hand sides and one-wave
+    kernels for segments of at most 32 DOFs: the coarse levels take the
+    256-thread separator kernels and four-wave segment solves on the matrix
+    cores, with skeletons above 64 rows (several row passes per segment) and
+    a full and a ragged chunk of right-hand-side columns; classical
+    refinement, whose residuals go straight into the next right-hand side."""
     P = make_config(4, side=127, nrhs=1)
     _write(P, str(tmp_path))
     mr = []
-    it, first, final = _run(exe, str(tmp_path), 32, 0, P.eps, 70, 1e-10, 8, tuning=SMALL_SHAPES, max_rank=mr)
+    it, first, final = _run(exe, str(tmp_path), 32, 0, P.eps, 70, 1e-10, 0, tuning=SMALL_SHAPES, max_rank=mr)
     assert mr[0] > 64, mr
     # the factor alone already solves to about 3e-3 (a wrong row pass or
-    # column chunk would leave whole skeleton blocks unsolved)
-    assert first <= 1e-2 and it <= 5, (first, it)
+    # column chunk would leave whole skeleton blocks unsolved), and each
+    # classical step gains about as much
+    assert first <= 1e-2 and it <= 6, (first, it)
     assert final <= 1e-10
