@@ -158,19 +158,28 @@ __host__ __device__ inline int leaf_solve_wave_lds_bytes(int ni) { return 8 * LE
 // l % 16 of rows leaf_tile_row(i0, r).
 template <typename T>
 __device__ inline void leaf_tile_mfma(const T* A, int lda, int rows, int K, const double* X, int i0, double out[4]) {
+  constexpr int KS = 16;  // k-steps whose operand loads are issued together (K <= 64: one batch)
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const int i = i0 + li;
   const bool irow = i < rows;
   const int ic = irow ? i : rows - 1;
   typedef double v4 __attribute__((ext_vector_type(4)));
   v4 d = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int k = k0 + lk;
-    const bool kin = k < K;
-    const int kc = kin ? k : K - 1;
-    const double a = double(A[size_t(kc) * lda + ic]);
-    const double b = X[kc * LEAF_SOLVE_CHUNK + li];
-    d = __builtin_amdgcn_mfma_f64_16x16x4f64(irow && kin ? a : 0.0, kin ? b : 0.0, d, 0, 0, 0);
+  for (int kb = 0; kb < K; kb += 4 * KS) {
+    T av[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = kb + 4 * s + lk;
+      av[s] = A[size_t(k < K ? k : K - 1) * lda + ic];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      if (kb + 4 * s >= K) break;
+      const int k = kb + 4 * s + lk;
+      const bool kin = k < K;
+      const double b = X[(kin ? k : K - 1) * LEAF_SOLVE_CHUNK + li];
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(irow && kin ? double(av[s]) : 0.0, kin ? b : 0.0, d, 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) out[r] = d[r];
