@@ -7,6 +7,7 @@
 
 #include "device_common.hpp"
 #include "layout.hpp"
+#include "mfma_tile.hpp"
 
 namespace spalu {
 
@@ -950,6 +951,15 @@ __host__ __device__ inline int blk_scale_wave_need(int kc, int kd) {
 __host__ __device__ inline bool blk_scale_wave_fits(int kc, int kd, int lds_doubles) {
   return kc <= 64 && kd <= 64 && blk_scale_wave_need(kc, kd) <= lds_doubles;
 }
+// LDS bytes of the matrix-core coupling scaling of a kc x kd block (the
+// gathered block and L^{-1} times it in FP64, the row and column maps).
+constexpr int SCALE_MFMA_MAX = 155648;
+__host__ __device__ inline size_t blk_scale_mfma_bytes(int kc, int kd) {
+  return size_t(2) * kc * kd * 8 + size_t(kc + kd) * 4 + 16;
+}
+__host__ __device__ inline bool blk_scale_mfma_fits(int kc, int kd, int lds_bytes) {
+  return kc <= 128 && kd <= 128 && blk_scale_mfma_bytes(kc, kd) <= size_t(lds_bytes);
+}
 
 // Coupling scaling: A'_{cd} = L_ss,c^{-1} P_s,c A_cd[s_c, s_d] U_ss,d^{-1},
 // with the skeleton blocks of the packed inverses of c and d (the inverse of
@@ -958,7 +968,7 @@ __host__ __device__ inline bool blk_scale_wave_fits(int kc, int kd, int lds_doub
 template <typename T>
 __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_t* blk_list, int nlist,
                                                   const DSeg* segs, const int32_t* iarena, T* varena,
-                                                  DLevelDyn dyn, int wave_lds_doubles) {
+                                                  DLevelDyn dyn, int wave_lds_doubles, int mfma_lds) {
   extern __shared__ double lds[];
   const int bi = blockIdx.x;
   if (bi >= nlist) return;
@@ -970,6 +980,7 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
   const int nrc = dyn.nr[c], nrd = dyn.nr[d];
   if (kc == 0 || kd == 0) return;
   if (blk_scale_wave_fits(kc, kd, wave_lds_doubles)) return;  // taken by k_blk_scale_wave
+  if (blk_scale_mfma_fits(kc, kd, mfma_lds)) return;          // taken by k_blk_scale_mfma
   const bool spc = dyn.passes[c] > 0, spd = dyn.passes[d] > 0;
   const int32_t* permc = iarena + segs[c].ioff + segs[c].cap;
   const int32_t* permd = iarena + segs[d].ioff + segs[d].cap;
@@ -1033,6 +1044,109 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
           v += double(out[size_t(i) * kd + u]) * double(Ud[size_t(nrd + u) * nd + nrd + j]);
         out[size_t(i) * kd + j] = T(v);
       }
+  }
+}
+
+// The same coupling scaling on the matrix cores, four waves per block, for
+// blocks beyond the one-wave kernel whose skeletons hold at most 128 DOFs:
+// the gathered block X and Y = L_c^{-1} X stay in LDS in FP64; Y is formed
+// in 16 x 64 tiles with the entries of the packed inverse of c read from
+// memory, then out = Y U_d^{-1} is formed transposed, out^T = U_d^{-T} Y^T,
+// so that the entries of U_d^{-1} are the ones read from memory too.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_blk_scale_mfma(const DBlk* blks, const int32_t* blk_list, int nlist,
+                                                       const DSeg* segs, const int32_t* iarena, T* varena,
+                                                       DLevelDyn dyn, int wave_lds_doubles, int mfma_lds) {
+  extern __shared__ double lds[];
+  const int bi = blockIdx.x;
+  if (bi >= nlist) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+  const DBlk B = blks[blk_list[bi]];
+  const int c = B.c, d = B.d;
+  const int kc = dyn.k[c], kd = dyn.k[d];
+  if (kc == 0 || kd == 0) return;
+  if (blk_scale_wave_fits(kc, kd, wave_lds_doubles) || !blk_scale_mfma_fits(kc, kd, mfma_lds)) return;
+  const int nc = dyn.n[c], nd = dyn.n[d];
+  const int nrc = dyn.nr[c], nrd = dyn.nr[d];
+  const bool spc = dyn.passes[c] > 0, spd = dyn.passes[d] > 0;
+  const int32_t* permc = iarena + segs[c].ioff + segs[c].cap;
+  const int32_t* permd = iarena + segs[d].ioff + segs[d].cap;
+  const int32_t* pivc = permc + segs[c].cap;
+  const T* A = varena + B.off;
+  T* out = varena + B.soff;
+  const T* Lc = varena + segs[c].lu_off;
+  const T* Ud = varena + segs[d].lu_off;
+  double* X = lds;            // kc x kd: P_s A_cd[s_c, s_d]
+  double* Y = X + kc * kd;    // kc x kd: L^{-1} X
+  int* rs = reinterpret_cast<int*>(Y + kc * kd);  // kc: block row of row i of P_s X
+  int* cs = rs + kc;                              // kd: block column of column j
+  for (int i = tid; i < kc; i += WG) {
+    const int r = pivc[nrc + i] - nrc;
+    rs[i] = spc ? permc[r] : r;
+  }
+  for (int j = tid; j < kd; j += WG) cs[j] = spd ? permd[j] : j;
+  __syncthreads();
+  load_batched<8>(
+      kc * kd, tid, WG,
+      [&](int t) {
+        const int i = t / kd, j = t - i * kd;
+        return A[size_t(rs[i]) * nd + cs[j]];
+      },
+      [&](int t, T v) { X[t] = double(v); });
+  __syncthreads();
+  // Y = L^{-1} X (unit lower): row tile i0 needs columns u <= i of L^{-1}
+  const int nti = (kc + 15) >> 4, ncg = (kd + 63) >> 6;
+  for (int unit = w; unit < nti * ncg; unit += NWAVE) {
+    const int ti = unit / ncg, cg = unit - ti * ncg, i0 = 16 * ti, j0 = 64 * cg;
+    const int nct = ((kd - j0 < 64 ? kd - j0 : 64) + 15) >> 4;
+    gg_v4 acc[4] = {};
+    wave_tile_mfma(
+        [&](int i, int u) {
+          const double l = double(Lc[size_t(nrc + (i < kc ? i : kc - 1)) * nc + nrc + (u < kc ? u : kc - 1)]);
+          return i < kc && u < i ? l : (i < kc && u == i ? 1.0 : 0.0);
+        },
+        [&](int u, int col) {
+          const int j = j0 + col;
+          return X[(u < kc ? u : kc - 1) * kd + (j < kd ? j : kd - 1)];
+        },
+        i0, 0, i0 + 16 < kc ? i0 + 16 : kc, nct, acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + lk + 4 * r;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int j = j0 + 16 * cc + li;
+        if (i < kc && j < kd && cc < nct) Y[i * kd + j] = acc[cc][r];
+      }
+    }
+  }
+  __syncthreads();
+  // out^T = U^{-T} Y^T: row tile j0 of out^T (columns j of out) needs rows
+  // u <= j of U^{-1}
+  const int ntj = (kd + 15) >> 4, ncgi = (kc + 63) >> 6;
+  for (int unit = w; unit < ntj * ncgi; unit += NWAVE) {
+    const int tj = unit / ncgi, cg = unit - tj * ncgi, j0 = 16 * tj, i0 = 64 * cg;
+    const int nct = ((kc - i0 < 64 ? kc - i0 : 64) + 15) >> 4;
+    gg_v4 acc[4] = {};
+    wave_tile_mfma(
+        [&](int j, int u) {
+          const double uv = double(Ud[size_t(nrd + (u < kd ? u : kd - 1)) * nd + nrd + (j < kd ? j : kd - 1)]);
+          return j < kd && u <= j ? uv : 0.0;
+        },
+        [&](int u, int col) {
+          const int i = i0 + col;
+          return Y[(i < kc ? i : kc - 1) * kd + (u < kd ? u : kd - 1)];
+        },
+        j0, 0, j0 + 16 < kd ? j0 + 16 : kd, nct, acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 + lk + 4 * r;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int i = i0 + 16 * cc + li;
+        if (j < kd && i < kc && cc < nct) out[size_t(i) * kd + j] = T(acc[cc][r]);
+      }
+    }
   }
 }
 

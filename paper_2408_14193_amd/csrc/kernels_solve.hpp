@@ -495,7 +495,6 @@ constexpr int GG_COLS = 64;                // 4 column tiles of 16
 constexpr int GG_LDA = GG_TILE + 2;        // A tile row stride: a half-wave's reads hit distinct banks
 constexpr int GG_LDX = GG_COLS + 16;       // W tile row stride: rows k and k+1 on opposite bank halves
 constexpr int GG_LDS_DOUBLES = GG_ROWS * GG_LDA + GG_TILE * GG_LDX;
-typedef double gg_v4 __attribute__((ext_vector_type(4)));
 
 __device__ inline int gg_row(int r) { return ((threadIdx.x >> 6) << 4) + ((threadIdx.x & 63) >> 4) + 4 * r; }
 __device__ inline int gg_col(int c) { return 16 * c + (threadIdx.x & 15); }
@@ -639,34 +638,7 @@ __global__ __launch_bounds__(WG) void k_sep_bwd(const DSeg* segs, int nseg, cons
   }
 }
 
-// One-wave products on the matrix cores for the levels of small segments:
-// acc[c] += sum over u in [u0, u1) of a(i, u) b(u, 16c + l%16) for the
-// 16-row tile at i0, FP64 16x16x4 MFMA.  Lane l of a k-step supplies
-// a(i0 + l%16, u) and b(u, .) for u = k0 + l/16 (a() loads with clamped
-// addresses and returns 0 outside the operator, b() reads clamped rows);
-// the operator entries of SW_KS k-steps are loaded together before their
-// products.  Lane l receives column 16c + l%16 of rows i0 + l/16 + 4r.
-constexpr int SW_KS = 8;
 constexpr int SW_LD = GG_LDX;  // FP64 LDS row of 64 right-hand sides
-
-template <typename AF, typename BF>
-__device__ inline void wave_tile_mfma(AF a, BF b, int i0, int u0, int u1, int nct, gg_v4 acc[4]) {
-  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-  const int i = i0 + li;
-  for (int ub = u0; ub < u1; ub += 4 * SW_KS) {
-    double av[SW_KS];
-#pragma unroll
-    for (int s = 0; s < SW_KS; ++s) av[s] = ub + 4 * s < u1 ? a(i, ub + 4 * s + lk) : 0.0;
-#pragma unroll
-    for (int s = 0; s < SW_KS; ++s) {
-      if (ub + 4 * s >= u1) break;
-      const int u = ub + 4 * s + lk;
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (c < nct) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], b(u, 16 * c + li), acc[c], 0, 0, 0);
-    }
-  }
-}
 
 // NW waves per segment of at most 16 * NW * TPW DOFs: forward (U_T, then P
 // and L^{-1}) or backward (U^{-1}, then L_T) on its DOFs in [remainder;

@@ -63,7 +63,9 @@ struct LevelTabs {
   int max_cap = 0;  // largest uncompressed segment
   int max_nbrs = 0;          // largest neighbour count of a segment
   int scale_wave_lds = 0;    // LDS doubles of the one-wave coupling scaling
-  bool scale_block = false;  // some block may need the 256-thread version
+  int scale_mfma_lds = 0;    // LDS bytes of the matrix-core coupling scaling
+  bool scale_block_old = false;  // blocks may exceed the matrix-core scaling
+  bool scale_block = false;  // some block exceeds the one-wave coupling scaling
 };
 
 struct Layout {
@@ -364,13 +366,22 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
     {
       constexpr int SCALE_WAVE_MAX = 6144;  // 48 KB of LDS per wave at most
       int need = 0;
+      size_t need_m = 0;
       for (int32_t b : T.scale_list) {
         const int cc = T.segs[T.blks[b].c].cap, cd = T.segs[T.blks[b].d].cap;
         const int w = blk_scale_wave_need(std::min(cc, 64), std::min(cd, 64));
-        if (cc > 64 || cd > 64 || w > SCALE_WAVE_MAX) T.scale_block = true;
+        if (cc > 64 || cd > 64 || w > SCALE_WAVE_MAX) {
+          // beyond the one-wave kernel: the matrix-core kernel for skeletons
+          // of at most 128 DOFs within its LDS, the 256-thread kernel else
+          T.scale_block = true;
+          const size_t m = blk_scale_mfma_bytes(std::min(cc, 128), std::min(cd, 128));
+          if (cc > 128 || cd > 128 || m > size_t(SCALE_MFMA_MAX)) T.scale_block_old = true;
+          need_m = std::max(need_m, std::min(m, size_t(SCALE_MFMA_MAX)));
+        }
         need = std::max(need, std::min(w, SCALE_WAVE_MAX));
       }
       T.scale_wave_lds = std::max(need, 1);
+      T.scale_mfma_lds = int(need_m);
     }
   }
 
@@ -1179,8 +1190,13 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
       LAUNCH(K_SCALE, l, k_blk_scale_wave<T><<<nsc, 64, size_t(T_.scale_wave_lds) * 8, st>>>(
           blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds));
       if (T_.scale_block)
+        LAUNCH_MORE(K_SCALE, l, k_blk_scale_mfma<T><<<nsc, WG, size_t(T_.scale_mfma_lds), st>>>(
+            blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds,
+            T_.scale_mfma_lds));
+      if (T_.scale_block_old)
         LAUNCH_MORE(K_SCALE, l, k_blk_scale<T><<<nsc, WG, LDS_BYTES, st>>>(
-            blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds));
+            blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds,
+            T_.scale_mfma_lds));
     }
     if (l > 1) {
       const LevelTabs& U = Y.lv[l - 1];
@@ -1225,6 +1241,7 @@ int factor_kernel_setup() {
     r = lds(reinterpret_cast<const void*>(&k_seg_id_cols<T, 8, 2, true, 6>), ID_LDS_LIMIT) && r;
     r = lds(reinterpret_cast<const void*>(&k_seg_lu<T, SEGLU_BLOCK_NT>), SEGLU_MAX_BYTES) && r;
     r = lds(reinterpret_cast<const void*>(&k_merge_elim<T, WG>), MELIM_MAX_BYTES) && r;
+    r = lds(reinterpret_cast<const void*>(&k_blk_scale_mfma<T>), SCALE_MFMA_MAX) && r;
     const size_t sb = size_t(seg_solve_mfma_lds_bytes(SEG_MFMA_BLOCK_N));
     r = lds(reinterpret_cast<const void*>(&k_seg_solve_mfma<T, false, 4, 2>), sb) && r;
     r = lds(reinterpret_cast<const void*>(&k_seg_solve_mfma<T, true, 4, 2>), sb) && r;

@@ -66,6 +66,16 @@ def test_exact_elimination_2d(exe, tmp_path):
     assert first <= 1e-12
 
 
+def test_exact_elimination_large_couplings(exe, tmp_path):
+    """127 x 127 with eps = 0: no skeleton shrinks, so the coupling blocks
+    of the coarse levels (up to 63 x 63) exceed the one-wave scaling and
+    take the four-wave matrix-core kernel; the factor is then an exact LU."""
+    P = make_config(0, side=127, nrhs=1)
+    _write(P, str(tmp_path))
+    it, first, final = _run(exe, str(tmp_path), 64, 0, 0.0, 3, 0.0, 0)
+    assert first <= 1e-12
+
+
 def test_sampled_ids_with_resampling_and_fgmres(exe, tmp_path):
     """A predictor that always says rank 0 starts every ID at 5 samples, so
     the probe check rejects some IDs and the doubling passes run."""
