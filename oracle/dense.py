@@ -1,5 +1,5 @@
-"""Oracle dense kernels: pivoted LU with a pivot window, triangular solves,
-and the column-pivoted QR interpolative decomposition.
+"""Oracle dense kernels: pivoted LU with a pivot window, Cholesky, triangular
+solves, and the column-pivoted QR interpolative decomposition.
 
 Plain loops in FP64; each routine is the textbook definition.
 """
@@ -79,6 +79,49 @@ def solve_upper_transposed(LU, X):
         X[j] /= LU[j, j]
         X[j + 1:] -= np.outer(LU[j, j + 1:], X[j])
     return X
+
+
+def cholesky(M):
+    """Lower-triangular C with M = C C^T, column by column (the textbook
+    Cholesky algorithm; only the lower triangle of M is read).  This is the
+    LDL^T factorization of a symmetric positive definite block with the
+    square root of D split evenly between its two factors, C = L D^{1/2}.
+    A pivot <= 0 (M not positive definite) raises ValueError."""
+    A = np.array(M, dtype=np.float64, copy=True)
+    n = A.shape[0]
+    C = np.zeros_like(A)
+    for j in range(n):
+        d = A[j, j] - np.dot(C[j, :j], C[j, :j])
+        if not d > 0.0:
+            raise ValueError("non-positive pivot %d: block not positive definite" % j)
+        C[j, j] = np.sqrt(d)
+        C[j + 1:, j] = (A[j + 1:, j] - C[j + 1:, :j] @ C[j, :j]) / C[j, j]
+    return C
+
+
+def solve_lower(C, X):
+    """C^{-1} X with C lower triangular (non-unit diagonal)."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    n = C.shape[0]
+    for j in range(n):
+        X[j] /= C[j, j]
+        X[j + 1:] -= np.outer(C[j + 1:, j], X[j])
+    return X
+
+
+def solve_lower_transposed(C, X):
+    """C^{-T} X with C lower triangular (back substitution with C^T)."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    n = C.shape[0]
+    for j in range(n - 1, -1, -1):
+        X[j] /= C[j, j]
+        X[:j] -= np.outer(C[j, :j], X[j])
+    return X
+
+
+def right_solve_lower_transposed(C, X):
+    """X C^{-T} (solve Z C^T = X for Z)."""
+    return solve_lower(C, np.asarray(X).T).T
 
 
 def lu_solve(LU, piv, X):

@@ -20,6 +20,14 @@ A^(l) of eq. (4.9)).
         segments (E_(l), eq. (4.11)).
   3. Solve: x = V~ W~ b with W, V of eqs. (4.12)-(4.13).
 
+Symmetric form (Section 4.4.2, Opts.symmetric = 1, for symmetric positive
+definite A): A_{s,n} and A_{n,s}^T share one ID, so the sampled matrix is
+the one-sided Y = [A_{N,s}; G A_{F,s} / sqrt(h)], and every segment block
+is factored as LDL^T, here in its Cholesky form C C^T with C = L D^{1/2}, in
+place of the pivoted LU: the couplings are scaled as C_c^{-1} A_cd C_d^{-T},
+which keeps every level's matrix symmetric, and W~ = V~^T.  The leaves keep
+the pivoted LU (their Schur complement is symmetric either way).
+
 Readings of points the paper leaves open (each is a documented choice):
   * near field N of a segment: neighbour DOFs within Chebyshev grid
     distance max(1, ceil(rho * span)) of the segment's bounding box, rho =
@@ -60,7 +68,7 @@ from .nd import ND
 @dataclasses.dataclass
 class Opts:
     eps: float = 1e-6
-    symmetric: int = -1        # -1 detect, 0 stacked non-symmetric ID, 1 symmetric
+    symmetric: int = 0         # 0: stacked ID + pivoted LU; 1: symmetric form (one-sided ID + LDL^T)
     seed: int = 1234
     rho: float = 0.5
     h0: int = 8
@@ -82,6 +90,7 @@ class SegRec:
     h: int = 0
     passes: int = 0
     margin: float = float("inf")   # closest rank / check decision to its threshold
+    chol: bool = False         # symmetric form: LU holds the Cholesky factor C (lower), piv = identity
 
     @property
     def skel(self):
@@ -125,12 +134,13 @@ def _dense(A, rows, cols):
     return A[rows][:, cols].toarray()
 
 
-def coupling_rows(nd, lev, c, blocks, cur, opts):
+def coupling_rows(nd, lev, c, blocks, cur, opts, sym=False):
     """Rows of the stacked coupling matrix [A_{n,c}; A_{c,n}^T] of segment c
     (eq. (4.12)), split into near rows B_N and far rows B_F (Section 4.2.3,
     hybrid sampling); also the vertex id and half (0: a row of A_{n,c}, 1: a
     row of A_{c,n}^T) of every far row, which key its Gaussian entries.
-    Returns None when the segment has no coupling rows."""
+    With sym (symmetric form, Section 4.4.2) only the rows of A_{n,c} are
+    taken.  Returns None when the segment has no coupling rows."""
     lvl = nd.levels[lev]
     seg = lvl.segs[c]
     nbrs = [d for (a, d) in lvl.pairs if a == c and d != c]
@@ -140,8 +150,9 @@ def coupling_rows(nd, lev, c, blocks, cur, opts):
             continue
         rows.append(blocks[(d, c)])
         verts.append(cur[d]); halves.append(np.zeros(len(cur[d]), dtype=np.int64))
-        rows.append(blocks[(c, d)].T)
-        verts.append(cur[d]); halves.append(np.ones(len(cur[d]), dtype=np.int64))
+        if not sym:
+            rows.append(blocks[(c, d)].T)
+            verts.append(cur[d]); halves.append(np.ones(len(cur[d]), dtype=np.int64))
     if not rows or len(cur[c]) == 0:
         return None
     Bm = np.vstack(rows)
@@ -190,7 +201,7 @@ def segment_id(nd, lev, c, blocks, cur, opts, sym):
     """ID of segment c of level lev against the level-start blocks; returns
     the result of sampled_id, or None when the segment has no coupling rows
     or a negative rank hint keeps it whole."""
-    rows = coupling_rows(nd, lev, c, blocks, cur, opts)
+    rows = coupling_rows(nd, lev, c, blocks, cur, opts, sym)
     if rows is None:
         return None
     BN, BF, vf, hf = rows
@@ -206,13 +217,28 @@ def segment_id(nd, lev, c, blocks, cur, opts, sym):
 
 def _scale_block(X, rc, rd):
     """L_ss,c^{-1} P_s,c X U_ss,d^{-1} with the skeleton parts of the
-    two-stage LUs of segments c and d (the coupling scaling of eq. (4.10))."""
+    two-stage LUs of segments c and d (the coupling scaling of eq. (4.10));
+    in the symmetric form C_ss,c^{-1} X C_ss,d^{-T} with the skeleton parts
+    of their Cholesky factors."""
     LUc, pivc, nrc = rc.LU, rc.piv, rc.nr
     LUd, nrd = rd.LU, rd.nr
+    if rc.chol:
+        X = dense.solve_lower(LUc[nrc:, nrc:], X)
+        return dense.right_solve_lower_transposed(LUd[nrd:, nrd:], X)
     X = dense.apply_row_pivots(pivc[nrc:] - nrc, X)
     X = dense.solve_lower_unit(LUc[nrc:, nrc:], X)
     X = dense.right_solve_upper(LUd[nrd:, nrd:], X)
     return X
+
+
+def _segment_factor(M, nr, sym):
+    """Two-stage factorization of a segment's diagonal block in [r; s] order:
+    pivoted LU with the remainder rows first (Section 4.3), or, in the
+    symmetric form, the Cholesky factor of the block (no pivoting, so the
+    remainder is eliminated first by construction) with identity pivots."""
+    if sym:
+        return dense.cholesky(M), np.arange(M.shape[0])
+    return dense.lu_window(M, split=nr)
 
 
 def factor(nd, A, opts=None):
@@ -220,10 +246,9 @@ def factor(nd, A, opts=None):
     opts = Opts() if opts is None else opts
     A = sp.csr_matrix(A)
     A.sort_indices()
-    if opts.symmetric < 0:
-        sym = bool((abs(A - A.T)).nnz == 0)
-    else:
-        sym = bool(opts.symmetric)
+    sym = bool(opts.symmetric)
+    if sym and (abs(A - A.T)).nnz != 0:
+        raise ValueError("the symmetric form needs a symmetric matrix")
     L = nd.L
     N = A.shape[0]
     lvlL = nd.levels[L]
@@ -274,13 +299,13 @@ def factor(nd, A, opts=None):
                 M1[:, :nr] -= M1[:, nr:] @ T
                 M2 = M1[order, :].copy()
                 M2[:nr, :] -= T.T @ M2[nr:, :]
-                LU, piv = dense.lu_window(M2, split=nr)
+                LU, piv = _segment_factor(M2, nr, sym)
                 recs.append(SegRec(dofs=cur[c][order], nr=nr, T=T, LU=LU, piv=piv,
-                                   sparsified=True, h=h, passes=passes, margin=margin))
+                                   sparsified=True, h=h, passes=passes, margin=margin, chol=sym))
             else:
-                LU, piv = dense.lu_window(M, split=0)
+                LU, piv = _segment_factor(M, 0, sym)
                 recs.append(SegRec(dofs=cur[c].copy(), nr=0, T=None, LU=LU, piv=piv,
-                                   sparsified=False))
+                                   sparsified=False, chol=sym))
         sel = {}
         for c in range(nseg):
             if c in ids:
@@ -377,7 +402,10 @@ def apply_inverse(F, B):
             v = x[r.dofs]
             if r.sparsified and r.nr > 0:
                 v[:r.nr] -= r.T.T @ v[r.nr:]
-            v = dense.solve_lower_unit(r.LU, dense.apply_row_pivots(r.piv, v))
+            if r.chol:
+                v = dense.solve_lower(r.LU, v)
+            else:
+                v = dense.solve_lower_unit(r.LU, dense.apply_row_pivots(r.piv, v))
             x[r.dofs] = v
         for s, lst in rec.sep_coup.items():
             xs = x[rec.segs[s].skel]
@@ -392,7 +420,10 @@ def apply_inverse(F, B):
                 acc += Asd @ x[rec.segs[d].skel]
             x[rec.segs[s].skel] -= acc
         for r in rec.segs:
-            v = dense.solve_upper(r.LU, x[r.dofs])
+            if r.chol:
+                v = dense.solve_lower_transposed(r.LU, x[r.dofs])
+            else:
+                v = dense.solve_upper(r.LU, x[r.dofs])
             if r.sparsified and r.nr > 0:
                 v[r.nr:] -= r.T @ v[:r.nr]
             x[r.dofs] = v

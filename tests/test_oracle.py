@@ -625,3 +625,132 @@ def test_factor_cost_near_linear():
     assert s[-1] <= 1.15 and s[-1] < s[0]
     s0 = slopes(0.0)
     assert s0[-1] >= 1.35 and s0[-1] > s0[0]
+
+
+# ------------------------------------------- symmetric form (Section 4.4.2)
+def test_cholesky_and_triangular_solves_match_lapack():
+    """The LDL^T factor in Cholesky form and its triangular solves equal
+    LAPACK's Cholesky and dense solves; a block that is not positive
+    definite is refused."""
+    rng = np.random.default_rng(21)
+    G = rng.standard_normal((30, 30))
+    M = G @ G.T + 30 * np.eye(30)
+    C = dense.cholesky(M)
+    assert np.allclose(C, np.linalg.cholesky(M), rtol=1e-13, atol=1e-13)
+    X = rng.standard_normal((30, 4))
+    assert np.allclose(dense.solve_lower(C, X), np.linalg.solve(C, X), rtol=1e-12)
+    assert np.allclose(dense.solve_lower_transposed(C, X), np.linalg.solve(C.T, X), rtol=1e-12)
+    Z = rng.standard_normal((5, 30))
+    assert np.allclose(dense.right_solve_lower_transposed(C, Z), Z @ np.linalg.inv(C.T), rtol=1e-10)
+    with pytest.raises(ValueError):
+        dense.cholesky(-M)
+
+
+@pytest.mark.parametrize("cfg,side", [(0, 15), (0, 31), (1, 31), (3, 7), (3, 15)])
+def test_sym_eps0_equals_dense_lu(cfg, side):
+    """Symmetric form with compression off: exact block LDL^T along the ND
+    tree, a dense solve to 1e-12."""
+    P = make_config(cfg, side=side, nrhs=2)
+    F = spalu.factor(nd_order(P.dims), P.scipy(), spalu.Opts(eps=0.0, symmetric=1))
+    x = spalu.apply_inverse(F, P.rhs)
+    xe = _solve_dense(P)
+    assert np.linalg.norm(x - xe) <= 1e-12 * np.linalg.norm(xe)
+
+
+def _level_asymmetry(cfg, side, eps, symmetric):
+    P = make_config(cfg, side=side)
+    seen = {}
+    spalu.factor(nd_order(P.dims), P.scipy(),
+                 spalu.Opts(eps=eps, symmetric=symmetric, trace=lambda lev, d: seen.setdefault(lev, d)))
+    out = {}
+    for lev, d in seen.items():
+        b = d["blocks"]
+        big = max(np.abs(v).max() for v in b.values() if v.size)
+        out[lev] = max((np.abs(v - b[(cd[1], cd[0])].T).max() for cd, v in b.items() if v.size),
+                       default=0.0) / big
+    return out
+
+
+def test_sym_level_matrices_stay_symmetric():
+    """W~ = V~^T (Section 4.4.2): with the LDL^T (Cholesky) scaling every
+    level's matrix is symmetric to rounding, which is what lets one ID
+    serve A_{s,n} and A_{n,s}^T; the LU scaling of the stacked form makes
+    it unsymmetric after the first level (the contrast shows the check
+    sees a one-sided scaling)."""
+    a_sym = _level_asymmetry(1, 31, 1e-6, 1)
+    a_lu = _level_asymmetry(1, 31, 1e-6, 0)
+    assert len(a_sym) >= 4
+    assert max(a_sym.values()) <= 1e-12
+    assert max(a_lu.values()) >= 1e-3
+
+
+def test_sym_level_L_ids_are_ids_of_the_exact_one_sided_couplings():
+    """Symmetric form: with every row near (rho large) each level-L ID is
+    LAPACK's pivoted QR ID of S_{n,c} alone, from the dense Schur
+    complement of the leaves computed here with numpy."""
+    P = make_config(1, side=31)
+    nd = nd_order(P.dims)
+    A = P.scipy()
+    seen = {}
+    o = spalu.Opts(eps=P.eps, rho=1e9, symmetric=1, trace=lambda lev, d: seen.setdefault(lev, d))
+    spalu.factor(nd, A, o)
+    L = nd.L
+    S, pos = _level_schur(A, nd, L)
+    lvl = nd.levels[L]
+    tr = seen[L]
+    checked = 0
+    for c, sg in enumerate(lvl.segs):
+        if c not in tr["ids"]:
+            continue
+        k, perm, T, h, passes, _ = tr["ids"][c]
+        vc = pos[tr["cur"][c]]
+        Y = np.vstack([S[np.ix_(pos[tr["cur"][d]], vc)] for (a, d) in lvl.pairs if a == c and d != c])
+        ks, ps, Ts = _scipy_id(Y, P.eps)
+        assert (k, passes) == (ks, 1)
+        _check_pivots(Y, perm, k, ps)
+        if np.array_equal(perm, ps):
+            assert np.allclose(T, Ts, rtol=1e-7, atol=1e-9)
+        checked += 1
+    assert checked >= 8
+
+
+@pytest.mark.parametrize("cfg,side", [(0, 63), (1, 63), (3, 15)])
+def test_sym_compressed_within_10_eps(cfg, side):
+    """Symmetric form, compression on: normwise backward error <= 10 eps,
+    the relative residual <= 10 eps for the Laplacians, and refinement to
+    1e-10."""
+    P = make_config(cfg, side=side, nrhs=2)
+    A = P.scipy()
+    F = spalu.factor(nd_order(P.dims), A, spalu.Opts(eps=P.eps, symmetric=1))
+    assert sum(r.sparsified for rec in F.levels.values() for r in rec.segs) > 0
+    x, it, hist = spalu.solve(F, P.rhs, tol=1e-10, max_iter=30)
+    assert hist[-1].max() <= 1e-10
+    x0 = spalu.apply_inverse(F, P.rhs)
+    normA = np.linalg.norm(A.toarray(), 2)
+    back = np.linalg.norm(P.rhs - A @ x0, axis=0) / (normA * np.linalg.norm(x0, axis=0))
+    assert back.max() <= 10 * P.eps
+    if cfg != 1:
+        assert hist[0].max() <= 10 * P.eps
+
+
+def test_sym_solution_operator_is_symmetric():
+    """W~ = V~^T: the symmetric form's approximate inverse is a symmetric
+    matrix to rounding even with compression on, while the stacked form's
+    is symmetric only to the truncation level."""
+    P = make_config(1, side=31)
+    nd = nd_order(P.dims)
+    M1 = spalu.apply_inverse(spalu.factor(nd, P.scipy(), spalu.Opts(eps=1e-4, symmetric=1)), np.eye(961))
+    M0 = spalu.apply_inverse(spalu.factor(nd, P.scipy(), spalu.Opts(eps=1e-4)), np.eye(961))
+    assert np.linalg.norm(M1 - M1.T) <= 1e-13 * np.linalg.norm(M1)
+    assert np.linalg.norm(M0 - M0.T) >= 1e-7 * np.linalg.norm(M0)
+
+
+def test_sym_refuses_what_it_cannot_factor():
+    """The symmetric form needs a symmetric matrix, and its LDL^T without
+    pivoting needs positive pivots (a negative definite operator has none)."""
+    P = make_config(2, side=15)
+    with pytest.raises(ValueError):
+        spalu.factor(nd_order(P.dims), P.scipy(), spalu.Opts(eps=1e-6, symmetric=1))
+    P = make_config(0, side=15)
+    with pytest.raises(ValueError):
+        spalu.factor(nd_order(P.dims), -P.scipy(), spalu.Opts(eps=1e-6, symmetric=1))
