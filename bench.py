@@ -20,6 +20,10 @@ whole when it predicts no compression.  Beside it: the mixed form (the same
 without the predictor) and the plain form (FP64 storage and FP64 MFMA,
 adaptive sampling, direct per-level launches).  Each form uses the launch
 shapes the autotuner cached for its workload, if any.
+
+A form name with the suffix "-sym" (e.g. --forms learned-sym,plain-sym,plain
+on a symmetric positive definite workload) runs that form in the symmetric
+variant: one-sided IDs and L D L^T segment factors (Section 4.4.2).
 """
 from __future__ import annotations
 
@@ -71,9 +75,10 @@ def log(*a):
 def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8, rho=0.5, tuning="cache"):
     import numpy as np
     import torch
-    prec = S.FP64 if form == "plain" else S.FP32
+    base, sym = form[:-4] if form.endswith("-sym") else form, form.endswith("-sym")
+    prec = S.FP64 if base == "plain" else S.FP32
     model = None
-    if form == "learned":
+    if base == "learned":
         from paper_2408_14193_amd import rank_model
         model = rank_model.load(device=dev)
     rp = torch.from_numpy(P.indptr).to(dev)
@@ -85,9 +90,9 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8,
 
     def step():
         t0 = time.perf_counter()
-        F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec, rank_model=model, rho=rho)
+        F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec, rank_model=model, rho=rho, symmetric=sym)
         t1 = time.perf_counter()
-        info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(graph and form != "plain"), restart=restart)
+        info, rr = F.solve_into(B, X, tol=tol, max_iter=50, graph=(graph and base != "plain"), restart=restart)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         return F, info, rr, t1 - t0, t2 - t1
@@ -95,7 +100,7 @@ def run_form(S, P, nd, dev, form, steps, warmup, profile, graph=True, restart=8,
     # launch shapes: the autotuner's cached choice for this workload (or,
     # with --tune, a fresh search before the warm-up), else the defaults
     from paper_2408_14193_amd import autotune
-    key = autotune.workload_key(P.dims, prec, form == "learned", P.nrhs, P.eps)
+    key = autotune.workload_key(P.dims, prec, base == "learned", P.nrhs, P.eps, symmetric=sym)
     if tuning == "tune":
         def one():
             t = time.perf_counter()
@@ -171,7 +176,7 @@ def measured_traffic(name, form):
     when there is none for this kernel and form or its sources changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % name)
-    if form == "plain" or not os.path.exists(path):
+    if form.startswith("plain") or form.endswith("-sym") or not os.path.exists(path):
         return None
     d = json.load(open(path))
     h = hashlib.sha256()
@@ -300,7 +305,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "storage": "f64" if head == "plain" else "f32",
+        "storage": "f64" if head.startswith("plain") else "f32",
         "data": "synthetic",
         "config": {"workload": "%s %s, N=%d, %d RHS, eps=%g, refinement to %g, %s form"
                                % (P.name, "x".join(map(str, P.dims)), P.n, P.nrhs, P.eps, P.tol, head),

@@ -146,6 +146,19 @@ typedef struct {
                             later calls with the same ones (batching form;
                             up to 4 graphs per handle, not while profiling);
                             0 (default): direct launches                  */
+  int32_t symmetric;     /* 1: symmetric form for a symmetric positive
+                            definite A (Section 4.4.2: A_{s,n} and A_{n,s}^T
+                            share one ID, L D L^T in place of LU): the ID
+                            samples the rows of A_{n,s} only (Y = [A_{N,s};
+                            G A_{F,s} / sqrt(h)]), the segment blocks are
+                            factored without interchanges as L D L^T and
+                            stored balanced as C^{-1} = D^{-1/2} L^{-1} and
+                            C^{-T} (C = L D^{1/2}), so every level's matrix
+                            stays symmetric and W~ = V~^T.  A that is not
+                            symmetric gives SPALU_EINVAL, a pivot that is
+                            not positive SPALU_ESINGULAR (the leaves keep
+                            their pivoted LU).  0 (default): the stacked ID
+                            and pivoted LU of any invertible A            */
 } spalu_factor_opts;
 
 typedef struct {

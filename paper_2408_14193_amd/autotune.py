@@ -41,10 +41,10 @@ def device_name():
     return getattr(p, "gcnArchName", "") or p.name
 
 
-def workload_key(dims, precision, learned, nrhs, eps, device=None):
-    return "%s | grid %s | %s | %s | nrhs %d | eps %g" % (
+def workload_key(dims, precision, learned, nrhs, eps, device=None, symmetric=False):
+    return "%s | grid %s | %s | %s | nrhs %d | eps %g%s" % (
         device or device_name(), "x".join(str(int(d)) for d in dims), "fp32" if precision == S.FP32 else "fp64",
-        "learned" if learned else "adaptive", int(nrhs), float(eps))
+        "learned" if learned else "adaptive", int(nrhs), float(eps), " | symmetric" if symmetric else "")
 
 
 def load_cache(path=CACHE):

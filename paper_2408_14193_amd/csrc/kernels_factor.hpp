@@ -118,6 +118,23 @@ __global__ void k_check_pattern(GridGeom g, int64_t n, const int64_t* rowptr, co
   }
 }
 
+// Symmetric form: every CSR entry (v, w) must have its mirror (w, v) with the
+// same value (the rows are short, so the mirror is found by a scan); flags
+// bit 2 otherwise.
+__global__ void k_check_symmetric(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
+                                  int* status) {
+  const int64_t v = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  for (int64_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+    const int w = colind[e];
+    if (w < 0 || w >= n) continue;  // reported by the pattern check
+    bool ok = false;
+    for (int64_t f = rowptr[w]; f < rowptr[w + 1]; ++f)
+      if (colind[f] == int(v)) ok = vals[f] == vals[e];
+    if (!ok) atomicOr(status, 4);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Leaf elimination (eq. (4.8)): A_II^{-1} by Gauss-Jordan elimination with
 // partial pivoting (in place; the row interchanges become column
@@ -499,6 +516,7 @@ struct IdParams {
   int level;
   int seg_base;           // index of this level's segments in h_init
   const int32_t* h_init;  // optional start samples (learned form)
+  int sym;                // symmetric form: one-sided coupling rows (A_{n,c} only)
 };
 
 // LU with partial pivoting of the row-major n x n A (in place) by one block,
@@ -507,15 +525,18 @@ struct IdParams {
 // column j is divided by its pivot in the next step, by all threads, while
 // wave 0 searches the next pivot.  Steps j < split search rows [j, split),
 // later steps rows [j, n); ties go to the smaller row.  piv[j] = row swapped
-// with row j.  Returns 1 if a pivot was zero (that step is skipped).
+// with row j.  Returns 1 if a pivot was zero (that step is skipped).  With
+// sym (symmetric form) no rows are interchanged: the LU of the symmetric
+// block is then L D L^T, U = D L^T, and a pivot that is not positive is
+// reported as well.
 template <int NT>
-__device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s_piv) {
+__device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s_piv, bool sym) {
   const int tid = threadIdx.x;
   int singular = 0;
   double dprev = 0.0;  // pivot of the previous step (0: nothing to scale)
   for (int j = 0; j < n; ++j) {
     if (tid < 64) {
-      const int hi = j < split ? split : n;
+      const int hi = sym ? j + 1 : (j < split ? split : n);
       double bv = -1.0;
       int bi = 1 << 30;
       for (int i = j + tid; i < hi; i += 64) {
@@ -542,6 +563,7 @@ __device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s
     __syncthreads();
     const double d = A[j * n + j];
     dprev = d;
+    if (sym && !(d > 0.0)) singular = 1;
     if (d == 0.0) {
       singular = 1;
       continue;  // uniform; column j stays unscaled
@@ -572,8 +594,22 @@ __device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s
 // of L and column n-1-s of U (disjoint triangles of X, one barrier per
 // step).  The diagonal of X holds 1 / U[i][i]; the unit diagonals are
 // implied.
+//
+// With sym (the L D L^T of the symmetric form, U = D L^T) the stored pair is
+// balanced by Delta = D^{1/2}: R = Delta^{-1} L^{-1} (lower, its strict part
+// stored, its diagonal 1 / Delta the same as that of the stored upper part)
+// and C = U^{-1} Delta = R^T, so the row scaling R and the column scaling C
+// are the Cholesky ones, C_ch^{-1} and C_ch^{-T} with C_ch = L Delta, and
+// every scaled coupling keeps the level's matrix symmetric.  Row operations
+// with the stored form then multiply row i's own entry by the stored
+// diagonal instead of taking a unit diagonal.
+__device__ inline double balance_entry(double v, int i, int c, double xii, double xcc) {
+  // xii, xcc: 1 / U_ii and 1 / U_cc; Delta_i = 1 / sqrt(xii)
+  return i > c ? v * sqrt(xii) : v / sqrt(xcc);
+}
+
 template <int NT, typename TO>
-__device__ inline void seg_block_inverse(const double* W, int n, double* X, TO* out) {
+__device__ inline void seg_block_inverse(const double* W, int n, double* X, TO* out, bool sym) {
   const int tid = threadIdx.x;
   for (int t = tid; t < n * n; t += NT) {
     const int i = t / n, c = t - i * n;
@@ -603,7 +639,8 @@ __device__ inline void seg_block_inverse(const double* W, int n, double* X, TO* 
   }
   for (int t = tid; t < n * n; t += NT) {
     const int i = t / n, c = t - i * n;
-    out[t] = TO(i > c ? X[t] : (i == c ? 1.0 : X[t]) * X[c * n + c]);
+    const double v = i > c ? X[t] : (i == c ? 1.0 : X[t]) * X[c * n + c];
+    out[t] = TO(sym ? balance_entry(v, i, c, X[i * n + i], X[c * n + c]) : v);
   }
   __syncthreads();
 }
@@ -616,7 +653,7 @@ template <typename T, int NT>
 __global__ __launch_bounds__(NT) void k_seg_lu(const DSeg* segs, int nseg, const DBlk* blks,
                                                int32_t* iarena, T* varena, double* scratch,
                                                DLevelDyn dyn, int* status, int need_lo, int need_hi,
-                                               int lds_doubles, int level) {
+                                               int lds_doubles, int level, int sym) {
   extern __shared__ double lds[];
   __shared__ int s_piv;
   const int c = blockIdx.x;
@@ -678,7 +715,7 @@ __global__ __launch_bounds__(NT) void k_seg_lu(const DSeg* segs, int nseg, const
   // would stall each step), copied out afterwards
   const bool pv_lds = inlds && need + (n + 1) / 2 <= lds_doubles;
   int* pv = pv_lds ? reinterpret_cast<int*>(lds + need) : piv;
-  if (seg_block_lu<NT>(W, n, sp ? nr : 0, pv, &s_piv)) flag_singular(status, level);
+  if (seg_block_lu<NT>(W, n, sp ? nr : 0, pv, &s_piv, sym != 0)) flag_singular(status, level);
   __syncthreads();
   // stored form of the interchanges: the composed row map (row i of P X is
   // row piv[i] of X), each entry traced back through the interchanges
@@ -696,7 +733,7 @@ __global__ __launch_bounds__(NT) void k_seg_lu(const DSeg* segs, int nseg, const
   // packed inverses: strictly lower part of L^{-1} (unit diagonal implied)
   // and upper part of U^{-1}, so every later application is a product
   T* LU = varena + S.lu_off;
-  seg_block_inverse<NT>(W, n, X, LU);
+  seg_block_inverse<NT>(W, n, X, LU, sym != 0);
   if (sp) {
     for (int p = tid; p < n; p += NT) tmp[p] = dofs[p < nr ? perm[k + p] : perm[p - nr]];
     __syncthreads();
@@ -716,7 +753,7 @@ __host__ __device__ inline int seglu_wave_lds_doubles(int nw) { return nw * nw +
 template <typename T, int CPL>
 __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, const DBlk* blks,
                                                     int32_t* iarena, T* varena, DLevelDyn dyn, int* status,
-                                                    int nmin, int nmax, int level) {
+                                                    int nmin, int nmax, int level, int sym) {
   extern __shared__ double lds[];
   const int c = blockIdx.x;
   if (c >= nseg) return;
@@ -792,7 +829,7 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
 #pragma unroll
   for (int u = 0; u < CPL; ++u) rm[u] = lane + 64 * u;
   for (int j = 0; j < n; ++j) {
-    const int hi = j < split ? split : n;
+    const int hi = sym ? j + 1 : (j < split ? split : n);  // symmetric form: no interchanges
     double bv = -1.0;
     int bi = 1 << 30;
 #pragma unroll
@@ -829,6 +866,7 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
     }
     wave_sync();
     const double d = W[j * n + j];
+    if (sym && !(d > 0.0)) singular = true;
     if (d == 0.0) {
       singular = true;
       continue;
@@ -929,7 +967,10 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
     wave_sync();
   }
   T* LU = varena + S.lu_off;
-  for (int t = lane; t < n * n; t += 64) LU[t] = T(W[t]);
+  for (int t = lane; t < n * n; t += 64) {
+    const int i = t / n, c = t - i * n;
+    LU[t] = T(sym ? balance_entry(W[t], i, c, W[i * n + i], W[c * n + c]) : W[t]);
+  }
   if (sp) {
     int nd[CPL];
 #pragma unroll
@@ -964,11 +1005,13 @@ __host__ __device__ inline bool blk_scale_mfma_fits(int kc, int kd, int lds_byte
 // Coupling scaling: A'_{cd} = L_ss,c^{-1} P_s,c A_cd[s_c, s_d] U_ss,d^{-1},
 // with the skeleton blocks of the packed inverses of c and d (the inverse of
 // a block triangular matrix has the inverse of its trailing diagonal block as
-// its trailing diagonal block).
+// its trailing diagonal block).  In the symmetric form (sym) the row
+// operator's diagonal is the stored diagonal (the balanced pair R, C of
+// seg_block_inverse) and P is the identity.
 template <typename T>
 __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_t* blk_list, int nlist,
                                                   const DSeg* segs, const int32_t* iarena, T* varena,
-                                                  DLevelDyn dyn, int wave_lds_doubles, int mfma_lds) {
+                                                  DLevelDyn dyn, int wave_lds_doubles, int mfma_lds, int sym) {
   extern __shared__ double lds[];
   const int bi = blockIdx.x;
   if (bi >= nlist) return;
@@ -1007,8 +1050,8 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
     __syncthreads();
     for (int t = tid; t < kc * kd; t += WG) {
       const int i = t / kd, j = t % kd;
-      double v = X[t];
       const T* lrow = Lc + size_t(nrc + i) * nc + nrc;
+      double v = sym ? double(lrow[i]) * X[t] : X[t];
       for (int u = 0; u < i; ++u) v += double(lrow[u]) * X[size_t(u) * kd + j];
       Yb[t] = v;
     }
@@ -1030,9 +1073,10 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
     }
     __syncthreads();
     for (int j = tid; j < kd; j += WG)
-      for (int i = kc - 1; i > 0; --i) {
-        double v = double(out[size_t(i) * kd + j]);
+      for (int i = kc - 1; i >= (sym ? 0 : 1); --i) {
         const T* lrow = Lc + size_t(nrc + i) * nc + nrc;
+        double v = double(out[size_t(i) * kd + j]);
+        if (sym) v *= double(lrow[i]);
         for (int u = 0; u < i; ++u) v += double(lrow[u]) * double(out[size_t(u) * kd + j]);
         out[size_t(i) * kd + j] = T(v);
       }
@@ -1056,7 +1100,7 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
 template <typename T>
 __global__ __launch_bounds__(WG) void k_blk_scale_mfma(const DBlk* blks, const int32_t* blk_list, int nlist,
                                                        const DSeg* segs, const int32_t* iarena, T* varena,
-                                                       DLevelDyn dyn, int wave_lds_doubles, int mfma_lds) {
+                                                       DLevelDyn dyn, int wave_lds_doubles, int mfma_lds, int sym) {
   extern __shared__ double lds[];
   const int bi = blockIdx.x;
   if (bi >= nlist) return;
@@ -1094,7 +1138,8 @@ __global__ __launch_bounds__(WG) void k_blk_scale_mfma(const DBlk* blks, const i
       },
       [&](int t, T v) { X[t] = double(v); });
   __syncthreads();
-  // Y = L^{-1} X (unit lower): row tile i0 needs columns u <= i of L^{-1}
+  // Y = L^{-1} X (unit lower; the stored diagonal in the symmetric form):
+  // row tile i0 needs columns u <= i of L^{-1}
   const int nti = (kc + 15) >> 4, ncg = (kd + 63) >> 6;
   for (int unit = w; unit < nti * ncg; unit += NWAVE) {
     const int ti = unit / ncg, cg = unit - ti * ncg, i0 = 16 * ti, j0 = 64 * cg;
@@ -1103,7 +1148,7 @@ __global__ __launch_bounds__(WG) void k_blk_scale_mfma(const DBlk* blks, const i
     wave_tile_mfma(
         [&](int i, int u) {
           const double l = double(Lc[size_t(nrc + (i < kc ? i : kc - 1)) * nc + nrc + (u < kc ? u : kc - 1)]);
-          return i < kc && u < i ? l : (i < kc && u == i ? 1.0 : 0.0);
+          return i < kc && u < i ? l : (i < kc && u == i ? (sym ? l : 1.0) : 0.0);
         },
         [&](int u, int col) {
           const int j = j0 + col;
@@ -1157,7 +1202,7 @@ __global__ __launch_bounds__(WG) void k_blk_scale_mfma(const DBlk* blks, const i
 template <typename T>
 __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const int32_t* blk_list, int nlist,
                                                        const DSeg* segs, const int32_t* iarena, T* varena,
-                                                       DLevelDyn dyn, int lds_doubles) {
+                                                       DLevelDyn dyn, int lds_doubles, int sym) {
   extern __shared__ double lds[];
   const int bi = blockIdx.x;
   if (bi >= nlist) return;
@@ -1178,7 +1223,7 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
   const T* Lc = varena + segs[c].lu_off;
   const T* Ud = varena + segs[d].lu_off;
   double* X = lds;                            // kc x kd
-  double* Lb = X + kc * kd;                   // kc x kc (strict lower part used)
+  double* Lb = X + kc * kd;                   // kc x kc (strict lower part used; diagonal too if sym)
   double* Ub = Lb + kc * kc;                  // kd x kd (upper part used)
   int* rs = reinterpret_cast<int*>(Ub + kd * kd);  // kc: block row of row i of P_s X
   int* cs = rs + kc;                               // kd: block column of column j
@@ -1201,7 +1246,7 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
       },
       [&](int t, T v) {
         const int i = t / kc, u = t - i * kc;
-        Lb[t] = u < i ? double(v) : 0.0;
+        Lb[t] = u < i || (sym && u == i) ? double(v) : 0.0;
       });
   load_batched<8>(
       kd * kd, lane, 64,
@@ -1224,9 +1269,10 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
   wave_sync();
   if (lane < kd) {
     const int j = lane;
-    // Y = L^{-1} X (unit lower), rows descending so X[u] (u < i) is still X
-    for (int i = kc - 1; i > 0; --i) {
-      double v = X[i * kd + j];
+    // Y = L^{-1} X (unit lower, or the stored diagonal in the symmetric
+    // form), rows descending so X[u] (u < i) is still X
+    for (int i = kc - 1; i >= 0; --i) {
+      double v = sym ? Lb[i * kc + i] * X[i * kd + j] : X[i * kd + j];
       for (int u = 0; u < i; ++u) v += Lb[i * kc + u] * X[u * kd + j];
       X[i * kd + j] = v;
     }

@@ -222,17 +222,19 @@ __device__ inline double idc_rowaxpy(YE* Y, int n, int i0, int m, int col, int q
 // rows[r] (block offset, column stride, vertex and half) for r < R, and
 // order[]: the near rows from the front, the far rows from the back (far row
 // f is order[R - 1 - f]); s_cnt receives (|N|, |F|).  The near field is the
-// neighbour DOFs within Chebyshev distance S.thr of the segment's box.
+// neighbour DOFs within Chebyshev distance S.thr of the segment's box.  hm
+// is the number of halves per neighbour: 2 (rows of A_{d,c} and of
+// A_{c,d}^T), or 1 in the symmetric form (rows of A_{d,c} only).
 __device__ inline void idc_row_table(const DSeg& S, const DSeg* segs, const DNbr* nbrs, const DBlk* blks,
                                      GridGeom g, const int32_t* iarena, const DLevelDyn& dyn, int n, int R,
-                                     IdRow* rows, int* order, int* s_cnt) {
+                                     int hm, IdRow* rows, int* order, int* s_cnt) {
   const int lane = threadIdx.x & 63;
   int nN = 0, nF = 0, r0 = 0;
   const int nnb = S.nbr_end - S.nbr_begin;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   if (nnb <= 64) {
     // neighbour e = lane: its size, DOF list and block offsets, loaded
-    // together; its rows start at rs (exclusive prefix sum of 2 n_d).
+    // together; its rows start at rs (exclusive prefix sum of hm n_d).
     // Row r of the table (neighbour, half, index) is then found by each
     // lane from these, so the whole table costs one more trip to memory
     int nd_l = 0;
@@ -244,13 +246,13 @@ __device__ inline void idc_row_table(const DSeg& S, const DSeg* segs, const DNbr
       o0_l = blks[nb.blk_dc].off;
       o1_l = blks[nb.blk_cd].off;
     }
-    int rs = 2 * nd_l;
+    int rs = hm * nd_l;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int t = __shfl_up(rs, o, 64);
       if (lane >= o) rs += t;
     }
-    rs -= 2 * nd_l;
+    rs -= hm * nd_l;
     for (int rb = 0; rb < R; rb += 64) {
       const int r = rb + lane;
       const bool valid = r < R;
@@ -295,7 +297,7 @@ __device__ inline void idc_row_table(const DSeg& S, const DSeg* segs, const DNbr
       const int nd = dyn.n[nb.d];
       const int32_t* dd = iarena + segs[nb.d].ioff;
       const int64_t off0 = blks[nb.blk_dc].off, off1 = blks[nb.blk_cd].off;
-      for (int half = 0; half < 2; ++half) {
+      for (int half = 0; half < hm; ++half) {
         for (int i0 = 0; i0 < nd; i0 += 64) {
           const int i = i0 + lane;
           const bool valid = i < nd;
@@ -330,7 +332,7 @@ __device__ inline void idc_row_table(const DSeg& S, const DSeg* segs, const DNbr
           nF += __popcll(mf);
         }
       }
-      r0 += 2 * nd;
+      r0 += hm * nd;
     }
   }
   if (lane == 0) {
@@ -355,7 +357,8 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   const DSeg S = segs[c];
   const int n = dyn.n[c];
   int R = 0;
-  for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += 2 * dyn.n[nbrs[e].d];
+  const int hm = prm.sym ? 1 : 2;  // halves of the coupling rows per neighbour
+  for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += hm * dyn.n[nbrs[e].d];
   const int tier = id_tier(S, n, R, prm, c, tiers);
   int32_t* dofs = iarena + S.ioff;
   int32_t* perm_out = dofs + S.cap;
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
   }
 
   // ---- 1. row table: near rows listed from the front, far rows from the back ----
-  if (w == 0) idc_row_table(S, segs, nbrs, blks, g, iarena, dyn, n, R, rows, order, s_cnt);
+  if (w == 0) idc_row_table(S, segs, nbrs, blks, g, iarena, dyn, n, R, hm, rows, order, s_cnt);
   __syncthreads();
   const int nN = s_cnt[0], nF = s_cnt[1];
 
@@ -907,7 +910,8 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
   const DSeg S = segs[c];
   const int n = dyn.n[c];
   int R = 0;
-  for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += 2 * dyn.n[nbrs[e].d];
+  const int hm = prm.sym ? 1 : 2;  // halves of the coupling rows per neighbour
+  for (int e = S.nbr_begin; e < S.nbr_end; ++e) R += hm * dyn.n[nbrs[e].d];
   if (id_tier(S, n, R, prm, c, tiers) != 5) return;
   int32_t* dofs = iarena + S.ioff;
   int32_t* perm = dofs + S.cap;
@@ -923,12 +927,13 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
     s_cnt[1] = 0;
   }
   __syncthreads();
-  // 1. stack [A_{n,c}; A_{c,n}^T] row by row, split near / far
+  // 1. stack [A_{n,c}; A_{c,n}^T] (A_{n,c} alone in the symmetric form) row
+  // by row, split near / far
   for (int e = S.nbr_begin; e < S.nbr_end; ++e) {
     const DNbr nb = nbrs[e];
     const int nd = dyn.n[nb.d];
     const int32_t* dd = iarena + segs[nb.d].ioff;
-    for (int half = 0; half < 2; ++half) {
+    for (int half = 0; half < hm; ++half) {
       const T* blk = varena + blks[half == 0 ? nb.blk_dc : nb.blk_cd].off;
       for (int base = 0; base < nd; base += WG) {
         const int i = base + tid;

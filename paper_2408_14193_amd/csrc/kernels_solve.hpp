@@ -326,9 +326,12 @@ __global__ void k_sep_from_leaves(int64_t nsep, const int32_t* sepv, const int8_
 // type, when they fit SEG_SOLVE_LDS_BYTES beside two right-hand-side columns.
 constexpr int SEG_SOLVE_LDS_BYTES = 65536;
 
+// In the symmetric form (sym) the forward row operator takes the stored
+// diagonal in place of the unit one (the balanced R = Delta^{-1} L^{-1} of
+// the segment factorization; the interchanges are the identity).
 template <typename T, bool BACKWARD>
 __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, const int32_t* iarena,
-                                                  const T* varena, DLevelDyn dyn, T* W, int nrhs) {
+                                                  const T* varena, DLevelDyn dyn, T* W, int nrhs, int sym) {
   extern __shared__ double lds[];
   const int c = blockIdx.x;
   if (c >= nseg) return;
@@ -391,9 +394,11 @@ __global__ __launch_bounds__(WG) void k_seg_solve(const DSeg* segs, int nseg, co
         double v = X[t];
         if (stage) {
           const T* row = sI + i * n;
+          if (sym) v *= double(row[i]);
           for (int u = 0; u < i; ++u) v += row[u] * X[size_t(u) * nc + j];
         } else {
           const T* row = Inv + size_t(i) * n;
+          if (sym) v *= double(row[i]);
           for (int u = 0; u < i; ++u) v += double(row[u]) * X[size_t(u) * nc + j];
         }
         W[size_t(dofs[i]) * nrhs + j0 + j] = T(v);
@@ -647,12 +652,15 @@ constexpr int SW_LD = GG_LDX;  // FP64 LDS row of 64 right-hand sides
 // tiles (tile t on wave t % NW), its operator entries (T, the packed
 // inverses) read from global memory.  One wave (NW = 1) serves the fine
 // levels' many small segments, four waves the coarse levels' larger ones.
+// In the symmetric form (sym) the forward operator's diagonal is the stored
+// one, as in k_seg_solve.
 __host__ __device__ inline int seg_solve_mfma_lds_bytes(int rows) { return 8 * rows * SW_LD; }
 constexpr int SEG_MFMA_BLOCK_N = 128;  // largest segment of the four-wave shape (4 waves x 2 tiles)
 
 template <typename T, bool BACKWARD, int NW, int TPW>
 __global__ __launch_bounds__(64 * NW) void k_seg_solve_mfma(const DSeg* segs, int nseg, const int32_t* iarena,
-                                                            const T* varena, DLevelDyn dyn, T* W, int nrhs) {
+                                                            const T* varena, DLevelDyn dyn, T* W, int nrhs,
+                                                            int sym) {
   extern __shared__ double lds[];
   constexpr int NMAX = 16 * NW * TPW;
   const int c = blockIdx.x;
@@ -727,7 +735,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_solve_mfma(const DSeg* segs, in
         wave_tile_mfma(
             [&](int i, int u) {
               const double l = double(Inv[size_t(i < n ? i : n - 1) * n + (u < n ? u : n - 1)]);
-              return i < n && u < i ? l : (i < n && u == i ? 1.0 : 0.0);
+              return i < n && u < i ? l : (i < n && u == i ? (sym ? l : 1.0) : 0.0);
             },
             [&](int u, int cc) { return X[piv_of(u < n ? u : n - 1) * SW_LD + cc]; }, i0, 0,
             i0 + 16 < n ? i0 + 16 : n, nct, acc);

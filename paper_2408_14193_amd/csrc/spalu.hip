@@ -177,6 +177,7 @@ struct spalu_factor_s {
   const Layout* lay = nullptr;
   std::shared_ptr<const Layout> lay_sp;
   int prec = 0;
+  int sym = 0;  // symmetric form (one-sided IDs, balanced L D L^T segment factors)
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   int64_t n = 0;
@@ -641,6 +642,7 @@ struct TimedLaunch {
   int64_t nrows;
   std::shared_ptr<const Layout> lay;
   std::shared_ptr<const std::vector<std::vector<int32_t>>> dyn;
+  int sym;  // symmetric form (one-sided ID rows)
 };
 
 struct Profiler {
@@ -716,7 +718,7 @@ void prof_end(int idx, hipStream_t st) {
 using DynHost = std::vector<std::vector<int32_t>>;
 
 void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, int nrhs, double& by,
-             double& fl) {
+             double& fl, int sym) {
   const double vs = double(Y.vsize);
   const double nnzrow = 2.0 * Y.dim + 1.0;
   by = fl = 0.0;
@@ -750,7 +752,7 @@ void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, 
         if (dynv(l, 4, int(c)) <= 0) continue;
         const double n = dynv(l, 0, int(c)), k = dynv(l, 1, int(c)), h = dynv(l, 3, int(c));
         double R = 0.0;
-        for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) R += 2.0 * dynv(l, 0, T.nbrs[e].d);
+        for (int e = T.segs[c].nbr_begin; e < T.segs[c].nbr_end; ++e) R += (sym ? 1.0 : 2.0) * dynv(l, 0, T.nbrs[e].d);
         const int tier = id_tier_of_size(int(n), int(R), T.tiers);
         if ((tier == 6 ? 4 : tier) != 1 + (kid - K_ID)) continue;
         // sketch G B_F of the far rows (none once h reaches them: exact rows),
@@ -877,13 +879,13 @@ void account(const Layout& Y, const DynHost& dh, int64_t nrows, int kid, int l, 
     case K_APPLY: {
       double a, b;
       for (int kid2 : {int(K_LSOLVE_F), int(K_SEPLEAF), int(K_LSOLVE_B)}) {
-        account(Y, dh, nrows, kid2, 0, nrhs, a, b);
+        account(Y, dh, nrows, kid2, 0, nrhs, a, b, sym);
         by += a;
         fl += b;
       }
       for (int l2 = 1; l2 <= Y.L; ++l2)
         for (int kid2 : {int(K_SSOLVE_F), int(K_SEPFWD), int(K_SEPBWD), int(K_SSOLVE_B)}) {
-          account(Y, dh, nrows, kid2, l2, nrhs, a, b);
+          account(Y, dh, nrows, kid2, l2, nrhs, a, b, sym);
           by += a;
           fl += b;
         }
@@ -902,7 +904,8 @@ void prof_flush(const spalu_factor_t* F, int nrhs) {
     float ms = 0.f;
     (void)hipEventSynchronize(p.b);
     if (hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) ms = 0.f;
-    g_prof.done.push_back(TimedLaunch{p.kid, p.level, nrhs, p.acct, double(ms), F->n, F->lay_sp, F->dyn_host});
+    g_prof.done.push_back(
+        TimedLaunch{p.kid, p.level, nrhs, p.acct, double(ms), F->n, F->lay_sp, F->dyn_host, F->sym});
     g_prof.spare.push_back(p.a);
     g_prof.spare.push_back(p.b);
   }
@@ -913,7 +916,7 @@ void prof_account_pending() {
   for (auto& t : g_prof.done) {
     double by, fl;
     by = fl = 0.0;
-    if (t.acct) account(*t.lay, *t.dyn, t.nrows, t.kid, t.level, t.nrhs, by, fl);
+    if (t.acct) account(*t.lay, *t.dyn, t.nrows, t.kid, t.level, t.nrhs, by, fl, t.sym);
     if (g_prof_verbose)
       std::fprintf(stderr, "spalu-prof %-16s level %2d  %9.4f ms  %12.0f B  %12.0f flop\n", kNames[t.kid], t.level,
                    t.ms, by, fl);
@@ -992,7 +995,7 @@ void factor_work(const spalu_factor_t* F, double& fl, double& by) {
   fl = by = 0.0;
   double a, b;
   for (int kid : {int(K_LEAF), int(K_ASM)}) {
-    account(Y, dh, F->n, kid, Y.L, 0, a, b);
+    account(Y, dh, F->n, kid, Y.L, 0, a, b, F->sym);
     by += a;
     fl += b;
   }
@@ -1000,7 +1003,7 @@ void factor_work(const spalu_factor_t* F, double& fl, double& by) {
     for (int kid : {int(K_ID), int(K_ID_B), int(K_ID_B2), int(K_ID_C), int(K_ID_BLK), int(K_LU), int(K_SCALE),
                     int(K_MSIZE), int(K_MELIM)}) {
       if (l == 1 && (kid == K_MSIZE || kid == K_MELIM)) continue;
-      account(Y, dh, F->n, kid, l, 0, a, b);
+      account(Y, dh, F->n, kid, l, 0, a, b, F->sym);
       by += a;
       fl += b;
     }
@@ -1019,6 +1022,9 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
   k_zero_i32<<<1, 64, 0, st>>>(status, 16);
   HIPCHK(hipGetLastError());
   LAUNCH(K_CHECK, 0, k_check_pattern<<<nblocks(F->n), WG, 0, st>>>(F->g, F->n, F->rowptr, F->colind, status));
+  if (F->sym)
+    LAUNCH_MORE(K_CHECK, 0, k_check_symmetric<<<nblocks(F->n), WG, 0, st>>>(F->n, F->rowptr, F->colind, F->vals,
+                                                                          status));
   {
     const LevelTabs& TL = Y.lv[L];
     DLevelDyn dL = dyn_of(ws, Y, L);
@@ -1096,6 +1102,7 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
     prm.level = l;
     prm.seg_base = int(Y.seg_base[l]);
     prm.h_init = o.h_init;
+    prm.sym = o.symmetric;
     if (predict) {
       // the finest level here; the others were done on aux[0] during the
       // level below
@@ -1158,12 +1165,13 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
       // with up to 152 KB of LDS (scratch beyond that)
       const int nw = std::min(SEGLU_WAVE_MAX_N, T_.max_cap);
       LAUNCH(K_LU, l, k_seg_lu_wave<T, 1><<<unsigned(ns), 64, size_t(seglu_wave_lds_doubles(nw)) * 8, st>>>(
-          segs, ns, blks, iar, var, d, status, 0, nw, l));
+          segs, ns, blks, iar, var, d, status, 0, nw, l, o.symmetric));
       if (T_.max_cap > SEGLU_WAVE_MAX_N) {
         const int64_t cap = T_.max_cap;
         const int big = int(std::min<int64_t>(2 * cap * cap + cap, int64_t(SEGLU_MAX_BYTES / 8)));
         LAUNCH_MORE(K_LU, l, k_seg_lu<T, SEGLU_BLOCK_NT><<<unsigned(ns), SEGLU_BLOCK_NT, size_t(big) * 8, st>>>(
-            segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, INT32_MAX, big, l));
+            segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, INT32_MAX, big, l,
+            o.symmetric));
       }
     }
     if (l > 1) {
@@ -1188,15 +1196,15 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
       // threads otherwise
       const unsigned nsc = unsigned(T_.scale_list.size());
       LAUNCH(K_SCALE, l, k_blk_scale_wave<T><<<nsc, 64, size_t(T_.scale_wave_lds) * 8, st>>>(
-          blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds));
+          blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds, o.symmetric));
       if (T_.scale_block)
         LAUNCH_MORE(K_SCALE, l, k_blk_scale_mfma<T><<<nsc, WG, size_t(T_.scale_mfma_lds), st>>>(
             blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds,
-            T_.scale_mfma_lds));
+            T_.scale_mfma_lds, o.symmetric));
       if (T_.scale_block_old)
         LAUNCH_MORE(K_SCALE, l, k_blk_scale<T><<<nsc, WG, LDS_BYTES, st>>>(
             blks, tab<int32_t>(ws, T_.o_scale), int(nsc), segs, iar, var, d, T_.scale_wave_lds,
-            T_.scale_mfma_lds));
+            T_.scale_mfma_lds, o.symmetric));
     }
     if (l > 1) {
       const LevelTabs& U = Y.lv[l - 1];
@@ -1262,7 +1270,7 @@ std::vector<uint64_t> factor_graph_key(const spalu_factor_t* F, const spalu_fact
   return {u(F->ws), u(F->rowptr), u(F->colind), u(F->vals), uint64_t(F->n), u(F->lay), uint64_t(o.precision),
           d(o.eps), uint64_t(o.seed), d(o.rho), uint64_t(uint32_t(o.h0)), uint64_t(uint32_t(o.probes)), d(o.tau),
           u(o.h_init), u(o.rank_model), u(o.features_out), d(o.rank_margin), uint64_t(uint32_t(o.rank_pad)),
-          d(o.rank_skip), uint64_t(g_tuning_gen)};
+          d(o.rank_skip), uint64_t(uint32_t(o.symmetric)), uint64_t(g_tuning_gen)};
 }
 
 // A factorization: its launches issued directly on the factor's stream,
@@ -1388,6 +1396,7 @@ template <typename T>
 int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStream_t st) {
   const Layout& Y = *F->lay;
   const Plan& P = F->nd->plan;
+  const int sym = F->sym;
   char* ws = F->ws;
   const int32_t* iar = reinterpret_cast<const int32_t*>(ws + Y.o_iarena);
   const T* var = reinterpret_cast<const T*>(ws + Y.o_varena);
@@ -1415,9 +1424,9 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
   {                                                                                                            \
     const size_t lb = size_t(seg_solve_mfma_lds_bytes(16 * RT));                                               \
     if (bwd)                                                                                                   \
-      LAUNCH(K_SSOLVE_B, l, k_seg_solve_mfma<T, true, 1, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs)); \
+      LAUNCH(K_SSOLVE_B, l, k_seg_solve_mfma<T, true, 1, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs, sym)); \
     else                                                                                                       \
-      LAUNCH(K_SSOLVE_F, l, k_seg_solve_mfma<T, false, 1, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs)); \
+      LAUNCH(K_SSOLVE_F, l, k_seg_solve_mfma<T, false, 1, RT><<<unsigned(ns), 64, lb, st>>>(sg, ns, iar, var, d, W, nrhs, sym)); \
   }
     if (P <= 16) SPALU_SSG(1) else if (P == 32) SPALU_SSG(2) else SPALU_SSG(4)
 #undef SPALU_SSG
@@ -1454,9 +1463,9 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
       const DSeg* sg = tab<DSeg>(ws, T_.o_segs);
       if (F->solve_nmax[l] <= SEG_MFMA_BLOCK_N)
         LAUNCH(K_SSOLVE_F, l, k_seg_solve_mfma<T, false, 4, 2><<<unsigned(ns), WG, seg_mfma_block_lds(F, l), st>>>(
-                                  sg, ns, iar, var, d, W, nrhs));
+                                  sg, ns, iar, var, d, W, nrhs, sym));
       else
-        LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
+        LAUNCH(K_SSOLVE_F, l, k_seg_solve<T, false><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs, sym));
       const dim3 gsep(unsigned(ns), unsigned((F->solve_kmax[l] + GG_ROWS - 1) / GG_ROWS));
       LAUNCH(K_SEPFWD, l, k_sep_fwd<T><<<gsep, WG, 0, st>>>(sg, ns, tab<DNbr>(ws, T_.o_nbrs),
                                                                    tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
@@ -1477,9 +1486,9 @@ int apply_inverse(const spalu_factor_t* F, T* B0, T* W, T* Z, int nrhs, hipStrea
                                                                    tab<DBlk>(ws, T_.o_blks), iar, var, d, W, nrhs));
       if (F->solve_nmax[l] <= SEG_MFMA_BLOCK_N)
         LAUNCH(K_SSOLVE_B, l, k_seg_solve_mfma<T, true, 4, 2><<<unsigned(ns), WG, seg_mfma_block_lds(F, l), st>>>(
-                                  sg, ns, iar, var, d, W, nrhs));
+                                  sg, ns, iar, var, d, W, nrhs, sym));
       else
-        LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs));
+        LAUNCH(K_SSOLVE_B, l, k_seg_solve<T, true><<<unsigned(ns), WG, size_t(SEG_SOLVE_LDS_BYTES), st>>>(sg, ns, iar, var, d, W, nrhs, sym));
     }
   }
   if (wave_leaf && Y.leaf_wc != 0) {
@@ -1864,6 +1873,7 @@ void spalu_factor_opts_default(spalu_factor_opts* o) {
   o->rank_pad = 5;
   o->rank_skip = 0.5f;
   o->graph = 0;
+  o->symmetric = 0;
 }
 
 void spalu_tuning_default(spalu_tuning* t) {
@@ -1941,7 +1951,8 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   if (opts) o = *opts;
   if (o.precision != SPALU_FP64 && o.precision != SPALU_FP32) return fail(SPALU_EINVAL, "bad precision");
   if (!(o.eps >= 0.0) || !(o.rho >= 0.0) || o.h0 < 1 || o.probes < 1 || o.probes > 8 || !(o.tau > 0.0) ||
-      !(o.rank_margin > 0.0f) || o.rank_pad < 1 || !(o.rank_skip >= 0.0f) || (o.graph != 0 && o.graph != 1))
+      !(o.rank_margin > 0.0f) || o.rank_pad < 1 || !(o.rank_skip >= 0.0f) || (o.graph != 0 && o.graph != 1) ||
+      (o.symmetric != 0 && o.symmetric != 1))
     return fail(SPALU_EINVAL, "bad factor options");
   const Layout* Y;
   try {
@@ -1960,6 +1971,7 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   F->lay = Y;
   F->lay_sp = layout_ptr(nd, o.precision);
   F->prec = o.precision;
+  F->sym = o.symmetric;
   F->ws = static_cast<char*>(workspace);
   F->stream = static_cast<hipStream_t>(stream);
   F->n = n;
@@ -2008,6 +2020,7 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   if (rc) return rc;
   const int status = stat[0];
   if (status & 2) return fail(SPALU_EUNSUPPORTED, "matrix pattern is not inside the grid stencil");
+  if (status & 4) return fail(SPALU_EINVAL, "symmetric form: the matrix is not symmetric");
   // statistics
   if (info) {
     std::memset(info, 0, sizeof(*info));
@@ -2045,6 +2058,9 @@ int spalu_factor(const spalu_nd_t* nd, int64_t n, const int64_t* rowptr, const i
   }
   if (status & 1) {
     if (info) info->singular_level = stat[1];
+    if (o.symmetric)
+      return fail(SPALU_ESINGULAR, "symmetric form: a pivot that is not positive (matrix not positive definite) "
+                                   "in a diagonal block of level " + std::to_string(stat[1]));
     return fail(SPALU_ESINGULAR, "zero pivot in a diagonal block of level " + std::to_string(stat[1]));
   }
   *out = F.release();

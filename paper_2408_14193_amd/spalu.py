@@ -47,7 +47,7 @@ class FactorOpts(C.Structure):
                 ("rho", C.c_double), ("h0", C.c_int32), ("probes", C.c_int32),
                 ("tau", C.c_double), ("h_init", C.c_void_p), ("rank_model", C.c_void_p),
                 ("features_out", C.c_void_p), ("rank_margin", C.c_float), ("rank_pad", C.c_int32),
-                ("rank_skip", C.c_float), ("graph", C.c_int32)]
+                ("rank_skip", C.c_float), ("graph", C.c_int32), ("symmetric", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -210,7 +210,7 @@ class ND:
 
 def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, tau=1.0,
                 h_init=None, rank_model=None, features_out=None, rank_margin=1.0, rank_pad=5,
-                rank_skip=0.5, graph=False):
+                rank_skip=0.5, graph=False, symmetric=False):
     o = FactorOpts()
     _lib.spalu_factor_opts_default(C.byref(o))
     o.eps, o.precision, o.seed, o.rho, o.h0, o.probes, o.tau = (
@@ -220,6 +220,7 @@ def factor_opts(eps=1e-6, precision=FP64, seed=1234, rho=0.5, h0=8, probes=5, ta
     o.features_out = None if features_out is None else int(features_out.data_ptr())
     o.rank_margin, o.rank_pad, o.rank_skip = float(rank_margin), int(rank_pad), float(rank_skip)
     o.graph = 1 if graph else 0
+    o.symmetric = 1 if symmetric else 0
     return o
 
 
@@ -258,14 +259,16 @@ def factor_workspace_bytes(nd, opts):
 class Factor:
     """spaLU factorization of a CSR matrix held in device memory (torch).
     graph: replay the level sweep from a HIP graph captured on the first
-    factorization with these pointers and options.  workspace: a uint8
+    factorization with these pointers and options.  symmetric: the
+    symmetric form for a symmetric positive definite matrix (one-sided IDs,
+    L D L^T segment factors).  workspace: a uint8
     device tensor to factor into (reused across factorizations, e.g. of a
     sequence of matrices with one pattern; the factor it held before is
     overwritten), else a new one."""
 
     def __init__(self, nd, rowptr, colind, vals, eps=1e-6, precision=FP64, seed=1234, rho=0.5,
                  h0=8, probes=5, tau=1.0, h_init=None, rank_model=None, features_out=None,
-                 stream=None, rank_skip=0.5, graph=False, workspace=None):
+                 stream=None, rank_skip=0.5, graph=False, workspace=None, symmetric=False):
         import torch
         assert rowptr.is_cuda and rowptr.dtype == torch.int64
         assert colind.is_cuda and colind.dtype == torch.int32
@@ -281,7 +284,7 @@ class Factor:
             assert features_out.is_cuda and features_out.dtype == torch.float32
             assert features_out.numel() >= nd.nsegments * 12
         self.opts = factor_opts(eps, precision, seed, rho, h0, probes, tau, h_init, rank_model,
-                                features_out, rank_skip=rank_skip, graph=graph)
+                                features_out, rank_skip=rank_skip, graph=graph, symmetric=symmetric)
         nbytes = factor_workspace_bytes(nd, self.opts)
         if workspace is None:
             workspace = torch.empty(nbytes, dtype=torch.uint8, device=rowptr.device)

@@ -76,6 +76,7 @@ int main(int argc, char** argv) {
   o.precision = prec == 32 ? SPALU_FP32 : SPALU_FP64;
   if (model) o.rank_model = to_guarded(pm);
   if (const char* h0 = std::getenv("EMU_H0")) o.h0 = std::atoi(h0);
+  if (const char* sy = std::getenv("EMU_SYM")) o.symmetric = std::atoi(sy);
   if (const char* tu = std::getenv("EMU_TUNING")) {
     // nine comma-separated spalu_tuning fields
     spalu_tuning t;

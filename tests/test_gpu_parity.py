@@ -75,6 +75,8 @@ def oracle_stable_levels(P, nd, ora, eps, want_factor=False, **okw):
     oracle factorization of the perturbed matrix."""
     A2 = P.scipy().copy()
     A2.data = A2.data * (1.0 + 1e-15 * np.random.default_rng(0).standard_normal(A2.nnz))
+    if okw.get("symmetric"):
+        A2 = ((A2 + A2.T) * 0.5).tocsr()     # the symmetric form needs a symmetric perturbation
     OF2 = O.factor(nd_order(P.dims), A2, O.Opts(eps=eps, seed=1234, **okw))
     p = _oracle_ranks(OF2, nd)
     base = nd.seg_base()

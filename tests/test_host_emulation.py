@@ -4,7 +4,7 @@ and every device buffer sits between inaccessible guard regions, so an
 out-of-bounds access by any kernel fails the test instead of faulting a GPU.
 The cases cover the paths the GPU tests take: exact elimination (eps = 0),
 sampled IDs with forced resampling, FP32 storage, the global-memory leaf
-path of 3D leaves, and flexible GMRES refinement."""
+path of 3D leaves, flexible GMRES refinement, and the symmetric form."""
 import os
 import re
 import subprocess
@@ -41,8 +41,10 @@ def _write(P, d, params=None):
     (params if params is not None else np.zeros(1, np.float32)).tofile(os.path.join(d, "params.bin"))
 
 
-def _run(exe, d, prec, model, eps, nrhs, tol, restart, h0=None, tuning=None, max_rank=None):
+def _run(exe, d, prec, model, eps, nrhs, tol, restart, h0=None, tuning=None, max_rank=None, sym=False):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1")
+    if sym:
+        env["EMU_SYM"] = "1"
     if h0 is not None:
         env["EMU_H0"] = str(h0)
     if tuning is not None:
@@ -155,3 +157,30 @@ def test_block_separator_solve_many_rhs(exe, tmp_path):
     # classical step gains about as much
     assert first <= 1e-2 and it <= 6, (first, it)
     assert final <= 1e-10
+
+
+def test_symmetric_form_exact_elimination(exe, tmp_path):
+    """Symmetric form with eps = 0: the balanced L D L^T of every segment
+    and the one-sided scaling kernels give an exact solve."""
+    P = make_config(1, side=63, nrhs=1)
+    _write(P, str(tmp_path))
+    it, first, final = _run(exe, str(tmp_path), 64, 0, 0.0, 2, 0.0, 0, sym=True)
+    assert first <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_symmetric_form_wide_tiers(exe, tmp_path, prec):
+    """Symmetric form at 127 x 127 (GRF diffusion): one-sided row tables in
+    every ID tier, the block scaling kernels on the coarse levels, and
+    refinement to 1e-10."""
+    P = make_config(1, side=127, nrhs=1)
+    _write(P, str(tmp_path))
+    it, first, final = _run(exe, str(tmp_path), prec, 0, P.eps, 2, 1e-10, 8, sym=True)
+    assert final <= 1e-10
+
+
+def test_symmetric_form_3d(exe, tmp_path):
+    P = make_config(3, side=15, nrhs=1)
+    _write(P, str(tmp_path))
+    it, first, final = _run(exe, str(tmp_path), 64, 0, P.eps, 2, 1e-10, 0, sym=True)
+    assert first <= 10 * P.eps and final <= 1e-10
