@@ -804,23 +804,33 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
 // CPQR of Y (m x n, column-major, ld) with fresh column norms each step and
 // the tie rule of the oracle; returns k and writes |R_11| to *r11.  perm[]
 // (original column index per position) is permuted alongside.
+//
+// Each step makes one pass over the trailing columns: a wave takes a column,
+// forms its Householder dot, updates it and sums the squares of the updated
+// entries below the pivot row, which are the fresh norms the next step
+// pivots on (recomputed from the entries, not downdated).  When the rows
+// below the pivot fit CPQR_RB entries per lane, the Householder vector stays
+// in registers for the whole step and each column is read once.
+constexpr int CPQR_RB = 32;
+
 __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps, double* nrm,
                           double* s_scal, int* s_int, double* r11_out) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int kk = m < n ? m : n;
   int k = kk;
   double r11 = 0.0;
-  for (int j = 0; j < kk; ++j) {
-    for (int col = j + wv; col < n; col += NWAVE) {
-      double s = 0.0;
-      for (int i = j + lane; i < m; i += 64) {
-        const double y = Y[size_t(col) * ld + i];
-        s += y * y;
-      }
-      s = wave_sum(s);
-      if (lane == 0) nrm[col] = sqrt(s);
+  // norms of the first step (rows 0..m-1)
+  for (int col = wv; col < n; col += NWAVE) {
+    double s = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      const double y = Y[size_t(col) * ld + i];
+      s += y * y;
     }
-    __syncthreads();
+    s = wave_sum(s);
+    if (lane == 0) nrm[col] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = 0; j < kk; ++j) {
     if (wv == 0) {
       double mx = 0.0;
       for (int col = j + lane; col < n; col += 64) mx = fmax(mx, nrm[col]);
@@ -838,11 +848,13 @@ __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps
       if (lane == 0) {
         s_scal[0] = mx;
         s_int[0] = q;
+        s_scal[2] = nrm[q];
       }
     }
     __syncthreads();
     const double mx = s_scal[0];
     const int q = s_int[0];
+    const double alpha = s_scal[2];
     if (j == 0) r11 = mx;
     if (mx == 0.0 || mx <= eps * r11) {
       k = j;
@@ -858,10 +870,10 @@ __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps
         const int t = perm[j];
         perm[j] = perm[q];
         perm[q] = t;
+        nrm[q] = nrm[j];  // the column moved to position q keeps its norm
       }
     }
     __syncthreads();
-    const double alpha = nrm[q];
     const double x0 = Y[size_t(j) * ld + j];
     const double sg = x0 >= 0.0 ? 1.0 : -1.0;
     const double v0 = x0 + sg * alpha;
@@ -876,13 +888,59 @@ __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps
     }
     __syncthreads();
     const double vv = s_scal[1];
-    for (int col = j + 1 + wv; col < n; col += NWAVE) {
-      double w = 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) w += Y[size_t(j) * ld + i] * Y[size_t(col) * ld + i];
-      w = wave_sum(w) + v0 * Y[size_t(col) * ld + j];
-      const double f = 2.0 * w / vv;
-      if (lane == 0) Y[size_t(col) * ld + j] -= f * v0;
-      for (int i = j + 1 + lane; i < m; i += 64) Y[size_t(col) * ld + i] -= f * Y[size_t(j) * ld + i];
+    const int i0 = j + 1 + lane;
+    if (m - (j + 1) <= 64 * CPQR_RB) {
+      // Householder vector in registers, one read and one write per column
+      double vr[CPQR_RB];
+#pragma unroll
+      for (int u = 0; u < CPQR_RB; ++u) {
+        const int i = i0 + 64 * u;
+        vr[u] = i < m ? Y[size_t(j) * ld + i] : 0.0;
+      }
+      for (int col = j + 1 + wv; col < n; col += NWAVE) {
+        double* yc = Y + size_t(col) * ld;
+        double yr[CPQR_RB];
+        double w = 0.0;
+#pragma unroll
+        for (int u = 0; u < CPQR_RB; ++u) {
+          const int i = i0 + 64 * u;
+          yr[u] = i < m ? yc[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < CPQR_RB; ++u) w += vr[u] * yr[u];
+        w = wave_sum(w) + v0 * yc[j];
+        const double f = 2.0 * w / vv;
+        if (lane == 0) yc[j] -= f * v0;
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < CPQR_RB; ++u) {
+          const int i = i0 + 64 * u;
+          const double y = yr[u] - f * vr[u];
+          if (i < m) {
+            yc[i] = y;
+            s += y * y;
+          }
+        }
+        s = wave_sum(s);
+        if (lane == 0) nrm[col] = sqrt(s);
+      }
+    } else {
+      for (int col = j + 1 + wv; col < n; col += NWAVE) {
+        double* yc = Y + size_t(col) * ld;
+        double w = 0.0;
+        for (int i = i0; i < m; i += 64) w += Y[size_t(j) * ld + i] * yc[i];
+        w = wave_sum(w) + v0 * yc[j];
+        const double f = 2.0 * w / vv;
+        if (lane == 0) yc[j] -= f * v0;
+        double s = 0.0;
+        for (int i = i0; i < m; i += 64) {
+          const double y = yc[i] - f * Y[size_t(j) * ld + i];
+          yc[i] = y;
+          s += y * y;
+        }
+        s = wave_sum(s);
+        if (lane == 0) nrm[col] = sqrt(s);
+      }
     }
     __syncthreads();
     if (tid == 0) Y[size_t(j) * ld + j] = -sg * alpha;
