@@ -56,8 +56,9 @@ __device__ inline void wave_argmin_int(int& key, int& i) {
   }
 }
 
-// Block-wide sum of one double per thread (all threads call).
-__device__ inline double block_sum(double v, double* red /* NWAVE */) {
+// Block-wide sum of one double per thread (all threads of NW waves call).
+template <int NW = NWAVE>
+__device__ inline double block_sum(double v, double* red /* NW */) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
@@ -65,13 +66,15 @@ __device__ inline double block_sum(double v, double* red /* NWAVE */) {
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < NWAVE; ++k) s += red[k];
+  for (int k = 0; k < NW; ++k) s += red[k];
   return s;
 }
 
-// Exclusive prefix count of a predicate over the workgroup; returns the
-// thread's offset and writes the total to *total (all threads call).
-__device__ inline int block_scan_flag(bool f, int* wtot /* NWAVE */, int* total) {
+// Exclusive prefix count of a predicate over the workgroup of NW waves;
+// returns the thread's offset and writes the total to *total (all threads
+// call).
+template <int NW = NWAVE>
+__device__ inline int block_scan_flag(bool f, int* wtot /* NW */, int* total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t m = __ballot(f);
   const uint64_t below = lane == 0 ? 0ull : (m & ((~0ull) >> (64 - lane)));
@@ -81,7 +84,7 @@ __device__ inline int block_scan_flag(bool f, int* wtot /* NWAVE */, int* total)
   __syncthreads();
   int off = 0, tot = 0;
 #pragma unroll
-  for (int k = 0; k < NWAVE; ++k) {
+  for (int k = 0; k < NW; ++k) {
     if (k < w) off += wtot[k];
     tot += wtot[k];
   }

@@ -798,7 +798,7 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
 
 // ---------------------------------------------------------------------------
 // Block-cooperative ID for segments wider than 128 columns: the stacked rows
-// are staged in the segment's global scratch, the CPQR runs on 256 threads.
+// are staged in the segment's global scratch, the CPQR runs on NT threads.
 // ---------------------------------------------------------------------------
 
 // CPQR of Y (m x n, column-major, ld) with fresh column norms each step and
@@ -809,18 +809,20 @@ __global__ __launch_bounds__(64 * NW) void k_seg_id_cols(const DSeg* segs, int n
 // forms its Householder dot, updates it and sums the squares of the updated
 // entries below the pivot row, which are the fresh norms the next step
 // pivots on (recomputed from the entries, not downdated).  When the rows
-// below the pivot fit CPQR_RB entries per lane, the Householder vector stays
-// in registers for the whole step and each column is read once.
-constexpr int CPQR_RB = 32;
-
+// below the pivot fit CPQR_RB entries per lane (32, or 16 for groups of 16
+// waves, which have half the registers), the Householder vector stays in
+// registers for the whole step and each column is read once.
+template <int NW>
 __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps, double* nrm,
                           double* s_scal, int* s_int, double* r11_out) {
+  constexpr int NT = 64 * NW;
+  constexpr int CPQR_RB = NW >= 16 ? 16 : 32;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int kk = m < n ? m : n;
   int k = kk;
   double r11 = 0.0;
   // norms of the first step (rows 0..m-1)
-  for (int col = wv; col < n; col += NWAVE) {
+  for (int col = wv; col < n; col += NW) {
     double s = 0.0;
     for (int i = lane; i < m; i += 64) {
       const double y = Y[size_t(col) * ld + i];
@@ -861,7 +863,7 @@ __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps
       break;
     }
     if (q != j) {
-      for (int i = tid; i < m; i += WG) {
+      for (int i = tid; i < m; i += NT) {
         const double t = Y[size_t(j) * ld + i];
         Y[size_t(j) * ld + i] = Y[size_t(q) * ld + i];
         Y[size_t(q) * ld + i] = t;
@@ -897,7 +899,7 @@ __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps
         const int i = i0 + 64 * u;
         vr[u] = i < m ? Y[size_t(j) * ld + i] : 0.0;
       }
-      for (int col = j + 1 + wv; col < n; col += NWAVE) {
+      for (int col = j + 1 + wv; col < n; col += NW) {
         double* yc = Y + size_t(col) * ld;
         double yr[CPQR_RB];
         double w = 0.0;
@@ -925,7 +927,7 @@ __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps
         if (lane == 0) nrm[col] = sqrt(s);
       }
     } else {
-      for (int col = j + 1 + wv; col < n; col += NWAVE) {
+      for (int col = j + 1 + wv; col < n; col += NW) {
         double* yc = Y + size_t(col) * ld;
         double w = 0.0;
         for (int i = i0; i < m; i += 64) w += Y[size_t(j) * ld + i] * yc[i];
@@ -951,16 +953,17 @@ __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps
 }
 
 
-template <typename T>
-__global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const DNbr* nbrs,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_seg_id(const DSeg* segs, int nseg, const DNbr* nbrs,
                                                const DBlk* blks, GridGeom g, int32_t* iarena,
                                                T* varena, double* scratch, DLevelDyn dyn,
                                                IdParams prm, IdTiers tiers) {
+  constexpr int NW = NT / 64;
   extern __shared__ double lds[];
   __shared__ double s_nrm[512];
-  __shared__ double s_scal[4];
+  __shared__ double s_scal[NW > 4 ? NW : 4];
   __shared__ int s_int[4];
-  __shared__ int s_w[NWAVE];
+  __shared__ int s_w[NW];
   __shared__ int s_cnt[2];
   const int c = blockIdx.x;
   if (c >= nseg) return;
@@ -974,7 +977,7 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
   int32_t* dofs = iarena + S.ioff;
   int32_t* perm = dofs + S.cap;
   int32_t* tag = perm + 2 * S.cap;  // after piv
-  for (int i = tid; i < n; i += WG) perm[i] = i;
+  for (int i = tid; i < n; i += NT) perm[i] = i;
   const size_t rc = size_t(S.rcap);
   double* BN = scratch + S.scr_off;  // near rows, column-major (ld rcap)
   double* BF = BN + rc * S.cap;      // far rows, row-major (ld n)
@@ -993,7 +996,7 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
     const int32_t* dd = iarena + segs[nb.d].ioff;
     for (int half = 0; half < hm; ++half) {
       const T* blk = varena + blks[half == 0 ? nb.blk_dc : nb.blk_cd].off;
-      for (int base = 0; base < nd; base += WG) {
+      for (int base = 0; base < nd; base += NT) {
         const int i = base + tid;
         const bool valid = i < nd;
         int v = 0;
@@ -1011,8 +1014,8 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
           near = dist <= S.thr;
         }
         int tn, tf;
-        const int pn = block_scan_flag(valid && near, s_w, &tn);
-        const int pf = block_scan_flag(valid && !near, s_w, &tf);
+        const int pn = block_scan_flag<NW>(valid && near, s_w, &tn);
+        const int pf = block_scan_flag<NW>(valid && !near, s_w, &tf);
         const int bn = s_cnt[0], bf = s_cnt[1];
         if (valid) {
           if (near) {
@@ -1060,29 +1063,29 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
     const bool sampled = h < nF;
     const int m = nN + (sampled ? h : nF);
     // 2. Y = [B_N; G B_F / sqrt(h)] (or the exact far rows)
-    for (int t = tid; t < nN * n; t += WG) {
+    for (int t = tid; t < nN * n; t += NT) {
       const int j = t / nN, i = t % nN;
       Yg[size_t(j) * rc + i] = BN[size_t(j) * rc + i];
     }
     if (!sampled) {
-      for (int t = tid; t < nF * n; t += WG) {
+      for (int t = tid; t < nF * n; t += NT) {
         const int f = t / n, j = t % n;
         Yg[size_t(j) * rc + nN + f] = BF[size_t(f) * n + j];
       }
     } else {
       const double sc = 1.0 / sqrt(double(h));
-      for (int t = tid; t < h * n; t += WG) {
+      for (int t = tid; t < h * n; t += NT) {
         const int i = t % h, j = t / h;
         Yg[size_t(j) * rc + nN + i] = 0.0;
       }
-      for (int t = tid; t < prm.probes * n; t += WG) P[t] = 0.0;
+      for (int t = tid; t < prm.probes * n; t += NT) P[t] = 0.0;
       const int hp = h + prm.probes;  // sample rows, then probe rows
       for (int i0 = 0; i0 < hp; i0 += 32) {
         const int ih = hp - i0 < 32 ? hp - i0 : 32;
         for (int f0 = 0; f0 < nF; f0 += 64) {
           const int fw = nF - f0 < 64 ? nF - f0 : 64;
           __syncthreads();
-          for (int t = tid; t < ih * fw; t += WG) {
+          for (int t = tid; t < ih * fw; t += NT) {
             const int ii = t / fw, f = t % fw;
             const int row = i0 + ii;
             const int stream = row < h ? 0 : 1;
@@ -1091,7 +1094,7 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
                                            tag[2 * (f0 + f) + 1]);
           }
           __syncthreads();
-          for (int t = tid; t < ih * n; t += WG) {
+          for (int t = tid; t < ih * n; t += NT) {
             const int ii = t / n, j = t % n;
             double acc = 0.0;
             for (int f = 0; f < fw; ++f) acc += lds[ii * 64 + f] * BF[size_t(f0 + f) * n + j];
@@ -1104,30 +1107,30 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
         }
       }
       __syncthreads();
-      for (int t = tid; t < h * n; t += WG) {
+      for (int t = tid; t < h * n; t += NT) {
         const int i = t % h, j = t / h;
         Yg[size_t(j) * rc + nN + i] *= sc;
       }
     }
-    for (int i = tid; i < n; i += WG) perm[i] = i;
+    for (int i = tid; i < n; i += NT) perm[i] = i;
     __syncthreads();
     // 3. CPQR (staged in LDS when it fits)
     const bool inlds = size_t(m) * n <= LDS_DOUBLES;
     double* Y = inlds ? lds : Yg;
     const int ld = inlds ? m : int(rc);
     if (inlds) {
-      for (int t = tid; t < m * n; t += WG) {
+      for (int t = tid; t < m * n; t += NT) {
         const int j = t / m, i = t % m;
         lds[t] = Yg[size_t(j) * rc + i];
       }
     }
     double* nrm = n <= 512 ? s_nrm : P + 8 * n;
     __syncthreads();
-    k = block_cpqr(Y, ld, m, n, perm, prm.eps, nrm, s_scal, s_int, &r11);
+    k = block_cpqr<NW>(Y, ld, m, n, perm, prm.eps, nrm, s_scal, s_int, &r11);
     __syncthreads();
     // 4. T = R11^{-1} R12 (back substitution in FP64, in place in Y)
     const int nr = n - k;
-    for (int q = tid; q < nr; q += WG) {
+    for (int q = tid; q < nr; q += NT) {
       double* col = Y + size_t(k + q) * ld;
       for (int i = k - 1; i >= 0; --i) {
         double s = col[i];
@@ -1142,18 +1145,18 @@ __global__ __launch_bounds__(WG) void k_seg_id(const DSeg* segs, int nseg, const
       double worst = 0.0;
       for (int pr = 0; pr < prm.probes; ++pr) {
         double s = 0.0;
-        for (int q = tid; q < nr; q += WG) {
+        for (int q = tid; q < nr; q += NT) {
           double e = P[pr * n + perm[k + q]];
           for (int t = 0; t < k; ++t) e -= P[pr * n + perm[t]] * Y[size_t(k + q) * ld + t];
           s += e * e;
         }
-        s = block_sum(s, s_scal);
+        s = block_sum<NW>(s, s_scal);
         worst = fmax(worst, sqrt(s));
       }
       accept = worst <= prm.tau * sqrt(double(nr)) * prm.eps * r11;
     }
     if (accept) {
-      for (int t = tid; t < k * nr; t += WG) {
+      for (int t = tid; t < k * nr; t += NT) {
         const int i = t / nr, q = t % nr;
         Tm[t] = T(Y[size_t(k + q) * ld + i]);
       }

@@ -204,7 +204,10 @@ namespace {
 constexpr size_t ID_LDS_LIMIT = 152 * 1024;  // largest LDS of one group (one per CU)
 constexpr size_t SEGLU_MAX_BYTES = 152 * 1024;   // segment LU of large segments
 constexpr int SEGLU_WAVE_MAX_N = 32;             // segments up to this size: one wave each
+constexpr int ID_BLK_THREADS = 1024;             // block ID of segments over 128 DOFs: sixteen waves
 constexpr int SEGLU_BLOCK_NT = 256;              // threads of the block segment LU (one block per CU)
+constexpr int SEGLU_WIDE_N = 128;                // segments beyond this size: the wide segment LU
+constexpr int SEGLU_WIDE_NT = 1024;              // its threads
 constexpr size_t MELIM_MAX_BYTES = 152 * 1024;  // staged separator terms of the merge (at most: one group per CU)
 
 // Launch-shape choices (the autotuner's search space); the defaults are the
@@ -1151,7 +1154,7 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
           LAUNCH(K_ID_C, l, k_seg_id_cols<T, 8, 2, true, 4, true><<<unsigned(ns), 512, size_t(tz.lds_c), st>>>(
               segs, ns, nb, blks, F->g, iar, var, scr, d, prm, tz));
         if (T_.id_old)
-          LAUNCH(K_ID_BLK, l, k_seg_id<T><<<unsigned(ns), WG, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var,
+          LAUNCH(K_ID_BLK, l, k_seg_id<T, ID_BLK_THREADS><<<unsigned(ns), ID_BLK_THREADS, LDS_BYTES, st>>>(segs, ns, nb, blks, F->g, iar, var,
                                                                               scr, d, prm, tz));
       }
       for (int i = 0; i < 3; ++i)
@@ -1169,9 +1172,15 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
       if (T_.max_cap > SEGLU_WAVE_MAX_N) {
         const int64_t cap = T_.max_cap;
         const int big = int(std::min<int64_t>(2 * cap * cap + cap, int64_t(SEGLU_MAX_BYTES / 8)));
+        const int wide = 2 * SEGLU_WIDE_N * SEGLU_WIDE_N;  // staging need beyond which a segment is wide
         LAUNCH_MORE(K_LU, l, k_seg_lu<T, SEGLU_BLOCK_NT><<<unsigned(ns), SEGLU_BLOCK_NT, size_t(big) * 8, st>>>(
-            segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, INT32_MAX, big, l,
+            segs, ns, blks, iar, var, scr, d, status, 2 * SEGLU_WAVE_MAX_N * SEGLU_WAVE_MAX_N, wide, big, l,
             o.symmetric));
+        // wide segments (staged in scratch): 1024 threads, for the few large
+        // fronts of the coarse levels
+        if (T_.max_cap > SEGLU_WIDE_N)
+          LAUNCH_MORE(K_LU, l, k_seg_lu<T, SEGLU_WIDE_NT><<<unsigned(ns), SEGLU_WIDE_NT, 0, st>>>(
+              segs, ns, blks, iar, var, scr, d, status, wide, INT32_MAX, 0, l, o.symmetric));
       }
     }
     if (l > 1) {
