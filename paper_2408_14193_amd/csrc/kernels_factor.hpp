@@ -1439,19 +1439,54 @@ __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk,
       __syncthreads();  // the next task restages
       continue;
     }
-    for (int t = tid; t < kc * kd; t += NT) {
-      const int i = t / kd, j = t % kd;
-      double v = tk.src == -2 ? (i == j ? 1.0 : 0.0) : (src ? double(src[t]) : 0.0);
-      for (int e = tk.sep_begin; e < tk.sep_end; ++e) {
-        const DSepTerm st = terms[e];
-        const int ks = dyn.k[st.s];
-        const T* Acs = varena + blks[st.blk_cs].soff;
-        const T* Asd = varena + blks[st.blk_sd].soff;
-        double acc = 0.0;
-        for (int u = 0; u < ks; ++u) acc += double(Acs[size_t(i) * ks + u]) * double(Asd[size_t(u) * kd + j]);
-        v -= acc;
+    if (tk.sep_end == tk.sep_begin) {
+      // no separator term: the scaled block or the identity
+      for (int t = tid; t < kc * kd; t += NT) {
+        const int i = t / kd, j = t % kd;
+        const double v = tk.src == -2 ? (i == j ? 1.0 : 0.0) : (src ? double(src[t]) : 0.0);
+        out[size_t(oc + i) * nD + od + j] = T(v);
       }
-      out[size_t(oc + i) * nD + od + j] = T(v);
+      continue;
+    }
+    // the block and its factors exceed the LDS: 16 x 64 output tiles on the
+    // matrix cores (FP64), one wave per tile, the factors' entries read from
+    // memory, every separator term accumulated before the tile is written
+    {
+      const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+      const int nti = (kc + 15) >> 4, ncg = (kd + 63) >> 6;
+      for (int unit = w; unit < nti * ncg; unit += NT / 64) {
+        const int ti = unit / ncg, cg = unit - ti * ncg, i0 = 16 * ti, j0 = 64 * cg;
+        const int nct = ((kd - j0 < 64 ? kd - j0 : 64) + 15) >> 4;
+        gg_v4 acc[4] = {};
+        for (int e = tk.sep_begin; e < tk.sep_end; ++e) {
+          const DSepTerm st = terms[e];
+          const int ks = dyn.k[st.s];
+          const T* Acs = varena + blks[st.blk_cs].soff;
+          const T* Asd = varena + blks[st.blk_sd].soff;
+          wave_tile_mfma(
+              [&](int i, int u) {
+                const double v = double(Acs[size_t(i < kc ? i : kc - 1) * ks + (u < ks ? u : ks - 1)]);
+                return i < kc && u < ks ? v : 0.0;
+              },
+              [&](int u, int col) {
+                const int j = j0 + col;
+                return double(Asd[size_t(u < ks ? u : ks - 1) * kd + (j < kd ? j : kd - 1)]);
+              },
+              i0, 0, ks, nct, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + lk + 4 * r;
+#pragma unroll
+          for (int cc = 0; cc < 4; ++cc) {
+            const int j = j0 + 16 * cc + li;
+            if (i < kc && j < kd && cc < nct) {
+              const double v0 = tk.src == -2 ? (i == j ? 1.0 : 0.0) : (src ? double(src[size_t(i) * kd + j]) : 0.0);
+              out[size_t(oc + i) * nD + od + j] = T(v0 - acc[cc][r]);
+            }
+          }
+        }
+      }
     }
   }
 }
