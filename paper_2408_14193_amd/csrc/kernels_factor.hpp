@@ -1032,62 +1032,82 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
   T* out = varena + B.soff;
   const T* Lc = varena + segs[c].lu_off;  // packed inverse of c
   const T* Ud = varena + segs[d].lu_off;  // packed inverse of d
-  // row map of the skeleton-part pivots of c: row i of P_s X is row rm[i]
-  __shared__ int s_rm[1024];
-  int* rm = kc <= 1024 ? s_rm : reinterpret_cast<int*>(lds);
-  for (int i = tid; i < kc; i += WG) rm[i] = pivc[nrc + i] - nrc;
+  // block row of row i of P_s A_cd[s_c, s_d] and block column of column j,
+  // in the dynamic LDS (LDS_DOUBLES * 2 ints)
+  int* rs = reinterpret_cast<int*>(lds);
+  int* cs = rs + kc;
+  if (kc + kd > 2 * LDS_DOUBLES) {
+    // (beyond every layout this library builds) poison the block so the
+    // residual check reports it
+    for (int t = tid; t < kc * kd; t += WG) out[t] = T(NAN);
+    return;
+  }
+  for (int i = tid; i < kc; i += WG) {
+    const int r = pivc[nrc + i] - nrc;
+    rs[i] = spc ? permc[r] : r;
+  }
+  for (int j = tid; j < kd; j += WG) cs[j] = spd ? permd[j] : j;
   __syncthreads();
-  const bool inlds = 2 * size_t(kc) * kd <= LDS_DOUBLES && kc <= 1024;
-  if (inlds) {
-    double* X = lds;
-    double* Yb = lds + size_t(kc) * kd;
-    for (int t = tid; t < kc * kd; t += WG) {
-      const int i = t / kd, j = t % kd;
-      const int r = rm[i];
-      const int si = spc ? permc[r] : r, sj = spd ? permd[j] : j;
-      X[t] = double(A[size_t(si) * nd + sj]);
-    }
-    __syncthreads();
-    for (int t = tid; t < kc * kd; t += WG) {
-      const int i = t / kd, j = t % kd;
-      const T* lrow = Lc + size_t(nrc + i) * nc + nrc;
-      double v = sym ? double(lrow[i]) * X[t] : X[t];
-      for (int u = 0; u < i; ++u) v += double(lrow[u]) * X[size_t(u) * kd + j];
-      Yb[t] = v;
-    }
-    __syncthreads();
-    for (int t = tid; t < kc * kd; t += WG) {
-      const int i = t / kd, j = t % kd;
-      double v = 0.0;
-      for (int u = 0; u <= j; ++u) v += Yb[size_t(i) * kd + u] * double(Ud[size_t(nrd + u) * nd + nrd + j]);
-      out[t] = T(v);
-    }
-  } else {
-    // large block: in place in the output region; columns for L^{-1}
-    // (rows descending), then rows for U^{-1} (columns descending)
-    for (int t = tid; t < kc * kd; t += WG) {
-      const int i = t / kd, j = t % kd;
-      const int r = rm[i];
-      const int si = spc ? permc[r] : r, sj = spd ? permd[j] : j;
-      out[t] = A[size_t(si) * nd + sj];
-    }
-    __syncthreads();
-    for (int j = tid; j < kd; j += WG)
-      for (int i = kc - 1; i >= (sym ? 0 : 1); --i) {
-        const T* lrow = Lc + size_t(nrc + i) * nc + nrc;
-        double v = double(out[size_t(i) * kd + j]);
-        if (sym) v *= double(lrow[i]);
-        for (int u = 0; u < i; ++u) v += double(lrow[u]) * double(out[size_t(u) * kd + j]);
-        out[size_t(i) * kd + j] = T(v);
+  // products on the matrix cores (FP64) in 16 x 64 tiles, operator entries
+  // read from memory: first Y = L^{-1} X into the output region (the stored
+  // diagonal in the symmetric form), then out = Y U^{-1} in place, each wave
+  // owning whole 16-row stripes and taking their column groups from the
+  // right, so a tile only reads columns that no tile has overwritten yet
+  const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int nti = (kc + 15) >> 4, ncg = (kd + 63) >> 6;
+  for (int unit = w; unit < nti * ncg; unit += NWAVE) {
+    const int ti = unit / ncg, cg = unit - ti * ncg, i0 = 16 * ti, j0 = 64 * cg;
+    const int nct = ((kd - j0 < 64 ? kd - j0 : 64) + 15) >> 4;
+    gg_v4 acc[4] = {};
+    wave_tile_mfma(
+        [&](int i, int u) {
+          const double l = double(Lc[size_t(nrc + (i < kc ? i : kc - 1)) * nc + nrc + (u < kc ? u : kc - 1)]);
+          return i < kc && u < i ? l : (i < kc && u == i ? (sym ? l : 1.0) : 0.0);
+        },
+        [&](int u, int col) {
+          const int j = j0 + col;
+          return double(A[size_t(rs[u < kc ? u : kc - 1]) * nd + cs[j < kd ? j : kd - 1]]);
+        },
+        i0, 0, i0 + 16 < kc ? i0 + 16 : kc, nct, acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + lk + 4 * r;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int j = j0 + 16 * cc + li;
+        if (i < kc && j < kd && cc < nct) out[size_t(i) * kd + j] = T(acc[cc][r]);
       }
-    __syncthreads();
-    for (int i = tid; i < kc; i += WG)
-      for (int j = kd - 1; j >= 0; --j) {
-        double v = 0.0;
-        for (int u = 0; u <= j; ++u)
-          v += double(out[size_t(i) * kd + u]) * double(Ud[size_t(nrd + u) * nd + nrd + j]);
-        out[size_t(i) * kd + j] = T(v);
+    }
+  }
+  __syncthreads();
+  for (int ti = w; ti < nti; ti += NWAVE) {
+    const int i0 = 16 * ti;
+    for (int cg = ncg - 1; cg >= 0; --cg) {
+      const int j0 = 64 * cg;
+      const int nct = ((kd - j0 < 64 ? kd - j0 : 64) + 15) >> 4;
+      const int u1 = j0 + 64 < kd ? j0 + 64 : kd;
+      gg_v4 acc[4] = {};
+      wave_tile_mfma(
+          [&](int i, int u) {
+            const double y = double(out[size_t(i < kc ? i : kc - 1) * kd + (u < u1 ? u : u1 - 1)]);
+            return i < kc && u < u1 ? y : 0.0;
+          },
+          [&](int u, int col) {
+            const int j = j0 + col;
+            const double uv = double(Ud[size_t(nrd + (u < kd ? u : kd - 1)) * nd + nrd + (j < kd ? j : kd - 1)]);
+            return u <= j && j < kd ? uv : 0.0;
+          },
+          i0, 0, u1, nct, acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + lk + 4 * r;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int j = j0 + 16 * cc + li;
+          if (i < kc && j < kd && cc < nct) out[size_t(i) * kd + j] = T(acc[cc][r]);
+        }
       }
+    }
   }
 }
 

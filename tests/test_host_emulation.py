@@ -184,3 +184,14 @@ def test_symmetric_form_3d(exe, tmp_path):
     _write(P, str(tmp_path))
     it, first, final = _run(exe, str(tmp_path), 64, 0, P.eps, 2, 1e-10, 0, sym=True)
     assert first <= 10 * P.eps and final <= 1e-10
+
+
+@pytest.mark.parametrize("sym", [False, True])
+def test_exact_elimination_3d_wide_blocks(exe, tmp_path, sym):
+    """15^3 with eps = 0: no skeleton shrinks, so the 225-DOF separator
+    blocks exceed every LDS-staged kernel and take the matrix-core tiles
+    read from memory (coupling scaling and merge), in both forms."""
+    P = make_config(3, side=15, nrhs=1)
+    _write(P, str(tmp_path))
+    it, first, final = _run(exe, str(tmp_path), 64, 0, 0.0, 2, 0.0, 0, sym=sym)
+    assert first <= 1e-12
