@@ -1356,6 +1356,11 @@ __global__ void k_merge_sizes(const DSeg* useg, int nuseg, const int32_t* cons_p
 // accumulation inside a term.  Lane l supplies A[i0 + l%16][k0 + l/16] and
 // B[k0 + l/16][j0 + l%16] (zero outside the matrices); its four results are
 // column j0 + l%16 of rows i0 + l/16 + 4r (FP64) or i0 + 4(l/16) + r (FP32).
+// Merge tasks whose skeletons exceed this size take the matrix-core tiles
+// read from memory when they do not fit the LDS; smaller ones, with too few
+// output tiles to occupy the waves, the per-thread dot products.
+constexpr int MELIM_TILE_MIN = 128;
+
 template <typename T, int NW>
 __device__ inline void schur_term_mfma(double* acc, const T* A, const T* B, int kc, int ks, int kd) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1407,7 +1412,11 @@ __device__ inline void schur_term_mfma(double* acc, const T* A, const T* B, int 
   }
 }
 
-template <typename T, int NT>
+// WIDE = false: zero the level-(l-1) block, then every task except the wide
+// ones (skeletons over MELIM_TILE_MIN that do not fit the LDS); WIDE = true,
+// launched after it: the wide tasks only, on the matrix-core tiles (a kernel
+// of its own, so their registers do not lower the occupancy of the others).
+template <typename T, int NT, bool WIDE = false>
 __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk, const int32_t* task_ptr,
                                                    const DTask* tasks, const DSepTerm* terms,
                                                    const DBlk* blks, T* varena, DLevelDyn dyn,
@@ -1419,8 +1428,10 @@ __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk,
   const DBlk U = ublks[b];
   const int nC = udyn.n[U.c], nD = udyn.n[U.d];
   T* out = varena + U.off;
-  for (int t = tid; t < nC * nD; t += NT) out[t] = T(0);
-  __syncthreads();
+  if (!WIDE) {
+    for (int t = tid; t < nC * nD; t += NT) out[t] = T(0);
+    __syncthreads();
+  }
   for (int q = task_ptr[b]; q < task_ptr[b + 1]; ++q) {
     const DTask tk = tasks[q];
     const int kc = dyn.k[tk.c], kd = dyn.k[tk.d];
@@ -1434,6 +1445,8 @@ __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk,
     const int acc_bytes = (kc * kd * 8 + 15) & ~15;
     const bool staged = lds_bytes > 0 && tk.sep_end > tk.sep_begin &&
                         acc_bytes + (kc + kd) * ksmax * int(sizeof(T)) <= lds_bytes;
+    const bool wide = !staged && (kc > MELIM_TILE_MIN || kd > MELIM_TILE_MIN);
+    if (wide != WIDE) continue;
     if (staged) {
       double* acc = lds;  // kc x kd
       T* sA = reinterpret_cast<T*>(reinterpret_cast<char*>(lds) + acc_bytes);
@@ -1459,19 +1472,29 @@ __global__ __launch_bounds__(NT) void k_merge_elim(const DBlk* ublks, int nublk,
       __syncthreads();  // the next task restages
       continue;
     }
-    if (tk.sep_end == tk.sep_begin) {
-      // no separator term: the scaled block or the identity
+    if (!WIDE) {
+      // the block and its factors exceed the LDS, but there are few output
+      // tiles: one output per thread, FP64 dot products from memory
       for (int t = tid; t < kc * kd; t += NT) {
         const int i = t / kd, j = t % kd;
-        const double v = tk.src == -2 ? (i == j ? 1.0 : 0.0) : (src ? double(src[t]) : 0.0);
+        double v = tk.src == -2 ? (i == j ? 1.0 : 0.0) : (src ? double(src[t]) : 0.0);
+        for (int e = tk.sep_begin; e < tk.sep_end; ++e) {
+          const DSepTerm st = terms[e];
+          const int ks = dyn.k[st.s];
+          const T* Acs = varena + blks[st.blk_cs].soff;
+          const T* Asd = varena + blks[st.blk_sd].soff;
+          double acc = 0.0;
+          for (int u = 0; u < ks; ++u) acc += double(Acs[size_t(i) * ks + u]) * double(Asd[size_t(u) * kd + j]);
+          v -= acc;
+        }
         out[size_t(oc + i) * nD + od + j] = T(v);
       }
       continue;
     }
-    // the block and its factors exceed the LDS: 16 x 64 output tiles on the
-    // matrix cores (FP64), one wave per tile, the factors' entries read from
-    // memory, every separator term accumulated before the tile is written
-    {
+    // wide blocks (3D fronts): 16 x 64 output tiles on the matrix cores
+    // (FP64), one wave per tile, the factors' entries read from memory, every
+    // separator term accumulated before the tile is written
+    if constexpr (WIDE) {
       const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
       const int nti = (kc + 15) >> 4, ncg = (kd + 63) >> 6;
       for (int unit = w; unit < nti * ncg; unit += NT / 64) {

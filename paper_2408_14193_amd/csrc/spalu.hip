@@ -1237,6 +1237,10 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
         LAUNCH(K_MELIM, l, k_merge_elim<T, WG><<<unsigned(U.blks.size()), WG, lb, st>>>(
             tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
             tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du, int(lb)));
+        if (T_.max_cap > MELIM_TILE_MIN)  // wide tasks (3D fronts), after the zeroing above
+          LAUNCH_MORE(K_MELIM, l, k_merge_elim<T, WG, true><<<unsigned(U.blks.size()), WG, 0, st>>>(
+              tab<DBlk>(ws, U.o_blks), int(U.blks.size()), tab<int32_t>(ws, T_.o_task_ptr),
+              tab<DTask>(ws, T_.o_tasks), tab<DSepTerm>(ws, T_.o_terms), blks, var, d, du, int(lb)));
       }
     }
   }
