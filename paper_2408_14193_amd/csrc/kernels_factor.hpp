@@ -985,12 +985,14 @@ __global__ __launch_bounds__(64) void k_seg_lu_wave(const DSeg* segs, int nseg, 
   }
 }
 
-// LDS doubles of the one-wave coupling scaling of a kc x kd block.
-__host__ __device__ inline int blk_scale_wave_need(int kc, int kd) {
-  return kc * kd + kc * kc + kd * kd + (kc + kd + 1) / 2;
+// LDS doubles of the one-wave coupling scaling of a kc x kd block: the block
+// in FP64, the two triangles in the storage type (vs bytes each), the maps.
+__host__ __device__ inline int blk_scale_wave_need(int kc, int kd, int vs) {
+  return kc * kd + ((kc * kc + kd * kd) * vs + 7) / 8 + (kc + kd + 1) / 2;
 }
+template <typename T>
 __host__ __device__ inline bool blk_scale_wave_fits(int kc, int kd, int lds_doubles) {
-  return kc <= 64 && kd <= 64 && blk_scale_wave_need(kc, kd) <= lds_doubles;
+  return kc <= 64 && kd <= 64 && blk_scale_wave_need(kc, kd, int(sizeof(T))) <= lds_doubles;
 }
 // LDS bytes of the matrix-core coupling scaling of a kc x kd block (the
 // gathered block and L^{-1} times it in FP64, the row and column maps).
@@ -1022,7 +1024,7 @@ __global__ __launch_bounds__(WG) void k_blk_scale(const DBlk* blks, const int32_
   const int kc = dyn.k[c], kd = dyn.k[d];
   const int nrc = dyn.nr[c], nrd = dyn.nr[d];
   if (kc == 0 || kd == 0) return;
-  if (blk_scale_wave_fits(kc, kd, wave_lds_doubles)) return;  // taken by k_blk_scale_wave
+  if (blk_scale_wave_fits<T>(kc, kd, wave_lds_doubles)) return;  // taken by k_blk_scale_wave
   if (blk_scale_mfma_fits(kc, kd, mfma_lds)) return;          // taken by k_blk_scale_mfma
   const bool spc = dyn.passes[c] > 0, spd = dyn.passes[d] > 0;
   const int32_t* permc = iarena + segs[c].ioff + segs[c].cap;
@@ -1129,7 +1131,7 @@ __global__ __launch_bounds__(WG) void k_blk_scale_mfma(const DBlk* blks, const i
   const int c = B.c, d = B.d;
   const int kc = dyn.k[c], kd = dyn.k[d];
   if (kc == 0 || kd == 0) return;
-  if (blk_scale_wave_fits(kc, kd, wave_lds_doubles) || !blk_scale_mfma_fits(kc, kd, mfma_lds)) return;
+  if (blk_scale_wave_fits<T>(kc, kd, wave_lds_doubles) || !blk_scale_mfma_fits(kc, kd, mfma_lds)) return;
   const int nc = dyn.n[c], nd = dyn.n[d];
   const int nrc = dyn.nr[c], nrd = dyn.nr[d];
   const bool spc = dyn.passes[c] > 0, spd = dyn.passes[d] > 0;
@@ -1230,7 +1232,7 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
   const DBlk B = blks[blk_list[bi]];
   const int c = B.c, d = B.d;
   const int kc = dyn.k[c], kd = dyn.k[d];
-  if (!blk_scale_wave_fits(kc, kd, lds_doubles)) return;
+  if (!blk_scale_wave_fits<T>(kc, kd, lds_doubles)) return;
   const int nc = dyn.n[c], nd = dyn.n[d];
   const int nrc = dyn.nr[c], nrd = dyn.nr[d];
   if (kc == 0 || kd == 0) return;
@@ -1242,9 +1244,9 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
   T* out = varena + B.soff;
   const T* Lc = varena + segs[c].lu_off;
   const T* Ud = varena + segs[d].lu_off;
-  double* X = lds;                            // kc x kd
-  double* Lb = X + kc * kd;                   // kc x kc (strict lower part used; diagonal too if sym)
-  double* Ub = Lb + kc * kc;                  // kd x kd (upper part used)
+  double* X = lds;                              // kc x kd
+  T* Lb = reinterpret_cast<T*>(X + kc * kd);    // kc x kc (strict lower part used; diagonal too if sym)
+  T* Ub = Lb + kc * kc;                         // kd x kd (upper part used)
   int* rs = reinterpret_cast<int*>(Ub + kd * kd);  // kc: block row of row i of P_s X
   int* cs = rs + kc;                               // kd: block column of column j
   // row map of the skeleton-part pivots of c (row i of P_s X is row
@@ -1266,7 +1268,7 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
       },
       [&](int t, T v) {
         const int i = t / kc, u = t - i * kc;
-        Lb[t] = u < i || (sym && u == i) ? double(v) : 0.0;
+        Lb[t] = u < i || (sym && u == i) ? v : T(0);
       });
   load_batched<8>(
       kd * kd, lane, 64,
@@ -1276,7 +1278,7 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
       },
       [&](int t, T v) {
         const int u = t / kd, j = t - u * kd;
-        Ub[t] = u <= j ? double(v) : 0.0;
+        Ub[t] = u <= j ? v : T(0);
       });
   wave_sync();
   load_batched<8>(
@@ -1292,8 +1294,8 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
     // Y = L^{-1} X (unit lower, or the stored diagonal in the symmetric
     // form), rows descending so X[u] (u < i) is still X
     for (int i = kc - 1; i >= 0; --i) {
-      double v = sym ? Lb[i * kc + i] * X[i * kd + j] : X[i * kd + j];
-      for (int u = 0; u < i; ++u) v += Lb[i * kc + u] * X[u * kd + j];
+      double v = sym ? double(Lb[i * kc + i]) * X[i * kd + j] : X[i * kd + j];
+      for (int u = 0; u < i; ++u) v += double(Lb[i * kc + u]) * X[u * kd + j];
       X[i * kd + j] = v;
     }
   }
@@ -1302,7 +1304,7 @@ __global__ __launch_bounds__(64) void k_blk_scale_wave(const DBlk* blks, const i
   for (int t = lane; t < kc * kd; t += 64) {
     const int i = t / kd, j = t - i * kd;
     double v = 0.0;
-    for (int u = 0; u <= j; ++u) v += X[i * kd + u] * Ub[u * kd + j];
+    for (int u = 0; u <= j; ++u) v += X[i * kd + u] * double(Ub[u * kd + j]);
     out[t] = T(v);
   }
 }

@@ -373,7 +373,7 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
       size_t need_m = 0;
       for (int32_t b : T.scale_list) {
         const int cc = T.segs[T.blks[b].c].cap, cd = T.segs[T.blks[b].d].cap;
-        const int w = blk_scale_wave_need(std::min(cc, 64), std::min(cd, 64));
+        const int w = blk_scale_wave_need(std::min(cc, 64), std::min(cd, 64), prec == SPALU_FP32 ? 4 : 8);
         if (cc > 64 || cd > 64 || w > SCALE_WAVE_MAX) {
           // beyond the one-wave kernel: the matrix-core kernel for skeletons
           // of at most 128 DOFs within its LDS, the 256-thread kernel else
