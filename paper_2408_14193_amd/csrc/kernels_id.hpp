@@ -927,18 +927,44 @@ __device__ int block_cpqr(double* Y, int ld, int m, int n, int* perm, double eps
         if (lane == 0) nrm[col] = sqrt(s);
       }
     } else {
+      // taller: the same in chunks of CPQR_RB rows per lane, the loads of a
+      // chunk issued together (the sums keep the row order of the lanes)
+      const double* vj = Y + size_t(j) * ld;
       for (int col = j + 1 + wv; col < n; col += NW) {
         double* yc = Y + size_t(col) * ld;
         double w = 0.0;
-        for (int i = i0; i < m; i += 64) w += Y[size_t(j) * ld + i] * yc[i];
+        for (int c0 = i0; c0 < m; c0 += 64 * CPQR_RB) {
+          double vr[CPQR_RB], yr[CPQR_RB];
+#pragma unroll
+          for (int u = 0; u < CPQR_RB; ++u) {
+            const int i = c0 + 64 * u;
+            vr[u] = i < m ? vj[i] : 0.0;
+            yr[u] = i < m ? yc[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < CPQR_RB; ++u) w += vr[u] * yr[u];
+        }
         w = wave_sum(w) + v0 * yc[j];
         const double f = 2.0 * w / vv;
         if (lane == 0) yc[j] -= f * v0;
         double s = 0.0;
-        for (int i = i0; i < m; i += 64) {
-          const double y = yc[i] - f * Y[size_t(j) * ld + i];
-          yc[i] = y;
-          s += y * y;
+        for (int c0 = i0; c0 < m; c0 += 64 * CPQR_RB) {
+          double vr[CPQR_RB], yr[CPQR_RB];
+#pragma unroll
+          for (int u = 0; u < CPQR_RB; ++u) {
+            const int i = c0 + 64 * u;
+            vr[u] = i < m ? vj[i] : 0.0;
+            yr[u] = i < m ? yc[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < CPQR_RB; ++u) {
+            const int i = c0 + 64 * u;
+            const double y = yr[u] - f * vr[u];
+            if (i < m) {
+              yc[i] = y;
+              s += y * y;
+            }
+          }
         }
         s = wave_sum(s);
         if (lane == 0) nrm[col] = sqrt(s);

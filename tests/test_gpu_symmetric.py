@@ -118,3 +118,37 @@ def test_sym_refuses_what_it_cannot_factor(S):
     with pytest.raises(S.SpaluError) as e:
         gpu_factor(S, P, eps=1e-6, symmetric=True)
     assert e.value.code == -3     # SPALU_ESINGULAR: a pivot that is not positive
+
+
+def test_sym_factor_graph_replays_match_direct_launches(S):
+    """The symmetric form's level sweep captured as a HIP graph and replayed
+    gives bitwise the factor of direct launches; switching the form on the
+    same workspace captures (then reuses) a graph per form, with eager work
+    between the replays."""
+    import torch
+    from paper_2408_14193_amd import rank_model
+    P = make_config(1, side=127, nrhs=2)
+    nd = S.ND(P.dims)
+    rp, ci, v, B = to_device(P)
+    Bt = B.t().contiguous()
+    kw = dict(eps=P.eps, precision=S.FP32, rank_model=rank_model.load())
+
+    def result(F):
+        X = torch.empty_like(Bt)
+        F.solve_into(Bt, X, tol=0.0, max_iter=1, graph=False)
+        torch.cuda.synchronize()
+        return F.ranks(), X.cpu().numpy()
+
+    ws = None
+    for sym in (True, False, True):
+        ref_ranks, ref_x = result(S.Factor(nd, rp, ci, v, symmetric=sym, **kw))
+        for rep in range(2):
+            F = S.Factor(nd, rp, ci, v, graph=True, workspace=ws, symmetric=sym, **kw)
+            ws = F.workspace
+            ranks, x = result(F)
+            for a, b in zip(ranks, ref_ranks):
+                assert np.array_equal(a, b), "symmetric %s replay %d: ranks differ" % (sym, rep)
+            assert np.array_equal(x, ref_x), "symmetric %s replay %d: solve differs" % (sym, rep)
+            (Bt * 2.0).sum().item()
+            del F
+

@@ -36,13 +36,15 @@ def _static(S, F, Bt, Xt, tol, restart):
 @pytest.mark.parametrize("tol", [0.0, 1e-10])
 def test_static_solve_matches_workspace_solve(S, tol):
     import torch
-    cases = [(1, 127, 4, S.FP32, 8), (0, 63, 2, S.FP64, 0)]     # the second call is smaller
-    for cfg, side, nrhs, prec, restart in cases:
-        print("case static solve cfg=%d side=%d nrhs=%d tol=%g" % (cfg, side, nrhs, tol), flush=True)
+    # the second call is smaller; the first factor is in the symmetric form
+    cases = [(1, 127, 4, S.FP32, 8, True), (0, 63, 2, S.FP64, 0, False)]
+    for cfg, side, nrhs, prec, restart, sym in cases:
+        print("case static solve cfg=%d side=%d nrhs=%d tol=%g symmetric=%s" % (cfg, side, nrhs, tol, sym),
+              flush=True)
         P = make_config(cfg, side=side, nrhs=nrhs)
         nd = S.ND(P.dims)
         rp, ci, v, B = to_device(P)
-        F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec)
+        F = S.Factor(nd, rp, ci, v, eps=P.eps, precision=prec, symmetric=sym)
         Bt = B.t().contiguous()
         Xs = torch.full_like(Bt, float("nan"))
         Xw = torch.full_like(Bt, float("nan"))
