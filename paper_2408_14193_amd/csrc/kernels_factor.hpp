@@ -146,7 +146,7 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
                                                     const int64_t* rowptr, const int32_t* colind,
                                                     const double* vals, int32_t* iarena, T* varena,
                                                     double* gscratch, int64_t gscr_stride, int* status,
-                                                    int level) {
+                                                    int level, int lds_doubles) {
   extern __shared__ double lds[];
   __shared__ int s_piv;
   __shared__ double s_d;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
   const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1;
   const int32_t* bverts = iarena + L.ioff;
   int32_t* piv = iarena + L.ioff + nb;
-  const bool fits = leaf_lds_need(ni, nb) <= LEAF_LDS_DOUBLES;
+  const bool fits = leaf_lds_need(ni, nb) <= lds_doubles;       // staging in LDS (lds_doubles given)
   double* A = fits ? lds : gscratch + size_t(lf) * gscr_stride;  // A_II, then its inverse
   double* B = A + ni * ni;                                        // A_IB
   double* X = B + ni * nb;                                        // A_II^{-1} A_IB

@@ -83,6 +83,7 @@ struct Layout {
   size_t o_varena = 0, n_varena = 0;
   size_t o_scratch = 0, n_scratch = 0;
   size_t leaf_scr_stride = 0;
+  size_t leaf_need_min = 0;  // smallest LDS staging need of a leaf (doubles)
   int leaf_wc = 0;                 // register slots of the one-wave leaf kernels (0: block kernels)
   int leaf_wave_lds = 0;           // their dynamic LDS bytes (factor)
   int leaf_ni_max = 0;
@@ -462,7 +463,7 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
   // leaves
   const PLevel& PLL = P.levels[L];
   Y.leaves.resize(P.leaves.size());
-  size_t leaf_need = 0;
+  size_t leaf_need = 0, leaf_need_min = SIZE_MAX;
   std::vector<std::vector<int32_t>> bsoff(P.leaves.size());
   for (size_t i = 0; i < P.leaves.size(); ++i) {
     const PLeaf& pl = P.leaves[i];
@@ -491,7 +492,9 @@ std::shared_ptr<Layout> build_layout(const Plan& P, int prec) {
     D.x_off = int64_t(var);
     if (leaf_wave_slots(D.ni, nb) != 0) var += size_t(D.ni) * nb;
     leaf_need = std::max(leaf_need, size_t(leaf_lds_need(D.ni, nb)));
+    leaf_need_min = std::min(leaf_need_min, size_t(leaf_lds_need(D.ni, nb)));
   }
+  Y.leaf_need_min = leaf_need_min;
   // one wave per leaf when every leaf fits its register row
   Y.leaf_wc = 0;
   Y.leaf_wave_lds = 0;
@@ -1048,9 +1051,12 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
         LAUNCH(K_LEAF, L, k_leaf_factor_wave<T, 96><<<nl, 64, wl, st>>>(lt, int(nl), F->g, F->rowptr, F->colind,
                                                                     F->vals, iar, var, status, L + 1));
       } else {
-        LAUNCH(K_LEAF, L, k_leaf_factor<T><<<nl, WG, LEAF_LDS_BYTES, st>>>(
+        // no LDS at all when no leaf fits its staging (3D leaves): the
+        // groups are then limited by waves, not by an unused LDS buffer
+        const bool lds_any = Y.leaf_need_min <= size_t(LEAF_LDS_DOUBLES);
+        LAUNCH(K_LEAF, L, k_leaf_factor<T><<<nl, WG, lds_any ? LEAF_LDS_BYTES : 0, st>>>(
             lt, int(nl), F->g, F->rowptr, F->colind, F->vals, iar, var, scr, int64_t(Y.leaf_scr_stride), status,
-            L + 1));
+            L + 1, lds_any ? LEAF_LDS_DOUBLES : 0));
       }
     }
     // blocks of small segments: one wave each
