@@ -587,6 +587,72 @@ __device__ inline int seg_block_lu(double* A, int n, int split, int* piv, int* s
   return singular;
 }
 
+// The LU without interchanges of the symmetric form (L D L^T, U = D L^T) by
+// panels of 16 columns, for wide segments staged in scratch: each panel is
+// factored by rows (one barrier per column), its rows of U are solved with
+// the unit-lower panel triangle (one column per thread), and the trailing
+// matrix takes the panel's rank-16 update on the matrix cores (FP64 16 x 64
+// tiles, one wave per tile, operands read from memory), so the trailing
+// matrix is read once per panel instead of once per column.  A pivot that is
+// not positive is reported (returns 1); piv receives the identity.
+template <int NT>
+__device__ inline int seg_block_ldl_panels(double* A, int n, int* piv) {
+  constexpr int NB = 16, NW = NT / 64;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  int singular = 0;
+  for (int i = tid; i < n; i += NT) piv[i] = i;
+  for (int jb = 0; jb < n; jb += NB) {
+    const int je = jb + NB < n ? jb + NB : n, nb = je - jb;
+    // 1. the panel: columns jb..je-1, rows below each pivot
+    for (int j = jb; j < je; ++j) {
+      const double d = A[size_t(j) * n + j];
+      if (!(d > 0.0)) singular = 1;
+      for (int i = j + 1 + tid; i < n; i += NT) {
+        const double l = A[size_t(i) * n + j] / d;
+        A[size_t(i) * n + j] = l;
+        for (int c = j + 1; c < je; ++c) A[size_t(i) * n + c] -= l * A[size_t(j) * n + c];
+      }
+      __syncthreads();
+    }
+    if (je == n) break;
+    // 2. rows jb..je-1 of U right of the panel: L11^{-1} A12
+    for (int c = je + tid; c < n; c += NT)
+      for (int j = jb; j < je; ++j) {
+        const double u = A[size_t(j) * n + c];
+        for (int i = j + 1; i < je; ++i) A[size_t(i) * n + c] -= A[size_t(i) * n + j] * u;
+      }
+    __syncthreads();
+    // 3. trailing matrix: A22 -= L21 U12
+    const int m = n - je, nti = (m + 15) >> 4, ncg = (m + 63) >> 6;
+    for (int unit = w; unit < nti * ncg; unit += NW) {
+      const int ti = unit / ncg, cg = unit - ti * ncg, i0 = je + 16 * ti, j0 = je + 64 * cg;
+      const int nct = ((n - j0 < 64 ? n - j0 : 64) + 15) >> 4;
+      gg_v4 acc[4] = {};
+      wave_tile_mfma(
+          [&](int i, int u) {
+            const double v = A[size_t(i < n ? i : n - 1) * n + jb + (u < nb ? u : nb - 1)];
+            return i < n && u < nb ? v : 0.0;
+          },
+          [&](int u, int col) {
+            const int c = j0 + col;
+            return A[size_t(jb + (u < nb ? u : nb - 1)) * n + (c < n ? c : n - 1)];
+          },
+          i0, 0, nb, nct, acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + lk + 4 * r;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int c = j0 + 16 * cc + li;
+          if (i < n && c < n && cc < nct) A[size_t(i) * n + c] -= acc[cc][r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return singular;
+}
+
 // Packed inverses of the unit-lower L and upper U held in W (row-major
 // n x n): out[i][c] = (L^{-1})[i][c] for i > c, (U^{-1})[i][c] for i <= c.
 // L^{-1} by forward elimination of the identity and U^{-1} = (D^{-1} U)^{-1}
@@ -715,7 +781,10 @@ __global__ __launch_bounds__(NT) void k_seg_lu(const DSeg* segs, int nseg, const
   // would stall each step), copied out afterwards
   const bool pv_lds = inlds && need + (n + 1) / 2 <= lds_doubles;
   int* pv = pv_lds ? reinterpret_cast<int*>(lds + need) : piv;
-  if (seg_block_lu<NT>(W, n, sp ? nr : 0, pv, &s_piv, sym != 0)) flag_singular(status, level);
+  // wide symmetric-form segments (in scratch) by panels, the others step by step
+  const bool panels = NT >= 1024 && sym && !inlds;
+  if (panels ? seg_block_ldl_panels<NT>(W, n, pv) : seg_block_lu<NT>(W, n, sp ? nr : 0, pv, &s_piv, sym != 0))
+    flag_singular(status, level);
   __syncthreads();
   // stored form of the interchanges: the composed row map (row i of P X is
   // row piv[i] of X), each entry traced back through the interchanges
