@@ -674,6 +674,110 @@ __device__ inline double balance_entry(double v, int i, int c, double xii, doubl
   return i > c ? v * sqrt(xii) : v / sqrt(xcc);
 }
 
+// The same packed inverses by panels of 16 rows, for wide segments staged
+// in scratch: X holds L^{-1} (strict lower part, unit diagonal implied) and
+// U^{-1} (upper part with its diagonal) directly.  L^{-1} by row panels from
+// the top: the panel rows' products with the finished rows above (FP64
+// 16 x 64 matrix-core tiles, operands read from memory), then a forward
+// substitution inside the panel, one barrier per row; U^{-1} likewise by row
+// panels from the bottom with a backward substitution.  The stored form is
+// that of seg_block_inverse, balanced in the symmetric form.
+template <int NT, typename TO>
+__device__ inline void seg_block_inverse_panels(const double* W, int n, double* X, TO* out, bool sym) {
+  constexpr int NB = 16, NW = NT / 64;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  // L^{-1}: row i, column c < i is -(sum over c <= u < i of L[i][u] Linv[u][c]), Linv[c][c] = 1
+  auto linv = [&](int u, int c) { return u > c ? X[size_t(u) * n + c] : (u == c ? 1.0 : 0.0); };
+  for (int ib = 0; ib < n; ib += NB) {
+    const int ie = ib + NB < n ? ib + NB : n;
+    // columns c < ib: the rows above the panel
+    const int ncg = (ib + 63) >> 6;
+    for (int cg = w; cg < ncg; cg += NW) {
+      const int j0 = 64 * cg;
+      const int nct = ((ib - j0 < 64 ? ib - j0 : 64) + 15) >> 4;
+      gg_v4 acc[4] = {};
+      wave_tile_mfma(
+          [&](int i, int u) {
+            const double l = W[size_t(i < ie ? i : ie - 1) * n + (u < ib ? u : ib - 1)];
+            return i < ie && u < ib ? l : 0.0;
+          },
+          [&](int u, int col) {
+            const int c = j0 + col;
+            return u < ib && c < ib ? linv(u, c) : 0.0;
+          },
+          ib, j0, ib, nct, acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ib + lk + 4 * r;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int c = j0 + 16 * cc + li;
+          if (i < ie && c < ib && cc < nct) X[size_t(i) * n + c] = -acc[cc][r];
+        }
+      }
+    }
+    __syncthreads();
+    // inside the panel, row by row
+    for (int i = ib; i < ie; ++i) {
+      for (int c = tid; c < i; c += NT) {
+        double v = c < ib ? X[size_t(i) * n + c] : 0.0;
+        for (int u = c > ib ? c : ib; u < i; ++u) v -= W[size_t(i) * n + u] * linv(u, c);
+        X[size_t(i) * n + c] = v;
+      }
+      __syncthreads();
+    }
+  }
+  // U^{-1}: row i, column c >= i is (delta_ic - sum over i < u <= c of U[i][u] Uinv[u][c]) / U[i][i]
+  auto uinv = [&](int u, int c) { return u <= c ? X[size_t(u) * n + c] : 0.0; };
+  for (int ie = n; ie > 0; ie -= NB) {
+    const int ib = ie - NB > 0 ? ie - NB : 0;
+    // columns c >= ie: the rows below the panel
+    const int m = n - ie, ncg = (m + 63) >> 6;
+    for (int cg = w; cg < ncg; cg += NW) {
+      const int j0 = ie + 64 * cg;
+      const int nct = ((n - j0 < 64 ? n - j0 : 64) + 15) >> 4;
+      const int u1 = j0 + 64 < n ? j0 + 64 : n;  // rows u <= c of the group's columns
+      gg_v4 acc[4] = {};
+      wave_tile_mfma(
+          [&](int i, int u) {
+            const double v = W[size_t(i < ie ? i : ie - 1) * n + (u < n ? u : n - 1)];
+            return i < ie && u >= ie && u < u1 ? v : 0.0;
+          },
+          [&](int u, int col) {
+            const int c = j0 + col;
+            return u >= ie && u < n && c < n ? uinv(u, c) : 0.0;
+          },
+          ib, ie, u1, nct, acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ib + lk + 4 * r;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int c = j0 + 16 * cc + li;
+          if (i < ie && c < n && cc < nct) X[size_t(i) * n + c] = -acc[cc][r];
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = ie - 1; i >= ib; --i) {
+      const double d = W[size_t(i) * n + i];
+      for (int c = i + tid; c < n; c += NT) {
+        double v = (c == i ? 1.0 : 0.0) + (c >= ie ? X[size_t(i) * n + c] : 0.0);
+        const int ue = c + 1 < ie ? c + 1 : ie;
+        for (int u = i + 1; u < ue; ++u) v -= W[size_t(i) * n + u] * uinv(u, c);
+        X[size_t(i) * n + c] = v / d;
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = tid; t < n * n; t += NT) {
+    const int i = t / n, c = t - i * n;
+    const double v = X[t];
+    out[t] = TO(sym ? balance_entry(v, i, c, X[size_t(i) * n + i], X[size_t(c) * n + c]) : v);
+  }
+  __syncthreads();
+}
+
 template <int NT, typename TO>
 __device__ inline void seg_block_inverse(const double* W, int n, double* X, TO* out, bool sym) {
   const int tid = threadIdx.x;
@@ -802,7 +906,10 @@ __global__ __launch_bounds__(NT) void k_seg_lu(const DSeg* segs, int nseg, const
   // packed inverses: strictly lower part of L^{-1} (unit diagonal implied)
   // and upper part of U^{-1}, so every later application is a product
   T* LU = varena + S.lu_off;
-  seg_block_inverse<NT>(W, n, X, LU, sym != 0);
+  if (NT >= 1024 && !inlds)
+    seg_block_inverse_panels<NT>(W, n, X, LU, sym != 0);
+  else
+    seg_block_inverse<NT>(W, n, X, LU, sym != 0);
   if (sp) {
     for (int p = tid; p < n; p += NT) tmp[p] = dofs[p < nr ? perm[k + p] : perm[p - nr]];
     __syncthreads();
