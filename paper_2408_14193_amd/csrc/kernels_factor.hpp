@@ -146,7 +146,7 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
                                                     const int64_t* rowptr, const int32_t* colind,
                                                     const double* vals, int32_t* iarena, T* varena,
                                                     double* gscratch, int64_t gscr_stride, int* status,
-                                                    int level, int lds_doubles) {
+                                                    int level, int lds_doubles, int defer) {
   extern __shared__ double lds[];
   __shared__ int s_piv;
   __shared__ double s_d;
@@ -255,6 +255,12 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
     }
     __syncthreads();
   }
+  // A_II^{-1}, stored transposed (entry (i, q) at q * ni + i) so that the
+  // solve's lanes, one per row, read consecutive addresses
+  T* LUo = varena + L.lu_off;
+  for (int t = tid; t < ni * ni; t += WG) LUo[t] = T(A[(t % ni) * ni + t / ni]);
+  // defer: X and S are left to k_leaf_x_mfma (staging in scratch)
+  if (defer) return;
   // X = A_II^{-1} A_IB
   for (int t = tid; t < ni * nb; t += WG) {
     const int i = t / nb, c = t - i * nb;
@@ -262,10 +268,75 @@ __global__ __launch_bounds__(WG) void k_leaf_factor(const DLeaf* leaves, int nle
     for (int q = 0; q < ni; ++q) acc += A[i * ni + q] * B[q * nb + c];
     X[t] = acc;
   }
-  // A_II^{-1}, stored transposed (entry (i, q) at q * ni + i) so that the
-  // solve's lanes, one per row, read consecutive addresses
-  T* LUo = varena + L.lu_off;
-  for (int t = tid; t < ni * ni; t += WG) LUo[t] = T(A[(t % ni) * ni + t / ni]);
+  __syncthreads();
+  // S = A_BI X (boundary rows, sparse)
+  T* S = varena + L.s_off;
+  for (int t = tid; t < nb * nb; t += WG) {
+    const int b = t / nb, c = t % nb;
+    const int u = bv[b];
+    double acc = 0.0;
+    for (int64_t e = rowptr[u]; e < rowptr[u + 1]; ++e) {
+      const int w = colind[e];
+      int cw[3];
+      vcoords(g, w, cw);
+      if (cw[0] >= L.lo[0] && cw[0] <= L.hi[0] && cw[1] >= L.lo[1] && cw[1] <= L.hi[1] &&
+          cw[2] >= L.lo[2] && cw[2] <= L.hi[2]) {
+        const int j = (cw[0] - L.lo[0]) + w0 * ((cw[1] - L.lo[1]) + w1 * (cw[2] - L.lo[2]));
+        acc += vals[e] * X[j * nb + c];
+      }
+    }
+    S[t] = T(acc);
+  }
+}
+
+// Second half of k_leaf_factor for leaves staged in scratch (3D), launched
+// after it with defer set: X = A_II^{-1} A_IB on the matrix cores (FP64
+// 16 x 64 output tiles, one wave per tile, operands read from the leaf's
+// scratch), then S = A_BI X.  A launch of its own keeps the tiles' registers
+// out of the Gauss-Jordan sweep, whose occupancy matters when many leaves
+// share a CU.
+template <typename T>
+__global__ __launch_bounds__(WG) void k_leaf_x_mfma(const DLeaf* leaves, int nleaf, GridGeom g,
+                                                    const int64_t* rowptr, const int32_t* colind,
+                                                    const double* vals, T* varena, double* gscratch,
+                                                    int64_t gscr_stride) {
+  const int lf = blockIdx.x;
+  if (lf >= nleaf) return;
+  const DLeaf L = leaves[lf];
+  const int ni = L.ni, nb = L.nb, tid = threadIdx.x;
+  const int w0 = L.hi[0] - L.lo[0] + 1, w1 = L.hi[1] - L.lo[1] + 1;
+  const double* A = gscratch + size_t(lf) * gscr_stride;  // A_II^{-1}
+  const double* B = A + ni * ni;                           // A_IB
+  double* X = const_cast<double*>(B) + ni * nb;            // A_II^{-1} A_IB
+  const int* bv = reinterpret_cast<const int*>(X + ni * nb + ni);
+  {
+    const int w = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int nti = (ni + 15) >> 4, ncg = (nb + 63) >> 6;
+    for (int unit = w; unit < nti * ncg; unit += NWAVE) {
+      const int ti = unit / ncg, cg = unit - ti * ncg, i0 = 16 * ti, j0 = 64 * cg;
+      const int nct = ((nb - j0 < 64 ? nb - j0 : 64) + 15) >> 4;
+      gg_v4 acc[4] = {};
+      wave_tile_mfma(
+          [&](int i, int q) {
+            const double v = A[(i < ni ? i : ni - 1) * ni + (q < ni ? q : ni - 1)];
+            return i < ni && q < ni ? v : 0.0;
+          },
+          [&](int q, int col) {
+            const int c = j0 + col;
+            return B[(q < ni ? q : ni - 1) * nb + (c < nb ? c : nb - 1)];
+          },
+          i0, 0, ni, nct, acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + lk + 4 * r;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int c = j0 + 16 * cc + li;
+          if (i < ni && c < nb && cc < nct) X[i * nb + c] = acc[cc][r];
+        }
+      }
+    }
+  }
   __syncthreads();
   // S = A_BI X (boundary rows, sparse)
   T* S = varena + L.s_off;

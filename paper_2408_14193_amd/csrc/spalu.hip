@@ -1056,7 +1056,12 @@ int issue_factor(spalu_factor_t* F, const spalu_factor_opts& o, hipStream_t st) 
         const bool lds_any = Y.leaf_need_min <= size_t(LEAF_LDS_DOUBLES);
         LAUNCH(K_LEAF, L, k_leaf_factor<T><<<nl, WG, lds_any ? LEAF_LDS_BYTES : 0, st>>>(
             lt, int(nl), F->g, F->rowptr, F->colind, F->vals, iar, var, scr, int64_t(Y.leaf_scr_stride), status,
-            L + 1, lds_any ? LEAF_LDS_DOUBLES : 0));
+            L + 1, lds_any ? LEAF_LDS_DOUBLES : 0, lds_any ? 0 : 1));
+        // every leaf in scratch: X = A_II^{-1} A_IB and S in a second launch
+        if (!lds_any)
+          LAUNCH_MORE(K_LEAF, L, k_leaf_x_mfma<T><<<nl, WG, 0, st>>>(lt, int(nl), F->g, F->rowptr, F->colind,
+                                                                      F->vals, var, scr,
+                                                                      int64_t(Y.leaf_scr_stride)));
       }
     }
     // blocks of small segments: one wave each
