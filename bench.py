@@ -48,7 +48,10 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--side", type=int, default=None)
     ap.add_argument("--nrhs", type=int, default=None)
-    ap.add_argument("--forms", default="learned,mixed,plain")
+    ap.add_argument("--forms", default=None,
+                    help="comma-separated forms, the first one the headline (default: learned,mixed,plain; on the "
+                         "symmetric positive definite workloads the symmetric learned form first, and on the 3D "
+                         "Laplacian only FP32 forms, whose workspace fits at 127^3)")
     ap.add_argument("--cpu-side", type=int, default=255)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--verbose", action="store_true")
@@ -280,6 +283,9 @@ def main():
     t_nd = time.perf_counter() - t0
     log("workload %s %s: N=%d, nrhs=%d, eps=%g, tol=%g, L=%d, ND %.2f s (host)"
         % (P.name, P.dims, P.n, P.nrhs, P.eps, P.tol, nd.L, t_nd))
+    if a.forms is None:
+        a.forms = {0: "learned-sym,learned,mixed,plain", 1: "learned-sym,learned,mixed,plain",
+                   3: "learned-sym,mixed-sym"}.get(a.config, "learned,mixed,plain")
     forms = a.forms.split(",")
     res = {}
     for i, f in enumerate(forms):
