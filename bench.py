@@ -52,7 +52,8 @@ def parse():
                     help="comma-separated forms, the first one the headline (default: learned,mixed,plain; on the "
                          "symmetric positive definite workloads the symmetric learned form first, and on the 3D "
                          "Laplacian only FP32 forms, whose workspace fits at 127^3)")
-    ap.add_argument("--cpu-side", type=int, default=255)
+    ap.add_argument("--cpu-side", type=int, default=None,
+                    help="grid side of the oracle's sample (default 255 in 2D, 23 for the 3D Laplacian)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="direct launches in every form")
@@ -357,7 +358,9 @@ def main():
             out["%s_form" % f]["max_rel_diff_vs_plain_fp64"] = err[f]
         out["ratio_%s_vs_%s" % (head, f)] = round(value / vf, 3)
     if not a.no_cpu:
-        log("cpu baseline: oracle on a %dx%d sample ..." % (a.cpu_side, a.cpu_side))
+        if a.cpu_side is None:
+            a.cpu_side = 23 if a.config == 3 else 255
+        log("cpu baseline: oracle on a side-%d sample ..." % a.cpu_side)
         out["cpu_baseline"] = cpu_baseline(a.config, a.cpu_side)
     print(json.dumps(out), flush=True)
 
